@@ -1,0 +1,245 @@
+"""Python access to the FP64 CPU oracle (liboracle.so, built from oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg use it.  It marshals the seeded input dictionaries into the
+oracle's own structs; it shares no code with the HIP library or its binding.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+MOTION_VALID, MOTION_PROJ_FAIL, MOTION_COLLISION = 0, 1, 2
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_u8p = C.POINTER(C.c_uint8)
+
+
+class _Robot(C.Structure):
+    _fields_ = [("dof", C.c_int32), ("n_chains", C.c_int32),
+                ("type", _ip), ("chain", _ip),
+                ("alpha", _dp), ("a", _dp), ("d", _dp), ("theta", _dp),
+                ("lo", _dp), ("hi", _dp), ("base", _dp), ("tool", _dp),
+                ("n_spheres", C.c_int32), ("sphere_link", _ip), ("sphere", _dp)]
+
+
+class _Env(C.Structure):
+    _fields_ = [("n_aabb", C.c_int32), ("n_obb", C.c_int32), ("n_sphere", C.c_int32),
+                ("n_capsule", C.c_int32), ("n_cylinder", C.c_int32),
+                ("aabb", _dp), ("obb", _dp), ("sphere", _dp), ("capsule", _dp),
+                ("cylinder", _dp)]
+
+
+class _Constraint(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("mask", C.c_int32 * 6), ("frame", C.c_double * 16),
+                ("target", C.c_double * 6), ("rel_target", C.c_double * 16)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("W", C.c_int32), ("max_iters", C.c_int32), ("tau", C.c_double),
+                ("tau_sm", C.c_double), ("tau_task", C.c_double), ("alpha", C.c_double),
+                ("lam", C.c_double)]
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c with gcc (OpenMP over independent items only)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-o", LIB_PATH,
+                               src, "-lm"], cwd=_HERE)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        L.or_config_min_sd.restype = C.c_double
+        for name in ("or_sd_aabb", "or_sd_obb", "or_sd_sphere", "or_sd_capsule", "or_sd_cylinder"):
+            getattr(L, name).restype = C.c_double
+            getattr(L, name).argtypes = [_dp, C.c_double, _dp]
+        L.or_task_dim.restype = C.c_int32
+        L.or_task_error.restype = C.c_int32
+        L.or_task_jacobian.restype = C.c_int32
+        L.or_parallel_project.restype = C.c_int32
+        L.or_project_config.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _ptr(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+class Robot:
+    """Oracle view of a robot dictionary (keeps the arrays alive)."""
+
+    def __init__(self, rd: dict):
+        self.keep = dict(
+            type=np.ascontiguousarray(rd["joint_type"], np.int32),
+            chain=np.ascontiguousarray(rd["joint_chain"], np.int32),
+            alpha=_f64(rd["alpha"]), a=_f64(rd["a"]), d=_f64(rd["d"]), theta=_f64(rd["theta"]),
+            lo=_f64(rd["lo"]), hi=_f64(rd["hi"]),
+            base=_f64(rd["base"]).reshape(-1), tool=_f64(rd["tool"]).reshape(-1),
+            sphere_link=np.ascontiguousarray(rd["sphere_link"], np.int32),
+            sphere=_f64(rd["sphere"]).reshape(-1),
+        )
+        k = self.keep
+        self.dof = int(rd["dof"])
+        self.n_chains = int(rd["n_chains"])
+        self.n_spheres = len(k["sphere_link"])
+        self.lo, self.hi = k["lo"], k["hi"]
+        self.s = _Robot(self.dof, self.n_chains, _ptr(k["type"], _ip), _ptr(k["chain"], _ip),
+                        _ptr(k["alpha"]), _ptr(k["a"]), _ptr(k["d"]), _ptr(k["theta"]),
+                        _ptr(k["lo"]), _ptr(k["hi"]), _ptr(k["base"]), _ptr(k["tool"]),
+                        self.n_spheres, _ptr(k["sphere_link"], _ip), _ptr(k["sphere"]))
+
+
+class Env:
+    def __init__(self, ed: dict):
+        names = ("aabb", "obb", "sphere", "capsule", "cylinder")
+        widths = (6, 15, 4, 7, 8)
+        self.keep = {n: _f64(np.asarray(ed[n]).reshape(-1, w)) for n, w in zip(names, widths)}
+        k = self.keep
+        self.s = _Env(*(len(k[n]) for n in names), *(_ptr(k[n]) for n in names))
+
+
+class Constraint:
+    def __init__(self, cd: dict):
+        self.s = _Constraint()
+        self.s.kind = int(cd["kind"])
+        for i in range(6):
+            self.s.mask[i] = int(cd["mask"][i])
+            self.s.target[i] = float(cd["target"][i])
+        fr = np.asarray(cd["frame"], np.float64).reshape(-1)
+        rt = np.asarray(cd["rel_target"], np.float64).reshape(-1)
+        for i in range(16):
+            self.s.frame[i] = fr[i]
+            self.s.rel_target[i] = rt[i]
+        self.m = lib().or_task_dim(C.byref(self.s))
+
+
+def params(W=64, max_iters=32, tau=0.05, tau_sm=0.025, tau_task=1e-3, alpha=1.0, lam=1e-2):
+    return _Params(W, max_iters, tau, tau_sm, tau_task, alpha, lam)
+
+
+# ------------------------------------------------------------------ wrappers
+
+def fk(robot: Robot, q):
+    q = _f64(q)
+    frames = np.zeros((robot.dof, 4, 4))
+    ee = np.zeros((robot.n_chains, 4, 4))
+    lib().or_fk(C.byref(robot.s), _ptr(q), _ptr(frames), _ptr(ee))
+    return frames, ee
+
+
+def task_coords(robot: Robot, con: Constraint, q):
+    q = _f64(q)
+    x = np.zeros(6)
+    lib().or_task_coords(C.byref(robot.s), C.byref(con.s), _ptr(q), _ptr(x))
+    return x
+
+
+def task_error(robot: Robot, con: Constraint, q):
+    q = _f64(q)
+    e = np.zeros(6)
+    m = lib().or_task_error(C.byref(robot.s), C.byref(con.s), _ptr(q), _ptr(e))
+    return e[:m].copy()
+
+
+def task_jacobian(robot: Robot, con: Constraint, q):
+    q = _f64(q)
+    J = np.zeros(6 * robot.dof)
+    m = lib().or_task_jacobian(C.byref(robot.s), C.byref(con.s), _ptr(q), _ptr(J))
+    return J[: m * robot.dof].reshape(m, robot.dof).copy()
+
+
+def dls_step(J, e, lam):
+    J = _f64(J)
+    e = _f64(e)
+    m, n = J.shape
+    g = np.zeros(n)
+    lib().or_dls_step(_ptr(J), _ptr(e), C.c_int32(m), C.c_int32(n), C.c_double(lam), _ptr(g))
+    return g
+
+
+def sd(kind: str, centre, radius, prim):
+    c = _f64(centre)
+    p = _f64(prim)
+    return getattr(lib(), "or_sd_" + kind)(_ptr(c), C.c_double(radius), _ptr(p))
+
+
+def sphere_centres(robot: Robot, q):
+    q = _f64(q)
+    out = np.zeros((robot.n_spheres, 3))
+    lib().or_sphere_centres(C.byref(robot.s), _ptr(q), _ptr(out))
+    return out
+
+
+def config_min_sd(robot: Robot, env: Env, q):
+    q = _f64(q)
+    return lib().or_config_min_sd(C.byref(robot.s), C.byref(env.s), _ptr(q))
+
+
+def fk_cc_batch(robot: Robot, env: Env, q, n_threads: int = 1):
+    q = _f64(q).reshape(-1, robot.dof)
+    n = len(q)
+    col = np.zeros(n, np.uint8)
+    msd = np.zeros(n)
+    lib().or_fk_cc_batch(C.byref(robot.s), C.byref(env.s), C.c_int32(n), _ptr(q),
+                         _ptr(col, _u8p), _ptr(msd), C.c_int32(n_threads))
+    return col, msd
+
+
+def parallel_project(robot: Robot, con: Constraint, prm, xi_init):
+    xi = _f64(xi_init).copy()
+    it = C.c_int32(0)
+    mg = C.c_double(0)
+    trace = np.zeros(prm.max_iters, np.int32)
+    ok = lib().or_parallel_project(C.byref(robot.s), C.byref(con.s), C.byref(prm), _ptr(xi),
+                                   C.byref(it), C.byref(mg), _ptr(trace, _ip))
+    return bool(ok), xi, it.value, mg.value, trace[: it.value].copy()
+
+
+def project_validate_motions(robot: Robot, env: Env, con: Constraint, prm, q_from, q_to,
+                             n_threads: int = 1):
+    q_from = _f64(q_from).reshape(-1, robot.dof)
+    q_to = _f64(q_to).reshape(-1, robot.dof)
+    M = len(q_from)
+    xi = np.zeros((M, prm.W, robot.dof))
+    status = np.zeros(M, np.int32)
+    iters = np.zeros(M, np.int32)
+    margin = np.zeros(M)
+    msd = np.zeros(M)
+    lib().or_project_validate_motions(C.byref(robot.s), C.byref(env.s), C.byref(con.s),
+                                      C.byref(prm), C.c_int32(M), _ptr(q_from), _ptr(q_to),
+                                      _ptr(xi), _ptr(status, _ip), _ptr(iters, _ip),
+                                      _ptr(margin), _ptr(msd), C.c_int32(n_threads))
+    return dict(xi=xi, status=status, iters=iters, proj_margin=margin, min_sd=msd)
+
+
+def project_config(robot: Robot, con: Constraint, q, tol=1e-9, max_iters=100, alpha=1.0,
+                   lam=1e-2):
+    q = _f64(q)
+    out = np.zeros(robot.dof)
+    it = C.c_int32(0)
+    ok = lib().or_project_config(C.byref(robot.s), C.byref(con.s), _ptr(q), C.c_double(tol),
+                                 C.c_int32(max_iters), C.c_double(alpha), C.c_double(lam),
+                                 _ptr(out), C.byref(it))
+    return bool(ok), out, it.value

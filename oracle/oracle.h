@@ -1,0 +1,105 @@
+/* FP64 CPU oracle for cpRRTC's constrained motion projection and validation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  It shares no source,
+ * header, table or helper with the HIP library, and the HIP library never
+ * calls it.
+ *
+ * Every quantity is double precision; float inputs are promoted exactly by
+ * the caller.  Nothing here is blocked, fused or reordered beyond what the
+ * definitions state.
+ */
+#ifndef CPRRTC_ORACLE_H
+#define CPRRTC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_REVOLUTE = 0, OR_PRISMATIC = 1 };
+enum { OR_CON_NONE = 0, OR_CON_POSE = 1, OR_CON_REL_POSE = 2 };
+enum { OR_MOTION_VALID = 0, OR_MOTION_PROJ_FAIL = 1, OR_MOTION_COLLISION = 2 };
+
+typedef struct {
+  int32_t dof, n_chains;
+  const int32_t* type;        /* [dof] OR_REVOLUTE / OR_PRISMATIC */
+  const int32_t* chain;       /* [dof] chain of each joint */
+  const double* alpha;        /* [dof] alpha_{i-1} */
+  const double* a;            /* [dof] a_{i-1} */
+  const double* d;            /* [dof] constant part of d_i */
+  const double* theta;        /* [dof] constant part of theta_i */
+  const double* lo;           /* [dof] */
+  const double* hi;           /* [dof] */
+  const double* base;         /* [n_chains][16] row-major */
+  const double* tool;         /* [n_chains][16] row-major */
+  int32_t n_spheres;
+  const int32_t* sphere_link; /* [S] joint whose frame carries the sphere */
+  const double* sphere;       /* [S][4] local centre, radius */
+} or_robot;
+
+typedef struct {
+  int32_t n_aabb, n_obb, n_sphere, n_capsule, n_cylinder;
+  const double* aabb;      /* [n][6]  centre, half extents */
+  const double* obb;       /* [n][15] centre, R row-major (columns = axes), half extents */
+  const double* sphere;    /* [n][4]  centre, radius */
+  const double* capsule;   /* [n][7]  p0, p1, radius */
+  const double* cylinder;  /* [n][8]  centre, unit axis, half length, radius */
+} or_env;
+
+typedef struct {
+  int32_t kind;
+  int32_t mask[6];          /* x y z roll pitch yaw */
+  double frame[16];         /* constraint frame in world, row-major */
+  double target[6];
+  double rel_target[16];    /* pose of end effector 2 in end effector 1's frame */
+} or_constraint;
+
+typedef struct {
+  int32_t W;                /* waypoints per motion, including the fixed start */
+  int32_t max_iters;
+  double tau;               /* spacing target (interpolation step) */
+  double tau_sm;            /* spacing slack: valid spacing is < tau + tau_sm */
+  double tau_task;          /* task tolerance on the infinity norm of the error */
+  double alpha;             /* step factor */
+  double lambda;            /* damping of the least-squares step */
+} or_params;
+
+/* Kinematics.  frames: [dof][16] joint frames in world; ee: [n_chains][16]. */
+void or_fk(const or_robot* r, const double* q, double* frames, double* ee);
+int32_t or_task_dim(const or_constraint* c);
+/* Full 6-vector task coordinates (before masking) and masked error/Jacobian. */
+void or_task_coords(const or_robot* r, const or_constraint* c, const double* q, double* x6);
+int32_t or_task_error(const or_robot* r, const or_constraint* c, const double* q, double* e);
+int32_t or_task_jacobian(const or_robot* r, const or_constraint* c, const double* q, double* J);
+void or_dls_step(const double* J, const double* e, int32_t m, int32_t n, double lambda, double* g);
+
+/* Geometry. */
+double or_sd_aabb(const double* c, double r, const double* box);
+double or_sd_obb(const double* c, double r, const double* box);
+double or_sd_sphere(const double* c, double r, const double* s);
+double or_sd_capsule(const double* c, double r, const double* cap);
+double or_sd_cylinder(const double* c, double r, const double* cyl);
+void or_sphere_centres(const or_robot* r, const double* q, double* xyz);
+double or_config_min_sd(const or_robot* r, const or_env* env, const double* q);
+
+/* Batched entry points (OpenMP over independent items; n_threads <= 0 means 1). */
+void or_fk_cc_batch(const or_robot* r, const or_env* env, int32_t n_cfg, const double* q,
+                    uint8_t* collide, double* min_sd, int32_t n_threads);
+
+int32_t or_parallel_project(const or_robot* r, const or_constraint* c, const or_params* p,
+                            double* xi, int32_t* iters, double* margin, int32_t* trace_prog);
+
+void or_project_validate_motions(const or_robot* r, const or_env* env, const or_constraint* c,
+                                 const or_params* p, int32_t n_motions, const double* q_from,
+                                 const double* q_to, double* xi, int32_t* status, int32_t* iters,
+                                 double* proj_margin, double* min_sd, int32_t n_threads);
+
+int32_t or_project_config(const or_robot* r, const or_constraint* c, const double* q_in,
+                          double tol, int32_t max_iters, double alpha, double lambda,
+                          double* q_out, int32_t* iters);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,429 @@
+"""Pins of the FP64 oracle against facts fixed outside it.
+
+Each test checks the oracle against something other than its own formulas:
+hand-worked fixtures (tests/golden), closed forms of special chains, finite
+differences, numpy/scipy library routines, brute force, and invariants that
+Algorithm 1 (ParallelProject, Section III-A) guarantees for any output.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2505_06791_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _chain_robot(alpha, a, d, theta, types, tool_z=0.0, spheres=None, links=None, lim=2.8):
+    n = len(alpha)
+    tool = np.eye(4)
+    tool[2, 3] = tool_z
+    return dict(dof=n, n_chains=1, joint_type=np.asarray(types, np.int32),
+                joint_chain=np.zeros(n, np.int32), alpha=np.asarray(alpha, float),
+                a=np.asarray(a, float), d=np.asarray(d, float), theta=np.asarray(theta, float),
+                lo=np.full(n, -lim), hi=np.full(n, lim), base=np.eye(4)[None].copy(),
+                tool=tool[None].copy(),
+                sphere_link=np.asarray(links if links is not None else [n - 1], np.int32),
+                sphere=np.asarray(spheres if spheres is not None else [[0, 0, 0, 0.05]], float))
+
+
+# ------------------------------------------------------------------ kinematics
+
+def test_fk_hand_worked(oracle_lib):
+    O = oracle_lib
+    fx = json.load(open(os.path.join(GOLDEN, "fk_zero.json")))
+    for ch in fx["chains"]:
+        rob = O.Robot(_chain_robot(ch["alpha"], ch["a"], ch["d"], ch["theta"], ch["type"],
+                                   ch["tool_z"]))
+        frames, ee = O.fk(rob, np.asarray(ch["q"], float))
+        np.testing.assert_allclose(frames[:, :3, 3], ch["frames_origin"], atol=1e-12)
+        np.testing.assert_allclose(frames[:, :3, 2], ch["frames_z"], atol=1e-12)
+        np.testing.assert_allclose(ee[0, :3, 3], ch["ee_origin"], atol=1e-12)
+
+
+def test_fk_planar_closed_form(oracle_lib):
+    """All twists zero: frame k is RotZ(phi_k) at
+    (sum_{i<=k} a_{i-1} cos phi_{i-1}, sum a_{i-1} sin phi_{i-1}, sum d_i),
+    phi_j = sum_{l<=j} (theta_l + q_l), for any q including the limits."""
+    O = oracle_lib
+    rng = np.random.default_rng(7)
+    n = 6
+    a = rng.uniform(0.05, 0.4, n)
+    d = rng.uniform(-0.1, 0.3, n)
+    th = rng.uniform(-1, 1, n)
+    rob = O.Robot(_chain_robot(np.zeros(n), a, d, th, np.zeros(n)))
+    qs = [rng.uniform(-2.8, 2.8, n) for _ in range(5)] + [np.full(n, 2.8), np.full(n, -2.8)]
+    for q in qs:
+        frames, _ = O.fk(rob, q)
+        phi = np.cumsum(th + q)
+        phi_prev = np.concatenate([[0.0], phi[:-1]])
+        px = np.cumsum(a * np.cos(phi_prev))
+        py = np.cumsum(a * np.sin(phi_prev))
+        pz = np.cumsum(d)
+        np.testing.assert_allclose(frames[:, 0, 3], px, atol=1e-12)
+        np.testing.assert_allclose(frames[:, 1, 3], py, atol=1e-12)
+        np.testing.assert_allclose(frames[:, 2, 3], pz, atol=1e-12)
+        np.testing.assert_allclose(frames[:, 0, 0], np.cos(phi), atol=1e-12)
+        np.testing.assert_allclose(frames[:, 1, 0], np.sin(phi), atol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["plain", "mobile", "dual"])
+def test_fk_rotations_orthonormal(oracle_lib, name):
+    O = oracle_lib
+    w = I.workload(name, 11)
+    rob = O.Robot(w["robot"])
+    for q in I.random_configs(w["robot"], 5, 3):
+        frames, ee = O.fk(rob, q)
+        for T in np.concatenate([frames, ee]):
+            R = T[:3, :3]
+            np.testing.assert_allclose(R.T @ R, np.eye(3), atol=1e-12)
+            assert abs(np.linalg.det(R) - 1.0) < 1e-12
+
+
+def test_prismatic_base_slides_along_world_axes(oracle_lib):
+    """The planar base's two prismatic joints move every frame rigidly by
+    q1 along world x and q2 along world y."""
+    O = oracle_lib
+    rd = I.make_mobile_arm(5)
+    rob = O.Robot(rd)
+    q = I.random_configs(rd, 1, 9)[0]
+    f0, e0 = O.fk(rob, q)
+    for j, axis in ((0, np.array([1.0, 0, 0])), (1, np.array([0, 1.0, 0]))):
+        q2 = q.copy()
+        q2[j] += 0.37
+        f1, e1 = O.fk(rob, q2)
+        np.testing.assert_allclose(f1[j:, :3, 3] - f0[j:, :3, 3],
+                                   np.tile(0.37 * axis, (rd["dof"] - j, 1)), atol=1e-12)
+        np.testing.assert_allclose(f1[:, :3, :3], f0[:, :3, :3], atol=1e-12)
+    # the first arm joint turns about world z
+    np.testing.assert_allclose(f0[2, :3, 2], [0, 0, 1], atol=1e-12)
+
+
+def _wrap(x):
+    return (x + np.pi) % (2 * np.pi) - np.pi
+
+
+@pytest.mark.parametrize("name,con", [("plain", "upright"), ("cluttered", "plane"),
+                                      ("mobile", "plane"), ("dual", "rel"),
+                                      ("plain", "line"), ("plain", "full")])
+def test_task_jacobian_matches_central_differences(oracle_lib, name, con):
+    O = oracle_lib
+    w = I.workload(name, 21)
+    cd = dict(upright=I.upright(), plane=I.plane_upright(3), rel=I.relative_pose(),
+              line=I.line_constraint(4),
+              full=dict(I.upright(), mask=np.ones(6, np.int32)))[con]
+    rob, c = O.Robot(w["robot"]), O.Constraint(cd)
+    h = 1e-6
+    for q in I.random_configs(w["robot"], 4, 5):
+        J = O.task_jacobian(rob, c, q)
+        Jfd = np.zeros_like(J)
+        ang = np.array([j >= 3 for j in range(6) if cd["mask"][j]])
+        for i in range(rob.dof):
+            qp, qm = q.copy(), q.copy()
+            qp[i] += h
+            qm[i] -= h
+            de = O.task_error(rob, c, qp) - O.task_error(rob, c, qm)
+            de[ang] = _wrap(de[ang])
+            Jfd[:, i] = de / (2 * h)
+        scale = max(1.0, np.abs(J).max())
+        assert np.abs(J - Jfd).max() < 1e-6 * scale
+
+
+def test_position_columns_orthogonal_to_revolute_axes(oracle_lib):
+    """With the position rows only, column i is z_i x (p_ee - p_i): orthogonal to z_i."""
+    O = oracle_lib
+    rd = I.make_arm(31, 7, 4)
+    rob = O.Robot(rd)
+    cd = dict(I.upright(), mask=np.array([1, 1, 1, 0, 0, 0], np.int32))
+    c = O.Constraint(cd)
+    for q in I.random_configs(rd, 3, 1):
+        J = O.task_jacobian(rob, c, q)
+        frames, ee = O.fk(rob, q)
+        for i in range(rob.dof):
+            z = frames[i, :3, 2]
+            assert abs(J[:, i] @ z) < 1e-12
+            np.testing.assert_allclose(J[:, i], np.cross(z, ee[0, :3, 3] - frames[i, :3, 3]),
+                                       atol=1e-12)
+
+
+@pytest.mark.parametrize("m,n", [(1, 7), (2, 7), (3, 9), (6, 14), (6, 6)])
+def test_dls_step_equals_stacked_least_squares(oracle_lib, m, n):
+    O = oracle_lib
+    rng = np.random.default_rng(m * 100 + n)
+    J = rng.normal(size=(m, n))
+    e = rng.normal(size=m)
+    for lam in (1e-2, 0.3):
+        g = O.dls_step(J, e, lam)
+        A = np.vstack([J, lam * np.eye(n)])
+        b = np.concatenate([e, np.zeros(n)])
+        ref = np.linalg.lstsq(A, b, rcond=None)[0]
+        np.testing.assert_allclose(g, ref, rtol=1e-9, atol=1e-12)
+    g0 = O.dls_step(J, e, 1e-9)
+    np.testing.assert_allclose(g0, np.linalg.pinv(J) @ e, rtol=1e-6, atol=1e-9)
+
+
+def test_single_config_projection_converges_quadratically(oracle_lib):
+    """Undamped Newton (lambda = 0, minimum-norm step) near a regular solution:
+    each residual is at most a constant times the square of the previous one."""
+    O = oracle_lib
+    w = I.workload("plain", 41)
+    rob, c = O.Robot(w["robot"]), O.Constraint(w["constraint"])
+    checked = 0
+    for q0 in I.random_configs(w["robot"], 10, 2):
+        res = []
+        for k in range(0, 12):
+            _, qk, _ = O.project_config(rob, c, q0, tol=0.0, max_iters=k, lam=0.0)
+            res.append(np.abs(O.task_error(rob, c, qk)).max())
+        ok, qf, _ = O.project_config(rob, c, q0, tol=1e-10, max_iters=50, lam=0.0)
+        if not ok or np.any(np.abs(qf) >= 2.8 - 1e-9):
+            continue          # a clamped joint makes the step a projected one
+        for r0, r1 in zip(res[:-1], res[1:]):
+            if 1e-12 < r0 < 1e-2:
+                assert r1 <= 50.0 * r0 * r0 + 1e-15, (r0, r1)
+                checked += 1
+    assert checked >= 5
+
+
+# ------------------------------------------------------------------ ParallelProject
+
+def _on_manifold(O, rob, c, rd, n, seed, tol=1e-12):
+    out = []
+    for q in I.random_configs(rd, 4 * n, seed):
+        ok, qp, _ = O.project_config(rob, c, q, tol=tol, max_iters=100)
+        if ok:
+            out.append(qp)
+        if len(out) == n:
+            break
+    assert len(out) == n
+    return np.asarray(out)
+
+
+def _segment(a, b, W):
+    s = np.arange(W)[:, None] / (W - 1)
+    return a[None] + s * (b - a)[None]
+
+
+def test_project_without_constraint_returns_input(oracle_lib):
+    """Constraint NONE: no task error, straight spacing <= tau, so every
+    waypoint is valid at the first snapshot and that snapshot is returned."""
+    O = oracle_lib
+    rd = I.make_arm(3)
+    rob, c = O.Robot(rd), O.Constraint(I.no_constraint())
+    prm = O.params(W=64)
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        a = rng.uniform(-2, 2, 7)
+        v = rng.normal(size=7)
+        b = a + v / np.linalg.norm(v) * rng.uniform(0.1, 63 * 0.05)
+        xi0 = _segment(a, b, 64)
+        ok, xi, it, _, trace = O.parallel_project(rob, c, prm, xi0)
+        assert ok and it == 1
+        assert np.array_equal(xi, xi0)
+
+
+@pytest.mark.parametrize("con", ["upright", "plane"])
+def test_project_joint1_motion_is_already_on_manifold(oracle_lib, con):
+    """Joint 1 turns about world z, which changes neither the end effector's
+    height nor its roll/pitch: such a motion from an on-manifold start stays on
+    the manifold and is returned unchanged after one iteration."""
+    O = oracle_lib
+    rd = I.make_arm(5)
+    cd = I.upright() if con == "upright" else I.plane_upright(6)
+    rob, c = O.Robot(rd), O.Constraint(cd)
+    prm = O.params(W=64)
+    for q0 in _on_manifold(O, rob, c, rd, 3, 8):
+        b = q0.copy()
+        b[0] = np.clip(q0[0] + 1.5, -2.8, 2.8)
+        xi0 = _segment(q0, b, 64)
+        ok, xi, it, _, _ = O.parallel_project(rob, c, prm, xi0)
+        assert ok and it == 1
+        assert np.array_equal(xi, xi0)
+
+
+def _check_projected(O, rob, c, prm, q_from, xi):
+    assert np.array_equal(xi[0], q_from)
+    for k in range(1, prm.W):
+        e = O.task_error(rob, c, xi[k])
+        assert np.abs(e).max() < prm.tau_task
+        assert np.linalg.norm(xi[k] - xi[k - 1]) < prm.tau + prm.tau_sm
+        assert np.all(xi[k] >= rob.lo) and np.all(xi[k] <= rob.hi)
+
+
+@pytest.mark.parametrize("name,W", [("plain", 64), ("plain", 32), ("cluttered", 64),
+                                    ("mobile", 32), ("dual", 32)])
+def test_project_output_invariants(oracle_lib, name, W):
+    """Any returned segment: start unchanged bitwise, every waypoint within
+    tolerance and limits, spacing below tau + tau_sm; prog never decreases and
+    the frozen prefix never changes after it is frozen."""
+    O = oracle_lib
+    w = I.workload(name, 52)
+    rob, c = O.Robot(w["robot"]), O.Constraint(w["constraint"])
+    prm = O.params(W=W, tau_task=w["tau_task"])
+    starts = _on_manifold(O, rob, c, w["robot"], 10, 3)
+    ends = I.random_displacements(w["robot"], starts, (W - 1) * 0.05, 4)
+    n_ok = 0
+    for a, b in zip(starts, ends):
+        xi0 = _segment(a, b, W)
+        ok, xi, it, _, trace = O.parallel_project(rob, c, prm, xi0)
+        assert np.all(np.diff(trace) >= 0)
+        if not ok:
+            continue
+        n_ok += 1
+        _check_projected(O, rob, c, prm, a, xi)
+        for t in range(1, it):
+            p_t = O.params(W=W, max_iters=t, tau_task=w["tau_task"])
+            _, xi_t, _, _, _ = O.parallel_project(rob, c, p_t, xi0)
+            frozen = trace[t - 1]
+            assert np.array_equal(xi_t[: frozen + 1], xi[: frozen + 1])
+    assert n_ok >= 2
+
+
+def test_project_fails_on_unreachable_plane(oracle_lib):
+    O = oracle_lib
+    rd = I.make_arm(5)
+    cd = I.plane_upright(1)
+    cd["target"][2] = 10.0
+    rob, c = O.Robot(rd), O.Constraint(cd)
+    prm = O.params(W=16, max_iters=8)
+    a = np.zeros(7)
+    ok, _, it, _, _ = O.parallel_project(rob, c, prm, _segment(a, a + 0.05, 16))
+    assert not ok and it == 8
+
+
+def test_project_single_iteration_budget_fails_off_manifold(oracle_lib):
+    O = oracle_lib
+    w = I.workload("plain", 9)
+    rob, c = O.Robot(w["robot"]), O.Constraint(w["constraint"])
+    prm = O.params(W=16, max_iters=1)
+    a = _on_manifold(O, rob, c, w["robot"], 1, 1)[0]
+    b = a.copy()
+    b[3] += 0.6
+    ok, _, _, _, _ = O.parallel_project(rob, c, prm, _segment(a, b, 16))
+    assert not ok
+
+
+# ------------------------------------------------------------------ distances
+
+def test_distances_hand_worked(oracle_lib):
+    O = oracle_lib
+    fx = json.load(open(os.path.join(GOLDEN, "distances.json")))
+    for case in fx["cases"]:
+        got = O.sd(case["kind"], case["c"], case["r"], case["prim"])
+        assert abs(got - case["sd"]) < 1e-12, (case, got)
+
+
+def _brute_box(c, R, h, n=41):
+    """Distance from c to a solid box by dense sampling of its surface
+    (plus 0 when c is inside)."""
+    loc = R.T @ c
+    if np.all(np.abs(loc) <= h):
+        return 0.0
+    g = np.linspace(-1, 1, n)
+    best = np.inf
+    for ax in range(3):
+        for sgn in (-1, 1):
+            u, v = np.meshgrid(g, g)
+            pts = np.zeros((u.size, 3))
+            others = [k for k in range(3) if k != ax]
+            pts[:, ax] = sgn * h[ax]
+            pts[:, others[0]] = u.ravel() * h[others[0]]
+            pts[:, others[1]] = v.ravel() * h[others[1]]
+            best = min(best, np.min(np.linalg.norm(pts - loc, axis=1)))
+    return best
+
+
+def test_box_distances_against_brute_force(oracle_lib):
+    O = oracle_lib
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        h = rng.uniform(0.05, 0.3, 3)
+        cen = rng.uniform(-0.5, 0.5, 3)
+        p = cen + rng.normal(size=3) * 0.4
+        r = 0.05
+        # closest point by clipping (a different construction from the oracle's)
+        ref = np.linalg.norm(p - np.clip(p, cen - h, cen + h)) - r
+        got = O.sd("aabb", p, r, np.concatenate([cen, h]))
+        assert abs(got - ref) < 1e-12
+        # OBB with R = I is the same box
+        got_obb = O.sd("obb", p, r, np.concatenate([cen, np.eye(3).ravel(), h]))
+        assert abs(got_obb - ref) < 1e-12
+        # rotated box: compare with sampled surface in the box frame
+        R = I._random_rotation(rng)
+        got_rot = O.sd("obb", p, r, np.concatenate([cen, R.ravel(), h]))
+        bf = _brute_box(p - cen, R, h) - r
+        assert got_rot <= bf + 1e-12 and got_rot >= bf - 0.02 * h.max()
+
+
+def test_capsule_and_cylinder_against_brute_force(oracle_lib):
+    from scipy.optimize import minimize_scalar
+    O = oracle_lib
+    rng = np.random.default_rng(4)
+    for _ in range(40):
+        p0 = rng.uniform(-0.5, 0.5, 3)
+        p1 = p0 + rng.normal(size=3) * 0.3
+        rho = rng.uniform(0.02, 0.2)
+        c = rng.uniform(-0.8, 0.8, 3)
+        f = lambda t: np.linalg.norm(c - (p0 + t * (p1 - p0)))
+        t = minimize_scalar(f, bounds=(0, 1), method="bounded", options=dict(xatol=1e-12))
+        ref = max(min(f(t.x), f(0.0), f(1.0)) - rho, 0.0) - 0.05
+        got = O.sd("capsule", c, 0.05, np.concatenate([p0, p1, [rho]]))
+        assert abs(got - ref) < 1e-7
+        # solid cylinder: sample its surface (side, caps) densely
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        hl = rng.uniform(0.05, 0.3)
+        got = O.sd("cylinder", c, 0.0, np.concatenate([p0, u, [hl, rho]]))
+        a_ = rng.normal(size=3)
+        e1 = np.cross(u, a_)
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(u, e1)
+        ang = np.linspace(0, 2 * np.pi, 721)
+        ts = np.linspace(-hl, hl, 301)
+        rr = np.linspace(0, rho, 101)
+        ring = np.cos(ang)[:, None] * e1 + np.sin(ang)[:, None] * e2
+        side = (p0 + ts[:, None, None] * u + rho * ring[None]).reshape(-1, 3)
+        caps = np.concatenate([(p0 + s * hl * u + rr[:, None, None] * ring[None]).reshape(-1, 3)
+                               for s in (-1, 1)])
+        rel = c - p0
+        inside = abs(rel @ u) <= hl and np.linalg.norm(rel - (rel @ u) * u) <= rho
+        bf = 0.0 if inside else np.min(np.linalg.norm(np.concatenate([side, caps]) - c, axis=1))
+        assert got <= bf + 1e-9 and got >= bf - 5e-3
+
+
+def test_config_distance_tiny_scene(oracle_lib):
+    """One revolute joint about world z carrying one sphere 0.5 m out along
+    its x axis at height 0.2: at angle q the sphere centre is
+    (0.5 cos q, 0.5 sin q, 0.2).  A cube of half extent 0.1 centred at
+    (0, 0.8, 0.2) is 0.2 from the centre at q = pi/2."""
+    O = oracle_lib
+    rd = _chain_robot([0.0], [0.0], [0.2], [0.0], [0], 0.0, spheres=[[0.5, 0, 0, 0.05]],
+                      links=[0], lim=3.1)
+    env = I.empty_env()
+    env["aabb"] = np.array([[0, 0.8, 0.2, 0.1, 0.1, 0.1]])
+    rob, E = O.Robot(rd), O.Env(env)
+    assert abs(O.config_min_sd(rob, E, [math.pi / 2]) - (0.2 - 0.05)) < 1e-12
+    x, y = 0.5 * math.cos(0.3), 0.5 * math.sin(0.3)
+    ref = math.hypot(max(abs(x) - 0.1, 0), max(abs(y - 0.8) - 0.1, 0)) - 0.05
+    assert abs(O.config_min_sd(rob, E, [0.3]) - ref) < 1e-12
+    col, msd = O.fk_cc_batch(rob, E, np.array([[math.pi / 2], [0.3], [-math.pi / 2]]))
+    assert list(col) == [0, 0, 0]
+
+
+def test_motion_verdicts_tiny_scene(oracle_lib):
+    """The same one-joint robot sweeping its sphere: a motion through the box's
+    bearing collides, one on the far side is valid (constraint NONE)."""
+    O = oracle_lib
+    rd = _chain_robot([0.0], [0.0], [0.2], [0.0], [0], 0.0, spheres=[[0.5, 0, 0, 0.05]],
+                      links=[0], lim=3.1)
+    env = I.empty_env()
+    env["aabb"] = np.array([[0, 0.5, 0.2, 0.05, 0.05, 0.05]])
+    rob, E, c = O.Robot(rd), O.Env(env), O.Constraint(I.no_constraint())
+    prm = O.params(W=32)
+    q_from = np.array([[1.0], [-1.0]])
+    q_to = np.array([[2.2], [-2.2]])
+    out = O.project_validate_motions(rob, E, c, prm, q_from, q_to)
+    assert list(out["status"]) == [O.MOTION_COLLISION, O.MOTION_VALID]
+    assert np.all(out["iters"] == 1)
