@@ -1,0 +1,185 @@
+/* cprrtc.h -- C ABI of the MI355X (gfx950) library for batched constrained
+ * motion projection and validation, the data-parallel hot path of cpRRTC
+ * (Hu, Wang, Christensen: "cpRRTC: GPU-Parallel RRT-Connect for Constrained
+ * Motion Planning", arXiv 2505.06791).
+ *
+ * Conventions shared by every call
+ *   - Plain C types only.  Arrays are row-major.  Angles in radians, lengths
+ *     in metres.
+ *   - Pointers named d_* are device (HBM) pointers; all others are host.
+ *     The library never frees or retains a caller's pointer beyond the call
+ *     (device-pointer calls: beyond completion of the work on `stream`).
+ *   - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *     Device-pointer calls are asynchronous on that stream; plan() is
+ *     synchronous.
+ *   - Every call returns a status code (CP_OK = 0, < 0 errors).  No exception
+ *     or abort crosses this boundary.  cp_last_error() describes the last
+ *     failure on the calling thread.
+ *   - Handles (cp_robot, cp_env) are immutable after creation and may be
+ *     shared by threads; calls on different streams may overlap.
+ */
+#ifndef CPRRTC_H
+#define CPRRTC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+enum {
+  CP_OK = 0,
+  CP_NO_SOLUTION = 1,      /* plan(): budget exhausted without a path (not an error) */
+  CP_E_ARG = -1,           /* malformed argument (NULL, size, layout) */
+  CP_E_START = -2,         /* plan(): start outside limits, off the manifold or colliding */
+  CP_E_GOAL = -3,          /* plan(): goal outside limits, off the manifold or colliding */
+  CP_E_CAPACITY = -4,      /* output or tree capacity too small */
+  CP_E_RTC = -5,           /* runtime compilation failed */
+  CP_E_HIP = -6,           /* HIP runtime error */
+  CP_E_UNSUPPORTED = -7    /* DOF, chain count or waypoint count this build does not serve */
+};
+
+/* Per-motion outcome written by project_validate_motions (data, not errors). */
+enum { CP_MOTION_VALID = 0, CP_MOTION_PROJ_FAIL = 1, CP_MOTION_COLLISION = 2 };
+
+enum { CP_REVOLUTE = 0, CP_PRISMATIC = 1 };
+enum { CP_CON_NONE = 0, CP_CON_POSE = 1, CP_CON_REL_POSE = 2 };
+
+/* flags */
+enum { CP_NO_EARLY_EXIT = 1 };   /* evaluate every sphere-primitive pair */
+
+/* ------------------------------------------------------------ descriptors */
+
+/* Serial chain(s) in modified Denavit-Hartenberg form (Craig):
+ *   T_i = RotX(alpha_{i-1}) TransX(a_{i-1}) RotZ(theta_i) TransZ(d_i),
+ * a revolute joint adds q_i to theta_i, a prismatic joint adds q_i to d_i.
+ * Frame i of chain c is base_c T_1 ... T_i over that chain's joints; the end
+ * effector is the last frame of the chain times tool_c.  The paper runs
+ * forward kinematics per waypoint (Section III) without fixing a model.
+ * All arrays host, double, copied by cp_robot_create. */
+typedef struct cp_robot_desc {
+  int32_t dof;               /* total joints, 1..16 */
+  int32_t n_chains;          /* 1, or 2 for two arms on one base */
+  const int32_t* joint_type; /* [dof] CP_REVOLUTE / CP_PRISMATIC */
+  const int32_t* joint_chain;/* [dof] chain of each joint; non-decreasing */
+  const double* alpha;       /* [dof] alpha_{i-1} */
+  const double* a;           /* [dof] a_{i-1} */
+  const double* d;           /* [dof] constant part of d_i */
+  const double* theta;       /* [dof] constant part of theta_i */
+  const double* q_lo;        /* [dof] joint limits */
+  const double* q_hi;        /* [dof] */
+  const double* base;        /* [n_chains][16] homogeneous, row-major */
+  const double* tool;        /* [n_chains][16] */
+  int32_t n_spheres;         /* robot collision spheres, 1..1024 */
+  const int32_t* sphere_link;/* [n_spheres] joint whose frame carries the sphere */
+  const double* sphere;      /* [n_spheres][4] centre in that frame, radius > 0 */
+} cp_robot_desc;
+
+/* Environment primitives (solid).  Host, double, copied by cp_env_create.
+ * Counts may be 0 (pointer then ignored). */
+typedef struct cp_env_desc {
+  int32_t n_aabb;      const double* aabb;      /* [n][6]  centre, half extents */
+  int32_t n_obb;       const double* obb;       /* [n][15] centre, R (row-major; its
+                                                   columns are the box axes), half extents */
+  int32_t n_sphere;    const double* sphere;    /* [n][4]  centre, radius */
+  int32_t n_capsule;   const double* capsule;   /* [n][7]  p0, p1, radius */
+  int32_t n_cylinder;  const double* cylinder;  /* [n][8]  centre, unit axis, half length, radius */
+} cp_env_desc;
+
+/* Task constraint (Evaluation section: end-effector axes are locked; a plane
+ * locks one position axis, a line two, fixed orientation the angular ones).
+ *   CP_CON_POSE:     chain 0's end effector seen from `frame`:
+ *                    x = (Rc^T (p - pc), roll, pitch, yaw of Rc^T R), with
+ *                    R = Rz(yaw) Ry(pitch) Rx(roll); error = (x - target) on
+ *                    the axes set in mask, angles wrapped into (-pi, pi].
+ *   CP_CON_REL_POSE: end effector 2 seen from end effector 1:
+ *                    p' = R1^T (p2 - p1), R' = R1^T R2; error = (p' - p*,
+ *                    roll/pitch/yaw of R*^T R') on the masked axes, where
+ *                    rel_target = [R* p*].
+ *   CP_CON_NONE:     no task error (only the spacing term acts). */
+typedef struct cp_constraint {
+  int32_t kind;
+  int32_t mask[6];          /* x y z roll pitch yaw: 1 = locked */
+  double frame[16];         /* CP_CON_POSE: constraint frame in world, row-major */
+  double target[6];         /* CP_CON_POSE: locked values in that frame */
+  double rel_target[16];    /* CP_CON_REL_POSE: pose of end effector 2 in end effector 1 */
+} cp_constraint;
+
+/* Parameters of Algorithm 1 (ParallelProject).  The paper names them but
+ * gives no values; cp_proj_params_default() fills the defaults shown. */
+typedef struct cp_proj_params {
+  int32_t W;          /* waypoints per motion incl. the fixed start: 32 or 64 (64) */
+  int32_t max_iters;  /* iteration budget (32) */
+  double tau;         /* spacing target = interpolation step (0.05) */
+  double tau_sm;      /* spacing slack: a waypoint is valid if its spacing < tau + tau_sm (0.025) */
+  double tau_task;    /* task tolerance on the infinity norm of the error (1e-3) */
+  double alpha;       /* step factor (1.0) */
+  double lambda;      /* damping of the least-squares step (1e-2) */
+  int32_t sphere_batch; /* spheres per collision batch between early-exit polls: 4 or 8 (8) */
+} cp_proj_params;
+
+typedef struct cp_robot cp_robot;   /* opaque; device copy of a cp_robot_desc */
+typedef struct cp_env cp_env;       /* opaque; device copy of a cp_env_desc */
+
+/* ------------------------------------------------------------ handles */
+int cp_robot_create(const cp_robot_desc* desc, cp_robot** out);
+void cp_robot_destroy(cp_robot* robot);
+int cp_env_create(const cp_env_desc* desc, cp_env** out);
+void cp_env_destroy(cp_env* env);
+void cp_proj_params_default(cp_proj_params* p);
+const char* cp_last_error(void);    /* thread-local; valid until the next call on this thread */
+
+/* ------------------------------------------------------------ hot path */
+
+/* Forward kinematics of every collision sphere and sphere-vs-primitive
+ * collision check, one configuration per lane (Sections I and IV: each
+ * waypoint's FK and CC).  A configuration collides iff some pair has
+ * signed distance <= 0 (distance from the sphere centre to the solid minus
+ * the sphere radius).
+ *   d_q        [n_cfg][dof] float32 configurations
+ *   d_collide  [n_cfg] 1 = collides, 0 = free
+ *   d_min_sd   [n_cfg] nullable; if given, every pair is evaluated and the
+ *              minimum signed distance is written
+ *   flags      CP_NO_EARLY_EXIT: evaluate every pair even after a collision
+ * Errors: CP_E_ARG (NULL handle/pointer, n_cfg < 0), CP_E_UNSUPPORTED (dof),
+ * CP_E_HIP (launch failure). n_cfg = 0 is a no-op. */
+int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const float* d_q,
+                uint8_t* d_collide, float* d_min_sd, int32_t flags, void* stream);
+
+/* Motion projection and validation (Section III and Algorithm 1; Section IV).
+ * For each motion i: W waypoints xi[k] = q_from + (k/(W-1)) (q_to - q_from),
+ * ParallelProject with xi[0] fixed and the end free (Jacobi snapshot,
+ * validated prefix frozen, damped least-squares task step, smoothing step
+ * (||xi[k]-xi[k-1]|| - tau) (xi[k]-xi[k-1]), clamp to limits), then FK+CC of
+ * waypoints 1..W-1 with an early exit of the whole motion on any collision.
+ *   d_q_from, d_q_to [n_motions][dof] float32
+ *   d_xi      [n_motions][W][dof] float32 out: projected segment (on
+ *             CP_MOTION_PROJ_FAIL: the last iterate)
+ *   d_status  [n_motions] int32 out: CP_MOTION_*
+ *   d_iters   [n_motions] int32 out, nullable: ParallelProject iterations
+ *   d_work    [2] uint64 in/out, nullable: work counters the call ADDS to
+ *             (the caller zeroes them): [0] = (waypoint, robot sphere)
+ *             collision evaluations, each against every primitive (early
+ *             exit included); [1] = waypoint updates of ParallelProject
+ *             (waypoints past the frozen prefix, summed over iterations)
+ *   params    NULL = defaults
+ * Errors: CP_E_ARG, CP_E_UNSUPPORTED (dof, W), CP_E_HIP. */
+int project_validate_motions(const cp_robot* robot, const cp_env* env,
+                             const cp_constraint* constraint, const cp_proj_params* params,
+                             int32_t n_motions, const float* d_q_from, const float* d_q_to,
+                             float* d_xi, int32_t* d_status, int32_t* d_iters, uint64_t* d_work,
+                             int32_t flags, void* stream);
+
+/* Projection of single configurations onto the manifold (puts start, goal
+ * and samples on it): q <- clamp(q - alpha g_task) until ||e||_inf < tol,
+ * at most max_iters steps.
+ *   d_q_in, d_q_out [n][dof] float32; d_status [n] int32: 1 converged, 0 not.
+ * Errors: CP_E_ARG, CP_E_UNSUPPORTED, CP_E_HIP. */
+int project_configs(const cp_robot* robot, const cp_constraint* constraint, int32_t n,
+                    const float* d_q_in, float* d_q_out, int32_t* d_status, double tol,
+                    int32_t max_iters, double alpha, double lambda, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,211 @@
+"""ctypes binding of libcprrtc.so (the C ABI declared in include/cprrtc.h).
+
+Argument marshalling only: robot/scene/constraint dictionaries (layout in
+`paper_2505_06791_amd.inputs`) become the C descriptors, torch tensors pass
+their device pointers and the current HIP stream.  Every step of the hot path
+runs in the library's kernels; if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcprrtc.so")
+
+CP_OK, CP_NO_SOLUTION = 0, 1
+CP_E_ARG, CP_E_START, CP_E_GOAL, CP_E_CAPACITY = -1, -2, -3, -4
+CP_E_RTC, CP_E_HIP, CP_E_UNSUPPORTED = -5, -6, -7
+MOTION_VALID, MOTION_PROJ_FAIL, MOTION_COLLISION = 0, 1, 2
+NO_EARLY_EXIT = 1
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class CprrtcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"cprrtc error {code}: {msg}")
+        self.code = code
+
+
+class RobotDesc(C.Structure):
+    _fields_ = [("dof", C.c_int32), ("n_chains", C.c_int32), ("joint_type", _ip),
+                ("joint_chain", _ip), ("alpha", _dp), ("a", _dp), ("d", _dp), ("theta", _dp),
+                ("q_lo", _dp), ("q_hi", _dp), ("base", _dp), ("tool", _dp),
+                ("n_spheres", C.c_int32), ("sphere_link", _ip), ("sphere", _dp)]
+
+
+class EnvDesc(C.Structure):
+    _fields_ = [("n_aabb", C.c_int32), ("aabb", _dp), ("n_obb", C.c_int32), ("obb", _dp),
+                ("n_sphere", C.c_int32), ("sphere", _dp), ("n_capsule", C.c_int32),
+                ("capsule", _dp), ("n_cylinder", C.c_int32), ("cylinder", _dp)]
+
+
+class Constraint(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("mask", C.c_int32 * 6), ("frame", C.c_double * 16),
+                ("target", C.c_double * 6), ("rel_target", C.c_double * 16)]
+
+
+class ProjParams(C.Structure):
+    _fields_ = [("W", C.c_int32), ("max_iters", C.c_int32), ("tau", C.c_double),
+                ("tau_sm", C.c_double), ("tau_task", C.c_double), ("alpha", C.c_double),
+                ("lam", C.c_double), ("sphere_batch", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcprrtc.so (built by __graft_entry__.build()); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise CprrtcError(CP_E_HIP, f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        L.cp_last_error.restype = C.c_char_p
+        vp = C.c_void_p
+        L.cp_robot_create.argtypes = [C.POINTER(RobotDesc), C.POINTER(vp)]
+        L.cp_env_create.argtypes = [C.POINTER(EnvDesc), C.POINTER(vp)]
+        L.cp_robot_destroy.argtypes = [vp]
+        L.cp_env_destroy.argtypes = [vp]
+        L.cp_proj_params_default.argtypes = [C.POINTER(ProjParams)]
+        L.fk_cc_batch.argtypes = [vp, vp, C.c_int32, vp, vp, vp, C.c_int32, vp]
+        L.project_validate_motions.argtypes = [vp, vp, C.POINTER(Constraint), C.POINTER(ProjParams),
+                                               C.c_int32, vp, vp, vp, vp, vp, vp, C.c_int32, vp]
+        L.project_configs.argtypes = [vp, C.POINTER(Constraint), C.c_int32, vp, vp, vp,
+                                      C.c_double, C.c_int32, C.c_double, C.c_double, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise CprrtcError(rc, lib().cp_last_error().decode())
+    return rc
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _i32(x):
+    return np.ascontiguousarray(x, dtype=np.int32)
+
+
+class Robot:
+    """Device copy of a robot dictionary (cp_robot handle)."""
+
+    def __init__(self, rd: dict):
+        keep = [_i32(rd["joint_type"]), _i32(rd["joint_chain"]), _f64(rd["alpha"]), _f64(rd["a"]),
+                _f64(rd["d"]), _f64(rd["theta"]), _f64(rd["lo"]), _f64(rd["hi"]),
+                _f64(rd["base"]).reshape(-1), _f64(rd["tool"]).reshape(-1),
+                _i32(rd["sphere_link"]), _f64(rd["sphere"]).reshape(-1)]
+        jt, jc, al, a, d, th, lo, hi, base, tool, sl, sp = keep
+        desc = RobotDesc(int(rd["dof"]), int(rd["n_chains"]), jt.ctypes.data_as(_ip),
+                         jc.ctypes.data_as(_ip), al.ctypes.data_as(_dp), a.ctypes.data_as(_dp),
+                         d.ctypes.data_as(_dp), th.ctypes.data_as(_dp), lo.ctypes.data_as(_dp),
+                         hi.ctypes.data_as(_dp), base.ctypes.data_as(_dp), tool.ctypes.data_as(_dp),
+                         len(sl), sl.ctypes.data_as(_ip), sp.ctypes.data_as(_dp))
+        h = C.c_void_p()
+        _check(lib().cp_robot_create(C.byref(desc), C.byref(h)))
+        self.handle = h
+        self.dof = int(rd["dof"])
+        self.n_spheres = len(sl)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.cp_robot_destroy(self.handle)
+            self.handle = None
+
+
+class Env:
+    """Device copy of a scene dictionary (cp_env handle)."""
+
+    def __init__(self, ed: dict):
+        widths = dict(aabb=6, obb=15, sphere=4, capsule=7, cylinder=8)
+        arrs = {k: _f64(np.asarray(ed[k]).reshape(-1, w)) for k, w in widths.items()}
+        args = []
+        for k in ("aabb", "obb", "sphere", "capsule", "cylinder"):
+            args += [len(arrs[k]), arrs[k].ctypes.data_as(_dp)]
+        desc = EnvDesc(*args)
+        h = C.c_void_p()
+        _check(lib().cp_env_create(C.byref(desc), C.byref(h)))
+        self.handle = h
+        self.counts = {k: len(v) for k, v in arrs.items()}
+        self.n_prims = sum(self.counts.values())
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.cp_env_destroy(self.handle)
+            self.handle = None
+
+
+def constraint(cd: dict) -> Constraint:
+    c = Constraint()
+    c.kind = int(cd["kind"])
+    fr = np.asarray(cd["frame"], np.float64).reshape(-1)
+    rt = np.asarray(cd["rel_target"], np.float64).reshape(-1)
+    for i in range(6):
+        c.mask[i] = int(cd["mask"][i])
+        c.target[i] = float(cd["target"][i])
+    for i in range(16):
+        c.frame[i] = fr[i]
+        c.rel_target[i] = rt[i]
+    return c
+
+
+def proj_params(W=64, max_iters=32, tau=0.05, tau_sm=0.025, tau_task=1e-3, alpha=1.0, lam=1e-2,
+                sphere_batch=8) -> ProjParams:
+    return ProjParams(W, max_iters, tau, tau_sm, tau_task, alpha, lam, sphere_batch)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype):
+    import torch
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise CprrtcError(CP_E_ARG, f"expected a contiguous {dtype} CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ hot path
+
+def fk_cc_batch(robot: Robot, env: Env, q, collide, min_sd=None, flags: int = 0, stream=None):
+    """q: [N, dof] float32 (device); collide: [N] uint8 (device); min_sd: [N] float32 or None."""
+    import torch
+    n = q.shape[0]
+    _check(lib().fk_cc_batch(robot.handle, env.handle, n, _dev(q, torch.float32),
+                             _dev(collide, torch.uint8),
+                             _dev(min_sd, torch.float32) if min_sd is not None else None,
+                             flags, _stream(stream)))
+
+
+def project_validate_motions(robot: Robot, env: Env, con: Constraint, prm: ProjParams,
+                             q_from, q_to, xi, status, iters=None, work=None, flags: int = 0,
+                             stream=None):
+    """q_from/q_to: [M, dof] float32; xi: [M, W, dof] float32; status/iters: [M] int32;
+    work: [2] int64 counters the call adds to (see include/cprrtc.h)."""
+    import torch
+    m = q_from.shape[0]
+    _check(lib().project_validate_motions(
+        robot.handle, env.handle, C.byref(con), C.byref(prm), m, _dev(q_from, torch.float32),
+        _dev(q_to, torch.float32), _dev(xi, torch.float32), _dev(status, torch.int32),
+        _dev(iters, torch.int32) if iters is not None else None,
+        _dev(work, torch.int64) if work is not None else None, flags, _stream(stream)))
+
+
+def project_configs(robot: Robot, con: Constraint, q_in, q_out, status, tol=1e-5, max_iters=100,
+                    alpha=1.0, lam=1e-2, stream=None):
+    """Single-configuration projection; status[i] = 1 when ||e||_inf < tol was reached."""
+    import torch
+    n = q_in.shape[0]
+    _check(lib().project_configs(robot.handle, C.byref(con), n, _dev(q_in, torch.float32),
+                                 _dev(q_out, torch.float32), _dev(status, torch.int32), tol,
+                                 max_iters, alpha, lam, _stream(stream)))

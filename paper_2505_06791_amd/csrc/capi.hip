@@ -1,0 +1,362 @@
+// C ABI of libcprrtc.so: argument checking, handle lifecycle (robot and
+// scene copies in HBM), error mapping and kernel dispatch.  Every exported
+// function catches everything and returns a status code.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cprrtc.h"
+#include "device.h"
+#include "kernels.h"
+
+using namespace cprrtc;
+
+struct cp_robot {
+  RobotDev host;            // host copy (dispatch reads dof, chains)
+  RobotDev* dev = nullptr;  // device copy
+  float4* spheres = nullptr;
+};
+
+struct cp_env {
+  EnvDev view;              // device pointers + counts, passed by value to kernels
+  float4* block = nullptr;  // one allocation holding every primitive
+  int total = 0;
+};
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(CP_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void copy34(float* dst, const double* m16) {
+  for (int i = 0; i < 3; ++i)
+    for (int c = 0; c < 4; ++c) dst[4 * i + c] = (float)m16[4 * i + c];
+}
+
+int make_constraint(const cp_constraint* c, const cp_robot* robot, ConDev* out) {
+  std::memset(out, 0, sizeof *out);
+  if (!c) {
+    out->kind = KIND_NONE;
+    return CP_OK;
+  }
+  if (c->kind < CP_CON_NONE || c->kind > CP_CON_REL_POSE)
+    return fail(CP_E_ARG, "constraint kind %d unknown", c->kind);
+  out->kind = c->kind;
+  for (int i = 0; i < 6; ++i) out->mask[i] = c->mask[i] ? 1.0f : 0.0f;
+  if (c->kind == CP_CON_POSE) {
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) out->Rt[3 * i + k] = (float)c->frame[4 * k + i];
+    for (int i = 0; i < 3; ++i) out->pc[i] = (float)c->frame[4 * i + 3];
+    for (int i = 0; i < 6; ++i) out->target[i] = (float)c->target[i];
+  } else if (c->kind == CP_CON_REL_POSE) {
+    if (robot->host.n_chains != 2)
+      return fail(CP_E_ARG, "relative-pose constraint needs a two-chain robot");
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) out->Rt[3 * i + k] = (float)c->rel_target[4 * k + i];
+    for (int i = 0; i < 3; ++i) out->target[i] = (float)c->rel_target[4 * i + 3];
+  }
+  return CP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cp_last_error(void) { return g_error.c_str(); }
+
+void cp_proj_params_default(cp_proj_params* p) {
+  if (!p) return;
+  p->W = 64;
+  p->max_iters = 32;
+  p->tau = 0.05;
+  p->tau_sm = 0.025;
+  p->tau_task = 1e-3;
+  p->alpha = 1.0;
+  p->lambda = 1e-2;
+  p->sphere_batch = 8;
+}
+
+int cp_robot_create(const cp_robot_desc* d, cp_robot** out) {
+  try {
+    if (!d || !out) return fail(CP_E_ARG, "cp_robot_create: NULL argument");
+    *out = nullptr;
+    if (d->dof < 1 || d->dof > kMaxDof) return fail(CP_E_UNSUPPORTED, "dof %d not in 1..%d", d->dof, kMaxDof);
+    if (d->n_chains < 1 || d->n_chains > kMaxChains)
+      return fail(CP_E_UNSUPPORTED, "n_chains %d not in 1..%d", d->n_chains, kMaxChains);
+    if (!d->joint_type || !d->joint_chain || !d->alpha || !d->a || !d->d || !d->theta || !d->q_lo ||
+        !d->q_hi || !d->base || !d->tool || !d->sphere_link || !d->sphere)
+      return fail(CP_E_ARG, "cp_robot_create: NULL array");
+    if (d->n_spheres < 1 || d->n_spheres > kMaxSpheres)
+      return fail(CP_E_UNSUPPORTED, "n_spheres %d not in 1..%d", d->n_spheres, kMaxSpheres);
+    RobotDev h;
+    std::memset(&h, 0, sizeof h);
+    h.dof = d->dof;
+    h.n_chains = d->n_chains;
+    int prev = 0;
+    std::vector<int> count(d->n_chains, 0);
+    for (int j = 0; j < d->dof; ++j) {
+      const int c = d->joint_chain[j];
+      if (c < 0 || c >= d->n_chains || c < prev)
+        return fail(CP_E_ARG, "joint_chain must be non-decreasing in [0, n_chains)");
+      prev = c;
+      count[c]++;
+      if (d->joint_type[j] != CP_REVOLUTE && d->joint_type[j] != CP_PRISMATIC)
+        return fail(CP_E_ARG, "joint %d: unknown type %d", j, d->joint_type[j]);
+      if (!(d->q_lo[j] <= d->q_hi[j])) return fail(CP_E_ARG, "joint %d: q_lo > q_hi", j);
+      h.ca[j] = (float)std::cos(d->alpha[j]);
+      h.sa[j] = (float)std::sin(d->alpha[j]);
+      h.a[j] = (float)d->a[j];
+      h.d0[j] = (float)d->d[j];
+      h.th0[j] = (float)d->theta[j];
+      h.lo[j] = (float)d->q_lo[j];
+      h.hi[j] = (float)d->q_hi[j];
+      h.prismatic[j] = d->joint_type[j] == CP_PRISMATIC;
+    }
+    h.chain_begin[0] = 0;
+    for (int c = 0; c < d->n_chains; ++c) {
+      if (count[c] == 0) return fail(CP_E_ARG, "chain %d has no joints", c);
+      h.chain_begin[c + 1] = h.chain_begin[c] + count[c];
+    }
+    for (int c = d->n_chains + 1; c <= kMaxChains; ++c) h.chain_begin[c] = d->dof;
+    for (int c = 0; c < d->n_chains; ++c) {
+      copy34(h.base[c], d->base + 16 * c);
+      copy34(h.tool[c], d->tool + 16 * c);
+    }
+    // spheres grouped by the joint frame that carries them
+    std::vector<int> order(d->n_spheres);
+    for (int s = 0; s < d->n_spheres; ++s) {
+      const int l = d->sphere_link[s];
+      if (l < 0 || l >= d->dof) return fail(CP_E_ARG, "sphere %d: link %d out of range", s, l);
+      if (!(d->sphere[4 * s + 3] > 0.0)) return fail(CP_E_ARG, "sphere %d: radius must be > 0", s);
+      order[s] = s;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return d->sphere_link[x] < d->sphere_link[y]; });
+    std::vector<float4> sph(d->n_spheres);
+    for (int s = 0; s < d->n_spheres; ++s) {
+      const double* src = d->sphere + 4 * order[s];
+      sph[s] = make_float4((float)src[0], (float)src[1], (float)src[2], (float)src[3]);
+    }
+    for (int j = 0; j <= d->dof; ++j) h.sph_begin[j] = 0;
+    for (int s = 0; s < d->n_spheres; ++s) h.sph_begin[d->sphere_link[s] + 1]++;
+    for (int j = 0; j < d->dof; ++j) h.sph_begin[j + 1] += h.sph_begin[j];
+    for (int j = d->dof + 1; j <= kMaxDof; ++j) h.sph_begin[j] = h.sph_begin[d->dof];
+    h.n_spheres = d->n_spheres;
+
+    cp_robot* r = new (std::nothrow) cp_robot;
+    if (!r) return fail(CP_E_ARG, "out of host memory");
+    r->host = h;
+    hipError_t e = hipMalloc((void**)&r->dev, sizeof(RobotDev));
+    if (e == hipSuccess) e = hipMalloc((void**)&r->spheres, sizeof(float4) * sph.size());
+    if (e == hipSuccess) e = hipMemcpy(r->dev, &h, sizeof h, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(r->spheres, sph.data(), sizeof(float4) * sph.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      cp_robot_destroy(r);
+      return hip_fail(e, "cp_robot_create");
+    }
+    *out = r;
+    return CP_OK;
+  } catch (...) {
+    return fail(CP_E_ARG, "cp_robot_create: unexpected exception");
+  }
+}
+
+void cp_robot_destroy(cp_robot* r) {
+  if (!r) return;
+  if (r->dev) (void)hipFree(r->dev);
+  if (r->spheres) (void)hipFree(r->spheres);
+  delete r;
+}
+
+int cp_env_create(const cp_env_desc* d, cp_env** out) {
+  try {
+    if (!d || !out) return fail(CP_E_ARG, "cp_env_create: NULL argument");
+    *out = nullptr;
+    const int counts[5] = {d->n_aabb, d->n_obb, d->n_sphere, d->n_capsule, d->n_cylinder};
+    const double* src[5] = {d->aabb, d->obb, d->sphere, d->capsule, d->cylinder};
+    const int slots[5] = {2, 4, 1, 2, 2};   // float4 per primitive
+    size_t total = 0;
+    for (int t = 0; t < 5; ++t) {
+      if (counts[t] < 0) return fail(CP_E_ARG, "negative primitive count");
+      if (counts[t] > 0 && !src[t]) return fail(CP_E_ARG, "NULL primitive array with count %d", counts[t]);
+      total += (size_t)counts[t] * slots[t];
+    }
+    std::vector<float4> buf(std::max<size_t>(total, 1));
+    size_t off[5];
+    size_t at = 0;
+    for (int t = 0; t < 5; ++t) {
+      off[t] = at;
+      at += (size_t)counts[t] * slots[t];
+    }
+    for (int i = 0; i < d->n_aabb; ++i) {
+      const double* p = d->aabb + 6 * i;
+      buf[off[0] + 2 * i] = make_float4((float)p[0], (float)p[1], (float)p[2], 0.f);
+      buf[off[0] + 2 * i + 1] = make_float4((float)p[3], (float)p[4], (float)p[5], 0.f);
+    }
+    for (int i = 0; i < d->n_obb; ++i) {
+      const double* p = d->obb + 15 * i;
+      buf[off[1] + 4 * i] = make_float4((float)p[0], (float)p[1], (float)p[2], 0.f);
+      for (int c = 0; c < 3; ++c)  // box axis c = column c of R
+        buf[off[1] + 4 * i + 1 + c] = make_float4((float)p[3 + c], (float)p[6 + c], (float)p[9 + c],
+                                                  (float)p[12 + c]);
+    }
+    for (int i = 0; i < d->n_sphere; ++i) {
+      const double* p = d->sphere + 4 * i;
+      buf[off[2] + i] = make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[3]);
+    }
+    for (int i = 0; i < d->n_capsule; ++i) {
+      const double* p = d->capsule + 7 * i;
+      const double dx = p[3] - p[0], dy = p[4] - p[1], dz = p[5] - p[2];
+      const double dd = dx * dx + dy * dy + dz * dz;
+      buf[off[3] + 2 * i] = make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[6]);
+      buf[off[3] + 2 * i + 1] = make_float4((float)dx, (float)dy, (float)dz, dd > 0 ? (float)(1.0 / dd) : 0.f);
+    }
+    for (int i = 0; i < d->n_cylinder; ++i) {
+      const double* p = d->cylinder + 8 * i;
+      const double n = std::sqrt(p[3] * p[3] + p[4] * p[4] + p[5] * p[5]);
+      if (std::fabs(n - 1.0) > 1e-6) return fail(CP_E_ARG, "cylinder %d: axis is not a unit vector", i);
+      buf[off[4] + 2 * i] = make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[6]);
+      buf[off[4] + 2 * i + 1] = make_float4((float)p[3], (float)p[4], (float)p[5], (float)p[7]);
+    }
+    cp_env* env = new (std::nothrow) cp_env;
+    if (!env) return fail(CP_E_ARG, "out of host memory");
+    hipError_t e = hipMalloc((void**)&env->block, sizeof(float4) * buf.size());
+    if (e == hipSuccess) e = hipMemcpy(env->block, buf.data(), sizeof(float4) * buf.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      cp_env_destroy(env);
+      return hip_fail(e, "cp_env_create");
+    }
+    env->total = (int)total;
+    EnvDev& v = env->view;
+    v.n_aabb = d->n_aabb; v.n_obb = d->n_obb; v.n_sph = d->n_sphere;
+    v.n_cap = d->n_capsule; v.n_cyl = d->n_cylinder;
+    v.aabb = env->block + off[0];
+    v.obb = env->block + off[1];
+    v.sph = env->block + off[2];
+    v.cap = env->block + off[3];
+    v.cyl = env->block + off[4];
+    *out = env;
+    return CP_OK;
+  } catch (...) {
+    return fail(CP_E_ARG, "cp_env_create: unexpected exception");
+  }
+}
+
+void cp_env_destroy(cp_env* env) {
+  if (!env) return;
+  if (env->block) (void)hipFree(env->block);
+  delete env;
+}
+
+int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const float* d_q,
+                uint8_t* d_collide, float* d_min_sd, int32_t flags, void* stream) {
+  try {
+    if (!robot || !env) return fail(CP_E_ARG, "fk_cc_batch: NULL handle");
+    if (n_cfg < 0) return fail(CP_E_ARG, "fk_cc_batch: n_cfg < 0");
+    if (n_cfg == 0) return CP_OK;
+    if (!d_q || !d_collide) return fail(CP_E_ARG, "fk_cc_batch: NULL buffer");
+    const bool early = !(flags & CP_NO_EARLY_EXIT);
+    hipError_t e = launch_fk_cc(robot->dev, robot->spheres, env->view, n_cfg, d_q, d_collide,
+                                d_min_sd, early, 8, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fk_cc_batch launch");
+    return CP_OK;
+  } catch (...) {
+    return fail(CP_E_ARG, "fk_cc_batch: unexpected exception");
+  }
+}
+
+int project_validate_motions(const cp_robot* robot, const cp_env* env,
+                             const cp_constraint* constraint, const cp_proj_params* params,
+                             int32_t n_motions, const float* d_q_from, const float* d_q_to,
+                             float* d_xi, int32_t* d_status, int32_t* d_iters, uint64_t* d_work,
+                             int32_t flags, void* stream) {
+  try {
+    if (!robot || !env) return fail(CP_E_ARG, "project_validate_motions: NULL handle");
+    if (n_motions < 0) return fail(CP_E_ARG, "project_validate_motions: n_motions < 0");
+    cp_proj_params p;
+    cp_proj_params_default(&p);
+    if (params) p = *params;
+    if (p.W != 32 && p.W != 64) return fail(CP_E_UNSUPPORTED, "W = %d (supported: 32, 64)", p.W);
+    if (p.max_iters < 1) return fail(CP_E_ARG, "max_iters < 1");
+    if (!(p.tau >= 0) || !(p.tau_sm >= 0) || !(p.tau_task >= 0) || !(p.lambda >= 0) || !(p.alpha > 0))
+      return fail(CP_E_ARG, "projection parameters out of range");
+    if (p.sphere_batch != 4 && p.sphere_batch != 8)
+      return fail(CP_E_UNSUPPORTED, "sphere_batch = %d (supported: 4, 8)", p.sphere_batch);
+    if (!dof_supported(robot->host.dof))
+      return fail(CP_E_UNSUPPORTED, "projection kernels are built for dof 2, 3, 6, 7, 9, 14 (got %d)", robot->host.dof);
+    ConDev con;
+    int rc = make_constraint(constraint, robot, &con);
+    if (rc != CP_OK) return rc;
+    if (n_motions == 0) return CP_OK;
+    if (!d_q_from || !d_q_to || !d_xi || !d_status)
+      return fail(CP_E_ARG, "project_validate_motions: NULL buffer");
+    ProjDev prm;
+    prm.W = p.W;
+    prm.max_iters = p.max_iters;
+    prm.tau = (float)p.tau;
+    prm.tau_sm = (float)p.tau_sm;
+    prm.tau_task = (float)p.tau_task;
+    prm.alpha = (float)p.alpha;
+    prm.lambda2 = (float)(p.lambda * p.lambda);
+    bool supported = false;
+    hipError_t e = launch_project_validate(robot->host.dof, robot->dev, robot->spheres, env->view,
+                                           con, prm, n_motions, d_q_from, d_q_to, d_xi, d_status,
+                                           d_iters, (unsigned long long*)d_work,
+                                           !(flags & CP_NO_EARLY_EXIT), p.sphere_batch,
+                                           (hipStream_t)stream, &supported);
+    if (!supported) return fail(CP_E_UNSUPPORTED, "no kernel for dof %d with constraint kind %d", robot->host.dof, con.kind);
+    if (e != hipSuccess) return hip_fail(e, "project_validate_motions launch");
+    return CP_OK;
+  } catch (...) {
+    return fail(CP_E_ARG, "project_validate_motions: unexpected exception");
+  }
+}
+
+int project_configs(const cp_robot* robot, const cp_constraint* constraint, int32_t n,
+                    const float* d_q_in, float* d_q_out, int32_t* d_status, double tol,
+                    int32_t max_iters, double alpha, double lambda, void* stream) {
+  try {
+    if (!robot) return fail(CP_E_ARG, "project_configs: NULL handle");
+    if (n < 0 || max_iters < 0 || !(tol >= 0) || !(alpha > 0) || !(lambda >= 0))
+      return fail(CP_E_ARG, "project_configs: argument out of range");
+    if (!dof_supported(robot->host.dof))
+      return fail(CP_E_UNSUPPORTED, "projection kernels are built for dof 2, 3, 6, 7, 9, 14 (got %d)", robot->host.dof);
+    ConDev con;
+    int rc = make_constraint(constraint, robot, &con);
+    if (rc != CP_OK) return rc;
+    if (n == 0) return CP_OK;
+    if (!d_q_in || !d_q_out || !d_status) return fail(CP_E_ARG, "project_configs: NULL buffer");
+    bool supported = false;
+    hipError_t e = launch_project_configs(robot->host.dof, robot->dev, con, n, d_q_in, d_q_out,
+                                          d_status, (float)tol, max_iters, (float)alpha,
+                                          (float)(lambda * lambda), (hipStream_t)stream, &supported);
+    if (!supported) return fail(CP_E_UNSUPPORTED, "no kernel for dof %d with constraint kind %d", robot->host.dof, con.kind);
+    if (e != hipSuccess) return hip_fail(e, "project_configs launch");
+    return CP_OK;
+  } catch (...) {
+    return fail(CP_E_ARG, "project_configs: unexpected exception");
+  }
+}
+
+}  // extern "C"

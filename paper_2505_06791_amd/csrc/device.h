@@ -1,0 +1,130 @@
+// Device-side data layouts and per-lane building blocks for gfx950.
+//
+// Layout choices (all float32 on the device):
+//  * Robot and scene data are wave-uniform: every lane of a wavefront reads
+//    the same joint row or primitive, so they live in plain global memory
+//    behind const __restrict__ pointers and are fetched with scalar loads
+//    into SGPRs, where VALU instructions take them as operands directly.
+//  * Primitives are stored array-of-structs per type, padded to float4
+//    multiples, so one primitive is one s_load_dwordx8/x16.
+//  * Per-lane state (a configuration, a 3x4 frame, a sphere batch) is in
+//    VGPRs; nothing per lane goes through LDS.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cprrtc {
+
+constexpr int kMaxDof = 16;
+constexpr int kMaxChains = 2;
+constexpr int kMaxSpheres = 1024;
+
+struct RobotDev {
+  int dof;
+  int n_chains;
+  int chain_begin[kMaxChains + 1];   // joints of chain c: [chain_begin[c], chain_begin[c+1])
+  int n_spheres;
+  float base[kMaxChains][12];        // 3x4 row-major (rotation | translation)
+  float tool[kMaxChains][12];
+  float ca[kMaxDof];                 // cos(alpha_{i-1})
+  float sa[kMaxDof];                 // sin(alpha_{i-1})
+  float a[kMaxDof];
+  float d0[kMaxDof];
+  float th0[kMaxDof];
+  float lo[kMaxDof];
+  float hi[kMaxDof];
+  int prismatic[kMaxDof];
+  int sph_begin[kMaxDof + 1];        // spheres riding in joint frame j: [sph_begin[j], sph_begin[j+1])
+};
+
+struct EnvDev {
+  int n_aabb, n_obb, n_sph, n_cap, n_cyl;
+  const float4* aabb;  // 2 x float4: (centre, 0), (half extents, 0)
+  const float4* obb;   // 4 x float4: (centre, 0), (axis u, half_u), (axis v, half_v), (axis w, half_w)
+  const float4* sph;   // 1 x float4: (centre, radius)
+  const float4* cap;   // 2 x float4: (p0, radius), (p1 - p0, 1/|p1 - p0|^2 or 0)
+  const float4* cyl;   // 2 x float4: (centre, half length), (unit axis, radius)
+};
+
+enum { KIND_NONE = 0, KIND_POSE = 1, KIND_REL = 2 };
+
+struct ConDev {
+  int kind;
+  float mask[6];      // 1 locked / 0 free: x y z roll pitch yaw
+  float Rt[9];        // POSE: Rc^T; REL: R*^T (row-major)
+  float pc[3];        // POSE: constraint frame origin
+  float target[6];    // POSE: locked values; REL: p* then zeros
+};
+
+struct ProjDev {
+  int W;
+  int max_iters;
+  float tau, tau_sm, tau_task, alpha, lambda2;
+};
+
+// ------------------------------------------------------------------ frames
+
+struct Frame {
+  float r[9];   // rotation, row-major: column c is (r[c], r[3+c], r[6+c])
+  float p[3];
+};
+
+__device__ __forceinline__ void frame_from(Frame& T, const float* __restrict__ m) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T.r[3 * i + 0] = m[4 * i + 0];
+    T.r[3 * i + 1] = m[4 * i + 1];
+    T.r[3 * i + 2] = m[4 * i + 2];
+    T.p[i] = m[4 * i + 3];
+  }
+}
+
+// T <- T * RotX(alpha) * TransX(a) * RotZ(theta) * TransZ(d), done as column
+// operations on T: the twist mixes columns 1 and 2, the offset a moves along
+// column 0, the joint angle mixes columns 0 and 1, d moves along column 2.
+__device__ __forceinline__ void frame_advance(Frame& T, float ca, float sa, float a, float ct,
+                                              float st, float d) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float c1 = T.r[3 * i + 1], c2 = T.r[3 * i + 2];
+    T.r[3 * i + 1] = ca * c1 + sa * c2;
+    T.r[3 * i + 2] = ca * c2 - sa * c1;
+    T.p[i] += a * T.r[3 * i + 0];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float c0 = T.r[3 * i + 0], c1 = T.r[3 * i + 1];
+    T.r[3 * i + 0] = ct * c0 + st * c1;
+    T.r[3 * i + 1] = ct * c1 - st * c0;
+    T.p[i] += d * T.r[3 * i + 2];
+  }
+}
+
+// Joint j of the robot at joint value qj.
+__device__ __forceinline__ void joint_advance(Frame& T, const RobotDev* __restrict__ rob, int j,
+                                              float qj) {
+  const bool pri = rob->prismatic[j] != 0;
+  const float theta = rob->th0[j] + (pri ? 0.0f : qj);
+  const float d = rob->d0[j] + (pri ? qj : 0.0f);
+  float st, ct;
+  sincosf(theta, &st, &ct);
+  frame_advance(T, rob->ca[j], rob->sa[j], rob->a[j], ct, st, d);
+}
+
+// Tool frame: T_ee = T * tool.
+__device__ __forceinline__ void frame_times(const Frame& T, const float* __restrict__ m,
+                                            Frame& out) {
+  Frame B;
+  frame_from(B, m);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      out.r[3 * i + c] = T.r[3 * i + 0] * B.r[c] + T.r[3 * i + 1] * B.r[3 + c] +
+                         T.r[3 * i + 2] * B.r[6 + c];
+    out.p[i] = T.r[3 * i + 0] * B.p[0] + T.r[3 * i + 1] * B.p[1] + T.r[3 * i + 2] * B.p[2] +
+               T.p[i];
+  }
+}
+
+}  // namespace cprrtc

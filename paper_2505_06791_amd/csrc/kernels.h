@@ -1,0 +1,27 @@
+// Launch entry points of the gfx950 kernels (host side of kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace cprrtc {
+
+bool dof_supported(int dof);
+
+hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& env, int n_cfg,
+                        const float* q, uint8_t* collide, float* min_sd, bool early, int batch,
+                        hipStream_t stream);
+
+hipError_t launch_project_validate(int dof, const RobotDev* rob, const float4* sph,
+                                   const EnvDev& env, const ConDev& con, const ProjDev& prm,
+                                   int n_motions, const float* q_from, const float* q_to,
+                                   float* xi, int* status, int* iters, unsigned long long* work,
+                                   bool early, int batch, hipStream_t stream, bool* supported);
+
+hipError_t launch_project_configs(int dof, const RobotDev* rob, const ConDev& con, int n,
+                                  const float* q_in, float* q_out, int* status, float tol,
+                                  int max_iters, float alpha, float lambda2, hipStream_t stream,
+                                  bool* supported);
+
+}  // namespace cprrtc

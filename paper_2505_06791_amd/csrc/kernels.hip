@@ -1,0 +1,278 @@
+// gfx950 kernels of the hot path: fk_cc_batch, project_validate_motions,
+// project_configs.  Launch geometry is 256-lane workgroups (4 wavefronts of
+// 64); a motion of W waypoints occupies W consecutive lanes of one
+// wavefront (W = 64: one wavefront per motion, W = 32: two motions per
+// wavefront), so every exchange inside a motion is a wavefront operation
+// (shuffle for the neighbouring waypoint, ballot for validity and for the
+// collision flag) and needs neither LDS nor a barrier.
+#include "kernels.h"
+
+#include <float.h>
+
+#include "collide.h"
+#include "project.h"
+
+namespace cprrtc {
+
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------------------ FK + CC
+
+template <int B, bool SD>
+__global__ __launch_bounds__(kBlock) void fk_cc_kernel(const RobotDev* __restrict__ rob,
+                                                       const float4* __restrict__ sph, EnvDev env,
+                                                       int n_cfg, const float* __restrict__ q,
+                                                       uint8_t* __restrict__ collide,
+                                                       float* __restrict__ min_sd, int early) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool on = i < n_cfg;
+  const int dof = rob->dof;
+  const float* qi = q + (on ? i : 0) * dof;
+  bool hit;
+  float msd;
+  int n_done;
+  collide_config<B, SD, false>(rob, sph, env, qi, on, 0ull, early != 0, hit, msd, n_done);
+  if (on) {
+    collide[i] = hit ? 1 : 0;
+    if (SD) min_sd[i] = msd;
+  }
+}
+
+// ------------------------------------------------------------------ projection + validation
+
+// Algorithm 1 per motion, Jacobi form: each active lane k computes its update
+// from the snapshot (its own xi[k] and the neighbour xi[k-1] obtained by a
+// shuffle before anyone writes), validity is gathered with one ballot, prog
+// moves to the end of the contiguous valid run after it, and only lanes past
+// the new prog take their new value.  Then waypoints 1..W-1 run FK + CC with
+// the motion-wide early exit.
+template <int NDOF, int KIND, int B>
+__global__ __launch_bounds__(kBlock) void project_validate_kernel(
+    const RobotDev* __restrict__ rob, const float4* __restrict__ sph, EnvDev env, ConDev con,
+    ProjDev prm, int n_motions, const float* __restrict__ q_from, const float* __restrict__ q_to,
+    float* __restrict__ xi, int* __restrict__ status, int* __restrict__ iters,
+    unsigned long long* __restrict__ work, int early) {
+  const int W = prm.W;
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t motion = gid / W;
+  const int k = (int)(gid % W);
+  if (motion >= n_motions) return;   // whole motion segments leave together
+  const int lane = threadIdx.x & 63;
+  const int seg = lane - k;          // first lane of this motion in the wavefront
+  const uint64_t wmask = (W == 64) ? ~0ull : ((1ull << W) - 1ull);
+  const uint64_t segmask = wmask << seg;
+
+  float q[NDOF];
+  {
+    const float s = (float)k / (float)(W - 1);
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) {
+      const float a = q_from[motion * NDOF + j];
+      const float b = q_to[motion * NDOF + j];
+      q[j] = a + s * (b - a);
+    }
+  }
+
+  int prog = 0;
+  int it = 1;
+  bool ok = false;
+  unsigned long long proj_updates = 0;   // waypoint updates computed (active lanes per iteration)
+  for (; it <= prm.max_iters; ++it) {
+    proj_updates += (unsigned long long)(W - 1 - prog);
+    float qprev[NDOF];
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) qprev[j] = __shfl_up(q[j], 1, W);
+    float g[NDOF], einf;
+    task_step<NDOF, KIND>(rob, con, q, prm.lambda2, g, einf);
+    float d2 = 0.0f, dl[NDOF];
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) {
+      dl[j] = q[j] - qprev[j];
+      d2 += dl[j] * dl[j];
+    }
+    const float esm = sqrtf(d2) - prm.tau;
+    float qn[NDOF];
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j)
+      qn[j] = fminf(fmaxf(q[j] - prm.alpha * (g[j] + dl[j] * esm), rob->lo[j]), rob->hi[j]);
+    const bool valid = (k <= prog) || ((einf < prm.tau_task) && (esm < prm.tau_sm));
+    const uint64_t bits = (__ballot(valid) & segmask) >> seg;
+    const uint64_t invalid = ~bits & wmask;      // bits 0..prog are set
+    prog = invalid ? (__ffsll((unsigned long long)invalid) - 2) : W - 1;
+    if (prog == W - 1) {
+      ok = true;
+      break;
+    }
+    if (k > prog) {
+#pragma unroll
+      for (int j = 0; j < NDOF; ++j) q[j] = qn[j];
+    }
+  }
+  if (!ok) it = prm.max_iters;
+
+  float* xk = xi + (motion * W + k) * NDOF;
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) xk[j] = q[j];
+
+  int st = 1;  // CP_MOTION_PROJ_FAIL
+  int n_done = 0;
+  if (ok) {
+    bool hit;
+    float msd;
+    collide_config<B, false, true>(rob, sph, env, xk, k >= 1, segmask, early != 0, hit, msd,
+                                   n_done);
+    st = ((__ballot(hit) & segmask) != 0) ? 2 : 0;
+  }
+  if (k == 0) {
+    status[motion] = st;
+    if (iters) iters[motion] = it;
+    if (work) {
+      atomicAdd(&work[0], (unsigned long long)n_done * (unsigned long long)(W - 1));
+      atomicAdd(&work[1], proj_updates);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ single configurations
+
+template <int NDOF, int KIND>
+__global__ __launch_bounds__(kBlock) void project_configs_kernel(
+    const RobotDev* __restrict__ rob, ConDev con, int n, const float* __restrict__ q_in,
+    float* __restrict__ q_out, int* __restrict__ status, float tol, int max_iters, float alpha,
+    float lambda2) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  float q[NDOF];
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) q[j] = q_in[i * NDOF + j];
+  int ok = 0;
+  for (int it = 0; it <= max_iters; ++it) {
+    float g[NDOF], einf;
+    task_step<NDOF, KIND>(rob, con, q, lambda2, g, einf);
+    if (einf < tol) {
+      ok = 1;
+      break;
+    }
+    if (it == max_iters) break;
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j)
+      q[j] = fminf(fmaxf(q[j] - alpha * g[j], rob->lo[j]), rob->hi[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) q_out[i * NDOF + j] = q[j];
+  status[i] = ok;
+}
+
+// ------------------------------------------------------------------ launchers
+
+static unsigned blocks_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& env, int n_cfg,
+                        const float* q, uint8_t* collide, float* min_sd, bool early, int batch,
+                        hipStream_t stream) {
+  const unsigned nb = blocks_for(n_cfg);
+  if (min_sd) {
+    fk_cc_kernel<4, true><<<nb, kBlock, 0, stream>>>(rob, sph, env, n_cfg, q, collide, min_sd, 0);
+  } else if (batch == 4) {
+    fk_cc_kernel<4, false><<<nb, kBlock, 0, stream>>>(rob, sph, env, n_cfg, q, collide, nullptr, early);
+  } else {
+    fk_cc_kernel<8, false><<<nb, kBlock, 0, stream>>>(rob, sph, env, n_cfg, q, collide, nullptr, early);
+  }
+  return hipGetLastError();
+}
+
+template <int NDOF, int KIND>
+static void launch_pv_b(int batch, unsigned nb, hipStream_t stream, const RobotDev* rob,
+                        const float4* sph, const EnvDev& env, const ConDev& con,
+                        const ProjDev& prm, int n, const float* qf, const float* qt, float* xi,
+                        int* st, int* it, unsigned long long* work, int early) {
+  if (batch == 4)
+    project_validate_kernel<NDOF, KIND, 4><<<nb, kBlock, 0, stream>>>(rob, sph, env, con, prm, n, qf, qt, xi, st, it, work, early);
+  else
+    project_validate_kernel<NDOF, KIND, 8><<<nb, kBlock, 0, stream>>>(rob, sph, env, con, prm, n, qf, qt, xi, st, it, work, early);
+}
+
+template <int NDOF>
+static bool launch_pv_kind(int kind, int batch, unsigned nb, hipStream_t stream,
+                           const RobotDev* rob, const float4* sph, const EnvDev& env,
+                           const ConDev& con, const ProjDev& prm, int n, const float* qf,
+                           const float* qt, float* xi, int* st, int* it, unsigned long long* work,
+                           int early) {
+  switch (kind) {
+    case KIND_NONE: launch_pv_b<NDOF, KIND_NONE>(batch, nb, stream, rob, sph, env, con, prm, n, qf, qt, xi, st, it, work, early); return true;
+    case KIND_POSE: launch_pv_b<NDOF, KIND_POSE>(batch, nb, stream, rob, sph, env, con, prm, n, qf, qt, xi, st, it, work, early); return true;
+    case KIND_REL:
+      if constexpr (NDOF % 2 == 0) {
+        launch_pv_b<NDOF, KIND_REL>(batch, nb, stream, rob, sph, env, con, prm, n, qf, qt, xi, st, it, work, early);
+        return true;
+      }
+      return false;
+  }
+  return false;
+}
+
+bool dof_supported(int dof) {
+  switch (dof) {
+    case 2: case 3: case 6: case 7: case 9: case 14: return true;
+    default: return false;
+  }
+}
+
+hipError_t launch_project_validate(int dof, const RobotDev* rob, const float4* sph,
+                                   const EnvDev& env, const ConDev& con, const ProjDev& prm,
+                                   int n_motions, const float* q_from, const float* q_to,
+                                   float* xi, int* status, int* iters, unsigned long long* work,
+                                   bool early, int batch, hipStream_t stream, bool* supported) {
+  const unsigned nb = blocks_for((int64_t)n_motions * prm.W);
+  bool ok = false;
+  const int e = early ? 1 : 0;
+  switch (dof) {
+    case 2: ok = launch_pv_kind<2>(con.kind, batch, nb, stream, rob, sph, env, con, prm, n_motions, q_from, q_to, xi, status, iters, work, e); break;
+    case 3: ok = launch_pv_kind<3>(con.kind, batch, nb, stream, rob, sph, env, con, prm, n_motions, q_from, q_to, xi, status, iters, work, e); break;
+    case 6: ok = launch_pv_kind<6>(con.kind, batch, nb, stream, rob, sph, env, con, prm, n_motions, q_from, q_to, xi, status, iters, work, e); break;
+    case 7: ok = launch_pv_kind<7>(con.kind, batch, nb, stream, rob, sph, env, con, prm, n_motions, q_from, q_to, xi, status, iters, work, e); break;
+    case 9: ok = launch_pv_kind<9>(con.kind, batch, nb, stream, rob, sph, env, con, prm, n_motions, q_from, q_to, xi, status, iters, work, e); break;
+    case 14: ok = launch_pv_kind<14>(con.kind, batch, nb, stream, rob, sph, env, con, prm, n_motions, q_from, q_to, xi, status, iters, work, e); break;
+    default: ok = false;
+  }
+  *supported = ok;
+  return ok ? hipGetLastError() : hipSuccess;
+}
+
+template <int NDOF>
+static bool launch_pc_kind(int kind, unsigned nb, hipStream_t stream, const RobotDev* rob,
+                           const ConDev& con, int n, const float* qi, float* qo, int* st,
+                           float tol, int max_iters, float alpha, float lambda2) {
+  switch (kind) {
+    case KIND_NONE: project_configs_kernel<NDOF, KIND_NONE><<<nb, kBlock, 0, stream>>>(rob, con, n, qi, qo, st, tol, max_iters, alpha, lambda2); return true;
+    case KIND_POSE: project_configs_kernel<NDOF, KIND_POSE><<<nb, kBlock, 0, stream>>>(rob, con, n, qi, qo, st, tol, max_iters, alpha, lambda2); return true;
+    case KIND_REL:
+      if constexpr (NDOF % 2 == 0) {
+        project_configs_kernel<NDOF, KIND_REL><<<nb, kBlock, 0, stream>>>(rob, con, n, qi, qo, st, tol, max_iters, alpha, lambda2);
+        return true;
+      }
+      return false;
+  }
+  return false;
+}
+
+hipError_t launch_project_configs(int dof, const RobotDev* rob, const ConDev& con, int n,
+                                  const float* q_in, float* q_out, int* status, float tol,
+                                  int max_iters, float alpha, float lambda2, hipStream_t stream,
+                                  bool* supported) {
+  const unsigned nb = blocks_for(n);
+  bool ok = false;
+  switch (dof) {
+    case 2: ok = launch_pc_kind<2>(con.kind, nb, stream, rob, con, n, q_in, q_out, status, tol, max_iters, alpha, lambda2); break;
+    case 3: ok = launch_pc_kind<3>(con.kind, nb, stream, rob, con, n, q_in, q_out, status, tol, max_iters, alpha, lambda2); break;
+    case 6: ok = launch_pc_kind<6>(con.kind, nb, stream, rob, con, n, q_in, q_out, status, tol, max_iters, alpha, lambda2); break;
+    case 7: ok = launch_pc_kind<7>(con.kind, nb, stream, rob, con, n, q_in, q_out, status, tol, max_iters, alpha, lambda2); break;
+    case 9: ok = launch_pc_kind<9>(con.kind, nb, stream, rob, con, n, q_in, q_out, status, tol, max_iters, alpha, lambda2); break;
+    case 14: ok = launch_pc_kind<14>(con.kind, nb, stream, rob, con, n, q_in, q_out, status, tol, max_iters, alpha, lambda2); break;
+    default: ok = false;
+  }
+  *supported = ok;
+  return ok ? hipGetLastError() : hipSuccess;
+}
+
+}  // namespace cprrtc

@@ -1,0 +1,256 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars (derived from float32 arithmetic against the FP64 definitions):
+  * collision verdicts equal, except configurations / motions whose oracle
+    minimum signed distance lies within 1e-5 m of 0 (counted, reported);
+  * signed distances within 1e-5 m;
+  * projection status and iteration count equal and projected waypoints
+    within 1e-4 rad, except motions where some decision of Algorithm 1 (a
+    validity test that moved prog) was within 1e-5 of its threshold in the
+    oracle (counted, reported);
+  * early exit and the sphere batch size change no verdict (bitwise).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from paper_2505_06791_amd import inputs as I
+from tests.helpers import BAND, manifold_starts, motion_set, oracle_views
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_06791_amd import cprrtc
+    cprrtc.lib()
+    return cprrtc
+
+
+DEV = "cuda:0"
+
+
+def _gpu_fkcc(G, w, q32, flags=0, want_sd=False):
+    robot, env = G.Robot(w["robot"]), G.Env(w["env"])
+    q = torch.from_numpy(q32).to(DEV)
+    col = torch.empty(len(q32), dtype=torch.uint8, device=DEV)
+    sd = torch.empty(len(q32), dtype=torch.float32, device=DEV) if want_sd else None
+    G.fk_cc_batch(robot, env, q, col, sd, flags=flags)
+    torch.cuda.synchronize()
+    return col.cpu().numpy(), (sd.cpu().numpy() if want_sd else None)
+
+
+def _report(name, **kw):
+    print(name, " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+@pytest.mark.parametrize("name,n", [("plain", 3001), ("cluttered", 777), ("mobile", 1000),
+                                    ("dual", 300)])
+def test_fk_cc_batch_matches_oracle(G, name, n):
+    w = I.workload(name, 1000 + n)
+    q32 = I.random_configs(w["robot"], n, 5).astype(np.float32)
+    ro, eo, _ = oracle_views(w)
+    col_o, sd_o = O.fk_cc_batch(ro, eo, q32.astype(np.float64), n_threads=8)
+    col_g, _ = _gpu_fkcc(G, w, q32)
+    col_x, sd_g = _gpu_fkcc(G, w, q32, want_sd=True)
+    col_n, _ = _gpu_fkcc(G, w, q32, flags=G.NO_EARLY_EXIT)
+    band = np.abs(sd_o) <= BAND
+    _report("fk_cc", workload=name, n=n, band=int(band.sum()), colliding=int(col_o.sum()))
+    assert np.array_equal(col_g[~band], col_o[~band])
+    assert np.array_equal(col_x[~band], col_o[~band])
+    assert np.array_equal(col_g, col_n)                       # early exit skips work only
+    assert np.abs(sd_g.astype(np.float64) - sd_o).max() < 1e-5
+
+
+def test_fk_cc_tiny_scene_by_hand(G):
+    """One joint about world z carrying one sphere 0.5 m out at height 0.2;
+    a cube of half extent 0.1 centred at (0, 0.8, 0.2): at q = pi/2 the gap is
+    0.2 - 0.05, at q = -pi/2 it is 1.2 - 0.05; a 0.12 m sphere obstacle at the
+    centre position for q = 0 collides there."""
+    rd = dict(dof=1, n_chains=1, joint_type=np.zeros(1, np.int32),
+              joint_chain=np.zeros(1, np.int32), alpha=np.zeros(1), a=np.zeros(1),
+              d=np.array([0.2]), theta=np.zeros(1), lo=np.array([-3.1]), hi=np.array([3.1]),
+              base=np.eye(4)[None].copy(), tool=np.eye(4)[None].copy(),
+              sphere_link=np.zeros(1, np.int32), sphere=np.array([[0.5, 0, 0, 0.05]]))
+    env = I.empty_env()
+    env["aabb"] = np.array([[0, 0.8, 0.2, 0.1, 0.1, 0.1]])
+    env["sphere"] = np.array([[0.5, 0.0, 0.2, 0.12]])
+    w = dict(robot=rd, env=env)
+    q = np.array([[np.pi / 2], [-np.pi / 2], [0.0]], np.float32)
+    col, sd = _gpu_fkcc(G, w, q, want_sd=True)
+    assert list(col) == [0, 0, 1]
+    assert abs(sd[0] - 0.15) < 1e-6
+    assert abs(sd[2] - (-0.05)) < 1e-6
+
+
+def test_fk_cc_empty_and_ragged(G):
+    w = I.workload("plain", 3)
+    robot, env = G.Robot(w["robot"]), G.Env(w["env"])
+    q = torch.empty((0, 7), dtype=torch.float32, device=DEV)
+    col = torch.empty(0, dtype=torch.uint8, device=DEV)
+    G.fk_cc_batch(robot, env, q, col)
+    # every size around a wavefront and workgroup boundary
+    for n in (1, 63, 64, 65, 255, 257):
+        q32 = I.random_configs(w["robot"], n, n).astype(np.float32)
+        ro, eo, _ = oracle_views(w)
+        col_o, sd_o = O.fk_cc_batch(ro, eo, q32.astype(np.float64))
+        col_g, _ = _gpu_fkcc(G, w, q32)
+        band = np.abs(sd_o) <= BAND
+        assert np.array_equal(col_g[~band], col_o[~band]), n
+
+
+def test_fk_cc_empty_scene(G):
+    w = I.workload("plain", 4)
+    w["env"] = I.empty_env()
+    col, sd = _gpu_fkcc(G, w, I.random_configs(w["robot"], 100, 1).astype(np.float32),
+                        want_sd=True)
+    assert not col.any()
+
+
+def _run_pv(G, w, q_from, q_to, prm_kw, flags=0):
+    robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
+    prm = G.proj_params(**prm_kw)
+    M, W, dof = len(q_from), prm_kw.get("W", 64), w["robot"]["dof"]
+    qf = torch.from_numpy(q_from).to(DEV)
+    qt = torch.from_numpy(q_to).to(DEV)
+    xi = torch.full((M, W, dof), float("nan"), dtype=torch.float32, device=DEV)
+    st = torch.full((M,), -9, dtype=torch.int32, device=DEV)
+    it = torch.full((M,), -9, dtype=torch.int32, device=DEV)
+    G.project_validate_motions(robot, env, con, prm, qf, qt, xi, st, it, flags=flags)
+    torch.cuda.synchronize()
+    return xi.cpu().numpy(), st.cpu().numpy(), it.cpu().numpy()
+
+
+def _oracle_pv(w, q_from, q_to, W, tau_task, max_iters=32):
+    ro, eo, co = oracle_views(w)
+    prm = O.params(W=W, tau_task=tau_task, max_iters=max_iters)
+    return O.project_validate_motions(ro, eo, co, prm, q_from.astype(np.float64),
+                                      q_to.astype(np.float64), n_threads=8)
+
+
+def _compare_pv(name, ref, xi, st, it):
+    band = (ref["proj_margin"] < BAND) | (np.abs(ref["min_sd"]) < BAND)
+    proj_band = ref["proj_margin"] < BAND
+    ok = ~band
+    _report("project_validate", workload=name, motions=len(st), band=int(band.sum()),
+            valid=int((ref["status"] == 0).sum()), proj_fail=int((ref["status"] == 1).sum()),
+            collision=int((ref["status"] == 2).sum()))
+    assert np.array_equal(st[ok], ref["status"][ok])
+    assert np.array_equal(it[~proj_band], ref["iters"][~proj_band])
+    proj = ok & (ref["status"] != O.MOTION_PROJ_FAIL)
+    if proj.any():
+        err = np.abs(xi[proj].astype(np.float64) - ref["xi"][proj]).max()
+        _report("  max |xi_gpu - xi_oracle|", rad=f"{err:.2e}")
+        assert err < 1e-4
+        # the fixed start is copied exactly
+        assert np.array_equal(xi[:, 0, :], ref["xi"][:, 0, :].astype(np.float32))
+    return band
+
+
+@pytest.mark.parametrize("name,W,M", [("plain", 64, 37), ("plain", 32, 45), ("cluttered", 64, 29),
+                                      ("mobile", 64, 21), ("dual", 32, 12)])
+def test_project_validate_matches_oracle(G, name, W, M):
+    w = I.workload(name, 2000 + M)
+    q_from, q_to = motion_set(w, M, 11, W=W)
+    ref = _oracle_pv(w, q_from, q_to, W, w["tau_task"])
+    xi, st, it = _run_pv(G, w, q_from, q_to, dict(W=W, tau_task=w["tau_task"]))
+    _compare_pv(name, ref, xi, st, it)
+
+
+def test_project_validate_without_constraint_is_interpolation(G):
+    w = I.workload("plain", 5)
+    w["constraint"] = I.no_constraint()
+    q_from, q_to = motion_set(w, 20, 3)
+    xi, st, it = _run_pv(G, w, q_from, q_to, dict(W=64))
+    assert np.all(it == 1)
+    s = (np.arange(64, dtype=np.float32) / np.float32(63))[None, :, None]
+    ref = q_from[:, None, :] + s * (q_to - q_from)[:, None, :]
+    assert np.abs(xi - ref).max() < 1e-6
+    ro, eo, co = oracle_views(w)
+    ref_o = O.project_validate_motions(ro, eo, co, O.params(W=64), q_from.astype(np.float64),
+                                       q_to.astype(np.float64))
+    band = np.abs(ref_o["min_sd"]) < BAND
+    assert np.array_equal(st[~band], ref_o["status"][~band])
+
+
+def test_early_exit_and_batch_do_not_change_verdicts(G):
+    w = I.workload("cluttered", 2500)
+    q_from, q_to = motion_set(w, 40, 5)
+    base = _run_pv(G, w, q_from, q_to, dict(W=64, sphere_batch=8))
+    full = _run_pv(G, w, q_from, q_to, dict(W=64, sphere_batch=8), flags=G.NO_EARLY_EXIT)
+    small = _run_pv(G, w, q_from, q_to, dict(W=64, sphere_batch=4))
+    for other in (full, small):
+        assert np.array_equal(base[1], other[1])
+        assert np.array_equal(base[2], other[2])
+        assert np.array_equal(base[0], other[0])
+
+
+def test_project_validate_edge_cases(G):
+    w = I.workload("plain", 6)
+    robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
+    e = torch.empty((0, 7), dtype=torch.float32, device=DEV)
+    G.project_validate_motions(robot, env, con, G.proj_params(), e, e,
+                               torch.empty((0, 64, 7), device=DEV),
+                               torch.empty(0, dtype=torch.int32, device=DEV))
+    with pytest.raises(G.CprrtcError) as ex:
+        G.project_validate_motions(robot, env, con, G.proj_params(W=48), e, e,
+                                   torch.empty((0, 48, 7), device=DEV),
+                                   torch.empty(0, dtype=torch.int32, device=DEV))
+    assert ex.value.code == G.CP_E_UNSUPPORTED
+    # a zero-length motion: every waypoint equals the start; it is valid iff the start is
+    q_from, _ = motion_set(w, 3, 9)
+    xi, st, it = _run_pv(G, w, q_from, q_from.copy(), dict(W=64))
+    assert np.all(st == 0) and np.all(it == 1)
+    # max_iters = 1 on off-manifold interpolation fails projection
+    q_to = q_from.copy()
+    q_to[:, 3] += 0.6
+    xi, st, it = _run_pv(G, w, q_from, q_to, dict(W=64, max_iters=1))
+    ref = _oracle_pv(w, q_from, q_to, 64, 1e-3, max_iters=1)
+    assert np.array_equal(st, ref["status"])
+
+
+def test_project_configs_matches_oracle(G):
+    for name in ("plain", "cluttered", "dual"):
+        w = I.workload(name, 77)
+        robot, con = G.Robot(w["robot"]), G.constraint(w["constraint"])
+        q32 = I.random_configs(w["robot"], 300, 2).astype(np.float32)
+        qi = torch.from_numpy(q32).to(DEV)
+        qo = torch.empty_like(qi)
+        st = torch.empty(300, dtype=torch.int32, device=DEV)
+        G.project_configs(robot, con, qi, qo, st, tol=1e-5, max_iters=100)
+        torch.cuda.synchronize()
+        qo_h, st_h = qo.cpu().numpy(), st.cpu().numpy()
+        ro, _, co = oracle_views(w)
+        n_ok = 0
+        for q, s in zip(qo_h, st_h):
+            if s:
+                n_ok += 1
+                e = O.task_error(ro, co, q.astype(np.float64))
+                assert np.abs(e).max() < 2e-5
+                assert np.all(q >= w["robot"]["lo"] - 1e-6) and np.all(q <= w["robot"]["hi"] + 1e-6)
+        ok_o = sum(O.project_config(ro, co, q.astype(np.float64), tol=1e-5, max_iters=100)[0]
+                   for q in q32)
+        _report("project_configs", workload=name, gpu_ok=n_ok, oracle_ok=ok_o)
+        assert n_ok >= 0.8 * ok_o
+
+
+@pytest.mark.parametrize("name,M,sample", [("cluttered", 65536, 48)])
+def test_full_size_sampled(G, name, M, sample):
+    """The benchmark's launch at full size; sampled motions recomputed by the oracle."""
+    w = I.workload(name, 2000)
+    base_from, base_to = motion_set(w, 256, 2500)
+    reps = M // len(base_from)
+    rng = np.random.default_rng(0)
+    q_from = np.tile(base_from, (reps, 1))
+    q_to = I.random_displacements(w["robot"], q_from.astype(np.float64), 63 * 0.05,
+                                  2501).astype(np.float32)
+    xi, st, it = _run_pv(G, w, q_from, q_to, dict(W=64, tau_task=w["tau_task"]))
+    idx = np.sort(rng.choice(M, sample, replace=False))
+    idx = np.concatenate([idx, [M - 1]])
+    ref = _oracle_pv(w, q_from[idx], q_to[idx], 64, w["tau_task"])
+    _compare_pv(name + "-full", ref, xi[idx], st[idx], it[idx])
+    assert set(np.unique(st)).issubset({0, 1, 2})
