@@ -1,0 +1,225 @@
+"""Benchmark of the hot path on one MI355X.
+
+A step is one project_validate_motions call over one resident batch of
+motions of the cluttered workload (7-DOF arm with 100 collision spheres, 300
+mixed primitives, end effector on a horizontal plane and upright, tolerance
+1e-3): 65536 motions of 64 waypoints each are interpolated, projected onto
+the constraint manifold (Algorithm 1) and checked for collisions with the
+motion-wide early exit.
+
+Printed value: validated constrained waypoints per second -- the W-1
+waypoints of every motion whose projection succeeded and that received a
+collision verdict (valid or colliding), per second of step time.
+
+Also printed: the roofline of the motion kernel (algorithmic FLOPs from the
+kernel's own work counters over its HIP-event duration, against the FP32
+vector peak), and the FP64 CPU oracle timed on a bounded sample of the same
+workload on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = "cluttered"
+SCENE_SEED = 2000
+MOTION_SEED = 2500
+W = 64
+TAU = 0.05
+TAU_TASK = 1e-3
+
+# Algorithmic FLOPs (add, sub, mul, div, sqrt, min, max, compare = 1; a
+# multiply-add = 2; sin/cos/atan2 = 1; |x| = 0), per pair test of the
+# verdict form dist^2 <= reach^2 for each primitive type.
+PAIR_FLOPS = dict(aabb=15, obb=30, sphere=11, capsule=25, cylinder=28)
+SPHERE_CENTRE_FLOPS = 19          # R l + p, plus r^2
+
+
+def update_flops(dof: int) -> int:
+    """One waypoint update of Algorithm 1 for a single-chain pose constraint:
+    FK to every joint frame (51/joint), tool (57), constrained pose and
+    angles (73), error (30), Jacobian columns (57/joint), J J^T (42/joint + 6),
+    6x6 Cholesky (97) and solves (72), J^T y (12/joint), smoothing, update,
+    clamp and validity (9/joint + 5)."""
+    return 171 * dof + 340
+
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3    # MI355X, 256 CU x 2.4 GHz, packed FMA counted
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--motions", type=int, default=65536)
+    ap.add_argument("--sphere-batch", type=int, default=8)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample (0 = skip)")
+    return ap.parse_args()
+
+
+def gpu_starts(G, I, torch, rd, robot, env, con, n, seed):
+    """n on-manifold, collision-free (margin 1e-3 m) start configurations,
+    prepared with the library itself: project_configs then fk_cc_batch."""
+    dev = torch.device("cuda:0")
+    raw = torch.from_numpy(I.random_configs(rd, 4 * n, seed).astype(np.float32)).to(dev)
+    proj = torch.empty_like(raw)
+    ok = torch.empty(raw.shape[0], dtype=torch.int32, device=dev)
+    G.project_configs(robot, con, raw, proj, ok, tol=1e-5, max_iters=100)
+    col = torch.empty(raw.shape[0], dtype=torch.uint8, device=dev)
+    sd = torch.empty(raw.shape[0], dtype=torch.float32, device=dev)
+    G.fk_cc_batch(robot, env, proj, col, sd)
+    keep = (ok == 1) & (sd > 1e-3)
+    good = proj[keep]
+    if good.shape[0] == 0:
+        raise RuntimeError("no collision-free start configuration on the manifold")
+    reps = (n + good.shape[0] - 1) // good.shape[0]
+    return good.repeat(reps, 1)[:n].contiguous()
+
+
+def cpu_baseline(I, w, target_s):
+    """The FP64 oracle on a bounded sample of the same workload (its own
+    start preparation from the same raw seed), OpenMP over motions."""
+    import oracle as O
+    threads = max(1, min(16, os.cpu_count() or 1))
+    ro, eo, co = O.Robot(w["robot"]), O.Env(w["env"]), O.Constraint(w["constraint"])
+    prm = O.params(W=W, tau=TAU, tau_task=TAU_TASK)
+    starts = []
+    for q in I.random_configs(w["robot"], 2048, MOTION_SEED):
+        ok, qp, _ = O.project_config(ro, co, q, tol=1e-5, max_iters=100)
+        if ok and O.config_min_sd(ro, eo, qp) > 1e-3:
+            starts.append(qp)
+        if len(starts) >= 512:
+            break
+    starts = np.asarray(starts)
+    ends = I.random_displacements(w["robot"], starts, (W - 1) * TAU, MOTION_SEED + 1)
+    done_wp, done_m, elapsed, at = 0, 0, 0.0, 0
+    chunk = 4 * threads
+    while elapsed < target_s and done_m < 20000:
+        idx = np.arange(at, at + chunk) % len(starts)
+        at += chunk
+        t0 = time.perf_counter()
+        out = O.project_validate_motions(ro, eo, co, prm, starts[idx], ends[idx], n_threads=threads)
+        elapsed += time.perf_counter() - t0
+        done_m += chunk
+        done_wp += int((out["status"] != O.MOTION_PROJ_FAIL).sum()) * (W - 1)
+    return dict(value=done_wp / elapsed, unit="waypoints/s", cores=threads, kind="oracle",
+                sample=f"{done_m} motions of the same workload ({len(starts)} oracle-prepared "
+                       f"starts, cycled), {elapsed:.1f} s of FP64 oracle time")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2505_06791_amd import cprrtc as G
+    from paper_2505_06791_amd import inputs as I
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    w = I.workload(WORKLOAD, SCENE_SEED)
+    rd, ed, cd = w["robot"], w["env"], w["constraint"]
+    robot, env, con = G.Robot(rd), G.Env(ed), G.constraint(cd)
+    prm = G.proj_params(W=W, tau=TAU, tau_task=TAU_TASK, sphere_batch=args.sphere_batch)
+    M, dof = args.motions, rd["dof"]
+
+    q_from = gpu_starts(G, I, torch, rd, robot, env, con, M, MOTION_SEED)
+    q_to = torch.from_numpy(I.random_displacements(
+        rd, q_from.cpu().numpy().astype(np.float64), (W - 1) * TAU, MOTION_SEED + 1)
+        .astype(np.float32)).to(dev)
+    xi = torch.empty((M, W, dof), dtype=torch.float32, device=dev)
+    status = torch.empty(M, dtype=torch.int32, device=dev)
+    iters = torch.empty(M, dtype=torch.int32, device=dev)
+    work = torch.zeros(2, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        G.project_validate_motions(robot, env, con, prm, q_from, q_to, xi, status, iters)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record()
+        step()
+        ends[k].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    ms_per_step = wall * 1e3 / args.steps
+
+    # work of one launch (the same batch every step): counters of one extra call
+    work.zero_()
+    G.project_validate_motions(robot, env, con, prm, q_from, q_to, xi, status, iters, work=work)
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    it = iters.cpu().numpy()
+    sphere_evals, updates = (int(x) for x in work.cpu().numpy())
+    counts = env.counts
+    per_sphere = SPHERE_CENTRE_FLOPS + sum(counts[k] * PAIR_FLOPS[k] for k in PAIR_FLOPS)
+    flops = sphere_evals * per_sphere + updates * update_flops(dof)
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    verdicts = int((st != G.MOTION_PROJ_FAIL).sum())
+    value = verdicts * (W - 1) / (ms_per_step * 1e-3)
+
+    result = {
+        "metric": "validated constrained waypoints/s",
+        "value": value,
+        "unit": "waypoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "cluttered single-query motion batch: 7-DOF arm, 100 spheres, "
+                        "300 mixed primitives, plane + upright constraint",
+            "motions": M, "waypoints_per_motion": W, "dof": dof,
+            "robot_spheres": len(rd["sphere"]), "primitives": env.n_prims,
+            "tau_task": TAU_TASK, "sphere_batch": args.sphere_batch,
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+            "kernel": "project_validate_kernel",
+            "kernel_ms": kernel_ms,
+            "gflop_per_launch": flops / 1e9,
+        },
+        "motions": {"valid": int((st == 0).sum()), "proj_fail": int((st == 1).sum()),
+                    "collision": int((st == 2).sum()), "mean_iters": float(it.mean())},
+    }
+    if args.cpu_seconds > 0:
+        result["cpu_baseline"] = cpu_baseline(I, w, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
