@@ -1,7 +1,8 @@
 """Benchmark of the hot path on one MI355X.
 
-A step is one project_validate_motions call over one resident batch of
-motions of the cluttered workload (7-DOF arm with 100 collision spheres, 300
+A step is one pass of motion projection and validation (the projection
+kernel, then the validation kernel) over one resident batch of motions of the
+cluttered workload (7-DOF arm with 100 collision spheres, 300
 mixed primitives, end effector on a horizontal plane and upright, tolerance
 1e-3): 65536 motions of 64 waypoints each are interpolated, projected onto
 the constraint manifold (Algorithm 1) and checked for collisions with the
@@ -11,10 +12,10 @@ Printed value: validated constrained waypoints per second -- the W-1
 waypoints of every motion whose projection succeeded and that received a
 collision verdict (valid or colliding), per second of step time.
 
-Also printed: the roofline of the motion kernel (algorithmic FLOPs from the
-kernel's own work counters over its HIP-event duration, against the FP32
-vector peak), and the FP64 CPU oracle timed on a bounded sample of the same
-workload on the host's cores.
+Also printed: the roofline of the dominant kernel of the step (algorithmic
+FLOPs from the kernels' own work counters over that kernel's HIP-event
+duration, against the FP32 vector peak), and the FP64 CPU oracle timed on a
+bounded sample of the same workload on the host's cores.
 """
 from __future__ import annotations
 
@@ -41,7 +42,9 @@ TAU_TASK = 1e-3
 # multiply-add = 2; sin/cos/atan2 = 1; |x| = 0), per pair test of the
 # verdict form dist^2 <= reach^2 for each primitive type.
 PAIR_FLOPS = dict(aabb=15, obb=30, sphere=11, capsule=25, cylinder=28)
+PAIR_ORDER = ("aabb", "obb", "sphere", "capsule", "cylinder")   # work counter slots 0..4
 SPHERE_CENTRE_FLOPS = 19          # R l + p, plus r^2
+CULL_FLOPS = 20                   # bounding sphere vs box: 3 x (2 sub, 2 max), |.|^2, reach^2, compare
 
 
 def update_flops(dof: int) -> int:
@@ -145,40 +148,52 @@ def main():
     xi = torch.empty((M, W, dof), dtype=torch.float32, device=dev)
     status = torch.empty(M, dtype=torch.int32, device=dev)
     iters = torch.empty(M, dtype=torch.int32, device=dev)
-    work = torch.zeros(2, dtype=torch.int64, device=dev)
+    work = torch.zeros(G.WORK_SLOTS, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
 
-    def step():
-        G.project_validate_motions(robot, env, con, prm, q_from, q_to, xi, status, iters)
+    # one step = the projection kernel, then the validation kernel, on the
+    # current stream; events around each launch time them separately
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        G.project_motions(robot, con, prm, q_from, q_to, xi, status, iters)
+        if ev is not None:
+            ev[1].record()
+        G.validate_motions(robot, env, prm, xi, status)
+        if ev is not None:
+            ev[2].record()
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        starts[k].record()
-        step()
-        ends[k].record()
+        step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    proj_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    val_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     ms_per_step = wall * 1e3 / args.steps
 
-    # work of one launch (the same batch every step): counters of one extra call
+    # work of one step (the same batch every step): counters of one extra call
     work.zero_()
-    G.project_validate_motions(robot, env, con, prm, q_from, q_to, xi, status, iters, work=work)
+    G.project_motions(robot, con, prm, q_from, q_to, xi, status, iters, work=work)
+    G.validate_motions(robot, env, prm, xi, status, work=work)
     torch.cuda.synchronize()
     st = status.cpu().numpy()
     it = iters.cpu().numpy()
-    sphere_evals, updates = (int(x) for x in work.cpu().numpy())
-    counts = env.counts
-    per_sphere = SPHERE_CENTRE_FLOPS + sum(counts[k] * PAIR_FLOPS[k] for k in PAIR_FLOPS)
-    flops = sphere_evals * per_sphere + updates * update_flops(dof)
-    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    wk = [int(x) for x in work.cpu().numpy()]
+    val_flops = (sum(wk[i] * PAIR_FLOPS[t] for i, t in enumerate(PAIR_ORDER))
+                 + wk[5] * SPHERE_CENTRE_FLOPS + wk[7] * CULL_FLOPS)
+    proj_flops = wk[6] * update_flops(dof)
+    if val_ms >= proj_ms:
+        dom, dom_ms, flops = "validate_kernel<8, true>", val_ms, val_flops
+    else:
+        dom, dom_ms, flops = "project_kernel<7, 1>", proj_ms, proj_flops
+    achieved = flops / (dom_ms * 1e-3) / 1e12
     verdicts = int((st != G.MOTION_PROJ_FAIL).sum())
     value = verdicts * (W - 1) / (ms_per_step * 1e-3)
 
@@ -209,9 +224,17 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
             "traffic": None,
-            "kernel": "project_validate_kernel",
-            "kernel_ms": kernel_ms,
+            "kernel": dom,
+            "kernel_ms": dom_ms,
             "gflop_per_launch": flops / 1e9,
+        },
+        "kernels": {
+            "project_ms": proj_ms, "validate_ms": val_ms,
+            "project_tflops": proj_flops / (proj_ms * 1e-3) / 1e12,
+            "validate_tflops": val_flops / (val_ms * 1e-3) / 1e12,
+            "work": dict(zip(("pairs_aabb", "pairs_obb", "pairs_sphere", "pairs_capsule",
+                              "pairs_cylinder", "sphere_centres", "waypoint_updates",
+                              "cull_tests"), wk)),
         },
         "motions": {"valid": int((st == 0).sum()), "proj_fail": int((st == 1).sum()),
                     "collision": int((st == 2).sum()), "mean_iters": float(it.mean())},

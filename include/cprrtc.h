@@ -46,7 +46,11 @@ enum { CP_REVOLUTE = 0, CP_PRISMATIC = 1 };
 enum { CP_CON_NONE = 0, CP_CON_POSE = 1, CP_CON_REL_POSE = 2 };
 
 /* flags */
-enum { CP_NO_EARLY_EXIT = 1 };   /* evaluate every sphere-primitive pair */
+enum {
+  CP_NO_EARLY_EXIT = 1,  /* keep checking a motion / configuration after its first collision */
+  CP_NO_CULL = 2         /* project_validate_motions: test every primitive, without the
+                            wave-level bounding-box culling (verdicts are the same) */
+};
 
 /* ------------------------------------------------------------ descriptors */
 
@@ -152,16 +156,19 @@ int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const f
  * validated prefix frozen, damped least-squares task step, smoothing step
  * (||xi[k]-xi[k-1]|| - tau) (xi[k]-xi[k-1]), clamp to limits), then FK+CC of
  * waypoints 1..W-1 with an early exit of the whole motion on any collision.
+ * Two kernels run on `stream`: projection, then validation.
  *   d_q_from, d_q_to [n_motions][dof] float32
  *   d_xi      [n_motions][W][dof] float32 out: projected segment (on
  *             CP_MOTION_PROJ_FAIL: the last iterate)
  *   d_status  [n_motions] int32 out: CP_MOTION_*
  *   d_iters   [n_motions] int32 out, nullable: ParallelProject iterations
- *   d_work    [2] uint64 in/out, nullable: work counters the call ADDS to
- *             (the caller zeroes them): [0] = (waypoint, robot sphere)
- *             collision evaluations, each against every primitive (early
- *             exit included); [1] = waypoint updates of ParallelProject
- *             (waypoints past the frozen prefix, summed over iterations)
+ *   d_work    [8] uint64 in/out, nullable: work counters the call ADDS to
+ *             (the caller zeroes them), in units of one waypoint's work:
+ *             [0..4] sphere-primitive pair tests against axis-aligned boxes,
+ *             oriented boxes, spheres, capsules, cylinders; [5] robot sphere
+ *             centres placed; [6] waypoint updates of ParallelProject
+ *             (waypoints past the frozen prefix, summed over iterations);
+ *             [7] bounding-sphere culling tests (per motion and batch)
  *   params    NULL = defaults
  * Errors: CP_E_ARG, CP_E_UNSUPPORTED (dof, W), CP_E_HIP. */
 int project_validate_motions(const cp_robot* robot, const cp_env* env,
@@ -169,6 +176,25 @@ int project_validate_motions(const cp_robot* robot, const cp_env* env,
                              int32_t n_motions, const float* d_q_from, const float* d_q_to,
                              float* d_xi, int32_t* d_status, int32_t* d_iters, uint64_t* d_work,
                              int32_t flags, void* stream);
+
+/* The two halves of project_validate_motions, for callers that want them
+ * apart (e.g. to time them, or to project without checking):
+ *   project_motions:  interpolation + ParallelProject; d_status[i] = 0 when
+ *                     the segment was projected, CP_MOTION_PROJ_FAIL when not;
+ *                     d_work adds to slot [6] only.
+ *   validate_motions: FK + CC of waypoints 1..W-1 of every motion whose
+ *                     d_status is 0 on entry (others are left untouched);
+ *                     d_status becomes CP_MOTION_VALID or CP_MOTION_COLLISION;
+ *                     d_work adds to slots [0..5] and [7].
+ * Arguments, layouts and errors as for project_validate_motions (W and
+ * sphere_batch are taken from params). */
+int project_motions(const cp_robot* robot, const cp_constraint* constraint,
+                    const cp_proj_params* params, int32_t n_motions, const float* d_q_from,
+                    const float* d_q_to, float* d_xi, int32_t* d_status, int32_t* d_iters,
+                    uint64_t* d_work, void* stream);
+int validate_motions(const cp_robot* robot, const cp_env* env, const cp_proj_params* params,
+                     int32_t n_motions, const float* d_xi, int32_t* d_status, uint64_t* d_work,
+                     int32_t flags, void* stream);
 
 /* Projection of single configurations onto the manifold (puts start, goal
  * and samples on it): q <- clamp(q - alpha g_task) until ||e||_inf < tol,

@@ -20,6 +20,8 @@ CP_E_ARG, CP_E_START, CP_E_GOAL, CP_E_CAPACITY = -1, -2, -3, -4
 CP_E_RTC, CP_E_HIP, CP_E_UNSUPPORTED = -5, -6, -7
 MOTION_VALID, MOTION_PROJ_FAIL, MOTION_COLLISION = 0, 1, 2
 NO_EARLY_EXIT = 1
+NO_CULL = 2
+WORK_SLOTS = 8
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -75,6 +77,10 @@ def lib():
         L.fk_cc_batch.argtypes = [vp, vp, C.c_int32, vp, vp, vp, C.c_int32, vp]
         L.project_validate_motions.argtypes = [vp, vp, C.POINTER(Constraint), C.POINTER(ProjParams),
                                                C.c_int32, vp, vp, vp, vp, vp, vp, C.c_int32, vp]
+        L.project_motions.argtypes = [vp, C.POINTER(Constraint), C.POINTER(ProjParams), C.c_int32,
+                                      vp, vp, vp, vp, vp, vp, vp]
+        L.validate_motions.argtypes = [vp, vp, C.POINTER(ProjParams), C.c_int32, vp, vp, vp,
+                                       C.c_int32, vp]
         L.project_configs.argtypes = [vp, C.POINTER(Constraint), C.c_int32, vp, vp, vp,
                                       C.c_double, C.c_int32, C.c_double, C.c_double, vp]
         _lib = L
@@ -191,7 +197,7 @@ def project_validate_motions(robot: Robot, env: Env, con: Constraint, prm: ProjP
                              q_from, q_to, xi, status, iters=None, work=None, flags: int = 0,
                              stream=None):
     """q_from/q_to: [M, dof] float32; xi: [M, W, dof] float32; status/iters: [M] int32;
-    work: [2] int64 counters the call adds to (see include/cprrtc.h)."""
+    work: [8] int64 counters the call adds to (see include/cprrtc.h)."""
     import torch
     m = q_from.shape[0]
     _check(lib().project_validate_motions(
@@ -199,6 +205,29 @@ def project_validate_motions(robot: Robot, env: Env, con: Constraint, prm: ProjP
         _dev(q_to, torch.float32), _dev(xi, torch.float32), _dev(status, torch.int32),
         _dev(iters, torch.int32) if iters is not None else None,
         _dev(work, torch.int64) if work is not None else None, flags, _stream(stream)))
+
+
+def project_motions(robot: Robot, con: Constraint, prm: ProjParams, q_from, q_to, xi, status,
+                    iters=None, work=None, stream=None):
+    """Interpolation + ParallelProject only; status 0 = projected, 1 = failed."""
+    import torch
+    m = q_from.shape[0]
+    _check(lib().project_motions(
+        robot.handle, C.byref(con), C.byref(prm), m, _dev(q_from, torch.float32),
+        _dev(q_to, torch.float32), _dev(xi, torch.float32), _dev(status, torch.int32),
+        _dev(iters, torch.int32) if iters is not None else None,
+        _dev(work, torch.int64) if work is not None else None, _stream(stream)))
+
+
+def validate_motions(robot: Robot, env: Env, prm: ProjParams, xi, status, work=None,
+                     flags: int = 0, stream=None):
+    """FK + CC of the motions whose status is 0; status becomes 0 (valid) or 2 (collision)."""
+    import torch
+    m = xi.shape[0]
+    _check(lib().validate_motions(
+        robot.handle, env.handle, C.byref(prm), m, _dev(xi, torch.float32),
+        _dev(status, torch.int32), _dev(work, torch.int64) if work is not None else None, flags,
+        _stream(stream)))
 
 
 def project_configs(robot: Robot, con: Constraint, q_in, q_out, status, tol=1e-5, max_iters=100,

@@ -196,23 +196,33 @@ int cp_env_create(const cp_env_desc* d, cp_env** out) {
     const int counts[5] = {d->n_aabb, d->n_obb, d->n_sphere, d->n_capsule, d->n_cylinder};
     const double* src[5] = {d->aabb, d->obb, d->sphere, d->capsule, d->cylinder};
     const int slots[5] = {2, 4, 1, 2, 2};   // float4 per primitive
-    size_t total = 0;
+    size_t total = 0, n_prims = 0;
     for (int t = 0; t < 5; ++t) {
       if (counts[t] < 0) return fail(CP_E_ARG, "negative primitive count");
       if (counts[t] > 0 && !src[t]) return fail(CP_E_ARG, "NULL primitive array with count %d", counts[t]);
       total += (size_t)counts[t] * slots[t];
+      n_prims += (size_t)counts[t];
     }
-    std::vector<float4> buf(std::max<size_t>(total, 1));
+    if (n_prims > 65535) return fail(CP_E_UNSUPPORTED, "%zu primitives (at most 65535)", n_prims);
+    // layout: per-type records, then one bounding sphere per primitive
+    std::vector<float4> buf(std::max<size_t>(total + n_prims, 1));
     size_t off[5];
     size_t at = 0;
     for (int t = 0; t < 5; ++t) {
       off[t] = at;
       at += (size_t)counts[t] * slots[t];
     }
+    const size_t boff = at;
+    size_t bi = boff;
+    auto bound = [&](double x, double y, double z, double r) {
+      // float rounding of the centre is covered by the culling margin
+      buf[bi++] = make_float4((float)x, (float)y, (float)z, (float)(r * (1.0 + 1e-6)));
+    };
     for (int i = 0; i < d->n_aabb; ++i) {
       const double* p = d->aabb + 6 * i;
       buf[off[0] + 2 * i] = make_float4((float)p[0], (float)p[1], (float)p[2], 0.f);
       buf[off[0] + 2 * i + 1] = make_float4((float)p[3], (float)p[4], (float)p[5], 0.f);
+      bound(p[0], p[1], p[2], std::sqrt(p[3] * p[3] + p[4] * p[4] + p[5] * p[5]));
     }
     for (int i = 0; i < d->n_obb; ++i) {
       const double* p = d->obb + 15 * i;
@@ -220,10 +230,12 @@ int cp_env_create(const cp_env_desc* d, cp_env** out) {
       for (int c = 0; c < 3; ++c)  // box axis c = column c of R
         buf[off[1] + 4 * i + 1 + c] = make_float4((float)p[3 + c], (float)p[6 + c], (float)p[9 + c],
                                                   (float)p[12 + c]);
+      bound(p[0], p[1], p[2], std::sqrt(p[12] * p[12] + p[13] * p[13] + p[14] * p[14]));
     }
     for (int i = 0; i < d->n_sphere; ++i) {
       const double* p = d->sphere + 4 * i;
       buf[off[2] + i] = make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[3]);
+      bound(p[0], p[1], p[2], p[3]);
     }
     for (int i = 0; i < d->n_capsule; ++i) {
       const double* p = d->capsule + 7 * i;
@@ -231,6 +243,7 @@ int cp_env_create(const cp_env_desc* d, cp_env** out) {
       const double dd = dx * dx + dy * dy + dz * dz;
       buf[off[3] + 2 * i] = make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[6]);
       buf[off[3] + 2 * i + 1] = make_float4((float)dx, (float)dy, (float)dz, dd > 0 ? (float)(1.0 / dd) : 0.f);
+      bound(p[0] + 0.5 * dx, p[1] + 0.5 * dy, p[2] + 0.5 * dz, 0.5 * std::sqrt(dd) + p[6]);
     }
     for (int i = 0; i < d->n_cylinder; ++i) {
       const double* p = d->cylinder + 8 * i;
@@ -238,6 +251,7 @@ int cp_env_create(const cp_env_desc* d, cp_env** out) {
       if (std::fabs(n - 1.0) > 1e-6) return fail(CP_E_ARG, "cylinder %d: axis is not a unit vector", i);
       buf[off[4] + 2 * i] = make_float4((float)p[0], (float)p[1], (float)p[2], (float)p[6]);
       buf[off[4] + 2 * i + 1] = make_float4((float)p[3], (float)p[4], (float)p[5], (float)p[7]);
+      bound(p[0], p[1], p[2], std::sqrt(p[6] * p[6] + p[7] * p[7]));
     }
     cp_env* env = new (std::nothrow) cp_env;
     if (!env) return fail(CP_E_ARG, "out of host memory");
@@ -247,7 +261,7 @@ int cp_env_create(const cp_env_desc* d, cp_env** out) {
       cp_env_destroy(env);
       return hip_fail(e, "cp_env_create");
     }
-    env->total = (int)total;
+    env->total = (int)n_prims;
     EnvDev& v = env->view;
     v.n_aabb = d->n_aabb; v.n_obb = d->n_obb; v.n_sph = d->n_sphere;
     v.n_cap = d->n_capsule; v.n_cyl = d->n_cylinder;
@@ -256,6 +270,7 @@ int cp_env_create(const cp_env_desc* d, cp_env** out) {
     v.sph = env->block + off[2];
     v.cap = env->block + off[3];
     v.cyl = env->block + off[4];
+    v.bound = env->block + boff;
     *out = env;
     return CP_OK;
   } catch (...) {
@@ -286,6 +301,95 @@ int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const f
   }
 }
 
+namespace {
+
+int check_params(const cp_proj_params* params, cp_proj_params* p) {
+  cp_proj_params_default(p);
+  if (params) *p = *params;
+  if (p->W != 32 && p->W != 64) return fail(CP_E_UNSUPPORTED, "W = %d (supported: 32, 64)", p->W);
+  if (p->max_iters < 1) return fail(CP_E_ARG, "max_iters < 1");
+  if (!(p->tau >= 0) || !(p->tau_sm >= 0) || !(p->tau_task >= 0) || !(p->lambda >= 0) ||
+      !(p->alpha > 0))
+    return fail(CP_E_ARG, "projection parameters out of range");
+  if (p->sphere_batch != 4 && p->sphere_batch != 8)
+    return fail(CP_E_UNSUPPORTED, "sphere_batch = %d (supported: 4, 8)", p->sphere_batch);
+  return CP_OK;
+}
+
+int do_project(const cp_robot* robot, const cp_constraint* constraint, const cp_proj_params& p,
+               int32_t n_motions, const float* d_q_from, const float* d_q_to, float* d_xi,
+               int32_t* d_status, int32_t* d_iters, uint64_t* d_work, void* stream) {
+  if (!dof_supported(robot->host.dof))
+    return fail(CP_E_UNSUPPORTED, "projection kernels are built for dof 2, 3, 6, 7, 9, 14 (got %d)", robot->host.dof);
+  ConDev con;
+  int rc = make_constraint(constraint, robot, &con);
+  if (rc != CP_OK) return rc;
+  if (n_motions == 0) return CP_OK;
+  if (!d_q_from || !d_q_to || !d_xi || !d_status) return fail(CP_E_ARG, "NULL buffer");
+  ProjDev prm;
+  prm.W = p.W;
+  prm.max_iters = p.max_iters;
+  prm.tau = (float)p.tau;
+  prm.tau_sm = (float)p.tau_sm;
+  prm.tau_task = (float)p.tau_task;
+  prm.alpha = (float)p.alpha;
+  prm.lambda2 = (float)(p.lambda * p.lambda);
+  bool supported = false;
+  hipError_t e = launch_project(robot->host.dof, robot->dev, con, prm, n_motions, d_q_from, d_q_to,
+                                d_xi, d_status, d_iters, (unsigned long long*)d_work,
+                                (hipStream_t)stream, &supported);
+  if (!supported) return fail(CP_E_UNSUPPORTED, "no kernel for dof %d with constraint kind %d", robot->host.dof, con.kind);
+  if (e != hipSuccess) return hip_fail(e, "projection launch");
+  return CP_OK;
+}
+
+int do_validate(const cp_robot* robot, const cp_env* env, const cp_proj_params& p,
+                int32_t n_motions, const float* d_xi, int32_t* d_status, uint64_t* d_work,
+                int32_t flags, void* stream) {
+  if (n_motions == 0) return CP_OK;
+  if (!d_xi || !d_status) return fail(CP_E_ARG, "NULL buffer");
+  hipError_t e = launch_validate(robot->dev, robot->spheres, env->view, p.W, n_motions, d_xi,
+                                 d_status, (unsigned long long*)d_work,
+                                 !(flags & CP_NO_EARLY_EXIT), !(flags & CP_NO_CULL),
+                                 p.sphere_batch, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "validation launch");
+  return CP_OK;
+}
+
+}  // namespace
+
+int project_motions(const cp_robot* robot, const cp_constraint* constraint,
+                    const cp_proj_params* params, int32_t n_motions, const float* d_q_from,
+                    const float* d_q_to, float* d_xi, int32_t* d_status, int32_t* d_iters,
+                    uint64_t* d_work, void* stream) {
+  try {
+    if (!robot) return fail(CP_E_ARG, "project_motions: NULL handle");
+    if (n_motions < 0) return fail(CP_E_ARG, "project_motions: n_motions < 0");
+    cp_proj_params p;
+    int rc = check_params(params, &p);
+    if (rc != CP_OK) return rc;
+    return do_project(robot, constraint, p, n_motions, d_q_from, d_q_to, d_xi, d_status, d_iters,
+                      d_work, stream);
+  } catch (...) {
+    return fail(CP_E_ARG, "project_motions: unexpected exception");
+  }
+}
+
+int validate_motions(const cp_robot* robot, const cp_env* env, const cp_proj_params* params,
+                     int32_t n_motions, const float* d_xi, int32_t* d_status, uint64_t* d_work,
+                     int32_t flags, void* stream) {
+  try {
+    if (!robot || !env) return fail(CP_E_ARG, "validate_motions: NULL handle");
+    if (n_motions < 0) return fail(CP_E_ARG, "validate_motions: n_motions < 0");
+    cp_proj_params p;
+    int rc = check_params(params, &p);
+    if (rc != CP_OK) return rc;
+    return do_validate(robot, env, p, n_motions, d_xi, d_status, d_work, flags, stream);
+  } catch (...) {
+    return fail(CP_E_ARG, "validate_motions: unexpected exception");
+  }
+}
+
 int project_validate_motions(const cp_robot* robot, const cp_env* env,
                              const cp_constraint* constraint, const cp_proj_params* params,
                              int32_t n_motions, const float* d_q_from, const float* d_q_to,
@@ -295,39 +399,12 @@ int project_validate_motions(const cp_robot* robot, const cp_env* env,
     if (!robot || !env) return fail(CP_E_ARG, "project_validate_motions: NULL handle");
     if (n_motions < 0) return fail(CP_E_ARG, "project_validate_motions: n_motions < 0");
     cp_proj_params p;
-    cp_proj_params_default(&p);
-    if (params) p = *params;
-    if (p.W != 32 && p.W != 64) return fail(CP_E_UNSUPPORTED, "W = %d (supported: 32, 64)", p.W);
-    if (p.max_iters < 1) return fail(CP_E_ARG, "max_iters < 1");
-    if (!(p.tau >= 0) || !(p.tau_sm >= 0) || !(p.tau_task >= 0) || !(p.lambda >= 0) || !(p.alpha > 0))
-      return fail(CP_E_ARG, "projection parameters out of range");
-    if (p.sphere_batch != 4 && p.sphere_batch != 8)
-      return fail(CP_E_UNSUPPORTED, "sphere_batch = %d (supported: 4, 8)", p.sphere_batch);
-    if (!dof_supported(robot->host.dof))
-      return fail(CP_E_UNSUPPORTED, "projection kernels are built for dof 2, 3, 6, 7, 9, 14 (got %d)", robot->host.dof);
-    ConDev con;
-    int rc = make_constraint(constraint, robot, &con);
+    int rc = check_params(params, &p);
     if (rc != CP_OK) return rc;
-    if (n_motions == 0) return CP_OK;
-    if (!d_q_from || !d_q_to || !d_xi || !d_status)
-      return fail(CP_E_ARG, "project_validate_motions: NULL buffer");
-    ProjDev prm;
-    prm.W = p.W;
-    prm.max_iters = p.max_iters;
-    prm.tau = (float)p.tau;
-    prm.tau_sm = (float)p.tau_sm;
-    prm.tau_task = (float)p.tau_task;
-    prm.alpha = (float)p.alpha;
-    prm.lambda2 = (float)(p.lambda * p.lambda);
-    bool supported = false;
-    hipError_t e = launch_project_validate(robot->host.dof, robot->dev, robot->spheres, env->view,
-                                           con, prm, n_motions, d_q_from, d_q_to, d_xi, d_status,
-                                           d_iters, (unsigned long long*)d_work,
-                                           !(flags & CP_NO_EARLY_EXIT), p.sphere_batch,
-                                           (hipStream_t)stream, &supported);
-    if (!supported) return fail(CP_E_UNSUPPORTED, "no kernel for dof %d with constraint kind %d", robot->host.dof, con.kind);
-    if (e != hipSuccess) return hip_fail(e, "project_validate_motions launch");
-    return CP_OK;
+    rc = do_project(robot, constraint, p, n_motions, d_q_from, d_q_to, d_xi, d_status, d_iters,
+                    d_work, stream);
+    if (rc != CP_OK) return rc;
+    return do_validate(robot, env, p, n_motions, d_xi, d_status, d_work, flags, stream);
   } catch (...) {
     return fail(CP_E_ARG, "project_validate_motions: unexpected exception");
   }

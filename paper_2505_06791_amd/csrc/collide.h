@@ -4,15 +4,24 @@
 //
 // One lane = one configuration.  The lane walks the chain joint by joint
 // (runtime loop, joint rows via scalar loads), and for each link takes its
-// spheres in batches of B: B sphere centres sit in VGPRs while the loop over
-// primitives streams each primitive once through SGPRs, so one scalar fetch
-// feeds B pair tests.  Between batches the wave polls the batch's verdict with
-// a ballot and leaves the loop when the motion (or every lane) has collided.
+// spheres in batches of B: B sphere centres sit in VGPRs while primitives
+// stream through SGPRs, so one scalar fetch feeds B pair tests.  Pair
+// verdicts are gathered with ballots into a wave-wide bit mask held in SGPRs
+// (one compare + one scalar OR per pair).  Between batches the wave polls the
+// mask and leaves when the motion (or every lane) has collided.
 //
-// A pair collides iff  dist(centre, solid) <= r.  The verdict form compares
-// squared distances (no square root except the cylinder's radial distance);
-// the exact form computes the signed distance dist - r itself and keeps its
-// minimum.
+// Two ways to choose the primitives a batch is tested against:
+//  * all of them (fk_cc_batch: lanes hold unrelated configurations);
+//  * culled (motions: the 64 lanes are consecutive waypoints of one short
+//    segment, so their spheres occupy a compact region): the wave reduces the
+//    batch's sphere boxes to one axis-aligned box, every lane tests 1/64 of the
+//    primitives' bounding spheres against it, and only the ballot's set bits
+//    are tested pair by pair.  A primitive whose bounding sphere is farther
+//    than kCullMargin from the box cannot touch any sphere of the batch in any
+//    lane, so the verdicts are those of the full test.
+//
+// A pair collides iff dist(centre, solid) <= r; the verdict form compares
+// squared distances, the exact form computes dist - r and keeps its minimum.
 #pragma once
 #include <float.h>
 
@@ -20,106 +29,237 @@
 
 namespace cprrtc {
 
-template <int B, bool SD>
-__device__ __forceinline__ void pair_tests(const EnvDev& env, const float (&cx)[B],
-                                           const float (&cy)[B], const float (&cz)[B],
-                                           const float (&rad)[B], bool& hit, float& msd) {
-  float r2[B];
-#pragma unroll
-  for (int b = 0; b < B; ++b) r2[b] = rad[b] * rad[b];
+constexpr float kCullMargin = 1e-4f;   // metres; far above float32 rounding of the box test
 
-#pragma unroll 1
-  for (int i = 0; i < env.n_aabb; ++i) {
-    const float4 c = env.aabb[2 * i], h = env.aabb[2 * i + 1];
+// ------------------------------------------------------------------ single-primitive tests
+// B sphere centres (per lane) against one primitive (uniform).  Verdict form
+// ORs ballots into hits; exact form lowers msd.
+
+template <int B, bool SD>
+__device__ __forceinline__ void test_aabb(const float4 c, const float4 h, const float (&cx)[B],
+                                          const float (&cy)[B], const float (&cz)[B],
+                                          const float (&rad)[B], uint64_t& hits, float& msd) {
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const float ex = fmaxf(fabsf(cx[b] - c.x) - h.x, 0.0f);
-      const float ey = fmaxf(fabsf(cy[b] - c.y) - h.y, 0.0f);
-      const float ez = fmaxf(fabsf(cz[b] - c.z) - h.z, 0.0f);
-      const float d2 = ex * ex + ey * ey + ez * ez;
-      if (SD) msd = fminf(msd, sqrtf(d2) - rad[b]);
-      else hit |= d2 <= r2[b];
-    }
+  for (int b = 0; b < B; ++b) {
+    const float ex = fmaxf(fabsf(cx[b] - c.x) - h.x, 0.0f);
+    const float ey = fmaxf(fabsf(cy[b] - c.y) - h.y, 0.0f);
+    const float ez = fmaxf(fabsf(cz[b] - c.z) - h.z, 0.0f);
+    const float d2 = ex * ex + ey * ey + ez * ez;
+    if (SD) msd = fminf(msd, sqrtf(d2) - rad[b]);
+    else hits |= __ballot(d2 <= rad[b] * rad[b]);
   }
-#pragma unroll 1
-  for (int i = 0; i < env.n_obb; ++i) {
-    const float4 c = env.obb[4 * i], u = env.obb[4 * i + 1], v = env.obb[4 * i + 2],
-                 w = env.obb[4 * i + 3];
+}
+
+template <int B, bool SD>
+__device__ __forceinline__ void test_obb(const float4 c, const float4 u, const float4 v,
+                                         const float4 w, const float (&cx)[B],
+                                         const float (&cy)[B], const float (&cz)[B],
+                                         const float (&rad)[B], uint64_t& hits, float& msd) {
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const float tx = cx[b] - c.x, ty = cy[b] - c.y, tz = cz[b] - c.z;
-      const float eu = fmaxf(fabsf(u.x * tx + u.y * ty + u.z * tz) - u.w, 0.0f);
-      const float ev = fmaxf(fabsf(v.x * tx + v.y * ty + v.z * tz) - v.w, 0.0f);
-      const float ew = fmaxf(fabsf(w.x * tx + w.y * ty + w.z * tz) - w.w, 0.0f);
-      const float d2 = eu * eu + ev * ev + ew * ew;
-      if (SD) msd = fminf(msd, sqrtf(d2) - rad[b]);
-      else hit |= d2 <= r2[b];
-    }
+  for (int b = 0; b < B; ++b) {
+    const float tx = cx[b] - c.x, ty = cy[b] - c.y, tz = cz[b] - c.z;
+    const float eu = fmaxf(fabsf(u.x * tx + u.y * ty + u.z * tz) - u.w, 0.0f);
+    const float ev = fmaxf(fabsf(v.x * tx + v.y * ty + v.z * tz) - v.w, 0.0f);
+    const float ew = fmaxf(fabsf(w.x * tx + w.y * ty + w.z * tz) - w.w, 0.0f);
+    const float d2 = eu * eu + ev * ev + ew * ew;
+    if (SD) msd = fminf(msd, sqrtf(d2) - rad[b]);
+    else hits |= __ballot(d2 <= rad[b] * rad[b]);
   }
-#pragma unroll 1
-  for (int i = 0; i < env.n_sph; ++i) {
-    const float4 s = env.sph[i];
+}
+
+template <int B, bool SD>
+__device__ __forceinline__ void test_sphere(const float4 s, const float (&cx)[B],
+                                            const float (&cy)[B], const float (&cz)[B],
+                                            const float (&rad)[B], uint64_t& hits, float& msd) {
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const float tx = cx[b] - s.x, ty = cy[b] - s.y, tz = cz[b] - s.z;
-      const float d2 = tx * tx + ty * ty + tz * tz;
-      if (SD) {
-        msd = fminf(msd, fmaxf(sqrtf(d2) - s.w, 0.0f) - rad[b]);
-      } else {
-        const float reach = s.w + rad[b];
-        hit |= d2 <= reach * reach;
-      }
-    }
-  }
-#pragma unroll 1
-  for (int i = 0; i < env.n_cap; ++i) {
-    const float4 p0 = env.cap[2 * i], dv = env.cap[2 * i + 1];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const float tx = cx[b] - p0.x, ty = cy[b] - p0.y, tz = cz[b] - p0.z;
-      float s = (tx * dv.x + ty * dv.y + tz * dv.z) * dv.w;
-      s = fminf(fmaxf(s, 0.0f), 1.0f);
-      const float wx = tx - s * dv.x, wy = ty - s * dv.y, wz = tz - s * dv.z;
-      const float d2 = wx * wx + wy * wy + wz * wz;
-      if (SD) {
-        msd = fminf(msd, fmaxf(sqrtf(d2) - p0.w, 0.0f) - rad[b]);
-      } else {
-        const float reach = p0.w + rad[b];
-        hit |= d2 <= reach * reach;
-      }
-    }
-  }
-#pragma unroll 1
-  for (int i = 0; i < env.n_cyl; ++i) {
-    const float4 c = env.cyl[2 * i], u = env.cyl[2 * i + 1];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const float tx = cx[b] - c.x, ty = cy[b] - c.y, tz = cz[b] - c.z;
-      const float al = tx * u.x + ty * u.y + tz * u.z;
-      const float wx = tx - al * u.x, wy = ty - al * u.y, wz = tz - al * u.z;
-      const float da = fmaxf(fabsf(al) - c.w, 0.0f);
-      const float dr = fmaxf(sqrtf(wx * wx + wy * wy + wz * wz) - u.w, 0.0f);
-      const float d2 = da * da + dr * dr;
-      if (SD) msd = fminf(msd, sqrtf(d2) - rad[b]);
-      else hit |= d2 <= r2[b];
+  for (int b = 0; b < B; ++b) {
+    const float tx = cx[b] - s.x, ty = cy[b] - s.y, tz = cz[b] - s.z;
+    const float d2 = tx * tx + ty * ty + tz * tz;
+    if (SD) {
+      msd = fminf(msd, fmaxf(sqrtf(d2) - s.w, 0.0f) - rad[b]);
+    } else {
+      const float reach = s.w + rad[b];
+      hits |= __ballot(d2 <= reach * reach);
     }
   }
 }
 
-// Collision state of one lane's configuration q (global memory, stride 1,
-// joint j at q[j]).  lane_on = the lane holds a configuration that counts.
-// MOTION: the wave stops once any counting lane of the motion's segment
-// (bits `segmask` of the ballot) has collided; otherwise once every counting
-// lane has.  early = false evaluates every pair.
-// n_done: robot spheres whose tests against every primitive were evaluated
-// (wave-uniform; a short batch counts only its real spheres).
-template <int B, bool SD, bool MOTION>
+template <int B, bool SD>
+__device__ __forceinline__ void test_capsule(const float4 p0, const float4 dv, const float (&cx)[B],
+                                             const float (&cy)[B], const float (&cz)[B],
+                                             const float (&rad)[B], uint64_t& hits, float& msd) {
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const float tx = cx[b] - p0.x, ty = cy[b] - p0.y, tz = cz[b] - p0.z;
+    float s = (tx * dv.x + ty * dv.y + tz * dv.z) * dv.w;
+    s = fminf(fmaxf(s, 0.0f), 1.0f);
+    const float wx = tx - s * dv.x, wy = ty - s * dv.y, wz = tz - s * dv.z;
+    const float d2 = wx * wx + wy * wy + wz * wz;
+    if (SD) {
+      msd = fminf(msd, fmaxf(sqrtf(d2) - p0.w, 0.0f) - rad[b]);
+    } else {
+      const float reach = p0.w + rad[b];
+      hits |= __ballot(d2 <= reach * reach);
+    }
+  }
+}
+
+template <int B, bool SD>
+__device__ __forceinline__ void test_cylinder(const float4 c, const float4 u, const float (&cx)[B],
+                                              const float (&cy)[B], const float (&cz)[B],
+                                              const float (&rad)[B], uint64_t& hits, float& msd) {
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const float tx = cx[b] - c.x, ty = cy[b] - c.y, tz = cz[b] - c.z;
+    const float al = tx * u.x + ty * u.y + tz * u.z;
+    const float wx = tx - al * u.x, wy = ty - al * u.y, wz = tz - al * u.z;
+    const float da = fmaxf(fabsf(al) - c.w, 0.0f);
+    const float dr = fmaxf(sqrtf(wx * wx + wy * wy + wz * wz) - u.w, 0.0f);
+    const float d2 = da * da + dr * dr;
+    if (SD) msd = fminf(msd, sqrtf(d2) - rad[b]);
+    else hits |= __ballot(d2 <= rad[b] * rad[b]);
+  }
+}
+
+// ------------------------------------------------------------------ all primitives
+
+template <int B, bool SD>
+__device__ __forceinline__ void test_all(const EnvDev& env, const float (&cx)[B],
+                                         const float (&cy)[B], const float (&cz)[B],
+                                         const float (&rad)[B], uint64_t& hits, float& msd) {
+  for (int i = 0; i < env.n_aabb; ++i)
+    test_aabb<B, SD>(env.aabb[2 * i], env.aabb[2 * i + 1], cx, cy, cz, rad, hits, msd);
+  for (int i = 0; i < env.n_obb; ++i)
+    test_obb<B, SD>(env.obb[4 * i], env.obb[4 * i + 1], env.obb[4 * i + 2], env.obb[4 * i + 3],
+                    cx, cy, cz, rad, hits, msd);
+  for (int i = 0; i < env.n_sph; ++i) test_sphere<B, SD>(env.sph[i], cx, cy, cz, rad, hits, msd);
+  for (int i = 0; i < env.n_cap; ++i)
+    test_capsule<B, SD>(env.cap[2 * i], env.cap[2 * i + 1], cx, cy, cz, rad, hits, msd);
+  for (int i = 0; i < env.n_cyl; ++i)
+    test_cylinder<B, SD>(env.cyl[2 * i], env.cyl[2 * i + 1], cx, cy, cz, rad, hits, msd);
+}
+
+// ------------------------------------------------------------------ culled primitives
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Box of the batch's spheres over the counting lanes of the wave.
+struct WaveBox {
+  float lo[3], hi[3];
+};
+
+template <int B>
+__device__ __forceinline__ WaveBox wave_box(const float (&cx)[B], const float (&cy)[B],
+                                            const float (&cz)[B], const float (&rad)[B],
+                                            bool lane_on) {
+  float lx = FLT_MAX, ly = FLT_MAX, lz = FLT_MAX, hx = -FLT_MAX, hy = -FLT_MAX, hz = -FLT_MAX;
+  if (lane_on) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      lx = fminf(lx, cx[b] - rad[b]); hx = fmaxf(hx, cx[b] + rad[b]);
+      ly = fminf(ly, cy[b] - rad[b]); hy = fmaxf(hy, cy[b] + rad[b]);
+      lz = fminf(lz, cz[b] - rad[b]); hz = fmaxf(hz, cz[b] + rad[b]);
+    }
+  }
+  WaveBox box;
+  box.lo[0] = wave_min(lx); box.lo[1] = wave_min(ly); box.lo[2] = wave_min(lz);
+  box.hi[0] = wave_max(hx); box.hi[1] = wave_max(hy); box.hi[2] = wave_max(hz);
+  return box;
+}
+
+// Does the bounding sphere (centre, radius) come within kCullMargin of the box?
+__device__ __forceinline__ bool near_box(const float4 bs, const WaveBox& box) {
+  const float ex = fmaxf(fmaxf(box.lo[0] - bs.x, bs.x - box.hi[0]), 0.0f);
+  const float ey = fmaxf(fmaxf(box.lo[1] - bs.y, bs.y - box.hi[1]), 0.0f);
+  const float ez = fmaxf(fmaxf(box.lo[2] - bs.z, bs.z - box.hi[2]), 0.0f);
+  const float reach = bs.w + kCullMargin;
+  return ex * ex + ey * ey + ez * ez <= reach * reach;
+}
+
+// Test the batch against the primitives of one type whose bounding spheres
+// come near `box`.  The active lanes share the bounding-sphere tests (ranked
+// among themselves: with W = 32 one motion of the wavefront may already have
+// left); set bits of the ballot are then walked in scalar registers.
+// Returns the candidate count.
+template <int B, int TYPE>
+__device__ __forceinline__ int test_culled_type(const EnvDev& env, const WaveBox& box,
+                                                const float (&cx)[B], const float (&cy)[B],
+                                                const float (&cz)[B], const float (&rad)[B],
+                                                uint64_t& hits) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t act = __ballot(1);
+  const int n_act = __popcll(act);
+  const int rank = __popcll(act & ((1ull << lane) - 1ull));
+  int n, boff;
+  if (TYPE == 0) { n = env.n_aabb; boff = 0; }
+  else if (TYPE == 1) { n = env.n_obb; boff = env.n_aabb; }
+  else if (TYPE == 2) { n = env.n_sph; boff = env.n_aabb + env.n_obb; }
+  else if (TYPE == 3) { n = env.n_cap; boff = env.n_aabb + env.n_obb + env.n_sph; }
+  else { n = env.n_cyl; boff = env.n_aabb + env.n_obb + env.n_sph + env.n_cap; }
+  float msd_unused = 0.0f;
+  int count = 0;
+  for (int base = 0; base < n; base += n_act) {
+    const int i = base + rank;
+    const bool cand = (i < n) && near_box(env.bound[boff + min(i, n - 1)], box);
+    uint64_t m = __ballot(cand);
+    count += __popcll(m);
+    while (m) {
+      const int l = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const int p = base + __popcll(act & ((1ull << l) - 1ull));
+      if (TYPE == 0) test_aabb<B, false>(env.aabb[2 * p], env.aabb[2 * p + 1], cx, cy, cz, rad, hits, msd_unused);
+      else if (TYPE == 1) test_obb<B, false>(env.obb[4 * p], env.obb[4 * p + 1], env.obb[4 * p + 2], env.obb[4 * p + 3], cx, cy, cz, rad, hits, msd_unused);
+      else if (TYPE == 2) test_sphere<B, false>(env.sph[p], cx, cy, cz, rad, hits, msd_unused);
+      else if (TYPE == 3) test_capsule<B, false>(env.cap[2 * p], env.cap[2 * p + 1], cx, cy, cz, rad, hits, msd_unused);
+      else test_cylinder<B, false>(env.cyl[2 * p], env.cyl[2 * p + 1], cx, cy, cz, rad, hits, msd_unused);
+    }
+  }
+  return count;
+}
+
+// ------------------------------------------------------------------ one configuration per lane
+
+// Work done by one wave, in units of one lane's work (what the work counters add up).
+struct CcWork {
+  unsigned long long pairs[5];     // pair tests per primitive type
+  unsigned long long centres;      // sphere centres placed
+  unsigned long long culls;        // bounding-sphere tests
+};
+
+__device__ __forceinline__ void cc_work_clear(CcWork& w) {
+  for (int t = 0; t < 5; ++t) w.pairs[t] = 0;
+  w.centres = 0;
+  w.culls = 0;
+}
+
+// Collision state of one lane's configuration q (joint j at q[j]).
+//   lane_on  the lane holds a configuration that counts
+//   MOTION   stop once any counting lane of the segment `segmask` collided
+//            (else once every counting lane has)
+//   CULL     test only primitives near the wave's batch box
+//   early    false: evaluate every batch
+// hits_out: ballot mask of colliding counting lanes; msd_out (SD only).
+// Control flow is wave-uniform except where W = 32 lets two motions of one
+// wave leave at different batches (a box reduced while the other motion has
+// left can only grow by stale lanes, which keeps the culling conservative).
+template <int B, bool SD, bool MOTION, bool CULL>
 __device__ void collide_config(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
                                const EnvDev& env, const float* q, bool lane_on, uint64_t segmask,
-                               bool early, bool& hit_out, float& msd_out, int& n_done) {
-  bool hit = false;
+                               bool early, uint64_t& hits_out, float& msd_out, CcWork& work) {
+  uint64_t hits = 0;
   float msd = FLT_MAX;
-  n_done = 0;
+  const uint64_t on_mask = __ballot(lane_on);
+  const int n_on = __popcll(on_mask & (MOTION ? segmask : ~0ull));
+  const int n_prims = env.n_aabb + env.n_obb + env.n_sph + env.n_cap + env.n_cyl;
   const int nch = rob->n_chains;
   for (int c = 0; c < nch; ++c) {
     Frame T;
@@ -138,21 +278,40 @@ __device__ void collide_config(const RobotDev* __restrict__ rob, const float4* _
           cz[b] = T.r[6] * l.x + T.r[7] * l.y + T.r[8] * l.z + T.p[2];
           rr[b] = l.w;
         }
-        pair_tests<B, SD>(env, cx, cy, cz, rr, hit, msd);
-        n_done += min(B, s1 - s);
-        if (SD) hit = msd <= 0.0f;
+        const int nb = min(B, s1 - s);
+        work.centres += (unsigned long long)nb * n_on;
+        if (CULL) {
+          const WaveBox box = wave_box<B>(cx, cy, cz, rr, lane_on);
+          const int k0 = test_culled_type<B, 0>(env, box, cx, cy, cz, rr, hits);
+          const int k1 = test_culled_type<B, 1>(env, box, cx, cy, cz, rr, hits);
+          const int k2 = test_culled_type<B, 2>(env, box, cx, cy, cz, rr, hits);
+          const int k3 = test_culled_type<B, 3>(env, box, cx, cy, cz, rr, hits);
+          const int k4 = test_culled_type<B, 4>(env, box, cx, cy, cz, rr, hits);
+          const unsigned long long f = (unsigned long long)nb * n_on;
+          work.pairs[0] += k0 * f; work.pairs[1] += k1 * f; work.pairs[2] += k2 * f;
+          work.pairs[3] += k3 * f; work.pairs[4] += k4 * f;
+          work.culls += n_prims;
+        } else {
+          test_all<B, SD>(env, cx, cy, cz, rr, hits, msd);
+          const unsigned long long f = (unsigned long long)nb * n_on;
+          work.pairs[0] += env.n_aabb * f; work.pairs[1] += env.n_obb * f;
+          work.pairs[2] += env.n_sph * f; work.pairs[3] += env.n_cap * f;
+          work.pairs[4] += env.n_cyl * f;
+        }
+        if (SD) hits = __ballot(msd <= 0.0f);
         if (early) {
           if (MOTION) {
-            if ((__ballot(hit && lane_on) & segmask) != 0) goto done;
+            // the segment is done once it collided, or if none of its lanes counts
+            if ((hits & on_mask & segmask) || !(on_mask & segmask)) goto done;
           } else {
-            if (__ballot(lane_on && !hit) == 0) goto done;
+            if ((on_mask & ~hits) == 0) goto done;
           }
         }
       }
     }
   }
 done:
-  hit_out = hit && lane_on;
+  hits_out = hits & on_mask;
   msd_out = msd;
 }
 

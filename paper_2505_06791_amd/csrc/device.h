@@ -44,6 +44,8 @@ struct EnvDev {
   const float4* sph;   // 1 x float4: (centre, radius)
   const float4* cap;   // 2 x float4: (p0, radius), (p1 - p0, 1/|p1 - p0|^2 or 0)
   const float4* cyl;   // 2 x float4: (centre, half length), (unit axis, radius)
+  const float4* bound; // 1 x float4 per primitive, types in the order above:
+                       // bounding sphere (centre, radius) used for culling
 };
 
 enum { KIND_NONE = 0, KIND_POSE = 1, KIND_REL = 2 };

@@ -13,11 +13,14 @@ hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& en
                         const float* q, uint8_t* collide, float* min_sd, bool early, int batch,
                         hipStream_t stream);
 
-hipError_t launch_project_validate(int dof, const RobotDev* rob, const float4* sph,
-                                   const EnvDev& env, const ConDev& con, const ProjDev& prm,
-                                   int n_motions, const float* q_from, const float* q_to,
-                                   float* xi, int* status, int* iters, unsigned long long* work,
-                                   bool early, int batch, hipStream_t stream, bool* supported);
+hipError_t launch_project(int dof, const RobotDev* rob, const ConDev& con, const ProjDev& prm,
+                          int n_motions, const float* q_from, const float* q_to, float* xi,
+                          int* status, int* iters, unsigned long long* work, hipStream_t stream,
+                          bool* supported);
+
+hipError_t launch_validate(const RobotDev* rob, const float4* sph, const EnvDev& env, int W,
+                           int n_motions, const float* xi, int* status, unsigned long long* work,
+                           bool early, bool cull, int batch, hipStream_t stream);
 
 hipError_t launch_project_configs(int dof, const RobotDev* rob, const ConDev& con, int n,
                                   const float* q_in, float* q_out, int* status, float tol,

@@ -1,10 +1,18 @@
-// gfx950 kernels of the hot path: fk_cc_batch, project_validate_motions,
+// gfx950 kernels of the hot path: fk_cc_batch, project_validate_motions
+// (a projection kernel followed by a validation kernel on the same stream),
 // project_configs.  Launch geometry is 256-lane workgroups (4 wavefronts of
 // 64); a motion of W waypoints occupies W consecutive lanes of one
 // wavefront (W = 64: one wavefront per motion, W = 32: two motions per
 // wavefront), so every exchange inside a motion is a wavefront operation
 // (shuffle for the neighbouring waypoint, ballot for validity and for the
 // collision flag) and needs neither LDS nor a barrier.
+//
+// Projection and validation are separate kernels because their register
+// needs differ by ~2x: the projection holds a 6 x n Jacobian and a 6 x 6
+// factor per lane, the collision loop a batch of sphere centres; fused, the
+// collision loop would run at the projection's occupancy.  The projected
+// segment goes through HBM between them (W * dof * 4 bytes per motion,
+// written anyway as the call's output).
 #include "kernels.h"
 
 #include <float.h>
@@ -16,7 +24,7 @@ namespace cprrtc {
 
 constexpr int kBlock = 256;
 
-// ------------------------------------------------------------------ FK + CC
+// ------------------------------------------------------------------ FK + CC, one configuration per lane
 
 template <int B, bool SD>
 __global__ __launch_bounds__(kBlock) void fk_cc_kernel(const RobotDev* __restrict__ rob,
@@ -28,30 +36,30 @@ __global__ __launch_bounds__(kBlock) void fk_cc_kernel(const RobotDev* __restric
   const bool on = i < n_cfg;
   const int dof = rob->dof;
   const float* qi = q + (on ? i : 0) * dof;
-  bool hit;
+  uint64_t hits;
   float msd;
-  int n_done;
-  collide_config<B, SD, false>(rob, sph, env, qi, on, 0ull, early != 0, hit, msd, n_done);
+  CcWork cw;
+  cc_work_clear(cw);
+  collide_config<B, SD, false, false>(rob, sph, env, qi, on, 0ull, early != 0, hits, msd, cw);
   if (on) {
-    collide[i] = hit ? 1 : 0;
+    collide[i] = (hits >> (threadIdx.x & 63)) & 1ull;
     if (SD) min_sd[i] = msd;
   }
 }
 
-// ------------------------------------------------------------------ projection + validation
+// ------------------------------------------------------------------ projection (Algorithm 1)
 
-// Algorithm 1 per motion, Jacobi form: each active lane k computes its update
+// One motion per W lanes, Jacobi form: each active lane k computes its update
 // from the snapshot (its own xi[k] and the neighbour xi[k-1] obtained by a
 // shuffle before anyone writes), validity is gathered with one ballot, prog
 // moves to the end of the contiguous valid run after it, and only lanes past
-// the new prog take their new value.  Then waypoints 1..W-1 run FK + CC with
-// the motion-wide early exit.
-template <int NDOF, int KIND, int B>
-__global__ __launch_bounds__(kBlock) void project_validate_kernel(
-    const RobotDev* __restrict__ rob, const float4* __restrict__ sph, EnvDev env, ConDev con,
-    ProjDev prm, int n_motions, const float* __restrict__ q_from, const float* __restrict__ q_to,
-    float* __restrict__ xi, int* __restrict__ status, int* __restrict__ iters,
-    unsigned long long* __restrict__ work, int early) {
+// the new prog take their new value.  Writes the segment, status
+// (0 = projected, 1 = projection failed) and the iteration count.
+template <int NDOF, int KIND>
+__global__ __launch_bounds__(kBlock) void project_kernel(
+    const RobotDev* __restrict__ rob, ConDev con, ProjDev prm, int n_motions,
+    const float* __restrict__ q_from, const float* __restrict__ q_to, float* __restrict__ xi,
+    int* __restrict__ status, int* __restrict__ iters, unsigned long long* __restrict__ work) {
   const int W = prm.W;
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t motion = gid / W;
@@ -76,9 +84,9 @@ __global__ __launch_bounds__(kBlock) void project_validate_kernel(
   int prog = 0;
   int it = 1;
   bool ok = false;
-  unsigned long long proj_updates = 0;   // waypoint updates computed (active lanes per iteration)
+  unsigned long long updates = 0;   // waypoint updates computed (lanes past prog, per iteration)
   for (; it <= prm.max_iters; ++it) {
-    proj_updates += (unsigned long long)(W - 1 - prog);
+    updates += (unsigned long long)(W - 1 - prog);
     float qprev[NDOF];
 #pragma unroll
     for (int j = 0; j < NDOF; ++j) qprev[j] = __shfl_up(q[j], 1, W);
@@ -113,22 +121,47 @@ __global__ __launch_bounds__(kBlock) void project_validate_kernel(
   float* xk = xi + (motion * W + k) * NDOF;
 #pragma unroll
   for (int j = 0; j < NDOF; ++j) xk[j] = q[j];
-
-  int st = 1;  // CP_MOTION_PROJ_FAIL
-  int n_done = 0;
-  if (ok) {
-    bool hit;
-    float msd;
-    collide_config<B, false, true>(rob, sph, env, xk, k >= 1, segmask, early != 0, hit, msd,
-                                   n_done);
-    st = ((__ballot(hit) & segmask) != 0) ? 2 : 0;
-  }
   if (k == 0) {
-    status[motion] = st;
+    status[motion] = ok ? 0 : 1;
     if (iters) iters[motion] = it;
+    if (work) atomicAdd(&work[6], updates);
+  }
+}
+
+// ------------------------------------------------------------------ validation (FK + CC of projected segments)
+
+// Waypoints 1..W-1 of every motion whose projection succeeded (status 0 from
+// project_kernel) run FK + CC; the motion leaves at the first batch in which
+// any of its waypoints collides.  Status becomes 0 (valid) or 2 (collision).
+template <int B, bool CULL>
+__global__ __launch_bounds__(kBlock) void validate_kernel(
+    const RobotDev* __restrict__ rob, const float4* __restrict__ sph, EnvDev env, int W,
+    int n_motions, const float* __restrict__ xi, int* __restrict__ status,
+    unsigned long long* __restrict__ work, int early) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t motion = gid / W;
+  const int k = (int)(gid % W);
+  const bool in_range = motion < n_motions;
+  const bool checks = in_range && status[motion] == 0;
+  if (__ballot(checks) == 0) return;   // wave-uniform: nothing to check here
+  const int lane = threadIdx.x & 63;
+  const int seg = lane - k;
+  const uint64_t wmask = (W == 64) ? ~0ull : ((1ull << W) - 1ull);
+  const uint64_t segmask = wmask << seg;
+  const bool lane_on = checks && k >= 1;
+  const float* q = xi + (in_range ? (motion * W + k) : 0) * rob->dof;
+  uint64_t hits;
+  float msd;
+  CcWork cw;
+  cc_work_clear(cw);
+  collide_config<B, false, true, CULL>(rob, sph, env, q, lane_on, segmask, early != 0, hits, msd,
+                                       cw);
+  if (checks && k == 0) {
+    status[motion] = (hits & segmask) ? 2 : 0;
     if (work) {
-      atomicAdd(&work[0], (unsigned long long)n_done * (unsigned long long)(W - 1));
-      atomicAdd(&work[1], proj_updates);
+      for (int t = 0; t < 5; ++t) atomicAdd(&work[t], cw.pairs[t]);
+      atomicAdd(&work[5], cw.centres);
+      atomicAdd(&work[7], cw.culls);
     }
   }
 }
@@ -181,29 +214,21 @@ hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& en
   return hipGetLastError();
 }
 
-template <int NDOF, int KIND>
-static void launch_pv_b(int batch, unsigned nb, hipStream_t stream, const RobotDev* rob,
-                        const float4* sph, const EnvDev& env, const ConDev& con,
-                        const ProjDev& prm, int n, const float* qf, const float* qt, float* xi,
-                        int* st, int* it, unsigned long long* work, int early) {
-  if (batch == 4)
-    project_validate_kernel<NDOF, KIND, 4><<<nb, kBlock, 0, stream>>>(rob, sph, env, con, prm, n, qf, qt, xi, st, it, work, early);
-  else
-    project_validate_kernel<NDOF, KIND, 8><<<nb, kBlock, 0, stream>>>(rob, sph, env, con, prm, n, qf, qt, xi, st, it, work, early);
-}
-
 template <int NDOF>
-static bool launch_pv_kind(int kind, int batch, unsigned nb, hipStream_t stream,
-                           const RobotDev* rob, const float4* sph, const EnvDev& env,
-                           const ConDev& con, const ProjDev& prm, int n, const float* qf,
-                           const float* qt, float* xi, int* st, int* it, unsigned long long* work,
-                           int early) {
+static bool launch_project_ndof(int kind, unsigned nb, hipStream_t stream, const RobotDev* rob,
+                                const ConDev& con, const ProjDev& prm, int n, const float* qf,
+                                const float* qt, float* xi, int* st, int* it,
+                                unsigned long long* work) {
   switch (kind) {
-    case KIND_NONE: launch_pv_b<NDOF, KIND_NONE>(batch, nb, stream, rob, sph, env, con, prm, n, qf, qt, xi, st, it, work, early); return true;
-    case KIND_POSE: launch_pv_b<NDOF, KIND_POSE>(batch, nb, stream, rob, sph, env, con, prm, n, qf, qt, xi, st, it, work, early); return true;
+    case KIND_NONE:
+      project_kernel<NDOF, KIND_NONE><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, xi, st, it, work);
+      return true;
+    case KIND_POSE:
+      project_kernel<NDOF, KIND_POSE><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, xi, st, it, work);
+      return true;
     case KIND_REL:
       if constexpr (NDOF % 2 == 0) {
-        launch_pv_b<NDOF, KIND_REL>(batch, nb, stream, rob, sph, env, con, prm, n, qf, qt, xi, st, it, work, early);
+        project_kernel<NDOF, KIND_REL><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, xi, st, it, work);
         return true;
       }
       return false;
@@ -218,25 +243,42 @@ bool dof_supported(int dof) {
   }
 }
 
-hipError_t launch_project_validate(int dof, const RobotDev* rob, const float4* sph,
-                                   const EnvDev& env, const ConDev& con, const ProjDev& prm,
-                                   int n_motions, const float* q_from, const float* q_to,
-                                   float* xi, int* status, int* iters, unsigned long long* work,
-                                   bool early, int batch, hipStream_t stream, bool* supported) {
+hipError_t launch_project(int dof, const RobotDev* rob, const ConDev& con, const ProjDev& prm,
+                          int n_motions, const float* q_from, const float* q_to, float* xi,
+                          int* status, int* iters, unsigned long long* work, hipStream_t stream,
+                          bool* supported) {
   const unsigned nb = blocks_for((int64_t)n_motions * prm.W);
   bool ok = false;
-  const int e = early ? 1 : 0;
   switch (dof) {
-    case 2: ok = launch_pv_kind<2>(con.kind, batch, nb, stream, rob, sph, env, con, prm, n_motions, q_from, q_to, xi, status, iters, work, e); break;
-    case 3: ok = launch_pv_kind<3>(con.kind, batch, nb, stream, rob, sph, env, con, prm, n_motions, q_from, q_to, xi, status, iters, work, e); break;
-    case 6: ok = launch_pv_kind<6>(con.kind, batch, nb, stream, rob, sph, env, con, prm, n_motions, q_from, q_to, xi, status, iters, work, e); break;
-    case 7: ok = launch_pv_kind<7>(con.kind, batch, nb, stream, rob, sph, env, con, prm, n_motions, q_from, q_to, xi, status, iters, work, e); break;
-    case 9: ok = launch_pv_kind<9>(con.kind, batch, nb, stream, rob, sph, env, con, prm, n_motions, q_from, q_to, xi, status, iters, work, e); break;
-    case 14: ok = launch_pv_kind<14>(con.kind, batch, nb, stream, rob, sph, env, con, prm, n_motions, q_from, q_to, xi, status, iters, work, e); break;
+    case 2: ok = launch_project_ndof<2>(con.kind, nb, stream, rob, con, prm, n_motions, q_from, q_to, xi, status, iters, work); break;
+    case 3: ok = launch_project_ndof<3>(con.kind, nb, stream, rob, con, prm, n_motions, q_from, q_to, xi, status, iters, work); break;
+    case 6: ok = launch_project_ndof<6>(con.kind, nb, stream, rob, con, prm, n_motions, q_from, q_to, xi, status, iters, work); break;
+    case 7: ok = launch_project_ndof<7>(con.kind, nb, stream, rob, con, prm, n_motions, q_from, q_to, xi, status, iters, work); break;
+    case 9: ok = launch_project_ndof<9>(con.kind, nb, stream, rob, con, prm, n_motions, q_from, q_to, xi, status, iters, work); break;
+    case 14: ok = launch_project_ndof<14>(con.kind, nb, stream, rob, con, prm, n_motions, q_from, q_to, xi, status, iters, work); break;
     default: ok = false;
   }
   *supported = ok;
   return ok ? hipGetLastError() : hipSuccess;
+}
+
+hipError_t launch_validate(const RobotDev* rob, const float4* sph, const EnvDev& env, int W,
+                           int n_motions, const float* xi, int* status, unsigned long long* work,
+                           bool early, bool cull, int batch, hipStream_t stream) {
+  const unsigned nb = blocks_for((int64_t)n_motions * W);
+  const int e = early ? 1 : 0;
+  if (cull) {
+    if (batch == 4)
+      validate_kernel<4, true><<<nb, kBlock, 0, stream>>>(rob, sph, env, W, n_motions, xi, status, work, e);
+    else
+      validate_kernel<8, true><<<nb, kBlock, 0, stream>>>(rob, sph, env, W, n_motions, xi, status, work, e);
+  } else {
+    if (batch == 4)
+      validate_kernel<4, false><<<nb, kBlock, 0, stream>>>(rob, sph, env, W, n_motions, xi, status, work, e);
+    else
+      validate_kernel<8, false><<<nb, kBlock, 0, stream>>>(rob, sph, env, W, n_motions, xi, status, work, e);
+  }
+  return hipGetLastError();
 }
 
 template <int NDOF>

@@ -132,10 +132,30 @@ def _oracle_pv(w, q_from, q_to, W, tau_task, max_iters=32):
                                       q_to.astype(np.float64), n_threads=8)
 
 
-def _compare_pv(name, ref, xi, st, it):
+def _revalidate(w, xi, st, W, tau_task, tau=0.05, tau_sm=0.025):
+    """Band-independent check: the oracle re-validates every motion the GPU
+    projected, on the GPU's own waypoints (task error, spacing, limits, and
+    the collision verdict outside the 1e-5 m band)."""
+    ro, eo, co = oracle_views(w)
+    lo, hi = w["robot"]["lo"], w["robot"]["hi"]
+    for m in np.nonzero(st != O.MOTION_PROJ_FAIL)[0]:
+        x = xi[m].astype(np.float64)
+        for k in range(1, W):
+            assert np.abs(O.task_error(ro, co, x[k])).max() < tau_task + BAND, (m, k)
+            assert np.linalg.norm(x[k] - x[k - 1]) < tau + tau_sm + BAND, (m, k)
+        assert np.all(x >= lo - 1e-6) and np.all(x <= hi + 1e-6)
+        col, sd = O.fk_cc_batch(ro, eo, x[1:])
+        msd = sd.min()
+        if abs(msd) > BAND:
+            assert (st[m] == O.MOTION_COLLISION) == (msd <= 0.0), (m, st[m], msd)
+
+
+def _compare_pv(name, ref, xi, st, it, w=None, W=64, tau_task=1e-3):
     band = (ref["proj_margin"] < BAND) | (np.abs(ref["min_sd"]) < BAND)
     proj_band = ref["proj_margin"] < BAND
     ok = ~band
+    if w is not None:
+        _revalidate(w, xi, st, W, tau_task)
     _report("project_validate", workload=name, motions=len(st), band=int(band.sum()),
             valid=int((ref["status"] == 0).sum()), proj_fail=int((ref["status"] == 1).sum()),
             collision=int((ref["status"] == 2).sum()))
@@ -158,7 +178,7 @@ def test_project_validate_matches_oracle(G, name, W, M):
     q_from, q_to = motion_set(w, M, 11, W=W)
     ref = _oracle_pv(w, q_from, q_to, W, w["tau_task"])
     xi, st, it = _run_pv(G, w, q_from, q_to, dict(W=W, tau_task=w["tau_task"]))
-    _compare_pv(name, ref, xi, st, it)
+    _compare_pv(name, ref, xi, st, it, w, W, w["tau_task"])
 
 
 def test_project_validate_without_constraint_is_interpolation(G):
@@ -177,16 +197,52 @@ def test_project_validate_without_constraint_is_interpolation(G):
     assert np.array_equal(st[~band], ref_o["status"][~band])
 
 
-def test_early_exit_and_batch_do_not_change_verdicts(G):
-    w = I.workload("cluttered", 2500)
-    q_from, q_to = motion_set(w, 40, 5)
-    base = _run_pv(G, w, q_from, q_to, dict(W=64, sphere_batch=8))
-    full = _run_pv(G, w, q_from, q_to, dict(W=64, sphere_batch=8), flags=G.NO_EARLY_EXIT)
-    small = _run_pv(G, w, q_from, q_to, dict(W=64, sphere_batch=4))
-    for other in (full, small):
+@pytest.mark.parametrize("name,W", [("cluttered", 64), ("cluttered", 32), ("dual", 64)])
+def test_early_exit_culling_and_batch_do_not_change_verdicts(G, name, W):
+    """Early exit, culling and the batch size only skip or reorder work."""
+    w = I.workload(name, 2500)
+    q_from, q_to = motion_set(w, 40, 5, W=W)
+    kw = dict(W=W, tau_task=w["tau_task"])
+    base = _run_pv(G, w, q_from, q_to, dict(kw, sphere_batch=8))
+    variants = [_run_pv(G, w, q_from, q_to, dict(kw, sphere_batch=8), flags=G.NO_EARLY_EXIT),
+                _run_pv(G, w, q_from, q_to, dict(kw, sphere_batch=8), flags=G.NO_CULL),
+                _run_pv(G, w, q_from, q_to, dict(kw, sphere_batch=8),
+                        flags=G.NO_CULL | G.NO_EARLY_EXIT),
+                _run_pv(G, w, q_from, q_to, dict(kw, sphere_batch=4))]
+    for other in variants:
         assert np.array_equal(base[1], other[1])
         assert np.array_equal(base[2], other[2])
         assert np.array_equal(base[0], other[0])
+
+
+def test_split_calls_equal_fused_call(G):
+    """project_motions then validate_motions == project_validate_motions; the
+    work counters add up the same way."""
+    w = I.workload("cluttered", 2600)
+    q_from, q_to = motion_set(w, 33, 6)
+    robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
+    prm = G.proj_params(W=64)
+    M = len(q_from)
+    qf, qt = torch.from_numpy(q_from).to(DEV), torch.from_numpy(q_to).to(DEV)
+    outs = []
+    for split in (False, True):
+        xi = torch.empty((M, 64, 7), device=DEV)
+        st = torch.empty(M, dtype=torch.int32, device=DEV)
+        it = torch.empty(M, dtype=torch.int32, device=DEV)
+        wk = torch.zeros(G.WORK_SLOTS, dtype=torch.int64, device=DEV)
+        if split:
+            G.project_motions(robot, con, prm, qf, qt, xi, st, it, work=wk)
+            proj_status = st.clone()
+            G.validate_motions(robot, env, prm, xi, st, work=wk)
+            assert set(proj_status.cpu().numpy().tolist()) <= {0, 1}
+        else:
+            G.project_validate_motions(robot, env, con, prm, qf, qt, xi, st, it, work=wk)
+        torch.cuda.synchronize()
+        outs.append((xi.cpu().numpy(), st.cpu().numpy(), it.cpu().numpy(), wk.cpu().numpy()))
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    wk = outs[0][3]
+    assert wk[6] > 0 and wk[5] > 0 and wk[7] > 0
 
 
 def test_project_validate_edge_cases(G):
@@ -252,5 +308,5 @@ def test_full_size_sampled(G, name, M, sample):
     idx = np.sort(rng.choice(M, sample, replace=False))
     idx = np.concatenate([idx, [M - 1]])
     ref = _oracle_pv(w, q_from[idx], q_to[idx], 64, w["tau_task"])
-    _compare_pv(name + "-full", ref, xi[idx], st[idx], it[idx])
+    _compare_pv(name + "-full", ref, xi[idx], st[idx], it[idx], w, 64, w["tau_task"])
     assert set(np.unique(st)).issubset({0, 1, 2})
