@@ -205,6 +205,63 @@ int project_configs(const cp_robot* robot, const cp_constraint* constraint, int3
                     const float* d_q_in, float* d_q_out, int32_t* d_status, double tol,
                     int32_t max_iters, double alpha, double lambda, void* stream);
 
+/* ------------------------------------------------------------ planning */
+
+/* Constrained bidirectional RRT-Connect (Section III): two trees rooted at
+ * start and goal; in each round n_groups wavefronts each sample a Halton
+ * point (shifted by the seed; sampling restarts with every call), extend
+ * their tree (half the wavefronts per tree) from its nearest node by one
+ * projected, validated motion of at most (W-1) tau, then keep extending the
+ * same tree towards the nearest node of the other tree while every segment is
+ * valid and strictly reduces that distance; the trees connect when an end
+ * comes within tau + tau_sm of that node.  Searches see the nodes published
+ * before the round. */
+typedef struct cp_plan_opts {
+  cp_proj_params proj;   /* projection / validation parameters */
+  int32_t n_groups;      /* extensions (wavefronts) per round, >= 2 (256) */
+  int32_t max_rounds;    /* round budget (2000) */
+  int32_t capacity;      /* nodes per tree (16384) */
+  int32_t max_connect;   /* extension steps towards the other tree per round (64) */
+  int32_t poll_every;    /* rounds between host checks of the done flag (1) */
+} cp_plan_opts;
+
+/* Dense path: every waypoint of every edge, consecutive spacing < tau + tau_sm;
+ * q[0] and q[len-1] are the caller's start and goal values. */
+typedef struct cp_path {
+  int32_t capacity;      /* in: rows of q allocated by the caller */
+  int32_t len;           /* out: rows of the path (also set when capacity is too small) */
+  int32_t dof;           /* out */
+  double* q;             /* [capacity][dof], caller-allocated, host */
+} cp_path;
+
+typedef struct cp_plan_stats {
+  int32_t rounds;        /* rounds launched */
+  int32_t nodes[2];      /* tree sizes (start tree, goal tree) */
+  int32_t overflow;      /* 1 if a tree reached its capacity */
+} cp_plan_stats;
+
+typedef struct cp_planner cp_planner;  /* opaque: device trees and scratch for one robot */
+
+void cp_plan_opts_default(cp_plan_opts* o);
+/* Allocates the trees (2 x capacity x (W+1) x dof floats) once, for repeated
+ * cp_plan calls.  Errors: CP_E_ARG, CP_E_UNSUPPORTED (dof), CP_E_HIP. */
+int cp_planner_create(const cp_robot* robot, const cp_plan_opts* opts, cp_planner** out);
+void cp_planner_destroy(cp_planner* planner);
+/* Synchronous on `stream` (NULL = default).  start, goal: [dof] host doubles,
+ * inside the limits, on the manifold (||e||_inf < tau_task) and collision-free.
+ * Returns CP_OK with the path in out, CP_NO_SOLUTION when max_rounds pass
+ * without a connection, CP_E_START / CP_E_GOAL for a bad endpoint,
+ * CP_E_CAPACITY when out->capacity < out->len or a tree fills up.
+ * stats: nullable.  A planner serves one call at a time. */
+int cp_plan(cp_planner* planner, const cp_env* env, const cp_constraint* constraint,
+            const double* start, const double* goal, uint64_t seed, cp_path* out,
+            cp_plan_stats* stats, void* stream);
+/* One-shot form: creates a planner with opts (NULL = defaults), plans on the
+ * default stream, destroys it. */
+int plan(const cp_robot* robot, const cp_env* env, const cp_constraint* constraint,
+         const double* start, const double* goal, uint64_t seed, const cp_plan_opts* opts,
+         cp_path* out);
+
 #ifdef __cplusplus
 }
 #endif

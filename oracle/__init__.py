@@ -243,3 +243,31 @@ def project_config(robot: Robot, con: Constraint, q, tol=1e-9, max_iters=100, al
                                  C.c_int32(max_iters), C.c_double(alpha), C.c_double(lam),
                                  _ptr(out), C.byref(it))
     return bool(ok), out, it.value
+
+
+def plan(robot: Robot, env: Env, con: Constraint, prm, start, goal, seed, max_samples=20000,
+         capacity=16384, max_connect=64):
+    """Sequential FP64 planner; returns (status, path [len, dof] or None, nodes)."""
+    start = _f64(start)
+    goal = _f64(goal)
+    cap_path = 2 * capacity * (prm.W - 1) + 2
+    cap_path = min(cap_path, 200000)
+    path = np.zeros((cap_path, robot.dof))
+    plen = C.c_int32(0)
+    nodes = np.zeros(2, np.int32)
+    L = lib()
+    L.or_plan.restype = C.c_int32
+    st = L.or_plan(C.byref(robot.s), C.byref(env.s), C.byref(con.s), C.byref(prm), _ptr(start),
+                   _ptr(goal), C.c_uint64(seed), C.c_int32(max_samples), C.c_int32(capacity),
+                   C.c_int32(max_connect), _ptr(path), C.c_int32(cap_path), C.byref(plen),
+                   _ptr(nodes, _ip))
+    return st, (path[: plen.value].copy() if st == 1 else None), nodes
+
+
+def path_report(robot: Robot, env: Env, con: Constraint, path):
+    """(worst task error, worst spacing, min signed distance, inside limits)."""
+    path = _f64(path)
+    out = np.zeros(4)
+    lib().or_path_report(C.byref(robot.s), C.byref(env.s), C.byref(con.s), _ptr(path),
+                         C.c_int32(len(path)), _ptr(out))
+    return dict(task_error=out[0], spacing=out[1], min_sd=out[2], inside=bool(out[3]))

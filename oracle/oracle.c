@@ -612,3 +612,188 @@ int32_t or_project_config(const or_robot* r, const or_constraint* c, const doubl
   if (iters) *iters = max_iters;
   return 0;
 }
+
+/* ---------------------------------------------------------------- planning */
+
+/* splitmix64 (Steele, Lea, Flood 2014): the per-dimension shifts of the
+ * Halton sequence are drawn from it, seeded with the planner's seed. */
+static uint64_t splitmix64_next(uint64_t* state) {
+  uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* Radical inverse of i in base b: the Halton coordinate (Evaluation section:
+ * samples come from the Halton sequence, reseeded only at the start). */
+static double radical_inverse(uint32_t i, uint32_t b) {
+  double f = 1.0 / b, r = 0.0;
+  while (i) {
+    r += f * (double)(i % b);
+    i /= b;
+    f /= b;
+  }
+  return r;
+}
+
+typedef struct {
+  int n, W, cap, count;
+  double* q;        /* [cap][n] */
+  int* parent;      /* [cap] */
+  double* edge;     /* [cap][W][n] */
+} or_tree;
+
+static int tree_nearest(const or_tree* t, const double* x, int n) {
+  int best = 0;
+  double bd = DBL_MAX;
+  for (int i = 0; i < t->count; ++i) {
+    double d = 0.0;
+    for (int j = 0; j < n; ++j) d += (t->q[(size_t)i * n + j] - x[j]) * (t->q[(size_t)i * n + j] - x[j]);
+    if (d < bd) { bd = d; best = i; }
+  }
+  return best;
+}
+
+static double dist_sq(const double* a, const double* b, int n) {
+  double d = 0.0;
+  for (int j = 0; j < n; ++j) d += (a[j] - b[j]) * (a[j] - b[j]);
+  return d;
+}
+
+/* q_steer = a + min(1, step / |b - a|) (b - a) */
+static void steer_to(const double* a, const double* b, double step, int n, double* out) {
+  const double d = sqrt(dist_sq(a, b, n));
+  const double s = d > step ? step / d : 1.0;
+  for (int j = 0; j < n; ++j) out[j] = a[j] + s * (b[j] - a[j]);
+}
+
+/* One motion a -> b: straight-line waypoints, ParallelProject, collision
+ * check of waypoints 1..W-1 (Section III).  xi receives the segment. */
+static int motion_ok(const or_robot* r, const or_env* env, const or_constraint* c,
+                     const or_params* p, const double* a, const double* b, double* xi) {
+  const int n = r->dof, W = p->W;
+  for (int k = 0; k < W; ++k) {
+    const double s = (double)k / (double)(W - 1);
+    for (int j = 0; j < n; ++j) xi[(size_t)k * n + j] = a[j] + s * (b[j] - a[j]);
+  }
+  int32_t it;
+  double mg;
+  if (!or_parallel_project(r, c, p, xi, &it, &mg, NULL)) return 0;
+  for (int k = 1; k < W; ++k)
+    if (or_config_min_sd(r, env, xi + (size_t)k * n) <= 0.0) return 0;
+  return 1;
+}
+
+static int tree_append(or_tree* t, int parent, const double* xi) {
+  if (t->count >= t->cap) return -1;
+  const int s = t->count++;
+  memcpy(t->q + (size_t)s * t->n, xi + (size_t)(t->W - 1) * t->n, sizeof(double) * t->n);
+  t->parent[s] = parent;
+  memcpy(t->edge + (size_t)s * t->W * t->n, xi, sizeof(double) * t->W * t->n);
+  return s;
+}
+
+int32_t or_plan(const or_robot* r, const or_env* env, const or_constraint* c, const or_params* p,
+                const double* start, const double* goal, uint64_t seed, int32_t max_samples,
+                int32_t capacity, int32_t max_connect, double* path, int32_t cap_path,
+                int32_t* path_len, int32_t* nodes) {
+  static const uint32_t primes[16] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53};
+  const int n = r->dof, W = p->W;
+  const double step = (W - 1) * p->tau, tol = p->tau + p->tau_sm;
+  or_tree tr[2];
+  for (int t = 0; t < 2; ++t) {
+    tr[t].n = n; tr[t].W = W; tr[t].cap = capacity; tr[t].count = 1;
+    tr[t].q = (double*)malloc(sizeof(double) * (size_t)capacity * n);
+    tr[t].parent = (int*)malloc(sizeof(int) * (size_t)capacity);
+    tr[t].edge = (double*)malloc(sizeof(double) * (size_t)capacity * W * n);
+    memcpy(tr[t].q, t == 0 ? start : goal, sizeof(double) * n);
+    tr[t].parent[0] = -1;
+  }
+  double shift[16];
+  uint64_t state = seed;
+  for (int j = 0; j < 16; ++j) shift[j] = (double)(splitmix64_next(&state) >> 11) * (1.0 / 9007199254740992.0);
+  double* xi = (double*)malloc(sizeof(double) * (size_t)W * n);
+  double qr[MAXDOF], qs[MAXDOF], qe[MAXDOF], qt[MAXDOF];
+  int found = 0, fa = -1, fb = -1, fx = 0, status = 0;
+  if (sqrt(dist_sq(start, goal, n)) < tol) { found = 1; fx = 0; fa = 0; fb = 0; }
+  for (int32_t i = 0; i < max_samples && !found; ++i) {
+    const int X = i & 1, Y = X ^ 1;
+    for (int j = 0; j < n; ++j) {
+      double u = radical_inverse((uint32_t)i + 1u, primes[j]) + shift[j];
+      u -= floor(u);
+      qr[j] = r->lo[j] + u * (r->hi[j] - r->lo[j]);
+    }
+    const int near = tree_nearest(&tr[X], qr, n);
+    steer_to(tr[X].q + (size_t)near * n, qr, step, n, qs);
+    if (!motion_ok(r, env, c, p, tr[X].q + (size_t)near * n, qs, xi)) continue;
+    int cur = tree_append(&tr[X], near, xi);
+    if (cur < 0) { status = -1; break; }
+    memcpy(qe, xi + (size_t)(W - 1) * n, sizeof(double) * n);
+    const int tgt = tree_nearest(&tr[Y], qe, n);
+    memcpy(qt, tr[Y].q + (size_t)tgt * n, sizeof(double) * n);
+    double dcur = dist_sq(qe, qt, n);
+    for (int s = 0;; ++s) {
+      if (dcur < tol * tol) { found = 1; fx = X; fa = cur; fb = tgt; break; }
+      if (s >= max_connect) break;
+      steer_to(qe, qt, step, n, qs);
+      if (!motion_ok(r, env, c, p, qe, qs, xi)) break;
+      const double dnew = dist_sq(xi + (size_t)(W - 1) * n, qt, n);
+      if (!(dnew < dcur)) break;
+      cur = tree_append(&tr[X], cur, xi);
+      if (cur < 0) { status = -1; break; }
+      memcpy(qe, xi + (size_t)(W - 1) * n, sizeof(double) * n);
+      dcur = dnew;
+    }
+    if (status < 0) break;
+  }
+  if (nodes) { nodes[0] = tr[0].count; nodes[1] = tr[1].count; }
+  if (found) {
+    const int n0 = fx == 0 ? fa : fb, n1 = fx == 0 ? fb : fa;
+    int len = 2, d0 = 0, d1 = 0;
+    for (int v = n0; v > 0; v = tr[0].parent[v]) ++d0;
+    for (int v = n1; v > 0; v = tr[1].parent[v]) ++d1;
+    len = 2 + (d0 + d1) * (W - 1);
+    if (sqrt(dist_sq(start, goal, n)) < tol && d0 == 0 && d1 == 0) len = 2;
+    *path_len = len;
+    if (len > cap_path) {
+      status = -2;
+    } else {
+      /* tree-0 chain root -> n0 (edges forward), then n1, then tree-1 chain n1 -> root (backward) */
+      int* chain = (int*)malloc(sizeof(int) * (size_t)(d0 + 1));
+      int m = 0;
+      for (int v = n0; v > 0; v = tr[0].parent[v]) chain[m++] = v;
+      int row = 0;
+      memcpy(path + (size_t)row++ * n, start, sizeof(double) * n);
+      for (int i2 = m - 1; i2 >= 0; --i2)
+        for (int k = 1; k < W; ++k)
+          memcpy(path + (size_t)row++ * n, tr[0].edge + ((size_t)chain[i2] * W + k) * n, sizeof(double) * n);
+      free(chain);
+      memcpy(path + (size_t)row++ * n, tr[1].q + (size_t)n1 * n, sizeof(double) * n);
+      for (int v = n1; v > 0; v = tr[1].parent[v])
+        for (int k = W - 2; k >= 0; --k)
+          memcpy(path + (size_t)row++ * n, tr[1].edge + ((size_t)v * W + k) * n, sizeof(double) * n);
+      memcpy(path + (size_t)(len - 1) * n, goal, sizeof(double) * n);
+      status = 1;
+    }
+  }
+  for (int t = 0; t < 2; ++t) { free(tr[t].q); free(tr[t].parent); free(tr[t].edge); }
+  free(xi);
+  return status;
+}
+
+void or_path_report(const or_robot* r, const or_env* env, const or_constraint* c,
+                    const double* path, int32_t len, double* out) {
+  const int n = r->dof;
+  double worst_e = 0.0, worst_sp = 0.0, msd = DBL_MAX;
+  int inside = 1;
+  for (int i = 0; i < len; ++i) {
+    const double* q = path + (size_t)i * n;
+    double e[MAXM];
+    const int m = or_task_error(r, c, q, e);
+    for (int k = 0; k < m; ++k) worst_e = fmax(worst_e, fabs(e[k]));
+    if (i > 0) worst_sp = fmax(worst_sp, sqrt(dist_sq(q, q - n, n)));
+    msd = fmin(msd, or_config_min_sd(r, env, q));
+    for (int j = 0; j < n; ++j) if (q[j] < r->lo[j] || q[j] > r->hi[j]) inside = 0;
+  }
+  out[0] = worst_e; out[1] = worst_sp; out[2] = msd; out[3] = inside;
+}

@@ -99,6 +99,22 @@ int32_t or_project_config(const or_robot* r, const or_constraint* c, const doubl
                           double tol, int32_t max_iters, double alpha, double lambda,
                           double* q_out, int32_t* iters);
 
+/* Sequential constrained RRT-Connect with the same semantics as the GPU
+ * planner run with one extension per round.  path: [cap_path][dof];
+ * returns 1 if a path was found (*path_len rows), 0 if the sample budget ran
+ * out, -1 if a tree filled up, -2 if the path buffer is too small. */
+int32_t or_plan(const or_robot* r, const or_env* env, const or_constraint* c, const or_params* p,
+                const double* start, const double* goal, uint64_t seed, int32_t max_samples,
+                int32_t capacity, int32_t max_connect, double* path, int32_t cap_path,
+                int32_t* path_len, int32_t* nodes);
+
+/* Re-validation of a dense path: limits, ||e||_inf < tau_task + slack,
+ * consecutive spacing < tau + tau_sm + slack, minimum signed distance of every
+ * waypoint.  out[0] = worst task error, out[1] = worst spacing, out[2] =
+ * minimum signed distance, out[3] = 1 if all waypoints are inside the limits. */
+void or_path_report(const or_robot* r, const or_env* env, const or_constraint* c,
+                    const double* path, int32_t len, double* out);
+
 #ifdef __cplusplus
 }
 #endif

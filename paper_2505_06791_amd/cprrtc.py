@@ -57,6 +57,19 @@ class ProjParams(C.Structure):
                 ("lam", C.c_double), ("sphere_batch", C.c_int32)]
 
 
+class PlanOpts(C.Structure):
+    _fields_ = [("proj", ProjParams), ("n_groups", C.c_int32), ("max_rounds", C.c_int32),
+                ("capacity", C.c_int32), ("max_connect", C.c_int32), ("poll_every", C.c_int32)]
+
+
+class Path(C.Structure):
+    _fields_ = [("capacity", C.c_int32), ("len", C.c_int32), ("dof", C.c_int32), ("q", _dp)]
+
+
+class PlanStats(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("nodes", C.c_int32 * 2), ("overflow", C.c_int32)]
+
+
 _lib = None
 
 
@@ -81,6 +94,13 @@ def lib():
                                       vp, vp, vp, vp, vp, vp, vp]
         L.validate_motions.argtypes = [vp, vp, C.POINTER(ProjParams), C.c_int32, vp, vp, vp,
                                        C.c_int32, vp]
+        L.cp_plan_opts_default.argtypes = [C.POINTER(PlanOpts)]
+        L.cp_planner_create.argtypes = [vp, C.POINTER(PlanOpts), C.POINTER(vp)]
+        L.cp_planner_destroy.argtypes = [vp]
+        L.cp_plan.argtypes = [vp, vp, C.POINTER(Constraint), _dp, _dp, C.c_uint64,
+                              C.POINTER(Path), C.POINTER(PlanStats), vp]
+        L.plan.argtypes = [vp, vp, C.POINTER(Constraint), _dp, _dp, C.c_uint64,
+                           C.POINTER(PlanOpts), C.POINTER(Path)]
         L.project_configs.argtypes = [vp, C.POINTER(Constraint), C.c_int32, vp, vp, vp,
                                       C.c_double, C.c_int32, C.c_double, C.c_double, vp]
         _lib = L
@@ -238,3 +258,51 @@ def project_configs(robot: Robot, con: Constraint, q_in, q_out, status, tol=1e-5
     _check(lib().project_configs(robot.handle, C.byref(con), n, _dev(q_in, torch.float32),
                                  _dev(q_out, torch.float32), _dev(status, torch.int32), tol,
                                  max_iters, alpha, lam, _stream(stream)))
+
+
+# ------------------------------------------------------------------ planning
+
+def plan_opts(n_groups=256, max_rounds=2000, capacity=16384, max_connect=64, poll_every=1,
+              **proj) -> PlanOpts:
+    o = PlanOpts()
+    lib().cp_plan_opts_default(C.byref(o))
+    o.proj = proj_params(**proj)
+    o.n_groups, o.max_rounds, o.capacity = n_groups, max_rounds, capacity
+    o.max_connect, o.poll_every = max_connect, poll_every
+    return o
+
+
+class Planner:
+    """cp_planner handle: device trees for one robot, reused across plans."""
+
+    def __init__(self, robot: Robot, opts: PlanOpts | None = None):
+        self.robot = robot
+        self.opts = opts if opts is not None else plan_opts()
+        h = C.c_void_p()
+        _check(lib().cp_planner_create(robot.handle, C.byref(self.opts), C.byref(h)))
+        self.handle = h
+
+    def plan(self, env: Env, con: Constraint, start, goal, seed: int, max_len: int = 200000,
+             stream=None):
+        """Returns (status, path [len, dof] float64 or None, stats dict).
+        status: CP_OK, CP_NO_SOLUTION, or raises CprrtcError for errors."""
+        start = _f64(start)
+        goal = _f64(goal)
+        buf = np.zeros((max_len, self.robot.dof))
+        path = Path(max_len, 0, 0, buf.ctypes.data_as(_dp))
+        stats = PlanStats()
+        strm = _stream(stream) if stream is not None else None
+        rc = lib().cp_plan(self.handle, env.handle, C.byref(con), start.ctypes.data_as(_dp),
+                           goal.ctypes.data_as(_dp), C.c_uint64(seed), C.byref(path),
+                           C.byref(stats), strm)
+        _check(rc)
+        st = dict(rounds=stats.rounds, nodes=(stats.nodes[0], stats.nodes[1]),
+                  overflow=stats.overflow)
+        if rc == CP_OK:
+            return rc, buf[: path.len].copy(), st
+        return rc, None, st
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.cp_planner_destroy(self.handle)
+            self.handle = None

@@ -14,21 +14,10 @@
 
 #include "cprrtc.h"
 #include "device.h"
+#include "handles.h"
 #include "kernels.h"
 
 using namespace cprrtc;
-
-struct cp_robot {
-  RobotDev host;            // host copy (dispatch reads dof, chains)
-  RobotDev* dev = nullptr;  // device copy
-  float4* spheres = nullptr;
-};
-
-struct cp_env {
-  EnvDev view;              // device pointers + counts, passed by value to kernels
-  float4* block = nullptr;  // one allocation holding every primitive
-  int total = 0;
-};
 
 namespace {
 
@@ -79,6 +68,22 @@ int make_constraint(const cp_constraint* c, const cp_robot* robot, ConDev* out) 
 }
 
 }  // namespace
+
+namespace cprrtc {
+int api_fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+int api_hip_fail(hipError_t e, const char* what) { return hip_fail(e, what); }
+int api_constraint(const cp_constraint* c, const cp_robot* robot, ConDev* out) {
+  return make_constraint(c, robot, out);
+}
+}  // namespace cprrtc
 
 extern "C" {
 
@@ -437,3 +442,7 @@ int project_configs(const cp_robot* robot, const cp_constraint* constraint, int3
 }
 
 }  // extern "C"
+
+namespace cprrtc {
+int api_params(const cp_proj_params* params, cp_proj_params* p) { return check_params(params, p); }
+}  // namespace cprrtc

@@ -49,11 +49,7 @@ __global__ __launch_bounds__(kBlock) void fk_cc_kernel(const RobotDev* __restric
 
 // ------------------------------------------------------------------ projection (Algorithm 1)
 
-// One motion per W lanes, Jacobi form: each active lane k computes its update
-// from the snapshot (its own xi[k] and the neighbour xi[k-1] obtained by a
-// shuffle before anyone writes), validity is gathered with one ballot, prog
-// moves to the end of the contiguous valid run after it, and only lanes past
-// the new prog take their new value.  Writes the segment, status
+// One motion per W lanes (project_segment).  Writes the segment, status
 // (0 = projected, 1 = projection failed) and the iteration count.
 template <int NDOF, int KIND>
 __global__ __launch_bounds__(kBlock) void project_kernel(
@@ -81,42 +77,10 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
     }
   }
 
-  int prog = 0;
-  int it = 1;
-  bool ok = false;
+  int it = 0;
   unsigned long long updates = 0;   // waypoint updates computed (lanes past prog, per iteration)
-  for (; it <= prm.max_iters; ++it) {
-    updates += (unsigned long long)(W - 1 - prog);
-    float qprev[NDOF];
-#pragma unroll
-    for (int j = 0; j < NDOF; ++j) qprev[j] = __shfl_up(q[j], 1, W);
-    float g[NDOF], einf;
-    task_step<NDOF, KIND>(rob, con, q, prm.lambda2, g, einf);
-    float d2 = 0.0f, dl[NDOF];
-#pragma unroll
-    for (int j = 0; j < NDOF; ++j) {
-      dl[j] = q[j] - qprev[j];
-      d2 += dl[j] * dl[j];
-    }
-    const float esm = sqrtf(d2) - prm.tau;
-    float qn[NDOF];
-#pragma unroll
-    for (int j = 0; j < NDOF; ++j)
-      qn[j] = fminf(fmaxf(q[j] - prm.alpha * (g[j] + dl[j] * esm), rob->lo[j]), rob->hi[j]);
-    const bool valid = (k <= prog) || ((einf < prm.tau_task) && (esm < prm.tau_sm));
-    const uint64_t bits = (__ballot(valid) & segmask) >> seg;
-    const uint64_t invalid = ~bits & wmask;      // bits 0..prog are set
-    prog = invalid ? (__ffsll((unsigned long long)invalid) - 2) : W - 1;
-    if (prog == W - 1) {
-      ok = true;
-      break;
-    }
-    if (k > prog) {
-#pragma unroll
-      for (int j = 0; j < NDOF; ++j) q[j] = qn[j];
-    }
-  }
-  if (!ok) it = prm.max_iters;
+  const bool ok = project_segment<NDOF, KIND>(rob, con, prm, k, seg, wmask, segmask, false, q, it,
+                                              updates);
 
   float* xk = xi + (motion * W + k) * NDOF;
 #pragma unroll

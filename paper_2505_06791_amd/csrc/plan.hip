@@ -1,0 +1,655 @@
+// plan(): constrained bidirectional RRT-Connect on one GPU (paper Section III).
+//
+// Two trees (rooted at start and goal) live in HBM.  The planner runs in
+// rounds; a round is one launch of plan_round_kernel with n_groups
+// wavefronts, each one tree extension as the paper describes it for one
+// thread block:
+//   sample q_rand (Halton, shifted by the seed) -> nearest node q_near of its
+//   tree -> steer to q_steer at most (W-1) tau away -> W straight-line
+//   waypoints -> ParallelProject -> FK + CC with early exit -> if valid,
+//   append q_end with parent q_near and the dense edge; then extend the same
+//   tree from q_end towards the nearest node of the other tree while each
+//   projected, collision-free segment strictly reduces the distance to it.
+// The trees are connected when an end comes within tau + tau_sm of that node.
+//
+// Concurrency: searches read only the nodes published before the round
+// (published[t]); appends reserve slots with an atomic counter and write the
+// node, its parent and its edge; a one-thread kernel publishes the counters
+// after the round.  So no search reads a node that is being written.  The
+// first wavefront to connect sets `done` by compare-and-swap and records the
+// connection; wavefronts that see `done` leave.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "collide.h"
+#include "cprrtc.h"
+#include "device.h"
+#include "handles.h"
+#include "kernels.h"
+#include "project.h"
+
+namespace cprrtc {
+
+constexpr int kPlanBlock = 256;
+constexpr unsigned kPrimes[kMaxDof] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53};
+
+struct PlanDev {
+  float* q[2];          // [dof][cap] node configurations (structure of arrays)
+  int* parent[2];       // [cap]
+  float* edge[2];       // [cap][W][dof] dense edge from the parent to the node
+  float* scratch;       // [n_groups][W][dof] segment under test
+  int* ctl;             // control block, see kCtl*
+  int cap;
+  int n_groups;
+  int max_connect;
+  float step;           // steer length (W - 1) tau
+  float connect2;       // (tau + tau_sm)^2
+  float shift[kMaxDof]; // Cranley-Patterson shift per dimension
+  unsigned sample_base; // Halton index of the round's first sample
+};
+
+// control block layout (ints)
+enum { kCtlCount = 0, kCtlPublished = 2, kCtlDone = 4, kCtlConn = 5, kCtlOverflow = 8, kCtlInts = 16 };
+
+// Radical inverse of i in base b (Halton coordinate).
+__device__ __forceinline__ float radical_inverse(unsigned i, unsigned b) {
+  const float inv = 1.0f / (float)b;
+  float f = inv, r = 0.0f;
+  while (i) {
+    const unsigned d = i % b;
+    r += (float)d * f;
+    i /= b;
+    f *= inv;
+  }
+  return r;
+}
+
+// Nearest published node (squared L2 in joint space, ties to the lowest
+// index): lanes scan nodes 64 apart, then a wavefront argmin.
+template <int NDOF>
+__device__ __forceinline__ int nearest_node(const float* __restrict__ qs, int n, int cap,
+                                            const float (&x)[NDOF], float& best_d2) {
+  const int lane = threadIdx.x & 63;
+  float best = FLT_MAX;
+  int bi = 0x7fffffff;
+  for (int i = lane; i < n; i += 64) {
+    float d = 0.0f;
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) {
+      const float t = qs[j * cap + i] - x[j];
+      d += t * t;
+    }
+    if (d < best) {
+      best = d;
+      bi = i;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const float ob = __shfl_xor(best, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ob < best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  best_d2 = best;
+  return bi;
+}
+
+template <int NDOF>
+__device__ __forceinline__ float dist2(const float (&a)[NDOF], const float (&b)[NDOF]) {
+  float d = 0.0f;
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) {
+    const float t = a[j] - b[j];
+    d += t * t;
+  }
+  return d;
+}
+
+// q_steer = a + min(1, step / |b - a|) (b - a)
+template <int NDOF>
+__device__ __forceinline__ void steer(const float (&a)[NDOF], const float (&b)[NDOF], float step,
+                                      float (&out)[NDOF]) {
+  const float d = sqrtf(dist2<NDOF>(a, b));
+  const float s = d > step ? step / d : 1.0f;
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) out[j] = a[j] + s * (b[j] - a[j]);
+}
+
+// One motion a -> b on this wavefront (lanes 0..W-1), projected and
+// validated.  q: this lane's projected waypoint; end: xi[W-1] broadcast.
+template <int NDOF, int KIND, int B>
+__device__ bool try_motion(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
+                           const EnvDev& env, const ConDev& con, const ProjDev& prm,
+                           float* __restrict__ scratch, const float (&a)[NDOF],
+                           const float (&b)[NDOF], float (&q)[NDOF], float (&end)[NDOF]) {
+  const int W = prm.W;
+  const int lane = threadIdx.x & 63;
+  const int k = lane % W;
+  const int seg = lane - k;
+  const bool in_motion = lane < W;
+  const uint64_t wmask = (W == 64) ? ~0ull : ((1ull << W) - 1ull);
+  const uint64_t segmask = wmask << seg;
+  const float s = (float)k / (float)(W - 1);
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) q[j] = a[j] + s * (b[j] - a[j]);
+  int iters = 0;
+  unsigned long long updates = 0;
+  const bool ok = project_segment<NDOF, KIND>(rob, con, prm, k, seg, wmask, segmask, !in_motion, q,
+                                              iters, updates);
+  if (!__shfl(ok ? 1 : 0, 0, 64)) return false;
+  float* xk = scratch + (size_t)(in_motion ? lane : 0) * NDOF;
+  if (in_motion) {
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) xk[j] = q[j];
+  }
+  uint64_t hits;
+  float msd;
+  CcWork cw;
+  cc_work_clear(cw);
+  collide_config<B, false, true, true>(rob, sph, env, xk, in_motion && k >= 1, segmask, true, hits,
+                                       msd, cw);
+  const uint64_t all_hits = __ballot((hits & segmask) != 0 && in_motion);
+  if (all_hits) return false;
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) end[j] = __shfl(q[j], W - 1, 64);
+  return true;
+}
+
+// Append the projected segment held in the lanes' q as a new node of tree t
+// with the given parent.  Returns the slot, or -1 if the tree is full.
+template <int NDOF>
+__device__ int append_node(const PlanDev& pd, int W, int t, int parent, const float (&q)[NDOF]) {
+  const int lane = threadIdx.x & 63;
+  int slot = 0;
+  if (lane == 0) slot = atomicAdd(&pd.ctl[kCtlCount + t], 1);
+  slot = __shfl(slot, 0, 64);
+  if (slot >= pd.cap) {
+    if (lane == 0) atomicExch(&pd.ctl[kCtlOverflow], 1);
+    return -1;
+  }
+  if (lane < W) {
+    float* e = pd.edge[t] + ((size_t)slot * W + lane) * NDOF;
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) e[j] = q[j];
+  }
+  if (lane == W - 1) {
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) pd.q[t][(size_t)j * pd.cap + slot] = q[j];
+    pd.parent[t][slot] = parent;
+  }
+  return slot;
+}
+
+template <int NDOF>
+__device__ __forceinline__ void load_node(const PlanDev& pd, int t, int i, float (&out)[NDOF]) {
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) out[j] = pd.q[t][(size_t)j * pd.cap + i];
+}
+
+__device__ __forceinline__ bool plan_done(const PlanDev& pd) {
+  return __atomic_load_n(&pd.ctl[kCtlDone], __ATOMIC_RELAXED) != 0;
+}
+
+template <int NDOF, int KIND, int B>
+__global__ __launch_bounds__(kPlanBlock) void plan_round_kernel(const RobotDev* __restrict__ rob,
+                                                                const float4* __restrict__ sph,
+                                                                EnvDev env, ConDev con,
+                                                                ProjDev prm, PlanDev pd) {
+  const int g = (int)((blockIdx.x * kPlanBlock + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= pd.n_groups) return;                  // wavefront-uniform
+  if (__shfl(plan_done(pd) ? 1 : 0, 0, 64)) return;
+  const int W = prm.W;
+  const int X = g & 1, Y = X ^ 1;               // half the wavefronts grow each tree
+  const int pubX = pd.ctl[kCtlPublished + X], pubY = pd.ctl[kCtlPublished + Y];
+  float* scratch = pd.scratch + (size_t)g * W * NDOF;
+
+  // Halton sample: lane j computes coordinate j, then every lane takes all.
+  float u = 0.0f;
+  if (lane < NDOF) {
+    u = radical_inverse(pd.sample_base + (unsigned)g + 1u, kPrimes[lane]) + pd.shift[lane];
+    u -= floorf(u);
+  }
+  float qr[NDOF];
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) qr[j] = rob->lo[j] + __shfl(u, j, 64) * (rob->hi[j] - rob->lo[j]);
+
+  float d2;
+  const int near = nearest_node<NDOF>(pd.q[X], pubX, pd.cap, qr, d2);
+  float qn[NDOF], qs[NDOF], q[NDOF], qe[NDOF];
+  load_node<NDOF>(pd, X, near, qn);
+  steer<NDOF>(qn, qr, pd.step, qs);
+  if (!try_motion<NDOF, KIND, B>(rob, sph, env, con, prm, scratch, qn, qs, q, qe)) return;
+  int cur = append_node<NDOF>(pd, W, X, near, q);
+  if (cur < 0) return;
+
+  // extend the same tree towards the nearest node of the other tree
+  float qt[NDOF];
+  const int tgt = nearest_node<NDOF>(pd.q[Y], pubY, pd.cap, qe, d2);
+  load_node<NDOF>(pd, Y, tgt, qt);
+  float dcur = dist2<NDOF>(qe, qt);
+  for (int c = 0;; ++c) {
+    if (dcur < pd.connect2) {
+      if (lane == 0 && atomicCAS(&pd.ctl[kCtlDone], 0, 1) == 0) {
+        pd.ctl[kCtlConn + 0] = X;
+        pd.ctl[kCtlConn + 1] = cur;
+        pd.ctl[kCtlConn + 2] = tgt;
+      }
+      return;
+    }
+    if (c >= pd.max_connect) return;
+    if (__shfl(plan_done(pd) ? 1 : 0, 0, 64)) return;
+    steer<NDOF>(qe, qt, pd.step, qs);
+    float qe2[NDOF];
+    if (!try_motion<NDOF, KIND, B>(rob, sph, env, con, prm, scratch, qe, qs, q, qe2)) return;
+    const float dnew = dist2<NDOF>(qe2, qt);
+    if (!(dnew < dcur)) return;                  // no progress: stop extending
+    cur = append_node<NDOF>(pd, W, X, cur, q);
+    if (cur < 0) return;
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) qe[j] = qe2[j];
+    dcur = dnew;
+  }
+}
+
+// Roots (start in tree 0, goal in tree 1) and counters of a fresh plan.
+__global__ void plan_init_kernel(PlanDev pd, const float* __restrict__ ends, int dof) {
+  const int t = threadIdx.x;
+  if (t < 2) {
+    for (int j = 0; j < dof; ++j) pd.q[t][(size_t)j * pd.cap] = ends[t * dof + j];
+    pd.parent[t][0] = -1;
+  }
+  if (t < kCtlInts) pd.ctl[t] = (t == kCtlCount || t == kCtlCount + 1 || t == kCtlPublished ||
+                                  t == kCtlPublished + 1) ? 1 : 0;
+}
+
+__global__ void publish_kernel(int* ctl, int cap) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl[kCtlPublished + 0] = min(ctl[kCtlCount + 0], cap);
+    ctl[kCtlPublished + 1] = min(ctl[kCtlCount + 1], cap);
+  }
+}
+
+// Path assembly.  Item i = (tree, node, mode, offset): mode 0 copies points
+// 1..W-1 of the node's edge, mode 1 copies points W-2..0 (the edge walked
+// backwards), mode 2 copies the node's own configuration (one point).
+__global__ void gather_path_kernel(PlanDev pd, const int* __restrict__ items, int n_items, int W,
+                                   int dof, float* __restrict__ out) {
+  const int i = blockIdx.x;
+  if (i >= n_items) return;
+  const int tree = items[4 * i + 0], node = items[4 * i + 1], mode = items[4 * i + 2],
+            off = items[4 * i + 3];
+  if (mode == 2) {
+    for (int j = threadIdx.x; j < dof; j += blockDim.x)
+      out[(size_t)off * dof + j] = pd.q[tree][(size_t)j * pd.cap + node];
+    return;
+  }
+  const float* e = pd.edge[tree] + (size_t)node * W * dof;
+  for (int t = threadIdx.x; t < (W - 1) * dof; t += blockDim.x) {
+    const int p = t / dof, j = t % dof;
+    const int src = mode == 1 ? (W - 2 - p) : (p + 1);
+    out[(size_t)(off + p) * dof + j] = e[(size_t)src * dof + j];
+  }
+}
+
+template <int NDOF, int KIND>
+static void launch_round_kind(int batch, unsigned nb, hipStream_t st, const RobotDev* rob,
+                              const float4* sph, const EnvDev& env, const ConDev& con,
+                              const ProjDev& prm, const PlanDev& pd) {
+  if (batch == 4)
+    plan_round_kernel<NDOF, KIND, 4><<<nb, kPlanBlock, 0, st>>>(rob, sph, env, con, prm, pd);
+  else
+    plan_round_kernel<NDOF, KIND, 8><<<nb, kPlanBlock, 0, st>>>(rob, sph, env, con, prm, pd);
+}
+
+template <int NDOF>
+static bool launch_round_ndof(int kind, int batch, unsigned nb, hipStream_t st, const RobotDev* rob,
+                              const float4* sph, const EnvDev& env, const ConDev& con,
+                              const ProjDev& prm, const PlanDev& pd) {
+  switch (kind) {
+    case KIND_NONE: launch_round_kind<NDOF, KIND_NONE>(batch, nb, st, rob, sph, env, con, prm, pd); return true;
+    case KIND_POSE: launch_round_kind<NDOF, KIND_POSE>(batch, nb, st, rob, sph, env, con, prm, pd); return true;
+    case KIND_REL:
+      if constexpr (NDOF % 2 == 0) {
+        launch_round_kind<NDOF, KIND_REL>(batch, nb, st, rob, sph, env, con, prm, pd);
+        return true;
+      }
+      return false;
+  }
+  return false;
+}
+
+static bool launch_round(int dof, int kind, int batch, unsigned nb, hipStream_t st,
+                         const RobotDev* rob, const float4* sph, const EnvDev& env,
+                         const ConDev& con, const ProjDev& prm, const PlanDev& pd) {
+  switch (dof) {
+    case 2: return launch_round_ndof<2>(kind, batch, nb, st, rob, sph, env, con, prm, pd);
+    case 3: return launch_round_ndof<3>(kind, batch, nb, st, rob, sph, env, con, prm, pd);
+    case 6: return launch_round_ndof<6>(kind, batch, nb, st, rob, sph, env, con, prm, pd);
+    case 7: return launch_round_ndof<7>(kind, batch, nb, st, rob, sph, env, con, prm, pd);
+    case 9: return launch_round_ndof<9>(kind, batch, nb, st, rob, sph, env, con, prm, pd);
+    case 14: return launch_round_ndof<14>(kind, batch, nb, st, rob, sph, env, con, prm, pd);
+    default: return false;
+  }
+}
+
+}  // namespace cprrtc
+
+// ------------------------------------------------------------------ host side
+
+using namespace cprrtc;
+
+struct cp_planner {
+  const cp_robot* robot = nullptr;
+  cp_plan_opts opts;
+  int dof = 0;
+  float* q[2] = {nullptr, nullptr};
+  int* parent[2] = {nullptr, nullptr};
+  float* edge[2] = {nullptr, nullptr};
+  float* scratch = nullptr;
+  int* ctl = nullptr;
+  int* items = nullptr;       // device list for gather_path_kernel
+  float* path_buf = nullptr;  // device path buffer
+  int* host_ctl = nullptr;    // pinned mirror of the control block
+  size_t path_cap = 0;        // points that fit in path_buf / items
+  float* cfg = nullptr;       // [2][dof] start/goal scratch for checks
+  float* cfg_out = nullptr;
+  int* cfg_status = nullptr;
+  uint8_t* cfg_col = nullptr;
+  float* cfg_sd = nullptr;
+};
+
+namespace {
+
+uint64_t splitmix64(uint64_t& state) {
+  uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+void free_planner(cp_planner* p) {
+  if (!p) return;
+  for (int t = 0; t < 2; ++t) {
+    if (p->q[t]) (void)hipFree(p->q[t]);
+    if (p->parent[t]) (void)hipFree(p->parent[t]);
+    if (p->edge[t]) (void)hipFree(p->edge[t]);
+  }
+  if (p->scratch) (void)hipFree(p->scratch);
+  if (p->ctl) (void)hipFree(p->ctl);
+  if (p->items) (void)hipFree(p->items);
+  if (p->path_buf) (void)hipFree(p->path_buf);
+  if (p->host_ctl) (void)hipHostFree(p->host_ctl);
+  if (p->cfg) (void)hipFree(p->cfg);
+  if (p->cfg_out) (void)hipFree(p->cfg_out);
+  if (p->cfg_status) (void)hipFree(p->cfg_status);
+  if (p->cfg_col) (void)hipFree(p->cfg_col);
+  if (p->cfg_sd) (void)hipFree(p->cfg_sd);
+  delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+void cp_plan_opts_default(cp_plan_opts* o) {
+  if (!o) return;
+  cp_proj_params_default(&o->proj);
+  o->n_groups = 256;
+  o->max_rounds = 2000;
+  o->capacity = 16384;
+  o->max_connect = 64;
+  o->poll_every = 1;
+}
+
+int cp_planner_create(const cp_robot* robot, const cp_plan_opts* opts, cp_planner** out) {
+  try {
+    if (!robot || !out) return api_fail(CP_E_ARG, "cp_planner_create: NULL argument");
+    *out = nullptr;
+    cp_plan_opts o;
+    cp_plan_opts_default(&o);
+    if (opts) o = *opts;
+    cp_proj_params p;
+    int rc = api_params(&o.proj, &p);
+    if (rc != CP_OK) return rc;
+    o.proj = p;
+    if (o.n_groups < 2 || o.n_groups > 65536) return api_fail(CP_E_ARG, "n_groups %d not in 2..65536", o.n_groups);
+    if (o.capacity < 2 || o.capacity > (1 << 24)) return api_fail(CP_E_ARG, "capacity %d not in 2..2^24", o.capacity);
+    if (o.max_rounds < 1 || o.max_connect < 0 || o.poll_every < 1)
+      return api_fail(CP_E_ARG, "max_rounds, max_connect or poll_every out of range");
+    if (!dof_supported(robot->host.dof))
+      return api_fail(CP_E_UNSUPPORTED, "planning kernels are built for dof 2, 3, 6, 7, 9, 14 (got %d)", robot->host.dof);
+    cp_planner* pl = new (std::nothrow) cp_planner;
+    if (!pl) return api_fail(CP_E_ARG, "out of host memory");
+    pl->robot = robot;
+    pl->opts = o;
+    const int n = robot->host.dof, W = o.proj.W;
+    pl->dof = n;
+    const size_t cap = (size_t)o.capacity;
+    // path: at most capacity nodes per tree, W-1 points per edge, + 2
+    pl->path_cap = 2 * cap * (size_t)(W - 1) + 2;
+    hipError_t e = hipSuccess;
+    for (int t = 0; t < 2 && e == hipSuccess; ++t) {
+      e = hipMalloc((void**)&pl->q[t], sizeof(float) * n * cap);
+      if (e == hipSuccess) e = hipMalloc((void**)&pl->parent[t], sizeof(int) * cap);
+      if (e == hipSuccess) e = hipMalloc((void**)&pl->edge[t], sizeof(float) * cap * W * n);
+    }
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->scratch, sizeof(float) * (size_t)o.n_groups * W * n);
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->ctl, sizeof(int) * kCtlInts);
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->items, sizeof(int) * 4 * 2 * cap);
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->path_buf, sizeof(float) * pl->path_cap * n);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&pl->host_ctl, sizeof(int) * kCtlInts, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->cfg, sizeof(float) * 2 * n);
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->cfg_out, sizeof(float) * 2 * n);
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->cfg_status, sizeof(int) * 2);
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->cfg_col, 2);
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->cfg_sd, sizeof(float) * 2);
+    if (e != hipSuccess) {
+      free_planner(pl);
+      return api_hip_fail(e, "cp_planner_create");
+    }
+    *out = pl;
+    return CP_OK;
+  } catch (...) {
+    return api_fail(CP_E_ARG, "cp_planner_create: unexpected exception");
+  }
+}
+
+void cp_planner_destroy(cp_planner* p) { free_planner(p); }
+
+int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
+            const double* start, const double* goal, uint64_t seed, cp_path* out,
+            cp_plan_stats* stats, void* stream_v) {
+  try {
+    if (!pl || !env || !start || !goal || !out) return api_fail(CP_E_ARG, "cp_plan: NULL argument");
+    if (out->capacity > 0 && !out->q) return api_fail(CP_E_ARG, "cp_plan: NULL path buffer");
+    hipStream_t st = (hipStream_t)stream_v;
+    const cp_robot* robot = pl->robot;
+    const int n = pl->dof, W = pl->opts.proj.W;
+    const cp_plan_opts& o = pl->opts;
+    out->len = 0;
+    out->dof = n;
+    if (stats) std::memset(stats, 0, sizeof *stats);
+    ConDev con;
+    int rc = api_constraint(constraint, robot, &con);
+    if (rc != CP_OK) return rc;
+    const cp_proj_params& pp = o.proj;
+    ProjDev prm;
+    prm.W = W;
+    prm.max_iters = pp.max_iters;
+    prm.tau = (float)pp.tau;
+    prm.tau_sm = (float)pp.tau_sm;
+    prm.tau_task = (float)pp.tau_task;
+    prm.alpha = (float)pp.alpha;
+    prm.lambda2 = (float)(pp.lambda * pp.lambda);
+
+    // endpoints: inside the limits (host), on the manifold and collision-free (device)
+    for (int e = 0; e < 2; ++e) {
+      const double* c = e == 0 ? start : goal;
+      for (int j = 0; j < n; ++j)
+        if (!(c[j] >= robot->host.lo[j] && c[j] <= robot->host.hi[j]))
+          return api_fail(e == 0 ? CP_E_START : CP_E_GOAL, "%s outside the joint limits", e == 0 ? "start" : "goal");
+    }
+    std::vector<float> ends(2 * n);
+    for (int j = 0; j < n; ++j) {
+      ends[j] = (float)start[j];
+      ends[n + j] = (float)goal[j];
+    }
+    hipError_t he = hipMemcpyAsync(pl->cfg, ends.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice, st);
+    if (he != hipSuccess) return api_hip_fail(he, "cp_plan");
+    bool sup = false;
+    he = launch_project_configs(n, robot->dev, con, 2, pl->cfg, pl->cfg_out, pl->cfg_status,
+                                (float)pp.tau_task, 0, 1.0f, 0.0f, st, &sup);
+    if (he == hipSuccess) he = launch_fk_cc(robot->dev, robot->spheres, env->view, 2, pl->cfg, pl->cfg_col, pl->cfg_sd, false, 4, st);
+    int ok_h[2];
+    float sd_h[2];
+    if (he == hipSuccess) he = hipMemcpyAsync(ok_h, pl->cfg_status, sizeof ok_h, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(sd_h, pl->cfg_sd, sizeof sd_h, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return api_hip_fail(he, "cp_plan endpoint checks");
+    if (!sup) return api_fail(CP_E_UNSUPPORTED, "no kernel for dof %d with constraint kind %d", n, con.kind);
+    if (!ok_h[0]) return api_fail(CP_E_START, "start is off the constraint manifold");
+    if (!ok_h[1]) return api_fail(CP_E_GOAL, "goal is off the constraint manifold");
+    if (!(sd_h[0] > 0.0f)) return api_fail(CP_E_START, "start is in collision");
+    if (!(sd_h[1] > 0.0f)) return api_fail(CP_E_GOAL, "goal is in collision");
+
+    const double tol = pp.tau + pp.tau_sm;
+    double dsg = 0.0;
+    for (int j = 0; j < n; ++j) dsg += (start[j] - goal[j]) * (start[j] - goal[j]);
+    if (std::sqrt(dsg) < tol) {   // already connected
+      out->len = 2;
+      if (out->capacity < 2) return api_fail(CP_E_CAPACITY, "path needs 2 rows");
+      std::memcpy(out->q, start, sizeof(double) * n);
+      std::memcpy(out->q + n, goal, sizeof(double) * n);
+      return CP_OK;
+    }
+
+    PlanDev pd;
+    std::memset(&pd, 0, sizeof pd);
+    for (int t = 0; t < 2; ++t) {
+      pd.q[t] = pl->q[t];
+      pd.parent[t] = pl->parent[t];
+      pd.edge[t] = pl->edge[t];
+    }
+    pd.scratch = pl->scratch;
+    pd.ctl = pl->ctl;
+    pd.cap = o.capacity;
+    pd.n_groups = o.n_groups;
+    pd.max_connect = o.max_connect;
+    pd.step = (float)((W - 1) * pp.tau);
+    he = hipMemcpyAsync(pl->cfg, ends.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) {
+      plan_init_kernel<<<1, 64, 0, st>>>(pd, pl->cfg, n);
+      he = hipGetLastError();
+    }
+    if (he != hipSuccess) return api_hip_fail(he, "cp_plan init");
+    pd.connect2 = (float)(tol * tol);
+    uint64_t state = seed;
+    for (int j = 0; j < kMaxDof; ++j)
+      pd.shift[j] = (float)((double)(splitmix64(state) >> 11) * (1.0 / 9007199254740992.0));
+    const unsigned nb = (unsigned)((o.n_groups * 64 + kPlanBlock - 1) / kPlanBlock);
+
+    int rounds = 0;
+    bool done = false;
+    while (rounds < o.max_rounds && !done) {
+      pd.sample_base = (unsigned)rounds * (unsigned)o.n_groups;
+      if (!launch_round(n, con.kind, pp.sphere_batch, nb, st, robot->dev, robot->spheres,
+                        env->view, con, prm, pd))
+        return api_fail(CP_E_UNSUPPORTED, "no planning kernel for dof %d, constraint kind %d", n, con.kind);
+      publish_kernel<<<1, 1, 0, st>>>(pl->ctl, o.capacity);
+      ++rounds;
+      if (rounds % o.poll_every == 0 || rounds == o.max_rounds) {
+        he = hipMemcpyAsync(pl->host_ctl, pl->ctl, sizeof(int) * kCtlInts, hipMemcpyDeviceToHost, st);
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+        if (he != hipSuccess) return api_hip_fail(he, "cp_plan round");
+        done = pl->host_ctl[kCtlDone] != 0;
+        if (!done && pl->host_ctl[kCtlOverflow]) break;
+      }
+    }
+    he = hipGetLastError();
+    if (he != hipSuccess) return api_hip_fail(he, "cp_plan launch");
+    const int* hc = pl->host_ctl;
+    if (stats) {
+      stats->rounds = rounds;
+      stats->nodes[0] = std::min(hc[kCtlCount + 0], o.capacity);
+      stats->nodes[1] = std::min(hc[kCtlCount + 1], o.capacity);
+      stats->overflow = hc[kCtlOverflow];
+    }
+    if (!done) {
+      if (hc[kCtlOverflow]) return api_fail(CP_E_CAPACITY, "a tree reached its capacity of %d nodes", o.capacity);
+      return CP_NO_SOLUTION;
+    }
+
+    // path: tree-0 chain root -> n0, bridge to n1, tree-1 chain n1 -> root
+    const int X = hc[kCtlConn + 0], a = hc[kCtlConn + 1], b = hc[kCtlConn + 2];
+    const int n0 = X == 0 ? a : b, n1 = X == 0 ? b : a;
+    std::vector<int> par[2];
+    for (int t = 0; t < 2; ++t) {
+      const int cnt = std::min(hc[kCtlCount + t], o.capacity);
+      par[t].resize(cnt);
+      he = hipMemcpy(par[t].data(), pl->parent[t], sizeof(int) * cnt, hipMemcpyDeviceToHost);
+      if (he != hipSuccess) return api_hip_fail(he, "cp_plan path");
+    }
+    std::vector<int> chain0, chain1;
+    for (int v = n0; v > 0; v = par[0][v]) chain0.push_back(v);
+    std::reverse(chain0.begin(), chain0.end());
+    for (int v = n1; v > 0; v = par[1][v]) chain1.push_back(v);
+    const size_t len = 1 + chain0.size() * (W - 1) + 1 + chain1.size() * (W - 1);
+    out->len = (int32_t)len;
+    if ((size_t)out->capacity < len) return api_fail(CP_E_CAPACITY, "path needs %zu rows", len);
+    std::vector<int> items;
+    int off = 1;
+    for (int v : chain0) {
+      items.insert(items.end(), {0, v, 0, off});
+      off += W - 1;
+    }
+    items.insert(items.end(), {1, n1, 2, off});
+    off += 1;
+    for (int v : chain1) {
+      items.insert(items.end(), {1, v, 1, off});
+      off += W - 1;
+    }
+    const int n_items = (int)items.size() / 4;
+    std::vector<float> pts(len * n);
+    he = hipMemcpyAsync(pl->items, items.data(), sizeof(int) * items.size(), hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) {
+      gather_path_kernel<<<n_items, 64, 0, st>>>(pd, pl->items, n_items, W, n, pl->path_buf);
+      he = hipGetLastError();
+    }
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(pts.data(), pl->path_buf, sizeof(float) * len * n, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return api_hip_fail(he, "cp_plan path");
+    for (size_t i = 1; i + 1 < len; ++i)
+      for (int j = 0; j < n; ++j) out->q[i * n + j] = (double)pts[i * n + j];
+    // the end points are the caller's own values
+    std::memcpy(out->q, start, sizeof(double) * n);
+    std::memcpy(out->q + (len - 1) * n, goal, sizeof(double) * n);
+    return CP_OK;
+  } catch (...) {
+    return api_fail(CP_E_ARG, "cp_plan: unexpected exception");
+  }
+}
+
+int plan(const cp_robot* robot, const cp_env* env, const cp_constraint* constraint,
+         const double* start, const double* goal, uint64_t seed, const cp_plan_opts* opts,
+         cp_path* out) {
+  cp_planner* pl = nullptr;
+  int rc = cp_planner_create(robot, opts, &pl);
+  if (rc != CP_OK) return rc;
+  rc = cp_plan(pl, env, constraint, start, goal, seed, out, nullptr, nullptr);
+  (void)hipStreamSynchronize(nullptr);
+  cp_planner_destroy(pl);
+  return rc;
+}
+
+}  // extern "C"

@@ -230,4 +230,56 @@ __device__ __forceinline__ void task_step(const RobotDev* __restrict__ rob, cons
   }
 }
 
+// Algorithm 1 on the W-lane segment this lane belongs to (Jacobi form).
+// q: this lane's waypoint xi[k]; in: the straight-line value, out: the
+// projected value (success) or the last iterate.  Each active lane computes its
+// update from the snapshot (its own xi[k] and xi[k-1] from a shuffle before
+// anyone writes); validity is gathered with one ballot; prog moves to the end
+// of the contiguous valid run after it; only lanes past the new prog take
+// their new value.  `idle` lanes (outside any motion) count as valid so that
+// their segment finishes at once.  Returns true on success; iters = iterations
+// used (max_iters on failure); updates += waypoint updates computed.
+template <int NDOF, int KIND>
+__device__ __forceinline__ bool project_segment(const RobotDev* __restrict__ rob, const ConDev& con,
+                                                const ProjDev& prm, int k, int seg,
+                                                uint64_t wmask, uint64_t segmask, bool idle,
+                                                float (&q)[NDOF], int& iters,
+                                                unsigned long long& updates) {
+  const int W = prm.W;
+  int prog = 0;
+  for (int it = 1; it <= prm.max_iters; ++it) {
+    updates += (unsigned long long)(W - 1 - prog);
+    float qprev[NDOF];
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) qprev[j] = __shfl_up(q[j], 1, W);
+    float g[NDOF], einf;
+    task_step<NDOF, KIND>(rob, con, q, prm.lambda2, g, einf);
+    float d2 = 0.0f, dl[NDOF];
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) {
+      dl[j] = q[j] - qprev[j];
+      d2 += dl[j] * dl[j];
+    }
+    const float esm = sqrtf(d2) - prm.tau;
+    float qn[NDOF];
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j)
+      qn[j] = fminf(fmaxf(q[j] - prm.alpha * (g[j] + dl[j] * esm), rob->lo[j]), rob->hi[j]);
+    const bool valid = idle || (k <= prog) || ((einf < prm.tau_task) && (esm < prm.tau_sm));
+    const uint64_t bits = (__ballot(valid) & segmask) >> seg;
+    const uint64_t invalid = ~bits & wmask;      // bits 0..prog are set
+    prog = invalid ? (__ffsll((unsigned long long)invalid) - 2) : W - 1;
+    if (prog == W - 1) {
+      iters = it;
+      return true;
+    }
+    if (k > prog) {
+#pragma unroll
+      for (int j = 0; j < NDOF; ++j) q[j] = qn[j];
+    }
+  }
+  iters = prm.max_iters;
+  return false;
+}
+
 }  // namespace cprrtc
