@@ -68,7 +68,100 @@ def parse():
     ap.add_argument("--sphere-batch", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
+    ap.add_argument("--plan-queries", type=int, default=100,
+                    help="planning queries per scene for the p50 plan time (0 = skip)")
     return ap.parse_args()
+
+
+def gpu_query(G, I, torch, w, seed):
+    """Start and goal for one planning query, prepared with the library:
+    random configurations projected onto the manifold, collision-free by
+    1e-3 m, the first pair at least 1 rad apart."""
+    rd = w["robot"]
+    robot, env, con = G.Robot(rd), G.Env(w["env"]), G.constraint(w["constraint"])
+    dev = torch.device("cuda:0")
+    raw = torch.from_numpy(I.random_configs(rd, 256, seed + 5).astype(np.float32)).to(dev)
+    proj = torch.empty_like(raw)
+    ok = torch.empty(256, dtype=torch.int32, device=dev)
+    G.project_configs(robot, con, raw, proj, ok, tol=1e-5, max_iters=100)
+    col = torch.empty(256, dtype=torch.uint8, device=dev)
+    sd = torch.empty(256, dtype=torch.float32, device=dev)
+    G.fk_cc_batch(robot, env, proj, col, sd)
+    good = proj[(ok == 1) & (sd > 1e-3)].cpu().numpy().astype(np.float64)
+    for i in range(len(good)):
+        for j in range(i + 1, len(good)):
+            if np.linalg.norm(good[i] - good[j]) >= 1.0:
+                return robot, env, con, good[i], good[j]
+    return robot, env, con, None, None
+
+
+def plan_bench(G, I, torch, name, seeds, tau_task):
+    """p50 wall time of cp_plan over seeded queries (planner creation and
+    query preparation excluded), success rate."""
+    times, ok, rounds = [], 0, []
+    n = 0
+    for seed in seeds:
+        w = I.workload(name, seed)
+        robot, env, con, start, goal = gpu_query(G, I, torch, w, seed)
+        if start is None:
+            continue
+        pl = G.Planner(robot, G.plan_opts(n_groups=256, max_rounds=500, capacity=65536,
+                                          tau_task=tau_task))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            rc, path, st = pl.plan(env, con, start, goal, seed)
+        except G.CprrtcError as e:      # a tree filled up: the query is unsolved
+            if e.code != G.CP_E_CAPACITY:
+                raise
+            rc, st = e.code, dict(rounds=500)
+        times.append((time.perf_counter() - t0) * 1e3)
+        n += 1
+        ok += rc == G.CP_OK
+        rounds.append(st["rounds"])
+    return dict(queries=n, p50_ms=float(np.median(times)), p90_ms=float(np.percentile(times, 90)),
+                success=ok / max(n, 1), mean_rounds=float(np.mean(rounds)))
+
+
+def cpu_plan_baseline(I, name, seeds, tau_task, target_s):
+    """The FP64 oracle planner (sequential extensions) on a bounded sample of
+    the same queries, each with its own oracle-prepared start and goal."""
+    import oracle as O
+    times, ok, n = [], 0, 0
+    spent = 0.0
+    for seed in seeds:
+        if spent > target_s:
+            break
+        w = I.workload(name, seed)
+        ro, eo, co = O.Robot(w["robot"]), O.Env(w["env"]), O.Constraint(w["constraint"])
+        good = []
+        for q in I.random_configs(w["robot"], 256, seed + 5):
+            okp, qp, _ = O.project_config(ro, co, q, tol=1e-5, max_iters=100)
+            if okp and O.config_min_sd(ro, eo, qp) > 1e-3:
+                good.append(qp)
+        pair = None
+        for i in range(len(good)):
+            for j in range(i + 1, len(good)):
+                if np.linalg.norm(good[i] - good[j]) >= 1.0:
+                    pair = (good[i], good[j])
+                    break
+            if pair:
+                break
+        if pair is None:
+            continue
+        prm = O.params(W=W, tau=TAU, tau_task=tau_task)
+        t0 = time.perf_counter()
+        st, path, nodes = O.plan(ro, eo, co, prm, pair[0], pair[1], seed, max_samples=400)
+        dt = time.perf_counter() - t0
+        spent += dt
+        times.append(dt * 1e3)
+        ok += st == 1
+        n += 1
+    return dict(p50_ms=float(np.median(times)) if times else None, success=ok / max(n, 1),
+                queries=n, cores=1, kind="oracle",
+                sample=f"{n} queries of the same scenes, sequential extensions, at most 400 "
+                       f"samples each, "
+                       f"{spent:.1f} s of FP64 oracle time")
 
 
 def gpu_starts(G, I, torch, rd, robot, env, con, n, seed):
@@ -239,6 +332,15 @@ def main():
         "motions": {"valid": int((st == 0).sum()), "proj_fail": int((st == 1).sum()),
                     "collision": int((st == 2).sum()), "mean_iters": float(it.mean())},
     }
+    if args.plan_queries > 0:
+        result["plan"] = {}
+        for name, base in (("plain", 1000), ("cluttered", 2000)):
+            seeds = range(base, base + args.plan_queries)
+            tt = I.workload(name, base)["tau_task"]
+            entry = plan_bench(G, I, torch, name, seeds, tt)
+            if args.cpu_seconds > 0:
+                entry["cpu_baseline"] = cpu_plan_baseline(I, name, seeds, tt, args.cpu_seconds / 2)
+            result["plan"][name] = entry
     if args.cpu_seconds > 0:
         result["cpu_baseline"] = cpu_baseline(I, w, args.cpu_seconds)
     print(json.dumps(result), flush=True)
