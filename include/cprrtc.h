@@ -205,6 +205,47 @@ int project_configs(const cp_robot* robot, const cp_constraint* constraint, int3
                     const float* d_q_in, float* d_q_out, int32_t* d_status, double tol,
                     int32_t max_iters, double alpha, double lambda, void* stream);
 
+/* ------------------------------------------------------------ learned warm start */
+
+/* A multilayer perceptron n_in -> hidden (SiLU) x n_hidden -> n_out with BF16
+ * weights and FP32 accumulation on the matrix cores, FP32 master weights and
+ * Adam state; all of it in device memory owned by the handle.  Parameters
+ * are one FP32 vector: for each layer, W [out][in] row-major, then b [out].
+ * Inputs x [M][n_in], outputs / targets [M][n_out], all float32 device
+ * pointers; calls are asynchronous on `stream`; a handle serves one stream at
+ * a time (it keeps activation workspace). */
+typedef struct cp_mlp cp_mlp;
+int cp_mlp_create(int32_t n_in, int32_t hidden, int32_t n_hidden, int32_t n_out, uint64_t seed,
+                  cp_mlp** out);
+void cp_mlp_destroy(cp_mlp* mlp);
+int64_t cp_mlp_num_params(const cp_mlp* mlp);
+int cp_mlp_get_params(const cp_mlp* mlp, float* d_params, void* stream);
+int cp_mlp_set_params(cp_mlp* mlp, const float* d_params, void* stream);
+int cp_mlp_forward(cp_mlp* mlp, int64_t M, const float* d_x, float* d_y, void* stream);
+/* Gradients of the mean squared error over the n_out outputs (and the loss)
+ * at the current parameters; d_grad [num_params] and d_loss [1] nullable. */
+int cp_mlp_gradients(cp_mlp* mlp, int64_t M, const float* d_x, const float* d_t, float* d_grad,
+                     float* d_loss, void* stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error. */
+int cp_mlp_train_step(cp_mlp* mlp, int64_t M, const float* d_x, const float* d_t, float lr,
+                      float* d_loss, void* stream);
+
+/* project_motions with a learned warm start: every waypoint k >= 1 starts at
+ * clamp(straight line + net(features)), features = (waypoint / joint range,
+ * constraint parameters: the locked pose targets (6), or p* and R* (12) for a
+ * relative pose); the network needs n_in = dof + 6 (or + 12), n_out = dof.
+ * ParallelProject then runs to the same tolerance; motions whose projection
+ * fails are projected again from the straight line (the plain projector is
+ * the fallback and the judge).  d_iters receives the iterations of both
+ * passes.  flags: CP_WARM_NO_FALLBACK skips the fallback (to measure the warm
+ * pass alone).  Otherwise as project_motions. */
+enum { CP_WARM_NO_FALLBACK = 4 };
+int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
+                         const cp_proj_params* params, cp_mlp* mlp, int32_t n_motions,
+                         const float* d_q_from, const float* d_q_to, float* d_xi,
+                         int32_t* d_status, int32_t* d_iters, uint64_t* d_work, int32_t flags,
+                         void* stream);
+
 /* ------------------------------------------------------------ planning */
 
 /* Constrained bidirectional RRT-Connect (Section III): two trees rooted at

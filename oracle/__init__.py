@@ -271,3 +271,28 @@ def path_report(robot: Robot, env: Env, con: Constraint, path):
     lib().or_path_report(C.byref(robot.s), C.byref(env.s), C.byref(con.s), _ptr(path),
                          C.c_int32(len(path)), _ptr(out))
     return dict(task_error=out[0], spacing=out[1], min_sd=out[2], inside=bool(out[3]))
+
+
+def mlp_forward(dims, params, x):
+    dims = np.ascontiguousarray(dims, np.int32)
+    params, x = _f64(params), _f64(x)
+    M = len(x)
+    y = np.zeros((M, dims[-1]))
+    lib().or_mlp_forward(C.c_int32(len(dims) - 1), _ptr(dims, _ip), _ptr(params), C.c_int32(M),
+                         _ptr(x), _ptr(y))
+    return y
+
+
+def mlp_gradients(dims, params, x, t):
+    dims = np.ascontiguousarray(dims, np.int32)
+    params, x, t = _f64(params), _f64(x), _f64(t)
+    grad = np.zeros_like(params)
+    L = lib()
+    L.or_mlp_gradients.restype = C.c_double
+    loss = L.or_mlp_gradients(C.c_int32(len(dims) - 1), _ptr(dims, _ip), _ptr(params),
+                              C.c_int32(len(x)), _ptr(x), _ptr(t), _ptr(grad))
+    return loss, grad
+
+
+def mlp_num_params(dims):
+    return int(sum(dims[i + 1] * dims[i] + dims[i + 1] for i in range(len(dims) - 1)))

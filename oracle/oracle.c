@@ -797,3 +797,99 @@ void or_path_report(const or_robot* r, const or_env* env, const or_constraint* c
   }
   out[0] = worst_e; out[1] = worst_sp; out[2] = msd; out[3] = inside;
 }
+
+/* ---------------------------------------------------------------- MLP */
+/* z_l = W_l h_{l-1} + b_l, h_l = silu(z_l) for hidden layers, y = z_L;
+ * silu(z) = z / (1 + exp(-z)); loss = mean over all M * n_out outputs of
+ * (y - t)^2; gradients by the chain rule, layer by layer. */
+
+static double silu_d(double z) { return z / (1.0 + exp(-z)); }
+static double silu_grad_d(double z) {
+  const double s = 1.0 / (1.0 + exp(-z));
+  return s * (1.0 + z * (1.0 - s));
+}
+
+static size_t mlp_offset_w(int32_t l, const int32_t* dims) {
+  size_t off = 0;
+  for (int32_t i = 0; i < l; ++i) off += (size_t)dims[i + 1] * dims[i] + dims[i + 1];
+  return off;
+}
+
+/* One sample through the network; z[l] and h[l] stored for the backward pass
+ * (h[0] = the input).  Buffers are [n_layers + 1][maxw]. */
+static void mlp_sample_forward(int32_t L, const int32_t* dims, const double* params,
+                               const double* x, double* z, double* h, int maxw) {
+  for (int j = 0; j < dims[0]; ++j) h[j] = x[j];
+  for (int32_t l = 0; l < L; ++l) {
+    const double* W = params + mlp_offset_w(l, dims);
+    const double* b = W + (size_t)dims[l + 1] * dims[l];
+    const double* hin = h + (size_t)l * maxw;
+    double* zo = z + (size_t)(l + 1) * maxw;
+    double* ho = h + (size_t)(l + 1) * maxw;
+    for (int o = 0; o < dims[l + 1]; ++o) {
+      double s = b[o];
+      for (int i = 0; i < dims[l]; ++i) s += W[(size_t)o * dims[l] + i] * hin[i];
+      zo[o] = s;
+      ho[o] = (l + 1 < L) ? silu_d(s) : s;
+    }
+  }
+}
+
+void or_mlp_forward(int32_t n_layers, const int32_t* dims, const double* params, int32_t M,
+                    const double* x, double* y) {
+  int maxw = 0;
+  for (int32_t l = 0; l <= n_layers; ++l) maxw = dims[l] > maxw ? dims[l] : maxw;
+  double* z = (double*)malloc(sizeof(double) * (size_t)(n_layers + 1) * maxw);
+  double* h = (double*)malloc(sizeof(double) * (size_t)(n_layers + 1) * maxw);
+  for (int32_t m = 0; m < M; ++m) {
+    mlp_sample_forward(n_layers, dims, params, x + (size_t)m * dims[0], z, h, maxw);
+    memcpy(y + (size_t)m * dims[n_layers], h + (size_t)n_layers * maxw, sizeof(double) * dims[n_layers]);
+  }
+  free(z);
+  free(h);
+}
+
+double or_mlp_gradients(int32_t n_layers, const int32_t* dims, const double* params, int32_t M,
+                        const double* x, const double* t, double* grad) {
+  const int32_t L = n_layers, nout = dims[L];
+  int maxw = 0;
+  for (int32_t l = 0; l <= L; ++l) maxw = dims[l] > maxw ? dims[l] : maxw;
+  const size_t np = mlp_offset_w(L, dims);
+  memset(grad, 0, sizeof(double) * np);
+  double* z = (double*)malloc(sizeof(double) * (size_t)(L + 1) * maxw);
+  double* h = (double*)malloc(sizeof(double) * (size_t)(L + 1) * maxw);
+  double* d = (double*)malloc(sizeof(double) * maxw);      /* dLoss/dz of the current layer */
+  double* dn = (double*)malloc(sizeof(double) * maxw);
+  double loss = 0.0;
+  const double scale = 1.0 / ((double)M * nout);
+  for (int32_t m = 0; m < M; ++m) {
+    mlp_sample_forward(L, dims, params, x + (size_t)m * dims[0], z, h, maxw);
+    for (int o = 0; o < nout; ++o) {
+      const double e = h[(size_t)L * maxw + o] - t[(size_t)m * nout + o];
+      loss += e * e * scale;
+      d[o] = 2.0 * e * scale;
+    }
+    for (int32_t l = L - 1; l >= 0; --l) {
+      const double* W = params + mlp_offset_w(l, dims);
+      double* gW = grad + mlp_offset_w(l, dims);
+      double* gb = gW + (size_t)dims[l + 1] * dims[l];
+      const double* hin = h + (size_t)l * maxw;
+      for (int o = 0; o < dims[l + 1]; ++o) {
+        gb[o] += d[o];
+        for (int i = 0; i < dims[l]; ++i) gW[(size_t)o * dims[l] + i] += d[o] * hin[i];
+      }
+      if (l == 0) break;
+      for (int i = 0; i < dims[l]; ++i) {
+        double s = 0.0;
+        for (int o = 0; o < dims[l + 1]; ++o) s += W[(size_t)o * dims[l] + i] * d[o];
+        dn[i] = s * silu_grad_d(z[(size_t)l * maxw + i]);
+      }
+      memcpy(d, dn, sizeof(double) * dims[l]);
+    }
+  }
+  free(z);
+  free(h);
+  free(d);
+  free(dn);
+  return loss;
+}

@@ -115,6 +115,16 @@ int32_t or_plan(const or_robot* r, const or_env* env, const or_constraint* c, co
 void or_path_report(const or_robot* r, const or_env* env, const or_constraint* c,
                     const double* path, int32_t len, double* out);
 
+/* Multilayer perceptron with SiLU hidden activations (the learned warm start).
+ * dims[0..n_layers]: widths; params: per layer W [dims[l+1]][dims[l]]
+ * row-major then b [dims[l+1]].  x [M][dims[0]], y/t [M][dims[n_layers]].
+ * or_mlp_gradients returns the mean squared error over all outputs and
+ * writes its gradient (same layout as params). */
+void or_mlp_forward(int32_t n_layers, const int32_t* dims, const double* params, int32_t M,
+                    const double* x, double* y);
+double or_mlp_gradients(int32_t n_layers, const int32_t* dims, const double* params, int32_t M,
+                        const double* x, const double* t, double* grad);
+
 #ifdef __cplusplus
 }
 #endif

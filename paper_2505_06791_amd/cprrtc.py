@@ -21,6 +21,7 @@ CP_E_RTC, CP_E_HIP, CP_E_UNSUPPORTED = -5, -6, -7
 MOTION_VALID, MOTION_PROJ_FAIL, MOTION_COLLISION = 0, 1, 2
 NO_EARLY_EXIT = 1
 NO_CULL = 2
+WARM_NO_FALLBACK = 4
 WORK_SLOTS = 8
 
 _dp = C.POINTER(C.c_double)
@@ -101,6 +102,18 @@ def lib():
                               C.POINTER(Path), C.POINTER(PlanStats), vp]
         L.plan.argtypes = [vp, vp, C.POINTER(Constraint), _dp, _dp, C.c_uint64,
                            C.POINTER(PlanOpts), C.POINTER(Path)]
+        L.cp_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+                                    C.POINTER(vp)]
+        L.cp_mlp_destroy.argtypes = [vp]
+        L.cp_mlp_num_params.argtypes = [vp]
+        L.cp_mlp_num_params.restype = C.c_int64
+        L.cp_mlp_get_params.argtypes = [vp, vp, vp]
+        L.cp_mlp_set_params.argtypes = [vp, vp, vp]
+        L.cp_mlp_forward.argtypes = [vp, C.c_int64, vp, vp, vp]
+        L.cp_mlp_gradients.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp]
+        L.cp_mlp_train_step.argtypes = [vp, C.c_int64, vp, vp, C.c_float, vp, vp]
+        L.project_motions_warm.argtypes = [vp, C.POINTER(Constraint), C.POINTER(ProjParams), vp,
+                                           C.c_int32, vp, vp, vp, vp, vp, vp, C.c_int32, vp]
         L.project_configs.argtypes = [vp, C.POINTER(Constraint), C.c_int32, vp, vp, vp,
                                       C.c_double, C.c_int32, C.c_double, C.c_double, vp]
         _lib = L
@@ -306,3 +319,72 @@ class Planner:
         if getattr(self, "handle", None) and _lib is not None:
             _lib.cp_planner_destroy(self.handle)
             self.handle = None
+
+
+# ------------------------------------------------------------------ learned warm start
+
+class MLP:
+    """cp_mlp handle: n_in -> hidden (SiLU) x n_hidden -> n_out, BF16 weights on
+    the matrix cores, FP32 masters and Adam state on the device."""
+
+    def __init__(self, n_in: int, hidden: int, n_hidden: int, n_out: int, seed: int = 0):
+        h = C.c_void_p()
+        _check(lib().cp_mlp_create(n_in, hidden, n_hidden, n_out, C.c_uint64(seed), C.byref(h)))
+        self.handle = h
+        self.n_in, self.hidden, self.n_hidden, self.n_out = n_in, hidden, n_hidden, n_out
+        self.n_params = int(lib().cp_mlp_num_params(h))
+
+    @property
+    def dims(self):
+        return [self.n_in] + [self.hidden] * self.n_hidden + [self.n_out]
+
+    def get_params(self):
+        import torch
+        p = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(lib().cp_mlp_get_params(self.handle, _dev(p, torch.float32), _stream()))
+        return p
+
+    def set_params(self, p):
+        import torch
+        _check(lib().cp_mlp_set_params(self.handle, _dev(p, torch.float32), _stream()))
+
+    def forward(self, x):
+        import torch
+        y = torch.empty((x.shape[0], self.n_out), dtype=torch.float32, device=x.device)
+        _check(lib().cp_mlp_forward(self.handle, x.shape[0], _dev(x, torch.float32),
+                                    _dev(y, torch.float32), _stream()))
+        return y
+
+    def gradients(self, x, t):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(lib().cp_mlp_gradients(self.handle, x.shape[0], _dev(x, torch.float32),
+                                      _dev(t, torch.float32), _dev(g, torch.float32),
+                                      _dev(loss, torch.float32), _stream()))
+        return g, loss
+
+    def train_step(self, x, t, lr: float, loss=None):
+        import torch
+        _check(lib().cp_mlp_train_step(self.handle, x.shape[0], _dev(x, torch.float32),
+                                       _dev(t, torch.float32), C.c_float(lr),
+                                       _dev(loss, torch.float32) if loss is not None else None,
+                                       _stream()))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.cp_mlp_destroy(self.handle)
+            self.handle = None
+
+
+def project_motions_warm(robot: Robot, con: Constraint, prm: ProjParams, mlp: MLP, q_from, q_to,
+                         xi, status, iters=None, work=None, flags: int = 0, stream=None):
+    """project_motions with the learned warm start and the plain fallback
+    (flags=WARM_NO_FALLBACK: the warm pass alone)."""
+    import torch
+    m = q_from.shape[0]
+    _check(lib().project_motions_warm(
+        robot.handle, C.byref(con), C.byref(prm), mlp.handle, m, _dev(q_from, torch.float32),
+        _dev(q_to, torch.float32), _dev(xi, torch.float32), _dev(status, torch.int32),
+        _dev(iters, torch.int32) if iters is not None else None,
+        _dev(work, torch.int64) if work is not None else None, flags, _stream(stream)))

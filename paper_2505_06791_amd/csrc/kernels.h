@@ -18,6 +18,12 @@ hipError_t launch_project(int dof, const RobotDev* rob, const ConDev& con, const
                           int* status, int* iters, unsigned long long* work, hipStream_t stream,
                           bool* supported);
 
+hipError_t launch_project_mode(int dof, int mode, const RobotDev* rob, const ConDev& con,
+                               const ProjDev& prm, int n_motions, const float* q_from,
+                               const float* q_to, const float* delta, float* xi, int* status,
+                               int* iters, unsigned long long* work, hipStream_t stream,
+                               bool* supported);
+
 hipError_t launch_validate(const RobotDev* rob, const float4* sph, const EnvDev& env, int W,
                            int n_motions, const float* xi, int* status, unsigned long long* work,
                            bool early, bool cull, int batch, hipStream_t stream);

@@ -51,16 +51,23 @@ __global__ __launch_bounds__(kBlock) void fk_cc_kernel(const RobotDev* __restric
 
 // One motion per W lanes (project_segment).  Writes the segment, status
 // (0 = projected, 1 = projection failed) and the iteration count.
-template <int NDOF, int KIND>
+// MODE 0: start from the straight line.
+// MODE 1: warm start, xi[k] = clamp(straight line + delta[motion][k-1]) for
+//         k >= 1 (delta from the network, [n_motions][W-1][NDOF]).
+// MODE 2: fallback, only motions whose status is 1 are projected again from
+//         the straight line; their iterations are added to iters.
+template <int NDOF, int KIND, int MODE>
 __global__ __launch_bounds__(kBlock) void project_kernel(
     const RobotDev* __restrict__ rob, ConDev con, ProjDev prm, int n_motions,
-    const float* __restrict__ q_from, const float* __restrict__ q_to, float* __restrict__ xi,
-    int* __restrict__ status, int* __restrict__ iters, unsigned long long* __restrict__ work) {
+    const float* __restrict__ q_from, const float* __restrict__ q_to,
+    const float* __restrict__ delta, float* __restrict__ xi, int* __restrict__ status,
+    int* __restrict__ iters, unsigned long long* __restrict__ work) {
   const int W = prm.W;
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t motion = gid / W;
   const int k = (int)(gid % W);
   if (motion >= n_motions) return;   // whole motion segments leave together
+  if (MODE == 2 && status[motion] != 1) return;
   const int lane = threadIdx.x & 63;
   const int seg = lane - k;          // first lane of this motion in the wavefront
   const uint64_t wmask = (W == 64) ? ~0ull : ((1ull << W) - 1ull);
@@ -75,6 +82,11 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
       const float b = q_to[motion * NDOF + j];
       q[j] = a + s * (b - a);
     }
+    if (MODE == 1 && k >= 1) {
+      const float* d = delta + (motion * (W - 1) + (k - 1)) * NDOF;
+#pragma unroll
+      for (int j = 0; j < NDOF; ++j) q[j] = fminf(fmaxf(q[j] + d[j], rob->lo[j]), rob->hi[j]);
+    }
   }
 
   int it = 0;
@@ -87,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
   for (int j = 0; j < NDOF; ++j) xk[j] = q[j];
   if (k == 0) {
     status[motion] = ok ? 0 : 1;
-    if (iters) iters[motion] = it;
+    if (iters) iters[motion] = (MODE == 2 ? iters[motion] : 0) + it;
     if (work) atomicAdd(&work[6], updates);
   }
 }
@@ -178,21 +190,34 @@ hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& en
   return hipGetLastError();
 }
 
-template <int NDOF>
-static bool launch_project_ndof(int kind, unsigned nb, hipStream_t stream, const RobotDev* rob,
+template <int NDOF, int KIND>
+static void launch_project_kind(int mode, unsigned nb, hipStream_t stream, const RobotDev* rob,
                                 const ConDev& con, const ProjDev& prm, int n, const float* qf,
-                                const float* qt, float* xi, int* st, int* it,
+                                const float* qt, const float* delta, float* xi, int* st, int* it,
                                 unsigned long long* work) {
+  if (mode == 1)
+    project_kernel<NDOF, KIND, 1><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+  else if (mode == 2)
+    project_kernel<NDOF, KIND, 2><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+  else
+    project_kernel<NDOF, KIND, 0><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+}
+
+template <int NDOF>
+static bool launch_project_ndof(int kind, int mode, unsigned nb, hipStream_t stream,
+                                const RobotDev* rob, const ConDev& con, const ProjDev& prm, int n,
+                                const float* qf, const float* qt, const float* delta, float* xi,
+                                int* st, int* it, unsigned long long* work) {
   switch (kind) {
     case KIND_NONE:
-      project_kernel<NDOF, KIND_NONE><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, xi, st, it, work);
+      launch_project_kind<NDOF, KIND_NONE>(mode, nb, stream, rob, con, prm, n, qf, qt, delta, xi, st, it, work);
       return true;
     case KIND_POSE:
-      project_kernel<NDOF, KIND_POSE><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, xi, st, it, work);
+      launch_project_kind<NDOF, KIND_POSE>(mode, nb, stream, rob, con, prm, n, qf, qt, delta, xi, st, it, work);
       return true;
     case KIND_REL:
       if constexpr (NDOF % 2 == 0) {
-        project_kernel<NDOF, KIND_REL><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, xi, st, it, work);
+        launch_project_kind<NDOF, KIND_REL>(mode, nb, stream, rob, con, prm, n, qf, qt, delta, xi, st, it, work);
         return true;
       }
       return false;
@@ -207,23 +232,32 @@ bool dof_supported(int dof) {
   }
 }
 
-hipError_t launch_project(int dof, const RobotDev* rob, const ConDev& con, const ProjDev& prm,
-                          int n_motions, const float* q_from, const float* q_to, float* xi,
-                          int* status, int* iters, unsigned long long* work, hipStream_t stream,
-                          bool* supported) {
+hipError_t launch_project_mode(int dof, int mode, const RobotDev* rob, const ConDev& con,
+                               const ProjDev& prm, int n_motions, const float* q_from,
+                               const float* q_to, const float* delta, float* xi, int* status,
+                               int* iters, unsigned long long* work, hipStream_t stream,
+                               bool* supported) {
   const unsigned nb = blocks_for((int64_t)n_motions * prm.W);
   bool ok = false;
   switch (dof) {
-    case 2: ok = launch_project_ndof<2>(con.kind, nb, stream, rob, con, prm, n_motions, q_from, q_to, xi, status, iters, work); break;
-    case 3: ok = launch_project_ndof<3>(con.kind, nb, stream, rob, con, prm, n_motions, q_from, q_to, xi, status, iters, work); break;
-    case 6: ok = launch_project_ndof<6>(con.kind, nb, stream, rob, con, prm, n_motions, q_from, q_to, xi, status, iters, work); break;
-    case 7: ok = launch_project_ndof<7>(con.kind, nb, stream, rob, con, prm, n_motions, q_from, q_to, xi, status, iters, work); break;
-    case 9: ok = launch_project_ndof<9>(con.kind, nb, stream, rob, con, prm, n_motions, q_from, q_to, xi, status, iters, work); break;
-    case 14: ok = launch_project_ndof<14>(con.kind, nb, stream, rob, con, prm, n_motions, q_from, q_to, xi, status, iters, work); break;
+    case 2: ok = launch_project_ndof<2>(con.kind, mode, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
+    case 3: ok = launch_project_ndof<3>(con.kind, mode, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
+    case 6: ok = launch_project_ndof<6>(con.kind, mode, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
+    case 7: ok = launch_project_ndof<7>(con.kind, mode, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
+    case 9: ok = launch_project_ndof<9>(con.kind, mode, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
+    case 14: ok = launch_project_ndof<14>(con.kind, mode, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
     default: ok = false;
   }
   *supported = ok;
   return ok ? hipGetLastError() : hipSuccess;
+}
+
+hipError_t launch_project(int dof, const RobotDev* rob, const ConDev& con, const ProjDev& prm,
+                          int n_motions, const float* q_from, const float* q_to, float* xi,
+                          int* status, int* iters, unsigned long long* work, hipStream_t stream,
+                          bool* supported) {
+  return launch_project_mode(dof, 0, rob, con, prm, n_motions, q_from, q_to, nullptr, xi, status,
+                             iters, work, stream, supported);
 }
 
 hipError_t launch_validate(const RobotDev* rob, const float4* sph, const EnvDev& env, int W,

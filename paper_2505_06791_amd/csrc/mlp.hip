@@ -1,0 +1,647 @@
+// Learned warm start: an MLP that predicts the projection correction dq from
+// (q, constraint parameters), with BF16 weights and FP32 accumulation on the
+// gfx950 matrix cores, trained on the GPU by the kernels below.
+//
+// Network: n_in -> hidden (SiLU) -> ... -> hidden (SiLU) -> n_out.  Every
+// parameter has an FP32 master copy (Adam updates it) and a BF16 copy (the
+// matrix cores read it).  Layer widths are padded inside the kernels: the
+// reduction dimension to a multiple of 32 (one MFMA step), the output to a
+// multiple of 16; padding is zero and never stored.
+//
+// One GEMM kernel serves the forward pass, both backward products and
+// inference: C[M][N] = A[M][K] * B[K][N] with A and B described by strides,
+// so W^T, dZ^T and X^T are read in place.  Tiles of 64 x 64 x 32 are staged in
+// LDS by the whole workgroup (4 wavefronts); each wavefront computes a 32 x 32
+// block as 2 x 2 v_mfma_f32_16x16x32_bf16 tiles, reading its operand
+// fragments from LDS (8 consecutive BF16 per lane: A row-major, B stored
+// transposed).  Epilogues fuse the bias, SiLU, and SiLU' of the backward pass.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <random>
+#include <vector>
+
+#include "cprrtc.h"
+#include "device.h"
+#include "handles.h"
+#include "kernels.h"
+#include "project.h"
+
+namespace cprrtc {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_grad(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// Operand of the GEMM: element (r, c) at p[r * rs + c * cs].
+struct Mat {
+  const uint16_t* p;
+  long rs, cs;
+};
+
+enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2, EPI_SILU_GRAD = 3 };
+
+constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8;
+
+// C[M][N] = A[M][K] B[K][N] (+ epilogue).
+//  EPI_STORE:     out_f = C (fp32)
+//  EPI_BIAS:      out_f = C + bias (fp32), out_b = bf16 of it (nullable)
+//  EPI_BIAS_SILU: z = C + bias -> out_f = z (pre-activation, nullable), out_b = bf16(silu(z))
+//  EPI_SILU_GRAD: out_b = bf16(C * silu'(aux)) with aux the stored pre-activation
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(Mat A, Mat B, int M, int N, int K,
+                                                        const float* __restrict__ bias,
+                                                        const float* __restrict__ aux,
+                                                        float* __restrict__ out_f,
+                                                        uint16_t* __restrict__ out_b, long ldo) {
+  __shared__ __align__(16) uint16_t As[kBM][kBK + kPad];
+  __shared__ __align__(16) uint16_t Bs[kBN][kBK + kPad];   // transposed: Bs[n][k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.x * kBM, n0 = blockIdx.y * kBN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;     // this wavefront's 32 x 32 block
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = 0; k0 < K; k0 += kBK) {
+    // stage: 64 x 32 of A and 32 x 64 of B, 8 elements per thread each
+    for (int e = tid; e < kBM * kBK; e += 256) {
+      const int r = e / kBK, c = e % kBK;
+      const int gm = m0 + r, gk = k0 + c;
+      As[r][c] = (gm < M && gk < K) ? A.p[gm * A.rs + gk * A.cs] : (uint16_t)0;
+    }
+    for (int e = tid; e < kBN * kBK; e += 256) {
+      const int n = e / kBK, c = e % kBK;
+      const int gn = n0 + n, gk = k0 + c;
+      Bs[n][c] = (gn < N && gk < K) ? B.p[gk * B.rs + gn * B.cs] : (uint16_t)0;
+    }
+    __syncthreads();
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    bf16x8 a[2], b[2];
+    for (int i = 0; i < 2; ++i)
+      a[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&As[wm + i * 16 + fr][fk]));
+    for (int j = 0; j < 2; ++j)
+      b[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bs[wn + j * 16 + fr][fk]));
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  // result layout of a 16 x 16 tile: lane holds rows 4*(lane/16) + t, column lane % 16
+  const int col = lane & 15, rb = (lane >> 4) * 4;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int t = 0; t < 4; ++t) {
+        const int gm = m0 + wm + i * 16 + rb + t, gn = n0 + wn + j * 16 + col;
+        if (gm >= M || gn >= N) continue;
+        const float c = acc[i][j][t];
+        const long o = (long)gm * ldo + gn;
+        if (EPI == EPI_STORE) {
+          out_f[o] = c;
+        } else if (EPI == EPI_BIAS) {
+          const float z = c + bias[gn];
+          if (out_f) out_f[o] = z;
+          if (out_b) out_b[o] = to_bf16(z);
+        } else if (EPI == EPI_BIAS_SILU) {
+          const float z = c + bias[gn];
+          if (out_f) out_f[o] = z;
+          out_b[o] = to_bf16(silu(z));
+        } else {
+          out_b[o] = to_bf16(c * silu_grad(aux[o]));
+        }
+      }
+}
+
+// fp32 [M][n] (row stride ld_in) -> bf16 [M][ld_out], zero-padded columns n..ld_out-1
+__global__ void to_bf16_kernel(const float* __restrict__ in, int M, int n, long ld_in,
+                               uint16_t* __restrict__ out, int ld_out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)M * ld_out) return;
+  const long m = i / ld_out;
+  const int c = (int)(i % ld_out);
+  out[i] = c < n ? to_bf16(in[m * ld_in + c]) : (uint16_t)0;
+}
+
+// MSE loss over the n real outputs: dy = 2 (y - t) / (M n) as bf16 [M][ld], loss sum.
+__global__ void mse_grad_kernel(const float* __restrict__ y, long ldy, const float* __restrict__ t,
+                                int M, int n, uint16_t* __restrict__ dy, int ld,
+                                float* __restrict__ loss) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  float l = 0.0f;
+  if (i < (long)M * ld) {
+    const long m = i / ld;
+    const int c = (int)(i % ld);
+    float g = 0.0f;
+    if (c < n) {
+      const float d = y[m * ldy + c] - t[m * n + c];
+      l = d * d;
+      g = 2.0f * d / ((float)M * (float)n);
+    }
+    dy[i] = to_bf16(g);
+  }
+  // wavefront sum, one atomic per wavefront
+  for (int o = 32; o >= 1; o >>= 1) l += __shfl_xor(l, o, 64);
+  if (loss && (threadIdx.x & 63) == 0) atomicAdd(loss, l / ((float)M * (float)n));
+}
+
+// bias gradient: db[n] = sum_m dz[m][n] (bf16 [M][ld]); one block per column slice
+__global__ void bias_grad_kernel(const uint16_t* __restrict__ dz, int M, int N, int ld,
+                                 float* __restrict__ db) {
+  const int n = blockIdx.x;
+  if (n >= N) return;
+  float s = 0.0f;
+  for (int m = threadIdx.x; m < M; m += blockDim.x) s += from_bf16(dz[(long)m * ld + n]);
+  __shared__ float red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[n] = red[0];
+}
+
+// Adam on the FP32 masters, refreshing the BF16 copies.
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g,
+                            float* __restrict__ m1, float* __restrict__ m2,
+                            uint16_t* __restrict__ wb, long n, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float a = b1 * m1[i] + (1.0f - b1) * gi;
+  const float v = b2 * m2[i] + (1.0f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = v;
+  const float upd = lr * (a / c1) / (sqrtf(v / c2) + eps);
+  const float nw = w[i] - upd;
+  w[i] = nw;
+  wb[i] = to_bf16(nw);
+}
+
+__global__ void refresh_bf16_kernel(const float* __restrict__ w, uint16_t* __restrict__ wb, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) wb[i] = to_bf16(w[i]);
+}
+
+}  // namespace cprrtc
+
+using namespace cprrtc;
+
+// ------------------------------------------------------------------ the network handle
+
+struct cp_mlp {
+  int n_in = 0, hidden = 0, n_hidden = 0, n_out = 0, n_layers = 0;
+  std::vector<int> in_dim, out_dim;          // per layer (unpadded)
+  std::vector<long> w_off, b_off;             // offsets into the parameter vector
+  long n_params = 0;
+  float* w = nullptr;                         // fp32 masters [n_params]
+  uint16_t* wb = nullptr;                     // bf16 copies
+  float* grad = nullptr;
+  float* m1 = nullptr;
+  float* m2 = nullptr;
+  long step = 0;
+  // activation workspace for up to ws_rows rows
+  long ws_rows = 0;
+  uint16_t* xb = nullptr;                     // [rows][in_pad]
+  std::vector<uint16_t*> hb;                  // per layer output, bf16 [rows][out_pad]
+  std::vector<float*> zf;                     // per hidden layer pre-activation fp32 [rows][hidden]
+  float* yf = nullptr;                        // [rows][out_pad] fp32
+  uint16_t* dyb = nullptr;                    // [rows][max_pad] bf16 gradient buffers
+  uint16_t* dzb = nullptr;
+  float* loss = nullptr;
+  // inference workspace (chunked, no stored pre-activations)
+  long inf_rows = 0;
+  uint16_t* ia = nullptr;                     // [rows][max width] bf16, ping
+  uint16_t* ib = nullptr;                     // pong
+  uint16_t* ix = nullptr;                     // [rows][in_pad] bf16 input
+  float* iy = nullptr;                        // [rows][out_pad] fp32 output
+  float* feat = nullptr;                      // warm start: [rows][n_in] features
+  float* delta = nullptr;                     // warm start: [rows][n_out] corrections
+  long warm_rows = 0;
+};
+
+namespace {
+
+int pad32(int x) { return (x + 31) / 32 * 32; }
+int pad16(int x) { return (x + 15) / 16 * 16; }
+
+void free_ws(cp_mlp* n) {
+  if (n->xb) (void)hipFree(n->xb);
+  for (auto p : n->hb) if (p) (void)hipFree(p);
+  for (auto p : n->zf) if (p) (void)hipFree(p);
+  if (n->yf) (void)hipFree(n->yf);
+  if (n->dyb) (void)hipFree(n->dyb);
+  if (n->dzb) (void)hipFree(n->dzb);
+  n->xb = nullptr;
+  n->hb.assign(n->hb.size(), nullptr);
+  n->zf.assign(n->zf.size(), nullptr);
+  n->yf = nullptr;
+  n->dyb = n->dzb = nullptr;
+  n->ws_rows = 0;
+}
+
+// width used for a layer's output buffer: hidden layers keep their width
+// (a multiple of 32), the last layer is padded to 16 columns
+int out_pad(const cp_mlp* n, int l) { return l + 1 < n->n_layers ? n->out_dim[l] : pad16(n->out_dim[l]); }
+int in_pad(const cp_mlp* n) { return pad32(n->n_in); }
+
+hipError_t ensure_ws(cp_mlp* n, long rows) {
+  if (rows <= n->ws_rows) return hipSuccess;
+  free_ws(n);
+  long r = std::max(rows, 256L);
+  hipError_t e = hipMalloc((void**)&n->xb, sizeof(uint16_t) * r * in_pad(n));
+  n->hb.assign(n->n_layers, nullptr);
+  n->zf.assign(n->n_layers, nullptr);
+  int maxw = in_pad(n);
+  for (int l = 0; l < n->n_layers && e == hipSuccess; ++l) {
+    e = hipMalloc((void**)&n->hb[l], sizeof(uint16_t) * r * out_pad(n, l));
+    if (e == hipSuccess && l + 1 < n->n_layers) e = hipMalloc((void**)&n->zf[l], sizeof(float) * r * n->out_dim[l]);
+    maxw = std::max(maxw, out_pad(n, l));
+  }
+  if (e == hipSuccess) e = hipMalloc((void**)&n->yf, sizeof(float) * r * out_pad(n, n->n_layers - 1));
+  if (e == hipSuccess) e = hipMalloc((void**)&n->dyb, sizeof(uint16_t) * r * maxw);
+  if (e == hipSuccess) e = hipMalloc((void**)&n->dzb, sizeof(uint16_t) * r * maxw);
+  if (e == hipSuccess) n->ws_rows = r;
+  return e;
+}
+
+void gemm(int epi, Mat A, Mat B, int M, int N, int K, const float* bias, const float* aux,
+          float* out_f, uint16_t* out_b, long ldo, hipStream_t st) {
+  dim3 grid((M + kBM - 1) / kBM, (N + kBN - 1) / kBN);
+  switch (epi) {
+    case EPI_STORE: gemm_bf16_kernel<EPI_STORE><<<grid, 256, 0, st>>>(A, B, M, N, K, bias, aux, out_f, out_b, ldo); break;
+    case EPI_BIAS: gemm_bf16_kernel<EPI_BIAS><<<grid, 256, 0, st>>>(A, B, M, N, K, bias, aux, out_f, out_b, ldo); break;
+    case EPI_BIAS_SILU: gemm_bf16_kernel<EPI_BIAS_SILU><<<grid, 256, 0, st>>>(A, B, M, N, K, bias, aux, out_f, out_b, ldo); break;
+    default: gemm_bf16_kernel<EPI_SILU_GRAD><<<grid, 256, 0, st>>>(A, B, M, N, K, bias, aux, out_f, out_b, ldo); break;
+  }
+}
+
+unsigned nblk(long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+// Forward of M rows; x: fp32 [M][n_in] (row stride ldx).  Leaves activations
+// in the workspace; the network output (fp32) is n->yf [M][out_pad].
+hipError_t forward(cp_mlp* n, long M, const float* x, long ldx, hipStream_t st) {
+  hipError_t e = ensure_ws(n, M);
+  if (e != hipSuccess) return e;
+  const int ip = in_pad(n);
+  to_bf16_kernel<<<nblk(M * ip), 256, 0, st>>>(x, (int)M, n->n_in, ldx, n->xb, ip);
+  const uint16_t* in = n->xb;
+  long ld_in = ip;
+  for (int l = 0; l < n->n_layers; ++l) {
+    const int K = n->in_dim[l], N = n->out_dim[l];
+    Mat A{in, ld_in, 1};
+    Mat B{n->wb + n->w_off[l], 1, (long)K};       // B[k][n] = W[n][k]
+    const float* bias = n->w + n->b_off[l];
+    if (l + 1 < n->n_layers) {
+      gemm(EPI_BIAS_SILU, A, B, (int)M, N, K, bias, nullptr, n->zf[l], n->hb[l], out_pad(n, l), st);
+    } else {
+      gemm(EPI_BIAS, A, B, (int)M, N, K, bias, nullptr, n->yf, nullptr, out_pad(n, l), st);
+    }
+    in = n->hb[l];
+    ld_in = out_pad(n, l);
+  }
+  return hipGetLastError();
+}
+
+// Backward of the MSE loss after forward(): gradients into n->grad.
+hipError_t backward(cp_mlp* n, long M, const float* t, hipStream_t st) {
+  const int L = n->n_layers;
+  const int op = out_pad(n, L - 1);
+  if (n->loss) (void)hipMemsetAsync(n->loss, 0, sizeof(float), st);
+  mse_grad_kernel<<<nblk(M * op), 256, 0, st>>>(n->yf, op, t, (int)M, n->n_out, n->dyb, op, n->loss);
+  uint16_t* dz = n->dyb;      // gradient wrt the current layer's output pre-activation
+  int ldz = op;
+  for (int l = L - 1; l >= 0; --l) {
+    const int K = n->in_dim[l], N = n->out_dim[l];
+    const uint16_t* in = l == 0 ? n->xb : n->hb[l - 1];
+    const long ld_in = l == 0 ? in_pad(n) : out_pad(n, l - 1);
+    // dW[N][K] = dZ^T[N][M] * X[M][K]
+    gemm(EPI_STORE, Mat{dz, 1, (long)ldz}, Mat{in, ld_in, 1}, N, K, (int)M, nullptr, nullptr,
+         n->grad + n->w_off[l], nullptr, K, st);
+    bias_grad_kernel<<<N, 256, 0, st>>>(dz, (int)M, N, ldz, n->grad + n->b_off[l]);
+    if (l == 0) break;
+    // dH[M][K] = dZ[M][N] * W[N][K], then dZ_prev = dH * silu'(z_prev)
+    uint16_t* next = (dz == n->dyb) ? n->dzb : n->dyb;
+    gemm(EPI_SILU_GRAD, Mat{dz, (long)ldz, 1}, Mat{n->wb + n->w_off[l], (long)K, 1}, (int)M, K, N,
+         nullptr, n->zf[l - 1], nullptr, next, K, st);
+    dz = next;
+    ldz = K;
+  }
+  return hipGetLastError();
+}
+
+constexpr long kInferChunk = 1L << 19;   // rows per inference chunk
+
+hipError_t ensure_infer(cp_mlp* n) {
+  if (n->inf_rows) return hipSuccess;
+  const long r = kInferChunk;
+  int maxw = 0;
+  for (int l = 0; l < n->n_layers; ++l) maxw = std::max(maxw, out_pad(n, l));
+  hipError_t e = hipMalloc((void**)&n->ia, sizeof(uint16_t) * r * maxw);
+  if (e == hipSuccess) e = hipMalloc((void**)&n->ib, sizeof(uint16_t) * r * maxw);
+  if (e == hipSuccess) e = hipMalloc((void**)&n->ix, sizeof(uint16_t) * r * in_pad(n));
+  if (e == hipSuccess) e = hipMalloc((void**)&n->iy, sizeof(float) * r * out_pad(n, n->n_layers - 1));
+  if (e == hipSuccess) n->inf_rows = r;
+  return e;
+}
+
+// y[M][n_out] = network(x[M][n_in]), in chunks of kInferChunk rows.
+hipError_t infer(cp_mlp* n, long M, const float* x, float* y, hipStream_t st) {
+  hipError_t e = ensure_infer(n);
+  const int ip = in_pad(n), op = out_pad(n, n->n_layers - 1);
+  for (long r0 = 0; r0 < M && e == hipSuccess; r0 += kInferChunk) {
+    const long R = std::min(kInferChunk, M - r0);
+    to_bf16_kernel<<<nblk(R * ip), 256, 0, st>>>(x + r0 * n->n_in, (int)R, n->n_in, n->n_in, n->ix, ip);
+    const uint16_t* in = n->ix;
+    long ld_in = ip;
+    uint16_t* bufs[2] = {n->ia, n->ib};
+    for (int l = 0; l < n->n_layers; ++l) {
+      const int K = n->in_dim[l], N = n->out_dim[l];
+      Mat A{in, ld_in, 1};
+      Mat B{n->wb + n->w_off[l], 1, (long)K};
+      const float* bias = n->w + n->b_off[l];
+      if (l + 1 < n->n_layers) {
+        gemm(EPI_BIAS_SILU, A, B, (int)R, N, K, bias, nullptr, nullptr, bufs[l & 1], out_pad(n, l), st);
+        in = bufs[l & 1];
+        ld_in = out_pad(n, l);
+      } else {
+        gemm(EPI_BIAS, A, B, (int)R, N, K, bias, nullptr, n->iy, nullptr, op, st);
+      }
+    }
+    e = hipMemcpy2DAsync(y + r0 * n->n_out, sizeof(float) * n->n_out, n->iy, sizeof(float) * op,
+                         sizeof(float) * n->n_out, R, hipMemcpyDeviceToDevice, st);
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  return e;
+}
+
+}  // namespace
+
+// Features of the warm start, one row per waypoint k = 1..W-1 of each
+// motion: the straight-line waypoint scaled by the joint range, then the
+// constraint parameters (pose: locked targets; relative pose: p* and R*).
+template <int NDOF>
+__global__ void warm_features_kernel(const RobotDev* __restrict__ rob, int W, int n_motions,
+                                     const float* __restrict__ q_from,
+                                     const float* __restrict__ q_to, const float* __restrict__ cp,
+                                     int n_cp, float* __restrict__ x) {
+  const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= (long)n_motions * (W - 1)) return;
+  const long m = row / (W - 1);
+  const int k = (int)(row % (W - 1)) + 1;
+  const float s = (float)k / (float)(W - 1);
+  float* o = x + row * (NDOF + n_cp);
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) {
+    const float a = q_from[m * NDOF + j], b = q_to[m * NDOF + j];
+    const float range = fmaxf(fabsf(rob->lo[j]), fabsf(rob->hi[j]));
+    o[j] = (a + s * (b - a)) / range;
+  }
+  for (int c = 0; c < n_cp; ++c) o[NDOF + c] = cp[c];
+}
+
+namespace cprrtc {
+// feature count of the warm start for a robot and constraint
+int warm_inputs(int dof, int kind) { return dof + (kind == KIND_REL ? 12 : 6); }
+}  // namespace cprrtc
+
+extern "C" {
+
+int cp_mlp_create(int32_t n_in, int32_t hidden, int32_t n_hidden, int32_t n_out, uint64_t seed,
+                  cp_mlp** out) {
+  try {
+    if (!out) return api_fail(CP_E_ARG, "cp_mlp_create: NULL argument");
+    *out = nullptr;
+    if (n_in < 1 || n_in > 256 || n_out < 1 || n_out > 256 || n_hidden < 1 || n_hidden > 8 ||
+        hidden < 32 || hidden > 2048 || hidden % 32)
+      return api_fail(CP_E_ARG, "cp_mlp_create: sizes out of range (hidden a multiple of 32)");
+    cp_mlp* n = new (std::nothrow) cp_mlp;
+    if (!n) return api_fail(CP_E_ARG, "out of host memory");
+    n->n_in = n_in; n->hidden = hidden; n->n_hidden = n_hidden; n->n_out = n_out;
+    n->n_layers = n_hidden + 1;
+    long off = 0;
+    for (int l = 0; l < n->n_layers; ++l) {
+      const int K = l == 0 ? n_in : hidden, N = l + 1 < n->n_layers ? hidden : n_out;
+      n->in_dim.push_back(K);
+      n->out_dim.push_back(N);
+      n->w_off.push_back(off);
+      off += (long)N * K;
+      n->b_off.push_back(off);
+      off += N;
+    }
+    n->n_params = off;
+    // He-style uniform initialisation from the seed, zero biases
+    std::vector<float> w(off, 0.0f);
+    std::mt19937_64 rng(seed);
+    for (int l = 0; l < n->n_layers; ++l) {
+      const float a = std::sqrt(6.0f / (float)n->in_dim[l]) * (l + 1 < n->n_layers ? 1.0f : 0.1f);
+      std::uniform_real_distribution<float> u(-a, a);
+      for (long i = 0; i < (long)n->in_dim[l] * n->out_dim[l]; ++i) w[n->w_off[l] + i] = u(rng);
+    }
+    hipError_t e = hipMalloc((void**)&n->w, sizeof(float) * off);
+    if (e == hipSuccess) e = hipMalloc((void**)&n->wb, sizeof(uint16_t) * off);
+    if (e == hipSuccess) e = hipMalloc((void**)&n->grad, sizeof(float) * off);
+    if (e == hipSuccess) e = hipMalloc((void**)&n->m1, sizeof(float) * off);
+    if (e == hipSuccess) e = hipMalloc((void**)&n->m2, sizeof(float) * off);
+    if (e == hipSuccess) e = hipMalloc((void**)&n->loss, sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(n->w, w.data(), sizeof(float) * off, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(n->m1, 0, sizeof(float) * off);
+    if (e == hipSuccess) e = hipMemset(n->m2, 0, sizeof(float) * off);
+    if (e == hipSuccess) {
+      refresh_bf16_kernel<<<nblk(off), 256>>>(n->w, n->wb, off);
+      e = hipDeviceSynchronize();
+    }
+    if (e != hipSuccess) {
+      cp_mlp_destroy(n);
+      return api_hip_fail(e, "cp_mlp_create");
+    }
+    *out = n;
+    return CP_OK;
+  } catch (...) {
+    return api_fail(CP_E_ARG, "cp_mlp_create: unexpected exception");
+  }
+}
+
+void cp_mlp_destroy(cp_mlp* n) {
+  if (!n) return;
+  free_ws(n);
+  for (void* p : {(void*)n->ia, (void*)n->ib, (void*)n->ix, (void*)n->iy, (void*)n->feat,
+                  (void*)n->delta})
+    if (p) (void)hipFree(p);
+  for (float* p : {n->w, n->grad, n->m1, n->m2, n->loss}) if (p) (void)hipFree(p);
+  if (n->wb) (void)hipFree(n->wb);
+  delete n;
+}
+
+int64_t cp_mlp_num_params(const cp_mlp* n) { return n ? n->n_params : 0; }
+
+int cp_mlp_get_params(const cp_mlp* n, float* d_out, void* stream) {
+  if (!n || !d_out) return api_fail(CP_E_ARG, "cp_mlp_get_params: NULL argument");
+  hipError_t e = hipMemcpyAsync(d_out, n->w, sizeof(float) * n->n_params, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_mlp_get_params");
+}
+
+int cp_mlp_set_params(cp_mlp* n, const float* d_in, void* stream) {
+  if (!n || !d_in) return api_fail(CP_E_ARG, "cp_mlp_set_params: NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(n->w, d_in, sizeof(float) * n->n_params, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) {
+    refresh_bf16_kernel<<<nblk(n->n_params), 256, 0, st>>>(n->w, n->wb, n->n_params);
+    e = hipGetLastError();
+  }
+  return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_mlp_set_params");
+}
+
+int cp_mlp_forward(cp_mlp* n, int64_t M, const float* d_x, float* d_y, void* stream) {
+  try {
+    if (!n) return api_fail(CP_E_ARG, "cp_mlp_forward: NULL handle");
+    if (M < 0) return api_fail(CP_E_ARG, "cp_mlp_forward: M < 0");
+    if (M == 0) return CP_OK;
+    if (!d_x || !d_y) return api_fail(CP_E_ARG, "cp_mlp_forward: NULL buffer");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = forward(n, M, d_x, n->n_in, st);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(d_y, sizeof(float) * n->n_out, n->yf, sizeof(float) * out_pad(n, n->n_layers - 1),
+                           sizeof(float) * n->n_out, M, hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_mlp_forward");
+  } catch (...) {
+    return api_fail(CP_E_ARG, "cp_mlp_forward: unexpected exception");
+  }
+}
+
+int cp_mlp_gradients(cp_mlp* n, int64_t M, const float* d_x, const float* d_t, float* d_grad,
+                     float* d_loss, void* stream) {
+  try {
+    if (!n || !d_x || !d_t) return api_fail(CP_E_ARG, "cp_mlp_gradients: NULL argument");
+    if (M < 1) return api_fail(CP_E_ARG, "cp_mlp_gradients: M < 1");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = forward(n, M, d_x, n->n_in, st);
+    if (e == hipSuccess) e = backward(n, M, d_t, st);
+    if (e == hipSuccess && d_grad) e = hipMemcpyAsync(d_grad, n->grad, sizeof(float) * n->n_params, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && d_loss) e = hipMemcpyAsync(d_loss, n->loss, sizeof(float), hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_mlp_gradients");
+  } catch (...) {
+    return api_fail(CP_E_ARG, "cp_mlp_gradients: unexpected exception");
+  }
+}
+
+int cp_mlp_train_step(cp_mlp* n, int64_t M, const float* d_x, const float* d_t, float lr,
+                      float* d_loss, void* stream) {
+  try {
+    if (!n || !d_x || !d_t) return api_fail(CP_E_ARG, "cp_mlp_train_step: NULL argument");
+    if (M < 1 || !(lr > 0)) return api_fail(CP_E_ARG, "cp_mlp_train_step: M < 1 or lr <= 0");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = forward(n, M, d_x, n->n_in, st);
+    if (e == hipSuccess) e = backward(n, M, d_t, st);
+    if (e != hipSuccess) return api_hip_fail(e, "cp_mlp_train_step");
+    n->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - std::pow(b1, (float)n->step), c2 = 1.0f - std::pow(b2, (float)n->step);
+    adam_kernel<<<nblk(n->n_params), 256, 0, st>>>(n->w, n->grad, n->m1, n->m2, n->wb, n->n_params,
+                                                    lr, b1, b2, 1e-8f, c1, c2);
+    e = hipGetLastError();
+    if (e == hipSuccess && d_loss) e = hipMemcpyAsync(d_loss, n->loss, sizeof(float), hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_mlp_train_step");
+  } catch (...) {
+    return api_fail(CP_E_ARG, "cp_mlp_train_step: unexpected exception");
+  }
+}
+
+int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
+                         const cp_proj_params* params, cp_mlp* mlp, int32_t n_motions,
+                         const float* d_q_from, const float* d_q_to, float* d_xi,
+                         int32_t* d_status, int32_t* d_iters, uint64_t* d_work, int32_t flags,
+                         void* stream) {
+  try {
+    if (!robot || !mlp) return api_fail(CP_E_ARG, "project_motions_warm: NULL handle");
+    if (n_motions < 0) return api_fail(CP_E_ARG, "project_motions_warm: n_motions < 0");
+    cp_proj_params p;
+    int rc = api_params(params, &p);
+    if (rc != CP_OK) return rc;
+    ConDev con;
+    rc = api_constraint(constraint, robot, &con);
+    if (rc != CP_OK) return rc;
+    const int dof = robot->host.dof;
+    if (!dof_supported(dof)) return api_fail(CP_E_UNSUPPORTED, "dof %d", dof);
+    if (mlp->n_in != warm_inputs(dof, con.kind) || mlp->n_out != dof)
+      return api_fail(CP_E_ARG, "network has %d inputs / %d outputs, the warm start needs %d / %d",
+                      mlp->n_in, mlp->n_out, warm_inputs(dof, con.kind), dof);
+    if (n_motions == 0) return CP_OK;
+    if (!d_q_from || !d_q_to || !d_xi || !d_status) return api_fail(CP_E_ARG, "NULL buffer");
+    hipStream_t st = (hipStream_t)stream;
+    const long rows = (long)n_motions * (p.W - 1);
+    hipError_t e = hipSuccess;
+    if (rows > mlp->warm_rows) {
+      if (mlp->feat) (void)hipFree(mlp->feat);
+      if (mlp->delta) (void)hipFree(mlp->delta);
+      mlp->feat = mlp->delta = nullptr;
+      mlp->warm_rows = 0;
+      e = hipMalloc((void**)&mlp->feat, sizeof(float) * rows * mlp->n_in);
+      if (e == hipSuccess) e = hipMalloc((void**)&mlp->delta, sizeof(float) * rows * dof);
+      if (e != hipSuccess) return api_hip_fail(e, "project_motions_warm workspace");
+      mlp->warm_rows = rows;
+    }
+    // constraint parameters as network inputs
+    float cp[12] = {0};
+    int n_cp = 6;
+    if (con.kind == KIND_POSE) {
+      for (int i = 0; i < 6; ++i) cp[i] = con.target[i] * con.mask[i];
+    } else if (con.kind == KIND_REL) {
+      n_cp = 12;
+      for (int i = 0; i < 3; ++i) cp[i] = con.target[i];
+      for (int i = 0; i < 3; ++i)
+        for (int c = 0; c < 3; ++c) cp[3 + 3 * i + c] = con.Rt[3 * c + i];   // R* row-major
+    }
+    float* d_cp = mlp->delta;   // borrow the first floats of delta for the parameters
+    e = hipMemcpyAsync(d_cp, cp, sizeof(float) * n_cp, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return api_hip_fail(e, "project_motions_warm");
+    const unsigned nb = nblk(rows);
+    switch (dof) {
+      case 2: warm_features_kernel<2><<<nb, 256, 0, st>>>(robot->dev, p.W, n_motions, d_q_from, d_q_to, d_cp, n_cp, mlp->feat); break;
+      case 3: warm_features_kernel<3><<<nb, 256, 0, st>>>(robot->dev, p.W, n_motions, d_q_from, d_q_to, d_cp, n_cp, mlp->feat); break;
+      case 6: warm_features_kernel<6><<<nb, 256, 0, st>>>(robot->dev, p.W, n_motions, d_q_from, d_q_to, d_cp, n_cp, mlp->feat); break;
+      case 7: warm_features_kernel<7><<<nb, 256, 0, st>>>(robot->dev, p.W, n_motions, d_q_from, d_q_to, d_cp, n_cp, mlp->feat); break;
+      case 9: warm_features_kernel<9><<<nb, 256, 0, st>>>(robot->dev, p.W, n_motions, d_q_from, d_q_to, d_cp, n_cp, mlp->feat); break;
+      default: warm_features_kernel<14><<<nb, 256, 0, st>>>(robot->dev, p.W, n_motions, d_q_from, d_q_to, d_cp, n_cp, mlp->feat); break;
+    }
+    e = hipGetLastError();
+    if (e == hipSuccess) e = infer(mlp, rows, mlp->feat, mlp->delta, st);
+    if (e != hipSuccess) return api_hip_fail(e, "project_motions_warm network");
+    ProjDev prm;
+    prm.W = p.W;
+    prm.max_iters = p.max_iters;
+    prm.tau = (float)p.tau;
+    prm.tau_sm = (float)p.tau_sm;
+    prm.tau_task = (float)p.tau_task;
+    prm.alpha = (float)p.alpha;
+    prm.lambda2 = (float)(p.lambda * p.lambda);
+    bool sup = false;
+    e = launch_project_mode(dof, 1, robot->dev, con, prm, n_motions, d_q_from, d_q_to, mlp->delta,
+                            d_xi, d_status, d_iters, (unsigned long long*)d_work, st, &sup);
+    if (e == hipSuccess && sup && !(flags & CP_WARM_NO_FALLBACK))
+      e = launch_project_mode(dof, 2, robot->dev, con, prm, n_motions, d_q_from, d_q_to, nullptr,
+                              d_xi, d_status, d_iters, (unsigned long long*)d_work, st, &sup);
+    if (!sup) return api_fail(CP_E_UNSUPPORTED, "no kernel for dof %d with constraint kind %d", dof, con.kind);
+    if (e != hipSuccess) return api_hip_fail(e, "project_motions_warm projection");
+    return CP_OK;
+  } catch (...) {
+    return api_fail(CP_E_ARG, "project_motions_warm: unexpected exception");
+  }
+}
+
+}  // extern "C"

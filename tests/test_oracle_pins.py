@@ -427,3 +427,36 @@ def test_motion_verdicts_tiny_scene(oracle_lib):
     out = O.project_validate_motions(rob, E, c, prm, q_from, q_to)
     assert list(out["status"]) == [O.MOTION_COLLISION, O.MOTION_VALID]
     assert np.all(out["iters"] == 1)
+
+
+# ------------------------------------------------------------------ MLP (learned warm start)
+
+def test_mlp_gradients_match_central_differences(oracle_lib):
+    O = oracle_lib
+    rng = np.random.default_rng(5)
+    dims = [3, 4, 4, 2]
+    p = rng.normal(size=O.mlp_num_params(dims)) * 0.7
+    x = rng.normal(size=(5, 3))
+    t = rng.normal(size=(5, 2))
+    loss, g = O.mlp_gradients(dims, p, x, t)
+    h = 1e-6
+    for i in range(len(p)):
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (O.mlp_gradients(dims, pp, x, t)[0] - O.mlp_gradients(dims, pm, x, t)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+    # the loss is the mean squared error of the forward pass
+    y = O.mlp_forward(dims, p, x)
+    assert abs(loss - np.mean((y - t) ** 2)) < 1e-14
+
+
+def test_mlp_forward_closed_form(oracle_lib):
+    """One hidden unit: y = w2 * silu(w1 x + b1) + b2 with silu(z) = z sigmoid(z)."""
+    O = oracle_lib
+    dims = [1, 1, 1]
+    w1, b1, w2, b2 = 0.7, -0.2, 1.3, 0.4
+    x = np.array([[0.5], [-1.5], [2.0]])
+    y = O.mlp_forward(dims, [w1, b1, w2, b2], x)
+    z = w1 * x + b1
+    np.testing.assert_allclose(y, w2 * z / (1 + np.exp(-z)) + b2, rtol=1e-14)
