@@ -303,6 +303,49 @@ int plan(const cp_robot* robot, const cp_env* env, const cp_constraint* constrai
          const double* start, const double* goal, uint64_t seed, const cp_plan_opts* opts,
          cp_path* out);
 
+/* ------------------------------------------------------------ batched planning */
+
+/* Many independent queries (robots, DOF, scenes, constraint kinds may all
+ * differ) planned together.  Queries are grouped by (DOF, constraint kind);
+ * a round is one launch per group, in which each query owns
+ * groups_per_query wavefronts and runs the extension step of cp_plan;
+ * rounds_per_graph rounds are captured in a HIP graph that is replayed until
+ * every query is solved, out of budget (max_rounds, rounded up to a whole
+ * replay) or out of tree capacity.  Each query's samples depend on its seed
+ * only, not on the other queries of the batch.
+ * Supported: dof 6, 7, 9 with no / pose constraint; dof 14 with pose /
+ * relative-pose constraint. */
+typedef struct cp_batch_opts {
+  cp_proj_params proj;        /* W and sphere_batch shared by the batch */
+  int32_t groups_per_query;   /* wavefronts per query per round (16) */
+  int32_t max_rounds;         /* round budget (500) */
+  int32_t capacity;           /* nodes per tree per query (2048) */
+  int32_t max_connect;        /* (64) */
+  int32_t rounds_per_graph;   /* rounds per graph replay (4) */
+} cp_batch_opts;
+
+typedef struct cp_query {
+  const cp_robot* robot;
+  const cp_env* env;
+  const cp_constraint* constraint;
+  const double* start;        /* [dof] host */
+  const double* goal;         /* [dof] host */
+  uint64_t seed;
+} cp_query;
+
+typedef struct cp_batch cp_batch;   /* opaque: tree pools for max_queries queries */
+
+void cp_batch_opts_default(cp_batch_opts* o);
+int cp_batch_create(const cp_batch_opts* opts, int32_t max_queries, int32_t max_dof,
+                    cp_batch** out);
+void cp_batch_destroy(cp_batch* batch);
+/* Synchronous (waits for `stream` first, works on its own stream).
+ * status[i]: CP_OK (path in paths[i]), CP_NO_SOLUTION, CP_E_START,
+ * CP_E_GOAL, CP_E_CAPACITY (tree full or paths[i].capacity too small).
+ * stats nullable ([n]).  Returns CP_OK unless the call itself fails. */
+int cp_plan_batch(cp_batch* batch, int32_t n, const cp_query* queries, cp_path* paths,
+                  int32_t* status, cp_plan_stats* stats, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

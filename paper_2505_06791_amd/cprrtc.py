@@ -71,6 +71,17 @@ class PlanStats(C.Structure):
     _fields_ = [("rounds", C.c_int32), ("nodes", C.c_int32 * 2), ("overflow", C.c_int32)]
 
 
+class BatchOpts(C.Structure):
+    _fields_ = [("proj", ProjParams), ("groups_per_query", C.c_int32), ("max_rounds", C.c_int32),
+                ("capacity", C.c_int32), ("max_connect", C.c_int32),
+                ("rounds_per_graph", C.c_int32)]
+
+
+class Query(C.Structure):
+    _fields_ = [("robot", C.c_void_p), ("env", C.c_void_p), ("constraint", C.c_void_p),
+                ("start", _dp), ("goal", _dp), ("seed", C.c_uint64)]
+
+
 _lib = None
 
 
@@ -102,6 +113,11 @@ def lib():
                               C.POINTER(Path), C.POINTER(PlanStats), vp]
         L.plan.argtypes = [vp, vp, C.POINTER(Constraint), _dp, _dp, C.c_uint64,
                            C.POINTER(PlanOpts), C.POINTER(Path)]
+        L.cp_batch_opts_default.argtypes = [C.POINTER(BatchOpts)]
+        L.cp_batch_create.argtypes = [C.POINTER(BatchOpts), C.c_int32, C.c_int32, C.POINTER(vp)]
+        L.cp_batch_destroy.argtypes = [vp]
+        L.cp_plan_batch.argtypes = [vp, C.c_int32, C.POINTER(Query), C.POINTER(Path),
+                                    C.POINTER(C.c_int32), C.POINTER(PlanStats), vp]
         L.cp_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
                                     C.POINTER(vp)]
         L.cp_mlp_destroy.argtypes = [vp]
@@ -318,6 +334,61 @@ class Planner:
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.cp_planner_destroy(self.handle)
+            self.handle = None
+
+
+def batch_opts(groups_per_query=16, max_rounds=500, capacity=2048, max_connect=64,
+               rounds_per_graph=4, **proj) -> BatchOpts:
+    o = BatchOpts()
+    lib().cp_batch_opts_default(C.byref(o))
+    o.proj = proj_params(**proj)
+    o.groups_per_query, o.max_rounds, o.capacity = groups_per_query, max_rounds, capacity
+    o.max_connect, o.rounds_per_graph = max_connect, rounds_per_graph
+    return o
+
+
+class BatchPlanner:
+    """cp_batch handle: tree pools for up to max_queries queries of up to
+    max_dof joints, planned together (one launch per (DOF, constraint kind)
+    class per round, rounds replayed from a HIP graph)."""
+
+    def __init__(self, max_queries: int, max_dof: int, opts: BatchOpts | None = None):
+        self.opts = opts if opts is not None else batch_opts()
+        self.max_queries, self.max_dof = max_queries, max_dof
+        h = C.c_void_p()
+        _check(lib().cp_batch_create(C.byref(self.opts), max_queries, max_dof, C.byref(h)))
+        self.handle = h
+
+    def plan(self, queries, max_len: int = 65536, stream=None):
+        """queries: list of (Robot, Env, Constraint, start, goal, seed).
+        Returns (status [n] int32, paths: list of [len, dof] float64 or None,
+        stats: list of dicts)."""
+        n = len(queries)
+        keep = []
+        qs = (Query * max(n, 1))()
+        paths = (Path * max(n, 1))()
+        bufs = []
+        for i, (robot, env, con, start, goal, seed) in enumerate(queries):
+            a, b = _f64(start), _f64(goal)
+            keep += [a, b, con]
+            qs[i] = Query(robot.handle.value, env.handle.value, C.addressof(con),
+                          a.ctypes.data_as(_dp), b.ctypes.data_as(_dp), seed)
+            buf = np.zeros((max_len, robot.dof))
+            bufs.append(buf)
+            paths[i] = Path(max_len, 0, 0, buf.ctypes.data_as(_dp))
+        status = (C.c_int32 * max(n, 1))()
+        stats = (PlanStats * max(n, 1))()
+        strm = _stream(stream) if stream is not None else None
+        _check(lib().cp_plan_batch(self.handle, n, qs, paths, status, stats, strm))
+        st = np.array([status[i] for i in range(n)], np.int32)
+        out = [bufs[i][: paths[i].len].copy() if st[i] == CP_OK else None for i in range(n)]
+        info = [dict(rounds=stats[i].rounds, nodes=(stats[i].nodes[0], stats[i].nodes[1]),
+                     overflow=stats[i].overflow) for i in range(n)]
+        return st, out, info
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.cp_batch_destroy(self.handle)
             self.handle = None
 
 

@@ -127,7 +127,7 @@ __device__ __forceinline__ void steer(const float (&a)[NDOF], const float (&b)[N
 // One motion a -> b on this wavefront (lanes 0..W-1), projected and
 // validated.  q: this lane's projected waypoint; end: xi[W-1] broadcast.
 template <int NDOF, int KIND, int B>
-__device__ bool try_motion(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
+__device__ __forceinline__ bool try_motion(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
                            const EnvDev& env, const ConDev& con, const ProjDev& prm,
                            float* __restrict__ scratch, const float (&a)[NDOF],
                            const float (&b)[NDOF], float (&q)[NDOF], float (&end)[NDOF]) {
@@ -167,7 +167,7 @@ __device__ bool try_motion(const RobotDev* __restrict__ rob, const float4* __res
 // Append the projected segment held in the lanes' q as a new node of tree t
 // with the given parent.  Returns the slot, or -1 if the tree is full.
 template <int NDOF>
-__device__ int append_node(const PlanDev& pd, int W, int t, int parent, const float (&q)[NDOF]) {
+__device__ __forceinline__ int append_node(const PlanDev& pd, int W, int t, int parent, const float (&q)[NDOF]) {
   const int lane = threadIdx.x & 63;
   int slot = 0;
   if (lane == 0) slot = atomicAdd(&pd.ctl[kCtlCount + t], 1);
@@ -199,14 +199,13 @@ __device__ __forceinline__ bool plan_done(const PlanDev& pd) {
   return __atomic_load_n(&pd.ctl[kCtlDone], __ATOMIC_RELAXED) != 0;
 }
 
+// One tree extension of one wavefront (group g of the round): sample, grow
+// the group's tree by one motion, then towards the other tree.
 template <int NDOF, int KIND, int B>
-__global__ __launch_bounds__(kPlanBlock) void plan_round_kernel(const RobotDev* __restrict__ rob,
-                                                                const float4* __restrict__ sph,
-                                                                EnvDev env, ConDev con,
-                                                                ProjDev prm, PlanDev pd) {
-  const int g = (int)((blockIdx.x * kPlanBlock + threadIdx.x) >> 6);
+__device__ __forceinline__ void plan_extend(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
+                            const EnvDev& env, const ConDev& con, const ProjDev& prm,
+                            const PlanDev& pd, unsigned sample_base, int g) {
   const int lane = threadIdx.x & 63;
-  if (g >= pd.n_groups) return;                  // wavefront-uniform
   if (__shfl(plan_done(pd) ? 1 : 0, 0, 64)) return;
   const int W = prm.W;
   const int X = g & 1, Y = X ^ 1;               // half the wavefronts grow each tree
@@ -216,7 +215,7 @@ __global__ __launch_bounds__(kPlanBlock) void plan_round_kernel(const RobotDev* 
   // Halton sample: lane j computes coordinate j, then every lane takes all.
   float u = 0.0f;
   if (lane < NDOF) {
-    u = radical_inverse(pd.sample_base + (unsigned)g + 1u, kPrimes[lane]) + pd.shift[lane];
+    u = radical_inverse(sample_base + (unsigned)g + 1u, kPrimes[lane]) + pd.shift[lane];
     u -= floorf(u);
   }
   float qr[NDOF];
@@ -261,6 +260,16 @@ __global__ __launch_bounds__(kPlanBlock) void plan_round_kernel(const RobotDev* 
   }
 }
 
+template <int NDOF, int KIND, int B>
+__global__ __launch_bounds__(kPlanBlock) void plan_round_kernel(const RobotDev* __restrict__ rob,
+                                                                const float4* __restrict__ sph,
+                                                                EnvDev env, ConDev con,
+                                                                ProjDev prm, PlanDev pd) {
+  const int g = (int)((blockIdx.x * kPlanBlock + threadIdx.x) >> 6);
+  if (g >= pd.n_groups) return;                  // wavefront-uniform
+  plan_extend<NDOF, KIND, B>(rob, sph, env, con, prm, pd, pd.sample_base, g);
+}
+
 // Roots (start in tree 0, goal in tree 1) and counters of a fresh plan.
 __global__ void plan_init_kernel(PlanDev pd, const float* __restrict__ ends, int dof) {
   const int t = threadIdx.x;
@@ -298,6 +307,110 @@ __global__ void gather_path_kernel(PlanDev pd, const int* __restrict__ items, in
     const int p = t / dof, j = t % dof;
     const int src = mode == 1 ? (W - 2 - p) : (p + 1);
     out[(size_t)(off + p) * dof + j] = e[(size_t)src * dof + j];
+  }
+}
+
+// ------------------------------------------------------------------ batched planning
+
+// One planning query of a batch: its robot, scene, constraint and trees.
+struct ProblemDev {
+  const RobotDev* rob;
+  const float4* sph;
+  EnvDev env;
+  ConDev con;
+  PlanDev pd;
+  int dof;
+};
+
+// One round for the queries of one (DOF, constraint kind) class of the
+// batch: wavefront w works for query w / groups of the class as group
+// w % groups.  The round number comes from the device (advanced by the
+// publish kernel), so a captured sequence of rounds can be replayed.
+template <int NDOF, int KIND, int B>
+__global__ __launch_bounds__(kPlanBlock) void plan_batch_round_kernel(
+    const ProblemDev* __restrict__ probs, int n_probs, int groups, ProjDev prm,
+    const unsigned* __restrict__ round) {
+  // the wavefront index is uniform: keep it in a scalar register so the
+  // problem descriptor is read with scalar loads
+  const int w = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * kPlanBlock + threadIdx.x) >> 6));
+  const int qi = w / groups, g = w % groups;
+  if (qi >= n_probs) return;                     // wavefront-uniform
+  const ProblemDev& P = probs[qi];
+  plan_extend<NDOF, KIND, B>(P.rob, P.sph, P.env, P.con, prm, P.pd, *round * (unsigned)groups, g);
+}
+
+template <int NDOF, int KIND>
+static void launch_batch_class(int batch, unsigned nb, hipStream_t st, const ProblemDev* probs,
+                               int n, int groups, const ProjDev& prm, const unsigned* round) {
+  if (batch == 4)
+    plan_batch_round_kernel<NDOF, KIND, 4><<<nb, kPlanBlock, 0, st>>>(probs, n, groups, prm, round);
+  else
+    plan_batch_round_kernel<NDOF, KIND, 8><<<nb, kPlanBlock, 0, st>>>(probs, n, groups, prm, round);
+}
+
+static bool launch_batch_round(int dof, int kind, int batch, unsigned nb, hipStream_t st,
+                               const ProblemDev* probs, int n, int groups, const ProjDev& prm,
+                               const unsigned* round) {
+  switch (dof * 4 + kind) {
+    case 6 * 4 + KIND_NONE: launch_batch_class<6, KIND_NONE>(batch, nb, st, probs, n, groups, prm, round); return true;
+    case 6 * 4 + KIND_POSE: launch_batch_class<6, KIND_POSE>(batch, nb, st, probs, n, groups, prm, round); return true;
+    case 7 * 4 + KIND_NONE: launch_batch_class<7, KIND_NONE>(batch, nb, st, probs, n, groups, prm, round); return true;
+    case 7 * 4 + KIND_POSE: launch_batch_class<7, KIND_POSE>(batch, nb, st, probs, n, groups, prm, round); return true;
+    case 9 * 4 + KIND_NONE: launch_batch_class<9, KIND_NONE>(batch, nb, st, probs, n, groups, prm, round); return true;
+    case 9 * 4 + KIND_POSE: launch_batch_class<9, KIND_POSE>(batch, nb, st, probs, n, groups, prm, round); return true;
+    case 14 * 4 + KIND_POSE: launch_batch_class<14, KIND_POSE>(batch, nb, st, probs, n, groups, prm, round); return true;
+    case 14 * 4 + KIND_REL: launch_batch_class<14, KIND_REL>(batch, nb, st, probs, n, groups, prm, round); return true;
+    default: return false;
+  }
+}
+
+__global__ void publish_batch_kernel(ProblemDev* probs, int n_probs, unsigned* round) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_probs) {
+    int* ctl = probs[i].pd.ctl;
+    const int cap = probs[i].pd.cap;
+    ctl[kCtlPublished + 0] = min(ctl[kCtlCount + 0], cap);
+    ctl[kCtlPublished + 1] = min(ctl[kCtlCount + 1], cap);
+  }
+  if (i == 0) *round += 1u;
+}
+
+__global__ void plan_batch_init_kernel(ProblemDev* probs, int n_probs, const float* __restrict__ ends,
+                                       const int* __restrict__ ends_off) {
+  const int i = blockIdx.x;
+  if (i >= n_probs) return;
+  const PlanDev& pd = probs[i].pd;
+  const int dof = probs[i].dof;
+  const int t = threadIdx.x;
+  if (t < 2) {
+    for (int j = 0; j < dof; ++j) pd.q[t][(size_t)j * pd.cap] = ends[ends_off[i] + t * dof + j];
+    pd.parent[t][0] = -1;
+  }
+  if (t < kCtlInts) pd.ctl[t] = (t == kCtlCount || t == kCtlCount + 1 || t == kCtlPublished ||
+                                  t == kCtlPublished + 1) ? 1 : 0;
+}
+
+// Path assembly for many queries: item = (query, tree, node, mode, offset).
+__global__ void gather_batch_kernel(const ProblemDev* __restrict__ probs, const int* __restrict__ items,
+                                    int n_items, int W, const long* __restrict__ out_off,
+                                    float* __restrict__ out) {
+  const int i = blockIdx.x;
+  if (i >= n_items) return;
+  const int qi = items[5 * i + 0], tree = items[5 * i + 1], node = items[5 * i + 2],
+            mode = items[5 * i + 3], off = items[5 * i + 4];
+  const PlanDev& pd = probs[qi].pd;
+  const int dof = probs[qi].dof;
+  float* o = out + out_off[qi];
+  if (mode == 2) {
+    for (int j = threadIdx.x; j < dof; j += blockDim.x)
+      o[(size_t)off * dof + j] = pd.q[tree][(size_t)j * pd.cap + node];
+    return;
+  }
+  const float* e = pd.edge[tree] + (size_t)node * W * dof;
+  for (int t = threadIdx.x; t < (W - 1) * dof; t += blockDim.x) {
+    const int p = t / dof, j = t % dof;
+    const int src = mode == 1 ? (W - 2 - p) : (p + 1);
+    o[(size_t)(off + p) * dof + j] = e[(size_t)src * dof + j];
   }
 }
 
@@ -650,6 +763,394 @@ int plan(const cp_robot* robot, const cp_env* env, const cp_constraint* constrai
   (void)hipStreamSynchronize(nullptr);
   cp_planner_destroy(pl);
   return rc;
+}
+
+void cp_batch_opts_default(cp_batch_opts* o) {
+  if (!o) return;
+  cp_proj_params_default(&o->proj);
+  o->groups_per_query = 16;
+  o->max_rounds = 500;
+  o->capacity = 2048;
+  o->max_connect = 64;
+  o->rounds_per_graph = 4;
+}
+
+}  // extern "C"
+
+struct cp_batch {
+  cp_batch_opts opts;
+  int max_queries = 0, max_dof = 0;
+  float* q = nullptr;          // [Q][2][max_dof][cap]
+  int* parent = nullptr;       // [Q][2][cap]
+  float* edge = nullptr;       // [Q][2][cap][W][max_dof]
+  float* scratch = nullptr;    // [Q][G][W][max_dof]
+  int* ctl = nullptr;          // [Q][kCtlInts]
+  unsigned* round = nullptr;   // device round counter
+  ProblemDev* probs = nullptr; // [Q]
+  int* host_ctl = nullptr;     // pinned [Q][kCtlInts]
+  float* ends = nullptr;       // [Q][2][max_dof] endpoint scratch
+  int* ends_off = nullptr;     // [Q]
+  float* cfg_out = nullptr;
+  int* cfg_status = nullptr;   // [2Q]
+  uint8_t* cfg_col = nullptr;  // [2Q]
+  float* cfg_sd = nullptr;     // [2Q]
+  hipStream_t stream = nullptr;
+};
+
+namespace {
+
+void free_batch(cp_batch* b) {
+  if (!b) return;
+  for (void* p : {(void*)b->q, (void*)b->parent, (void*)b->edge, (void*)b->scratch, (void*)b->ctl,
+                  (void*)b->round, (void*)b->probs, (void*)b->ends, (void*)b->ends_off,
+                  (void*)b->cfg_out, (void*)b->cfg_status, (void*)b->cfg_col, (void*)b->cfg_sd})
+    if (p) (void)hipFree(p);
+  if (b->host_ctl) (void)hipHostFree(b->host_ctl);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+bool batch_kind_supported(int dof, int kind) {
+  if (dof == 6 || dof == 7 || dof == 9) return kind == KIND_NONE || kind == KIND_POSE;
+  if (dof == 14) return kind == KIND_POSE || kind == KIND_REL;
+  return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cp_batch_create(const cp_batch_opts* opts, int32_t max_queries, int32_t max_dof,
+                    cp_batch** out) {
+  try {
+    if (!out) return api_fail(CP_E_ARG, "cp_batch_create: NULL argument");
+    *out = nullptr;
+    cp_batch_opts o;
+    cp_batch_opts_default(&o);
+    if (opts) o = *opts;
+    cp_proj_params p;
+    int rc = api_params(&o.proj, &p);
+    if (rc != CP_OK) return rc;
+    o.proj = p;
+    if (max_queries < 1 || max_queries > 65536 || max_dof < 1 || max_dof > kMaxDof)
+      return api_fail(CP_E_ARG, "cp_batch_create: max_queries or max_dof out of range");
+    if (o.groups_per_query < 2 || o.capacity < 2 || o.max_rounds < 1 || o.max_connect < 0 ||
+        o.rounds_per_graph < 1 || o.rounds_per_graph > 64)
+      return api_fail(CP_E_ARG, "cp_batch_create: options out of range");
+    cp_batch* b = new (std::nothrow) cp_batch;
+    if (!b) return api_fail(CP_E_ARG, "out of host memory");
+    b->opts = o;
+    b->max_queries = max_queries;
+    b->max_dof = max_dof;
+    const size_t Q = max_queries, C = o.capacity, W = o.proj.W, D = max_dof, Gq = o.groups_per_query;
+    hipError_t e = hipMalloc((void**)&b->q, sizeof(float) * Q * 2 * D * C);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->parent, sizeof(int) * Q * 2 * C);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->edge, sizeof(float) * Q * 2 * C * W * D);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->scratch, sizeof(float) * Q * Gq * W * D);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->ctl, sizeof(int) * Q * kCtlInts);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->round, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->probs, sizeof(ProblemDev) * Q);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&b->host_ctl, sizeof(int) * Q * kCtlInts, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->ends, sizeof(float) * Q * 2 * D);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->ends_off, sizeof(int) * Q);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->cfg_out, sizeof(float) * Q * 2 * D);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->cfg_status, sizeof(int) * Q * 2);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->cfg_col, Q * 2);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->cfg_sd, sizeof(float) * Q * 2);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      free_batch(b);
+      return api_hip_fail(e, "cp_batch_create");
+    }
+    *out = b;
+    return CP_OK;
+  } catch (...) {
+    return api_fail(CP_E_ARG, "cp_batch_create: unexpected exception");
+  }
+}
+
+void cp_batch_destroy(cp_batch* b) { free_batch(b); }
+
+int cp_plan_batch(cp_batch* b, int32_t n, const cp_query* queries, cp_path* paths,
+                  int32_t* status, cp_plan_stats* stats, void* caller_stream) {
+  try {
+    if (!b || !queries || !paths || !status) return api_fail(CP_E_ARG, "cp_plan_batch: NULL argument");
+    if (n < 0 || n > b->max_queries) return api_fail(CP_E_ARG, "cp_plan_batch: %d queries (max %d)", n, b->max_queries);
+    if (n == 0) return CP_OK;
+    const cp_batch_opts& o = b->opts;
+    const cp_proj_params& pp = o.proj;
+    const int W = pp.W, D = b->max_dof, Gq = o.groups_per_query;
+    const size_t C = o.capacity;
+    hipError_t he = hipStreamSynchronize((hipStream_t)caller_stream);
+    if (he != hipSuccess) return api_hip_fail(he, "cp_plan_batch");
+    hipStream_t st = b->stream;
+    ProjDev prm;
+    prm.W = W;
+    prm.max_iters = pp.max_iters;
+    prm.tau = (float)pp.tau;
+    prm.tau_sm = (float)pp.tau_sm;
+    prm.tau_task = (float)pp.tau_task;
+    prm.alpha = (float)pp.alpha;
+    prm.lambda2 = (float)(pp.lambda * pp.lambda);
+    const double tol = pp.tau + pp.tau_sm;
+
+    // queries sorted by (DOF, constraint kind) class; slot k of the pools
+    // and of the problem table serves query perm[k]
+    std::vector<int> perm(n), cls(n);
+    for (int i = 0; i < n; ++i) {
+      if (!queries[i].robot) return api_fail(CP_E_ARG, "query %d: NULL robot", i);
+      const int kind = queries[i].constraint ? queries[i].constraint->kind : CP_CON_NONE;
+      cls[i] = queries[i].robot->host.dof * 4 + kind;
+      perm[i] = i;
+    }
+    std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return cls[x] < cls[y]; });
+    std::vector<cp_query> sq(n);
+    for (int k = 0; k < n; ++k) sq[k] = queries[perm[k]];
+    std::vector<int32_t> st_k(n, CP_OK);
+    std::vector<cp_plan_stats> stats_k(n);
+    std::vector<cp_path*> path_k(n);
+    for (int k = 0; k < n; ++k) path_k[k] = &paths[perm[k]];
+    queries = sq.data();
+    int32_t* const status_out = status;
+    status = st_k.data();
+
+    // per-query descriptors, endpoint limits
+    std::vector<ProblemDev> probs(n);
+    std::vector<float> ends((size_t)n * 2 * D, 0.0f);
+    std::vector<int> ends_off(n);
+    for (int i = 0; i < n; ++i) {
+      const cp_query& qq = queries[i];
+      status[i] = CP_OK;
+      std::memset(&stats_k[i], 0, sizeof stats_k[i]);
+      path_k[i]->len = 0;
+      if (!qq.robot || !qq.env || !qq.start || !qq.goal) return api_fail(CP_E_ARG, "query %d: NULL member", perm[i]);
+      const int dof = qq.robot->host.dof;
+      if (dof > D) return api_fail(CP_E_ARG, "query %d: dof %d above the batch's %d", perm[i], dof, D);
+      path_k[i]->dof = dof;
+      ProblemDev& P = probs[i];
+      std::memset(&P, 0, sizeof P);
+      int rc = api_constraint(qq.constraint, qq.robot, &P.con);
+      if (rc != CP_OK) return rc;
+      if (!batch_kind_supported(dof, P.con.kind))
+        return api_fail(CP_E_UNSUPPORTED, "query %d: dof %d with constraint kind %d", perm[i], dof, P.con.kind);
+      P.rob = qq.robot->dev;
+      P.sph = qq.robot->spheres;
+      P.env = qq.env->view;
+      P.dof = dof;
+      PlanDev& pd = P.pd;
+      for (int t = 0; t < 2; ++t) {
+        pd.q[t] = b->q + ((size_t)i * 2 + t) * D * C;
+        pd.parent[t] = b->parent + ((size_t)i * 2 + t) * C;
+        pd.edge[t] = b->edge + ((size_t)i * 2 + t) * C * W * D;
+      }
+      pd.scratch = b->scratch + (size_t)i * Gq * W * D;
+      pd.ctl = b->ctl + (size_t)i * kCtlInts;
+      pd.cap = o.capacity;
+      pd.n_groups = Gq;
+      pd.max_connect = o.max_connect;
+      pd.step = (float)((W - 1) * pp.tau);
+      pd.connect2 = (float)(tol * tol);
+      uint64_t state = qq.seed;
+      for (int j = 0; j < kMaxDof; ++j)
+        pd.shift[j] = (float)((double)(splitmix64(state) >> 11) * (1.0 / 9007199254740992.0));
+      ends_off[i] = i * 2 * D;
+      for (int j = 0; j < dof; ++j) {
+        ends[(size_t)i * 2 * D + j] = (float)qq.start[j];
+        ends[(size_t)i * 2 * D + dof + j] = (float)qq.goal[j];
+        if (!(qq.start[j] >= qq.robot->host.lo[j] && qq.start[j] <= qq.robot->host.hi[j])) status[i] = CP_E_START;
+        if (!(qq.goal[j] >= qq.robot->host.lo[j] && qq.goal[j] <= qq.robot->host.hi[j]) && status[i] == CP_OK) status[i] = CP_E_GOAL;
+      }
+    }
+    he = hipMemcpyAsync(b->ends, ends.data(), sizeof(float) * ends.size(), hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(b->ends_off, ends_off.data(), sizeof(int) * n, hipMemcpyHostToDevice, st);
+    // endpoints on the manifold and collision-free (device checks per query)
+    for (int i = 0; i < n && he == hipSuccess; ++i) {
+      const cp_query& qq = queries[i];
+      bool sup = false;
+      he = launch_project_configs(probs[i].dof, qq.robot->dev, probs[i].con, 2, b->ends + (size_t)i * 2 * D,
+                                  b->cfg_out + (size_t)i * 2 * D, b->cfg_status + 2 * i,
+                                  (float)pp.tau_task, 0, 1.0f, 0.0f, st, &sup);
+      if (he == hipSuccess)
+        he = launch_fk_cc(qq.robot->dev, qq.robot->spheres, qq.env->view, 2, b->ends + (size_t)i * 2 * D,
+                          b->cfg_col + 2 * i, b->cfg_sd + 2 * i, false, 4, st);
+    }
+    std::vector<int> ok_h(2 * n);
+    std::vector<float> sd_h(2 * n);
+    if (he == hipSuccess) he = hipMemcpyAsync(ok_h.data(), b->cfg_status, sizeof(int) * 2 * n, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(sd_h.data(), b->cfg_sd, sizeof(float) * 2 * n, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return api_hip_fail(he, "cp_plan_batch endpoint checks");
+    std::vector<int> active(n, 0);
+    for (int i = 0; i < n; ++i) {
+      if (status[i] == CP_OK && !(ok_h[2 * i] && sd_h[2 * i] > 0.0f)) status[i] = CP_E_START;
+      if (status[i] == CP_OK && !(ok_h[2 * i + 1] && sd_h[2 * i + 1] > 0.0f)) status[i] = CP_E_GOAL;
+      active[i] = status[i] == CP_OK;
+    }
+    // problems whose endpoints fail are given a zero group budget by marking them done
+    he = hipMemcpyAsync(b->probs, probs.data(), sizeof(ProblemDev) * n, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) {
+      plan_batch_init_kernel<<<n, 64, 0, st>>>(b->probs, n, b->ends, b->ends_off);
+      he = hipGetLastError();
+    }
+    for (int i = 0; i < n && he == hipSuccess; ++i) {
+      double dsg = 0.0;
+      for (int j = 0; j < probs[i].dof; ++j) dsg += (queries[i].start[j] - queries[i].goal[j]) * (queries[i].start[j] - queries[i].goal[j]);
+      const bool trivial = active[i] && std::sqrt(dsg) < tol;
+      if (!active[i] || trivial) {   // nothing to search: done flag set, connection at the roots
+        const int done_block[4] = {1, 0, 0, 0};
+        he = hipMemcpyAsync(b->ctl + (size_t)i * kCtlInts + kCtlDone, done_block, sizeof done_block, hipMemcpyHostToDevice, st);
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+      }
+    }
+    const unsigned zero = 0;
+    if (he == hipSuccess) he = hipMemcpyAsync(b->round, &zero, sizeof zero, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return api_hip_fail(he, "cp_plan_batch init");
+
+    // capture R rounds in a graph (per round: one launch per class, then the
+    // publish kernel), replay until every query is done
+    std::vector<std::pair<int, int>> ranges;   // [begin, end) of each class
+    for (int k = 0; k < n;) {
+      int e2 = k;
+      while (e2 < n && probs[e2].dof * 4 + probs[e2].con.kind == probs[k].dof * 4 + probs[k].con.kind) ++e2;
+      ranges.push_back({k, e2});
+      k = e2;
+    }
+    const int R = o.rounds_per_graph;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    he = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (he == hipSuccess) {
+      for (int r = 0; r < R; ++r) {
+        for (const auto& rg : ranges) {
+          const int cnt = rg.second - rg.first;
+          const long waves = (long)cnt * Gq;
+          const unsigned nb = (unsigned)((waves * 64 + kPlanBlock - 1) / kPlanBlock);
+          launch_batch_round(probs[rg.first].dof, probs[rg.first].con.kind, pp.sphere_batch, nb, st,
+                             b->probs + rg.first, cnt, Gq, prm, b->round);
+        }
+        publish_batch_kernel<<<(n + 255) / 256, 256, 0, st>>>(b->probs, n, b->round);
+      }
+      he = hipStreamEndCapture(st, &graph);
+    }
+    if (he == hipSuccess) he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (he != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return api_hip_fail(he, "cp_plan_batch graph");
+    }
+    int rounds = 0;
+    std::vector<int> done_round(n, -1);
+    while (rounds < o.max_rounds) {
+      he = hipGraphLaunch(exec, st);
+      if (he == hipSuccess) he = hipMemcpyAsync(b->host_ctl, b->ctl, sizeof(int) * n * kCtlInts, hipMemcpyDeviceToHost, st);
+      if (he == hipSuccess) he = hipStreamSynchronize(st);
+      if (he != hipSuccess) break;
+      rounds += R;
+      bool all = true;
+      for (int i = 0; i < n; ++i) {
+        const int* hc = b->host_ctl + (size_t)i * kCtlInts;
+        if (hc[kCtlDone] && done_round[i] < 0) done_round[i] = rounds;
+        all = all && (hc[kCtlDone] || hc[kCtlOverflow]);
+      }
+      if (all) break;
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (he != hipSuccess) return api_hip_fail(he, "cp_plan_batch rounds");
+
+    // paths of the solved queries
+    std::vector<int> par((size_t)n * 2 * C);
+    he = hipMemcpyAsync(par.data(), b->parent, sizeof(int) * par.size(), hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return api_hip_fail(he, "cp_plan_batch paths");
+    std::vector<int> items;
+    std::vector<long> out_off(n, 0);
+    std::vector<size_t> lens(n, 0);
+    long total = 0;
+    for (int i = 0; i < n; ++i) {
+      const int* hc = b->host_ctl + (size_t)i * kCtlInts;
+      stats_k[i].rounds = done_round[i] >= 0 ? done_round[i] : rounds;
+      stats_k[i].nodes[0] = std::min(hc[kCtlCount + 0], o.capacity);
+      stats_k[i].nodes[1] = std::min(hc[kCtlCount + 1], o.capacity);
+      stats_k[i].overflow = hc[kCtlOverflow];
+      if (status[i] != CP_OK) continue;
+      if (!hc[kCtlDone]) {
+        status[i] = hc[kCtlOverflow] ? CP_E_CAPACITY : CP_NO_SOLUTION;
+        continue;
+      }
+      const int dof = probs[i].dof;
+      const int X = hc[kCtlConn + 0], a = hc[kCtlConn + 1], c2 = hc[kCtlConn + 2];
+      const int n0 = X == 0 ? a : c2, n1 = X == 0 ? c2 : a;
+      const int* p0 = par.data() + ((size_t)i * 2 + 0) * C;
+      const int* p1 = par.data() + ((size_t)i * 2 + 1) * C;
+      std::vector<int> chain0, chain1;
+      for (int v = n0; v > 0; v = p0[v]) chain0.push_back(v);
+      std::reverse(chain0.begin(), chain0.end());
+      for (int v = n1; v > 0; v = p1[v]) chain1.push_back(v);
+      const size_t len = 1 + chain0.size() * (W - 1) + 1 + chain1.size() * (W - 1);
+      lens[i] = len;
+      path_k[i]->len = (int32_t)len;
+      if ((size_t)path_k[i]->capacity < len || !path_k[i]->q) {
+        status[i] = CP_E_CAPACITY;
+        continue;
+      }
+      out_off[i] = total;
+      total += (long)len * dof;
+      int off = 1;
+      for (int v : chain0) { items.insert(items.end(), {i, 0, v, 0, off}); off += W - 1; }
+      items.insert(items.end(), {i, 1, n1, 2, off});
+      off += 1;
+      for (int v : chain1) { items.insert(items.end(), {i, 1, v, 1, off}); off += W - 1; }
+    }
+    if (total > 0) {
+      float* d_out = nullptr;
+      int* d_items = nullptr;
+      long* d_off = nullptr;
+      he = hipMalloc((void**)&d_out, sizeof(float) * total);
+      if (he == hipSuccess) he = hipMalloc((void**)&d_items, sizeof(int) * items.size());
+      if (he == hipSuccess) he = hipMalloc((void**)&d_off, sizeof(long) * n);
+      if (he == hipSuccess) he = hipMemcpyAsync(d_items, items.data(), sizeof(int) * items.size(), hipMemcpyHostToDevice, st);
+      if (he == hipSuccess) he = hipMemcpyAsync(d_off, out_off.data(), sizeof(long) * n, hipMemcpyHostToDevice, st);
+      const int n_items = (int)items.size() / 5;
+      if (he == hipSuccess && n_items > 0) {
+        gather_batch_kernel<<<n_items, 64, 0, st>>>(b->probs, d_items, n_items, W, d_off, d_out);
+        he = hipGetLastError();
+      }
+      std::vector<float> pts(total);
+      if (he == hipSuccess) he = hipMemcpyAsync(pts.data(), d_out, sizeof(float) * total, hipMemcpyDeviceToHost, st);
+      if (he == hipSuccess) he = hipStreamSynchronize(st);
+      if (d_out) (void)hipFree(d_out);
+      if (d_items) (void)hipFree(d_items);
+      if (d_off) (void)hipFree(d_off);
+      if (he != hipSuccess) return api_hip_fail(he, "cp_plan_batch gather");
+      for (int i = 0; i < n; ++i) {
+        if (status[i] != CP_OK || lens[i] == 0) continue;
+        const int dof = probs[i].dof;
+        const size_t len = lens[i];
+        double* pq = path_k[i]->q;
+        for (size_t r = 1; r + 1 < len; ++r)
+          for (int j = 0; j < dof; ++j) pq[r * dof + j] = (double)pts[out_off[i] + r * dof + j];
+        std::memcpy(pq, queries[i].start, sizeof(double) * dof);
+        std::memcpy(pq + (len - 1) * dof, queries[i].goal, sizeof(double) * dof);
+      }
+    }
+    // queries whose start and goal are within reach of each other
+    for (int i = 0; i < n; ++i) {
+      if (status[i] != CP_OK || lens[i] != 0) continue;
+      const int dof = probs[i].dof;
+      path_k[i]->len = 2;
+      if (path_k[i]->capacity < 2 || !path_k[i]->q) { status[i] = CP_E_CAPACITY; continue; }
+      std::memcpy(path_k[i]->q, queries[i].start, sizeof(double) * dof);
+      std::memcpy(path_k[i]->q + dof, queries[i].goal, sizeof(double) * dof);
+    }
+    for (int k = 0; k < n; ++k) {
+      status_out[perm[k]] = st_k[k];
+      if (stats) stats[perm[k]] = stats_k[k];
+    }
+    return CP_OK;
+  } catch (...) {
+    return api_fail(CP_E_ARG, "cp_plan_batch: unexpected exception");
+  }
 }
 
 }  // extern "C"

@@ -1,0 +1,132 @@
+"""Batched planning of uneven queries on the GPU.
+
+One call plans queries that differ in robot, DOF, scene and constraint kind;
+every returned path is judged by the FP64 oracle on the path itself (limits,
+task error, spacing, clearance outside the 1e-5 m band, exact endpoints), and
+statuses are reported in the caller's query order whatever the internal
+grouping by (DOF, constraint kind).  Like single-query planning, end-to-end
+batched planning is parity unpinned against the paper; these checks pin it.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2505_06791_amd import inputs as I
+from tests.helpers import manifold_starts
+from tests.test_gpu_plan import _check_path
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_06791_amd import cprrtc
+    cprrtc.lib()
+    return cprrtc
+
+
+def six_dof(seed):
+    """6-DOF arm, 20 spheres, 10 boxes, no task constraint."""
+    return dict(robot=I.make_arm(seed, 6, 20), env=I.make_boxes(seed + 1, 10),
+                constraint=I.no_constraint(), tau_task=1e-3)
+
+
+def _queries(G, specs):
+    """specs: list of (workload dict, seed).  Returns the query tuples, the
+    workloads and the (start, goal) pairs."""
+    qs, ws, ends = [], [], []
+    for w, seed in specs:
+        e = manifold_starts(w, 2, seed + 5).astype(np.float64)
+        robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
+        qs.append((robot, env, con, e[0], e[1], seed))
+        ws.append(w)
+        ends.append(e)
+    return qs, ws, ends
+
+
+def test_uneven_batch_paths_pass_oracle_revalidation(G):
+    specs = ([(I.workload("plain", s), s) for s in range(1000, 1004)]
+             + [(six_dof(s), s) for s in (1500, 1501)]
+             + [(I.workload("mobile", 3000), 3000)]
+             + [(I.workload("plain", 1004), 1004)])          # classes interleaved on purpose
+    qs, ws, ends = _queries(G, specs)
+    bp = G.BatchPlanner(len(qs), 9, G.batch_opts(groups_per_query=32, max_rounds=400,
+                                                 capacity=4096, tau_task=1e-3))
+    status, paths, stats = bp.plan(qs)
+    print("status", status.tolist(), "rounds", [s["rounds"] for s in stats], flush=True)
+    for i, (w, e) in enumerate(zip(ws, ends)):
+        assert status[i] in (G.CP_OK, G.CP_NO_SOLUTION, G.CP_E_CAPACITY)
+        if status[i] == G.CP_OK:
+            assert paths[i].shape[1] == w["robot"]["dof"]
+            _check_path(w, paths[i], e[0], e[1], w["tau_task"])
+    # the unconstrained 6-DOF and plain upright queries are easy
+    assert (status[:6] == G.CP_OK).sum() >= 5, status
+    # a second call on the same handle starts from a clean state
+    status2, paths2, _ = bp.plan(qs[:3])
+    for i in range(3):
+        if status2[i] == G.CP_OK:
+            _check_path(ws[i], paths2[i], ends[i][0], ends[i][1], 1e-3)
+    assert (status2 == G.CP_OK).sum() >= 2
+
+
+def test_batch_statuses_follow_the_caller_order(G):
+    """Endpoint errors and trivial queries, mixed with real ones of two
+    classes: each status lands on its own query."""
+    specs = [(I.workload("plain", 1010), 1010), (six_dof(1510), 1510),
+             (I.workload("plain", 1011), 1011)]
+    qs, ws, ends = _queries(G, specs)
+    robot, env, con, s0, g0, _ = qs[0]
+    bad = s0.copy()
+    bad[0] = 10.0                                  # outside the joint limits
+    trivial = (robot, env, con, s0, s0.copy(), 5)  # start == goal
+    qs2 = [qs[1], (robot, env, con, bad, g0, 3), qs[0], trivial,
+           (robot, env, con, s0, bad, 4), qs[2]]
+    bp = G.BatchPlanner(8, 7, G.batch_opts(groups_per_query=32, max_rounds=400, capacity=4096))
+    status, paths, stats = bp.plan(qs2)
+    print("status", status.tolist(), flush=True)
+    assert status[1] == G.CP_E_START
+    assert status[4] == G.CP_E_GOAL
+    assert status[3] == G.CP_OK and paths[3].shape == (2, 7)
+    assert np.array_equal(paths[3][0], s0) and np.array_equal(paths[3][1], s0)
+    for i, (w, e) in ((0, (six_dof(1510), ends[1])), (2, (ws[0], ends[0])), (5, (ws[2], ends[2]))):
+        if status[i] == G.CP_OK:
+            assert paths[i].shape[1] == w["robot"]["dof"]
+            _check_path(w, paths[i], e[0], e[1], 1e-3)
+    assert (status[[0, 2, 5]] == G.CP_OK).sum() >= 2
+
+
+def test_batch_dual_arm_relative_pose_runs(G):
+    """A 14-DOF relative-pose query alongside a 7-DOF one: the dual-arm class
+    runs in the same replayed rounds; any path it returns passes the oracle."""
+    wd = I.workload("dual", 4000)
+    specs = [(wd, 4000), (I.workload("plain", 1020), 1020)]
+    qs, ws, ends = _queries(G, specs)
+    bp = G.BatchPlanner(2, 14, G.batch_opts(groups_per_query=32, max_rounds=64, capacity=4096,
+                                            tau_task=1e-4))
+    status, paths, stats = bp.plan(qs)
+    print("status", status.tolist(), stats, flush=True)
+    for i in range(2):
+        assert status[i] in (G.CP_OK, G.CP_NO_SOLUTION, G.CP_E_CAPACITY)
+        if status[i] == G.CP_OK:
+            _check_path(ws[i], paths[i], ends[i][0], ends[i][1], 1e-4)
+    assert stats[0]["nodes"][0] >= 1 and stats[0]["nodes"][1] >= 1
+
+
+def test_batch_rejects_bad_arguments(G):
+    w = I.workload("plain", 1000)
+    robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
+    e = np.zeros(7)
+    bp = G.BatchPlanner(2, 7, G.batch_opts(max_rounds=4))
+    with pytest.raises(G.CprrtcError) as ex:        # more queries than the handle holds
+        bp.plan([(robot, env, con, e, e, 0)] * 3)
+    assert ex.value.code == G.CP_E_ARG
+    w9 = I.workload("mobile", 3000)
+    r9 = G.Robot(w9["robot"])
+    with pytest.raises(G.CprrtcError) as ex:        # DOF above the handle's maximum
+        bp.plan([(r9, G.Env(w9["env"]), G.constraint(w9["constraint"]), np.zeros(9), np.zeros(9), 0)])
+    assert ex.value.code == G.CP_E_ARG
+    status, paths, stats = bp.plan([])
+    assert len(status) == 0
