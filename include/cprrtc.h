@@ -246,6 +246,34 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
                          int32_t* d_status, int32_t* d_iters, uint64_t* d_work, int32_t flags,
                          void* stream);
 
+/* ------------------------------------------------------------ launch autotuning */
+
+/* Picks the launch shape for a workload by measurement: for every candidate
+ * (W in {32, 64} if flags has CP_TUNE_W, else the W of *params; sphere batch
+ * in {4, 8}) runs project_validate_motions once untimed and reps times timed
+ * on the caller's sample motions (d_q_from, d_q_to: [n_motions][dof] device
+ * floats, steered for the W of *params; for another W the end points are
+ * moved along the same direction by (W' - 1) / (W - 1) so the initial
+ * spacing is unchanged) and keeps the candidate with the most waypoints per
+ * second over motions whose projection succeeded (W - 1 each).  *params: in,
+ * the base parameters; out, the chosen W and sphere_batch (other fields
+ * unchanged).  report: nullable, one entry per candidate timed.  Synchronous
+ * on stream; allocates its own scratch (n_motions x 64 x dof floats).
+ * Errors as project_validate_motions, CP_E_ARG for n_motions < 1 or reps
+ * outside 1..1000. */
+enum { CP_TUNE_W = 1 };
+typedef struct cp_tune_report {
+  int32_t n;                   /* candidates timed */
+  int32_t W[4];
+  int32_t sphere_batch[4];
+  double ms[4];                /* mean time per call */
+  double waypoints_per_s[4];
+} cp_tune_report;
+int cp_autotune(const cp_robot* robot, const cp_env* env, const cp_constraint* constraint,
+                cp_proj_params* params, int32_t n_motions, const float* d_q_from,
+                const float* d_q_to, int32_t flags, int32_t reps, cp_tune_report* report,
+                void* stream);
+
 /* ------------------------------------------------------------ planning */
 
 /* Constrained bidirectional RRT-Connect (Section III): two trees rooted at

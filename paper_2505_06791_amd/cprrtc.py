@@ -22,6 +22,7 @@ MOTION_VALID, MOTION_PROJ_FAIL, MOTION_COLLISION = 0, 1, 2
 NO_EARLY_EXIT = 1
 NO_CULL = 2
 WARM_NO_FALLBACK = 4
+CP_TUNE_W = 1
 WORK_SLOTS = 8
 
 _dp = C.POINTER(C.c_double)
@@ -71,6 +72,11 @@ class PlanStats(C.Structure):
     _fields_ = [("rounds", C.c_int32), ("nodes", C.c_int32 * 2), ("overflow", C.c_int32)]
 
 
+class TuneReport(C.Structure):
+    _fields_ = [("n", C.c_int32), ("W", C.c_int32 * 4), ("sphere_batch", C.c_int32 * 4),
+                ("ms", C.c_double * 4), ("waypoints_per_s", C.c_double * 4)]
+
+
 class BatchOpts(C.Structure):
     _fields_ = [("proj", ProjParams), ("groups_per_query", C.c_int32), ("max_rounds", C.c_int32),
                 ("capacity", C.c_int32), ("max_connect", C.c_int32),
@@ -113,6 +119,8 @@ def lib():
                               C.POINTER(Path), C.POINTER(PlanStats), vp]
         L.plan.argtypes = [vp, vp, C.POINTER(Constraint), _dp, _dp, C.c_uint64,
                            C.POINTER(PlanOpts), C.POINTER(Path)]
+        L.cp_autotune.argtypes = [vp, vp, C.POINTER(Constraint), C.POINTER(ProjParams), C.c_int32,
+                                  vp, vp, C.c_int32, C.c_int32, C.POINTER(TuneReport), vp]
         L.cp_batch_opts_default.argtypes = [C.POINTER(BatchOpts)]
         L.cp_batch_create.argtypes = [C.POINTER(BatchOpts), C.c_int32, C.c_int32, C.POINTER(vp)]
         L.cp_batch_destroy.argtypes = [vp]
@@ -287,6 +295,21 @@ def project_configs(robot: Robot, con: Constraint, q_in, q_out, status, tol=1e-5
     _check(lib().project_configs(robot.handle, C.byref(con), n, _dev(q_in, torch.float32),
                                  _dev(q_out, torch.float32), _dev(status, torch.int32), tol,
                                  max_iters, alpha, lam, _stream(stream)))
+
+
+def autotune(robot: Robot, env: Env, con: Constraint, params: ProjParams, q_from, q_to,
+             tune_W: bool = False, reps: int = 3, stream=None):
+    """Times project_validate_motions for each candidate launch shape on the
+    sample motions; returns (chosen ProjParams, list of candidate dicts)."""
+    import torch
+    p = ProjParams.from_buffer_copy(params)
+    rep = TuneReport()
+    _check(lib().cp_autotune(robot.handle, env.handle, C.byref(con), C.byref(p), q_from.shape[0],
+                             _dev(q_from, torch.float32), _dev(q_to, torch.float32),
+                             CP_TUNE_W if tune_W else 0, reps, C.byref(rep), _stream(stream)))
+    cands = [dict(W=rep.W[i], sphere_batch=rep.sphere_batch[i], ms=rep.ms[i],
+                  waypoints_per_s=rep.waypoints_per_s[i]) for i in range(rep.n)]
+    return p, cands
 
 
 # ------------------------------------------------------------------ planning
