@@ -70,6 +70,8 @@ def parse():
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--plan-queries", type=int, default=100,
                     help="planning queries per scene for the p50 plan time (0 = skip)")
+    ap.add_argument("--batch-queries", type=int, default=512,
+                    help="uneven queries planned in one batch and one by one (0 = skip)")
     return ap.parse_args()
 
 
@@ -121,6 +123,53 @@ def plan_bench(G, I, torch, name, seeds, tau_task):
         rounds.append(st["rounds"])
     return dict(queries=n, p50_ms=float(np.median(times)), p90_ms=float(np.percentile(times, 90)),
                 success=ok / max(n, 1), mean_rounds=float(np.mean(rounds)))
+
+
+def batch_bench(G, I, torch, n, base=3000):
+    """Uneven queries (DOF 6/7/9, 10-1000 primitives, three constraint kinds)
+    planned in one cp_plan_batch call and, for comparison, one cp_plan call
+    each in sequence.  Both get the same extension budget per query (32
+    wavefronts x 800 rounds batched, 256 x 100 sequential) and tree
+    capacity; query preparation and tree allocation are excluded."""
+    queries = []
+    for s in range(base, base + n):
+        w = I.uneven_query(s)
+        robot, env, con, start, goal = gpu_query(G, I, torch, w, s)
+        if start is not None:
+            queries.append((robot, env, con, start, goal, s))
+    print(f"batch: {len(queries)} queries prepared", file=sys.stderr, flush=True)
+    cap = 16384
+    bp = G.BatchPlanner(len(queries), 9, G.batch_opts(groups_per_query=32, max_rounds=800,
+                                                      capacity=cap))
+    bp.plan(queries[:8])                          # module load and first-touch, untimed
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_b, _, info = bp.plan(queries)
+    batch_ms = (time.perf_counter() - t0) * 1e3
+    print(f"batch: batched {batch_ms:.0f} ms, {(st_b == G.CP_OK).sum()} solved",
+          file=sys.stderr, flush=True)
+    del bp
+    seq_ms, ok_s = 0.0, 0
+    for robot, env, con, start, goal, s in queries:
+        pl = G.Planner(robot, G.plan_opts(n_groups=256, max_rounds=100, capacity=cap))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            rc, _, _ = pl.plan(env, con, start, goal, s)
+        except G.CprrtcError as e:      # a tree filled up: the query is unsolved
+            if e.code != G.CP_E_CAPACITY:
+                raise
+            rc = e.code
+        seq_ms += (time.perf_counter() - t0) * 1e3
+        ok_s += rc == G.CP_OK
+        del pl
+        if (s - base) % 128 == 127:
+            print(f"batch: sequential through seed {s}, {seq_ms:.0f} ms", file=sys.stderr, flush=True)
+    return dict(queries=len(queries), batched_ms=batch_ms,
+                batched_solved=int((st_b == G.CP_OK).sum()),
+                batched_rounds=int(max(i["rounds"] for i in info)),
+                sequential_ms=seq_ms, sequential_solved=ok_s,
+                speedup=seq_ms / batch_ms)
 
 
 def cpu_plan_baseline(I, name, seeds, tau_task, target_s):
@@ -341,6 +390,8 @@ def main():
             if args.cpu_seconds > 0:
                 entry["cpu_baseline"] = cpu_plan_baseline(I, name, seeds, tt, args.cpu_seconds / 2)
             result["plan"][name] = entry
+    if args.batch_queries > 0:
+        result["batch"] = batch_bench(G, I, torch, args.batch_queries)
     if args.cpu_seconds > 0:
         result["cpu_baseline"] = cpu_baseline(I, w, args.cpu_seconds)
     print(json.dumps(result), flush=True)

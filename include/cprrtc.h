@@ -325,6 +325,12 @@ void cp_planner_destroy(cp_planner* planner);
 int cp_plan(cp_planner* planner, const cp_env* env, const cp_constraint* constraint,
             const double* start, const double* goal, uint64_t seed, cp_path* out,
             cp_plan_stats* stats, void* stream);
+/* The search tree `tree` (0: start, 1: goal) as the last cp_plan left it:
+ * *count nodes (capped at the capacity), q [count][dof] host doubles (the
+ * device floats widened), parent [count] (-1 for the root).  Returns
+ * CP_E_CAPACITY with *count set when capacity < *count.  Synchronous. */
+int cp_planner_tree(const cp_planner* planner, int32_t tree, int32_t capacity, double* q,
+                    int32_t* parent, int32_t* count);
 /* One-shot form: creates a planner with opts (NULL = defaults), plans on the
  * default stream, destroys it. */
 int plan(const cp_robot* robot, const cp_env* env, const cp_constraint* constraint,

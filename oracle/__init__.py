@@ -264,6 +264,34 @@ def plan(robot: Robot, env: Env, con: Constraint, prm, start, goal, seed, max_sa
     return st, (path[: plen.value].copy() if st == 1 else None), nodes
 
 
+def plan_rounds(robot: Robot, env: Env, con: Constraint, prm, start, goal, seed, n_groups, rounds,
+                capacity=4096, max_connect=64):
+    """Round-synchronous FP64 planner (the GPU planner's schedule, one
+    extension after another).  Returns dict(trees=[(q [count, dof],
+    parent [count], band [count]) for tree 0, 1], found_round, band_round,
+    band_extensions, status)."""
+    start = _f64(start)
+    goal = _f64(goal)
+    n = robot.dof
+    q = [np.zeros((capacity, n)), np.zeros((capacity, n))]
+    par = [np.zeros(capacity, np.int32), np.zeros(capacity, np.int32)]
+    band = [np.zeros(capacity, np.int32), np.zeros(capacity, np.int32)]
+    counts = np.zeros(2, np.int32)
+    found, bround, bext = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    L = lib()
+    L.or_plan_rounds.restype = C.c_int32
+    st = L.or_plan_rounds(C.byref(robot.s), C.byref(env.s), C.byref(con.s), C.byref(prm),
+                          _ptr(start), _ptr(goal), C.c_uint64(seed), C.c_int32(n_groups),
+                          C.c_int32(rounds), C.c_int32(capacity), C.c_int32(max_connect),
+                          _ptr(q[0]), _ptr(par[0], _ip), _ptr(band[0], _ip),
+                          _ptr(q[1]), _ptr(par[1], _ip), _ptr(band[1], _ip),
+                          _ptr(counts, _ip), C.byref(found), C.byref(bround), C.byref(bext))
+    trees = [(q[t][: counts[t]].copy(), par[t][: counts[t]].copy(), band[t][: counts[t]].copy())
+             for t in range(2)]
+    return dict(trees=trees, found_round=found.value, band_round=bround.value,
+                band_extensions=bext.value, status=st)
+
+
 def path_report(robot: Robot, env: Env, con: Constraint, path):
     """(worst task error, worst spacing, min signed distance, inside limits)."""
     path = _f64(path)

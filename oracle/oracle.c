@@ -781,6 +781,129 @@ int32_t or_plan(const or_robot* r, const or_env* env, const or_constraint* c, co
   return status;
 }
 
+/* Nearest node among the first `count` nodes (lowest index on ties) and the
+ * distance gap to the runner-up (DBL_MAX with a single node). */
+static int tree_nearest_gap(const or_tree* t, int count, const double* x, int n, double* gap) {
+  int best = 0;
+  double b1 = DBL_MAX, b2 = DBL_MAX;
+  for (int i = 0; i < count; ++i) {
+    const double d = dist_sq(t->q + (size_t)i * n, x, n);
+    if (d < b1) { b2 = b1; b1 = d; best = i; }
+    else if (d < b2) b2 = d;
+  }
+  *gap = b2 == DBL_MAX ? DBL_MAX : sqrt(b2) - sqrt(b1);
+  return best;
+}
+
+/* motion_ok with the closeness of its decisions: *margin = min(projection
+ * margin, |minimum signed distance over waypoints 1..W-1|). */
+static int motion_ok_margin(const or_robot* r, const or_env* env, const or_constraint* c,
+                            const or_params* p, const double* a, const double* b, double* xi,
+                            double* margin) {
+  const int n = r->dof, W = p->W;
+  for (int k = 0; k < W; ++k) {
+    const double s = (double)k / (double)(W - 1);
+    for (int j = 0; j < n; ++j) xi[(size_t)k * n + j] = a[j] + s * (b[j] - a[j]);
+  }
+  int32_t it;
+  double mg = DBL_MAX;
+  const int proj = or_parallel_project(r, c, p, xi, &it, &mg, NULL);
+  *margin = mg;
+  if (!proj) return 0;
+  double msd = DBL_MAX;
+  for (int k = 1; k < W; ++k) msd = fmin(msd, or_config_min_sd(r, env, xi + (size_t)k * n));
+  *margin = fmin(mg, fabs(msd));
+  return msd > 0.0;
+}
+
+int32_t or_plan_rounds(const or_robot* r, const or_env* env, const or_constraint* c,
+                       const or_params* p, const double* start, const double* goal, uint64_t seed,
+                       int32_t n_groups, int32_t rounds, int32_t capacity, int32_t max_connect,
+                       double* q0, int32_t* parent0, int32_t* band0, double* q1, int32_t* parent1,
+                       int32_t* band1, int32_t* counts, int32_t* found_round, int32_t* band_round,
+                       int32_t* band_extensions) {
+  static const uint32_t primes[16] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53};
+  const double kBandProj = 1e-5, kBandDist = 1e-4, kBandSample = 1e-5;
+  const int n = r->dof, W = p->W;
+  const double step = (W - 1) * p->tau, tol = p->tau + p->tau_sm;
+  or_tree tr[2];
+  int32_t* flag[2] = {band0, band1};
+  for (int t = 0; t < 2; ++t) {
+    tr[t].n = n; tr[t].W = W; tr[t].cap = capacity; tr[t].count = 1;
+    tr[t].q = t == 0 ? q0 : q1;
+    tr[t].parent = t == 0 ? parent0 : parent1;
+    tr[t].edge = (double*)malloc(sizeof(double) * (size_t)capacity * W * n);
+    memcpy(tr[t].q, t == 0 ? start : goal, sizeof(double) * n);
+    tr[t].parent[0] = -1;
+    flag[t][0] = 0;
+  }
+  double shift[16];
+  uint64_t state = seed;
+  for (int j = 0; j < 16; ++j) shift[j] = (double)(splitmix64_next(&state) >> 11) * (1.0 / 9007199254740992.0);
+  double* xi = (double*)malloc(sizeof(double) * (size_t)W * n);
+  double qr[MAXDOF], qs[MAXDOF], qe[MAXDOF], qt[MAXDOF];
+  int status = 0;
+  *found_round = 0;
+  *band_round = 0;
+  *band_extensions = 0;
+  for (int32_t rd = 0; rd < rounds && !*found_round && status == 0; ++rd) {
+    const int pub[2] = {tr[0].count, tr[1].count};   /* snapshot seen by this round's searches */
+    for (int g = 0; g < n_groups && !*found_round && status == 0; ++g) {
+      const int X = g & 1, Y = X ^ 1;
+      const uint32_t idx = (uint32_t)rd * (uint32_t)n_groups + (uint32_t)g + 1u;
+      int band = 0;   /* a decision of this extension so far lay near its threshold */
+      for (int j = 0; j < n; ++j) {
+        double u = radical_inverse(idx, primes[j]) + shift[j];
+        u -= floor(u);
+        if (u < kBandSample || u > 1.0 - kBandSample) band = 1;
+        qr[j] = r->lo[j] + u * (r->hi[j] - r->lo[j]);
+      }
+      double gap, mg;
+      const int near = tree_nearest_gap(&tr[X], pub[X], qr, n, &gap);
+      if (gap < kBandDist) band = 1;
+      steer_to(tr[X].q + (size_t)near * n, qr, step, n, qs);
+      const int ok = motion_ok_margin(r, env, c, p, tr[X].q + (size_t)near * n, qs, xi, &mg);
+      if (mg < kBandProj) band = 1;
+      if (ok) {
+        int cur = tree_append(&tr[X], near, xi);
+        if (cur < 0) { status = -1; break; }
+        flag[X][cur] = band;
+        memcpy(qe, xi + (size_t)(W - 1) * n, sizeof(double) * n);
+        const int tgt = tree_nearest_gap(&tr[Y], pub[Y], qe, n, &gap);
+        if (gap < kBandDist) band = 1;
+        memcpy(qt, tr[Y].q + (size_t)tgt * n, sizeof(double) * n);
+        double dcur = dist_sq(qe, qt, n);
+        for (int s = 0;; ++s) {
+          if (fabs(sqrt(dcur) - tol) < kBandDist) band = 1;
+          if (dcur < tol * tol) { *found_round = rd + 1; break; }
+          if (s >= max_connect) break;
+          steer_to(qe, qt, step, n, qs);
+          const int ok2 = motion_ok_margin(r, env, c, p, qe, qs, xi, &mg);
+          if (mg < kBandProj) band = 1;
+          if (!ok2) break;
+          const double dnew = dist_sq(xi + (size_t)(W - 1) * n, qt, n);
+          if (fabs(sqrt(dnew) - sqrt(dcur)) < kBandDist) band = 1;
+          if (!(dnew < dcur)) break;
+          cur = tree_append(&tr[X], cur, xi);
+          if (cur < 0) { status = -1; break; }
+          flag[X][cur] = band;
+          memcpy(qe, xi + (size_t)(W - 1) * n, sizeof(double) * n);
+          dcur = dnew;
+        }
+      }
+      if (band) {
+        ++*band_extensions;
+        if (!*band_round) *band_round = rd + 1;
+      }
+    }
+  }
+  counts[0] = tr[0].count;
+  counts[1] = tr[1].count;
+  for (int t = 0; t < 2; ++t) free(tr[t].edge);
+  free(xi);
+  return status;
+}
+
 void or_path_report(const or_robot* r, const or_env* env, const or_constraint* c,
                     const double* path, int32_t len, double* out) {
   const int n = r->dof;

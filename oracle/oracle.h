@@ -108,6 +108,27 @@ int32_t or_plan(const or_robot* r, const or_env* env, const or_constraint* c, co
                 int32_t capacity, int32_t max_connect, double* path, int32_t cap_path,
                 int32_t* path_len, int32_t* nodes);
 
+/* The GPU planner's round schedule run sequentially (its lockstep replay):
+ * in round r (0-based) extension g = 0..n_groups-1 takes Halton index
+ * r * n_groups + g + 1, grows tree g & 1 and searches only the nodes present
+ * when the round began; nodes are appended in extension order.  Stops in the
+ * round the trees connect or after `rounds` rounds.  q0/q1: [capacity][dof],
+ * parent0/parent1 and band0/band1: [capacity], counts[2].  A decision lies
+ * in the band when it is near its threshold: a sample coordinate within
+ * 1e-5 of wrapping, a nearest-node runner-up within 1e-4, a projection
+ * margin or |signed distance| below 1e-5, a connection or progress distance
+ * within 1e-4.  band0/band1[i] = 1 when a decision of the extension that
+ * appended node i, up to that node, was in the band.  *found_round: 1-based
+ * round of the connection, else 0; *band_round: 1-based first round with an
+ * extension holding a band decision, else 0; *band_extensions: how many
+ * extensions held one.  Returns 0, or -1 when a tree fills up. */
+int32_t or_plan_rounds(const or_robot* r, const or_env* env, const or_constraint* c,
+                       const or_params* p, const double* start, const double* goal, uint64_t seed,
+                       int32_t n_groups, int32_t rounds, int32_t capacity, int32_t max_connect,
+                       double* q0, int32_t* parent0, int32_t* band0, double* q1, int32_t* parent1,
+                       int32_t* band1, int32_t* counts, int32_t* found_round, int32_t* band_round,
+                       int32_t* band_extensions);
+
 /* Re-validation of a dense path: limits, ||e||_inf < tau_task + slack,
  * consecutive spacing < tau + tau_sm + slack, minimum signed distance of every
  * waypoint.  out[0] = worst task error, out[1] = worst spacing, out[2] =

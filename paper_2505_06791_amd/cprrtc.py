@@ -115,6 +115,8 @@ def lib():
         L.cp_plan_opts_default.argtypes = [C.POINTER(PlanOpts)]
         L.cp_planner_create.argtypes = [vp, C.POINTER(PlanOpts), C.POINTER(vp)]
         L.cp_planner_destroy.argtypes = [vp]
+        L.cp_planner_tree.argtypes = [vp, C.c_int32, C.c_int32, _dp, C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32)]
         L.cp_plan.argtypes = [vp, vp, C.POINTER(Constraint), _dp, _dp, C.c_uint64,
                               C.POINTER(Path), C.POINTER(PlanStats), vp]
         L.plan.argtypes = [vp, vp, C.POINTER(Constraint), _dp, _dp, C.c_uint64,
@@ -353,6 +355,19 @@ class Planner:
         if rc == CP_OK:
             return rc, buf[: path.len].copy(), st
         return rc, None, st
+
+    def tree(self, t: int):
+        """Tree t (0 start, 1 goal) of the last plan: (q [count, dof] float64,
+        parent [count] int32)."""
+        cnt = C.c_int32(0)
+        rc = lib().cp_planner_tree(self.handle, t, 0, None, None, C.byref(cnt))
+        if rc not in (CP_OK, CP_E_CAPACITY):
+            _check(rc)
+        q = np.zeros((max(cnt.value, 1), self.robot.dof))
+        par = np.zeros(max(cnt.value, 1), np.int32)
+        _check(lib().cp_planner_tree(self.handle, t, cnt.value, q.ctypes.data_as(_dp),
+                                     par.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(cnt)))
+        return q[: cnt.value], par[: cnt.value]
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

@@ -753,6 +753,34 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
   }
 }
 
+int cp_planner_tree(const cp_planner* pl, int32_t tree, int32_t capacity, double* q,
+                    int32_t* parent, int32_t* count) {
+  try {
+    if (!pl || !count || tree < 0 || tree > 1) return api_fail(CP_E_ARG, "cp_planner_tree: bad argument");
+    int ctl[kCtlInts];
+    hipError_t he = hipMemcpy(ctl, pl->ctl, sizeof ctl, hipMemcpyDeviceToHost);
+    if (he != hipSuccess) return api_hip_fail(he, "cp_planner_tree");
+    const int cap = pl->opts.capacity, n = pl->dof;
+    const int cnt = std::min(ctl[kCtlCount + tree], cap);
+    *count = cnt;
+    if (capacity < cnt) return api_fail(CP_E_CAPACITY, "tree holds %d nodes", cnt);
+    if (cnt > 0 && (!q || !parent)) return api_fail(CP_E_ARG, "cp_planner_tree: NULL buffer");
+    std::vector<float> col(cnt);
+    for (int j = 0; j < n && cnt > 0; ++j) {
+      he = hipMemcpy(col.data(), pl->q[tree] + (size_t)j * cap, sizeof(float) * cnt, hipMemcpyDeviceToHost);
+      if (he != hipSuccess) return api_hip_fail(he, "cp_planner_tree");
+      for (int i = 0; i < cnt; ++i) q[(size_t)i * n + j] = (double)col[i];
+    }
+    if (cnt > 0) {
+      he = hipMemcpy(parent, pl->parent[tree], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost);
+      if (he != hipSuccess) return api_hip_fail(he, "cp_planner_tree");
+    }
+    return CP_OK;
+  } catch (...) {
+    return api_fail(CP_E_ARG, "cp_planner_tree: unexpected exception");
+  }
+}
+
 int plan(const cp_robot* robot, const cp_env* env, const cp_constraint* constraint,
          const double* start, const double* goal, uint64_t seed, const cp_plan_opts* opts,
          cp_path* out) {

@@ -362,3 +362,21 @@ def workload(name: str, seed: int) -> dict:
                     env=make_mixed(seed + 1, 1000, cube_side=3.6, keep_out=DUAL_KEEP_OUT),
                     constraint=relative_pose(), tau_task=1e-4)
     raise ValueError(f"unknown workload {name!r}")
+
+
+def uneven_query(seed: int) -> dict:
+    """One query of the uneven batch: DOF uniform in {6, 7, 9} (6: 17
+    spheres, 7: 20, 9: planar base with 8 base spheres + 7-DOF arm with 20),
+    round(exp U[ln 10, ln 1000]) mixed primitives in the 3.0 m cube, and a
+    constraint uniform in {none, upright, plane + upright}; tolerance 1e-3."""
+    rng = rng_for(seed)
+    dof = int(rng.choice([6, 7, 9]))
+    n_obs = int(round(math.exp(rng.uniform(math.log(10.0), math.log(1000.0)))))
+    kind = int(rng.integers(0, 3))
+    if dof == 9:
+        robot = make_mobile_arm(seed)
+    else:
+        robot = make_arm(seed, dof, 17 if dof == 6 else 20)
+    con = (no_constraint(), upright(), plane_upright(seed + 2))[kind]
+    return dict(robot=robot, env=make_mixed(seed + 1, n_obs, cube_side=3.0), constraint=con,
+                tau_task=1e-3)

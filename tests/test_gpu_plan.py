@@ -119,3 +119,69 @@ def test_plan_budget_and_capacity(G):
         assert rc in (G.CP_OK, G.CP_NO_SOLUTION)
     except G.CprrtcError as e:
         assert e.code == G.CP_E_CAPACITY
+
+
+def _match_trees(q_gpu, p_gpu, q_or, p_or, band_or, slack, tol=1e-4):
+    """Node-for-node match, independent of append order: every oracle node
+    appended without a band decision pairs with a distinct GPU node whose
+    configuration and parent configuration agree within tol; at most `slack`
+    GPU nodes stay unpaired (outputs of extensions that held a band
+    decision)."""
+    used = np.zeros(len(q_gpu), bool)
+    assert np.abs(q_gpu[0] - q_or[0]).max() < tol and p_gpu[0] == -1
+    used[0] = True
+    for i in range(1, len(q_or)):
+        if band_or[i]:
+            continue
+        d = np.abs(q_gpu - q_or[i]).max(1)
+        pd = np.abs(q_gpu[np.maximum(p_gpu, 0)] - q_or[p_or[i]]).max(1)
+        cand = np.nonzero((d < tol) & (pd < tol) & ~used & (p_gpu >= 0))[0]
+        assert len(cand) >= 1, (i, d.min())
+        used[cand[0]] = True
+    assert (~used).sum() <= slack, ((~used).sum(), slack)
+    return int(used.sum()) - 1
+
+
+def test_plan_lockstep_replay_matches_oracle_rounds(G):
+    """Rounds of the GPU planner against the oracle's round-synchronous
+    replay (same Halton indices, same tree per extension, searches over the
+    nodes present when the round began).  Compared through the first round
+    that holds a decision within the band of its threshold: every node the
+    oracle appended without such a decision has its GPU twin."""
+    compared, matched = 0, 0
+    for name, seed in (("cluttered", 2001), ("plain", 1000), ("plain", 1001), ("plain", 1003),
+                       ("plain", 1004), ("plain", 1005), ("mobile", 3000)):
+        w = I.workload(name, seed)
+        ro, eo, co = oracle_views(w)
+        ends = manifold_starts(w, 2, seed + 5).astype(np.float64)
+        prm_o = O.params(W=64, tau_task=w["tau_task"])
+        groups, R = 32, 3
+        ref = O.plan_rounds(ro, eo, co, prm_o, ends[0], ends[1], seed, n_groups=groups, rounds=R)
+        lim = min(R, ref["band_round"]) if ref["band_round"] else R
+        if ref["found_round"]:
+            lim = min(lim, ref["found_round"] - 1)
+        print(name, seed, "found", ref["found_round"], "band round", ref["band_round"],
+              "rounds compared", lim, flush=True)
+        if lim < 1:
+            continue
+        if lim < R:
+            ref = O.plan_rounds(ro, eo, co, prm_o, ends[0], ends[1], seed, n_groups=groups,
+                                rounds=lim)
+        robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
+        pl = G.Planner(robot, G.plan_opts(n_groups=groups, max_rounds=lim, capacity=4096,
+                                          tau_task=w["tau_task"]))
+        rc, path, st = pl.plan(env, con, ends[0], ends[1], seed)
+        if rc == G.CP_OK:            # a band extension connected on the GPU
+            assert ref["band_extensions"] > 0
+            continue
+        assert rc == G.CP_NO_SOLUTION and st["rounds"] == lim
+        slack = ref["band_extensions"] * 65
+        for t in range(2):
+            qg, pg = pl.tree(t)
+            qo, po, bo = ref["trees"][t]
+            m = _match_trees(qg, pg, qo, po, bo, slack)
+            print("  tree", t, "nodes gpu", len(qg), "oracle", len(qo), "band", int(bo.sum()),
+                  "matched", m, flush=True)
+            matched += m
+        compared += 1
+    assert compared >= 3 and matched >= 10

@@ -460,3 +460,138 @@ def test_mlp_forward_closed_form(oracle_lib):
     y = O.mlp_forward(dims, [w1, b1, w2, b2], x)
     z = w1 * x + b1
     np.testing.assert_allclose(y, w2 * z / (1 + np.exp(-z)) + b2, rtol=1e-14)
+
+
+# ------------------------------------------------------------------ round schedule of the planner
+
+def _splitmix64(state):
+    """splitmix64 (Steele, Lea and Flood, 2014), as published: returns
+    (next state, output)."""
+    M = (1 << 64) - 1
+    state = (state + 0x9E3779B97F4A7C15) & M
+    z = state
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+    return state, z ^ (z >> 31)
+
+
+def _free_space_rounds(lo, hi, start, goal, seed, n_groups, rounds, W, tau, tau_sm, max_connect):
+    """The round schedule in free space without a task constraint, where every
+    motion is valid and ends at its steer target: Halton points from scipy
+    (unscrambled; row i is the radical inverse of i in the first primes),
+    shifted per dimension by splitmix64 draws, nearest node by numpy among
+    the nodes present when the round began, steer by at most (W-1) tau."""
+    from scipy.stats import qmc
+    n = len(lo)
+    H = qmc.Halton(d=n, scramble=False).random(n_groups * rounds + 1)
+    state, shift = seed, []
+    for _ in range(16):
+        state, z = _splitmix64(state)
+        shift.append((z >> 11) * 2.0 ** -53)
+    shift = np.array(shift[:n])
+    trees = [[np.array(start, float)], [np.array(goal, float)]]
+    parents = [[-1], [-1]]
+    step, tol = (W - 1) * tau, tau + tau_sm
+
+    def steer(a, b):
+        d = np.linalg.norm(b - a)
+        s = step / d if d > step else 1.0
+        return a + s * (b - a)
+
+    def nearest(t, x, count):
+        return int(np.argmin(((np.array(trees[t][:count]) - x) ** 2).sum(1)))
+
+    found = 0
+    for rd in range(rounds):
+        pub = [len(trees[0]), len(trees[1])]
+        for g in range(n_groups):
+            X, Y = g & 1, (g & 1) ^ 1
+            u = H[rd * n_groups + g + 1] + shift
+            u -= np.floor(u)
+            qr = lo + u * (hi - lo)
+            near = nearest(X, qr, pub[X])
+            qe = steer(trees[X][near], qr)
+            trees[X].append(qe)
+            parents[X].append(near)
+            cur = len(trees[X]) - 1
+            qt = trees[Y][nearest(Y, qe, pub[Y])]
+            dcur = ((qe - qt) ** 2).sum()
+            for s in range(max_connect + 1):
+                if dcur < tol * tol:
+                    found = rd + 1
+                    break
+                if s >= max_connect:
+                    break
+                q2 = steer(qe, qt)
+                dnew = ((q2 - qt) ** 2).sum()
+                if not dnew < dcur:
+                    break
+                trees[X].append(q2)
+                parents[X].append(cur)
+                cur = len(trees[X]) - 1
+                qe, dcur = q2, dnew
+            if found:
+                return trees, parents, found
+    return trees, parents, found
+
+
+@pytest.mark.parametrize("max_connect,rounds", [(0, 3), (64, 2)])
+def test_plan_rounds_free_space_schedule(oracle_lib, max_connect, rounds):
+    """Free space, no constraint: the oracle's round-synchronous planner
+    equals the schedule rebuilt from scipy's Halton sequence and numpy."""
+    O = oracle_lib
+    rd = I.make_arm(1000, 7, 20)
+    w = dict(robot=rd, env=I.empty_env(), constraint=I.no_constraint())
+    ro, eo, co = O.Robot(rd), O.Env(w["env"]), O.Constraint(w["constraint"])
+    prm = O.params(W=64, tau_task=1e-3)
+    rng = np.random.default_rng(5)
+    start = rng.uniform(rd["lo"], rd["hi"])
+    goal = rng.uniform(rd["lo"], rd["hi"])
+    out = O.plan_rounds(ro, eo, co, prm, start, goal, 77, n_groups=8, rounds=rounds,
+                        max_connect=max_connect)
+    trees, parents, found = _free_space_rounds(rd["lo"], rd["hi"], start, goal, 77, 8, rounds, 64,
+                                               0.05, 0.025, max_connect)
+    assert out["found_round"] == found
+    if max_connect:
+        assert found == 1               # in free space the first extension connects
+    else:
+        assert found == 0
+    assert out["band_extensions"] == 0
+    for t in range(2):
+        q, par, band = out["trees"][t]
+        assert not band.any()
+        assert len(q) == len(trees[t])
+        np.testing.assert_allclose(q, np.array(trees[t]), atol=1e-12, rtol=0)
+        assert par.tolist() == parents[t]
+
+
+def test_plan_rounds_tree_invariants(oracle_lib):
+    """Cluttered scene with plane + upright: every node is inside the limits,
+    on the manifold, collision-free and within one extension of its parent;
+    the start and goal are the roots."""
+    O = oracle_lib
+    w = I.workload("cluttered", 2001)
+    ro, eo, co = O.Robot(w["robot"]), O.Env(w["env"]), O.Constraint(w["constraint"])
+    rd = w["robot"]
+    ends = []
+    for q in I.random_configs(rd, 400, 2006):
+        ok, qp, _ = O.project_config(ro, co, q, tol=1e-9, max_iters=100)
+        if ok and O.config_min_sd(ro, eo, qp) > 1e-3:
+            ends.append(qp)
+        if len(ends) == 2:
+            break
+    prm = O.params(W=64, tau_task=1e-3)
+    out = O.plan_rounds(ro, eo, co, prm, ends[0], ends[1], 11, n_groups=8, rounds=3)
+    assert out["status"] == 0
+    total = 0
+    for t in range(2):
+        q, par, _ = out["trees"][t]
+        assert np.array_equal(q[0], ends[t]) and par[0] == -1
+        for i in range(1, len(q)):
+            assert 0 <= par[i] < i
+            assert np.all(q[i] >= rd["lo"]) and np.all(q[i] <= rd["hi"])
+            assert np.abs(O.task_error(ro, co, q[i])).max() < 1e-3
+            assert O.config_min_sd(ro, eo, q[i]) > 0
+            assert np.linalg.norm(q[i] - q[par[i]]) <= 63 * 0.075
+        total += len(q) - 1
+    assert total >= 1
