@@ -47,13 +47,25 @@ SPHERE_CENTRE_FLOPS = 19          # R l + p, plus r^2
 CULL_FLOPS = 20                   # bounding sphere vs box: 3 x (2 sub, 2 max), |.|^2, reach^2, compare
 
 
-def update_flops(dof: int) -> int:
-    """One waypoint update of Algorithm 1 for a single-chain pose constraint:
-    FK to every joint frame (51/joint), tool (57), constrained pose and
-    angles (73), error (30), Jacobian columns (57/joint), J J^T (42/joint + 6),
-    6x6 Cholesky (97) and solves (72), J^T y (12/joint), smoothing, update,
-    clamp and validity (9/joint + 5)."""
-    return 171 * dof + 340
+def update_flops(dof: int, m_pos: int, m_ang: int) -> int:
+    """One waypoint update of Algorithm 1 for a single-chain pose constraint
+    with m_pos locked position axes and m_ang locked angle axes (m = m_pos +
+    m_ang rows of the task Jacobian): FK to every joint frame (51/joint) and
+    the tool (57), the position error frame (18), the constrained rotation
+    and its angles (45 + 8 + 1 per locked angle, when an angle is locked),
+    the error (2 per position, 6 per angle), Jacobian rows (12 + 5 per
+    position row, + 19 + 2 per angle row when an angle is locked, per joint),
+    J J^T + lambda^2 I (m(m+1)/2 entries x 2 dof, + m), Cholesky
+    (sum over columns c of (2c+1)(m-c)), two triangular solves (2 m^2),
+    J^T y (2 m dof), smoothing, update, clamp and validity (9/joint + 5)."""
+    m = m_pos + m_ang
+    fk = 51 * dof + 57
+    orient = (45 + 8 + m_ang) if m_ang else 0
+    err = 2 * m_pos + 6 * m_ang
+    jac = dof * (12 + 5 * m_pos + ((19 + 2 * m_ang) if m_ang else 0))
+    jjt = m * (m + 1) // 2 * 2 * dof + m
+    chol = sum((2 * c + 1) * (m - c) for c in range(m))
+    return fk + 18 + orient + err + jac + jjt + chol + 2 * m * m + 2 * m * dof + 9 * dof + 5
 
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3    # MI355X, 256 CU x 2.4 GHz, packed FMA counted
@@ -70,6 +82,11 @@ def parse():
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--plan-queries", type=int, default=100,
                     help="planning queries per scene for the p50 plan time (0 = skip)")
+    ap.add_argument("--learned", type=int, default=1,
+                    help="measure the warm-start network and the warm-started projector (0 = skip)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB three times "
+                         "(calibration of the HBM traffic counters) and exit")
     ap.add_argument("--batch-queries", type=int, default=512,
                     help="uneven queries planned in one batch and one by one (0 = skip)")
     return ap.parse_args()
@@ -170,6 +187,86 @@ def batch_bench(G, I, torch, n, base=3000):
                 batched_rounds=int(max(i["rounds"] for i in info)),
                 sequential_ms=seq_ms, sequential_solved=ok_s,
                 speedup=seq_ms / batch_ms)
+
+
+def _time_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
+BF16_MFMA_PEAK_TFLOPS = 2500.0     # MI355X dense BF16 matrix cores
+
+
+def mlp_bench(G, torch, M=65536):
+    """Matrix-core throughput of the warm-start network: inference over M
+    samples and one training step (forward, both backward products, Adam)
+    over a 4096-sample batch, for the 7-DOF (13 -> 3 x 256 -> 7) and the
+    dual-arm (26 -> 3 x 512 -> 14) networks.  FLOPs: 2 k n per sample and
+    layer for the forward pass and for dW, and again for dX except at the
+    first layer."""
+    out = {}
+    dev = torch.device("cuda:0")
+    for name, (n_in, hid, nh, n_out) in (("arm7", (13, 256, 3, 7)), ("dual14", (26, 512, 3, 14))):
+        net = G.MLP(n_in, hid, nh, n_out, seed=1)
+        dims = [n_in] + [hid] * nh + [n_out]
+        kn = [dims[i] * dims[i + 1] for i in range(len(dims) - 1)]
+        x = torch.randn((M, n_in), device=dev)
+        fwd_ms = _time_ms(torch, lambda: net.forward(x), 5)
+        B = 4096
+        xb, tb = x[:B].contiguous(), torch.randn((B, n_out), device=dev)
+        loss = torch.zeros(1, device=dev)
+        train_ms = _time_ms(torch, lambda: net.train_step(xb, tb, 1e-4, loss), 10)
+        fwd_flops = 2 * M * sum(kn)
+        train_flops = 2 * B * (2 * sum(kn) + sum(kn[1:]))
+        out[name] = dict(inference_samples=M, inference_ms=fwd_ms,
+                         inference_tflops=fwd_flops / (fwd_ms * 1e-3) / 1e12,
+                         train_batch=B, train_step_ms=train_ms,
+                         train_tflops=train_flops / (train_ms * 1e-3) / 1e12,
+                         peak_tflops=BF16_MFMA_PEAK_TFLOPS)
+    return out
+
+
+def warm_bench(G, I, torch, n_train=8192, n_eval=4096, tau_task=1e-4):
+    """Learned warm start against the plain projector at tolerance 1e-4
+    (plain scene, seed 1000): the network is trained on pairs from
+    n_train projector motions, then both project n_eval held-out motions."""
+    from paper_2505_06791_amd import warmstart
+    w = I.workload("plain", 1000)
+    rd, cd = w["robot"], w["constraint"]
+    robot, con = G.Robot(rd), G.constraint(cd)
+    t0 = time.perf_counter()
+    X, T = warmstart.make_pairs(rd, cd, n_train, seed=4000, tau_task=tau_task, robot=robot, con=con)
+    net = G.MLP(warmstart.n_inputs(rd, cd), 256, 3, rd["dof"], seed=4000)
+    hist = warmstart.train(net, X, T, epochs=6, batch=4096)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    q_from, q_to = warmstart.motion_ends(rd, robot, con, n_eval, seed=4100)
+    M, dof = q_from.shape[0], rd["dof"]
+    prm = G.proj_params(W=W, tau=TAU, tau_task=tau_task)
+    xi = torch.empty((M, W, dof), device=q_from.device)
+    st = torch.empty(M, dtype=torch.int32, device=q_from.device)
+    it = torch.empty(M, dtype=torch.int32, device=q_from.device)
+    res = {}
+    for name, fn in (("plain", lambda: G.project_motions(robot, con, prm, q_from, q_to, xi, st, it)),
+                     ("warm_only", lambda: G.project_motions_warm(robot, con, prm, net, q_from, q_to,
+                                                                  xi, st, it,
+                                                                  flags=G.WARM_NO_FALLBACK)),
+                     ("warm_fallback", lambda: G.project_motions_warm(robot, con, prm, net, q_from,
+                                                                      q_to, xi, st, it))):
+        ms = _time_ms(torch, fn, 5)
+        s_h, i_h = st.cpu().numpy(), it.cpu().numpy()
+        res[name] = dict(ms=ms, success=float((s_h == 0).mean()), mean_iters=float(i_h.mean()))
+    res.update(motions=M, tau_task=tau_task, train_pairs=int(X.shape[0]), train_seconds=train_s,
+               train_loss=[float(h) for h in hist])
+    return res
 
 
 def cpu_plan_baseline(I, name, seeds, tau_task, target_s):
@@ -277,6 +374,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.copy_mb > 0:
+        n = args.copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": n * 4, "launches": 3}), flush=True)
+        return
     w = I.workload(WORKLOAD, SCENE_SEED)
     rd, ed, cd = w["robot"], w["env"], w["constraint"]
     robot, env, con = G.Robot(rd), G.Env(ed), G.constraint(cd)
@@ -330,7 +436,8 @@ def main():
     wk = [int(x) for x in work.cpu().numpy()]
     val_flops = (sum(wk[i] * PAIR_FLOPS[t] for i, t in enumerate(PAIR_ORDER))
                  + wk[5] * SPHERE_CENTRE_FLOPS + wk[7] * CULL_FLOPS)
-    proj_flops = wk[6] * update_flops(dof)
+    mask = np.asarray(cd["mask"]) != 0
+    proj_flops = wk[6] * update_flops(dof, int(mask[:3].sum()), int(mask[3:].sum()))
     if val_ms >= proj_ms:
         dom, dom_ms, flops = "validate_kernel<8, true>", val_ms, val_flops
     else:
@@ -392,6 +499,9 @@ def main():
             result["plan"][name] = entry
     if args.batch_queries > 0:
         result["batch"] = batch_bench(G, I, torch, args.batch_queries)
+    if args.learned:
+        result["mlp"] = mlp_bench(G, torch)
+        result["warm_start"] = warm_bench(G, I, torch)
     if args.cpu_seconds > 0:
         result["cpu_baseline"] = cpu_baseline(I, w, args.cpu_seconds)
     print(json.dumps(result), flush=True)

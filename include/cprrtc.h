@@ -120,7 +120,22 @@ typedef struct cp_proj_params {
   double alpha;       /* step factor (1.0) */
   double lambda;      /* damping of the least-squares step (1e-2) */
   int32_t sphere_batch; /* spheres per collision batch between early-exit polls: 4 or 8 (8) */
+  int32_t variant;    /* projection operator, CP_PROJECT_* (CP_PROJECT_PARALLEL) */
 } cp_proj_params;
+
+/* Projection operators (Section III-A and its comparison in the Evaluation):
+ * PARALLEL     Algorithm 1: every waypoint projected at once with the
+ *              smoothing term, frozen validated prefix;
+ * INDEPENDENT  the same iteration without the smoothing term (waypoints
+ *              projected in parallel and independently; spacing is still
+ *              required for validity);
+ * SEQUENTIAL   the CBiRRT-style projection of cpRRTC-Naive: waypoint k
+ *              starts at the projected waypoint k-1 plus one interpolation
+ *              step and is projected alone (damped least squares, no
+ *              smoothing term) until it is valid (task error and spacing to
+ *              k-1), at most max_iters steps per waypoint; iterations are
+ *              summed over the waypoints. */
+enum { CP_PROJECT_PARALLEL = 0, CP_PROJECT_INDEPENDENT = 1, CP_PROJECT_SEQUENTIAL = 2 };
 
 typedef struct cp_robot cp_robot;   /* opaque; device copy of a cp_robot_desc */
 typedef struct cp_env cp_env;       /* opaque; device copy of a cp_env_desc */
@@ -238,7 +253,9 @@ int cp_mlp_train_step(cp_mlp* mlp, int64_t M, const float* d_x, const float* d_t
  * fails are projected again from the straight line (the plain projector is
  * the fallback and the judge).  d_iters receives the iterations of both
  * passes.  flags: CP_WARM_NO_FALLBACK skips the fallback (to measure the warm
- * pass alone).  Otherwise as project_motions. */
+ * pass alone).  Only the parallel projector (variant CP_PROJECT_PARALLEL) is
+ * warm-started; other variants return CP_E_UNSUPPORTED.  Otherwise as
+ * project_motions. */
 enum { CP_WARM_NO_FALLBACK = 4 };
 int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
                          const cp_proj_params* params, cp_mlp* mlp, int32_t n_motions,

@@ -45,7 +45,10 @@ class _Constraint(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("W", C.c_int32), ("max_iters", C.c_int32), ("tau", C.c_double),
                 ("tau_sm", C.c_double), ("tau_task", C.c_double), ("alpha", C.c_double),
-                ("lam", C.c_double)]
+                ("lam", C.c_double), ("variant", C.c_int32)]
+
+
+PROJECT_PARALLEL, PROJECT_INDEPENDENT, PROJECT_SEQUENTIAL = 0, 1, 2
 
 
 def build(force: bool = False) -> str:
@@ -135,8 +138,9 @@ class Constraint:
         self.m = lib().or_task_dim(C.byref(self.s))
 
 
-def params(W=64, max_iters=32, tau=0.05, tau_sm=0.025, tau_task=1e-3, alpha=1.0, lam=1e-2):
-    return _Params(W, max_iters, tau, tau_sm, tau_task, alpha, lam)
+def params(W=64, max_iters=32, tau=0.05, tau_sm=0.025, tau_task=1e-3, alpha=1.0, lam=1e-2,
+           variant=PROJECT_PARALLEL):
+    return _Params(W, max_iters, tau, tau_sm, tau_task, alpha, lam, variant)
 
 
 # ------------------------------------------------------------------ wrappers
@@ -215,6 +219,16 @@ def parallel_project(robot: Robot, con: Constraint, prm, xi_init):
     ok = lib().or_parallel_project(C.byref(robot.s), C.byref(con.s), C.byref(prm), _ptr(xi),
                                    C.byref(it), C.byref(mg), _ptr(trace, _ip))
     return bool(ok), xi, it.value, mg.value, trace[: it.value].copy()
+
+
+def project_motion(robot: Robot, con: Constraint, prm, xi_init):
+    """The projection operator prm.variant selects; returns (ok, xi, iters, margin)."""
+    xi = _f64(xi_init).copy()
+    it = C.c_int32(0)
+    mg = C.c_double(0)
+    ok = lib().or_project_motion(C.byref(robot.s), C.byref(con.s), C.byref(prm), _ptr(xi),
+                                 C.byref(it), C.byref(mg))
+    return bool(ok), xi, it.value, mg.value
 
 
 def project_validate_motions(robot: Robot, env: Env, con: Constraint, prm, q_from, q_to,

@@ -520,7 +520,7 @@ int32_t or_parallel_project(const or_robot* r, const or_constraint* c, const or_
       }
       const double E_sm = sqrt(dist2) - p->tau;
       for (int j = 0; j < n; ++j) {
-        const double g_sm = delta[j] * E_sm;
+        const double g_sm = p->variant == OR_PROJECT_INDEPENDENT ? 0.0 : delta[j] * E_sm;
         double v = qk[j] - p->alpha * (g_task[j] + g_sm);
         v = fmin(fmax(v, r->lo[j]), r->hi[j]);
         xi_new[(size_t)k * n + j] = v;
@@ -550,6 +550,49 @@ int32_t or_parallel_project(const or_robot* r, const or_constraint* c, const or_
   return ok;
 }
 
+int32_t or_sequential_project(const or_robot* r, const or_constraint* c, const or_params* p,
+                              double* xi, int32_t* iters, double* margin) {
+  const int n = r->dof, W = p->W;
+  double* init = (double*)malloc(sizeof(double) * (size_t)W * n);
+  memcpy(init, xi, sizeof(double) * (size_t)W * n);
+  double mg = DBL_MAX;
+  int32_t total = 0;
+  int ok = 1;
+  for (int k = 1; k < W && ok; ++k) {
+    const double* prev = xi + (size_t)(k - 1) * n;
+    double* x = xi + (size_t)k * n;
+    for (int j = 0; j < n; ++j) x[j] = prev[j] + (init[(size_t)k * n + j] - init[(size_t)(k - 1) * n + j]);
+    int valid = 0;
+    for (int it = 1; it <= p->max_iters; ++it) {
+      double e[MAXM], J[MAXM * MAXDOF], g[MAXDOF];
+      const int m = or_task_error(r, c, x, e);
+      double einf = 0.0, dist2 = 0.0;
+      for (int i = 0; i < m; ++i) einf = fmax(einf, fabs(e[i]));
+      for (int j = 0; j < n; ++j) dist2 += (x[j] - prev[j]) * (x[j] - prev[j]);
+      const double m_task = p->tau_task - einf;
+      const double m_sm = p->tau_sm - (sqrt(dist2) - p->tau);
+      const int v = (m_task > 0.0) && (m_sm > 0.0);
+      mg = fmin(mg, v ? fmin(m_task, m_sm) : fmax(-m_task, -m_sm));
+      ++total;
+      if (v) { valid = 1; break; }
+      or_task_jacobian(r, c, x, J);
+      or_dls_step(J, e, m, n, p->lambda, g);
+      for (int j = 0; j < n; ++j) x[j] = fmin(fmax(x[j] - p->alpha * g[j], r->lo[j]), r->hi[j]);
+    }
+    if (!valid) ok = 0;
+  }
+  if (iters) *iters = total;
+  if (margin) *margin = mg;
+  free(init);
+  return ok;
+}
+
+int32_t or_project_motion(const or_robot* r, const or_constraint* c, const or_params* p,
+                          double* xi, int32_t* iters, double* margin) {
+  if (p->variant == OR_PROJECT_SEQUENTIAL) return or_sequential_project(r, c, p, xi, iters, margin);
+  return or_parallel_project(r, c, p, xi, iters, margin, NULL);
+}
+
 /* One motion per (q_from, q_to): W straight-line waypoints
  * xi_init[k] = q_from + (k / (W-1)) (q_to - q_from)  (Section III: a fixed
  * number of linearly interpolated states from q_near), ParallelProject, then
@@ -573,7 +616,7 @@ void or_project_validate_motions(const or_robot* r, const or_env* env, const or_
     }
     int32_t it = 0;
     double mg = DBL_MAX;
-    const int ok = or_parallel_project(r, c, p, x, &it, &mg, NULL);
+    const int ok = or_project_motion(r, c, p, x, &it, &mg);
     double best = DBL_MAX;
     int st = OR_MOTION_PROJ_FAIL;
     if (ok) {
@@ -678,7 +721,7 @@ static int motion_ok(const or_robot* r, const or_env* env, const or_constraint* 
   }
   int32_t it;
   double mg;
-  if (!or_parallel_project(r, c, p, xi, &it, &mg, NULL)) return 0;
+  if (!or_project_motion(r, c, p, xi, &it, &mg)) return 0;
   for (int k = 1; k < W; ++k)
     if (or_config_min_sd(r, env, xi + (size_t)k * n) <= 0.0) return 0;
   return 1;
@@ -807,7 +850,7 @@ static int motion_ok_margin(const or_robot* r, const or_env* env, const or_const
   }
   int32_t it;
   double mg = DBL_MAX;
-  const int proj = or_parallel_project(r, c, p, xi, &it, &mg, NULL);
+  const int proj = or_project_motion(r, c, p, xi, &it, &mg);
   *margin = mg;
   if (!proj) return 0;
   double msd = DBL_MAX;

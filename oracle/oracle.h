@@ -63,7 +63,14 @@ typedef struct {
   double tau_task;          /* task tolerance on the infinity norm of the error */
   double alpha;             /* step factor */
   double lambda;            /* damping of the least-squares step */
+  int32_t variant;          /* OR_PROJECT_PARALLEL, _INDEPENDENT or _SEQUENTIAL */
 } or_params;
+
+/* Projection operators: Algorithm 1 (PARALLEL); the same iteration without
+ * the smoothing term (INDEPENDENT: the naive parallel projection Section
+ * III-A sets aside); waypoint after waypoint (SEQUENTIAL: the CBiRRT-style
+ * projection of cpRRTC-Naive in the Evaluation). */
+enum { OR_PROJECT_PARALLEL = 0, OR_PROJECT_INDEPENDENT = 1, OR_PROJECT_SEQUENTIAL = 2 };
 
 /* Kinematics.  frames: [dof][16] joint frames in world; ee: [n_chains][16]. */
 void or_fk(const or_robot* r, const double* q, double* frames, double* ee);
@@ -94,6 +101,20 @@ void or_project_validate_motions(const or_robot* r, const or_env* env, const or_
                                  const or_params* p, int32_t n_motions, const double* q_from,
                                  const double* q_to, double* xi, int32_t* status, int32_t* iters,
                                  double* proj_margin, double* min_sd, int32_t n_threads);
+
+/* Sequential projection: for k = 1..W-1 in turn, waypoint k starts at the
+ * projected waypoint k-1 plus one interpolation step (xi_init[k] -
+ * xi_init[k-1]) and takes damped least-squares steps (no smoothing term),
+ * validity (||e||_inf < tau_task and ||xi[k] - xi[k-1]|| - tau < tau_sm)
+ * checked before each step, at most max_iters checks; the motion fails at
+ * the first waypoint that never becomes valid.  *iters: checks summed over
+ * the waypoints; *margin: as or_parallel_project. */
+int32_t or_sequential_project(const or_robot* r, const or_constraint* c, const or_params* p,
+                              double* xi, int32_t* iters, double* margin);
+/* The operator p->variant selects (or_parallel_project or
+ * or_sequential_project). */
+int32_t or_project_motion(const or_robot* r, const or_constraint* c, const or_params* p,
+                          double* xi, int32_t* iters, double* margin);
 
 int32_t or_project_config(const or_robot* r, const or_constraint* c, const double* q_in,
                           double tol, int32_t max_iters, double alpha, double lambda,

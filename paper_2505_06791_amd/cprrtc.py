@@ -23,6 +23,7 @@ NO_EARLY_EXIT = 1
 NO_CULL = 2
 WARM_NO_FALLBACK = 4
 CP_TUNE_W = 1
+PROJECT_PARALLEL, PROJECT_INDEPENDENT, PROJECT_SEQUENTIAL = 0, 1, 2
 WORK_SLOTS = 8
 
 _dp = C.POINTER(C.c_double)
@@ -56,7 +57,7 @@ class Constraint(C.Structure):
 class ProjParams(C.Structure):
     _fields_ = [("W", C.c_int32), ("max_iters", C.c_int32), ("tau", C.c_double),
                 ("tau_sm", C.c_double), ("tau_task", C.c_double), ("alpha", C.c_double),
-                ("lam", C.c_double), ("sphere_batch", C.c_int32)]
+                ("lam", C.c_double), ("sphere_batch", C.c_int32), ("variant", C.c_int32)]
 
 
 class PlanOpts(C.Structure):
@@ -223,8 +224,10 @@ def constraint(cd: dict) -> Constraint:
 
 
 def proj_params(W=64, max_iters=32, tau=0.05, tau_sm=0.025, tau_task=1e-3, alpha=1.0, lam=1e-2,
-                sphere_batch=8) -> ProjParams:
-    return ProjParams(W, max_iters, tau, tau_sm, tau_task, alpha, lam, sphere_batch)
+                sphere_batch=8, variant=0) -> ProjParams:
+    """variant: PROJECT_PARALLEL (Algorithm 1), PROJECT_INDEPENDENT (no
+    smoothing term) or PROJECT_SEQUENTIAL (waypoint after waypoint)."""
+    return ProjParams(W, max_iters, tau, tau_sm, tau_task, alpha, lam, sphere_batch, variant)
 
 
 def _stream(stream=None):

@@ -99,6 +99,7 @@ void cp_proj_params_default(cp_proj_params* p) {
   p->alpha = 1.0;
   p->lambda = 1e-2;
   p->sphere_batch = 8;
+  p->variant = CP_PROJECT_PARALLEL;
 }
 
 int cp_robot_create(const cp_robot_desc* d, cp_robot** out) {
@@ -318,6 +319,8 @@ int check_params(const cp_proj_params* params, cp_proj_params* p) {
     return fail(CP_E_ARG, "projection parameters out of range");
   if (p->sphere_batch != 4 && p->sphere_batch != 8)
     return fail(CP_E_UNSUPPORTED, "sphere_batch = %d (supported: 4, 8)", p->sphere_batch);
+  if (p->variant < CP_PROJECT_PARALLEL || p->variant > CP_PROJECT_SEQUENTIAL)
+    return fail(CP_E_ARG, "variant = %d (CP_PROJECT_*)", p->variant);
   return CP_OK;
 }
 
@@ -339,6 +342,7 @@ int do_project(const cp_robot* robot, const cp_constraint* constraint, const cp_
   prm.tau_task = (float)p.tau_task;
   prm.alpha = (float)p.alpha;
   prm.lambda2 = (float)(p.lambda * p.lambda);
+    prm.variant = p.variant;
   bool supported = false;
   hipError_t e = launch_project(robot->host.dof, robot->dev, con, prm, n_motions, d_q_from, d_q_to,
                                 d_xi, d_status, d_iters, (unsigned long long*)d_work,

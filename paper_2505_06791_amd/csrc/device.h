@@ -62,6 +62,7 @@ struct ProjDev {
   int W;
   int max_iters;
   float tau, tau_sm, tau_task, alpha, lambda2;
+  int variant;        // CP_PROJECT_PARALLEL / _INDEPENDENT / _SEQUENTIAL
 };
 
 // ------------------------------------------------------------------ frames

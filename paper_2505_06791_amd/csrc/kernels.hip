@@ -56,6 +56,9 @@ __global__ __launch_bounds__(kBlock) void fk_cc_kernel(const RobotDev* __restric
 //         k >= 1 (delta from the network, [n_motions][W-1][NDOF]).
 // MODE 2: fallback, only motions whose status is 1 are projected again from
 //         the straight line; their iterations are added to iters.
+// MODE 3: the sequential projection (CP_PROJECT_SEQUENTIAL) from the
+//         straight line; modes 0-2 run Algorithm 1 (with or without the
+//         smoothing term, by prm.variant).
 template <int NDOF, int KIND, int MODE>
 __global__ __launch_bounds__(kBlock) void project_kernel(
     const RobotDev* __restrict__ rob, ConDev con, ProjDev prm, int n_motions,
@@ -91,7 +94,9 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
 
   int it = 0;
   unsigned long long updates = 0;   // waypoint updates computed (lanes past prog, per iteration)
-  const bool ok = project_segment<NDOF, KIND>(rob, con, prm, k, seg, wmask, segmask, false, q, it,
+  const bool ok =
+      MODE == 3 ? project_sequential<NDOF, KIND>(rob, con, prm, k, seg, false, q, it, updates)
+                : project_segment<NDOF, KIND>(rob, con, prm, k, seg, wmask, segmask, false, q, it,
                                               updates);
 
   float* xk = xi + (motion * W + k) * NDOF;
@@ -197,6 +202,8 @@ static void launch_project_kind(int mode, unsigned nb, hipStream_t stream, const
                                 unsigned long long* work) {
   if (mode == 1)
     project_kernel<NDOF, KIND, 1><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+  else if (mode == 3)
+    project_kernel<NDOF, KIND, 3><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
   else if (mode == 2)
     project_kernel<NDOF, KIND, 2><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
   else
@@ -256,8 +263,9 @@ hipError_t launch_project(int dof, const RobotDev* rob, const ConDev& con, const
                           int n_motions, const float* q_from, const float* q_to, float* xi,
                           int* status, int* iters, unsigned long long* work, hipStream_t stream,
                           bool* supported) {
-  return launch_project_mode(dof, 0, rob, con, prm, n_motions, q_from, q_to, nullptr, xi, status,
-                             iters, work, stream, supported);
+  return launch_project_mode(dof, prm.variant == CP_PROJECT_SEQUENTIAL ? 3 : 0, rob, con, prm,
+                             n_motions, q_from, q_to, nullptr, xi, status, iters, work, stream,
+                             supported);
 }
 
 hipError_t launch_validate(const RobotDev* rob, const float4* sph, const EnvDev& env, int W,

@@ -573,6 +573,8 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
     cp_proj_params p;
     int rc = api_params(params, &p);
     if (rc != CP_OK) return rc;
+    if (p.variant != CP_PROJECT_PARALLEL)
+      return api_fail(CP_E_UNSUPPORTED, "project_motions_warm: the warm start serves the parallel projector only");
     ConDev con;
     rc = api_constraint(constraint, robot, &con);
     if (rc != CP_OK) return rc;
@@ -630,6 +632,7 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
     prm.tau_task = (float)p.tau_task;
     prm.alpha = (float)p.alpha;
     prm.lambda2 = (float)(p.lambda * p.lambda);
+    prm.variant = p.variant;
     bool sup = false;
     e = launch_project_mode(dof, 1, robot->dev, con, prm, n_motions, d_q_from, d_q_to, mlp->delta,
                             d_xi, d_status, d_iters, (unsigned long long*)d_work, st, &sup);

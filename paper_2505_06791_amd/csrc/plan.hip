@@ -143,8 +143,11 @@ __device__ __forceinline__ bool try_motion(const RobotDev* __restrict__ rob, con
   for (int j = 0; j < NDOF; ++j) q[j] = a[j] + s * (b[j] - a[j]);
   int iters = 0;
   unsigned long long updates = 0;
-  const bool ok = project_segment<NDOF, KIND>(rob, con, prm, k, seg, wmask, segmask, !in_motion, q,
-                                              iters, updates);
+  const bool ok =
+      prm.variant == CP_PROJECT_SEQUENTIAL
+          ? project_sequential<NDOF, KIND>(rob, con, prm, k, seg, !in_motion, q, iters, updates)
+          : project_segment<NDOF, KIND>(rob, con, prm, k, seg, wmask, segmask, !in_motion, q,
+                                        iters, updates);
   if (!__shfl(ok ? 1 : 0, 0, 64)) return false;
   float* xk = scratch + (size_t)(in_motion ? lane : 0) * NDOF;
   if (in_motion) {
@@ -604,6 +607,7 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
     prm.tau_task = (float)pp.tau_task;
     prm.alpha = (float)pp.alpha;
     prm.lambda2 = (float)(pp.lambda * pp.lambda);
+    prm.variant = pp.variant;
 
     // endpoints: inside the limits (host), on the manifold and collision-free (device)
     for (int e = 0; e < 2; ++e) {
@@ -920,6 +924,7 @@ int cp_plan_batch(cp_batch* b, int32_t n, const cp_query* queries, cp_path* path
     prm.tau_task = (float)pp.tau_task;
     prm.alpha = (float)pp.alpha;
     prm.lambda2 = (float)(pp.lambda * pp.lambda);
+    prm.variant = pp.variant;
     const double tol = pp.tau + pp.tau_sm;
 
     // queries sorted by (DOF, constraint kind) class; slot k of the pools

@@ -13,19 +13,18 @@
 // rates are read straight off the rotation matrix (cos pitch = |(R00, R10)|,
 // sin pitch = -R20, yaw from R00/R10), so no trigonometry is needed there.
 //
-// Free axes are handled by zeroing their error and Jacobian rows and putting
-// 1 (instead of lambda^2) on their diagonal: the 6x6 system
-// (J J^T + D) y = e then leaves y = 0 on those rows, which is exactly the
-// step of the reduced m x m system (J_m J_m^T + lambda^2 I) y_m = e_m, also
-// for lambda = 0.  The factorisation is an unrolled Cholesky in registers.
+// Only the rows of locked axes are formed: the m x m system
+// (J_m J_m^T + lambda^2 I) y_m = e_m is factored by an unrolled Cholesky in
+// registers, with the free rows skipped by uniform branches on the mask.
 #pragma once
+#include "cprrtc.h"
 #include "device.h"
 
 namespace cprrtc {
 
 __device__ __forceinline__ float wrap_pi(float x) {
-  const float two_pi = 6.28318530717958647692f;
-  return x - two_pi * floorf((x + 3.14159265358979323846f) / two_pi);
+  const float two_pi = 6.28318530717958647692f, inv_two_pi = 0.15915494309189533577f;
+  return x - two_pi * floorf((x + 3.14159265358979323846f) * inv_two_pi);
 }
 
 template <int NDOF, int KIND>
@@ -38,6 +37,14 @@ __device__ __forceinline__ void task_step(const RobotDev* __restrict__ rob, cons
     einf = 0.0f;
     return;
   }
+  // Locked axes.  The mask is the same for every lane, so the tests below
+  // are uniform branches: rows of free axes are neither formed nor factored,
+  // and the work is that of the m x m system of the locked axes.
+  bool lock[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) lock[i] = con.mask[i] != 0.0f;
+  const bool any_ang = lock[3] || lock[4] || lock[5];
+
   // Forward kinematics: joint axes z_j and origins o_j, end effectors.
   float zx[NDOF], zy[NDOF], zz[NDOF], ox[NDOF], oy[NDOF], oz[NDOF];
   const int b1 = rob->n_chains > 1 ? rob->chain_begin[1] : NDOF;
@@ -58,7 +65,7 @@ __device__ __forceinline__ void task_step(const RobotDev* __restrict__ rob, cons
 
   // Frame the error is measured in: A1 = rotation from world to the
   // reference (Rc^T or R1^T), P1 = reference origin, E = end effector.
-  float A1[9], P1[3], Pe[3], Rp[9], pp[3];
+  float A1[9], P1[3], Pe[3], pp[3];
   if (KIND == KIND_POSE) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) A1[i] = con.Rt[i];
@@ -73,64 +80,59 @@ __device__ __forceinline__ void task_step(const RobotDev* __restrict__ rob, cons
     for (int i = 0; i < 3; ++i) { P1[i] = ee0.p[i]; Pe[i] = ee1.p[i]; }
   }
   const Frame& E2 = (KIND == KIND_POSE) ? ee0 : ee1;
-  // R' = A1 * R_E2, p' = A1 (Pe - P1)
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      Rp[3 * i + c] = A1[3 * i] * E2.r[c] + A1[3 * i + 1] * E2.r[3 + c] + A1[3 * i + 2] * E2.r[6 + c];
-  }
+  // p' = A1 (Pe - P1)
   const float dPx = Pe[0] - P1[0], dPy = Pe[1] - P1[1], dPz = Pe[2] - P1[2];
 #pragma unroll
   for (int i = 0; i < 3; ++i) pp[i] = A1[3 * i] * dPx + A1[3 * i + 1] * dPy + A1[3 * i + 2] * dPz;
 
-  // Rotation whose roll/pitch/yaw is measured, and the matrix taking world
-  // angular velocity into its frame (Aw).
-  float Re[9], Aw[9];
-  if (KIND == KIND_POSE) {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) { Re[i] = Rp[i]; Aw[i] = A1[i]; }
-  } else {
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        Re[3 * i + c] = con.Rt[3 * i] * Rp[c] + con.Rt[3 * i + 1] * Rp[3 + c] + con.Rt[3 * i + 2] * Rp[6 + c];
-        Aw[3 * i + c] = con.Rt[3 * i] * A1[c] + con.Rt[3 * i + 1] * A1[3 + c] + con.Rt[3 * i + 2] * A1[6 + c];
-      }
-  }
-  const float cp = sqrtf(Re[0] * Re[0] + Re[3] * Re[3]);
-  const float sp = -Re[6];
-  const float inv_cp = 1.0f / cp;
-  const float cy = Re[0] * inv_cp, sy = Re[3] * inv_cp;
-  const float roll = atan2f(Re[7], Re[8]);
-  const float pitch = atan2f(-Re[6], cp);
-  const float yaw = atan2f(Re[3], Re[0]);
-
   float e[6];
-  if (KIND == KIND_POSE) {
-    e[0] = pp[0] - con.target[0];
-    e[1] = pp[1] - con.target[1];
-    e[2] = pp[2] - con.target[2];
-    e[3] = wrap_pi(roll - con.target[3]);
-    e[4] = wrap_pi(pitch - con.target[4]);
-    e[5] = wrap_pi(yaw - con.target[5]);
-  } else {
-    e[0] = pp[0] - con.target[0];
-    e[1] = pp[1] - con.target[1];
-    e[2] = pp[2] - con.target[2];
-    e[3] = roll;
-    e[4] = pitch;
-    e[5] = yaw;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) e[i] = lock[i] ? pp[i] - con.target[i] : 0.0f;
+  e[3] = e[4] = e[5] = 0.0f;
+
+  // Orientation: R' = A1 R_E2, the rotation whose roll/pitch/yaw is measured
+  // (Re) and the matrix taking world angular velocity into its frame (Aw).
+  float Aw[9], cy = 1.0f, sy = 0.0f, sp = 0.0f, inv_cp = 1.0f;
+  if (any_ang) {
+    float Rp[9], Re[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        Rp[3 * i + c] = A1[3 * i] * E2.r[c] + A1[3 * i + 1] * E2.r[3 + c] + A1[3 * i + 2] * E2.r[6 + c];
+    }
+    if (KIND == KIND_POSE) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) { Re[i] = Rp[i]; Aw[i] = A1[i]; }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          Re[3 * i + c] = con.Rt[3 * i] * Rp[c] + con.Rt[3 * i + 1] * Rp[3 + c] + con.Rt[3 * i + 2] * Rp[6 + c];
+          Aw[3 * i + c] = con.Rt[3 * i] * A1[c] + con.Rt[3 * i + 1] * A1[3 + c] + con.Rt[3 * i + 2] * A1[6 + c];
+        }
+    }
+    const float cp = sqrtf(Re[0] * Re[0] + Re[3] * Re[3]);
+    sp = -Re[6];
+    inv_cp = __builtin_amdgcn_rcpf(cp);   // step direction only; decisions use e
+    cy = Re[0] * inv_cp;
+    sy = Re[3] * inv_cp;
+    if (KIND == KIND_POSE) {
+      if (lock[3]) e[3] = wrap_pi(atan2f(Re[7], Re[8]) - con.target[3]);
+      if (lock[4]) e[4] = wrap_pi(atan2f(-Re[6], cp) - con.target[4]);
+      if (lock[5]) e[5] = wrap_pi(atan2f(Re[3], Re[0]) - con.target[5]);
+    } else {
+      if (lock[3]) e[3] = atan2f(Re[7], Re[8]);
+      if (lock[4]) e[4] = atan2f(-Re[6], cp);
+      if (lock[5]) e[5] = atan2f(Re[3], Re[0]);
+    }
   }
   einf = 0.0f;
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
-    e[i] *= con.mask[i];
-    einf = fmaxf(einf, fabsf(e[i]));
-  }
+  for (int i = 0; i < 6; ++i) einf = fmaxf(einf, fabsf(e[i]));
 
-  // Jacobian columns.
+  // Jacobian rows of the locked axes.
   float J[6][NDOF];
   const float d21x = Pe[0] - P1[0], d21y = Pe[1] - P1[1], d21z = Pe[2] - P1[2];
 #pragma unroll
@@ -158,75 +160,72 @@ __device__ __forceinline__ void task_step(const RobotDev* __restrict__ rob, cons
       vx = cxp - vx; vy = cyp - vy; vz = czp - vz;
       sgn = -1.0f;
     }
-    if (KIND == KIND_POSE && !first) {
-      vx = vy = vz = wx = wy = wz = 0.0f;
+    const bool moves = !(KIND == KIND_POSE && !first);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (lock[i]) J[i][j] = moves ? A1[3 * i] * vx + A1[3 * i + 1] * vy + A1[3 * i + 2] * vz : 0.0f;
+    if (any_ang) {
+      const float da0 = sgn * (Aw[0] * wx + Aw[1] * wy + Aw[2] * wz);
+      const float da1 = sgn * (Aw[3] * wx + Aw[4] * wy + Aw[5] * wz);
+      const float da2 = sgn * (Aw[6] * wx + Aw[7] * wy + Aw[8] * wz);
+      const float rr = (cy * da0 + sy * da1) * inv_cp;
+      if (lock[3]) J[3][j] = moves ? rr : 0.0f;
+      if (lock[4]) J[4][j] = moves ? cy * da1 - sy * da0 : 0.0f;
+      if (lock[5]) J[5][j] = moves ? da2 + sp * rr : 0.0f;
     }
-    const float dp0 = A1[0] * vx + A1[1] * vy + A1[2] * vz;
-    const float dp1 = A1[3] * vx + A1[4] * vy + A1[5] * vz;
-    const float dp2 = A1[6] * vx + A1[7] * vy + A1[8] * vz;
-    const float da0 = sgn * (Aw[0] * wx + Aw[1] * wy + Aw[2] * wz);
-    const float da1 = sgn * (Aw[3] * wx + Aw[4] * wy + Aw[5] * wz);
-    const float da2 = sgn * (Aw[6] * wx + Aw[7] * wy + Aw[8] * wz);
-    const float rr = (cy * da0 + sy * da1) * inv_cp;
-    const float pr = cy * da1 - sy * da0;
-    const float yr = da2 + sp * rr;
-    J[0][j] = dp0 * con.mask[0];
-    J[1][j] = dp1 * con.mask[1];
-    J[2][j] = dp2 * con.mask[2];
-    J[3][j] = rr * con.mask[3];
-    J[4][j] = pr * con.mask[4];
-    J[5][j] = yr * con.mask[5];
   }
 
-  // (J J^T + lambda^2 I) y = e by Cholesky, g = J^T y.
-  float M[6][6];
-#pragma unroll
-  for (int a = 0; a < 6; ++a)
-#pragma unroll
-    for (int b = 0; b <= a; ++b) {
-      float s = (a == b) ? (con.mask[a] != 0.0f ? lambda2 : 1.0f) : 0.0f;
-#pragma unroll
-      for (int j = 0; j < NDOF; ++j) s += J[a][j] * J[b][j];
-      M[a][b] = s;
-    }
+  // (J J^T + lambda^2 I) y = e over the locked rows by Cholesky, g = J^T y.
+  // Entries that involve a free row are never read.
   float L[6][6], inv_diag[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    float s = M[c][c];
+    if (!lock[c]) continue;
+    float s = lambda2;
 #pragma unroll
-    for (int k = 0; k < c; ++k) s -= L[c][k] * L[c][k];
-    const float l = sqrtf(s);
-    L[c][c] = l;
-    inv_diag[c] = 1.0f / l;
+    for (int j = 0; j < NDOF; ++j) s += J[c][j] * J[c][j];
+#pragma unroll
+    for (int k = 0; k < c; ++k)
+      if (lock[k]) s -= L[c][k] * L[c][k];
+    inv_diag[c] = __builtin_amdgcn_rsqf(s);   // 1 / L[c][c]
 #pragma unroll
     for (int r = c + 1; r < 6; ++r) {
-      float t = M[r][c];
+      if (!lock[r]) continue;
+      float t = 0.0f;
 #pragma unroll
-      for (int k = 0; k < c; ++k) t -= L[r][k] * L[c][k];
+      for (int j = 0; j < NDOF; ++j) t += J[r][j] * J[c][j];
+#pragma unroll
+      for (int k = 0; k < c; ++k)
+        if (lock[k]) t -= L[r][k] * L[c][k];
       L[r][c] = t * inv_diag[c];
     }
   }
   float z[6], y[6];
 #pragma unroll
   for (int r = 0; r < 6; ++r) {
+    if (!lock[r]) continue;
     float s = e[r];
 #pragma unroll
-    for (int k = 0; k < r; ++k) s -= L[r][k] * z[k];
+    for (int k = 0; k < r; ++k)
+      if (lock[k]) s -= L[r][k] * z[k];
     z[r] = s * inv_diag[r];
   }
 #pragma unroll
   for (int r = 5; r >= 0; --r) {
+    if (!lock[r]) continue;
     float s = z[r];
 #pragma unroll
-    for (int k = r + 1; k < 6; ++k) s -= L[k][r] * y[k];
+    for (int k = r + 1; k < 6; ++k)
+      if (lock[k]) s -= L[k][r] * y[k];
     y[r] = s * inv_diag[r];
   }
 #pragma unroll
-  for (int j = 0; j < NDOF; ++j) {
-    float s = 0.0f;
+  for (int j = 0; j < NDOF; ++j) g[j] = 0.0f;
 #pragma unroll
-    for (int a = 0; a < 6; ++a) s += J[a][j] * y[a];
-    g[j] = s;
+  for (int a = 0; a < 6; ++a) {
+    if (!lock[a]) continue;
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) g[j] += J[a][j] * y[a];
   }
 }
 
@@ -261,10 +260,11 @@ __device__ __forceinline__ bool project_segment(const RobotDev* __restrict__ rob
       d2 += dl[j] * dl[j];
     }
     const float esm = sqrtf(d2) - prm.tau;
+    const float wsm = prm.variant == CP_PROJECT_INDEPENDENT ? 0.0f : esm;   // smoothing term
     float qn[NDOF];
 #pragma unroll
     for (int j = 0; j < NDOF; ++j)
-      qn[j] = fminf(fmaxf(q[j] - prm.alpha * (g[j] + dl[j] * esm), rob->lo[j]), rob->hi[j]);
+      qn[j] = fminf(fmaxf(q[j] - prm.alpha * (g[j] + dl[j] * wsm), rob->lo[j]), rob->hi[j]);
     const bool valid = idle || (k <= prog) || ((einf < prm.tau_task) && (esm < prm.tau_sm));
     const uint64_t bits = (__ballot(valid) & segmask) >> seg;
     const uint64_t invalid = ~bits & wmask;      // bits 0..prog are set
@@ -280,6 +280,66 @@ __device__ __forceinline__ bool project_segment(const RobotDev* __restrict__ rob
   }
   iters = prm.max_iters;
   return false;
+}
+
+// Sequential projection of the segment (CP_PROJECT_SEQUENTIAL): for
+// k = 1..W-1 in turn, lane k starts from the projected waypoint k-1 plus one
+// interpolation step (its straight-line value minus lane k-1's) and takes
+// damped least-squares steps, without the smoothing term, until its task
+// error and its spacing to waypoint k-1 are valid (checked before each step),
+// at most max_iters steps.  The other lanes of the segment wait.  q: in, the
+// straight-line value of this lane's waypoint; out, the projected value.
+// iters: steps summed over the waypoints (max_iters for each waypoint that
+// failed and every waypoint after it); updates += single-waypoint steps.
+template <int NDOF, int KIND>
+__device__ __forceinline__ bool project_sequential(const RobotDev* __restrict__ rob,
+                                                   const ConDev& con, const ProjDev& prm, int k,
+                                                   int seg, bool idle, float (&q)[NDOF],
+                                                   int& iters, unsigned long long& updates) {
+  const int W = prm.W;
+  float step[NDOF];
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) step[j] = q[j] - __shfl_up(q[j], 1, W);
+  int total = 0;
+  bool failed = false;   // this lane's segment has a waypoint that did not project
+  for (int kk = 1; kk < W; ++kk) {
+    // every lane runs every trip, so the shuffles always read active lanes
+    float prev[NDOF];
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) prev[j] = __shfl(q[j], seg + kk - 1, 64);
+    int used = 0;
+    bool valid = true;
+    if (k == kk && !failed && !idle) {
+#pragma unroll
+      for (int j = 0; j < NDOF; ++j) q[j] = prev[j] + step[j];
+      valid = false;
+      for (int it = 1; it <= prm.max_iters; ++it) {
+        float g[NDOF], einf;
+        task_step<NDOF, KIND>(rob, con, q, prm.lambda2, g, einf);
+        float d2 = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NDOF; ++j) d2 += (q[j] - prev[j]) * (q[j] - prev[j]);
+        const float esm = sqrtf(d2) - prm.tau;
+        used = it;
+        if (einf < prm.tau_task && esm < prm.tau_sm) {
+          valid = true;
+          break;
+        }
+#pragma unroll
+        for (int j = 0; j < NDOF; ++j)
+          q[j] = fminf(fmaxf(q[j] - prm.alpha * g[j], rob->lo[j]), rob->hi[j]);
+      }
+    }
+    // lane seg + kk decided for its segment
+    const bool seg_ok = __shfl(valid ? 1 : 0, seg + kk, 64) != 0;
+    const int seg_used = __shfl(used, seg + kk, 64);
+    if (!failed) total += seg_used;
+    if (!seg_ok) failed = true;
+    if (__ballot(!failed && !idle) == 0) break;   // uniform: no segment left to project
+  }
+  iters = total;
+  updates += (unsigned long long)total;
+  return !failed;
 }
 
 }  // namespace cprrtc

@@ -181,6 +181,22 @@ def test_project_validate_matches_oracle(G, name, W, M):
     _compare_pv(name, ref, xi, st, it, w, W, w["tau_task"])
 
 
+@pytest.mark.parametrize("name,W,variant", [("plain", 64, 1), ("cluttered", 64, 1),
+                                             ("plain", 64, 2), ("plain", 32, 2),
+                                             ("cluttered", 64, 2), ("mobile", 64, 2)])
+def test_projection_variants_match_oracle(G, name, W, variant):
+    """The independent (no smoothing) and sequential projection operators
+    against the oracle's, with the same band accounting."""
+    w = I.workload(name, 2100 + W + variant)
+    q_from, q_to = motion_set(w, 24, 13, W=W)
+    ro, eo, co = oracle_views(w)
+    prm = O.params(W=W, tau_task=w["tau_task"], variant=variant)
+    ref = O.project_validate_motions(ro, eo, co, prm, q_from.astype(np.float64),
+                                     q_to.astype(np.float64), n_threads=8)
+    xi, st, it = _run_pv(G, w, q_from, q_to, dict(W=W, tau_task=w["tau_task"], variant=variant))
+    _compare_pv(f"{name} variant {variant}", ref, xi, st, it, w, W, w["tau_task"])
+
+
 def test_project_validate_without_constraint_is_interpolation(G):
     w = I.workload("plain", 5)
     w["constraint"] = I.no_constraint()

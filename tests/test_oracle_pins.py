@@ -595,3 +595,88 @@ def test_plan_rounds_tree_invariants(oracle_lib):
             assert np.linalg.norm(q[i] - q[par[i]]) <= 63 * 0.075
         total += len(q) - 1
     assert total >= 1
+
+
+# ------------------------------------------------------------------ projection operators compared in the paper
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_variants_without_constraint_return_the_straight_line(oracle_lib, variant):
+    """No task constraint and straight spacing <= tau: the independent
+    projection returns its input bitwise after one iteration; the sequential
+    one rebuilds it from consecutive steps (to rounding) with one check per
+    waypoint."""
+    O = oracle_lib
+    rd = I.make_arm(3)
+    rob, c = O.Robot(rd), O.Constraint(I.no_constraint())
+    prm = O.params(W=64, variant=variant)
+    rng = np.random.default_rng(2)
+    for _ in range(4):
+        a = rng.uniform(-2, 2, 7)
+        v = rng.normal(size=7)
+        b = a + v / np.linalg.norm(v) * rng.uniform(0.1, 63 * 0.05)
+        xi0 = _segment(a, b, 64)
+        ok, xi, it, _ = O.project_motion(rob, c, prm, xi0)
+        assert ok
+        if variant == 1:
+            assert it == 1 and np.array_equal(xi, xi0)
+        else:
+            assert it == 63 and np.abs(xi - xi0).max() < 1e-13
+
+
+def test_sequential_joint1_motion_is_already_on_manifold(oracle_lib):
+    """Joint-1-only motion from an on-manifold start (joint 1 is vertical):
+    every waypoint is valid at its first check."""
+    O = oracle_lib
+    rd = I.make_arm(5)
+    rob, c = O.Robot(rd), O.Constraint(I.plane_upright(6))
+    prm = O.params(W=64, variant=2)
+    for q0 in _on_manifold(O, rob, c, rd, 3, 8):
+        b = q0.copy()
+        b[0] = np.clip(q0[0] + 1.5, -2.8, 2.8)
+        xi0 = _segment(q0, b, 64)
+        ok, xi, it, _ = O.project_motion(rob, c, prm, xi0)
+        assert ok and it == 63
+        assert np.abs(xi - xi0).max() < 1e-13
+
+
+def test_sequential_single_waypoint_is_the_single_configuration_projection(oracle_lib):
+    """W = 2: the one free waypoint is projected alone from the straight-line
+    end, which is the single-configuration projection (pinned above by its
+    convergence) whenever the spacing stays valid."""
+    O = oracle_lib
+    w = I.workload("plain", 31)
+    rob, c = O.Robot(w["robot"]), O.Constraint(w["constraint"])
+    tol = 1e-3
+    prm = O.params(W=2, tau=0.05, tau_sm=10.0, tau_task=tol, max_iters=32, variant=2)
+    starts = _on_manifold(O, rob, c, w["robot"], 6, 12)
+    ends = I.random_displacements(w["robot"], starts, 0.05, 13)
+    n = 0
+    for a, b in zip(starts, ends):
+        ok, xi, it, _ = O.project_motion(rob, c, prm, np.stack([a, b]))
+        ok1, q1, it1 = O.project_config(rob, c, b, tol=tol, max_iters=31)
+        assert ok == ok1
+        if ok:
+            assert it == it1 + 1            # checks = steps + 1
+            assert np.array_equal(xi[1], q1)
+            n += 1
+    assert n >= 3
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("name,W", [("plain", 64), ("cluttered", 32), ("mobile", 64)])
+def test_variant_output_invariants(oracle_lib, variant, name, W):
+    """Any segment either operator returns: start unchanged bitwise, every
+    waypoint within tolerance and limits, spacing below tau + tau_sm."""
+    O = oracle_lib
+    w = I.workload(name, 52)
+    rob, c = O.Robot(w["robot"]), O.Constraint(w["constraint"])
+    prm = O.params(W=W, tau_task=w["tau_task"], variant=variant)
+    starts = _on_manifold(O, rob, c, w["robot"], 10, 3)
+    ends = I.random_displacements(w["robot"], starts, (W - 1) * 0.05, 4)
+    n_ok = 0
+    for a, b in zip(starts, ends):
+        ok, xi, it, _ = O.project_motion(rob, c, prm, _segment(a, b, W))
+        if ok:
+            n_ok += 1
+            _check_projected(O, rob, c, prm, a, xi)
+    assert n_ok >= 1
