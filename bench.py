@@ -71,6 +71,37 @@ def update_flops(dof: int, m_pos: int, m_ang: int) -> int:
 FP32_VECTOR_PEAK_TFLOPS = 157.3    # MI355X, 256 CU x 2.4 GHz, packed FMA counted
 
 
+# HBM traffic of the projection kernel on this workload, from two rocprofv3
+# --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by
+# what the same counter reads for a plain 256 MiB device copy (FETCH_SIZE
+# reads 131083.5 KiB of 262144, WRITE_SIZE 262144 of 262144).  Valid only
+# for the kernel sources they were taken on.
+TRAFFIC = {
+    "kernel": "project_kernel<7, 1>",
+    "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
+                "paper_2505_06791_amd/csrc/kernels.hip"),
+    "sources_sha256": "81ce70e6a9c755aaff05a43f0a30f7223a2e91592824bf9b94e03cc313117db2",
+    "fetch_kib": 3754.3, "fetch_scale": 262144.0 / 131083.5,
+    "write_kib": 115713.0, "write_scale": 1.0,
+}
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the recorded counters, or None
+    when the kernel or its sources changed since they were taken."""
+    import hashlib
+    if kernel != TRAFFIC["kernel"]:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["sources_sha256"]:
+        return None
+    return (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"]
+            + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]) * 1024.0
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -472,7 +503,7 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": recorded_traffic(dom),
             "kernel": dom,
             "kernel_ms": dom_ms,
             "gflop_per_launch": flops / 1e9,
