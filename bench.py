@@ -472,7 +472,7 @@ def main():
     if val_ms >= proj_ms:
         dom, dom_ms, flops = "validate_kernel<8, true>", val_ms, val_flops
     else:
-        dom, dom_ms, flops = "project_kernel<7, 1>", proj_ms, proj_flops
+        dom, dom_ms, flops = "project_pool_kernel<7, 1, 0, 6>", proj_ms, proj_flops
     achieved = flops / (dom_ms * 1e-3) / 1e12
     verdicts = int((st != G.MOTION_PROJ_FAIL).sum())
     value = verdicts * (W - 1) / (ms_per_step * 1e-3)

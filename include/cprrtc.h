@@ -48,8 +48,12 @@ enum { CP_CON_NONE = 0, CP_CON_POSE = 1, CP_CON_REL_POSE = 2 };
 /* flags */
 enum {
   CP_NO_EARLY_EXIT = 1,  /* keep checking a motion / configuration after its first collision */
-  CP_NO_CULL = 2         /* project_validate_motions: test every primitive, without the
+  CP_NO_CULL = 2,        /* project_validate_motions: test every primitive, without the
                             wave-level bounding-box culling (verdicts are the same) */
+  CP_POOLED = 8,         /* project_validate_motions: project with several motions per
+                            wavefront whatever the batch size (results are the same) */
+  CP_PER_MOTION = 16     /* project_validate_motions: project with one motion per wavefront
+                            whatever the batch size (results are the same) */
 };
 
 /* ------------------------------------------------------------ descriptors */
@@ -171,7 +175,11 @@ int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const f
  * validated prefix frozen, damped least-squares task step, smoothing step
  * (||xi[k]-xi[k-1]|| - tau) (xi[k]-xi[k-1]), clamp to limits), then FK+CC of
  * waypoints 1..W-1 with an early exit of the whole motion on any collision.
- * Two kernels run on `stream`: projection, then validation.
+ * Two kernels run on `stream`: projection, then validation.  Batches of at
+ * least 24576 motions are projected with several motions per wavefront and
+ * only their unfrozen waypoints on its lanes, smaller ones with one motion
+ * per wavefront (flags CP_POOLED / CP_PER_MOTION force either; the results
+ * are identical).
  *   d_q_from, d_q_to [n_motions][dof] float32
  *   d_xi      [n_motions][W][dof] float32 out: projected segment (on
  *             CP_MOTION_PROJ_FAIL: the last iterate)

@@ -23,6 +23,7 @@ NO_EARLY_EXIT = 1
 NO_CULL = 2
 WARM_NO_FALLBACK = 4
 CP_TUNE_W = 1
+POOLED, PER_MOTION = 8, 16
 PROJECT_PARALLEL, PROJECT_INDEPENDENT, PROJECT_SEQUENTIAL = 0, 1, 2
 WORK_SLOTS = 8
 

@@ -326,7 +326,7 @@ int check_params(const cp_proj_params* params, cp_proj_params* p) {
 
 int do_project(const cp_robot* robot, const cp_constraint* constraint, const cp_proj_params& p,
                int32_t n_motions, const float* d_q_from, const float* d_q_to, float* d_xi,
-               int32_t* d_status, int32_t* d_iters, uint64_t* d_work, void* stream) {
+               int32_t* d_status, int32_t* d_iters, uint64_t* d_work, int32_t flags, void* stream) {
   if (!dof_supported(robot->host.dof))
     return fail(CP_E_UNSUPPORTED, "projection kernels are built for dof 2, 3, 6, 7, 9, 14 (got %d)", robot->host.dof);
   ConDev con;
@@ -342,10 +342,13 @@ int do_project(const cp_robot* robot, const cp_constraint* constraint, const cp_
   prm.tau_task = (float)p.tau_task;
   prm.alpha = (float)p.alpha;
   prm.lambda2 = (float)(p.lambda * p.lambda);
-    prm.variant = p.variant;
+  prm.variant = p.variant;
+  if ((flags & CP_POOLED) && (flags & CP_PER_MOTION))
+    return fail(CP_E_ARG, "CP_POOLED and CP_PER_MOTION together");
+  const int pooled = (flags & CP_POOLED) ? 1 : (flags & CP_PER_MOTION) ? 0 : -1;
   bool supported = false;
   hipError_t e = launch_project(robot->host.dof, robot->dev, con, prm, n_motions, d_q_from, d_q_to,
-                                d_xi, d_status, d_iters, (unsigned long long*)d_work,
+                                d_xi, d_status, d_iters, (unsigned long long*)d_work, pooled,
                                 (hipStream_t)stream, &supported);
   if (!supported) return fail(CP_E_UNSUPPORTED, "no kernel for dof %d with constraint kind %d", robot->host.dof, con.kind);
   if (e != hipSuccess) return hip_fail(e, "projection launch");
@@ -378,7 +381,7 @@ int project_motions(const cp_robot* robot, const cp_constraint* constraint,
     int rc = check_params(params, &p);
     if (rc != CP_OK) return rc;
     return do_project(robot, constraint, p, n_motions, d_q_from, d_q_to, d_xi, d_status, d_iters,
-                      d_work, stream);
+                      d_work, 0, stream);
   } catch (...) {
     return fail(CP_E_ARG, "project_motions: unexpected exception");
   }
@@ -411,7 +414,7 @@ int project_validate_motions(const cp_robot* robot, const cp_env* env,
     int rc = check_params(params, &p);
     if (rc != CP_OK) return rc;
     rc = do_project(robot, constraint, p, n_motions, d_q_from, d_q_to, d_xi, d_status, d_iters,
-                    d_work, stream);
+                    d_work, flags, stream);
     if (rc != CP_OK) return rc;
     return do_validate(robot, env, p, n_motions, d_xi, d_status, d_work, flags, stream);
   } catch (...) {

@@ -103,6 +103,34 @@ __device__ __forceinline__ void frame_advance(Frame& T, float ca, float sa, floa
   }
 }
 
+// sin and cos of a joint angle (|x| up to a few turns): x = k pi/2 + r with
+// |r| <= pi/4 by a two-constant Cody-Waite reduction (pi/2 split into a float
+// and its remainder), then the Taylor polynomials of sin r to r^9 and cos r
+// to r^10, whose truncation error on |r| <= pi/4 is below 2e-9; the quadrant
+// k mod 4 swaps and negates the pair.  Absolute error about 6e-8 (one unit
+// in the last place of 1), at roughly half the instructions of the general
+// library routine, which also handles huge arguments.
+__device__ __forceinline__ void sincos_joint(float x, float& s, float& c) {
+  const float k = rintf(x * 0.636619772367581343f);
+  float r = fmaf(-k, 1.57079637050628662109375f, x);
+  r = fmaf(-k, -4.37113900018624283e-8f, r);
+  const float r2 = r * r;
+  float ps = fmaf(r2, 2.75573192e-6f, -1.98412698e-4f);   // 1/9!, -1/7!
+  ps = fmaf(r2, ps, 8.33333333e-3f);                       // 1/5!
+  ps = fmaf(r2, ps, -1.66666667e-1f);                      // -1/3!
+  const float sr = fmaf(r * r2, ps, r);
+  float pc = fmaf(r2, -2.75573192e-7f, 2.48015873e-5f);   // -1/10!, 1/8!
+  pc = fmaf(r2, pc, -1.38888889e-3f);                      // -1/6!
+  pc = fmaf(r2, pc, 4.16666667e-2f);                       // 1/4!
+  pc = fmaf(r2, pc, -0.5f);                                // -1/2!
+  const float cr = fmaf(r2, pc, 1.0f);
+  const int q = (int)k;
+  const float a = (q & 1) ? cr : sr;
+  const float b = (q & 1) ? sr : cr;
+  s = (q & 2) ? -a : a;
+  c = ((q + 1) & 2) ? -b : b;
+}
+
 // Joint j of the robot at joint value qj.
 __device__ __forceinline__ void joint_advance(Frame& T, const RobotDev* __restrict__ rob, int j,
                                               float qj) {
@@ -110,7 +138,7 @@ __device__ __forceinline__ void joint_advance(Frame& T, const RobotDev* __restri
   const float theta = rob->th0[j] + (pri ? 0.0f : qj);
   const float d = rob->d0[j] + (pri ? qj : 0.0f);
   float st, ct;
-  sincosf(theta, &st, &ct);
+  sincos_joint(theta, st, ct);
   frame_advance(T, rob->ca[j], rob->sa[j], rob->a[j], ct, st, d);
 }
 

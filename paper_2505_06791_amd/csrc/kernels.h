@@ -13,16 +13,18 @@ hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& en
                         const float* q, uint8_t* collide, float* min_sd, bool early, int batch,
                         hipStream_t stream);
 
+// pooled: 1 = several motions per wavefront, 0 = one motion per wavefront,
+// -1 = by batch size.
 hipError_t launch_project(int dof, const RobotDev* rob, const ConDev& con, const ProjDev& prm,
                           int n_motions, const float* q_from, const float* q_to, float* xi,
-                          int* status, int* iters, unsigned long long* work, hipStream_t stream,
-                          bool* supported);
+                          int* status, int* iters, unsigned long long* work, int pooled,
+                          hipStream_t stream, bool* supported);
 
 hipError_t launch_project_mode(int dof, int mode, const RobotDev* rob, const ConDev& con,
                                const ProjDev& prm, int n_motions, const float* q_from,
                                const float* q_to, const float* delta, float* xi, int* status,
-                               int* iters, unsigned long long* work, hipStream_t stream,
-                               bool* supported);
+                               int* iters, unsigned long long* work, int pooled,
+                               hipStream_t stream, bool* supported);
 
 hipError_t launch_validate(const RobotDev* rob, const float4* sph, const EnvDev& env, int W,
                            int n_motions, const float* xi, int* status, unsigned long long* work,

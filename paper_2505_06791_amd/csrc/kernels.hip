@@ -1,21 +1,25 @@
 // gfx950 kernels of the hot path: fk_cc_batch, project_validate_motions
 // (a projection kernel followed by a validation kernel on the same stream),
-// project_configs.  Launch geometry is 256-lane workgroups (4 wavefronts of
-// 64); a motion of W waypoints occupies W consecutive lanes of one
-// wavefront (W = 64: one wavefront per motion, W = 32: two motions per
-// wavefront), so every exchange inside a motion is a wavefront operation
-// (shuffle for the neighbouring waypoint, ballot for validity and for the
-// collision flag) and needs neither LDS nor a barrier.
+// project_configs.
+//
+// Validation (and fk_cc): a motion of W waypoints occupies W consecutive
+// lanes of one wavefront (W = 64: one wavefront per motion, W = 32: two), so
+// the collision flag is a ballot and needs neither LDS nor a barrier.
+//
+// Projection: a wavefront holds several motions in LDS and spreads only the
+// waypoints that are still being projected over its lanes (project_pool_kernel);
+// a one-motion-per-wavefront form (project_kernel) serves the sequential
+// operator, whose waypoints wait for each other anyway.
 //
 // Projection and validation are separate kernels because their register
-// needs differ by ~2x: the projection holds a 6 x n Jacobian and a 6 x 6
-// factor per lane, the collision loop a batch of sphere centres; fused, the
-// collision loop would run at the projection's occupancy.  The projected
-// segment goes through HBM between them (W * dof * 4 bytes per motion,
-// written anyway as the call's output).
+// needs differ: fused, the collision loop would run at the projection's
+// occupancy.  The projected segment goes through HBM between them
+// (W * dof * 4 bytes per motion, written anyway as the call's output).
 #include "kernels.h"
 
 #include <float.h>
+
+#include <algorithm>
 
 #include "collide.h"
 #include "project.h"
@@ -109,6 +113,152 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
   }
 }
 
+// Pooled projection (modes 0-2): one wavefront keeps S motions in LDS and,
+// every iteration, spreads only their active waypoints (k > prog) over its 64
+// lanes in rounds of 64, so no lane spends an iteration on a frozen prefix.
+// Item i of an iteration is waypoint prog_s + 1 + (i - off_s) of slot s
+// (off = prefix sums of the slots' active counts).  Each item reads its
+// waypoint and the previous one from the slot's snapshot in LDS and computes
+// the same update as project_segment.  A slot's new prog is the number of
+// leading valid items (first invalid item from the rounds' ballots); items
+// past it take their new values, written as soon as their round is judged
+// (the one waypoint a later round still reads from the snapshot is carried
+// over in registers).  A finished motion (success, or failure
+// after max_iters) is written out and its slot refilled from the
+// wavefront's share of the motions: blockIdx.x, + gridDim.x, ...
+template <int NDOF, int KIND, int MODE, int S>
+__global__ __launch_bounds__(64) void project_pool_kernel(
+    const RobotDev* __restrict__ rob, ConDev con, ProjDev prm, int n_motions,
+    const float* __restrict__ q_from, const float* __restrict__ q_to,
+    const float* __restrict__ delta, float* __restrict__ xi, int* __restrict__ status,
+    int* __restrict__ iters, unsigned long long* __restrict__ work) {
+  __shared__ float sx[S][64][NDOF];
+  const int lane = threadIdx.x;
+  const int W = prm.W;
+  const int stride = gridDim.x;
+  int next = blockIdx.x;                 // wavefront-uniform local queue
+  int mot[S], prog[S], its[S];
+  unsigned long long updates = 0;
+
+  // Fills slot s with the wavefront's next motion (straight-line segment,
+  // plus the network's correction in MODE 1); mot[s] = -1 when none is left.
+  auto fetch = [&](int s) {
+    int m = -1;
+    while (next < n_motions) {
+      const int cand = next;
+      next += stride;
+      if (MODE != 2 || status[cand] == 1) {
+        m = cand;
+        break;
+      }
+    }
+    mot[s] = m;
+    prog[s] = 0;
+    its[s] = 0;
+    if (m >= 0 && lane < W) {
+      const float t = (float)lane / (float)(W - 1);
+#pragma unroll
+      for (int j = 0; j < NDOF; ++j) {
+        const float a = q_from[(int64_t)m * NDOF + j];
+        const float b = q_to[(int64_t)m * NDOF + j];
+        float v = a + t * (b - a);
+        if (MODE == 1 && lane >= 1)
+          v = fminf(fmaxf(v + delta[((int64_t)m * (W - 1) + (lane - 1)) * NDOF + j], rob->lo[j]), rob->hi[j]);
+        sx[s][lane][j] = v;
+      }
+    }
+  };
+
+#pragma unroll
+  for (int s = 0; s < S; ++s) fetch(s);
+  __syncthreads();
+
+  while (true) {
+    int off[S + 1];
+    off[0] = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) off[s + 1] = off[s] + (mot[s] >= 0 ? W - 1 - prog[s] : 0);
+    const int A = off[S];
+    if (A == 0) break;                   // every slot empty: the share is done
+    updates += (unsigned long long)A;
+
+    int first_bad[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) first_bad[s] = W;
+    float carry[NDOF];                   // snapshot of the previous round's last item
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) carry[j] = 0.0f;
+    for (int base = 0; base < A; base += 64) {   // uniform trip count
+      const int i = base + lane;
+      const bool on = i < A;
+      int si = 0, sp = prog[0], so = off[0];
+#pragma unroll
+      for (int s = 1; s < S; ++s)
+        if (i >= off[s]) { si = s; sp = prog[s]; so = off[s]; }
+      const int k = on ? sp + 1 + (i - so) : 1;
+      // Items are consecutive waypoints of their slot, so only the first
+      // lane can need a waypoint that the previous round already moved: it
+      // takes that round's snapshot value (carry) instead.
+      const bool from_carry = lane == 0 && base > 0 && i - 1 >= so;
+      float q[NDOF], qp[NDOF], qn[NDOF];
+#pragma unroll
+      for (int j = 0; j < NDOF; ++j) {
+        q[j] = sx[si][k][j];
+        qp[j] = from_carry ? carry[j] : sx[si][k - 1][j];
+      }
+      bool valid = true;
+      if (on) valid = waypoint_update<NDOF, KIND>(rob, con, prm, q, qp, qn);
+      const uint64_t inv = __ballot(on && !valid);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int lo = max(off[s] - base, 0), hi = min(off[s + 1] - base, 64);
+        if (lo < hi && first_bad[s] == W) {
+          const uint64_t span = (hi - lo == 64) ? ~0ull : (((1ull << (hi - lo)) - 1ull) << lo);
+          const uint64_t m = inv & span;
+          if (m) first_bad[s] = base + (__ffsll((unsigned long long)m) - 1) - off[s];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NDOF; ++j) carry[j] = __shfl(q[j], 63, 64);
+      // Every item before this one in its slot has been judged: it moves
+      // iff an invalid item precedes it or is it (it lies past the new prog).
+      int fb = first_bad[0];
+#pragma unroll
+      for (int s = 1; s < S; ++s)
+        if (si == s) fb = first_bad[s];
+      if (on && i - so >= fb) {
+#pragma unroll
+        for (int j = 0; j < NDOF; ++j) sx[si][k][j] = qn[j];
+      }
+    }
+    int newprog[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) newprog[s] = prog[s] + min(first_bad[s], W - 1 - prog[s]);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      if (mot[s] < 0) continue;
+      its[s] += 1;
+      prog[s] = newprog[s];
+      const bool ok = prog[s] == W - 1;
+      if (!ok && its[s] < prm.max_iters) continue;
+      const int m = mot[s];
+      if (lane < W) {
+#pragma unroll
+        for (int j = 0; j < NDOF; ++j) xi[((int64_t)m * W + lane) * NDOF + j] = sx[s][lane][j];
+      }
+      if (lane == 0) {
+        status[m] = ok ? 0 : 1;
+        if (iters) iters[m] = (MODE == 2 ? iters[m] : 0) + (ok ? its[s] : prm.max_iters);
+      }
+      __syncthreads();                   // the slot is read out before it is refilled
+      fetch(s);
+    }
+    __syncthreads();
+  }
+  if (work && lane == 0) atomicAdd(&work[6], updates);
+}
+
 // ------------------------------------------------------------------ validation (FK + CC of projected segments)
 
 // Waypoints 1..W-1 of every motion whose projection succeeded (status 0 from
@@ -195,36 +345,61 @@ hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& en
   return hipGetLastError();
 }
 
+// Motions per pooled wavefront and the number of wavefronts.  Measured on
+// the cluttered 65 536-motion batch (slots x wavefront cap): many short
+// wavefronts that take their slots' motions once balance best (6 slots,
+// up to 64 wavefronts per CU: 1.67 ms; 4 x 16 with refills: 2.08 ms; the
+// one-motion-per-wavefront kernel: 2.53 ms).
+constexpr int kPoolSlots = 6;
+// Below this many motions the pooled form has too few wavefronts to fill the
+// chip (fewer than 4 per SIMD) and one motion per wavefront is used.
+constexpr int kPoolMinMotions = kPoolSlots * 4 * 1024;
+static unsigned pool_blocks(int n) {
+  const int per = (n + kPoolSlots - 1) / kPoolSlots;
+  return (unsigned)std::max(1, std::min(per, 256 * 64));
+}
+
 template <int NDOF, int KIND>
-static void launch_project_kind(int mode, unsigned nb, hipStream_t stream, const RobotDev* rob,
-                                const ConDev& con, const ProjDev& prm, int n, const float* qf,
-                                const float* qt, const float* delta, float* xi, int* st, int* it,
-                                unsigned long long* work) {
+static void launch_project_kind(int mode, int pooled, unsigned nb, hipStream_t stream,
+                                const RobotDev* rob, const ConDev& con, const ProjDev& prm, int n,
+                                const float* qf, const float* qt, const float* delta, float* xi,
+                                int* st, int* it, unsigned long long* work) {
+  const bool pool = mode != 3 && (pooled == 1 || (pooled < 0 && n >= kPoolMinMotions));
+  if (!pool) {
+    if (mode == 1)
+      project_kernel<NDOF, KIND, 1><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+    else if (mode == 2)
+      project_kernel<NDOF, KIND, 2><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+    else if (mode == 3)
+      project_kernel<NDOF, KIND, 3><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+    else
+      project_kernel<NDOF, KIND, 0><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+    return;
+  }
+  const unsigned np = pool_blocks(n);
   if (mode == 1)
-    project_kernel<NDOF, KIND, 1><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
-  else if (mode == 3)
-    project_kernel<NDOF, KIND, 3><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+    project_pool_kernel<NDOF, KIND, 1, kPoolSlots><<<np, 64, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
   else if (mode == 2)
-    project_kernel<NDOF, KIND, 2><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+    project_pool_kernel<NDOF, KIND, 2, kPoolSlots><<<np, 64, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
   else
-    project_kernel<NDOF, KIND, 0><<<nb, kBlock, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+    project_pool_kernel<NDOF, KIND, 0, kPoolSlots><<<np, 64, 0, stream>>>(rob, con, prm, n, qf, qt, delta, xi, st, it, work);
 }
 
 template <int NDOF>
-static bool launch_project_ndof(int kind, int mode, unsigned nb, hipStream_t stream,
+static bool launch_project_ndof(int kind, int mode, int pooled, unsigned nb, hipStream_t stream,
                                 const RobotDev* rob, const ConDev& con, const ProjDev& prm, int n,
                                 const float* qf, const float* qt, const float* delta, float* xi,
                                 int* st, int* it, unsigned long long* work) {
   switch (kind) {
     case KIND_NONE:
-      launch_project_kind<NDOF, KIND_NONE>(mode, nb, stream, rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+      launch_project_kind<NDOF, KIND_NONE>(mode, pooled, nb, stream, rob, con, prm, n, qf, qt, delta, xi, st, it, work);
       return true;
     case KIND_POSE:
-      launch_project_kind<NDOF, KIND_POSE>(mode, nb, stream, rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+      launch_project_kind<NDOF, KIND_POSE>(mode, pooled, nb, stream, rob, con, prm, n, qf, qt, delta, xi, st, it, work);
       return true;
     case KIND_REL:
       if constexpr (NDOF % 2 == 0) {
-        launch_project_kind<NDOF, KIND_REL>(mode, nb, stream, rob, con, prm, n, qf, qt, delta, xi, st, it, work);
+        launch_project_kind<NDOF, KIND_REL>(mode, pooled, nb, stream, rob, con, prm, n, qf, qt, delta, xi, st, it, work);
         return true;
       }
       return false;
@@ -242,17 +417,17 @@ bool dof_supported(int dof) {
 hipError_t launch_project_mode(int dof, int mode, const RobotDev* rob, const ConDev& con,
                                const ProjDev& prm, int n_motions, const float* q_from,
                                const float* q_to, const float* delta, float* xi, int* status,
-                               int* iters, unsigned long long* work, hipStream_t stream,
-                               bool* supported) {
+                               int* iters, unsigned long long* work, int pooled,
+                               hipStream_t stream, bool* supported) {
   const unsigned nb = blocks_for((int64_t)n_motions * prm.W);
   bool ok = false;
   switch (dof) {
-    case 2: ok = launch_project_ndof<2>(con.kind, mode, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
-    case 3: ok = launch_project_ndof<3>(con.kind, mode, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
-    case 6: ok = launch_project_ndof<6>(con.kind, mode, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
-    case 7: ok = launch_project_ndof<7>(con.kind, mode, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
-    case 9: ok = launch_project_ndof<9>(con.kind, mode, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
-    case 14: ok = launch_project_ndof<14>(con.kind, mode, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
+    case 2: ok = launch_project_ndof<2>(con.kind, mode, pooled, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
+    case 3: ok = launch_project_ndof<3>(con.kind, mode, pooled, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
+    case 6: ok = launch_project_ndof<6>(con.kind, mode, pooled, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
+    case 7: ok = launch_project_ndof<7>(con.kind, mode, pooled, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
+    case 9: ok = launch_project_ndof<9>(con.kind, mode, pooled, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
+    case 14: ok = launch_project_ndof<14>(con.kind, mode, pooled, nb, stream, rob, con, prm, n_motions, q_from, q_to, delta, xi, status, iters, work); break;
     default: ok = false;
   }
   *supported = ok;
@@ -261,11 +436,11 @@ hipError_t launch_project_mode(int dof, int mode, const RobotDev* rob, const Con
 
 hipError_t launch_project(int dof, const RobotDev* rob, const ConDev& con, const ProjDev& prm,
                           int n_motions, const float* q_from, const float* q_to, float* xi,
-                          int* status, int* iters, unsigned long long* work, hipStream_t stream,
-                          bool* supported) {
+                          int* status, int* iters, unsigned long long* work, int pooled,
+                          hipStream_t stream, bool* supported) {
   return launch_project_mode(dof, prm.variant == CP_PROJECT_SEQUENTIAL ? 3 : 0, rob, con, prm,
-                             n_motions, q_from, q_to, nullptr, xi, status, iters, work, stream,
-                             supported);
+                             n_motions, q_from, q_to, nullptr, xi, status, iters, work, pooled,
+                             stream, supported);
 }
 
 hipError_t launch_validate(const RobotDev* rob, const float4* sph, const EnvDev& env, int W,

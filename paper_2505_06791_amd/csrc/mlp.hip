@@ -635,10 +635,10 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
     prm.variant = p.variant;
     bool sup = false;
     e = launch_project_mode(dof, 1, robot->dev, con, prm, n_motions, d_q_from, d_q_to, mlp->delta,
-                            d_xi, d_status, d_iters, (unsigned long long*)d_work, st, &sup);
+                            d_xi, d_status, d_iters, (unsigned long long*)d_work, -1, st, &sup);
     if (e == hipSuccess && sup && !(flags & CP_WARM_NO_FALLBACK))
       e = launch_project_mode(dof, 2, robot->dev, con, prm, n_motions, d_q_from, d_q_to, nullptr,
-                              d_xi, d_status, d_iters, (unsigned long long*)d_work, st, &sup);
+                              d_xi, d_status, d_iters, (unsigned long long*)d_work, -1, st, &sup);
     if (!sup) return api_fail(CP_E_UNSUPPORTED, "no kernel for dof %d with constraint kind %d", dof, con.kind);
     if (e != hipSuccess) return api_hip_fail(e, "project_motions_warm projection");
     return CP_OK;

@@ -27,6 +27,31 @@ __device__ __forceinline__ float wrap_pi(float x) {
   return x - two_pi * floorf((x + 3.14159265358979323846f) * inv_two_pi);
 }
 
+// atan2 for the orientation error: t = min(|x|,|y|) / max(|x|,|y|) in [0, 1];
+// above tan(pi/8) the identity atan t = pi/4 + atan((t - 1) / (t + 1)) brings
+// the argument into [-tan(pi/8), tan(pi/8)], where the Taylor series of atan
+// to z^15 is within 2e-8; the octant then follows from |y| > |x|, the sign of
+// x and the sign of y.  Error about one unit in the last place of the result.
+__device__ __forceinline__ float atan2_task(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mn = fminf(ax, ay), mx = fmaxf(ax, ay);
+  const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+  const bool big = t > 0.414213562373095049f;
+  const float z = big ? (t - 1.0f) * __builtin_amdgcn_rcpf(t + 1.0f) : t;
+  const float z2 = z * z;
+  float p = fmaf(z2, -1.0f / 15.0f, 1.0f / 13.0f);
+  p = fmaf(z2, p, -1.0f / 11.0f);
+  p = fmaf(z2, p, 1.0f / 9.0f);
+  p = fmaf(z2, p, -1.0f / 7.0f);
+  p = fmaf(z2, p, 1.0f / 5.0f);
+  p = fmaf(z2, p, -1.0f / 3.0f);
+  p = fmaf(z2, p, 1.0f);
+  float r = fmaf(z, p, big ? 0.785398163397448310f : 0.0f);
+  if (ay > ax) r = 1.57079632679489662f - r;
+  if (x < 0.0f) r = 3.14159265358979324f - r;
+  return copysignf(r, y);
+}
+
 template <int NDOF, int KIND>
 __device__ __forceinline__ void task_step(const RobotDev* __restrict__ rob, const ConDev& con,
                                           const float (&q)[NDOF], float lambda2,
@@ -119,13 +144,13 @@ __device__ __forceinline__ void task_step(const RobotDev* __restrict__ rob, cons
     cy = Re[0] * inv_cp;
     sy = Re[3] * inv_cp;
     if (KIND == KIND_POSE) {
-      if (lock[3]) e[3] = wrap_pi(atan2f(Re[7], Re[8]) - con.target[3]);
-      if (lock[4]) e[4] = wrap_pi(atan2f(-Re[6], cp) - con.target[4]);
-      if (lock[5]) e[5] = wrap_pi(atan2f(Re[3], Re[0]) - con.target[5]);
+      if (lock[3]) e[3] = wrap_pi(atan2_task(Re[7], Re[8]) - con.target[3]);
+      if (lock[4]) e[4] = wrap_pi(atan2_task(-Re[6], cp) - con.target[4]);
+      if (lock[5]) e[5] = wrap_pi(atan2_task(Re[3], Re[0]) - con.target[5]);
     } else {
-      if (lock[3]) e[3] = atan2f(Re[7], Re[8]);
-      if (lock[4]) e[4] = atan2f(-Re[6], cp);
-      if (lock[5]) e[5] = atan2f(Re[3], Re[0]);
+      if (lock[3]) e[3] = atan2_task(Re[7], Re[8]);
+      if (lock[4]) e[4] = atan2_task(-Re[6], cp);
+      if (lock[5]) e[5] = atan2_task(Re[3], Re[0]);
     }
   }
   einf = 0.0f;
@@ -238,6 +263,39 @@ __device__ __forceinline__ void task_step(const RobotDev* __restrict__ rob, cons
 // their new value.  `idle` lanes (outside any motion) count as valid so that
 // their segment finishes at once.  Returns true on success; iters = iterations
 // used (max_iters on failure); updates += waypoint updates computed.
+// One waypoint update of Algorithm 1 from the snapshot: q = xi[k], qprev =
+// xi[k-1].  qn receives the new value (task step, smoothing term unless the
+// operator is the independent one, clamp to the limits); returns the
+// waypoint's validity at q (task error and spacing).
+template <int NDOF, int KIND>
+__device__ __forceinline__ bool waypoint_update(const RobotDev* __restrict__ rob, const ConDev& con,
+                                                const ProjDev& prm, const float (&q)[NDOF],
+                                                const float (&qprev)[NDOF], float (&qn)[NDOF]) {
+  float g[NDOF], einf;
+  task_step<NDOF, KIND>(rob, con, q, prm.lambda2, g, einf);
+  float d2 = 0.0f, dl[NDOF];
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) {
+    dl[j] = q[j] - qprev[j];
+    d2 += dl[j] * dl[j];
+  }
+  const float esm = sqrtf(d2) - prm.tau;
+  const float wsm = prm.variant == CP_PROJECT_INDEPENDENT ? 0.0f : esm;   // smoothing term
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j)
+    qn[j] = fminf(fmaxf(q[j] - prm.alpha * (g[j] + dl[j] * wsm), rob->lo[j]), rob->hi[j]);
+  return (einf < prm.tau_task) && (esm < prm.tau_sm);
+}
+
+// Algorithm 1 on the W-lane segment this lane belongs to (Jacobi form).
+// q: this lane's waypoint xi[k]; in: the straight-line value, out: the
+// projected value (success) or the last iterate.  Each active lane computes its
+// update from the snapshot (its own xi[k] and xi[k-1] from a shuffle before
+// anyone writes); validity is gathered with one ballot; prog moves to the end
+// of the contiguous valid run after it; only lanes past the new prog take
+// their new value.  `idle` lanes (outside any motion) count as valid so that
+// their segment finishes at once.  Returns true on success; iters = iterations
+// used (max_iters on failure); updates += waypoint updates computed.
 template <int NDOF, int KIND>
 __device__ __forceinline__ bool project_segment(const RobotDev* __restrict__ rob, const ConDev& con,
                                                 const ProjDev& prm, int k, int seg,
@@ -251,21 +309,9 @@ __device__ __forceinline__ bool project_segment(const RobotDev* __restrict__ rob
     float qprev[NDOF];
 #pragma unroll
     for (int j = 0; j < NDOF; ++j) qprev[j] = __shfl_up(q[j], 1, W);
-    float g[NDOF], einf;
-    task_step<NDOF, KIND>(rob, con, q, prm.lambda2, g, einf);
-    float d2 = 0.0f, dl[NDOF];
-#pragma unroll
-    for (int j = 0; j < NDOF; ++j) {
-      dl[j] = q[j] - qprev[j];
-      d2 += dl[j] * dl[j];
-    }
-    const float esm = sqrtf(d2) - prm.tau;
-    const float wsm = prm.variant == CP_PROJECT_INDEPENDENT ? 0.0f : esm;   // smoothing term
     float qn[NDOF];
-#pragma unroll
-    for (int j = 0; j < NDOF; ++j)
-      qn[j] = fminf(fmaxf(q[j] - prm.alpha * (g[j] + dl[j] * wsm), rob->lo[j]), rob->hi[j]);
-    const bool valid = idle || (k <= prog) || ((einf < prm.tau_task) && (esm < prm.tau_sm));
+    const bool ok = waypoint_update<NDOF, KIND>(rob, con, prm, q, qprev, qn);
+    const bool valid = idle || (k <= prog) || ok;
     const uint64_t bits = (__ballot(valid) & segmask) >> seg;
     const uint64_t invalid = ~bits & wmask;      // bits 0..prog are set
     prog = invalid ? (__ffsll((unsigned long long)invalid) - 2) : W - 1;

@@ -197,6 +197,37 @@ def test_projection_variants_match_oracle(G, name, W, variant):
     _compare_pv(f"{name} variant {variant}", ref, xi, st, it, w, W, w["tau_task"])
 
 
+@pytest.mark.parametrize("name,W,variant", [("plain", 64, 0), ("plain", 32, 0), ("cluttered", 64, 0),
+                                             ("dual", 64, 0), ("mobile", 32, 1),
+                                             ("cluttered", 64, 1)])
+def test_pooled_and_per_motion_projection_agree(G, name, W, variant):
+    """The pooled projection (several motions per wavefront, only unfrozen
+    waypoints on lanes) and the one-motion-per-wavefront form compute the
+    same updates: segments, statuses and iterations are equal bit for bit,
+    and the pooled results meet the oracle."""
+    w = I.workload(name, 2200 + W + variant)
+    q_from, q_to = motion_set(w, 41, 17, W=W)
+    kw = dict(W=W, tau_task=w["tau_task"], variant=variant)
+    xi_p, st_p, it_p = _run_pv(G, w, q_from, q_to, kw, flags=G.POOLED)
+    xi_m, st_m, it_m = _run_pv(G, w, q_from, q_to, kw, flags=G.PER_MOTION)
+    assert np.array_equal(xi_p, xi_m)
+    assert np.array_equal(st_p, st_m)
+    assert np.array_equal(it_p, it_m)
+    ro, eo, co = oracle_views(w)
+    prm = O.params(W=W, tau_task=w["tau_task"], variant=variant)
+    ref = O.project_validate_motions(ro, eo, co, prm, q_from.astype(np.float64),
+                                     q_to.astype(np.float64), n_threads=8)
+    _compare_pv(f"{name} pooled", ref, xi_p, st_p, it_p, w, W, w["tau_task"])
+
+
+def test_pooled_flags_are_exclusive(G):
+    w = I.workload("plain", 1000)
+    q_from, q_to = motion_set(w, 2, 3)
+    with pytest.raises(G.CprrtcError) as ex:
+        _run_pv(G, w, q_from, q_to, dict(W=64), flags=G.POOLED | G.PER_MOTION)
+    assert ex.value.code == G.CP_E_ARG
+
+
 def test_project_validate_without_constraint_is_interpolation(G):
     w = I.workload("plain", 5)
     w["constraint"] = I.no_constraint()
