@@ -77,12 +77,12 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3    # MI355X, 256 CU x 2.4 GHz, packed FMA counte
 # reads 131083.5 KiB of 262144, WRITE_SIZE 262144 of 262144).  Valid only
 # for the kernel sources they were taken on.
 TRAFFIC = {
-    "kernel": "project_kernel<7, 1>",
+    "kernel": "project_pool_kernel<7, 1, 0, 6>",
     "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                 "paper_2505_06791_amd/csrc/kernels.hip"),
-    "sources_sha256": "81ce70e6a9c755aaff05a43f0a30f7223a2e91592824bf9b94e03cc313117db2",
-    "fetch_kib": 3754.3, "fetch_scale": 262144.0 / 131083.5,
-    "write_kib": 115713.0, "write_scale": 1.0,
+    "sources_sha256": "3889924350551fd92538324037568b9486c9bd6de7ccdb92cb3ae6fd7bc85c3f",
+    "fetch_kib": 4959.8, "fetch_scale": 262144.0 / 131083.5,
+    "write_kib": 116022.8, "write_scale": 1.0,
 }
 
 

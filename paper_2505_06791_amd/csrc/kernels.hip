@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void project_kernel(
 // (the one waypoint a later round still reads from the snapshot is carried
 // over in registers).  A finished motion (success, or failure
 // after max_iters) is written out and its slot refilled from the
-// wavefront's share of the motions: blockIdx.x, + gridDim.x, ...
+// wavefront's share of the motions (a contiguous run).
 template <int NDOF, int KIND, int MODE, int S>
 __global__ __launch_bounds__(64) void project_pool_kernel(
     const RobotDev* __restrict__ rob, ConDev con, ProjDev prm, int n_motions,
@@ -135,8 +135,11 @@ __global__ __launch_bounds__(64) void project_pool_kernel(
   __shared__ float sx[S][64][NDOF];
   const int lane = threadIdx.x;
   const int W = prm.W;
-  const int stride = gridDim.x;
-  int next = blockIdx.x;                 // wavefront-uniform local queue
+  // this wavefront's share: a contiguous run of motions, so that the
+  // wavefronts of a neighbourhood read and write neighbouring lines
+  const int chunk = (n_motions + (int)gridDim.x - 1) / (int)gridDim.x;
+  int next = (int)blockIdx.x * chunk;    // wavefront-uniform local queue
+  const int share_end = min(next + chunk, n_motions);
   int mot[S], prog[S], its[S];
   unsigned long long updates = 0;
 
@@ -144,9 +147,9 @@ __global__ __launch_bounds__(64) void project_pool_kernel(
   // plus the network's correction in MODE 1); mot[s] = -1 when none is left.
   auto fetch = [&](int s) {
     int m = -1;
-    while (next < n_motions) {
+    while (next < share_end) {
       const int cand = next;
-      next += stride;
+      ++next;
       if (MODE != 2 || status[cand] == 1) {
         m = cand;
         break;
