@@ -53,17 +53,73 @@ struct Mat {
   long rs, cs;
 };
 
-enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2, EPI_SILU_GRAD = 3 };
+enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_BIAS = 2, EPI_SILU_GRAD = 3, EPI_PARTIAL = 4 };
 
 constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8;
 
-// C[M][N] = A[M][K] B[K][N] (+ epilogue).
+// Loads 8 consecutive bf16 from p (16-byte aligned) as a uint4.
+__device__ __forceinline__ uint4 load8(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+__device__ __forceinline__ uint16_t lane16(const uint4& v, int i) {
+  const uint32_t w = i < 2 ? v.x : i < 4 ? v.y : i < 6 ? v.z : v.w;
+  return (uint16_t)(w >> (16 * (i & 1)));
+}
+__device__ __forceinline__ bool aligned16(const void* p) {
+  return ((uintptr_t)p & 15u) == 0;
+}
+
+// Stages the R x kBK tile of operand X (element (r, k) at p[r * rs + k * cs],
+// rows r0.., reduction columns k0..) into S[r][k] (zero outside R_tot x K).
+// When the reduction dimension is contiguous, a thread moves 8 consecutive
+// elements of a row with one 16-byte load and store; when the row dimension
+// is contiguous, 8 consecutive rows of one column with one load; otherwise
+// element by element.
+template <int R>
+__device__ __forceinline__ void stage(uint16_t (&S)[R][kBK + kPad], const Mat& X, int r0, int k0,
+                                      int R_tot, int K, int tid) {
+  static_assert(R * kBK == 8 * 256, "one 8-element chunk per thread");
+  if (X.cs == 1) {
+    const int r = tid >> 2, c8 = (tid & 3) * 8;
+    const int gr = r0 + r, gk = k0 + c8;
+    const uint16_t* src = X.p + (long)gr * X.rs + gk;
+    if (gr < R_tot && gk + 8 <= K && aligned16(src)) {
+      *reinterpret_cast<uint4*>(&S[r][c8]) = load8(src);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        S[r][c8 + i] = (gr < R_tot && gk + i < K) ? X.p[(long)gr * X.rs + gk + i] : (uint16_t)0;
+    }
+  } else if (X.rs == 1) {
+    const int c = tid >> 3, r8 = (tid & 7) * 8;
+    const int gk = k0 + c, gr = r0 + r8;
+    const uint16_t* src = X.p + gr + (long)gk * X.cs;
+    if (gk < K && gr + 8 <= R_tot && aligned16(src)) {
+      const uint4 v = load8(src);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) S[r8 + i][c] = lane16(v, i);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        S[r8 + i][c] = (gk < K && gr + i < R_tot) ? X.p[(long)(gr + i) + (long)gk * X.cs] : (uint16_t)0;
+    }
+  } else {
+    for (int e = tid; e < R * kBK; e += 256) {
+      const int r = e / kBK, c = e % kBK;
+      const int gr = r0 + r, gk = k0 + c;
+      S[r][c] = (gr < R_tot && gk < K) ? X.p[(long)gr * X.rs + (long)gk * X.cs] : (uint16_t)0;
+    }
+  }
+}
+
+// C[M][N] = A[M][K] B[K][N] (+ epilogue); blockIdx.z splits the reduction
+// into gridDim.z ranges of k_split (a multiple of kBK).
 //  EPI_STORE:     out_f = C (fp32)
+//  EPI_PARTIAL:   out_f[z][M][ldo] = this range's part of C (summed by reduce_parts_kernel)
 //  EPI_BIAS:      out_f = C + bias (fp32), out_b = bf16 of it (nullable)
 //  EPI_BIAS_SILU: z = C + bias -> out_f = z (pre-activation, nullable), out_b = bf16(silu(z))
 //  EPI_SILU_GRAD: out_b = bf16(C * silu'(aux)) with aux the stored pre-activation
 template <int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(Mat A, Mat B, int M, int N, int K,
+                                                        int k_split,
                                                         const float* __restrict__ bias,
                                                         const float* __restrict__ aux,
                                                         float* __restrict__ out_f,
@@ -73,22 +129,16 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(Mat A, Mat B, int M, int
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.x * kBM, n0 = blockIdx.y * kBN;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;     // this wavefront's 32 x 32 block
+  const int kb = blockIdx.z * k_split, ke = min(K, kb + k_split);
+  // B as an operand with rows n and reduction k: element (n, k) = B(k, n)
+  const Mat Bt{B.p, B.cs, B.rs};
   f32x4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < K; k0 += kBK) {
-    // stage: 64 x 32 of A and 32 x 64 of B, 8 elements per thread each
-    for (int e = tid; e < kBM * kBK; e += 256) {
-      const int r = e / kBK, c = e % kBK;
-      const int gm = m0 + r, gk = k0 + c;
-      As[r][c] = (gm < M && gk < K) ? A.p[gm * A.rs + gk * A.cs] : (uint16_t)0;
-    }
-    for (int e = tid; e < kBN * kBK; e += 256) {
-      const int n = e / kBK, c = e % kBK;
-      const int gn = n0 + n, gk = k0 + c;
-      Bs[n][c] = (gn < N && gk < K) ? B.p[gk * B.rs + gn * B.cs] : (uint16_t)0;
-    }
+  for (int k0 = kb; k0 < ke; k0 += kBK) {
+    stage<kBM>(As, A, m0, k0, M, ke, tid);
+    stage<kBN>(Bs, Bt, n0, k0, N, ke, tid);
     __syncthreads();
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     bf16x8 a[2], b[2];
@@ -112,6 +162,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(Mat A, Mat B, int M, int
         const long o = (long)gm * ldo + gn;
         if (EPI == EPI_STORE) {
           out_f[o] = c;
+        } else if (EPI == EPI_PARTIAL) {
+          out_f[(long)blockIdx.z * M * ldo + o] = c;
         } else if (EPI == EPI_BIAS) {
           const float z = c + bias[gn];
           if (out_f) out_f[o] = z;
@@ -124,6 +176,17 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(Mat A, Mat B, int M, int
           out_b[o] = to_bf16(c * silu_grad(aux[o]));
         }
       }
+}
+
+// out[r][c] = sum over z of part[z][r][c] (c < N, row stride ld), in a fixed order.
+__global__ void reduce_parts_kernel(const float* __restrict__ part, int splits, int M, int N,
+                                    long ld, float* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)M * N) return;
+  const long r = i / N, c = i % N, o = r * ld + c;
+  float s = 0.0f;
+  for (int z = 0; z < splits; ++z) s += part[(long)z * M * ld + o];
+  out[o] = s;
 }
 
 // fp32 [M][n] (row stride ld_in) -> bf16 [M][ld_out], zero-padded columns n..ld_out-1
@@ -230,6 +293,8 @@ struct cp_mlp {
   uint16_t* ib = nullptr;                     // pong
   uint16_t* ix = nullptr;                     // [rows][in_pad] bf16 input
   float* iy = nullptr;                        // [rows][out_pad] fp32 output
+  float* parts = nullptr;                     // split-reduction parts of the weight gradients
+  long parts_cap = 0;                         // floats
   float* feat = nullptr;                      // warm start: [rows][n_in] features
   float* delta = nullptr;                     // warm start: [rows][n_out] corrections
   long warm_rows = 0;
@@ -276,22 +341,53 @@ hipError_t ensure_ws(cp_mlp* n, long rows) {
   if (e == hipSuccess) e = hipMalloc((void**)&n->yf, sizeof(float) * r * out_pad(n, n->n_layers - 1));
   if (e == hipSuccess) e = hipMalloc((void**)&n->dyb, sizeof(uint16_t) * r * maxw);
   if (e == hipSuccess) e = hipMalloc((void**)&n->dzb, sizeof(uint16_t) * r * maxw);
+  if (e == hipSuccess && !n->parts) {
+    long wmax = 0;
+    for (int l = 0; l < n->n_layers; ++l) wmax = std::max(wmax, (long)n->out_dim[l] * n->in_dim[l]);
+    n->parts_cap = 32 * wmax;
+    e = hipMalloc((void**)&n->parts, sizeof(float) * n->parts_cap);
+  }
   if (e == hipSuccess) n->ws_rows = r;
   return e;
 }
 
 void gemm(int epi, Mat A, Mat B, int M, int N, int K, const float* bias, const float* aux,
           float* out_f, uint16_t* out_b, long ldo, hipStream_t st) {
-  dim3 grid((M + kBM - 1) / kBM, (N + kBN - 1) / kBN);
+  dim3 grid((M + kBM - 1) / kBM, (N + kBN - 1) / kBN, 1);
+  const int ks = (K + kBK - 1) / kBK * kBK;
   switch (epi) {
-    case EPI_STORE: gemm_bf16_kernel<EPI_STORE><<<grid, 256, 0, st>>>(A, B, M, N, K, bias, aux, out_f, out_b, ldo); break;
-    case EPI_BIAS: gemm_bf16_kernel<EPI_BIAS><<<grid, 256, 0, st>>>(A, B, M, N, K, bias, aux, out_f, out_b, ldo); break;
-    case EPI_BIAS_SILU: gemm_bf16_kernel<EPI_BIAS_SILU><<<grid, 256, 0, st>>>(A, B, M, N, K, bias, aux, out_f, out_b, ldo); break;
-    default: gemm_bf16_kernel<EPI_SILU_GRAD><<<grid, 256, 0, st>>>(A, B, M, N, K, bias, aux, out_f, out_b, ldo); break;
+    case EPI_STORE: gemm_bf16_kernel<EPI_STORE><<<grid, 256, 0, st>>>(A, B, M, N, K, ks, bias, aux, out_f, out_b, ldo); break;
+    case EPI_BIAS: gemm_bf16_kernel<EPI_BIAS><<<grid, 256, 0, st>>>(A, B, M, N, K, ks, bias, aux, out_f, out_b, ldo); break;
+    case EPI_BIAS_SILU: gemm_bf16_kernel<EPI_BIAS_SILU><<<grid, 256, 0, st>>>(A, B, M, N, K, ks, bias, aux, out_f, out_b, ldo); break;
+    default: gemm_bf16_kernel<EPI_SILU_GRAD><<<grid, 256, 0, st>>>(A, B, M, N, K, ks, bias, aux, out_f, out_b, ldo); break;
   }
 }
 
-unsigned nblk(long n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+unsigned nblk(long n, int b = 256);
+
+// C = A B stored to out_f (fp32, row stride ldo) with the reduction split
+// over enough workgroups to fill the chip when the output is small and the
+// reduction long (the weight gradients: output = layer size, reduction =
+// batch); parts go to `parts` ([splits][M][ldo] fp32) and are summed in a
+// fixed order, so the result does not depend on scheduling.
+void gemm_split(Mat A, Mat B, int M, int N, int K, float* out_f, long ldo, float* parts,
+                long parts_cap, hipStream_t st) {
+  const int tiles = ((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+  const int ksteps = (K + kBK - 1) / kBK;
+  int splits = std::min(std::max(1, 1024 / tiles), std::max(1, ksteps / 4));
+  while (splits > 1 && (long)splits * M * ldo > parts_cap) --splits;
+  if (splits == 1) {
+    gemm(EPI_STORE, A, B, M, N, K, nullptr, nullptr, out_f, nullptr, ldo, st);
+    return;
+  }
+  const int ks = (ksteps + splits - 1) / splits * kBK;
+  splits = (K + ks - 1) / ks;
+  dim3 grid((M + kBM - 1) / kBM, (N + kBN - 1) / kBN, splits);
+  gemm_bf16_kernel<EPI_PARTIAL><<<grid, 256, 0, st>>>(A, B, M, N, K, ks, nullptr, nullptr, parts, nullptr, ldo);
+  reduce_parts_kernel<<<nblk((long)M * N), 256, 0, st>>>(parts, splits, M, N, ldo, out_f);
+}
+
+unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // Forward of M rows; x: fp32 [M][n_in] (row stride ldx).  Leaves activations
 // in the workspace; the network output (fp32) is n->yf [M][out_pad].
@@ -330,9 +426,9 @@ hipError_t backward(cp_mlp* n, long M, const float* t, hipStream_t st) {
     const int K = n->in_dim[l], N = n->out_dim[l];
     const uint16_t* in = l == 0 ? n->xb : n->hb[l - 1];
     const long ld_in = l == 0 ? in_pad(n) : out_pad(n, l - 1);
-    // dW[N][K] = dZ^T[N][M] * X[M][K]
-    gemm(EPI_STORE, Mat{dz, 1, (long)ldz}, Mat{in, ld_in, 1}, N, K, (int)M, nullptr, nullptr,
-         n->grad + n->w_off[l], nullptr, K, st);
+    // dW[N][K] = dZ^T[N][M] * X[M][K], the batch reduction split over workgroups
+    gemm_split(Mat{dz, 1, (long)ldz}, Mat{in, ld_in, 1}, N, K, (int)M, n->grad + n->w_off[l], K,
+               n->parts, n->parts_cap, st);
     bias_grad_kernel<<<N, 256, 0, st>>>(dz, (int)M, N, ldz, n->grad + n->b_off[l]);
     if (l == 0) break;
     // dH[M][K] = dZ[M][N] * W[N][K], then dZ_prev = dH * silu'(z_prev)
@@ -481,7 +577,7 @@ void cp_mlp_destroy(cp_mlp* n) {
   if (!n) return;
   free_ws(n);
   for (void* p : {(void*)n->ia, (void*)n->ib, (void*)n->ix, (void*)n->iy, (void*)n->feat,
-                  (void*)n->delta})
+                  (void*)n->delta, (void*)n->parts})
     if (p) (void)hipFree(p);
   for (float* p : {n->w, n->grad, n->m1, n->m2, n->loss}) if (p) (void)hipFree(p);
   if (n->wb) (void)hipFree(n->wb);
