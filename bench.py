@@ -113,6 +113,8 @@ def parse():
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--plan-queries", type=int, default=100,
                     help="planning queries per scene for the p50 plan time (0 = skip)")
+    ap.add_argument("--density", type=int, default=1,
+                    help="obstacle-density sweep of the validation kernel (0 = skip)")
     ap.add_argument("--learned", type=int, default=1,
                     help="measure the warm-start network and the warm-started projector (0 = skip)")
     ap.add_argument("--copy-mb", type=int, default=0,
@@ -298,6 +300,49 @@ def warm_bench(G, I, torch, n_train=8192, n_eval=4096, tau_task=1e-4):
     res.update(motions=M, tau_task=tau_task, train_pairs=int(X.shape[0]), train_seconds=train_s,
                train_loss=[float(h) for h in hist])
     return res
+
+
+def density_bench(G, I, torch, M=65536, reps=3):
+    """Obstacle-density sweep: the plain scene's 10 boxes split into k^3 boxes
+    that tile them (k = 1, 2, 5: 10, 80, 1250 boxes; every verdict is
+    unchanged), 65536 projected motions validated with and without the
+    motion-wide early exit, with and without the bounding-sphere culling."""
+    w = I.workload("plain", 1000)
+    rd = w["robot"]
+    robot, con = G.Robot(rd), G.constraint(w["constraint"])
+    env1 = G.Env(w["env"])
+    dev = torch.device("cuda:0")
+    q_from = gpu_starts(G, I, torch, rd, robot, env1, con, M, 1500)
+    q_to = torch.from_numpy(I.random_displacements(
+        rd, q_from.cpu().numpy().astype(np.float64), (W - 1) * TAU, 1501).astype(np.float32)).to(dev)
+    prm = G.proj_params(W=W, tau=TAU, tau_task=w["tau_task"])
+    xi = torch.empty((M, W, rd["dof"]), device=dev)
+    st0 = torch.empty(M, dtype=torch.int32, device=dev)
+    G.project_motions(robot, con, prm, q_from, q_to, xi, st0)
+    st = torch.empty_like(st0)
+    out = {}
+    for k in (1, 2, 5):
+        env = G.Env(I.subdivide_boxes(w["env"], k))
+        row, verdicts = {"boxes": env.n_prims}, set()
+        for name, flags in (("early_exit", 0), ("no_early_exit", G.NO_EARLY_EXIT),
+                            ("early_exit_no_cull", G.NO_CULL),
+                            ("no_early_exit_no_cull", G.NO_EARLY_EXIT | G.NO_CULL)):
+            ts = []
+            for _ in range(reps):
+                st.copy_(st0)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                G.validate_motions(robot, env, prm, xi, st, flags=flags)
+                b.record()
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b))
+            row[name + "_ms"] = float(np.median(ts))
+            verdicts.add(tuple(np.bincount(st.cpu().numpy(), minlength=3)))
+        row["verdicts_identical"] = len(verdicts) == 1
+        row["early_exit_speedup_no_cull"] = row["no_early_exit_no_cull_ms"] / row["early_exit_no_cull_ms"]
+        row["early_exit_speedup"] = row["no_early_exit_ms"] / row["early_exit_ms"]
+        out[f"x{k ** 3}"] = row
+    return out
 
 
 def cpu_plan_baseline(I, name, seeds, tau_task, target_s):
@@ -530,6 +575,8 @@ def main():
             result["plan"][name] = entry
     if args.batch_queries > 0:
         result["batch"] = batch_bench(G, I, torch, args.batch_queries)
+    if args.density:
+        result["density"] = density_bench(G, I, torch)
     if args.learned:
         result["mlp"] = mlp_bench(G, torch)
         result["warm_start"] = warm_bench(G, I, torch)

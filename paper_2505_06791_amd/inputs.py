@@ -276,6 +276,24 @@ def make_mixed(seed: int, n: int = 300, size_lo: float = 0.02, size_hi: float = 
     return env
 
 
+def subdivide_boxes(env: dict, k: int) -> dict:
+    """Every axis-aligned box split into k x k x k boxes that tile it exactly
+    (the union, hence every signed distance from outside and every collision
+    verdict, is unchanged; the primitive count grows k^3-fold)."""
+    out = dict(env)
+    rows = []
+    for b in np.asarray(env["aabb"], np.float64).reshape(-1, 6):
+        c, h = b[:3], b[3:]
+        hs = h / k
+        for i in range(k):
+            for j in range(k):
+                for l in range(k):
+                    off = np.array([i, j, l], np.float64)
+                    rows.append([*(c - h + hs * (2.0 * off + 1.0)), *hs])
+    out["aabb"] = np.asarray(rows, np.float64).reshape(-1, 6)
+    return out
+
+
 def env_count(env: dict) -> int:
     return sum(len(env[k]) for k in ("aabb", "obb", "sphere", "capsule", "cylinder"))
 
@@ -307,6 +325,15 @@ def line_constraint(seed: int) -> dict:
     target[1] = rng.uniform(-0.2, 0.2)
     target[2] = rng.uniform(0.3, 0.9)
     return dict(kind=CON_POSE, mask=np.array([0, 1, 1, 0, 0, 0], np.int32),
+                frame=np.eye(4), target=target, rel_target=np.eye(4))
+
+
+def fixed_orientation(seed: int) -> dict:
+    """End effector orientation fixed (roll = pitch = 0, yaw = y_c ~ U[-pi, pi]),
+    position free."""
+    target = np.zeros(6)
+    target[5] = rng_for(seed).uniform(-math.pi, math.pi)
+    return dict(kind=CON_POSE, mask=np.array([0, 0, 0, 1, 1, 1], np.int32),
                 frame=np.eye(4), target=target, rel_target=np.eye(4))
 
 

@@ -111,6 +111,29 @@ def test_fk_cc_empty_scene(G):
     assert not col.any()
 
 
+@pytest.mark.parametrize("k", [2, 5])
+def test_subdivided_scene_keeps_verdicts(G, k):
+    """Boxes split into k^3 boxes that tile them (the density sweep's
+    scenes): configuration verdicts and motion verdicts, with and without
+    early exit, equal those of the original scene outside the band."""
+    w = I.workload("plain", 1000)
+    wk = dict(w, env=I.subdivide_boxes(w["env"], k))
+    q = I.random_configs(w["robot"], 2000, 31).astype(np.float32)
+    c1, sd1 = _gpu_fkcc(G, w, q, want_sd=True)
+    ck, sdk = _gpu_fkcc(G, wk, q, want_sd=True)
+    ok = np.abs(sd1) > BAND
+    assert np.array_equal(c1[ok], ck[ok])
+    q_from, q_to = motion_set(w, 40, 23)
+    xi, st, _ = _run_pv(G, w, q_from, q_to, dict(W=64))
+    for flags in (0, G.NO_EARLY_EXIT):
+        _, stk, _ = _run_pv(G, wk, q_from, q_to, dict(W=64), flags=flags)
+        ro, eo, co = oracle_views(w)
+        for m in np.nonzero(st != O.MOTION_PROJ_FAIL)[0]:
+            _, sd = O.fk_cc_batch(ro, eo, xi[m, 1:].astype(np.float64))
+            if abs(sd.min()) > BAND:
+                assert st[m] == stk[m], (m, st[m], stk[m])
+
+
 def _run_pv(G, w, q_from, q_to, prm_kw, flags=0):
     robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
     prm = G.proj_params(**prm_kw)
@@ -218,6 +241,24 @@ def test_pooled_and_per_motion_projection_agree(G, name, W, variant):
     ref = O.project_validate_motions(ro, eo, co, prm, q_from.astype(np.float64),
                                      q_to.astype(np.float64), n_threads=8)
     _compare_pv(f"{name} pooled", ref, xi_p, st_p, it_p, w, W, w["tau_task"])
+
+
+@pytest.mark.parametrize("con,W", [("line", 64), ("line", 32), ("orientation", 64),
+                                   ("orientation", 32)])
+def test_other_constraint_sets_match_oracle(G, con, W):
+    """The paper's other constraint sets through the same masks: the end
+    effector on a horizontal line (y and z locked) and a fixed orientation
+    (roll, pitch, yaw locked), pooled and per-motion."""
+    w = dict(I.workload("plain", 2364))   # an arm that reaches the line
+    w["constraint"] = I.line_constraint(7) if con == "line" else I.fixed_orientation(7)
+    q_from, q_to = motion_set(w, 30, 19, W=W)
+    ro, eo, co = oracle_views(w)
+    ref = O.project_validate_motions(ro, eo, co, O.params(W=W, tau_task=w["tau_task"]),
+                                     q_from.astype(np.float64), q_to.astype(np.float64),
+                                     n_threads=8)
+    for flags in (G.POOLED, G.PER_MOTION):
+        xi, st, it = _run_pv(G, w, q_from, q_to, dict(W=W, tau_task=w["tau_task"]), flags=flags)
+        _compare_pv(f"plain {con}", ref, xi, st, it, w, W, w["tau_task"])
 
 
 def test_pooled_flags_are_exclusive(G):

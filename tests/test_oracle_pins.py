@@ -680,3 +680,21 @@ def test_variant_output_invariants(oracle_lib, variant, name, W):
             n_ok += 1
             _check_projected(O, rob, c, prm, a, xi)
     assert n_ok >= 1
+
+
+def test_subdivided_boxes_keep_every_distance(oracle_lib):
+    """Splitting each box into k^3 boxes that tile it leaves the solid, hence
+    every signed distance from outside it and every verdict, unchanged."""
+    O = oracle_lib
+    w = I.workload("plain", 1000)
+    ro = O.Robot(w["robot"])
+    e1 = O.Env(w["env"])
+    for k in (2, 3):
+        ek = O.Env(I.subdivide_boxes(w["env"], k))
+        assert len(I.subdivide_boxes(w["env"], k)["aabb"]) == 10 * k ** 3
+        for q in I.random_configs(w["robot"], 40, 9):
+            d1, dk = O.config_min_sd(ro, e1, q), O.config_min_sd(ro, ek, q)
+            if d1 > 0:
+                assert abs(d1 - dk) < 1e-12
+            else:
+                assert dk <= 1e-12      # inside the union: inside (or on) some part
