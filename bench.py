@@ -113,6 +113,8 @@ def parse():
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--plan-queries", type=int, default=100,
                     help="planning queries per scene for the p50 plan time (0 = skip)")
+    ap.add_argument("--dual-queries", type=int, default=128,
+                    help="dual-arm relative-pose queries planned in one batch and one by one (0 = skip)")
     ap.add_argument("--density", type=int, default=1,
                     help="obstacle-density sweep of the validation kernel (0 = skip)")
     ap.add_argument("--learned", type=int, default=1,
@@ -147,9 +149,10 @@ def gpu_query(G, I, torch, w, seed):
     return robot, env, con, None, None
 
 
-def plan_bench(G, I, torch, name, seeds, tau_task):
+def plan_bench(G, I, torch, name, seeds, tau_task, variant=0):
     """p50 wall time of cp_plan over seeded queries (planner creation and
-    query preparation excluded), success rate."""
+    query preparation excluded), success rate; variant selects the
+    projection operator (0: Algorithm 1, 2: sequential, as cpRRTC-Naive)."""
     times, ok, rounds = [], 0, []
     n = 0
     for seed in seeds:
@@ -158,7 +161,7 @@ def plan_bench(G, I, torch, name, seeds, tau_task):
         if start is None:
             continue
         pl = G.Planner(robot, G.plan_opts(n_groups=256, max_rounds=500, capacity=65536,
-                                          tau_task=tau_task))
+                                          tau_task=tau_task, variant=variant))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
@@ -171,26 +174,31 @@ def plan_bench(G, I, torch, name, seeds, tau_task):
         n += 1
         ok += rc == G.CP_OK
         rounds.append(st["rounds"])
+        if n % 10 == 0:
+            print(f"plan {name} variant {variant}: {n} queries, {ok} solved, "
+                  f"{sum(times):.0f} ms", file=sys.stderr, flush=True)
     return dict(queries=n, p50_ms=float(np.median(times)), p90_ms=float(np.percentile(times, 90)),
                 success=ok / max(n, 1), mean_rounds=float(np.mean(rounds)))
 
 
-def batch_bench(G, I, torch, n, base=3000):
-    """Uneven queries (DOF 6/7/9, 10-1000 primitives, three constraint kinds)
-    planned in one cp_plan_batch call and, for comparison, one cp_plan call
-    each in sequence.  Both get the same extension budget per query (32
-    wavefronts x 800 rounds batched, 256 x 100 sequential) and tree
-    capacity; query preparation and tree allocation are excluded."""
+def batch_bench(G, I, torch, n, base=3000, make=None, max_dof=9, rounds=800, tau_task=1e-3):
+    """Uneven queries (DOF 6/7/9, 10-1000 primitives, three constraint kinds;
+    or the workloads `make(seed)` gives) planned in one cp_plan_batch call
+    and, for comparison, one cp_plan call each in sequence.  Both get the
+    same extension budget per query (32 wavefronts x `rounds` rounds batched,
+    256 x rounds/8 sequential) and tree capacity; query preparation and tree
+    allocation are excluded."""
+    make = make or I.uneven_query
     queries = []
     for s in range(base, base + n):
-        w = I.uneven_query(s)
+        w = make(s)
         robot, env, con, start, goal = gpu_query(G, I, torch, w, s)
         if start is not None:
             queries.append((robot, env, con, start, goal, s))
     print(f"batch: {len(queries)} queries prepared", file=sys.stderr, flush=True)
     cap = 16384
-    bp = G.BatchPlanner(len(queries), 9, G.batch_opts(groups_per_query=32, max_rounds=800,
-                                                      capacity=cap))
+    bp = G.BatchPlanner(len(queries), max_dof, G.batch_opts(groups_per_query=32, max_rounds=rounds,
+                                                            capacity=cap, tau_task=tau_task))
     bp.plan(queries[:8])                          # module load and first-touch, untimed
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -201,7 +209,8 @@ def batch_bench(G, I, torch, n, base=3000):
     del bp
     seq_ms, ok_s = 0.0, 0
     for robot, env, con, start, goal, s in queries:
-        pl = G.Planner(robot, G.plan_opts(n_groups=256, max_rounds=100, capacity=cap))
+        pl = G.Planner(robot, G.plan_opts(n_groups=256, max_rounds=rounds // 8, capacity=cap,
+                                          tau_task=tau_task))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
@@ -213,7 +222,7 @@ def batch_bench(G, I, torch, n, base=3000):
         seq_ms += (time.perf_counter() - t0) * 1e3
         ok_s += rc == G.CP_OK
         del pl
-        if (s - base) % 128 == 127:
+        if (s - base) % 16 == 15:
             print(f"batch: sequential through seed {s}, {seq_ms:.0f} ms", file=sys.stderr, flush=True)
     return dict(queries=len(queries), batched_ms=batch_ms,
                 batched_solved=int((st_b == G.CP_OK).sum()),
@@ -570,11 +579,22 @@ def main():
             seeds = range(base, base + args.plan_queries)
             tt = I.workload(name, base)["tau_task"]
             entry = plan_bench(G, I, torch, name, seeds, tt)
+            # cpRRTC-Naive (sequential projection) on the same queries; its
+            # motions take several times longer, so the cluttered scene, where
+            # most unsolved queries run out the round budget, uses the first 20
+            sub = seeds if name == "plain" else seeds[:20]
+            entry["naive"] = plan_bench(G, I, torch, name, sub, tt, variant=G.PROJECT_SEQUENTIAL)
+            if sub != seeds:
+                entry["naive"]["parallel_same_queries"] = plan_bench(G, I, torch, name, sub, tt)
             if args.cpu_seconds > 0:
                 entry["cpu_baseline"] = cpu_plan_baseline(I, name, seeds, tt, args.cpu_seconds / 2)
             result["plan"][name] = entry
     if args.batch_queries > 0:
         result["batch"] = batch_bench(G, I, torch, args.batch_queries)
+    if args.dual_queries > 0:
+        result["dual_batch"] = batch_bench(G, I, torch, args.dual_queries, base=5000,
+                                           make=lambda s: I.workload("dual", s), max_dof=14,
+                                           rounds=400, tau_task=1e-4)
     if args.density:
         result["density"] = density_bench(G, I, torch)
     if args.learned:
