@@ -44,6 +44,7 @@ TAU_TASK = 1e-3
 PAIR_FLOPS = dict(aabb=15, obb=30, sphere=11, capsule=25, cylinder=28)
 PAIR_ORDER = ("aabb", "obb", "sphere", "capsule", "cylinder")   # work counter slots 0..4
 SPHERE_CENTRE_FLOPS = 19          # R l + p, plus r^2
+FK_JOINT_FLOPS = 51               # one joint frame of the chain (sin/cos counted as 1 each)
 CULL_FLOPS = 20                   # bounding sphere vs box: 3 x (2 sub, 2 max), |.|^2, reach^2, compare
 
 
@@ -76,30 +77,33 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3    # MI355X, 256 CU x 2.4 GHz, packed FMA counte
 # what the same counter reads for a plain 256 MiB device copy (FETCH_SIZE
 # reads 131083.5 KiB of 262144, WRITE_SIZE 262144 of 262144).  Valid only
 # for the kernel sources they were taken on.
-TRAFFIC = {
-    "kernel": "project_pool_kernel<7, 1, 0, 6>",
-    "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
-                "paper_2505_06791_amd/csrc/kernels.hip"),
-    "sources_sha256": "3889924350551fd92538324037568b9486c9bd6de7ccdb92cb3ae6fd7bc85c3f",
-    "fetch_kib": 4959.8, "fetch_scale": 262144.0 / 131083.5,
-    "write_kib": 116022.8, "write_scale": 1.0,
-}
+TRAFFIC = [
+    {
+        "kernel": "project_pool_kernel<7, 1, 0, 6>",
+        "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
+                    "paper_2505_06791_amd/csrc/kernels.hip"),
+        "sources_sha256": "3889924350551fd92538324037568b9486c9bd6de7ccdb92cb3ae6fd7bc85c3f",
+        "fetch_kib": 4959.8, "fetch_scale": 262144.0 / 131083.5,
+        "write_kib": 116022.8, "write_scale": 1.0,
+    },
+]
 
 
 def recorded_traffic(kernel):
     """HBM bytes per launch of `kernel` from the recorded counters, or None
     when the kernel or its sources changed since they were taken."""
     import hashlib
-    if kernel != TRAFFIC["kernel"]:
-        return None
-    h = hashlib.sha256()
-    for f in TRAFFIC["sources"]:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != TRAFFIC["sources_sha256"]:
-        return None
-    return (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"]
-            + TRAFFIC["write_kib"] * TRAFFIC["write_scale"]) * 1024.0
+    for rec in TRAFFIC:
+        if kernel != rec["kernel"]:
+            continue
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            return None
+        return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
+    return None
 
 
 def parse():
@@ -115,6 +119,8 @@ def parse():
                     help="planning queries per scene for the p50 plan time (0 = skip)")
     ap.add_argument("--dual-queries", type=int, default=128,
                     help="dual-arm relative-pose queries planned in one batch and one by one (0 = skip)")
+    ap.add_argument("--rtc", type=int, default=1,
+                    help="project with the kernel compiled at run time for the robot (0 = library kernel)")
     ap.add_argument("--density", type=int, default=1,
                     help="obstacle-density sweep of the validation kernel (0 = skip)")
     ap.add_argument("--learned", type=int, default=1,
@@ -311,6 +317,30 @@ def warm_bench(G, I, torch, n_train=8192, n_eval=4096, tau_task=1e-4):
     return res
 
 
+def fkcc_bench(G, I, torch, n=1 << 20, reps=5):
+    """fk_cc_batch on n uniform configurations of the cluttered scene (7-DOF
+    arm, 100 spheres, 300 mixed primitives) with every pair evaluated
+    (CP_NO_EARLY_EXIT): algorithmic FLOPs = n x (joint frames + spheres x
+    (sphere centre + sum over primitives of the pair test)) against the FP32
+    vector peak; and
+    the same call with the early exit, as the planner uses it."""
+    w = I.workload(WORKLOAD, SCENE_SEED)
+    rd = w["robot"]
+    robot, env = G.Robot(rd), G.Env(w["env"])
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(I.random_configs(rd, n, 2600).astype(np.float32)).to(dev)
+    col = torch.empty(n, dtype=torch.uint8, device=dev)
+    full_ms = _time_ms(torch, lambda: G.fk_cc_batch(robot, env, q, col, flags=G.NO_EARLY_EXIT), reps)
+    early_ms = _time_ms(torch, lambda: G.fk_cc_batch(robot, env, q, col), reps)
+    per_cfg = rd["dof"] * FK_JOINT_FLOPS + len(rd["sphere"]) * (
+        SPHERE_CENTRE_FLOPS + sum(env.counts[t] * PAIR_FLOPS[t] for t in PAIR_ORDER))
+    tflops = n * per_cfg / (full_ms * 1e-3) / 1e12
+    return dict(configs=n, every_pair_ms=full_ms, early_exit_ms=early_ms,
+                colliding=int(col.sum().item()), gflop_per_launch=n * per_cfg / 1e9,
+                achieved_tflops=tflops, peak_tflops=FP32_VECTOR_PEAK_TFLOPS,
+                frac=tflops / FP32_VECTOR_PEAK_TFLOPS)
+
+
 def density_bench(G, I, torch, M=65536, reps=3):
     """Obstacle-density sweep: the plain scene's 10 boxes split into k^3 boxes
     that tile them (k = 1, 2, 5: 10, 80, 1250 boxes; every verdict is
@@ -472,6 +502,9 @@ def main():
     rd, ed, cd = w["robot"], w["env"], w["constraint"]
     robot, env, con = G.Robot(rd), G.Env(ed), G.constraint(cd)
     prm = G.proj_params(W=W, tau=TAU, tau_task=TAU_TASK, sphere_batch=args.sphere_batch)
+    # the projection kernel compiled at run time for this robot and mask
+    # (hipRTC); compile time is reported, not timed
+    rtc_ms = robot.specialize(con) if args.rtc else None
     M, dof = args.motions, rd["dof"]
 
     q_from = gpu_starts(G, I, torch, rd, robot, env, con, M, MOTION_SEED)
@@ -526,7 +559,8 @@ def main():
     if val_ms >= proj_ms:
         dom, dom_ms, flops = "validate_kernel<8, true>", val_ms, val_flops
     else:
-        dom, dom_ms, flops = "project_pool_kernel<7, 1, 0, 6>", proj_ms, proj_flops
+        dom = "cp_rtc_pool<7, 1> (hipRTC)" if args.rtc else "project_pool_kernel<7, 1, 0, 6>"
+        dom_ms, flops = proj_ms, proj_flops
     achieved = flops / (dom_ms * 1e-3) / 1e12
     verdicts = int((st != G.MOTION_PROJ_FAIL).sum())
     value = verdicts * (W - 1) / (ms_per_step * 1e-3)
@@ -573,6 +607,12 @@ def main():
         "motions": {"valid": int((st == 0).sum()), "proj_fail": int((st == 1).sum()),
                     "collision": int((st == 2).sum()), "mean_iters": float(it.mean())},
     }
+    if args.rtc:
+        # the library kernel on the same motions, for comparison
+        robot_lib = G.Robot(rd)
+        lib_ms = _time_ms(torch, lambda: G.project_motions(robot_lib, con, prm, q_from, q_to, xi,
+                                                           status, iters), 5)
+        result["rtc"] = {"compile_ms": rtc_ms, "project_ms": proj_ms, "library_kernel_ms": lib_ms}
     if args.plan_queries > 0:
         result["plan"] = {}
         for name, base in (("plain", 1000), ("cluttered", 2000)):
@@ -595,6 +635,7 @@ def main():
         result["dual_batch"] = batch_bench(G, I, torch, args.dual_queries, base=5000,
                                            make=lambda s: I.workload("dual", s), max_dof=14,
                                            rounds=400, tau_task=1e-4)
+    result["fk_cc"] = fkcc_bench(G, I, torch)
     if args.density:
         result["density"] = density_bench(G, I, torch)
     if args.learned:

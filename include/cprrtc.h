@@ -52,8 +52,10 @@ enum {
                             wave-level bounding-box culling (verdicts are the same) */
   CP_POOLED = 8,         /* project_validate_motions: project with several motions per
                             wavefront whatever the batch size (results are the same) */
-  CP_PER_MOTION = 16     /* project_validate_motions: project with one motion per wavefront
+  CP_PER_MOTION = 16,    /* project_validate_motions: project with one motion per wavefront
                             whatever the batch size (results are the same) */
+  CP_GENERIC = 32        /* project_validate_motions: use the library's projection kernel
+                            even where cp_robot_specialize compiled one for the robot */
 };
 
 /* ------------------------------------------------------------ descriptors */
@@ -270,6 +272,24 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
                          const float* d_q_from, const float* d_q_to, float* d_xi,
                          int32_t* d_status, int32_t* d_iters, uint64_t* d_work, int32_t flags,
                          void* stream);
+
+/* ------------------------------------------------------------ run-time specialisation */
+
+/* Compiles at run time (hipRTC) the pooled projection kernel for this robot
+ * and for constraints of this one's kind and locked axes, with the robot's
+ * joint constants, base and tool frames and the mask written in as
+ * constants (the kernel source is the library's own device code; only the
+ * constants differ), and keeps it in the robot handle.  Later calls that
+ * project this robot's motions in the pooled form (project_motions,
+ * project_validate_motions; see CP_POOLED) with a constraint of the same
+ * kind and mask use it, unless flags hold CP_GENERIC.  The constraint's
+ * other values (frame, targets) stay arguments.  Rotation entries within
+ * 1e-6 of 0 or +-1 are taken as those values.  Calling it again for the same
+ * key returns at once.  compile_ms: nullable, out (compile and load time).
+ * Thread-safe with concurrent projections of the same robot.  Errors:
+ * CP_E_ARG, CP_E_UNSUPPORTED (dof, kind), CP_E_RTC (compilation; the log
+ * head in cp_last_error), CP_E_HIP (module load). */
+int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, double* compile_ms);
 
 /* ------------------------------------------------------------ launch autotuning */
 

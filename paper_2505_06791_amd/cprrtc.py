@@ -23,7 +23,7 @@ NO_EARLY_EXIT = 1
 NO_CULL = 2
 WARM_NO_FALLBACK = 4
 CP_TUNE_W = 1
-POOLED, PER_MOTION = 8, 16
+POOLED, PER_MOTION, GENERIC = 8, 16, 32
 PROJECT_PARALLEL, PROJECT_INDEPENDENT, PROJECT_SEQUENTIAL = 0, 1, 2
 WORK_SLOTS = 8
 
@@ -105,6 +105,7 @@ def lib():
         L.cp_robot_create.argtypes = [C.POINTER(RobotDesc), C.POINTER(vp)]
         L.cp_env_create.argtypes = [C.POINTER(EnvDesc), C.POINTER(vp)]
         L.cp_robot_destroy.argtypes = [vp]
+        L.cp_robot_specialize.argtypes = [vp, C.POINTER(Constraint), C.POINTER(C.c_double)]
         L.cp_env_destroy.argtypes = [vp]
         L.cp_proj_params_default.argtypes = [C.POINTER(ProjParams)]
         L.fk_cc_batch.argtypes = [vp, vp, C.c_int32, vp, vp, vp, C.c_int32, vp]
@@ -181,6 +182,13 @@ class Robot:
         self.handle = h
         self.dof = int(rd["dof"])
         self.n_spheres = len(sl)
+
+    def specialize(self, con) -> float:
+        """Compiles (hipRTC) the pooled projection kernel for this robot and
+        the constraint's kind and locked axes; returns the compile time in ms."""
+        ms = C.c_double(0.0)
+        _check(lib().cp_robot_specialize(self.handle, C.byref(con), C.byref(ms)))
+        return ms.value
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

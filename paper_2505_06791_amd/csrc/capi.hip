@@ -37,6 +37,16 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(CP_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Rotation entries within 1e-6 of 0 or +-1 are stored as those values (cos
+// and sin of multiples of pi/2 land a few 1e-8 off in float), so that a
+// kernel compiled with the robot's constants can drop the terms they zero.
+float snap_unit(float v) {
+  if (std::fabs(v) < 1e-6f) return 0.0f;
+  if (std::fabs(v - 1.0f) < 1e-6f) return 1.0f;
+  if (std::fabs(v + 1.0f) < 1e-6f) return -1.0f;
+  return v;
+}
+
 void copy34(float* dst, const double* m16) {
   for (int i = 0; i < 3; ++i)
     for (int c = 0; c < 4; ++c) dst[4 * i + c] = (float)m16[4 * i + c];
@@ -129,8 +139,8 @@ int cp_robot_create(const cp_robot_desc* d, cp_robot** out) {
       if (d->joint_type[j] != CP_REVOLUTE && d->joint_type[j] != CP_PRISMATIC)
         return fail(CP_E_ARG, "joint %d: unknown type %d", j, d->joint_type[j]);
       if (!(d->q_lo[j] <= d->q_hi[j])) return fail(CP_E_ARG, "joint %d: q_lo > q_hi", j);
-      h.ca[j] = (float)std::cos(d->alpha[j]);
-      h.sa[j] = (float)std::sin(d->alpha[j]);
+      h.ca[j] = snap_unit((float)std::cos(d->alpha[j]));
+      h.sa[j] = snap_unit((float)std::sin(d->alpha[j]));
       h.a[j] = (float)d->a[j];
       h.d0[j] = (float)d->d[j];
       h.th0[j] = (float)d->theta[j];
@@ -147,6 +157,11 @@ int cp_robot_create(const cp_robot_desc* d, cp_robot** out) {
     for (int c = 0; c < d->n_chains; ++c) {
       copy34(h.base[c], d->base + 16 * c);
       copy34(h.tool[c], d->tool + 16 * c);
+      for (int i = 0; i < 12; ++i)
+        if (i % 4 != 3) {
+          h.base[c][i] = snap_unit(h.base[c][i]);
+          h.tool[c][i] = snap_unit(h.tool[c][i]);
+        }
     }
     // spheres grouped by the joint frame that carries them
     std::vector<int> order(d->n_spheres);
@@ -190,6 +205,7 @@ int cp_robot_create(const cp_robot_desc* d, cp_robot** out) {
 
 void cp_robot_destroy(cp_robot* r) {
   if (!r) return;
+  rtc_release(r);
   if (r->dev) (void)hipFree(r->dev);
   if (r->spheres) (void)hipFree(r->spheres);
   delete r;
@@ -346,6 +362,18 @@ int do_project(const cp_robot* robot, const cp_constraint* constraint, const cp_
   if ((flags & CP_POOLED) && (flags & CP_PER_MOTION))
     return fail(CP_E_ARG, "CP_POOLED and CP_PER_MOTION together");
   const int pooled = (flags & CP_POOLED) ? 1 : (flags & CP_PER_MOTION) ? 0 : -1;
+  // the kernel compiled for this robot and mask (cp_robot_specialize), when
+  // the pooled form is the one to run
+  if (!(flags & CP_GENERIC) && p.variant != CP_PROJECT_SEQUENTIAL && use_pool(n_motions, pooled)) {
+    const RtcKernel* rk = rtc_find(const_cast<cp_robot*>(robot), con);
+    if (rk) {
+      hipError_t e = launch_rtc_pool(rk, robot, con, prm, n_motions, d_q_from, d_q_to, d_xi,
+                                     d_status, d_iters, (unsigned long long*)d_work,
+                                     (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "projection launch (run-time compiled kernel)");
+      return CP_OK;
+    }
+  }
   bool supported = false;
   hipError_t e = launch_project(robot->host.dof, robot->dev, con, prm, n_motions, d_q_from, d_q_to,
                                 d_xi, d_status, d_iters, (unsigned long long*)d_work, pooled,

@@ -10,7 +10,9 @@
 //  * Per-lane state (a configuration, a 3x4 frame, a sphere batch) is in
 //    VGPRs; nothing per lane goes through LDS.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 #include <stdint.h>
 
 namespace cprrtc {
@@ -131,15 +133,67 @@ __device__ __forceinline__ void sincos_joint(float x, float& s, float& c) {
   c = ((q + 1) & 2) ? -b : b;
 }
 
+// Where the projection reads the robot's constants and the constraint's
+// locked axes: RobotMem reads the device copy of the robot and the
+// constraint's mask at run time; a kernel compiled at run time for one robot
+// and one mask (hipRTC) supplies a policy with the same functions returning
+// compile-time constants, so unrolled loops fold them (zero twists and
+// offsets vanish, prismatic tests and free-axis branches disappear).
+struct RobotMem {
+  static __device__ __forceinline__ float ca(const RobotDev* r, int j) { return r->ca[j]; }
+  static __device__ __forceinline__ float sa(const RobotDev* r, int j) { return r->sa[j]; }
+  static __device__ __forceinline__ float a(const RobotDev* r, int j) { return r->a[j]; }
+  static __device__ __forceinline__ float d0(const RobotDev* r, int j) { return r->d0[j]; }
+  static __device__ __forceinline__ float th0(const RobotDev* r, int j) { return r->th0[j]; }
+  static __device__ __forceinline__ float lo(const RobotDev* r, int j) { return r->lo[j]; }
+  static __device__ __forceinline__ float hi(const RobotDev* r, int j) { return r->hi[j]; }
+  static __device__ __forceinline__ bool prismatic(const RobotDev* r, int j) { return r->prismatic[j] != 0; }
+  // first joint of chain 1 (ndof for a single chain)
+  static __device__ __forceinline__ int chain1(const RobotDev* r, int ndof) {
+    return r->n_chains > 1 ? r->chain_begin[1] : ndof;
+  }
+  static __device__ __forceinline__ float base(const RobotDev* r, int c, int i) { return r->base[c][i]; }
+  static __device__ __forceinline__ float tool(const RobotDev* r, int c, int i) { return r->tool[c][i]; }
+  static __device__ __forceinline__ bool lock(const ConDev& c, int i) { return c.mask[i] != 0.0f; }
+};
+
+// T * tool_c of the policy.
+template <class P>
+__device__ __forceinline__ void frame_times_p(const Frame& T, const RobotDev* __restrict__ rob,
+                                              int c, Frame& out) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      out.r[3 * i + k] = T.r[3 * i + 0] * P::tool(rob, c, k) + T.r[3 * i + 1] * P::tool(rob, c, 4 + k) +
+                         T.r[3 * i + 2] * P::tool(rob, c, 8 + k);
+    out.p[i] = T.r[3 * i + 0] * P::tool(rob, c, 3) + T.r[3 * i + 1] * P::tool(rob, c, 7) +
+               T.r[3 * i + 2] * P::tool(rob, c, 11) + T.p[i];
+  }
+}
+
+template <class P>
+__device__ __forceinline__ void frame_from_p(Frame& T, const RobotDev* __restrict__ rob, int c,
+                                             bool tool) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      T.r[3 * i + k] = tool ? P::tool(rob, c, 4 * i + k) : P::base(rob, c, 4 * i + k);
+    T.p[i] = tool ? P::tool(rob, c, 4 * i + 3) : P::base(rob, c, 4 * i + 3);
+  }
+}
+
 // Joint j of the robot at joint value qj.
+template <class P = RobotMem>
 __device__ __forceinline__ void joint_advance(Frame& T, const RobotDev* __restrict__ rob, int j,
                                               float qj) {
-  const bool pri = rob->prismatic[j] != 0;
-  const float theta = rob->th0[j] + (pri ? 0.0f : qj);
-  const float d = rob->d0[j] + (pri ? qj : 0.0f);
+  const bool pri = P::prismatic(rob, j);
+  const float theta = P::th0(rob, j) + (pri ? 0.0f : qj);
+  const float d = P::d0(rob, j) + (pri ? qj : 0.0f);
   float st, ct;
   sincos_joint(theta, st, ct);
-  frame_advance(T, rob->ca[j], rob->sa[j], rob->a[j], ct, st, d);
+  frame_advance(T, P::ca(rob, j), P::sa(rob, j), P::a(rob, j), ct, st, d);
 }
 
 // Tool frame: T_ee = T * tool.

@@ -3,13 +3,30 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <deque>
+#include <mutex>
+
 #include "cprrtc.h"
 #include "device.h"
+
+namespace cprrtc {
+// A pooled projection kernel compiled at run time for one robot, constraint
+// kind and set of locked axes.
+struct RtcKernel {
+  int kind = 0;
+  unsigned mask = 0;                // bit i = axis i locked
+  hipModule_t module = nullptr;
+  hipFunction_t fn = nullptr;
+  double compile_ms = 0.0;
+};
+}  // namespace cprrtc
 
 struct cp_robot {
   cprrtc::RobotDev host;            // host copy (dispatch reads dof, chains, limits)
   cprrtc::RobotDev* dev = nullptr;  // device copy
   float4* spheres = nullptr;        // device spheres, grouped by link
+  std::mutex rtc_lock;              // guards rtc (specialisation may run beside projections)
+  std::deque<cprrtc::RtcKernel> rtc; // a deque: entries stay put as more are added
 };
 
 struct cp_env {
@@ -23,4 +40,12 @@ int api_fail(int code, const char* fmt, ...);
 int api_hip_fail(hipError_t e, const char* what);
 int api_constraint(const cp_constraint* c, const cp_robot* robot, ConDev* out);
 int api_params(const cp_proj_params* params, cp_proj_params* p);
+// The run-time compiled pooled kernel for this robot and constraint, if one
+// was made (nullptr otherwise).
+const RtcKernel* rtc_find(cp_robot* robot, const ConDev& con);
+hipError_t launch_rtc_pool(const RtcKernel* k, const cp_robot* robot, const ConDev& con,
+                           const ProjDev& prm, int n_motions, const float* q_from,
+                           const float* q_to, float* xi, int* status, int* iters,
+                           unsigned long long* work, hipStream_t stream);
+void rtc_release(cp_robot* robot);
 }  // namespace cprrtc

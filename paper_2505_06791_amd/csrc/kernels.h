@@ -13,6 +13,12 @@ hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& en
                         const float* q, uint8_t* collide, float* min_sd, bool early, int batch,
                         hipStream_t stream);
 
+// Pooled projection: slots per wavefront, whether a launch of n motions uses
+// it (pooled: 1 = always, 0 = never, -1 = by batch size), its grid size.
+constexpr int kPoolSlots = 6;
+bool use_pool(int n_motions, int pooled);
+unsigned pool_blocks(int n_motions);
+
 // pooled: 1 = several motions per wavefront, 0 = one motion per wavefront,
 // -1 = by batch size.
 hipError_t launch_project(int dof, const RobotDev* rob, const ConDev& con, const ProjDev& prm,

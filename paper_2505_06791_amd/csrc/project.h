@@ -52,7 +52,7 @@ __device__ __forceinline__ float atan2_task(float y, float x) {
   return copysignf(r, y);
 }
 
-template <int NDOF, int KIND>
+template <int NDOF, int KIND, class P = RobotMem>
 __device__ __forceinline__ void task_step(const RobotDev* __restrict__ rob, const ConDev& con,
                                           const float (&q)[NDOF], float lambda2,
                                           float (&g)[NDOF], float& einf) {
@@ -67,26 +67,26 @@ __device__ __forceinline__ void task_step(const RobotDev* __restrict__ rob, cons
   // and the work is that of the m x m system of the locked axes.
   bool lock[6];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) lock[i] = con.mask[i] != 0.0f;
+  for (int i = 0; i < 6; ++i) lock[i] = P::lock(con, i);
   const bool any_ang = lock[3] || lock[4] || lock[5];
 
   // Forward kinematics: joint axes z_j and origins o_j, end effectors.
   float zx[NDOF], zy[NDOF], zz[NDOF], ox[NDOF], oy[NDOF], oz[NDOF];
-  const int b1 = rob->n_chains > 1 ? rob->chain_begin[1] : NDOF;
+  const int b1 = P::chain1(rob, NDOF);
   Frame T, ee0, ee1;
-  frame_from(T, rob->base[0]);
+  frame_from_p<P>(T, rob, 0, false);
 #pragma unroll
   for (int j = 0; j < NDOF; ++j) {
     if (j == b1) {
-      frame_times(T, rob->tool[0], ee0);
-      frame_from(T, rob->base[1]);
+      frame_times_p<P>(T, rob, 0, ee0);
+      frame_from_p<P>(T, rob, 1, false);
     }
-    joint_advance(T, rob, j, q[j]);
+    joint_advance<P>(T, rob, j, q[j]);
     zx[j] = T.r[2]; zy[j] = T.r[5]; zz[j] = T.r[8];
     ox[j] = T.p[0]; oy[j] = T.p[1]; oz[j] = T.p[2];
   }
-  if (b1 < NDOF) frame_times(T, rob->tool[1], ee1);
-  else frame_times(T, rob->tool[0], ee0);
+  if (b1 < NDOF) frame_times_p<P>(T, rob, 1, ee1);
+  else frame_times_p<P>(T, rob, 0, ee0);
 
   // Frame the error is measured in: A1 = rotation from world to the
   // reference (Rc^T or R1^T), P1 = reference origin, E = end effector.
@@ -163,7 +163,7 @@ __device__ __forceinline__ void task_step(const RobotDev* __restrict__ rob, cons
 #pragma unroll
   for (int j = 0; j < NDOF; ++j) {
     const bool first = j < b1;   // joint moves end effector 1 (REL) / the constrained one (POSE)
-    const bool pri = rob->prismatic[j] != 0;
+    const bool pri = P::prismatic(rob, j);
     float vx, vy, vz, wx, wy, wz;
     const bool at1 = KIND == KIND_REL && first;
     const float tx = at1 ? P1[0] : Pe[0], ty = at1 ? P1[1] : Pe[1], tz = at1 ? P1[2] : Pe[2];
@@ -267,12 +267,12 @@ __device__ __forceinline__ void task_step(const RobotDev* __restrict__ rob, cons
 // xi[k-1].  qn receives the new value (task step, smoothing term unless the
 // operator is the independent one, clamp to the limits); returns the
 // waypoint's validity at q (task error and spacing).
-template <int NDOF, int KIND>
+template <int NDOF, int KIND, class P = RobotMem>
 __device__ __forceinline__ bool waypoint_update(const RobotDev* __restrict__ rob, const ConDev& con,
                                                 const ProjDev& prm, const float (&q)[NDOF],
                                                 const float (&qprev)[NDOF], float (&qn)[NDOF]) {
   float g[NDOF], einf;
-  task_step<NDOF, KIND>(rob, con, q, prm.lambda2, g, einf);
+  task_step<NDOF, KIND, P>(rob, con, q, prm.lambda2, g, einf);
   float d2 = 0.0f, dl[NDOF];
 #pragma unroll
   for (int j = 0; j < NDOF; ++j) {
@@ -283,7 +283,7 @@ __device__ __forceinline__ bool waypoint_update(const RobotDev* __restrict__ rob
   const float wsm = prm.variant == CP_PROJECT_INDEPENDENT ? 0.0f : esm;   // smoothing term
 #pragma unroll
   for (int j = 0; j < NDOF; ++j)
-    qn[j] = fminf(fmaxf(q[j] - prm.alpha * (g[j] + dl[j] * wsm), rob->lo[j]), rob->hi[j]);
+    qn[j] = fminf(fmaxf(q[j] - prm.alpha * (g[j] + dl[j] * wsm), P::lo(rob, j)), P::hi(rob, j));
   return (einf < prm.tau_task) && (esm < prm.tau_sm);
 }
 

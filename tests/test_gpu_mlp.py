@@ -115,7 +115,7 @@ def _revalidate_segments(w, xi, st, W, tau_task):
     for m in np.nonzero(st == 0)[0]:
         x = xi[m].astype(np.float64)
         for k in range(1, W):
-            assert np.abs(O.task_error(ro, co, x[k])).max() < tau_task + BAND
+            assert np.abs(O.task_error(ro, co, x[k])).max(initial=0.0) < tau_task + BAND
             assert np.linalg.norm(x[k] - x[k - 1]) < 0.075 + BAND
 
 

@@ -164,7 +164,7 @@ def _revalidate(w, xi, st, W, tau_task, tau=0.05, tau_sm=0.025):
     for m in np.nonzero(st != O.MOTION_PROJ_FAIL)[0]:
         x = xi[m].astype(np.float64)
         for k in range(1, W):
-            assert np.abs(O.task_error(ro, co, x[k])).max() < tau_task + BAND, (m, k)
+            assert np.abs(O.task_error(ro, co, x[k])).max(initial=0.0) < tau_task + BAND, (m, k)
             assert np.linalg.norm(x[k] - x[k - 1]) < tau + tau_sm + BAND, (m, k)
         assert np.all(x >= lo - 1e-6) and np.all(x <= hi + 1e-6)
         col, sd = O.fk_cc_batch(ro, eo, x[1:])

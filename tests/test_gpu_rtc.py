@@ -1,0 +1,100 @@
+"""Run-time specialisation (hipRTC) of the pooled projection kernel: the
+kernel compiled with a robot's constants and a constraint's locked axes
+computes what the library kernel computes and meets the oracle.  Folding the
+constants lets the compiler fuse multiply-adds differently, so waypoints may
+differ in the last bits: statuses and iterations must agree outside the
+oracle's threshold band, waypoints of motions projected by both within
+1e-5 rad."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from paper_2505_06791_amd import inputs as I
+from tests.helpers import motion_set, oracle_views
+from tests.test_gpu_parity import _compare_pv
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_06791_amd import cprrtc
+    cprrtc.lib()
+    return cprrtc
+
+
+def _workload(name):
+    if name == "line":
+        w = dict(I.workload("plain", 2364))
+        w["constraint"] = I.line_constraint(7)
+        return w
+    if name == "none":
+        w = dict(I.workload("plain", 2401))
+        w["constraint"] = I.no_constraint()
+        return w
+    return I.workload(name, 2400)
+
+
+def _run(G, robot, env, con, w, q_from, q_to, kw, flags):
+    M, dof, W = len(q_from), w["robot"]["dof"], kw["W"]
+    qf, qt = torch.from_numpy(q_from).to("cuda:0"), torch.from_numpy(q_to).to("cuda:0")
+    xi = torch.full((M, W, dof), float("nan"), device="cuda:0")
+    st = torch.full((M,), -9, dtype=torch.int32, device="cuda:0")
+    it = torch.full((M,), -9, dtype=torch.int32, device="cuda:0")
+    G.project_validate_motions(robot, env, con, G.proj_params(**kw), qf, qt, xi, st, it, flags=flags)
+    torch.cuda.synchronize()
+    return xi.cpu().numpy(), st.cpu().numpy(), it.cpu().numpy()
+
+
+def _oracle(w, q_from, q_to, kw):
+    ro, eo, co = oracle_views(w)
+    return O.project_validate_motions(ro, eo, co, O.params(**kw), q_from.astype(np.float64),
+                                      q_to.astype(np.float64), n_threads=8)
+
+
+@pytest.mark.parametrize("name,W", [("plain", 64), ("cluttered", 64), ("mobile", 32),
+                                    ("dual", 64), ("line", 64), ("none", 64)])
+def test_specialised_kernel_equals_library_kernel(G, name, W):
+    w = _workload(name)
+    q_from, q_to = motion_set(w, 48, 29, W=W)
+    robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
+    ms = robot.specialize(con)
+    assert ms > 0
+    assert robot.specialize(con) == ms          # kept: the second call compiles nothing
+    kw = dict(W=W, tau_task=w["tau_task"])
+    xi_s, st_s, it_s = _run(G, robot, env, con, w, q_from, q_to, kw, G.POOLED)
+    xi_g, st_g, it_g = _run(G, robot, env, con, w, q_from, q_to, kw, G.POOLED | G.GENERIC)
+    print(name, "compile ms", round(ms, 1), "statuses", np.bincount(st_s, minlength=3), flush=True)
+    ref = _oracle(w, q_from, q_to, kw)
+    _agree(ref, (xi_s, st_s, it_s), (xi_g, st_g, it_g))
+    _compare_pv(f"{name} specialised", ref, xi_s, st_s, it_s, w, W, w["tau_task"])
+
+
+def _agree(ref, a, b):
+    band = (ref["proj_margin"] < 1e-5) | (np.abs(ref["min_sd"]) < 1e-5)
+    assert np.array_equal(a[1][~band], b[1][~band])
+    proj_band = ref["proj_margin"] < 1e-5
+    assert np.array_equal(a[2][~proj_band], b[2][~proj_band])
+    both = (a[1] != O.MOTION_PROJ_FAIL) & (b[1] != O.MOTION_PROJ_FAIL) & ~band
+    if both.any():
+        assert np.abs(a[0][both] - b[0][both]).max() < 1e-5
+
+
+def test_specialised_kernel_serves_only_its_mask(G):
+    """A robot specialised for upright projects plane + upright motions with
+    the library kernel (same results as with CP_GENERIC), meeting the oracle."""
+    w = dict(I.workload("plain", 2400), constraint=I.plane_upright(3))
+    robot, env = G.Robot(w["robot"]), G.Env(w["env"])
+    robot.specialize(G.constraint(I.upright()))
+    con = G.constraint(w["constraint"])
+    q_from, q_to = motion_set(w, 32, 41)
+    kw = dict(W=64, tau_task=1e-3)
+    a = _run(G, robot, env, con, w, q_from, q_to, kw, G.POOLED)
+    b = _run(G, robot, env, con, w, q_from, q_to, kw, G.POOLED | G.GENERIC)
+    for x, y in zip(a, b):                      # the same kernel ran both times
+        assert np.array_equal(x, y)
+    _compare_pv("plain other mask", _oracle(w, q_from, q_to, kw), *a, w, 64, 1e-3)
