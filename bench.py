@@ -86,6 +86,15 @@ TRAFFIC = [
         "fetch_kib": 4959.8, "fetch_scale": 262144.0 / 131083.5,
         "write_kib": 116022.8, "write_scale": 1.0,
     },
+    {
+        "kernel": "cp_rtc_pool<7, 1> (hipRTC)",
+        "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
+                    "paper_2505_06791_amd/csrc/project_pool.h", "paper_2505_06791_amd/csrc/rtc.hip",
+                    "include/cprrtc.h"),
+        "sources_sha256": "b3ab708c62345e022b60abcc72cb8762931bdf1f44e252b7c321642d6c5cae3c",
+        "fetch_kib": 4927.6, "fetch_scale": 262144.0 / 131083.5,
+        "write_kib": 115932.0, "write_scale": 1.0,
+    },
 ]
 
 
