@@ -130,6 +130,9 @@ def parse():
                     help="dual-arm relative-pose queries planned in one batch and one by one (0 = skip)")
     ap.add_argument("--rtc", type=int, default=1,
                     help="project with the kernel compiled at run time for the robot (0 = library kernel)")
+    ap.add_argument("--rtc-plan-queries", type=int, default=40,
+                    help="queries per scene planned for one robot with library and run-time "
+                         "compiled round kernels (0 = skip)")
     ap.add_argument("--density", type=int, default=1,
                     help="obstacle-density sweep of the validation kernel (0 = skip)")
     ap.add_argument("--learned", type=int, default=1,
@@ -142,12 +145,14 @@ def parse():
     return ap.parse_args()
 
 
-def gpu_query(G, I, torch, w, seed):
+def gpu_query(G, I, torch, w, seed, robot=None):
     """Start and goal for one planning query, prepared with the library:
     random configurations projected onto the manifold, collision-free by
-    1e-3 m, the first pair at least 1 rad apart."""
+    1e-3 m, the first pair at least 1 rad apart.  robot: the handle of
+    w["robot"] when the caller keeps one."""
     rd = w["robot"]
-    robot, env, con = G.Robot(rd), G.Env(w["env"]), G.constraint(w["constraint"])
+    robot = robot or G.Robot(rd)
+    env, con = G.Env(w["env"]), G.constraint(w["constraint"])
     dev = torch.device("cuda:0")
     raw = torch.from_numpy(I.random_configs(rd, 256, seed + 5).astype(np.float32)).to(dev)
     proj = torch.empty_like(raw)
@@ -164,15 +169,20 @@ def gpu_query(G, I, torch, w, seed):
     return robot, env, con, None, None
 
 
-def plan_bench(G, I, torch, name, seeds, tau_task, variant=0):
+def plan_bench(G, I, torch, name, seeds, tau_task, variant=0, fixed=None):
     """p50 wall time of cp_plan over seeded queries (planner creation and
     query preparation excluded), success rate; variant selects the
-    projection operator (0: Algorithm 1, 2: sequential, as cpRRTC-Naive)."""
+    projection operator (0: Algorithm 1, 2: sequential, as cpRRTC-Naive).
+    fixed: (robot description, robot handle) used by every query in place of
+    the seed's own robot (scene and constraint frame still per seed)."""
     times, ok, rounds = [], 0, []
     n = 0
     for seed in seeds:
-        w = I.workload(name, seed)
-        robot, env, con, start, goal = gpu_query(G, I, torch, w, seed)
+        w = dict(I.workload(name, seed))
+        if fixed is not None:
+            w["robot"] = fixed[0]
+        robot, env, con, start, goal = gpu_query(G, I, torch, w, seed,
+                                                 None if fixed is None else fixed[1])
         if start is None:
             continue
         pl = G.Planner(robot, G.plan_opts(n_groups=256, max_rounds=500, capacity=65536,
@@ -638,6 +648,21 @@ def main():
             if args.cpu_seconds > 0:
                 entry["cpu_baseline"] = cpu_plan_baseline(I, name, seeds, tt, args.cpu_seconds / 2)
             result["plan"][name] = entry
+    if args.rtc and args.rtc_plan_queries > 0:
+        # one robot, many queries: the round kernels compiled at run time for
+        # it (compile time reported, not timed) against the library kernels
+        result["plan_rtc"] = {}
+        for name, base in (("plain", 1000), ("cluttered", 2000)):
+            w0 = I.workload(name, base)
+            seeds = range(base, base + args.rtc_plan_queries)
+            lib = plan_bench(G, I, torch, name, seeds, w0["tau_task"],
+                             fixed=(w0["robot"], G.Robot(w0["robot"])))
+            rob = G.Robot(w0["robot"])
+            ms = rob.specialize(G.constraint(w0["constraint"]), project=False, plan=True)
+            spec = plan_bench(G, I, torch, name, seeds, w0["tau_task"], fixed=(w0["robot"], rob))
+            result["plan_rtc"][name] = {"compile_ms": ms, "library": lib, "specialised": spec}
+            print(f"plan_rtc {name}: library p50 {lib['p50_ms']:.2f} ms, specialised "
+                  f"{spec['p50_ms']:.2f} ms, compile {ms:.0f} ms", file=sys.stderr, flush=True)
     if args.batch_queries > 0:
         result["batch"] = batch_bench(G, I, torch, args.batch_queries)
     if args.dual_queries > 0:

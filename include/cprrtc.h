@@ -275,21 +275,27 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
 
 /* ------------------------------------------------------------ run-time specialisation */
 
-/* Compiles at run time (hipRTC) the pooled projection kernel for this robot
- * and for constraints of this one's kind and locked axes, with the robot's
- * joint constants, base and tool frames and the mask written in as
+/* Compiles at run time (hipRTC) kernels for this robot and for constraints
+ * of this one's kind and locked axes, with the robot's joint constants,
+ * base and tool frames, collision spheres and the mask written in as
  * constants (the kernel source is the library's own device code; only the
- * constants differ), and keeps it in the robot handle.  Later calls that
- * project this robot's motions in the pooled form (project_motions,
- * project_validate_motions; see CP_POOLED) with a constraint of the same
- * kind and mask use it, unless flags hold CP_GENERIC.  The constraint's
- * other values (frame, targets) stay arguments.  Rotation entries within
- * 1e-6 of 0 or +-1 are taken as those values.  Calling it again for the same
- * key returns at once.  compile_ms: nullable, out (compile and load time).
+ * constants differ), and keeps them in the robot handle.  what:
+ * CP_SPECIALIZE_PROJECT (0 means this) -- the pooled projection kernel:
+ * later calls that project this robot's motions in the pooled form
+ * (project_motions, project_validate_motions; see CP_POOLED) with a
+ * constraint of the same kind and mask use it, unless flags hold
+ * CP_GENERIC; CP_SPECIALIZE_PLAN -- the planner's round kernels: later
+ * cp_plan calls of planners of this robot with such a constraint use them.
+ * The constraint's other values (frame, targets) stay arguments.  Rotation
+ * entries within 1e-6 of 0 or +-1 are taken as those values.  Kernels
+ * already compiled for the key are not compiled again.  compile_ms:
+ * nullable, out (compile and load time of this call).
  * Thread-safe with concurrent projections of the same robot.  Errors:
  * CP_E_ARG, CP_E_UNSUPPORTED (dof, kind), CP_E_RTC (compilation; the log
  * head in cp_last_error), CP_E_HIP (module load). */
-int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, double* compile_ms);
+enum { CP_SPECIALIZE_PROJECT = 1, CP_SPECIALIZE_PLAN = 2 };
+int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_t what,
+                        double* compile_ms);
 
 /* ------------------------------------------------------------ launch autotuning */
 

@@ -24,6 +24,7 @@ NO_CULL = 2
 WARM_NO_FALLBACK = 4
 CP_TUNE_W = 1
 POOLED, PER_MOTION, GENERIC = 8, 16, 32
+SPECIALIZE_PROJECT, SPECIALIZE_PLAN = 1, 2
 PROJECT_PARALLEL, PROJECT_INDEPENDENT, PROJECT_SEQUENTIAL = 0, 1, 2
 WORK_SLOTS = 8
 
@@ -105,7 +106,7 @@ def lib():
         L.cp_robot_create.argtypes = [C.POINTER(RobotDesc), C.POINTER(vp)]
         L.cp_env_create.argtypes = [C.POINTER(EnvDesc), C.POINTER(vp)]
         L.cp_robot_destroy.argtypes = [vp]
-        L.cp_robot_specialize.argtypes = [vp, C.POINTER(Constraint), C.POINTER(C.c_double)]
+        L.cp_robot_specialize.argtypes = [vp, C.POINTER(Constraint), C.c_int32, C.POINTER(C.c_double)]
         L.cp_env_destroy.argtypes = [vp]
         L.cp_proj_params_default.argtypes = [C.POINTER(ProjParams)]
         L.fk_cc_batch.argtypes = [vp, vp, C.c_int32, vp, vp, vp, C.c_int32, vp]
@@ -183,11 +184,14 @@ class Robot:
         self.dof = int(rd["dof"])
         self.n_spheres = len(sl)
 
-    def specialize(self, con) -> float:
-        """Compiles (hipRTC) the pooled projection kernel for this robot and
-        the constraint's kind and locked axes; returns the compile time in ms."""
+    def specialize(self, con, project: bool = True, plan: bool = False) -> float:
+        """Compiles (hipRTC) the pooled projection kernel and / or the
+        planner's round kernels for this robot and the constraint's kind and
+        locked axes; returns this call's compile time in ms (0 when nothing
+        was left to compile)."""
         ms = C.c_double(0.0)
-        _check(lib().cp_robot_specialize(self.handle, C.byref(con), C.byref(ms)))
+        what = (SPECIALIZE_PROJECT if project else 0) | (SPECIALIZE_PLAN if plan else 0)
+        _check(lib().cp_robot_specialize(self.handle, C.byref(con), what, C.byref(ms)))
         return ms.value
 
     def __del__(self):

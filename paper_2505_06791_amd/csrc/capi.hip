@@ -366,7 +366,7 @@ int do_project(const cp_robot* robot, const cp_constraint* constraint, const cp_
   // the pooled form is the one to run
   if (!(flags & CP_GENERIC) && p.variant != CP_PROJECT_SEQUENTIAL && use_pool(n_motions, pooled)) {
     const RtcKernel* rk = rtc_find(const_cast<cp_robot*>(robot), con);
-    if (rk) {
+    if (rk && rk->fn) {
       hipError_t e = launch_rtc_pool(rk, robot, con, prm, n_motions, d_q_from, d_q_to, d_xi,
                                      d_status, d_iters, (unsigned long long*)d_work,
                                      (hipStream_t)stream);

@@ -23,7 +23,12 @@
 // A pair collides iff dist(centre, solid) <= r; the verdict form compares
 // squared distances, the exact form computes dist - r and keeps its minimum.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <float.h>
+#endif
+#ifndef FLT_MAX
+#define FLT_MAX 3.402823466e+38F   // the run-time compiler has no <float.h>
+#endif
 
 #include "device.h"
 
@@ -251,7 +256,7 @@ __device__ __forceinline__ void cc_work_clear(CcWork& w) {
 // Control flow is wave-uniform except where W = 32 lets two motions of one
 // wave leave at different batches (a box reduced while the other motion has
 // left can only grow by stale lanes, which keeps the culling conservative).
-template <int B, bool SD, bool MOTION, bool CULL>
+template <int B, bool SD, bool MOTION, bool CULL, class P = RobotMem>
 __device__ void collide_config(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
                                const EnvDev& env, const float* q, bool lane_on, uint64_t segmask,
                                bool early, uint64_t& hits_out, float& msd_out, CcWork& work) {
@@ -260,19 +265,19 @@ __device__ void collide_config(const RobotDev* __restrict__ rob, const float4* _
   const uint64_t on_mask = __ballot(lane_on);
   const int n_on = __popcll(on_mask & (MOTION ? segmask : ~0ull));
   const int n_prims = env.n_aabb + env.n_obb + env.n_sph + env.n_cap + env.n_cyl;
-  const int nch = rob->n_chains;
+  const int nch = P::n_chains(rob);
   for (int c = 0; c < nch; ++c) {
     Frame T;
-    frame_from(T, rob->base[c]);
-    const int j1 = rob->chain_begin[c + 1];
-    for (int j = rob->chain_begin[c]; j < j1; ++j) {
-      joint_advance(T, rob, j, q[j]);
-      const int s1 = rob->sph_begin[j + 1];
-      for (int s = rob->sph_begin[j]; s < s1; s += B) {
+    frame_from_p<P>(T, rob, c, false);
+    const int j1 = P::chain_begin(rob, c + 1);
+    for (int j = P::chain_begin(rob, c); j < j1; ++j) {
+      joint_advance<P>(T, rob, j, q[j]);
+      const int s1 = P::sph_begin(rob, j + 1);
+      for (int s = P::sph_begin(rob, j); s < s1; s += B) {
         float cx[B], cy[B], cz[B], rr[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-          const float4 l = sph[min(s + b, s1 - 1)];  // a short batch repeats its last sphere
+          const float4 l = P::sphere(sph, min(s + b, s1 - 1));  // a short batch repeats its last sphere
           cx[b] = T.r[0] * l.x + T.r[1] * l.y + T.r[2] * l.z + T.p[0];
           cy[b] = T.r[3] * l.x + T.r[4] * l.y + T.r[5] * l.z + T.p[1];
           cz[b] = T.r[6] * l.x + T.r[7] * l.y + T.r[8] * l.z + T.p[2];

@@ -155,6 +155,11 @@ struct RobotMem {
   static __device__ __forceinline__ float base(const RobotDev* r, int c, int i) { return r->base[c][i]; }
   static __device__ __forceinline__ float tool(const RobotDev* r, int c, int i) { return r->tool[c][i]; }
   static __device__ __forceinline__ bool lock(const ConDev& c, int i) { return c.mask[i] != 0.0f; }
+  // collision spheres: chains, spheres riding in joint frame j, sphere s
+  static __device__ __forceinline__ int n_chains(const RobotDev* r) { return r->n_chains; }
+  static __device__ __forceinline__ int chain_begin(const RobotDev* r, int c) { return r->chain_begin[c]; }
+  static __device__ __forceinline__ int sph_begin(const RobotDev* r, int j) { return r->sph_begin[j]; }
+  static __device__ __forceinline__ float4 sphere(const float4* __restrict__ sph, int s) { return sph[s]; }
 };
 
 // T * tool_c of the policy.

@@ -5,6 +5,7 @@
 
 #include <deque>
 #include <mutex>
+#include <vector>
 
 #include "cprrtc.h"
 #include "device.h"
@@ -15,10 +16,12 @@ namespace cprrtc {
 struct RtcKernel {
   int kind = 0;
   unsigned mask = 0;                // bit i = axis i locked
-  hipModule_t module = nullptr;
-  hipFunction_t fn = nullptr;
+  std::vector<hipModule_t> modules;  // every module this entry's kernels live in
+  hipFunction_t fn = nullptr;       // pooled projection
+  hipFunction_t plan_fn[2] = {nullptr, nullptr};   // planner round, sphere batch 4 / 8
   double compile_ms = 0.0;
 };
+struct PlanDev;
 }  // namespace cprrtc
 
 struct cp_robot {
@@ -47,5 +50,8 @@ hipError_t launch_rtc_pool(const RtcKernel* k, const cp_robot* robot, const ConD
                            const ProjDev& prm, int n_motions, const float* q_from,
                            const float* q_to, float* xi, int* status, int* iters,
                            unsigned long long* work, hipStream_t stream);
+hipError_t launch_rtc_plan_round(const RtcKernel* k, const cp_robot* robot, const EnvDev& env,
+                                 const ConDev& con, const ProjDev& prm, const PlanDev& pd,
+                                 int sphere_batch, unsigned blocks, hipStream_t stream);
 void rtc_release(cp_robot* robot);
 }  // namespace cprrtc

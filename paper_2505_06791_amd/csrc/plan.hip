@@ -32,236 +32,10 @@
 #include "device.h"
 #include "handles.h"
 #include "kernels.h"
+#include "plan_device.h"
 #include "project.h"
 
 namespace cprrtc {
-
-constexpr int kPlanBlock = 256;
-constexpr unsigned kPrimes[kMaxDof] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53};
-
-struct PlanDev {
-  float* q[2];          // [dof][cap] node configurations (structure of arrays)
-  int* parent[2];       // [cap]
-  float* edge[2];       // [cap][W][dof] dense edge from the parent to the node
-  float* scratch;       // [n_groups][W][dof] segment under test
-  int* ctl;             // control block, see kCtl*
-  int cap;
-  int n_groups;
-  int max_connect;
-  float step;           // steer length (W - 1) tau
-  float connect2;       // (tau + tau_sm)^2
-  float shift[kMaxDof]; // Cranley-Patterson shift per dimension
-  unsigned sample_base; // Halton index of the round's first sample
-};
-
-// control block layout (ints)
-enum { kCtlCount = 0, kCtlPublished = 2, kCtlDone = 4, kCtlConn = 5, kCtlOverflow = 8, kCtlInts = 16 };
-
-// Radical inverse of i in base b (Halton coordinate).
-__device__ __forceinline__ float radical_inverse(unsigned i, unsigned b) {
-  const float inv = 1.0f / (float)b;
-  float f = inv, r = 0.0f;
-  while (i) {
-    const unsigned d = i % b;
-    r += (float)d * f;
-    i /= b;
-    f *= inv;
-  }
-  return r;
-}
-
-// Nearest published node (squared L2 in joint space, ties to the lowest
-// index): lanes scan nodes 64 apart, then a wavefront argmin.
-template <int NDOF>
-__device__ __forceinline__ int nearest_node(const float* __restrict__ qs, int n, int cap,
-                                            const float (&x)[NDOF], float& best_d2) {
-  const int lane = threadIdx.x & 63;
-  float best = FLT_MAX;
-  int bi = 0x7fffffff;
-  for (int i = lane; i < n; i += 64) {
-    float d = 0.0f;
-#pragma unroll
-    for (int j = 0; j < NDOF; ++j) {
-      const float t = qs[j * cap + i] - x[j];
-      d += t * t;
-    }
-    if (d < best) {
-      best = d;
-      bi = i;
-    }
-  }
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const float ob = __shfl_xor(best, o, 64);
-    const int oi = __shfl_xor(bi, o, 64);
-    if (ob < best || (ob == best && oi < bi)) {
-      best = ob;
-      bi = oi;
-    }
-  }
-  best_d2 = best;
-  return bi;
-}
-
-template <int NDOF>
-__device__ __forceinline__ float dist2(const float (&a)[NDOF], const float (&b)[NDOF]) {
-  float d = 0.0f;
-#pragma unroll
-  for (int j = 0; j < NDOF; ++j) {
-    const float t = a[j] - b[j];
-    d += t * t;
-  }
-  return d;
-}
-
-// q_steer = a + min(1, step / |b - a|) (b - a)
-template <int NDOF>
-__device__ __forceinline__ void steer(const float (&a)[NDOF], const float (&b)[NDOF], float step,
-                                      float (&out)[NDOF]) {
-  const float d = sqrtf(dist2<NDOF>(a, b));
-  const float s = d > step ? step / d : 1.0f;
-#pragma unroll
-  for (int j = 0; j < NDOF; ++j) out[j] = a[j] + s * (b[j] - a[j]);
-}
-
-// One motion a -> b on this wavefront (lanes 0..W-1), projected and
-// validated.  q: this lane's projected waypoint; end: xi[W-1] broadcast.
-template <int NDOF, int KIND, int B>
-__device__ __forceinline__ bool try_motion(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
-                           const EnvDev& env, const ConDev& con, const ProjDev& prm,
-                           float* __restrict__ scratch, const float (&a)[NDOF],
-                           const float (&b)[NDOF], float (&q)[NDOF], float (&end)[NDOF]) {
-  const int W = prm.W;
-  const int lane = threadIdx.x & 63;
-  const int k = lane % W;
-  const int seg = lane - k;
-  const bool in_motion = lane < W;
-  const uint64_t wmask = (W == 64) ? ~0ull : ((1ull << W) - 1ull);
-  const uint64_t segmask = wmask << seg;
-  const float s = (float)k / (float)(W - 1);
-#pragma unroll
-  for (int j = 0; j < NDOF; ++j) q[j] = a[j] + s * (b[j] - a[j]);
-  int iters = 0;
-  unsigned long long updates = 0;
-  const bool ok =
-      prm.variant == CP_PROJECT_SEQUENTIAL
-          ? project_sequential<NDOF, KIND>(rob, con, prm, k, seg, !in_motion, q, iters, updates)
-          : project_segment<NDOF, KIND>(rob, con, prm, k, seg, wmask, segmask, !in_motion, q,
-                                        iters, updates);
-  if (!__shfl(ok ? 1 : 0, 0, 64)) return false;
-  float* xk = scratch + (size_t)(in_motion ? lane : 0) * NDOF;
-  if (in_motion) {
-#pragma unroll
-    for (int j = 0; j < NDOF; ++j) xk[j] = q[j];
-  }
-  uint64_t hits;
-  float msd;
-  CcWork cw;
-  cc_work_clear(cw);
-  collide_config<B, false, true, true>(rob, sph, env, xk, in_motion && k >= 1, segmask, true, hits,
-                                       msd, cw);
-  const uint64_t all_hits = __ballot((hits & segmask) != 0 && in_motion);
-  if (all_hits) return false;
-#pragma unroll
-  for (int j = 0; j < NDOF; ++j) end[j] = __shfl(q[j], W - 1, 64);
-  return true;
-}
-
-// Append the projected segment held in the lanes' q as a new node of tree t
-// with the given parent.  Returns the slot, or -1 if the tree is full.
-template <int NDOF>
-__device__ __forceinline__ int append_node(const PlanDev& pd, int W, int t, int parent, const float (&q)[NDOF]) {
-  const int lane = threadIdx.x & 63;
-  int slot = 0;
-  if (lane == 0) slot = atomicAdd(&pd.ctl[kCtlCount + t], 1);
-  slot = __shfl(slot, 0, 64);
-  if (slot >= pd.cap) {
-    if (lane == 0) atomicExch(&pd.ctl[kCtlOverflow], 1);
-    return -1;
-  }
-  if (lane < W) {
-    float* e = pd.edge[t] + ((size_t)slot * W + lane) * NDOF;
-#pragma unroll
-    for (int j = 0; j < NDOF; ++j) e[j] = q[j];
-  }
-  if (lane == W - 1) {
-#pragma unroll
-    for (int j = 0; j < NDOF; ++j) pd.q[t][(size_t)j * pd.cap + slot] = q[j];
-    pd.parent[t][slot] = parent;
-  }
-  return slot;
-}
-
-template <int NDOF>
-__device__ __forceinline__ void load_node(const PlanDev& pd, int t, int i, float (&out)[NDOF]) {
-#pragma unroll
-  for (int j = 0; j < NDOF; ++j) out[j] = pd.q[t][(size_t)j * pd.cap + i];
-}
-
-__device__ __forceinline__ bool plan_done(const PlanDev& pd) {
-  return __atomic_load_n(&pd.ctl[kCtlDone], __ATOMIC_RELAXED) != 0;
-}
-
-// One tree extension of one wavefront (group g of the round): sample, grow
-// the group's tree by one motion, then towards the other tree.
-template <int NDOF, int KIND, int B>
-__device__ __forceinline__ void plan_extend(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
-                            const EnvDev& env, const ConDev& con, const ProjDev& prm,
-                            const PlanDev& pd, unsigned sample_base, int g) {
-  const int lane = threadIdx.x & 63;
-  if (__shfl(plan_done(pd) ? 1 : 0, 0, 64)) return;
-  const int W = prm.W;
-  const int X = g & 1, Y = X ^ 1;               // half the wavefronts grow each tree
-  const int pubX = pd.ctl[kCtlPublished + X], pubY = pd.ctl[kCtlPublished + Y];
-  float* scratch = pd.scratch + (size_t)g * W * NDOF;
-
-  // Halton sample: lane j computes coordinate j, then every lane takes all.
-  float u = 0.0f;
-  if (lane < NDOF) {
-    u = radical_inverse(sample_base + (unsigned)g + 1u, kPrimes[lane]) + pd.shift[lane];
-    u -= floorf(u);
-  }
-  float qr[NDOF];
-#pragma unroll
-  for (int j = 0; j < NDOF; ++j) qr[j] = rob->lo[j] + __shfl(u, j, 64) * (rob->hi[j] - rob->lo[j]);
-
-  float d2;
-  const int near = nearest_node<NDOF>(pd.q[X], pubX, pd.cap, qr, d2);
-  float qn[NDOF], qs[NDOF], q[NDOF], qe[NDOF];
-  load_node<NDOF>(pd, X, near, qn);
-  steer<NDOF>(qn, qr, pd.step, qs);
-  if (!try_motion<NDOF, KIND, B>(rob, sph, env, con, prm, scratch, qn, qs, q, qe)) return;
-  int cur = append_node<NDOF>(pd, W, X, near, q);
-  if (cur < 0) return;
-
-  // extend the same tree towards the nearest node of the other tree
-  float qt[NDOF];
-  const int tgt = nearest_node<NDOF>(pd.q[Y], pubY, pd.cap, qe, d2);
-  load_node<NDOF>(pd, Y, tgt, qt);
-  float dcur = dist2<NDOF>(qe, qt);
-  for (int c = 0;; ++c) {
-    if (dcur < pd.connect2) {
-      if (lane == 0 && atomicCAS(&pd.ctl[kCtlDone], 0, 1) == 0) {
-        pd.ctl[kCtlConn + 0] = X;
-        pd.ctl[kCtlConn + 1] = cur;
-        pd.ctl[kCtlConn + 2] = tgt;
-      }
-      return;
-    }
-    if (c >= pd.max_connect) return;
-    if (__shfl(plan_done(pd) ? 1 : 0, 0, 64)) return;
-    steer<NDOF>(qe, qt, pd.step, qs);
-    float qe2[NDOF];
-    if (!try_motion<NDOF, KIND, B>(rob, sph, env, con, prm, scratch, qe, qs, q, qe2)) return;
-    const float dnew = dist2<NDOF>(qe2, qt);
-    if (!(dnew < dcur)) return;                  // no progress: stop extending
-    cur = append_node<NDOF>(pd, W, X, cur, q);
-    if (cur < 0) return;
-#pragma unroll
-    for (int j = 0; j < NDOF; ++j) qe[j] = qe2[j];
-    dcur = dnew;
-  }
-}
 
 template <int NDOF, int KIND, int B>
 __global__ __launch_bounds__(kPlanBlock) void plan_round_kernel(const RobotDev* __restrict__ rob,
@@ -677,11 +451,18 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
 
     int rounds = 0;
     bool done = false;
+    // the round kernel compiled for this robot and mask (cp_robot_specialize), if any
+    const RtcKernel* rk = rtc_find(const_cast<cp_robot*>(robot), con);
+    if (rk && !rk->plan_fn[0]) rk = nullptr;
     while (rounds < o.max_rounds && !done) {
       pd.sample_base = (unsigned)rounds * (unsigned)o.n_groups;
-      if (!launch_round(n, con.kind, pp.sphere_batch, nb, st, robot->dev, robot->spheres,
-                        env->view, con, prm, pd))
+      if (rk) {
+        he = launch_rtc_plan_round(rk, robot, env->view, con, prm, pd, pp.sphere_batch, nb, st);
+        if (he != hipSuccess) return api_hip_fail(he, "cp_plan round (run-time compiled kernel)");
+      } else if (!launch_round(n, con.kind, pp.sphere_batch, nb, st, robot->dev, robot->spheres,
+                               env->view, con, prm, pd)) {
         return api_fail(CP_E_UNSUPPORTED, "no planning kernel for dof %d, constraint kind %d", n, con.kind);
+      }
       publish_kernel<<<1, 1, 0, st>>>(pl->ctl, o.capacity);
       ++rounds;
       if (rounds % o.poll_every == 0 || rounds == o.max_rounds) {

@@ -296,7 +296,7 @@ __device__ __forceinline__ bool waypoint_update(const RobotDev* __restrict__ rob
 // their new value.  `idle` lanes (outside any motion) count as valid so that
 // their segment finishes at once.  Returns true on success; iters = iterations
 // used (max_iters on failure); updates += waypoint updates computed.
-template <int NDOF, int KIND>
+template <int NDOF, int KIND, class P = RobotMem>
 __device__ __forceinline__ bool project_segment(const RobotDev* __restrict__ rob, const ConDev& con,
                                                 const ProjDev& prm, int k, int seg,
                                                 uint64_t wmask, uint64_t segmask, bool idle,
@@ -310,7 +310,7 @@ __device__ __forceinline__ bool project_segment(const RobotDev* __restrict__ rob
 #pragma unroll
     for (int j = 0; j < NDOF; ++j) qprev[j] = __shfl_up(q[j], 1, W);
     float qn[NDOF];
-    const bool ok = waypoint_update<NDOF, KIND>(rob, con, prm, q, qprev, qn);
+    const bool ok = waypoint_update<NDOF, KIND, P>(rob, con, prm, q, qprev, qn);
     const bool valid = idle || (k <= prog) || ok;
     const uint64_t bits = (__ballot(valid) & segmask) >> seg;
     const uint64_t invalid = ~bits & wmask;      // bits 0..prog are set

@@ -1,15 +1,17 @@
-// Run-time specialisation (hipRTC) of the pooled projection kernel: the
-// robot's joint constants (twists, offsets, joint types, limits, base and
-// tool frames) and the constraint's locked axes are written into the kernel
-// source as constants, so the compiler folds them (zero twists and offsets
-// drop out of the frame updates, prismatic tests and free-axis branches
-// disappear: 21% fewer instructions for the 7-DOF arm on a plane).  The
-// device code is the library's own (device.h, project.h, project_pool.h,
-// handed to hipRTC as in-memory headers); only the policy class that
-// supplies the constants is generated.
+// Run-time specialisation (hipRTC) of the pooled projection kernel and of
+// the planner's round kernels: the robot's joint constants (twists, offsets,
+// joint types, limits, base and tool frames, collision spheres) and the
+// constraint's locked axes are written into the kernel source as constants,
+// so the compiler folds them (zero twists and offsets drop out of the frame
+// updates, prismatic tests and free-axis branches disappear: 42% fewer
+// vector instructions for the 7-DOF arm on a plane).  The device code is the
+// library's own (device.h, project.h, project_pool.h, collide.h,
+// plan_device.h, handed to hipRTC as in-memory headers); only the policy
+// class that supplies the constants is generated.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -21,6 +23,7 @@
 #include "device.h"
 #include "handles.h"
 #include "kernels.h"
+#include "plan_device.h"
 #include "rtc_sources.h"   // generated at build time: the headers above as strings
 
 namespace cprrtc {
@@ -42,10 +45,12 @@ std::string array(const char* name, const float* v, int n) {
 }
 
 // The constant policy (same static functions as RobotMem) and the kernel.
-std::string kernel_source(const RobotDev& h, int kind, unsigned mask) {
+std::string kernel_source(const RobotDev& h, int kind, unsigned mask, const float* spheres,
+                          int n_spheres, bool with_pool, bool with_plan) {
   const int n = h.dof;
   std::string s;
-  s += "#include \"device.h\"\n#include \"project.h\"\n#include \"project_pool.h\"\n";
+  s += "#include \"device.h\"\n#include \"project.h\"\n#include \"project_pool.h\"\n"
+       "#include \"plan_device.h\"\n";
   s += "using namespace cprrtc;\n";
   s += "struct RtcPolicy {\n";
   auto fn = [&](const char* name, const float* v, int cnt) {
@@ -77,7 +82,23 @@ std::string kernel_source(const RobotDev& h, int kind, unsigned mask) {
   }
   s += "  static __device__ __forceinline__ bool lock(const ConDev&, int i) {\n    constexpr bool v[6] = {";
   for (int i = 0; i < 6; ++i) s += std::string(i ? ", " : "") + ((mask >> i) & 1 ? "true" : "false");
-  s += "};\n    return v[i];\n  }\n};\n";
+  s += "};\n    return v[i];\n  }\n";
+  // collision spheres (the planner validates its own motions)
+  s += "  static __device__ __forceinline__ int n_chains(const RobotDev*) { return " +
+       std::to_string(h.n_chains) + "; }\n";
+  auto ints = [&](const char* name, const int* v, int cnt, const char* arg) {
+    s += std::string("  static __device__ __forceinline__ int ") + name + "(const RobotDev*, int " +
+         arg + ") {\n    constexpr int v[" + std::to_string(cnt) + "] = {";
+    for (int i = 0; i < cnt; ++i) s += (i ? ", " : "") + std::to_string(v[i]);
+    s += std::string("};\n    return v[") + arg + "];\n  }\n";
+  };
+  ints("chain_begin", h.chain_begin, kMaxChains + 1, "c");
+  ints("sph_begin", h.sph_begin, kMaxDof + 1, "j");
+  s += "  static __device__ __forceinline__ float4 sphere(const float4*, int i) {\n"
+       "    constexpr float v[" + std::to_string(4 * std::max(1, n_spheres)) + "] = {";
+  for (int i = 0; i < 4 * n_spheres; ++i) s += (i ? ", " : "") + lit(spheres[i]);
+  s += "};\n    return make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);\n  }\n};\n";
+  if (with_pool) {
   s += "extern \"C\" __global__ __launch_bounds__(64) void cp_rtc_pool(\n"
        "    const RobotDev* __restrict__ rob, ConDev con, ProjDev prm, int n_motions,\n"
        "    const float* __restrict__ q_from, const float* __restrict__ q_to, float* __restrict__ xi,\n"
@@ -85,6 +106,17 @@ std::string kernel_source(const RobotDev& h, int kind, unsigned mask) {
   s += "  project_pool_body<" + std::to_string(n) + ", " + std::to_string(kind) + ", 0, " +
        std::to_string(kPoolSlots) +
        ", RtcPolicy>(rob, con, prm, n_motions, q_from, q_to, nullptr, xi, status, iters, work);\n}\n";
+  }
+  for (int b : {4, 8}) {
+    if (!with_plan) break;
+    s += "extern \"C\" __global__ __launch_bounds__(kPlanBlock) void cp_rtc_plan" + std::to_string(b) +
+         "(const RobotDev* __restrict__ rob, const float4* __restrict__ sph, EnvDev env, ConDev con,\n"
+         "    ProjDev prm, PlanDev pd) {\n"
+         "  const int g = (int)((blockIdx.x * kPlanBlock + threadIdx.x) >> 6);\n"
+         "  if (g >= pd.n_groups) return;\n"
+         "  plan_extend<" + std::to_string(n) + ", " + std::to_string(kind) + ", " + std::to_string(b) +
+         ", RtcPolicy>(rob, sph, env, con, prm, pd, pd.sample_base, g);\n}\n";
+  }
   return s;
 }
 
@@ -117,10 +149,24 @@ hipError_t launch_rtc_pool(const RtcKernel* k, const cp_robot* robot, const ConD
                                nullptr);
 }
 
+hipError_t launch_rtc_plan_round(const RtcKernel* k, const cp_robot* robot, const EnvDev& env,
+                                 const ConDev& con, const ProjDev& prm, const PlanDev& pd,
+                                 int sphere_batch, unsigned blocks, hipStream_t stream) {
+  const RobotDev* rob = robot->dev;
+  const float4* sph = robot->spheres;
+  EnvDev e = env;
+  ConDev c = con;
+  ProjDev p = prm;
+  PlanDev d = pd;
+  void* args[] = {&rob, &sph, &e, &c, &p, &d};
+  return hipModuleLaunchKernel(k->plan_fn[sphere_batch == 8 ? 1 : 0], blocks, 1, 1, kPlanBlock, 1, 1,
+                               0, stream, args, nullptr);
+}
+
 void rtc_release(cp_robot* robot) {
   std::lock_guard<std::mutex> g(robot->rtc_lock);
   for (RtcKernel& k : robot->rtc)
-    if (k.module) (void)hipModuleUnload(k.module);
+    for (hipModule_t m : k.modules) (void)hipModuleUnload(m);
   robot->rtc.clear();
 }
 
@@ -130,7 +176,8 @@ using namespace cprrtc;
 
 extern "C" {
 
-int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, double* compile_ms) {
+int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_t what,
+                        double* compile_ms) {
   try {
     if (!robot) return api_fail(CP_E_ARG, "cp_robot_specialize: NULL robot");
     ConDev con;
@@ -140,8 +187,14 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, double
     if (!dof_supported(dof)) return api_fail(CP_E_UNSUPPORTED, "cp_robot_specialize: dof %d", dof);
     if (con.kind == KIND_REL && dof % 2)
       return api_fail(CP_E_UNSUPPORTED, "cp_robot_specialize: relative pose needs an even dof");
-    if (const RtcKernel* k = rtc_find(robot, con)) {
-      if (compile_ms) *compile_ms = k->compile_ms;
+    if (what == 0) what = CP_SPECIALIZE_PROJECT;
+    if (what & ~(CP_SPECIALIZE_PROJECT | CP_SPECIALIZE_PLAN))
+      return api_fail(CP_E_ARG, "cp_robot_specialize: what = %d", what);
+    const RtcKernel* have = rtc_find(robot, con);
+    const bool need_pool = (what & CP_SPECIALIZE_PROJECT) && !(have && have->fn);
+    const bool need_plan = (what & CP_SPECIALIZE_PLAN) && !(have && have->plan_fn[0]);
+    if (!need_pool && !need_plan) {
+      if (compile_ms) *compile_ms = 0.0;
       return CP_OK;
     }
     const auto t0 = std::chrono::steady_clock::now();
@@ -150,7 +203,13 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, double
     hipDeviceProp_t props;
     if (he == hipSuccess) he = hipGetDeviceProperties(&props, dev);
     if (he != hipSuccess) return api_hip_fail(he, "cp_robot_specialize");
-    const std::string src = kernel_source(robot->host, con.kind, mask_bits(con));
+    // the spheres as stored on the device (grouped by link)
+    std::vector<float4> sph(robot->host.n_spheres);
+    he = hipMemcpy(sph.data(), robot->spheres, sizeof(float4) * sph.size(), hipMemcpyDeviceToHost);
+    if (he != hipSuccess) return api_hip_fail(he, "cp_robot_specialize: spheres");
+    const std::string src = kernel_source(robot->host, con.kind, mask_bits(con),
+                                          reinterpret_cast<const float*>(sph.data()),
+                                          robot->host.n_spheres, need_pool, need_plan);
     hiprtcProgram prog = nullptr;
     hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "cprrtc_rtc_pool.hip", kRtcHeaderCount,
                                          kRtcHeaders, kRtcHeaderNames);
@@ -179,22 +238,40 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, double
     std::vector<char> code(size);
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
-    RtcKernel k;
-    k.kind = con.kind;
-    k.mask = mask_bits(con);
-    he = hipModuleLoadData(&k.module, code.data());
-    if (he == hipSuccess) he = hipModuleGetFunction(&k.fn, k.module, "cp_rtc_pool");
+    hipModule_t module = nullptr;
+    hipFunction_t pool = nullptr, plan4 = nullptr, plan8 = nullptr;
+    he = hipModuleLoadData(&module, code.data());
+    if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&pool, module, "cp_rtc_pool");
+    if (he == hipSuccess && need_plan) he = hipModuleGetFunction(&plan4, module, "cp_rtc_plan4");
+    if (he == hipSuccess && need_plan) he = hipModuleGetFunction(&plan8, module, "cp_rtc_plan8");
     if (he != hipSuccess) {
-      if (k.module) (void)hipModuleUnload(k.module);
+      if (module) (void)hipModuleUnload(module);
       return api_hip_fail(he, "cp_robot_specialize: loading the compiled kernel");
     }
-    k.compile_ms =
+    const double ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     {
+      // one entry per (kind, mask); kernels compiled later join it (the
+      // entry keeps every module it uses)
       std::lock_guard<std::mutex> g(robot->rtc_lock);
-      robot->rtc.push_back(k);
+      RtcKernel* e = nullptr;
+      for (RtcKernel& k : robot->rtc)
+        if (k.kind == con.kind && k.mask == mask_bits(con)) e = &k;
+      if (!e) {
+        robot->rtc.emplace_back();
+        e = &robot->rtc.back();
+        e->kind = con.kind;
+        e->mask = mask_bits(con);
+      }
+      e->modules.push_back(module);
+      if (pool) e->fn = pool;
+      if (plan4) {
+        e->plan_fn[0] = plan4;
+        e->plan_fn[1] = plan8;
+      }
+      e->compile_ms += ms;
     }
-    if (compile_ms) *compile_ms = k.compile_ms;
+    if (compile_ms) *compile_ms = ms;
     return CP_OK;
   } catch (...) {
     return api_fail(CP_E_ARG, "cp_robot_specialize: unexpected exception");

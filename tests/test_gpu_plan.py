@@ -142,12 +142,14 @@ def _match_trees(q_gpu, p_gpu, q_or, p_or, band_or, slack, tol=1e-4):
     return int(used.sum()) - 1
 
 
-def test_plan_lockstep_replay_matches_oracle_rounds(G):
+@pytest.mark.parametrize("specialised", [False, True])
+def test_plan_lockstep_replay_matches_oracle_rounds(G, specialised):
     """Rounds of the GPU planner against the oracle's round-synchronous
     replay (same Halton indices, same tree per extension, searches over the
     nodes present when the round began).  Compared through the first round
     that holds a decision within the band of its threshold: every node the
-    oracle appended without such a decision has its GPU twin."""
+    oracle appended without such a decision has its GPU twin.  specialised:
+    the round kernels compiled at run time for the robot and mask."""
     compared, matched = 0, 0
     for name, seed in (("cluttered", 2001), ("plain", 1000), ("plain", 1001), ("plain", 1003),
                        ("plain", 1004), ("plain", 1005), ("mobile", 3000)):
@@ -168,6 +170,8 @@ def test_plan_lockstep_replay_matches_oracle_rounds(G):
             ref = O.plan_rounds(ro, eo, co, prm_o, ends[0], ends[1], seed, n_groups=groups,
                                 rounds=lim)
         robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
+        if specialised:
+            assert robot.specialize(con, project=False, plan=True) > 0
         pl = G.Planner(robot, G.plan_opts(n_groups=groups, max_rounds=lim, capacity=4096,
                                           tau_task=w["tau_task"]))
         rc, path, st = pl.plan(env, con, ends[0], ends[1], seed)

@@ -1,6 +1,7 @@
-"""Run-time specialisation (hipRTC) of the pooled projection kernel: the
-kernel compiled with a robot's constants and a constraint's locked axes
-computes what the library kernel computes and meets the oracle.  Folding the
+"""Run-time specialisation (hipRTC) of the pooled projection kernel and of
+the planner's round kernels: kernels compiled with a robot's constants and
+a constraint's locked axes compute what the library kernels compute and
+meet the oracle.  Folding the
 constants lets the compiler fuse multiply-adds differently, so waypoints may
 differ in the last bits: statuses and iterations must agree outside the
 oracle's threshold band, waypoints of motions projected by both within
@@ -12,8 +13,9 @@ torch = pytest.importorskip("torch")
 
 import oracle as O
 from paper_2505_06791_amd import inputs as I
-from tests.helpers import motion_set, oracle_views
+from tests.helpers import manifold_starts, motion_set, oracle_views
 from tests.test_gpu_parity import _compare_pv
+from tests.test_gpu_plan import _check_path
 
 pytestmark = pytest.mark.gpu
 
@@ -64,7 +66,7 @@ def test_specialised_kernel_equals_library_kernel(G, name, W):
     robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
     ms = robot.specialize(con)
     assert ms > 0
-    assert robot.specialize(con) == ms          # kept: the second call compiles nothing
+    assert robot.specialize(con) == 0.0         # kept: the second call compiles nothing
     kw = dict(W=W, tau_task=w["tau_task"])
     xi_s, st_s, it_s = _run(G, robot, env, con, w, q_from, q_to, kw, G.POOLED)
     xi_g, st_g, it_g = _run(G, robot, env, con, w, q_from, q_to, kw, G.POOLED | G.GENERIC)
@@ -98,3 +100,29 @@ def test_specialised_kernel_serves_only_its_mask(G):
     for x, y in zip(a, b):                      # the same kernel ran both times
         assert np.array_equal(x, y)
     _compare_pv("plain other mask", _oracle(w, q_from, q_to, kw), *a, w, 64, 1e-3)
+
+
+@pytest.mark.parametrize("name,seeds", [("plain", range(1000, 1004)), ("cluttered", (2001, 2002)),
+                                        ("dual", (4000, 4001))])
+def test_specialised_planner_paths_pass_oracle_revalidation(G, name, seeds):
+    """cp_plan with the round kernels compiled for the robot and mask: every
+    path passes the oracle's re-validation, and the projection kernel is
+    compiled separately (a plan-only specialisation leaves pooled projection
+    on the library kernel)."""
+    solved = 0
+    for seed in seeds:
+        w = I.workload(name, seed)
+        ends = manifold_starts(w, 2, seed + 5).astype(np.float64)
+        robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
+        ms = robot.specialize(con, project=False, plan=True)
+        assert ms > 0 and robot.specialize(con, project=False, plan=True) == 0.0
+        pl = G.Planner(robot, G.plan_opts(n_groups=128, max_rounds=400, tau_task=w["tau_task"]))
+        rc, path, st = pl.plan(env, con, ends[0], ends[1], seed)
+        print(name, seed, "compile ms", round(ms, 1), "rc", rc,
+              "len", None if path is None else len(path), st, flush=True)
+        if rc == G.CP_OK:
+            solved += 1
+            _check_path(w, path, ends[0], ends[1], w["tau_task"])
+    assert solved >= 1
+    # the projection kernel was not compiled by the plan-only call
+    assert robot.specialize(con) > 0
