@@ -15,7 +15,7 @@ hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& en
 
 // Pooled projection: slots per wavefront, whether a launch of n motions uses
 // it (pooled: 1 = always, 0 = never, -1 = by batch size), its grid size.
-constexpr int kPoolSlots = 6;
+constexpr int kPoolSlots = 4;
 bool use_pool(int n_motions, int pooled);
 unsigned pool_blocks(int n_motions);
 

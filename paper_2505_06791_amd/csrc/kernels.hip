@@ -213,13 +213,16 @@ hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& en
 }
 
 // Motions per pooled wavefront and the number of wavefronts.  Measured on
-// the cluttered 65 536-motion batch (slots x wavefront cap): many short
-// wavefronts that take their slots' motions once balance best (6 slots,
-// up to 64 wavefronts per CU: 1.67 ms; 4 x 16 with refills: 2.08 ms; the
-// one-motion-per-wavefront kernel: 2.53 ms).
+// the cluttered 65 536-motion batch: many short wavefronts that take their
+// slots' motions once balance best (4 slots, one share of 4 motions per
+// wavefront: 1.44 ms, 0.76 ms compiled for the robot; shares of 12: 1.76 /
+// 0.88 ms; 3 slots: 1.48 / 0.76 ms; 6 slots: 1.67 / 1.05 ms; the
+// one-motion-per-wavefront kernel: 2.53 ms).  Fewer slots leave LDS for
+// more wavefronts per CU (4 x 64 x 7 floats: 22 workgroups), which hide
+// the latency of each wavefront's scalar bookkeeping.
 // Below this many motions the pooled form has too few wavefronts to fill the
 // chip (fewer than 4 per SIMD) and one motion per wavefront is used.
-constexpr int kPoolMinMotions = kPoolSlots * 4 * 1024;
+constexpr int kPoolMinMotions = 24576;
 unsigned pool_blocks(int n) {
   const int per = (n + kPoolSlots - 1) / kPoolSlots;
   return (unsigned)std::max(1, std::min(per, 256 * 64));

@@ -68,6 +68,16 @@ std::string kernel_source(const RobotDev& h, int kind, unsigned mask, const floa
        "    constexpr bool v[" + std::to_string(n) + "] = {";
   for (int j = 0; j < n; ++j) s += std::string(j ? ", " : "") + (h.prismatic[j] ? "true" : "false");
   s += "};\n    return v[j];\n  }\n";
+  // a revolute joint whose limits (plus offset) stay within +-3.2 rad takes
+  // the half-angle sine and cosine
+  s += "  static __device__ __forceinline__ bool short_angle(const RobotDev*, int j) {\n"
+       "    constexpr bool v[" + std::to_string(n) + "] = {";
+  for (int j = 0; j < n; ++j) {
+    const bool sh = !h.prismatic[j] && std::fabs(h.lo[j] + h.th0[j]) <= 3.2f &&
+                    std::fabs(h.hi[j] + h.th0[j]) <= 3.2f;
+    s += std::string(j ? ", " : "") + (sh ? "true" : "false");
+  }
+  s += "};\n    return v[j];\n  }\n";
   const int b1 = h.n_chains > 1 ? h.chain_begin[1] : n;
   s += "  static __device__ __forceinline__ int chain1(const RobotDev*, int) { return " +
        std::to_string(b1) + "; }\n";
