@@ -54,8 +54,9 @@ enum {
                             wavefront whatever the batch size (results are the same) */
   CP_PER_MOTION = 16,    /* project_validate_motions: project with one motion per wavefront
                             whatever the batch size (results are the same) */
-  CP_GENERIC = 32        /* project_validate_motions: use the library's projection kernel
-                            even where cp_robot_specialize compiled one for the robot */
+  CP_GENERIC = 32        /* project_validate_motions, validate_motions: use the library's
+                            projection and validation kernels even where
+                            cp_robot_specialize compiled some for the robot */
 };
 
 /* ------------------------------------------------------------ descriptors */
@@ -280,11 +281,16 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
  * base and tool frames, collision spheres and the mask written in as
  * constants (the kernel source is the library's own device code; only the
  * constants differ), and keeps them in the robot handle.  what:
- * CP_SPECIALIZE_PROJECT (0 means this) -- the pooled projection kernel:
- * later calls that project this robot's motions in the pooled form
- * (project_motions, project_validate_motions; see CP_POOLED) with a
- * constraint of the same kind and mask use it, unless flags hold
- * CP_GENERIC; CP_SPECIALIZE_PLAN -- the planner's round kernels: later
+ * CP_SPECIALIZE_PROJECT (0 means this) -- the pooled projection kernel and
+ * the culled validation kernels: later calls that project this robot's
+ * motions in the pooled form (project_motions, project_validate_motions;
+ * see CP_POOLED) with a constraint of the same kind and mask use the
+ * first, and every later culled validation of this robot's motions
+ * (validate_motions, project_validate_motions; the validation kernels
+ * depend on the robot only) the second, unless flags hold CP_GENERIC;
+ * revolute joints whose limits stay within +-3.2 rad take a short sine and
+ * cosine valid there (waypoints are expected within the joint limits);
+ * CP_SPECIALIZE_PLAN -- the planner's round kernels: later
  * cp_plan calls of planners of this robot with such a constraint use them.
  * The constraint's other values (frame, targets) stay arguments.  Rotation
  * entries within 1e-6 of 0 or +-1 are taken as those values.  Kernels

@@ -388,6 +388,17 @@ int do_validate(const cp_robot* robot, const cp_env* env, const cp_proj_params& 
                 int32_t flags, void* stream) {
   if (n_motions == 0) return CP_OK;
   if (!d_xi || !d_status) return fail(CP_E_ARG, "NULL buffer");
+  // the kernels compiled for this robot (cp_robot_specialize), for the
+  // culled form
+  if (!(flags & (CP_GENERIC | CP_NO_CULL))) {
+    if (const RtcKernel* rk = rtc_find_validate(const_cast<cp_robot*>(robot))) {
+      hipError_t e = launch_rtc_validate(rk, robot, env->view, p.W, n_motions, d_xi, d_status,
+                                         (unsigned long long*)d_work, !(flags & CP_NO_EARLY_EXIT),
+                                         p.sphere_batch, (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "validation launch (run-time compiled kernel)");
+      return CP_OK;
+    }
+  }
   hipError_t e = launch_validate(robot->dev, robot->spheres, env->view, p.W, n_motions, d_xi,
                                  d_status, (unsigned long long*)d_work,
                                  !(flags & CP_NO_EARLY_EXIT), !(flags & CP_NO_CULL),

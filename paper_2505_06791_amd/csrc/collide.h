@@ -320,4 +320,44 @@ done:
   msd_out = msd;
 }
 
+// Validation of projected segments, thread gid of the launch: waypoints
+// 1..W-1 of every motion whose projection succeeded (status 0) run FK + CC,
+// one waypoint per lane; the motion leaves at the first batch in which any
+// of its waypoints collides.  Status becomes 0 (valid) or 2 (collision).
+// Shared by the library kernel (RobotMem) and kernels compiled at run time
+// for one robot (a constant policy).
+template <int B, bool CULL, class P>
+__device__ __forceinline__ void validate_body(const RobotDev* __restrict__ rob,
+                                              const float4* __restrict__ sph, const EnvDev& env,
+                                              int W, int n_motions, const float* __restrict__ xi,
+                                              int* __restrict__ status,
+                                              unsigned long long* __restrict__ work, int early,
+                                              int64_t gid) {
+  const int64_t motion = gid / W;
+  const int k = (int)(gid % W);
+  const bool in_range = motion < n_motions;
+  const bool checks = in_range && status[motion] == 0;
+  if (__ballot(checks) == 0) return;   // wave-uniform: nothing to check here
+  const int lane = threadIdx.x & 63;
+  const int seg = lane - k;
+  const uint64_t wmask = (W == 64) ? ~0ull : ((1ull << W) - 1ull);
+  const uint64_t segmask = wmask << seg;
+  const bool lane_on = checks && k >= 1;
+  const float* q = xi + (in_range ? (motion * W + k) : 0) * rob->dof;
+  uint64_t hits;
+  float msd;
+  CcWork cw;
+  cc_work_clear(cw);
+  collide_config<B, false, true, CULL, P>(rob, sph, env, q, lane_on, segmask, early != 0, hits,
+                                          msd, cw);
+  if (checks && k == 0) {
+    status[motion] = (hits & segmask) ? 2 : 0;
+    if (work) {
+      for (int t = 0; t < 5; ++t) atomicAdd(&work[t], cw.pairs[t]);
+      atomicAdd(&work[5], cw.centres);
+      atomicAdd(&work[7], cw.culls);
+    }
+  }
+}
+
 }  // namespace cprrtc

@@ -19,6 +19,7 @@ struct RtcKernel {
   std::vector<hipModule_t> modules;  // every module this entry's kernels live in
   hipFunction_t fn = nullptr;       // pooled projection
   hipFunction_t plan_fn[2] = {nullptr, nullptr};   // planner round, sphere batch 4 / 8
+  hipFunction_t validate_fn[2] = {nullptr, nullptr};   // validation (culled), batch 4 / 8
   double compile_ms = 0.0;
 };
 struct PlanDev;
@@ -46,6 +47,12 @@ int api_params(const cp_proj_params* params, cp_proj_params* p);
 // The run-time compiled pooled kernel for this robot and constraint, if one
 // was made (nullptr otherwise).
 const RtcKernel* rtc_find(cp_robot* robot, const ConDev& con);
+// Any entry of the robot with validation kernels (they depend on the robot only).
+const RtcKernel* rtc_find_validate(cp_robot* robot);
+hipError_t launch_rtc_validate(const RtcKernel* k, const cp_robot* robot, const EnvDev& env, int W,
+                               int n_motions, const float* xi, int* status,
+                               unsigned long long* work, bool early, int batch,
+                               hipStream_t stream);
 hipError_t launch_rtc_pool(const RtcKernel* k, const cp_robot* robot, const ConDev& con,
                            const ProjDev& prm, int n_motions, const float* q_from,
                            const float* q_to, float* xi, int* status, int* iters,

@@ -116,6 +116,13 @@ std::string kernel_source(const RobotDev& h, int kind, unsigned mask, const floa
   s += "  project_pool_body<" + std::to_string(n) + ", " + std::to_string(kind) + ", 0, " +
        std::to_string(kPoolSlots) +
        ", RtcPolicy>(rob, con, prm, n_motions, q_from, q_to, nullptr, xi, status, iters, work);\n}\n";
+    for (int b : {4, 8})
+      s += "extern \"C\" __global__ __launch_bounds__(256) void cp_rtc_validate" + std::to_string(b) +
+           "(const RobotDev* __restrict__ rob, const float4* __restrict__ sph, EnvDev env, int W,\n"
+           "    int n_motions, const float* __restrict__ xi, int* __restrict__ status,\n"
+           "    unsigned long long* __restrict__ work, int early) {\n"
+           "  validate_body<" + std::to_string(b) + ", true, RtcPolicy>(rob, sph, env, W, n_motions, xi,\n"
+           "      status, work, early, (int64_t)blockIdx.x * 256 + threadIdx.x);\n}\n";
   }
   for (int b : {4, 8}) {
     if (!with_plan) break;
@@ -157,6 +164,27 @@ hipError_t launch_rtc_pool(const RtcKernel* k, const cp_robot* robot, const ConD
   void* args[] = {&rob, &c, &p, &n_motions, &q_from, &q_to, &xi, &status, &iters, &work};
   return hipModuleLaunchKernel(k->fn, pool_blocks(n_motions), 1, 1, 64, 1, 1, 0, stream, args,
                                nullptr);
+}
+
+const RtcKernel* rtc_find_validate(cp_robot* robot) {
+  std::lock_guard<std::mutex> g(robot->rtc_lock);
+  for (const RtcKernel& k : robot->rtc)
+    if (k.validate_fn[0]) return &k;
+  return nullptr;
+}
+
+hipError_t launch_rtc_validate(const RtcKernel* k, const cp_robot* robot, const EnvDev& env, int W,
+                               int n_motions, const float* xi, int* status,
+                               unsigned long long* work, bool early, int batch,
+                               hipStream_t stream) {
+  const RobotDev* rob = robot->dev;
+  const float4* sph = robot->spheres;
+  EnvDev e = env;
+  int early_i = early ? 1 : 0;
+  void* args[] = {&rob, &sph, &e, &W, &n_motions, &xi, &status, &work, &early_i};
+  const unsigned nb = (unsigned)(((int64_t)n_motions * W + 255) / 256);
+  return hipModuleLaunchKernel(k->validate_fn[batch == 4 ? 0 : 1], nb, 1, 1, 256, 1, 1, 0, stream,
+                               args, nullptr);
 }
 
 hipError_t launch_rtc_plan_round(const RtcKernel* k, const cp_robot* robot, const EnvDev& env,
@@ -249,9 +277,11 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
     hipModule_t module = nullptr;
-    hipFunction_t pool = nullptr, plan4 = nullptr, plan8 = nullptr;
+    hipFunction_t pool = nullptr, plan4 = nullptr, plan8 = nullptr, val4 = nullptr, val8 = nullptr;
     he = hipModuleLoadData(&module, code.data());
     if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&pool, module, "cp_rtc_pool");
+    if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&val4, module, "cp_rtc_validate4");
+    if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&val8, module, "cp_rtc_validate8");
     if (he == hipSuccess && need_plan) he = hipModuleGetFunction(&plan4, module, "cp_rtc_plan4");
     if (he == hipSuccess && need_plan) he = hipModuleGetFunction(&plan8, module, "cp_rtc_plan8");
     if (he != hipSuccess) {
@@ -274,7 +304,11 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
         e->mask = mask_bits(con);
       }
       e->modules.push_back(module);
-      if (pool) e->fn = pool;
+      if (pool) {
+        e->fn = pool;
+        e->validate_fn[0] = val4;
+        e->validate_fn[1] = val8;
+      }
       if (plan4) {
         e->plan_fn[0] = plan4;
         e->plan_fn[1] = plan8;

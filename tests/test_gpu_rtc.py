@@ -126,3 +126,35 @@ def test_specialised_planner_paths_pass_oracle_revalidation(G, name, seeds):
     assert solved >= 1
     # the projection kernel was not compiled by the plan-only call
     assert robot.specialize(con) > 0
+
+
+@pytest.mark.parametrize("name,W,batch", [("cluttered", 64, 8), ("cluttered", 32, 4),
+                                          ("dual", 64, 8), ("mobile", 64, 4)])
+def test_specialised_validation_equals_library_validation(G, name, W, batch):
+    """validate_motions with the kernels compiled for the robot: the same
+    verdicts as the library's kernels (CP_GENERIC) and as the oracle's
+    clearance of waypoints 1..W-1, outside the 1e-5 m band."""
+    w = _workload(name)
+    q_from, q_to = motion_set(w, 40, 53, W=W)
+    robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
+    kw = dict(W=W, tau_task=w["tau_task"], sphere_batch=batch)
+    xi, st, _ = _run(G, robot, env, con, w, q_from, q_to, kw, G.GENERIC)
+    assert robot.specialize(con) > 0
+    prm = G.proj_params(**kw)
+    ro, eo, co = oracle_views(w)
+    sd = np.array([O.path_report(ro, eo, co, xi[m, 1:].astype(np.float64))["min_sd"]
+                   for m in range(len(xi))])
+    band = np.abs(sd) < 1e-5
+    out = {}
+    for flags in (0, G.GENERIC, G.NO_EARLY_EXIT, G.GENERIC | G.NO_EARLY_EXIT):
+        s = torch.from_numpy(np.where(st == O.MOTION_PROJ_FAIL, 1, 0).astype(np.int32)).to("cuda:0")
+        G.validate_motions(robot, env, prm, torch.from_numpy(xi).to("cuda:0"), s, flags=flags)
+        torch.cuda.synchronize()
+        out[flags] = s.cpu().numpy()
+    print(name, W, batch, "band", int(band.sum()), "statuses", np.bincount(out[0], minlength=3),
+          flush=True)
+    checked = st != O.MOTION_PROJ_FAIL
+    want = np.where(sd < 0, 2, 0)
+    for flags, s in out.items():
+        assert np.array_equal(s[~checked], np.ones((~checked).sum(), np.int32))
+        assert np.array_equal(s[checked & ~band], want[checked & ~band]), flags
