@@ -45,7 +45,7 @@ class _Constraint(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("W", C.c_int32), ("max_iters", C.c_int32), ("tau", C.c_double),
                 ("tau_sm", C.c_double), ("tau_task", C.c_double), ("alpha", C.c_double),
-                ("lam", C.c_double), ("variant", C.c_int32)]
+                ("lam", C.c_double), ("variant", C.c_int32), ("self_collision", C.c_int32)]
 
 
 PROJECT_PARALLEL, PROJECT_INDEPENDENT, PROJECT_SEQUENTIAL = 0, 1, 2
@@ -78,6 +78,8 @@ def lib():
         L.or_task_jacobian.restype = C.c_int32
         L.or_parallel_project.restype = C.c_int32
         L.or_project_config.restype = C.c_int32
+        L.or_self_pairs.restype = C.c_int32
+        L.or_self_min_sd.restype = C.c_double
         _lib = L
     return _lib
 
@@ -139,8 +141,8 @@ class Constraint:
 
 
 def params(W=64, max_iters=32, tau=0.05, tau_sm=0.025, tau_task=1e-3, alpha=1.0, lam=1e-2,
-           variant=PROJECT_PARALLEL):
-    return _Params(W, max_iters, tau, tau_sm, tau_task, alpha, lam, variant)
+           variant=PROJECT_PARALLEL, self_collision=False):
+    return _Params(W, max_iters, tau, tau_sm, tau_task, alpha, lam, variant, int(self_collision))
 
 
 # ------------------------------------------------------------------ wrappers
@@ -208,6 +210,31 @@ def fk_cc_batch(robot: Robot, env: Env, q, n_threads: int = 1):
     msd = np.zeros(n)
     lib().or_fk_cc_batch(C.byref(robot.s), C.byref(env.s), C.c_int32(n), _ptr(q),
                          _ptr(col, _u8p), _ptr(msd), C.c_int32(n_threads))
+    return col, msd
+
+
+def self_pairs(robot: Robot):
+    """Checked self-collision sphere pairs [P][2] (s < t, description order)."""
+    n = lib().or_self_pairs(C.byref(robot.s), C.c_int32(0), None)
+    out = np.zeros((max(n, 1), 2), np.int32)
+    lib().or_self_pairs(C.byref(robot.s), C.c_int32(n), _ptr(out, _ip))
+    return out[:n].copy()
+
+
+def self_min_sd(robot: Robot, q, pairs=None):
+    pairs = self_pairs(robot) if pairs is None else np.ascontiguousarray(pairs, np.int32)
+    return lib().or_self_min_sd(C.byref(robot.s), C.c_int32(len(pairs)),
+                            _ptr(pairs.reshape(-1) if len(pairs) else np.zeros(2, np.int32), _ip),
+                            _ptr(_f64(q)))
+
+
+def self_cc_batch(robot: Robot, q, n_threads: int = 1):
+    q = _f64(q).reshape(-1, robot.dof)
+    n = len(q)
+    col = np.zeros(n, np.uint8)
+    msd = np.zeros(n)
+    lib().or_self_cc_batch(C.byref(robot.s), C.c_int32(n), _ptr(q), _ptr(col, _u8p), _ptr(msd),
+                           C.c_int32(n_threads))
     return col, msd
 
 

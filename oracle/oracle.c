@@ -460,6 +460,73 @@ double or_config_min_sd(const or_robot* r, const or_env* env, const double* q) {
 
 static int clamp_threads(int32_t n) { return n > 0 ? n : 1; }
 
+/* ---------------------------------------------------------------- self-collision */
+
+/* Candidate pair by the link rule (before the home-clearance test). */
+static int self_candidate(const or_robot* r, int s, int t) {
+  const int ls = r->sphere_link[s], lt = r->sphere_link[t];
+  if (r->chain[ls] != r->chain[lt]) return 1;
+  return abs(ls - lt) >= 2;
+}
+
+static double self_pair_sd(const or_robot* r, const double* xyz, int s, int t) {
+  const double dx = xyz[3 * s] - xyz[3 * t];
+  const double dy = xyz[3 * s + 1] - xyz[3 * t + 1];
+  const double dz = xyz[3 * s + 2] - xyz[3 * t + 2];
+  return sqrt(dx * dx + dy * dy + dz * dz) - r->sphere[4 * s + 3] - r->sphere[4 * t + 3];
+}
+
+int32_t or_self_pairs(const or_robot* r, int32_t capacity, int32_t* pairs) {
+  double home[MAXDOF];
+  for (int j = 0; j < r->dof; ++j) home[j] = fmin(fmax(0.0, r->lo[j]), r->hi[j]);
+  double* xyz = (double*)malloc(sizeof(double) * 3 * (r->n_spheres + 1));
+  or_sphere_centres(r, home, xyz);
+  int32_t count = 0;
+  for (int s = 0; s < r->n_spheres; ++s)
+    for (int t = s + 1; t < r->n_spheres; ++t) {
+      if (!self_candidate(r, s, t)) continue;
+      if (!(self_pair_sd(r, xyz, s, t) > OR_SELF_HOME_CLEARANCE)) continue;
+      if (count < capacity) {
+        pairs[2 * count] = s;
+        pairs[2 * count + 1] = t;
+      }
+      ++count;
+    }
+  free(xyz);
+  return count;
+}
+
+double or_self_min_sd(const or_robot* r, int32_t n_pairs, const int32_t* pairs, const double* q) {
+  double* xyz = (double*)malloc(sizeof(double) * 3 * (r->n_spheres + 1));
+  or_sphere_centres(r, q, xyz);
+  double best = DBL_MAX;
+  for (int i = 0; i < n_pairs; ++i) best = fmin(best, self_pair_sd(r, xyz, pairs[2 * i], pairs[2 * i + 1]));
+  free(xyz);
+  return best;
+}
+
+/* The checked pairs of r, allocated (free with free()); *n receives their number. */
+static int32_t* self_pair_list(const or_robot* r, int32_t* n) {
+  *n = or_self_pairs(r, 0, NULL);
+  int32_t* pairs = (int32_t*)malloc(sizeof(int32_t) * 2 * (*n + 1));
+  or_self_pairs(r, *n, pairs);
+  return pairs;
+}
+
+void or_self_cc_batch(const or_robot* r, int32_t n_cfg, const double* q, uint8_t* collide,
+                      double* min_sd, int32_t n_threads) {
+  int32_t np = 0;
+  int32_t* pairs = self_pair_list(r, &np);
+  const int nt = clamp_threads(n_threads);
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 16)
+  for (int32_t i = 0; i < n_cfg; ++i) {
+    const double sd = or_self_min_sd(r, np, pairs, q + (size_t)i * r->dof);
+    if (collide) collide[i] = sd <= 0.0;
+    if (min_sd) min_sd[i] = sd;
+  }
+  free(pairs);
+}
+
 void or_fk_cc_batch(const or_robot* r, const or_env* env, int32_t n_cfg, const double* q,
                     uint8_t* collide, double* min_sd, int32_t n_threads) {
   const int nt = clamp_threads(n_threads);
@@ -605,6 +672,8 @@ void or_project_validate_motions(const or_robot* r, const or_env* env, const or_
                                  double* proj_margin, double* min_sd, int32_t n_threads) {
   const int n = r->dof, W = p->W;
   const int nt = clamp_threads(n_threads);
+  int32_t np = 0;
+  int32_t* pairs = p->self_collision ? self_pair_list(r, &np) : NULL;
 #pragma omp parallel for num_threads(nt) schedule(dynamic, 4)
   for (int32_t i = 0; i < n_motions; ++i) {
     double* x = xi + (size_t)i * W * n;
@@ -620,7 +689,10 @@ void or_project_validate_motions(const or_robot* r, const or_env* env, const or_
     double best = DBL_MAX;
     int st = OR_MOTION_PROJ_FAIL;
     if (ok) {
-      for (int k = 1; k < W; ++k) best = fmin(best, or_config_min_sd(r, env, x + (size_t)k * n));
+      for (int k = 1; k < W; ++k) {
+        best = fmin(best, or_config_min_sd(r, env, x + (size_t)k * n));
+        if (pairs) best = fmin(best, or_self_min_sd(r, np, pairs, x + (size_t)k * n));
+      }
       st = best <= 0.0 ? OR_MOTION_COLLISION : OR_MOTION_VALID;
     }
     status[i] = st;
@@ -628,6 +700,7 @@ void or_project_validate_motions(const or_robot* r, const or_env* env, const or_
     if (proj_margin) proj_margin[i] = mg;
     if (min_sd) min_sd[i] = best;
   }
+  free(pairs);
 }
 
 /* Projection of one configuration (used to put start, goal and tree roots on

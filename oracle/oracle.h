@@ -64,6 +64,7 @@ typedef struct {
   double alpha;             /* step factor */
   double lambda;            /* damping of the least-squares step */
   int32_t variant;          /* OR_PROJECT_PARALLEL, _INDEPENDENT or _SEQUENTIAL */
+  int32_t self_collision;   /* 1: motions are also checked against the robot itself */
 } or_params;
 
 /* Projection operators: Algorithm 1 (PARALLEL); the same iteration without
@@ -89,6 +90,22 @@ double or_sd_capsule(const double* c, double r, const double* cap);
 double or_sd_cylinder(const double* c, double r, const double* cyl);
 void or_sphere_centres(const or_robot* r, const double* q, double* xyz);
 double or_config_min_sd(const or_robot* r, const or_env* env, const double* q);
+
+/* Self-collision (specified here; the paper checks the robot against the
+ * environment only).  Checked pairs: spheres whose links lie in different
+ * chains, or in one chain at least two joints apart, and that are clear by
+ * more than OR_SELF_HOME_CLEARANCE at the home configuration (every joint
+ * at 0 clamped into its limits; pairs overlapping there touch across a
+ * joint by construction and are allowed).  or_self_pairs writes up to
+ * `capacity` pairs (s, t), s < t, description order, lexicographic, and
+ * returns their number.  or_self_min_sd: minimum over the given pairs of
+ * |c_s - c_t| - r_s - r_t (DBL_MAX without pairs); a configuration
+ * self-collides iff it is <= 0. */
+#define OR_SELF_HOME_CLEARANCE 1e-3
+int32_t or_self_pairs(const or_robot* r, int32_t capacity, int32_t* pairs);
+double or_self_min_sd(const or_robot* r, int32_t n_pairs, const int32_t* pairs, const double* q);
+void or_self_cc_batch(const or_robot* r, int32_t n_cfg, const double* q, uint8_t* collide,
+                      double* min_sd, int32_t n_threads);
 
 /* Batched entry points (OpenMP over independent items; n_threads <= 0 means 1). */
 void or_fk_cc_batch(const or_robot* r, const or_env* env, int32_t n_cfg, const double* q,

@@ -698,3 +698,103 @@ def test_subdivided_boxes_keep_every_distance(oracle_lib):
                 assert abs(d1 - dk) < 1e-12
             else:
                 assert dk <= 1e-12      # inside the union: inside (or on) some part
+
+
+# ------------------------------------------------------------------ self-collision
+
+def _planar_3r(spheres, links):
+    """Planar 3R arm (all twists 0, links 0.3 and 0.25 m along x), spheres
+    given as (x, r) on the x axis of their joint frames."""
+    n = len(spheres)
+    return dict(dof=3, n_chains=1, joint_type=np.zeros(3, np.int32),
+                joint_chain=np.zeros(3, np.int32), alpha=np.zeros(3),
+                a=np.array([0.0, 0.3, 0.25]), d=np.zeros(3), theta=np.zeros(3),
+                lo=np.full(3, -3.0), hi=np.full(3, 3.0), base=np.eye(4)[None].copy(),
+                tool=np.eye(4)[None].copy(), sphere_link=np.asarray(links, np.int32),
+                sphere=np.array([[x, 0.0, 0.0, r] for x, r in spheres]).reshape(n, 4))
+
+
+_P3R_SPHERES = [(0.1, 0.05), (0.1, 0.03), (0.2, 0.04), (0.29, 0.05), (-0.24, 0.03)]
+_P3R_LINKS = [0, 1, 2, 0, 2]
+
+
+def test_self_pairs_planar_by_hand(oracle_lib):
+    """Link rule and home clearance on a hand-checked arm: at q = 0 the
+    spheres sit at x = 0.1, 0.4, 0.75, 0.29, 0.31; the link-0 / link-2 pairs
+    are (0,2) clear by 0.56, (0,4) by 0.13, (2,3) by 0.37, and (3,4) overlaps
+    (0.02 apart, radii 0.08) so it is allowed; link 1 is adjacent to both."""
+    O = oracle_lib
+    ro = O.Robot(_planar_3r(_P3R_SPHERES, _P3R_LINKS))
+    assert O.self_pairs(ro).tolist() == [[0, 2], [0, 4], [2, 3]]
+
+
+def test_self_min_sd_planar_closed_form(oracle_lib):
+    """Relative position of a link-0 sphere at x_s and a link-2 sphere at
+    x_t, in joint 0's frame, as a complex number:
+    z = (0.3 - x_s) + e^{i q1} (0.25 + x_t e^{i q2}); sd = |z| - r_s - r_t."""
+    O = oracle_lib
+    ro = O.Robot(_planar_3r(_P3R_SPHERES, _P3R_LINKS))
+    rng = np.random.default_rng(7)
+    n_hit = 0
+    for q in np.concatenate([rng.uniform(-3, 3, (300, 3)), [[0.4, 3.0, 3.0], [1.0, -2.9, 2.6]]]):
+        want = np.inf
+        for s, t in ((0, 2), (0, 4), (2, 3)):
+            (xs, rs), (xt, rt) = _P3R_SPHERES[s], _P3R_SPHERES[t]
+            if _P3R_LINKS[s] == 2:
+                (xs, rs), (xt, rt) = (xt, rt), (xs, rs)
+            z = (0.3 - xs) + np.exp(1j * q[1]) * (0.25 + xt * np.exp(1j * q[2]))
+            want = min(want, abs(z) - rs - rt)
+        got = O.self_min_sd(ro, q)
+        assert abs(got - want) < 1e-12, (q, got, want)
+        n_hit += want <= 0
+    col, msd = O.self_cc_batch(ro, rng.uniform(-3, 3, (50, 3)))
+    assert np.array_equal(col, (msd <= 0).astype(np.uint8))
+    assert n_hit >= 1          # the fold-back configurations collide
+
+
+@pytest.mark.parametrize("name", ["plain", "cluttered", "mobile", "dual"])
+def test_self_pairs_rule_on_workload_robots(oracle_lib, name):
+    """Every listed pair obeys the link rule and is clear at home by more
+    than 1e-3 m; every other pair breaks the rule or is not clear there."""
+    O = oracle_lib
+    w = I.workload(name, 2400)
+    rd = w["robot"]
+    ro = O.Robot(rd)
+    pairs = O.self_pairs(ro)
+    links, chains = np.asarray(rd["sphere_link"]), np.asarray(rd["joint_chain"])
+    home = np.clip(0.0, rd["lo"], rd["hi"])
+    c = O.sphere_centres(ro, home)
+    r = np.asarray(rd["sphere"])[:, 3]
+    listed = {tuple(p) for p in pairs.tolist()}
+    assert len(listed) == len(pairs) and all(s < t for s, t in listed)
+    assert pairs.tolist() == sorted(pairs.tolist())
+    S = len(r)
+    for s in range(S):
+        for t in range(s + 1, S):
+            rule = chains[links[s]] != chains[links[t]] or abs(links[s] - links[t]) >= 2
+            clear = np.linalg.norm(c[s] - c[t]) - r[s] - r[t] > 1e-3
+            assert ((s, t) in listed) == (rule and clear), (s, t)
+    if name == "dual":         # the two arms see each other
+        assert any(chains[links[s]] != chains[links[t]] for s, t in listed)
+
+
+def test_project_validate_with_self_collision(oracle_lib):
+    """With the self-check on, a motion's minimum signed distance is the
+    smaller of its environment and self clearances over waypoints 1..W-1,
+    and collision verdicts only grow."""
+    O = oracle_lib
+    w = I.workload("cluttered", 2401)
+    ro, eo, co = O.Robot(w["robot"]), O.Env(w["env"]), O.Constraint(w["constraint"])
+    rng = np.random.default_rng(3)
+    q_from = I.random_configs(w["robot"], 12, 11)
+    q_to = np.clip(q_from + rng.uniform(-1.5, 1.5, q_from.shape), w["robot"]["lo"], w["robot"]["hi"])
+    a = O.project_validate_motions(ro, eo, co, O.params(), q_from, q_to, n_threads=4)
+    b = O.project_validate_motions(ro, eo, co, O.params(self_collision=True), q_from, q_to,
+                                   n_threads=4)
+    pairs = O.self_pairs(ro)
+    for m in range(len(q_from)):
+        assert b["status"][m] == a["status"][m] or (a["status"][m] == 0 and b["status"][m] == 2)
+        if a["status"][m] == O.MOTION_PROJ_FAIL:
+            continue
+        self_sd = min(O.self_min_sd(ro, x, pairs) for x in b["xi"][m][1:])
+        assert b["min_sd"][m] == min(a["min_sd"][m], self_sd)
