@@ -45,6 +45,9 @@ PAIR_FLOPS = dict(aabb=15, obb=30, sphere=11, capsule=25, cylinder=28)
 PAIR_ORDER = ("aabb", "obb", "sphere", "capsule", "cylinder")   # work counter slots 0..4
 SPHERE_CENTRE_FLOPS = 19          # R l + p, plus r^2
 FK_JOINT_FLOPS = 51               # one joint frame of the chain (sin/cos counted as 1 each)
+# one self-collision pair: centre difference (3), squared length (5), square
+# root (1), minus both radii (2)
+SELF_PAIR_FLOPS = 11
 CULL_FLOPS = 20                   # bounding sphere vs box: 3 x (2 sub, 2 max), |.|^2, reach^2, compare
 
 
@@ -355,10 +358,27 @@ def fkcc_bench(G, I, torch, n=1 << 20, reps=5):
     per_cfg = rd["dof"] * FK_JOINT_FLOPS + len(rd["sphere"]) * (
         SPHERE_CENTRE_FLOPS + sum(env.counts[t] * PAIR_FLOPS[t] for t in PAIR_ORDER))
     tflops = n * per_cfg / (full_ms * 1e-3) / 1e12
+    colliding = int(col.sum().item())
+    # self-collision (CP_SELF_COLLISION): the environment kernel, then one
+    # wavefront per configuration over the checked sphere pairs; its time is
+    # the difference to the environment-only call, every pair evaluated
+    pairs = len(robot.self_pairs())
+    both_ms = _time_ms(torch, lambda: G.fk_cc_batch(robot, env, q, col,
+                                                    flags=G.NO_EARLY_EXIT | G.SELF_COLLISION),
+                       reps)
+    colliding_self = int(col.sum().item())
+    self_ms = both_ms - full_ms
+    self_per_cfg = rd["dof"] * FK_JOINT_FLOPS + len(rd["sphere"]) * SPHERE_CENTRE_FLOPS + \
+        pairs * SELF_PAIR_FLOPS
+    self_tflops = n * self_per_cfg / (self_ms * 1e-3) / 1e12
     return dict(configs=n, every_pair_ms=full_ms, early_exit_ms=early_ms,
-                colliding=int(col.sum().item()), gflop_per_launch=n * per_cfg / 1e9,
+                colliding=colliding, gflop_per_launch=n * per_cfg / 1e9,
                 achieved_tflops=tflops, peak_tflops=FP32_VECTOR_PEAK_TFLOPS,
-                frac=tflops / FP32_VECTOR_PEAK_TFLOPS)
+                frac=tflops / FP32_VECTOR_PEAK_TFLOPS,
+                self_collision=dict(pairs=pairs, with_self_ms=both_ms, self_ms=self_ms,
+                                    colliding_with_self=colliding_self,
+                                    gflop=n * self_per_cfg / 1e9, achieved_tflops=self_tflops,
+                                    frac=self_tflops / FP32_VECTOR_PEAK_TFLOPS))
 
 
 def density_bench(G, I, torch, M=65536, reps=3):

@@ -54,9 +54,11 @@ enum {
                             wavefront whatever the batch size (results are the same) */
   CP_PER_MOTION = 16,    /* project_validate_motions: project with one motion per wavefront
                             whatever the batch size (results are the same) */
-  CP_GENERIC = 32        /* project_validate_motions, validate_motions: use the library's
+  CP_GENERIC = 32,       /* project_validate_motions, validate_motions: use the library's
                             projection and validation kernels even where
                             cp_robot_specialize compiled some for the robot */
+  CP_SELF_COLLISION = 64 /* fk_cc_batch, validate_motions, project_validate_motions: also
+                            check the robot against itself (cp_robot_self_pairs) */
 };
 
 /* ------------------------------------------------------------ descriptors */
@@ -166,11 +168,29 @@ const char* cp_last_error(void);    /* thread-local; valid until the next call o
  *   d_collide  [n_cfg] 1 = collides, 0 = free
  *   d_min_sd   [n_cfg] nullable; if given, every pair is evaluated and the
  *              minimum signed distance is written
- *   flags      CP_NO_EARLY_EXIT: evaluate every pair even after a collision
+ *   flags      CP_NO_EARLY_EXIT: evaluate every pair even after a collision;
+ *              CP_SELF_COLLISION: also the robot against itself
  * Errors: CP_E_ARG (NULL handle/pointer, n_cfg < 0), CP_E_UNSUPPORTED (dof),
  * CP_E_HIP (launch failure). n_cfg = 0 is a no-op. */
 int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const float* d_q,
                 uint8_t* d_collide, float* d_min_sd, int32_t flags, void* stream);
+
+/* Self-collision pairs of a robot (specified here; the paper checks the
+ * robot against the environment only).  A pair of spheres (s, t) is checked
+ * when their links lie in different chains, or in one chain at least two
+ * joints apart, and they are clear by more than 1e-3 m at the home
+ * configuration (every joint at 0 clamped into its limits; pairs that
+ * overlap there touch across a joint by construction and are allowed).  A
+ * configuration self-collides iff some checked pair has signed distance
+ * |c_s - c_t| - r_s - r_t <= 0.  With CP_SELF_COLLISION, fk_cc_batch ORs
+ * this into d_collide (and takes the minimum into d_min_sd), and motion
+ * validation marks a motion colliding (status 2) if any of waypoints
+ * 1..W-1 self-collides (one wavefront per waypoint, lanes over the pairs).
+ *   pairs     out, host, nullable: [capacity][2] sphere indices in
+ *             description order, s < t, sorted; at most capacity written
+ *   count     out: the number of checked pairs
+ * The list is computed once, at cp_robot_create.  Errors: CP_E_ARG. */
+int cp_robot_self_pairs(const cp_robot* robot, int32_t capacity, int32_t* pairs, int32_t* count);
 
 /* Motion projection and validation (Section III and Algorithm 1; Section IV).
  * For each motion i: W waypoints xi[k] = q_from + (k/(W-1)) (q_to - q_from),

@@ -25,6 +25,7 @@ WARM_NO_FALLBACK = 4
 CP_TUNE_W = 1
 POOLED, PER_MOTION, GENERIC = 8, 16, 32
 SPECIALIZE_PROJECT, SPECIALIZE_PLAN = 1, 2
+SELF_COLLISION = 64
 PROJECT_PARALLEL, PROJECT_INDEPENDENT, PROJECT_SEQUENTIAL = 0, 1, 2
 WORK_SLOTS = 8
 
@@ -107,6 +108,7 @@ def lib():
         L.cp_env_create.argtypes = [C.POINTER(EnvDesc), C.POINTER(vp)]
         L.cp_robot_destroy.argtypes = [vp]
         L.cp_robot_specialize.argtypes = [vp, C.POINTER(Constraint), C.c_int32, C.POINTER(C.c_double)]
+        L.cp_robot_self_pairs.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.cp_env_destroy.argtypes = [vp]
         L.cp_proj_params_default.argtypes = [C.POINTER(ProjParams)]
         L.fk_cc_batch.argtypes = [vp, vp, C.c_int32, vp, vp, vp, C.c_int32, vp]
@@ -183,6 +185,15 @@ class Robot:
         self.handle = h
         self.dof = int(rd["dof"])
         self.n_spheres = len(sl)
+
+    def self_pairs(self):
+        """Checked self-collision sphere pairs [P][2] (description order)."""
+        n = C.c_int32(0)
+        _check(lib().cp_robot_self_pairs(self.handle, 0, None, C.byref(n)))
+        out = np.zeros((max(n.value, 1), 2), np.int32)
+        _check(lib().cp_robot_self_pairs(self.handle, n.value,
+                                         out.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(n)))
+        return out[: n.value].copy()
 
     def specialize(self, con, project: bool = True, plan: bool = False) -> float:
         """Compiles (hipRTC) the pooled projection kernel and / or the

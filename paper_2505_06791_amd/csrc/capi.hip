@@ -112,6 +112,76 @@ void cp_proj_params_default(cp_proj_params* p) {
   p->variant = CP_PROJECT_PARALLEL;
 }
 
+namespace {
+
+// Sphere centres (double, world) of a robot description at the home
+// configuration (every joint at 0 clamped into its limits), by the modified
+// DH convention: per joint, rotate about x by alpha, move a along x, rotate
+// about z by theta, move d along z.
+std::vector<double> home_centres(const cp_robot_desc* d) {
+  std::vector<double> frames((size_t)d->dof * 16);
+  for (int c = 0; c < d->n_chains; ++c) {
+    double T[16];
+    std::memcpy(T, d->base + 16 * c, sizeof T);
+    for (int j = 0; j < d->dof; ++j) {
+      if (d->joint_chain[j] != c) continue;
+      const double q = std::min(std::max(0.0, d->q_lo[j]), d->q_hi[j]);
+      const bool pri = d->joint_type[j] == CP_PRISMATIC;
+      const double th = d->theta[j] + (pri ? 0.0 : q), dd = d->d[j] + (pri ? q : 0.0);
+      const double ca = std::cos(d->alpha[j]), sa = std::sin(d->alpha[j]);
+      const double ct = std::cos(th), st = std::sin(th);
+      // the joint's local transform (rows of the 3x4 part)
+      const double L[12] = {ct, -st, 0.0, d->a[j],
+                            ca * st, ca * ct, -sa, -sa * dd,
+                            sa * st, sa * ct, ca, ca * dd};
+      double N[16] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1};
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 4; ++k) {
+          double v = k == 3 ? T[4 * r + 3] : 0.0;
+          for (int m = 0; m < 3; ++m) v += T[4 * r + m] * L[4 * m + k];
+          N[4 * r + k] = v;
+        }
+      std::memcpy(T, N, sizeof T);
+      std::memcpy(&frames[(size_t)j * 16], T, sizeof T);
+    }
+  }
+  std::vector<double> xyz((size_t)d->n_spheres * 3);
+  for (int s = 0; s < d->n_spheres; ++s) {
+    const double* T = &frames[(size_t)d->sphere_link[s] * 16];
+    const double* l = d->sphere + 4 * s;
+    for (int r = 0; r < 3; ++r)
+      xyz[3 * s + r] = T[4 * r] * l[0] + T[4 * r + 1] * l[1] + T[4 * r + 2] * l[2] + T[4 * r + 3];
+  }
+  return xyz;
+}
+
+// Self-collision pairs (description order, s < t, lexicographic): spheres on
+// links of different chains, or of one chain at least two joints apart, that
+// are clear by more than kSelfHomeClearance at the home configuration
+// (pairs that overlap there touch across a joint by construction).
+constexpr double kSelfHomeClearance = 1e-3;
+std::vector<int32_t> self_pairs(const cp_robot_desc* d) {
+  const std::vector<double> c = home_centres(d);
+  std::vector<int32_t> out;
+  for (int s = 0; s < d->n_spheres; ++s)
+    for (int t = s + 1; t < d->n_spheres; ++t) {
+      const int ls = d->sphere_link[s], lt = d->sphere_link[t];
+      const bool rule = d->joint_chain[ls] != d->joint_chain[lt] || std::abs(ls - lt) >= 2;
+      if (!rule) continue;
+      const double dx = c[3 * s] - c[3 * t], dy = c[3 * s + 1] - c[3 * t + 1],
+                   dz = c[3 * s + 2] - c[3 * t + 2];
+      const double sd = std::sqrt(dx * dx + dy * dy + dz * dz) - d->sphere[4 * s + 3] -
+                        d->sphere[4 * t + 3];
+      if (sd > kSelfHomeClearance) {
+        out.push_back(s);
+        out.push_back(t);
+      }
+    }
+  return out;
+}
+
+}  // namespace
+
 int cp_robot_create(const cp_robot_desc* d, cp_robot** out) {
   try {
     if (!d || !out) return fail(CP_E_ARG, "cp_robot_create: NULL argument");
@@ -187,11 +257,23 @@ int cp_robot_create(const cp_robot_desc* d, cp_robot** out) {
     cp_robot* r = new (std::nothrow) cp_robot;
     if (!r) return fail(CP_E_ARG, "out of host memory");
     r->host = h;
+    // self-collision pairs, kept in description order for cp_robot_self_pairs
+    // and as positions in the link-grouped sphere array for the kernels
+    r->self_pairs = self_pairs(d);
+    std::vector<int> rank(d->n_spheres);
+    for (int s = 0; s < d->n_spheres; ++s) rank[order[s]] = s;
+    const int n_pairs = (int)r->self_pairs.size() / 2;
+    std::vector<int2> dev_pairs(n_pairs);
+    for (int i = 0; i < n_pairs; ++i)
+      dev_pairs[i] = make_int2(rank[r->self_pairs[2 * i]], rank[r->self_pairs[2 * i + 1]]);
     hipError_t e = hipMalloc((void**)&r->dev, sizeof(RobotDev));
     if (e == hipSuccess) e = hipMalloc((void**)&r->spheres, sizeof(float4) * sph.size());
+    if (e == hipSuccess && n_pairs > 0) e = hipMalloc((void**)&r->pairs, sizeof(int2) * n_pairs);
     if (e == hipSuccess) e = hipMemcpy(r->dev, &h, sizeof h, hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(r->spheres, sph.data(), sizeof(float4) * sph.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_pairs > 0)
+      e = hipMemcpy(r->pairs, dev_pairs.data(), sizeof(int2) * n_pairs, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       cp_robot_destroy(r);
       return hip_fail(e, "cp_robot_create");
@@ -208,7 +290,24 @@ void cp_robot_destroy(cp_robot* r) {
   rtc_release(r);
   if (r->dev) (void)hipFree(r->dev);
   if (r->spheres) (void)hipFree(r->spheres);
+  if (r->pairs) (void)hipFree(r->pairs);
   delete r;
+}
+
+int cp_robot_self_pairs(const cp_robot* robot, int32_t capacity, int32_t* pairs, int32_t* count) {
+  try {
+    if (!robot || !count) return fail(CP_E_ARG, "cp_robot_self_pairs: NULL argument");
+    if (capacity < 0 || (capacity > 0 && !pairs))
+      return fail(CP_E_ARG, "cp_robot_self_pairs: capacity < 0 or NULL pairs");
+    const int n = (int)robot->self_pairs.size() / 2;
+    *count = n;
+    const int copy = std::min(n, capacity);
+    if (copy > 0)
+      std::memcpy(pairs, robot->self_pairs.data(), sizeof(int32_t) * 2 * (size_t)copy);
+    return CP_OK;
+  } catch (...) {
+    return fail(CP_E_ARG, "cp_robot_self_pairs: unexpected exception");
+  }
 }
 
 int cp_env_create(const cp_env_desc* d, cp_env** out) {
@@ -317,6 +416,12 @@ int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const f
     hipError_t e = launch_fk_cc(robot->dev, robot->spheres, env->view, n_cfg, d_q, d_collide,
                                 d_min_sd, early, 8, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fk_cc_batch launch");
+    if (flags & CP_SELF_COLLISION) {
+      e = launch_self_cc(robot->dev, robot->host, robot->spheres, robot->pairs,
+                         (int)robot->self_pairs.size() / 2, n_cfg, d_q, d_collide, d_min_sd, early,
+                         (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "fk_cc_batch self-collision launch");
+    }
     return CP_OK;
   } catch (...) {
     return fail(CP_E_ARG, "fk_cc_batch: unexpected exception");
@@ -390,20 +495,26 @@ int do_validate(const cp_robot* robot, const cp_env* env, const cp_proj_params& 
   if (!d_xi || !d_status) return fail(CP_E_ARG, "NULL buffer");
   // the kernels compiled for this robot (cp_robot_specialize), for the
   // culled form
-  if (!(flags & (CP_GENERIC | CP_NO_CULL))) {
-    if (const RtcKernel* rk = rtc_find_validate(const_cast<cp_robot*>(robot))) {
-      hipError_t e = launch_rtc_validate(rk, robot, env->view, p.W, n_motions, d_xi, d_status,
-                                         (unsigned long long*)d_work, !(flags & CP_NO_EARLY_EXIT),
-                                         p.sphere_batch, (hipStream_t)stream);
-      if (e != hipSuccess) return hip_fail(e, "validation launch (run-time compiled kernel)");
-      return CP_OK;
-    }
+  const RtcKernel* rk = nullptr;
+  if (!(flags & (CP_GENERIC | CP_NO_CULL))) rk = rtc_find_validate(const_cast<cp_robot*>(robot));
+  if (rk) {
+    hipError_t e = launch_rtc_validate(rk, robot, env->view, p.W, n_motions, d_xi, d_status,
+                                       (unsigned long long*)d_work, !(flags & CP_NO_EARLY_EXIT),
+                                       p.sphere_batch, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "validation launch (run-time compiled kernel)");
+  } else {
+    hipError_t e = launch_validate(robot->dev, robot->spheres, env->view, p.W, n_motions, d_xi,
+                                   d_status, (unsigned long long*)d_work,
+                                   !(flags & CP_NO_EARLY_EXIT), !(flags & CP_NO_CULL),
+                                   p.sphere_batch, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "validation launch");
   }
-  hipError_t e = launch_validate(robot->dev, robot->spheres, env->view, p.W, n_motions, d_xi,
-                                 d_status, (unsigned long long*)d_work,
-                                 !(flags & CP_NO_EARLY_EXIT), !(flags & CP_NO_CULL),
-                                 p.sphere_batch, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "validation launch");
+  if (flags & CP_SELF_COLLISION) {
+    hipError_t e = launch_self_cc_motions(robot->dev, robot->host, robot->spheres, robot->pairs,
+                                          (int)robot->self_pairs.size() / 2, p.W, n_motions,
+                                          d_xi, d_status, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "self-collision launch");
+  }
   return CP_OK;
 }
 

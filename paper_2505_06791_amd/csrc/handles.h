@@ -29,6 +29,8 @@ struct cp_robot {
   cprrtc::RobotDev host;            // host copy (dispatch reads dof, chains, limits)
   cprrtc::RobotDev* dev = nullptr;  // device copy
   float4* spheres = nullptr;        // device spheres, grouped by link
+  int2* pairs = nullptr;            // device self-collision pairs (positions in `spheres`)
+  std::vector<int32_t> self_pairs;  // host, description order: s0 t0 s1 t1 ...
   std::mutex rtc_lock;              // guards rtc (specialisation may run beside projections)
   std::deque<cprrtc::RtcKernel> rtc; // a deque: entries stay put as more are added
 };

@@ -32,6 +32,15 @@ hipError_t launch_project_mode(int dof, int mode, const RobotDev* rob, const Con
                                int* iters, unsigned long long* work, int pooled,
                                hipStream_t stream, bool* supported);
 
+// Self-collision of configurations (OR into collide, min into min_sd) and of
+// motions' waypoints 1..W-1 (status 0 -> 2 on a hit).
+hipError_t launch_self_cc(const RobotDev* rob, const RobotDev& host, const float4* sph,
+                          const int2* pairs, int n_pairs, int n_cfg, const float* q,
+                          uint8_t* collide, float* min_sd, bool early, hipStream_t stream);
+hipError_t launch_self_cc_motions(const RobotDev* rob, const RobotDev& host, const float4* sph,
+                                  const int2* pairs, int n_pairs, int W, int n_motions,
+                                  const float* xi, int* status, hipStream_t stream);
+
 hipError_t launch_validate(const RobotDev* rob, const float4* sph, const EnvDev& env, int W,
                            int n_motions, const float* xi, int* status, unsigned long long* work,
                            bool early, bool cull, int batch, hipStream_t stream);

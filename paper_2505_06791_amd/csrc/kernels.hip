@@ -139,6 +139,112 @@ __global__ __launch_bounds__(kBlock) void validate_kernel(
                                    (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
+// ------------------------------------------------------------------ self-collision
+
+// One wavefront per configuration: every lane runs the (uniform) forward
+// kinematics, lanes place the sphere centres into LDS (sphere s by lane
+// s mod 64), then lanes test the checked pairs 64 at a time:
+// sd = |c_s - c_t| - r_s - r_t, colliding iff sd <= 0.
+//   MOTION = false: item i is configuration i of q; collide[i] |= hit and,
+//                   with min_sd, min_sd[i] = min(min_sd[i], min pair sd)
+//                   (every pair evaluated).
+//   MOTION = true:  item i is waypoint 1 + i mod (W - 1) of motion
+//                   i / (W - 1) in xi; motions whose status is not 0 are
+//                   skipped; a hit sets the status to 2.
+// Four wavefronts per workgroup; LDS holds 4 x n_spheres float4.
+constexpr int kSelfWaves = 4;
+
+template <bool MOTION>
+__global__ __launch_bounds__(64 * kSelfWaves) void self_cc_kernel(
+    const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
+    const int2* __restrict__ pairs, int n_pairs, int64_t n_items, int W,
+    const float* __restrict__ q_all, uint8_t* __restrict__ collide, float* __restrict__ min_sd,
+    int* __restrict__ status, int early) {
+  extern __shared__ float4 centres[];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * kSelfWaves + w;
+  if (item >= n_items) return;                    // wave-uniform
+  const int dof = rob->dof;
+  int64_t motion = 0;
+  const float* q;
+  if (MOTION) {
+    motion = item / (W - 1);
+    if (status[motion] != 0) return;              // failed or already colliding
+    q = q_all + (motion * W + 1 + item % (W - 1)) * dof;
+  } else {
+    q = q_all + item * dof;
+  }
+  float4* c = centres + (size_t)w * rob->n_spheres;
+  for (int ch = 0; ch < rob->n_chains; ++ch) {
+    Frame T;
+    frame_from(T, rob->base[ch]);
+    for (int j = rob->chain_begin[ch]; j < rob->chain_begin[ch + 1]; ++j) {
+      joint_advance(T, rob, j, q[j]);
+      for (int s = rob->sph_begin[j] + lane; s < rob->sph_begin[j + 1]; s += 64) {
+        const float4 l = sph[s];
+        c[s] = make_float4(T.r[0] * l.x + T.r[1] * l.y + T.r[2] * l.z + T.p[0],
+                           T.r[3] * l.x + T.r[4] * l.y + T.r[5] * l.z + T.p[1],
+                           T.r[6] * l.x + T.r[7] * l.y + T.r[8] * l.z + T.p[2], l.w);
+      }
+    }
+  }
+  // the centres other lanes placed are read below: order the stores before
+  // the loads (one wavefront, so a wavefront-scope fence suffices)
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const bool all_pairs = !MOTION && min_sd;
+  float msd = FLT_MAX;
+  bool hit_any = false;
+  for (int base = 0; base < n_pairs; base += 64) {
+    const int p = base + lane;
+    bool hit = false;
+    if (p < n_pairs) {
+      const int2 st = pairs[p];
+      const float4 a = c[st.x], b = c[st.y];
+      const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+      const float sd = sqrtf(dx * dx + dy * dy + dz * dz) - a.w - b.w;
+      msd = fminf(msd, sd);
+      hit = sd <= 0.0f;
+    }
+    if (__ballot(hit)) {
+      hit_any = true;
+      if (early && !all_pairs) break;
+    }
+  }
+  if (all_pairs) msd = wave_min(msd);
+  if (lane == 0) {
+    if (MOTION) {
+      if (hit_any) status[motion] = 2;
+    } else {
+      if (hit_any) collide[item] = 1;
+      if (all_pairs) min_sd[item] = fminf(min_sd[item], msd);
+    }
+  }
+}
+
+hipError_t launch_self_cc(const RobotDev* rob, const RobotDev& host, const float4* sph,
+                          const int2* pairs, int n_pairs, int n_cfg, const float* q,
+                          uint8_t* collide, float* min_sd, bool early, hipStream_t stream) {
+  if (n_pairs == 0 || n_cfg == 0) return hipSuccess;
+  const size_t lds = sizeof(float4) * kSelfWaves * host.n_spheres;
+  const unsigned nb = (unsigned)((n_cfg + kSelfWaves - 1) / kSelfWaves);
+  self_cc_kernel<false><<<nb, 64 * kSelfWaves, lds, stream>>>(
+      rob, sph, pairs, n_pairs, n_cfg, 0, q, collide, min_sd, nullptr, early ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_self_cc_motions(const RobotDev* rob, const RobotDev& host, const float4* sph,
+                                  const int2* pairs, int n_pairs, int W, int n_motions,
+                                  const float* xi, int* status, hipStream_t stream) {
+  if (n_pairs == 0 || n_motions == 0) return hipSuccess;
+  const size_t lds = sizeof(float4) * kSelfWaves * host.n_spheres;
+  const int64_t items = (int64_t)n_motions * (W - 1);
+  const unsigned nb = (unsigned)((items + kSelfWaves - 1) / kSelfWaves);
+  self_cc_kernel<true><<<nb, 64 * kSelfWaves, lds, stream>>>(
+      rob, sph, pairs, n_pairs, items, W, xi, nullptr, nullptr, status, 1);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ single configurations
 
 template <int NDOF, int KIND>

@@ -1,0 +1,120 @@
+"""Self-collision on the GPU against the oracle: the checked pair list, the
+per-configuration check (fk_cc_batch with CP_SELF_COLLISION) and motion
+validation with the self-check.  Verdicts must agree outside the 1e-5 m band
+of the oracle's signed distance; minimum signed distances within 1e-5 m."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from paper_2505_06791_amd import inputs as I
+from tests.helpers import BAND, motion_set, oracle_views
+from tests.test_gpu_parity import _compare_pv, _gpu_fkcc, _run_pv
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_06791_amd import cprrtc
+    cprrtc.lib()
+    return cprrtc
+
+
+@pytest.mark.parametrize("name", ["plain", "cluttered", "mobile", "dual"])
+def test_self_pairs_equal_oracle(G, name):
+    w = I.workload(name, 2400)
+    got = G.Robot(w["robot"]).self_pairs()
+    want = O.self_pairs(O.Robot(w["robot"]))
+    print(name, "pairs", len(got), flush=True)
+    assert len(want) > 0 and np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("name,n", [("plain", 777), ("mobile", 1000), ("dual", 513),
+                                    ("cluttered", 129)])
+def test_fk_cc_with_self_collision_matches_oracle(G, name, n):
+    w = I.workload(name, 2400)
+    q32 = I.random_configs(w["robot"], n, 17).astype(np.float32)
+    ro, eo, _ = oracle_views(w)
+    q64 = q32.astype(np.float64)
+    col_e, sd_e = O.fk_cc_batch(ro, eo, q64, n_threads=8)
+    col_s, sd_s = O.self_cc_batch(ro, q64, n_threads=8)
+    sd_o = np.minimum(sd_e, sd_s)
+    col_o = (sd_o <= 0).astype(np.uint8)
+    col_g, _ = _gpu_fkcc(G, w, q32, flags=G.SELF_COLLISION)
+    col_x, sd_g = _gpu_fkcc(G, w, q32, flags=G.SELF_COLLISION, want_sd=True)
+    col_n, _ = _gpu_fkcc(G, w, q32, flags=G.SELF_COLLISION | G.NO_EARLY_EXIT)
+    col_env, _ = _gpu_fkcc(G, w, q32)
+    band = np.abs(sd_o) <= BAND
+    print(name, n, "self-colliding", int(col_s.sum()), "colliding", int(col_o.sum()),
+          "band", int(band.sum()), flush=True)
+    assert col_s.sum() > 0                     # the check has something to find
+    assert np.array_equal(col_g[~band], col_o[~band])
+    assert np.array_equal(col_x[~band], col_o[~band])
+    assert np.array_equal(col_g, col_n)
+    assert np.abs(sd_g.astype(np.float64) - sd_o).max() < 1e-5
+    # without the flag only the environment counts
+    band_e = np.abs(sd_e) <= BAND
+    assert np.array_equal(col_env[~band_e], col_e[~band_e])
+
+
+def test_fk_cc_self_ragged_sizes(G):
+    """Sizes around the four-wavefront workgroup; one configuration per
+    wavefront, so every count exercises a partial last workgroup."""
+    w = I.workload("mobile", 2401)
+    ro, eo, _ = oracle_views(w)
+    for n in (1, 3, 4, 5, 63, 65):
+        q32 = I.random_configs(w["robot"], n, n + 40).astype(np.float32)
+        q64 = q32.astype(np.float64)
+        sd_o = np.minimum(O.fk_cc_batch(ro, eo, q64)[1], O.self_cc_batch(ro, q64)[1])
+        col_g, sd_g = _gpu_fkcc(G, w, q32, flags=G.SELF_COLLISION, want_sd=True)
+        band = np.abs(sd_o) <= BAND
+        assert np.array_equal(col_g[~band], (sd_o <= 0)[~band].astype(np.uint8)), n
+        assert np.abs(sd_g.astype(np.float64) - sd_o).max() < 1e-5, n
+
+
+def test_robot_without_checked_pairs(G):
+    """Spheres only on adjacent links: no pair is checked and the flag
+    changes nothing."""
+    rd = dict(dof=2, n_chains=1, joint_type=np.zeros(2, np.int32),
+              joint_chain=np.zeros(2, np.int32), alpha=np.zeros(2), a=np.array([0.0, 0.4]),
+              d=np.zeros(2), theta=np.zeros(2), lo=np.full(2, -3.0), hi=np.full(2, 3.0),
+              base=np.eye(4)[None].copy(), tool=np.eye(4)[None].copy(),
+              sphere_link=np.array([0, 1], np.int32),
+              sphere=np.array([[0.2, 0, 0, 0.05], [0.2, 0, 0, 0.05]]))
+    w = dict(robot=rd, env=I.empty_env())
+    robot = G.Robot(rd)
+    assert len(robot.self_pairs()) == 0 and len(O.self_pairs(O.Robot(rd))) == 0
+    q32 = np.random.default_rng(1).uniform(-3, 3, (100, 2)).astype(np.float32)
+    a = _gpu_fkcc(G, w, q32, want_sd=True)
+    b = _gpu_fkcc(G, w, q32, flags=G.SELF_COLLISION, want_sd=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("name,W,M", [("mobile", 64, 40), ("dual", 32, 16), ("plain", 64, 40)])
+def test_project_validate_with_self_collision_matches_oracle(G, name, W, M):
+    w = I.workload(name, 2402)
+    q_from, q_to = motion_set(w, M, 23, W=W)
+    kw = dict(W=W, tau_task=w["tau_task"])
+    xi, st, it = _run_pv(G, w, q_from, q_to, kw, flags=G.SELF_COLLISION)
+    ro, eo, co = oracle_views(w)
+    ref = O.project_validate_motions(ro, eo, co, O.params(self_collision=True, **kw),
+                                     q_from.astype(np.float64), q_to.astype(np.float64),
+                                     n_threads=8)
+    _compare_pv(f"{name} self", ref, xi, st, it, None, W, w["tau_task"])
+    # on the GPU's own waypoints: the verdict is the oracle's (environment or
+    # self) outside the band
+    pairs = O.self_pairs(ro)
+    for m in np.nonzero(st != O.MOTION_PROJ_FAIL)[0]:
+        x = xi[m, 1:].astype(np.float64)
+        sd = min(O.fk_cc_batch(ro, eo, x)[1].min(), min(O.self_min_sd(ro, y, pairs) for y in x))
+        if abs(sd) > BAND:
+            assert (st[m] == O.MOTION_COLLISION) == (sd <= 0.0), (m, st[m], sd)
+    plain_st = _run_pv(G, w, q_from, q_to, kw)[1]
+    grew = (plain_st == 0) & (st == 2)
+    print(name, "motions", M, "self-check turned", int(grew.sum()), "valid into colliding",
+          flush=True)
+    assert np.all((st == plain_st) | grew)
