@@ -137,6 +137,8 @@ def parse():
     ap.add_argument("--rtc-plan-queries", type=int, default=40,
                     help="queries per scene planned for one robot with library and run-time "
                          "compiled round kernels (0 = skip)")
+    ap.add_argument("--shortcut-paths", type=int, default=20,
+                    help="queries per scene whose planned paths are shortcut (0 = skip)")
     ap.add_argument("--density", type=int, default=1,
                     help="obstacle-density sweep of the validation kernel (0 = skip)")
     ap.add_argument("--learned", type=int, default=1,
@@ -208,6 +210,47 @@ def plan_bench(G, I, torch, name, seeds, tau_task, variant=0, fixed=None):
                   f"{sum(times):.0f} ms", file=sys.stderr, flush=True)
     return dict(queries=n, p50_ms=float(np.median(times)), p90_ms=float(np.percentile(times, 90)),
                 success=ok / max(n, 1), mean_rounds=float(np.mean(rounds)))
+
+
+def shortcut_bench(G, I, torch, name, seeds, tau_task, rounds=5, cpu_paths=2):
+    """cp_shortcut on the paths the GPU planner finds for seeded queries
+    (five rounds; planning excluded): wall time per path, path length before
+    and after, and the FP64 oracle's shortcutting of the first few of the
+    same paths on one core for comparison."""
+    import oracle as O
+    times, before, after, paths = [], [], [], []
+    for seed in seeds:
+        w = I.workload(name, seed)
+        robot, env, con, start, goal = gpu_query(G, I, torch, w, seed)
+        if start is None:
+            continue
+        pl = G.Planner(robot, G.plan_opts(n_groups=256, max_rounds=500, capacity=65536,
+                                          tau_task=tau_task))
+        try:
+            rc, path, _ = pl.plan(env, con, start, goal, seed)
+        except G.CprrtcError:
+            continue
+        if rc != G.CP_OK:
+            continue
+        prm = G.proj_params(tau_task=tau_task)
+        t0 = time.perf_counter()
+        _, st = G.shortcut(robot, env, con, prm, path, rounds=rounds)
+        times.append((time.perf_counter() - t0) * 1e3)
+        before.append(st["length_before"])
+        after.append(st["length_after"])
+        paths.append((w, path))
+    cpu = []
+    for w, path in paths[:cpu_paths]:
+        ro, eo, co = O.Robot(w["robot"]), O.Env(w["env"]), O.Constraint(w["constraint"])
+        t0 = time.perf_counter()
+        O.shortcut(ro, eo, co, O.params(tau_task=tau_task), path, rounds=rounds, n_threads=1)
+        cpu.append((time.perf_counter() - t0) * 1e3)
+    print(f"shortcut {name}: {len(times)} paths, p50 {np.median(times):.1f} ms", file=sys.stderr,
+          flush=True)
+    return dict(paths=len(times), rounds=rounds, p50_ms=float(np.median(times)),
+                mean_length_before=float(np.mean(before)), mean_length_after=float(np.mean(after)),
+                cpu_baseline=dict(p50_ms=float(np.median(cpu)), paths=len(cpu), cores=1,
+                                  kind="oracle", sample=f"the first {len(cpu)} of the same paths"))
 
 
 def batch_bench(G, I, torch, n, base=3000, make=None, max_dof=9, rounds=800, tau_task=1e-3):
@@ -684,6 +727,11 @@ def main():
             result["plan_rtc"][name] = {"compile_ms": ms, "library": lib, "specialised": spec}
             print(f"plan_rtc {name}: library p50 {lib['p50_ms']:.2f} ms, specialised "
                   f"{spec['p50_ms']:.2f} ms, compile {ms:.0f} ms", file=sys.stderr, flush=True)
+    if args.shortcut_paths > 0:
+        result["shortcut"] = {name: shortcut_bench(G, I, torch, name,
+                                                   range(base, base + args.shortcut_paths),
+                                                   I.workload(name, base)["tau_task"])
+                              for name, base in (("plain", 1000), ("cluttered", 2000))}
     if args.batch_queries > 0:
         result["batch"] = batch_bench(G, I, torch, args.batch_queries)
     if args.dual_queries > 0:

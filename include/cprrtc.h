@@ -386,6 +386,37 @@ typedef struct cp_plan_stats {
   int32_t overflow;      /* 1 if a tree reached its capacity */
 } cp_plan_stats;
 
+/* Path shortcutting (specified here; the paper returns the planner's path
+ * as it is).  Each round: for every index i of the path P, the farthest
+ * j >= i + 2 with ||P[j] - P[i]|| <= (W-1) tau whose subpath is longer than
+ * the chord is a candidate; all candidates of the round are projected and
+ * validated in one project_validate_motions call (from P[i] towards P[j],
+ * Algorithm 1, flags as given); a candidate is accepted when its motion is
+ * valid, waypoint W-2 lies within tau + tau_sm of P[j], and the piece
+ * (waypoints 1 .. W-2, then P[j]) is shorter than P[i..j]; accepted pieces
+ * replace their subpaths by decreasing gain, skipping any whose interval
+ * meets a kept one except at an end point.  Rounds stop early when none is
+ * accepted.  The result is a dense path between the same end points, every
+ * spacing < tau + tau_sm, never longer than the input.
+ *   path, len   in: [len][dof] host doubles (a dense path, as cp_plan returns)
+ *   rounds      round budget, >= 0
+ *   flags       passed to project_validate_motions (e.g. CP_SELF_COLLISION)
+ *   out         out: the shortened path (out->capacity rows available)
+ *   stats       nullable
+ * Synchronous on `stream`.  Allocates its candidate buffers per call.
+ * Errors: CP_E_ARG, CP_E_UNSUPPORTED (W), CP_E_CAPACITY (out too small;
+ * out->len is set), CP_E_HIP, and those of project_validate_motions. */
+typedef struct cp_shortcut_stats {
+  int32_t rounds;        /* rounds run */
+  int32_t candidates;    /* motions projected over all rounds */
+  int32_t replaced;      /* pieces spliced in */
+  double length_before;  /* sum of consecutive joint-space distances */
+  double length_after;
+} cp_shortcut_stats;
+int cp_shortcut(const cp_robot* robot, const cp_env* env, const cp_constraint* constraint,
+                const cp_proj_params* params, const double* path, int32_t len, int32_t rounds,
+                int32_t flags, cp_path* out, cp_shortcut_stats* stats, void* stream);
+
 typedef struct cp_planner cp_planner;  /* opaque: device trees and scratch for one robot */
 
 void cp_plan_opts_default(cp_plan_opts* o);

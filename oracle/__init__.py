@@ -238,6 +238,72 @@ def self_cc_batch(robot: Robot, q, n_threads: int = 1):
     return col, msd
 
 
+def shortcut(robot: Robot, env: Env, con: Constraint, prm, path, rounds: int, n_threads: int = 8):
+    """Path shortcutting as specified for the library (the paper returns the
+    planner's path as it is).  Per round: for every index i, the farthest
+    j >= i + 2 with |P[j] - P[i]| <= (W-1) tau whose subpath is longer than
+    the chord is a candidate; every candidate motion P[i] -> P[j] is
+    projected and validated (Algorithm 1, then the collision check); it is
+    accepted when valid, waypoint W-2 lies within tau + tau_sm of P[j], and
+    the piece (waypoints 1..W-2, then P[j]) is shorter than P[i..j]; pieces
+    replace their subpaths by decreasing gain, skipping any whose interval
+    meets a kept one except at an end point; stop when none is accepted.
+    Returns (path, dict(rounds, candidates, replaced, length_before,
+    length_after))."""
+    P = [np.asarray(x, np.float64) for x in _f64(path)]
+    W = prm.W
+    reach, link = (W - 1) * prm.tau, prm.tau + prm.tau_sm
+
+    def length(v):
+        return sum(np.linalg.norm(v[k] - v[k - 1]) for k in range(1, len(v)))
+
+    stats = dict(rounds=0, candidates=0, replaced=0, length_before=length(P))
+    for r in range(rounds):
+        L = len(P)
+        cand = []
+        for i in range(L - 2):
+            j = next((k for k in range(L - 1, i + 1, -1) if np.linalg.norm(P[k] - P[i]) <= reach),
+                     None)
+            if j is None:
+                continue
+            if length(P[i:j + 1]) - np.linalg.norm(P[j] - P[i]) <= 1e-9:
+                continue
+            cand.append((i, j))
+        if not cand:
+            break
+        res = project_validate_motions(robot, env, con, prm, np.array([P[i] for i, _ in cand]),
+                                       np.array([P[j] for _, j in cand]), n_threads=n_threads)
+        stats["candidates"] += len(cand)
+        acc = []
+        for m, (i, j) in enumerate(cand):
+            if res["status"][m] != MOTION_VALID:
+                continue
+            x = res["xi"][m]
+            if not np.linalg.norm(x[W - 2] - P[j]) < link:
+                continue
+            piece = [P[i]] + [x[k] for k in range(1, W - 1)] + [P[j]]
+            gain = length(P[i:j + 1]) - length(piece)
+            if gain > 0:
+                acc.append((gain, m, i, j))
+        stats["rounds"] = r + 1
+        if not acc:
+            break
+        acc.sort(key=lambda a: -a[0])          # stable: ties keep candidate order
+        keep = []
+        for gain, m, i, j in acc:
+            if all(j <= ki or kj <= i for _, _, ki, kj in keep):
+                keep.append((gain, m, i, j))
+        keep.sort(key=lambda a: a[2])
+        Q, at = [], 0
+        for _, m, i, j in keep:
+            Q += P[at:i + 1] + [res["xi"][m][k] for k in range(1, W - 1)]
+            at = j
+        P = Q + P[at:]
+        stats["replaced"] += len(keep)
+    stats["length_after"] = length(P)
+    return np.array(P), stats
+
+
 def parallel_project(robot: Robot, con: Constraint, prm, xi_init):
     xi = _f64(xi_init).copy()
     it = C.c_int32(0)

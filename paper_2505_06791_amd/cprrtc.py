@@ -76,6 +76,11 @@ class PlanStats(C.Structure):
     _fields_ = [("rounds", C.c_int32), ("nodes", C.c_int32 * 2), ("overflow", C.c_int32)]
 
 
+class ShortcutStats(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("candidates", C.c_int32), ("replaced", C.c_int32),
+                ("length_before", C.c_double), ("length_after", C.c_double)]
+
+
 class TuneReport(C.Structure):
     _fields_ = [("n", C.c_int32), ("W", C.c_int32 * 4), ("sphere_batch", C.c_int32 * 4),
                 ("ms", C.c_double * 4), ("waypoints_per_s", C.c_double * 4)]
@@ -303,6 +308,25 @@ def project_motions(robot: Robot, con: Constraint, prm: ProjParams, q_from, q_to
         _dev(q_to, torch.float32), _dev(xi, torch.float32), _dev(status, torch.int32),
         _dev(iters, torch.int32) if iters is not None else None,
         _dev(work, torch.int64) if work is not None else None, _stream(stream)))
+
+
+def shortcut(robot: Robot, env: Env, con: Constraint, prm: ProjParams, path, rounds: int,
+             flags: int = 0, max_len: int = None, stream=None):
+    """Path shortcutting (cp_shortcut): path [len, dof] float64 host.
+    Returns (shortened path [len', dof] float64, stats dict)."""
+    path = _f64(path)
+    n, dof = path.shape
+    max_len = max_len or max(n * 64, 1024)
+    buf = np.zeros((max_len, dof))
+    out = Path(max_len, 0, 0, buf.ctypes.data_as(_dp))
+    stats = ShortcutStats()
+    _check(lib().cp_shortcut(robot.handle, env.handle, C.byref(con), C.byref(prm),
+                             path.ctypes.data_as(_dp), n, rounds, flags, C.byref(out),
+                             C.byref(stats), _stream(stream)))
+    return buf[: out.len].copy(), dict(rounds=stats.rounds, candidates=stats.candidates,
+                                       replaced=stats.replaced,
+                                       length_before=stats.length_before,
+                                       length_after=stats.length_after)
 
 
 def validate_motions(robot: Robot, env: Env, prm: ProjParams, xi, status, work=None,

@@ -798,3 +798,64 @@ def test_project_validate_with_self_collision(oracle_lib):
             continue
         self_sd = min(O.self_min_sd(ro, x, pairs) for x in b["xi"][m][1:])
         assert b["min_sd"][m] == min(a["min_sd"][m], self_sd)
+
+
+# ------------------------------------------------------------------ path shortcutting
+
+def _zigzag(start, n=30):
+    steps = np.zeros((n, len(start)))
+    steps[:, 0] = 0.04
+    steps[:, 1] = np.where(np.arange(n) % 2 == 0, 0.02, -0.02)
+    return np.vstack([start, start + np.cumsum(steps, axis=0)])
+
+
+def test_shortcut_unconstrained_free_space_is_the_chord(oracle_lib):
+    """Without constraint or obstacles a zig-zag within the steer length
+    shortcuts to its chord in one round: the straight-line waypoints, length
+    |end - start|, and the next round finds nothing to shorten."""
+    O = oracle_lib
+    w = I.workload("plain", 2403)
+    ro, eo = O.Robot(w["robot"]), O.Env(I.empty_env())
+    co = O.Constraint(I.no_constraint())
+    P = _zigzag(np.zeros(7))
+    out, st = O.shortcut(ro, eo, co, O.params(), P, rounds=3)
+    chord = np.linalg.norm(P[-1] - P[0])
+    assert np.array_equal(out[0], P[0]) and np.array_equal(out[-1], P[-1])
+    assert abs(st["length_after"] - chord) < 1e-12
+    assert st["replaced"] == 1 and st["rounds"] == 1
+    u = (P[-1] - P[0]) / chord
+    for x in out:                                   # every point on the chord
+        d = x - P[0]
+        assert np.linalg.norm(d - (d @ u) * u) < 1e-12
+    assert len(out) == 64                           # start, waypoints 1..62, end
+
+
+def test_shortcut_invariants_on_planned_paths(oracle_lib):
+    """On oracle-planned constrained paths: same end points, never longer,
+    and the result passes the path checks (limits, task error, spacing,
+    clearance)."""
+    O = oracle_lib
+    done = 0
+    for seed in (1000, 1001, 1002):
+        w = I.workload("plain", seed)
+        ro, eo, co = O.Robot(w["robot"]), O.Env(w["env"]), O.Constraint(w["constraint"])
+        rng = np.random.default_rng(seed)
+        ends = []
+        for q in I.random_configs(w["robot"], 64, seed + 5):
+            ok, qp, _ = O.project_config(ro, co, q, tol=1e-9, max_iters=100)
+            if ok and O.config_min_sd(ro, eo, qp) > 1e-3:
+                ends.append(qp)
+            if len(ends) == 2:
+                break
+        prm = O.params(tau_task=w["tau_task"])
+        found, path, _ = O.plan(ro, eo, co, prm, ends[0], ends[1], seed, max_samples=400)
+        if not found:
+            continue
+        out, st = O.shortcut(ro, eo, co, prm, path, rounds=4)
+        assert np.array_equal(out[0], path[0]) and np.array_equal(out[-1], path[-1])
+        assert st["length_after"] <= st["length_before"] + 1e-12
+        rep = O.path_report(ro, eo, co, out)
+        assert rep["inside"] and rep["task_error"] < w["tau_task"]
+        assert rep["spacing"] < 0.075 and rep["min_sd"] > 0
+        done += 1
+    assert done >= 1
