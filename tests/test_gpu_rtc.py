@@ -158,3 +158,30 @@ def test_specialised_validation_equals_library_validation(G, name, W, batch):
     for flags, s in out.items():
         assert np.array_equal(s[~checked], np.ones((~checked).sum(), np.int32))
         assert np.array_equal(s[checked & ~band], want[checked & ~band]), flags
+
+
+def test_full_size_sampled_specialised(G):
+    """The benchmark's launch as bench.py times it: 65 536 cluttered motions
+    with the projection and validation kernels compiled for the robot;
+    sampled motions (and the last) recomputed by the oracle."""
+    from tests.test_gpu_parity import _oracle_pv
+    w = I.workload("cluttered", 2000)
+    base_from, _ = motion_set(w, 256, 2500)
+    M = 65536
+    q_from = np.tile(base_from, (M // len(base_from), 1))
+    q_to = I.random_displacements(w["robot"], q_from.astype(np.float64), 63 * 0.05,
+                                  2501).astype(np.float32)
+    robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
+    assert robot.specialize(con) > 0
+    kw = dict(W=64, tau_task=w["tau_task"])
+    xi, st, it = _run(G, robot, env, con, w, q_from, q_to, kw, 0)
+    idx = np.concatenate([np.sort(np.random.default_rng(0).choice(M, 48, replace=False)), [M - 1]])
+    ref = _oracle_pv(w, q_from[idx], q_to[idx], 64, w["tau_task"])
+    _compare_pv("cluttered-full specialised", ref, xi[idx], st[idx], it[idx], w, 64,
+                w["tau_task"])
+    # the library kernels on the same launch: the same verdicts outside the band
+    xi_g, st_g, it_g = _run(G, robot, env, con, w, q_from, q_to, kw, G.GENERIC)
+    assert set(np.unique(st)).issubset({0, 1, 2})
+    print("statuses specialised", np.bincount(st, minlength=3), "library",
+          np.bincount(st_g, minlength=3), flush=True)
+    assert np.abs(np.bincount(st, minlength=3) - np.bincount(st_g, minlength=3)).max() <= 0.01 * M
