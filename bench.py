@@ -86,18 +86,18 @@ TRAFFIC = [
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h",
                     "paper_2505_06791_amd/csrc/kernels.hip", "paper_2505_06791_amd/csrc/kernels.h"),
-        "sources_sha256": "df4ce27b0802a23836e44f5f5cece3fd70cd8cd81dd982eed2bd8006b0c6ccda",
-        "fetch_kib": 5291.3, "fetch_scale": 262144.0 / 131083.5,
-        "write_kib": 115977.0, "write_scale": 1.0,
+        "sources_sha256": "3493bc62a632345f433e44293604a9d85f241580bf4692528805f105be1a40d0",
+        "fetch_kib": 5290.0, "fetch_scale": 262144.0 / 131083.5,
+        "write_kib": 115976.1, "write_scale": 1.0,
     },
     {
         "kernel": "cp_rtc_pool<7, 1> (hipRTC)",
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h", "paper_2505_06791_amd/csrc/rtc.hip",
                     "paper_2505_06791_amd/csrc/kernels.h", "include/cprrtc.h"),
-        "sources_sha256": "d1b28df5ce642ba29600f70c2eaf7cfe4511189038fd59725d03b1ac1218a99d",
-        "fetch_kib": 5223.3, "fetch_scale": 262144.0 / 131083.5,
-        "write_kib": 116252.2, "write_scale": 1.0,
+        "sources_sha256": "eedc67b4043ee2d6e1aaf621d14e545df795ffd9bdc78cf8a870ca19fa70f280",
+        "fetch_kib": 5223.6, "fetch_scale": 262144.0 / 131083.5,
+        "write_kib": 116254.6, "write_scale": 1.0,
     },
 ]
 
