@@ -369,6 +369,10 @@ typedef struct cp_plan_opts {
   int32_t capacity;      /* nodes per tree (16384) */
   int32_t max_connect;   /* extension steps towards the other tree per round (64) */
   int32_t poll_every;    /* rounds between host checks of the done flag (1) */
+  int32_t flags;         /* CP_SELF_COLLISION: every extension also checks its waypoints
+                            against the robot itself (cp_robot_self_pairs), one
+                            configuration at a time by the wavefront; these rounds use
+                            the library's kernels even for a specialised robot (0) */
 } cp_plan_opts;
 
 /* Dense path: every waypoint of every edge, consecutive spacing < tau + tau_sm;

@@ -65,7 +65,8 @@ class ProjParams(C.Structure):
 
 class PlanOpts(C.Structure):
     _fields_ = [("proj", ProjParams), ("n_groups", C.c_int32), ("max_rounds", C.c_int32),
-                ("capacity", C.c_int32), ("max_connect", C.c_int32), ("poll_every", C.c_int32)]
+                ("capacity", C.c_int32), ("max_connect", C.c_int32), ("poll_every", C.c_int32),
+                ("flags", C.c_int32)]
 
 
 class Path(C.Structure):
@@ -368,12 +369,12 @@ def autotune(robot: Robot, env: Env, con: Constraint, params: ProjParams, q_from
 # ------------------------------------------------------------------ planning
 
 def plan_opts(n_groups=256, max_rounds=2000, capacity=16384, max_connect=64, poll_every=1,
-              **proj) -> PlanOpts:
+              flags=0, **proj) -> PlanOpts:
     o = PlanOpts()
     lib().cp_plan_opts_default(C.byref(o))
     o.proj = proj_params(**proj)
     o.n_groups, o.max_rounds, o.capacity = n_groups, max_rounds, capacity
-    o.max_connect, o.poll_every = max_connect, poll_every
+    o.max_connect, o.poll_every, o.flags = max_connect, poll_every, flags
     return o
 
 

@@ -61,6 +61,7 @@ hipError_t launch_rtc_pool(const RtcKernel* k, const cp_robot* robot, const ConD
                            unsigned long long* work, hipStream_t stream);
 hipError_t launch_rtc_plan_round(const RtcKernel* k, const cp_robot* robot, const EnvDev& env,
                                  const ConDev& con, const ProjDev& prm, const PlanDev& pd,
-                                 int sphere_batch, unsigned blocks, hipStream_t stream);
+                                 int sphere_batch, unsigned blocks, size_t lds,
+                                 hipStream_t stream);
 void rtc_release(cp_robot* robot);
 }  // namespace cprrtc

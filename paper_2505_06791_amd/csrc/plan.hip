@@ -37,14 +37,16 @@
 
 namespace cprrtc {
 
-template <int NDOF, int KIND, int B>
+// SELF: extensions also check their waypoints against the robot itself
+// (a separate instantiation, so that the plain kernels keep their registers).
+template <int NDOF, int KIND, int B, bool SELF>
 __global__ __launch_bounds__(kPlanBlock) void plan_round_kernel(const RobotDev* __restrict__ rob,
                                                                 const float4* __restrict__ sph,
                                                                 EnvDev env, ConDev con,
                                                                 ProjDev prm, PlanDev pd) {
   const int g = (int)((blockIdx.x * kPlanBlock + threadIdx.x) >> 6);
   if (g >= pd.n_groups) return;                  // wavefront-uniform
-  plan_extend<NDOF, KIND, B>(rob, sph, env, con, prm, pd, pd.sample_base, g);
+  plan_extend<NDOF, KIND, B, RobotMem, SELF>(rob, sph, env, con, prm, pd, pd.sample_base, g);
 }
 
 // Roots (start in tree 0, goal in tree 1) and counters of a fresh plan.
@@ -194,23 +196,29 @@ __global__ void gather_batch_kernel(const ProblemDev* __restrict__ probs, const 
 template <int NDOF, int KIND>
 static void launch_round_kind(int batch, unsigned nb, hipStream_t st, const RobotDev* rob,
                               const float4* sph, const EnvDev& env, const ConDev& con,
-                              const ProjDev& prm, const PlanDev& pd) {
-  if (batch == 4)
-    plan_round_kernel<NDOF, KIND, 4><<<nb, kPlanBlock, 0, st>>>(rob, sph, env, con, prm, pd);
-  else
-    plan_round_kernel<NDOF, KIND, 8><<<nb, kPlanBlock, 0, st>>>(rob, sph, env, con, prm, pd);
+                              const ProjDev& prm, const PlanDev& pd, size_t lds) {
+  if (lds > 0) {
+    if (batch == 4)
+      plan_round_kernel<NDOF, KIND, 4, true><<<nb, kPlanBlock, lds, st>>>(rob, sph, env, con, prm, pd);
+    else
+      plan_round_kernel<NDOF, KIND, 8, true><<<nb, kPlanBlock, lds, st>>>(rob, sph, env, con, prm, pd);
+  } else if (batch == 4) {
+    plan_round_kernel<NDOF, KIND, 4, false><<<nb, kPlanBlock, 0, st>>>(rob, sph, env, con, prm, pd);
+  } else {
+    plan_round_kernel<NDOF, KIND, 8, false><<<nb, kPlanBlock, 0, st>>>(rob, sph, env, con, prm, pd);
+  }
 }
 
 template <int NDOF>
 static bool launch_round_ndof(int kind, int batch, unsigned nb, hipStream_t st, const RobotDev* rob,
                               const float4* sph, const EnvDev& env, const ConDev& con,
-                              const ProjDev& prm, const PlanDev& pd) {
+                              const ProjDev& prm, const PlanDev& pd, size_t lds) {
   switch (kind) {
-    case KIND_NONE: launch_round_kind<NDOF, KIND_NONE>(batch, nb, st, rob, sph, env, con, prm, pd); return true;
-    case KIND_POSE: launch_round_kind<NDOF, KIND_POSE>(batch, nb, st, rob, sph, env, con, prm, pd); return true;
+    case KIND_NONE: launch_round_kind<NDOF, KIND_NONE>(batch, nb, st, rob, sph, env, con, prm, pd, lds); return true;
+    case KIND_POSE: launch_round_kind<NDOF, KIND_POSE>(batch, nb, st, rob, sph, env, con, prm, pd, lds); return true;
     case KIND_REL:
       if constexpr (NDOF % 2 == 0) {
-        launch_round_kind<NDOF, KIND_REL>(batch, nb, st, rob, sph, env, con, prm, pd);
+        launch_round_kind<NDOF, KIND_REL>(batch, nb, st, rob, sph, env, con, prm, pd, lds);
         return true;
       }
       return false;
@@ -220,14 +228,14 @@ static bool launch_round_ndof(int kind, int batch, unsigned nb, hipStream_t st, 
 
 static bool launch_round(int dof, int kind, int batch, unsigned nb, hipStream_t st,
                          const RobotDev* rob, const float4* sph, const EnvDev& env,
-                         const ConDev& con, const ProjDev& prm, const PlanDev& pd) {
+                         const ConDev& con, const ProjDev& prm, const PlanDev& pd, size_t lds) {
   switch (dof) {
-    case 2: return launch_round_ndof<2>(kind, batch, nb, st, rob, sph, env, con, prm, pd);
-    case 3: return launch_round_ndof<3>(kind, batch, nb, st, rob, sph, env, con, prm, pd);
-    case 6: return launch_round_ndof<6>(kind, batch, nb, st, rob, sph, env, con, prm, pd);
-    case 7: return launch_round_ndof<7>(kind, batch, nb, st, rob, sph, env, con, prm, pd);
-    case 9: return launch_round_ndof<9>(kind, batch, nb, st, rob, sph, env, con, prm, pd);
-    case 14: return launch_round_ndof<14>(kind, batch, nb, st, rob, sph, env, con, prm, pd);
+    case 2: return launch_round_ndof<2>(kind, batch, nb, st, rob, sph, env, con, prm, pd, lds);
+    case 3: return launch_round_ndof<3>(kind, batch, nb, st, rob, sph, env, con, prm, pd, lds);
+    case 6: return launch_round_ndof<6>(kind, batch, nb, st, rob, sph, env, con, prm, pd, lds);
+    case 7: return launch_round_ndof<7>(kind, batch, nb, st, rob, sph, env, con, prm, pd, lds);
+    case 9: return launch_round_ndof<9>(kind, batch, nb, st, rob, sph, env, con, prm, pd, lds);
+    case 14: return launch_round_ndof<14>(kind, batch, nb, st, rob, sph, env, con, prm, pd, lds);
     default: return false;
   }
 }
@@ -299,6 +307,7 @@ void cp_plan_opts_default(cp_plan_opts* o) {
   o->capacity = 16384;
   o->max_connect = 64;
   o->poll_every = 1;
+  o->flags = 0;
 }
 
 int cp_planner_create(const cp_robot* robot, const cp_plan_opts* opts, cp_planner** out) {
@@ -316,6 +325,9 @@ int cp_planner_create(const cp_robot* robot, const cp_plan_opts* opts, cp_planne
     if (o.capacity < 2 || o.capacity > (1 << 24)) return api_fail(CP_E_ARG, "capacity %d not in 2..2^24", o.capacity);
     if (o.max_rounds < 1 || o.max_connect < 0 || o.poll_every < 1)
       return api_fail(CP_E_ARG, "max_rounds, max_connect or poll_every out of range");
+    if (o.flags & ~CP_SELF_COLLISION) return api_fail(CP_E_ARG, "plan flags %d", o.flags);
+    if ((o.flags & CP_SELF_COLLISION) && plan_lds_bytes(robot->host.n_spheres) > 65536)
+      return api_fail(CP_E_UNSUPPORTED, "self-collision planning supports at most 1020 spheres");
     if (!dof_supported(robot->host.dof))
       return api_fail(CP_E_UNSUPPORTED, "planning kernels are built for dof 2, 3, 6, 7, 9, 14 (got %d)", robot->host.dof);
     cp_planner* pl = new (std::nothrow) cp_planner;
@@ -448,19 +460,28 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
     for (int j = 0; j < kMaxDof; ++j)
       pd.shift[j] = (float)((double)(splitmix64(state) >> 11) * (1.0 / 9007199254740992.0));
     const unsigned nb = (unsigned)((o.n_groups * 64 + kPlanBlock - 1) / kPlanBlock);
+    // self-collision in the extensions: the robot's pairs and the LDS for
+    // one configuration's sphere centres per wavefront
+    const int n_pairs = (int)robot->self_pairs.size() / 2;
+    if ((o.flags & CP_SELF_COLLISION) && n_pairs > 0) {
+      pd.self_pairs = robot->pairs;
+      pd.n_self = n_pairs;
+    }
+    const size_t lds = pd.n_self > 0 ? plan_lds_bytes(robot->host.n_spheres) : 0;
 
     int rounds = 0;
     bool done = false;
     // the round kernel compiled for this robot and mask (cp_robot_specialize), if any
     const RtcKernel* rk = rtc_find(const_cast<cp_robot*>(robot), con);
-    if (rk && !rk->plan_fn[0]) rk = nullptr;
+    if (rk && (!rk->plan_fn[0] || lds > 0)) rk = nullptr;   // compiled without the self-check
     while (rounds < o.max_rounds && !done) {
       pd.sample_base = (unsigned)rounds * (unsigned)o.n_groups;
       if (rk) {
-        he = launch_rtc_plan_round(rk, robot, env->view, con, prm, pd, pp.sphere_batch, nb, st);
+        he = launch_rtc_plan_round(rk, robot, env->view, con, prm, pd, pp.sphere_batch, nb, lds,
+                                   st);
         if (he != hipSuccess) return api_hip_fail(he, "cp_plan round (run-time compiled kernel)");
       } else if (!launch_round(n, con.kind, pp.sphere_batch, nb, st, robot->dev, robot->spheres,
-                               env->view, con, prm, pd)) {
+                               env->view, con, prm, pd, lds)) {
         return api_fail(CP_E_UNSUPPORTED, "no planning kernel for dof %d, constraint kind %d", n, con.kind);
       }
       publish_kernel<<<1, 1, 0, st>>>(pl->ctl, o.capacity);

@@ -27,7 +27,17 @@ struct PlanDev {
   float connect2;       // (tau + tau_sm)^2
   float shift[kMaxDof]; // Cranley-Patterson shift per dimension
   unsigned sample_base; // Halton index of the round's first sample
+  const int2* self_pairs; // self-collision pairs (positions in the sphere array)
+  int n_self;           // checked pairs (used by the round kernels built with SELF)
 };
+
+// Dynamic LDS of a round kernel when extensions check self-collision:
+// per wavefront, the sphere centres of one configuration (n_spheres float4)
+// and that configuration's joint values (4 float4).
+extern __shared__ float4 cp_plan_lds[];
+__host__ __device__ inline size_t plan_lds_bytes(int n_spheres) {
+  return sizeof(float4) * (size_t)(kPlanBlock / 64) * (size_t)(n_spheres + 4);
+}
 
 // control block layout (ints)
 enum { kCtlCount = 0, kCtlPublished = 2, kCtlDone = 4, kCtlConn = 5, kCtlOverflow = 8, kCtlInts = 16 };
@@ -99,12 +109,56 @@ __device__ __forceinline__ void steer(const float (&a)[NDOF], const float (&b)[N
   for (int j = 0; j < NDOF; ++j) out[j] = a[j] + s * (b[j] - a[j]);
 }
 
+// Self-collision of one configuration (joint values qq in LDS, read by
+// every lane) by the whole wavefront: the lanes place the sphere centres in
+// `cent`, then test the checked pairs 64 at a time (colliding iff
+// |c_s - c_t| - r_s - r_t <= 0).  Uniform result.
+template <class P>
+__device__ __forceinline__ bool self_collides(const RobotDev* __restrict__ rob,
+                                              const float4* __restrict__ sph, const float* qq,
+                                              const int2* __restrict__ pairs, int n_pairs,
+                                              float4* cent) {
+  const int lane = threadIdx.x & 63;
+  for (int c = 0; c < P::n_chains(rob); ++c) {
+    Frame T;
+    frame_from_p<P>(T, rob, c, false);
+    for (int j = P::chain_begin(rob, c); j < P::chain_begin(rob, c + 1); ++j) {
+      joint_advance<P>(T, rob, j, qq[j]);
+      for (int s = P::sph_begin(rob, j) + lane; s < P::sph_begin(rob, j + 1); s += 64) {
+        const float4 l = P::sphere(sph, s);
+        cent[s] = make_float4(T.r[0] * l.x + T.r[1] * l.y + T.r[2] * l.z + T.p[0],
+                              T.r[3] * l.x + T.r[4] * l.y + T.r[5] * l.z + T.p[1],
+                              T.r[6] * l.x + T.r[7] * l.y + T.r[8] * l.z + T.p[2], l.w);
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // centres of other lanes
+  __builtin_amdgcn_wave_barrier();
+  bool hit = false;
+  for (int base = 0; base < n_pairs && !hit; base += 64) {
+    const int p = base + lane;
+    bool h = false;
+    if (p < n_pairs) {
+      const int2 st = pairs[p];
+      const float4 a = cent[st.x], b = cent[st.y];
+      const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+      h = sqrtf(dx * dx + dy * dy + dz * dz) - a.w - b.w <= 0.0f;
+    }
+    hit = __ballot(h) != 0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");   // reads before the next writes
+  __builtin_amdgcn_wave_barrier();
+  return hit;
+}
+
 // One motion a -> b on this wavefront (lanes 0..W-1), projected and
-// validated.  q: this lane's projected waypoint; end: xi[W-1] broadcast.
-template <int NDOF, int KIND, int B, class P = RobotMem>
+// validated (with n_self > 0 also against the robot itself).  q: this
+// lane's projected waypoint; end: xi[W-1] broadcast.
+template <int NDOF, int KIND, int B, class P = RobotMem, bool SELF = false>
 __device__ __forceinline__ bool try_motion(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
                            const EnvDev& env, const ConDev& con, const ProjDev& prm,
-                           float* __restrict__ scratch, const float (&a)[NDOF],
+                           float* __restrict__ scratch, const int2* __restrict__ self_pairs,
+                           int n_self, const float (&a)[NDOF],
                            const float (&b)[NDOF], float (&q)[NDOF], float (&end)[NDOF]) {
   const int W = prm.W;
   const int lane = threadIdx.x & 63;
@@ -137,6 +191,22 @@ __device__ __forceinline__ bool try_motion(const RobotDev* __restrict__ rob, con
                                        msd, cw);
   const uint64_t all_hits = __ballot((hits & segmask) != 0 && in_motion);
   if (all_hits) return false;
+  if (SELF && n_self > 0) {
+    // waypoints 1..W-1 against the robot itself, one configuration at a
+    // time by the whole wavefront
+    float4* cent = cp_plan_lds + (size_t)(threadIdx.x >> 6) * (rob->n_spheres + 4);
+    float* qq = reinterpret_cast<float*>(cent + rob->n_spheres);
+    for (int kk = 1; kk < W; ++kk) {
+      if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NDOF; ++j)
+          qq[j] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, q[j]), kk));
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (self_collides<P>(rob, sph, qq, self_pairs, n_self, cent)) return false;
+    }
+  }
 #pragma unroll
   for (int j = 0; j < NDOF; ++j) end[j] = __shfl(q[j], W - 1, 64);
   return true;
@@ -179,7 +249,7 @@ __device__ __forceinline__ bool plan_done(const PlanDev& pd) {
 
 // One tree extension of one wavefront (group g of the round): sample, grow
 // the group's tree by one motion, then towards the other tree.
-template <int NDOF, int KIND, int B, class P = RobotMem>
+template <int NDOF, int KIND, int B, class P = RobotMem, bool SELF = false>
 __device__ __forceinline__ void plan_extend(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
                             const EnvDev& env, const ConDev& con, const ProjDev& prm,
                             const PlanDev& pd, unsigned sample_base, int g) {
@@ -205,7 +275,8 @@ __device__ __forceinline__ void plan_extend(const RobotDev* __restrict__ rob, co
   float qn[NDOF], qs[NDOF], q[NDOF], qe[NDOF];
   load_node<NDOF>(pd, X, near, qn);
   steer<NDOF>(qn, qr, pd.step, qs);
-  if (!try_motion<NDOF, KIND, B, P>(rob, sph, env, con, prm, scratch, qn, qs, q, qe)) return;
+  if (!try_motion<NDOF, KIND, B, P, SELF>(rob, sph, env, con, prm, scratch, pd.self_pairs, pd.n_self, qn,
+                                    qs, q, qe)) return;
   int cur = append_node<NDOF>(pd, W, X, near, q);
   if (cur < 0) return;
 
@@ -227,7 +298,8 @@ __device__ __forceinline__ void plan_extend(const RobotDev* __restrict__ rob, co
     if (__shfl(plan_done(pd) ? 1 : 0, 0, 64)) return;
     steer<NDOF>(qe, qt, pd.step, qs);
     float qe2[NDOF];
-    if (!try_motion<NDOF, KIND, B, P>(rob, sph, env, con, prm, scratch, qe, qs, q, qe2)) return;
+    if (!try_motion<NDOF, KIND, B, P, SELF>(rob, sph, env, con, prm, scratch, pd.self_pairs, pd.n_self, qe,
+                                      qs, q, qe2)) return;
     const float dnew = dist2<NDOF>(qe2, qt);
     if (!(dnew < dcur)) return;                  // no progress: stop extending
     cur = append_node<NDOF>(pd, W, X, cur, q);

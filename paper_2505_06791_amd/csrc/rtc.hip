@@ -189,7 +189,8 @@ hipError_t launch_rtc_validate(const RtcKernel* k, const cp_robot* robot, const 
 
 hipError_t launch_rtc_plan_round(const RtcKernel* k, const cp_robot* robot, const EnvDev& env,
                                  const ConDev& con, const ProjDev& prm, const PlanDev& pd,
-                                 int sphere_batch, unsigned blocks, hipStream_t stream) {
+                                 int sphere_batch, unsigned blocks, size_t lds,
+                                 hipStream_t stream) {
   const RobotDev* rob = robot->dev;
   const float4* sph = robot->spheres;
   EnvDev e = env;
@@ -198,7 +199,7 @@ hipError_t launch_rtc_plan_round(const RtcKernel* k, const cp_robot* robot, cons
   PlanDev d = pd;
   void* args[] = {&rob, &sph, &e, &c, &p, &d};
   return hipModuleLaunchKernel(k->plan_fn[sphere_batch == 8 ? 1 : 0], blocks, 1, 1, kPlanBlock, 1, 1,
-                               0, stream, args, nullptr);
+                               (unsigned)lds, stream, args, nullptr);
 }
 
 void rtc_release(cp_robot* robot) {
