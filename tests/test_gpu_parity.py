@@ -243,6 +243,20 @@ def test_pooled_and_per_motion_projection_agree(G, name, W, variant):
     _compare_pv(f"{name} pooled", ref, xi_p, st_p, it_p, w, W, w["tau_task"])
 
 
+@pytest.mark.parametrize("W", [64, 32])
+def test_pooled_ragged_batches(G, W):
+    """Batches of 1..9 motions (fewer motions than slots, a partial last
+    share) through the pooled kernel: bit for bit the per-motion results."""
+    w = I.workload("cluttered", 2290 + W)
+    q_from, q_to = motion_set(w, 9, 31, W=W)
+    kw = dict(W=W, tau_task=w["tau_task"])
+    for M in (1, 2, 3, 4, 5, 7, 9):
+        a = _run_pv(G, w, q_from[:M], q_to[:M], kw, flags=G.POOLED)
+        b = _run_pv(G, w, q_from[:M], q_to[:M], kw, flags=G.PER_MOTION)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), M
+
+
 @pytest.mark.parametrize("con,W", [("line", 64), ("line", 32), ("orientation", 64),
                                    ("orientation", 32)])
 def test_other_constraint_sets_match_oracle(G, con, W):
