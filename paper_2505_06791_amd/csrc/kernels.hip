@@ -298,8 +298,8 @@ hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& en
 // slots' motions once balance best (4 slots, one share of 4 motions per
 // wavefront: 1.44 ms, 0.76 ms compiled for the robot; shares of 8: 1.54 /
 // 0.83 ms; shares of 12: 1.76 / 0.88 ms; half the batch in shares of 8,
-// the rest in shares of 4: 1.41 / 0.80 ms; 3 slots: 1.48 / 0.76 ms; 6
-// slots: 1.67 / 1.05 ms; the
+// the rest in shares of 4: 1.41 / 0.80 ms; 3 slots: 1.48 / 0.76 ms; 5
+// slots: 1.53 / 0.96 ms; 6 slots: 1.67 / 1.05 ms; the
 // one-motion-per-wavefront kernel: 2.53 ms).  Fewer slots leave LDS for
 // more wavefronts per CU (4 x 64 x 7 floats: 22 workgroups), which hide
 // the latency of each wavefront's scalar bookkeeping.
