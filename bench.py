@@ -86,8 +86,8 @@ TRAFFIC = [
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h",
                     "paper_2505_06791_amd/csrc/kernels.hip", "paper_2505_06791_amd/csrc/kernels.h"),
-        "sources_sha256": "3493bc62a632345f433e44293604a9d85f241580bf4692528805f105be1a40d0",
-        "fetch_kib": 5290.0, "fetch_scale": 262144.0 / 131083.5,
+        "sources_sha256": "2ea1648bcc101e46854f13ebc9cefe203006125446cdd8a9f09472d07fc74c74",
+        "fetch_kib": 5289.9, "fetch_scale": 262144.0 / 131083.5,
         "write_kib": 115976.1, "write_scale": 1.0,
     },
     {
@@ -95,9 +95,9 @@ TRAFFIC = [
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h", "paper_2505_06791_amd/csrc/rtc.hip",
                     "paper_2505_06791_amd/csrc/kernels.h", "include/cprrtc.h"),
-        "sources_sha256": "eedc67b4043ee2d6e1aaf621d14e545df795ffd9bdc78cf8a870ca19fa70f280",
-        "fetch_kib": 5223.6, "fetch_scale": 262144.0 / 131083.5,
-        "write_kib": 116254.6, "write_scale": 1.0,
+        "sources_sha256": "f89b30d1fe6e359038918b522f68d4c7687c8254de3678d37d52d0747f91d7a3",
+        "fetch_kib": 5224.4, "fetch_scale": 262144.0 / 131083.5,
+        "write_kib": 116249.8, "write_scale": 1.0,
     },
 ]
 
