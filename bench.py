@@ -45,9 +45,9 @@ PAIR_FLOPS = dict(aabb=15, obb=30, sphere=11, capsule=25, cylinder=28)
 PAIR_ORDER = ("aabb", "obb", "sphere", "capsule", "cylinder")   # work counter slots 0..4
 SPHERE_CENTRE_FLOPS = 19          # R l + p, plus r^2
 FK_JOINT_FLOPS = 51               # one joint frame of the chain (sin/cos counted as 1 each)
-# one self-collision pair: centre difference (3), squared length (5), square
-# root (1), minus both radii (2)
-SELF_PAIR_FLOPS = 11
+# one self-collision pair, verdict form: centre difference (3), squared
+# length (5), sum of the radii (1) and its square (1)
+SELF_PAIR_FLOPS = 10
 CULL_FLOPS = 20                   # bounding sphere vs box: 3 x (2 sub, 2 max), |.|^2, reach^2, compare
 
 

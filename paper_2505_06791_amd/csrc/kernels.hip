@@ -144,7 +144,8 @@ __global__ __launch_bounds__(kBlock) void validate_kernel(
 // One wavefront per configuration: every lane runs the (uniform) forward
 // kinematics, lanes place the sphere centres into LDS (sphere s by lane
 // s mod 64), then lanes test the checked pairs 64 at a time:
-// sd = |c_s - c_t| - r_s - r_t, colliding iff sd <= 0.
+// sd = |c_s - c_t| - r_s - r_t, colliding iff sd <= 0 (for the verdict
+// alone, |c_s - c_t|^2 <= (r_s + r_t)^2).
 //   MOTION = false: item i is configuration i of q; collide[i] |= hit and,
 //                   with min_sd, min_sd[i] = min(min_sd[i], min pair sd)
 //                   (every pair evaluated).
@@ -202,9 +203,14 @@ __global__ __launch_bounds__(64 * kSelfWaves) void self_cc_kernel(
       const int2 st = pairs[p];
       const float4 a = c[st.x], b = c[st.y];
       const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
-      const float sd = sqrtf(dx * dx + dy * dy + dz * dz) - a.w - b.w;
-      msd = fminf(msd, sd);
-      hit = sd <= 0.0f;
+      const float d2 = dx * dx + dy * dy + dz * dz, reach = a.w + b.w;
+      if (all_pairs) {
+        const float sd = sqrtf(d2) - reach;
+        msd = fminf(msd, sd);
+        hit = sd <= 0.0f;
+      } else {
+        hit = d2 <= reach * reach;       // the verdict alone: no square root
+      }
     }
     if (__ballot(hit)) {
       hit_any = true;

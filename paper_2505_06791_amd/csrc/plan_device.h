@@ -141,8 +141,8 @@ __device__ __forceinline__ bool self_collides(const RobotDev* __restrict__ rob,
     if (p < n_pairs) {
       const int2 st = pairs[p];
       const float4 a = cent[st.x], b = cent[st.y];
-      const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
-      h = sqrtf(dx * dx + dy * dy + dz * dz) - a.w - b.w <= 0.0f;
+      const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z, reach = a.w + b.w;
+      h = dx * dx + dy * dy + dz * dz <= reach * reach;   // |c_s - c_t| <= r_s + r_t
     }
     hit = __ballot(h) != 0;
   }
