@@ -128,7 +128,8 @@ typedef struct cp_proj_params {
   double tau_task;    /* task tolerance on the infinity norm of the error (1e-3) */
   double alpha;       /* step factor (1.0) */
   double lambda;      /* damping of the least-squares step (1e-2) */
-  int32_t sphere_batch; /* spheres per collision batch between early-exit polls: 4 or 8 (8) */
+  int32_t sphere_batch; /* spheres per collision batch between early-exit polls: 4, 8 or 16
+                           (8); the planner's rounds take 8 for 16 */
   int32_t variant;    /* projection operator, CP_PROJECT_* (CP_PROJECT_PARALLEL) */
 } cp_proj_params;
 
@@ -327,7 +328,7 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
 
 /* Picks the launch shape for a workload by measurement: for every candidate
  * (W in {32, 64} if flags has CP_TUNE_W, else the W of *params; sphere batch
- * in {4, 8}) runs project_validate_motions once untimed and reps times timed
+ * in {4, 8, 16}) runs project_validate_motions once untimed and reps times timed
  * on the caller's sample motions (d_q_from, d_q_to: [n_motions][dof] device
  * floats, steered for the W of *params; for another W the end points are
  * moved along the same direction by (W' - 1) / (W - 1) so the initial
@@ -341,10 +342,10 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
 enum { CP_TUNE_W = 1 };
 typedef struct cp_tune_report {
   int32_t n;                   /* candidates timed */
-  int32_t W[4];
-  int32_t sphere_batch[4];
-  double ms[4];                /* mean time per call */
-  double waypoints_per_s[4];
+  int32_t W[8];
+  int32_t sphere_batch[8];
+  double ms[8];                /* mean time per call */
+  double waypoints_per_s[8];
 } cp_tune_report;
 int cp_autotune(const cp_robot* robot, const cp_env* env, const cp_constraint* constraint,
                 cp_proj_params* params, int32_t n_motions, const float* d_q_from,

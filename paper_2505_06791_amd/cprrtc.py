@@ -83,8 +83,8 @@ class ShortcutStats(C.Structure):
 
 
 class TuneReport(C.Structure):
-    _fields_ = [("n", C.c_int32), ("W", C.c_int32 * 4), ("sphere_batch", C.c_int32 * 4),
-                ("ms", C.c_double * 4), ("waypoints_per_s", C.c_double * 4)]
+    _fields_ = [("n", C.c_int32), ("W", C.c_int32 * 8), ("sphere_batch", C.c_int32 * 8),
+                ("ms", C.c_double * 8), ("waypoints_per_s", C.c_double * 8)]
 
 
 class BatchOpts(C.Structure):

@@ -438,8 +438,8 @@ int check_params(const cp_proj_params* params, cp_proj_params* p) {
   if (!(p->tau >= 0) || !(p->tau_sm >= 0) || !(p->tau_task >= 0) || !(p->lambda >= 0) ||
       !(p->alpha > 0))
     return fail(CP_E_ARG, "projection parameters out of range");
-  if (p->sphere_batch != 4 && p->sphere_batch != 8)
-    return fail(CP_E_UNSUPPORTED, "sphere_batch = %d (supported: 4, 8)", p->sphere_batch);
+  if (p->sphere_batch != 4 && p->sphere_batch != 8 && p->sphere_batch != 16)
+    return fail(CP_E_UNSUPPORTED, "sphere_batch = %d (supported: 4, 8, 16)", p->sphere_batch);
   if (p->variant < CP_PROJECT_PARALLEL || p->variant > CP_PROJECT_SEQUENTIAL)
     return fail(CP_E_ARG, "variant = %d (CP_PROJECT_*)", p->variant);
   return CP_OK;

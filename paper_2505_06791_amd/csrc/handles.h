@@ -19,7 +19,7 @@ struct RtcKernel {
   std::vector<hipModule_t> modules;  // every module this entry's kernels live in
   hipFunction_t fn = nullptr;       // pooled projection
   hipFunction_t plan_fn[2] = {nullptr, nullptr};   // planner round, sphere batch 4 / 8
-  hipFunction_t validate_fn[2] = {nullptr, nullptr};   // validation (culled), batch 4 / 8
+  hipFunction_t validate_fn[3] = {nullptr, nullptr, nullptr};   // validation (culled), batch 4 / 8 / 16
   double compile_ms = 0.0;
 };
 struct PlanDev;

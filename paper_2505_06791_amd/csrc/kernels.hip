@@ -410,11 +410,15 @@ hipError_t launch_validate(const RobotDev* rob, const float4* sph, const EnvDev&
   if (cull) {
     if (batch == 4)
       validate_kernel<4, true><<<nb, kBlock, 0, stream>>>(rob, sph, env, W, n_motions, xi, status, work, e);
+    else if (batch == 16)
+      validate_kernel<16, true><<<nb, kBlock, 0, stream>>>(rob, sph, env, W, n_motions, xi, status, work, e);
     else
       validate_kernel<8, true><<<nb, kBlock, 0, stream>>>(rob, sph, env, W, n_motions, xi, status, work, e);
   } else {
     if (batch == 4)
       validate_kernel<4, false><<<nb, kBlock, 0, stream>>>(rob, sph, env, W, n_motions, xi, status, work, e);
+    else if (batch == 16)
+      validate_kernel<16, false><<<nb, kBlock, 0, stream>>>(rob, sph, env, W, n_motions, xi, status, work, e);
     else
       validate_kernel<8, false><<<nb, kBlock, 0, stream>>>(rob, sph, env, W, n_motions, xi, status, work, e);
   }

@@ -116,7 +116,7 @@ std::string kernel_source(const RobotDev& h, int kind, unsigned mask, const floa
   s += "  project_pool_body<" + std::to_string(n) + ", " + std::to_string(kind) + ", 0, " +
        std::to_string(kPoolSlots) +
        ", RtcPolicy>(rob, con, prm, n_motions, q_from, q_to, nullptr, xi, status, iters, work);\n}\n";
-    for (int b : {4, 8})
+    for (int b : {4, 8, 16})
       s += "extern \"C\" __global__ __launch_bounds__(256) void cp_rtc_validate" + std::to_string(b) +
            "(const RobotDev* __restrict__ rob, const float4* __restrict__ sph, EnvDev env, int W,\n"
            "    int n_motions, const float* __restrict__ xi, int* __restrict__ status,\n"
@@ -183,7 +183,8 @@ hipError_t launch_rtc_validate(const RtcKernel* k, const cp_robot* robot, const 
   int early_i = early ? 1 : 0;
   void* args[] = {&rob, &sph, &e, &W, &n_motions, &xi, &status, &work, &early_i};
   const unsigned nb = (unsigned)(((int64_t)n_motions * W + 255) / 256);
-  return hipModuleLaunchKernel(k->validate_fn[batch == 4 ? 0 : 1], nb, 1, 1, 256, 1, 1, 0, stream,
+  return hipModuleLaunchKernel(k->validate_fn[batch == 4 ? 0 : batch == 8 ? 1 : 2], nb, 1, 1, 256,
+                               1, 1, 0, stream,
                                args, nullptr);
 }
 
@@ -198,7 +199,7 @@ hipError_t launch_rtc_plan_round(const RtcKernel* k, const cp_robot* robot, cons
   ProjDev p = prm;
   PlanDev d = pd;
   void* args[] = {&rob, &sph, &e, &c, &p, &d};
-  return hipModuleLaunchKernel(k->plan_fn[sphere_batch == 8 ? 1 : 0], blocks, 1, 1, kPlanBlock, 1, 1,
+  return hipModuleLaunchKernel(k->plan_fn[sphere_batch == 4 ? 0 : 1], blocks, 1, 1, kPlanBlock, 1, 1,
                                (unsigned)lds, stream, args, nullptr);
 }
 
@@ -278,11 +279,13 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
     hiprtcGetCode(prog, code.data());
     hiprtcDestroyProgram(&prog);
     hipModule_t module = nullptr;
-    hipFunction_t pool = nullptr, plan4 = nullptr, plan8 = nullptr, val4 = nullptr, val8 = nullptr;
+    hipFunction_t pool = nullptr, plan4 = nullptr, plan8 = nullptr, val4 = nullptr, val8 = nullptr,
+                  val16 = nullptr;
     he = hipModuleLoadData(&module, code.data());
     if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&pool, module, "cp_rtc_pool");
     if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&val4, module, "cp_rtc_validate4");
     if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&val8, module, "cp_rtc_validate8");
+    if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&val16, module, "cp_rtc_validate16");
     if (he == hipSuccess && need_plan) he = hipModuleGetFunction(&plan4, module, "cp_rtc_plan4");
     if (he == hipSuccess && need_plan) he = hipModuleGetFunction(&plan8, module, "cp_rtc_plan8");
     if (he != hipSuccess) {
@@ -309,6 +312,7 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
         e->fn = pool;
         e->validate_fn[0] = val4;
         e->validate_fn[1] = val8;
+        e->validate_fn[2] = val16;
       }
       if (plan4) {
         e->plan_fn[0] = plan4;

@@ -1,6 +1,6 @@
 // Launch-shape autotuner: times project_validate_motions on the caller's
-// sample motions for every candidate (W, sphere batch) and keeps the fastest
-// by validated-waypoint throughput.
+// sample motions for every candidate (W, sphere batch 4 / 8 / 16) and keeps
+// the fastest by validated-waypoint throughput.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -60,7 +60,7 @@ int cp_autotune(const cp_robot* robot, const cp_env* env, const cp_constraint* c
     }
 
     const int Ws[2] = {32, 64};
-    const int Bs[2] = {4, 8};
+    const int Bs[3] = {4, 8, 16};
     std::vector<int32_t> st_h(n_motions);
     cp_tune_report rep;
     std::memset(&rep, 0, sizeof rep);
@@ -78,7 +78,7 @@ int cp_autotune(const cp_robot* robot, const cp_env* env, const cp_constraint* c
         rc = api_hip_fail(e, "cp_autotune rescale");
         break;
       }
-      for (int bi = 0; bi < 2 && rc == CP_OK; ++bi) {
+      for (int bi = 0; bi < 3 && rc == CP_OK; ++bi) {
         cp_proj_params p = base;
         p.W = W;
         p.sphere_batch = Bs[bi];

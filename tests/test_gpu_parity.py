@@ -310,7 +310,9 @@ def test_early_exit_culling_and_batch_do_not_change_verdicts(G, name, W):
                 _run_pv(G, w, q_from, q_to, dict(kw, sphere_batch=8), flags=G.NO_CULL),
                 _run_pv(G, w, q_from, q_to, dict(kw, sphere_batch=8),
                         flags=G.NO_CULL | G.NO_EARLY_EXIT),
-                _run_pv(G, w, q_from, q_to, dict(kw, sphere_batch=4))]
+                _run_pv(G, w, q_from, q_to, dict(kw, sphere_batch=4)),
+                _run_pv(G, w, q_from, q_to, dict(kw, sphere_batch=16)),
+                _run_pv(G, w, q_from, q_to, dict(kw, sphere_batch=16), flags=G.NO_CULL)]
     for other in variants:
         assert np.array_equal(base[1], other[1])
         assert np.array_equal(base[2], other[2])

@@ -41,7 +41,7 @@ def test_autotune_picks_the_fastest_candidate(G, tune_W):
     qf, qt = torch.from_numpy(q_from).to(DEV), torch.from_numpy(q_to).to(DEV)
     chosen, cands = G.autotune(robot, env, con, base, qf, qt, tune_W=tune_W, reps=2)
     print(cands, "->", chosen.W, chosen.sphere_batch, flush=True)
-    assert len(cands) == (4 if tune_W else 2)
+    assert len(cands) == (6 if tune_W else 3)
     best = max(cands, key=lambda c: c["waypoints_per_s"])
     assert (chosen.W, chosen.sphere_batch) == (best["W"], best["sphere_batch"])
     assert all(c["ms"] > 0 for c in cands)
