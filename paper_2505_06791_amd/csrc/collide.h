@@ -190,45 +190,58 @@ __device__ __forceinline__ bool near_box(const float4 bs, const WaveBox& box) {
   return ex * ex + ey * ey + ez * ez <= reach * reach;
 }
 
-// Test the batch against the primitives of one type whose bounding spheres
-// come near `box`.  The active lanes share the bounding-sphere tests (ranked
-// among themselves: with W = 32 one motion of the wavefront may already have
-// left); set bits of the ballot are then walked in scalar registers.
-// Returns the candidate count.
-template <int B, int TYPE>
-__device__ __forceinline__ int test_culled_type(const EnvDev& env, const WaveBox& box,
+// Test the batch against the primitives whose bounding spheres come near
+// `box`, all types in one pass: the bounding spheres are stored in type
+// order (AABB, OBB, sphere, capsule, cylinder), so the active lanes share one
+// loop over all of them (ceil(n / lanes) rounds rather than one or more per
+// type; lanes are ranked among the active ones: with W = 32 one motion of the
+// wavefront may already have left), the set bits of the ballot are walked in
+// scalar registers, and each candidate goes to its type's pair test by its
+// index (a wavefront-uniform branch).  Adds the candidates per type to
+// count[].
+template <int B>
+__device__ __forceinline__ void test_culled_all(const EnvDev& env, const WaveBox& box,
                                                 const float (&cx)[B], const float (&cy)[B],
                                                 const float (&cz)[B], const float (&rad)[B],
-                                                uint64_t& hits) {
+                                                uint64_t& hits, int (&count)[5]) {
   const int lane = threadIdx.x & 63;
   const uint64_t act = __ballot(1);
   const int n_act = __popcll(act);
   const int rank = __popcll(act & ((1ull << lane) - 1ull));
-  int n, boff;
-  if (TYPE == 0) { n = env.n_aabb; boff = 0; }
-  else if (TYPE == 1) { n = env.n_obb; boff = env.n_aabb; }
-  else if (TYPE == 2) { n = env.n_sph; boff = env.n_aabb + env.n_obb; }
-  else if (TYPE == 3) { n = env.n_cap; boff = env.n_aabb + env.n_obb + env.n_sph; }
-  else { n = env.n_cyl; boff = env.n_aabb + env.n_obb + env.n_sph + env.n_cap; }
+  const int b1 = env.n_aabb, b2 = b1 + env.n_obb, b3 = b2 + env.n_sph, b4 = b3 + env.n_cap;
+  const int n = b4 + env.n_cyl;
   float msd_unused = 0.0f;
-  int count = 0;
   for (int base = 0; base < n; base += n_act) {
     const int i = base + rank;
-    const bool cand = (i < n) && near_box(env.bound[boff + min(i, n - 1)], box);
+    const bool cand = (i < n) && near_box(env.bound[min(i, n - 1)], box);
     uint64_t m = __ballot(cand);
-    count += __popcll(m);
     while (m) {
       const int l = __ffsll((unsigned long long)m) - 1;
       m &= m - 1;
       const int p = base + __popcll(act & ((1ull << l) - 1ull));
-      if (TYPE == 0) test_aabb<B, false>(env.aabb[2 * p], env.aabb[2 * p + 1], cx, cy, cz, rad, hits, msd_unused);
-      else if (TYPE == 1) test_obb<B, false>(env.obb[4 * p], env.obb[4 * p + 1], env.obb[4 * p + 2], env.obb[4 * p + 3], cx, cy, cz, rad, hits, msd_unused);
-      else if (TYPE == 2) test_sphere<B, false>(env.sph[p], cx, cy, cz, rad, hits, msd_unused);
-      else if (TYPE == 3) test_capsule<B, false>(env.cap[2 * p], env.cap[2 * p + 1], cx, cy, cz, rad, hits, msd_unused);
-      else test_cylinder<B, false>(env.cyl[2 * p], env.cyl[2 * p + 1], cx, cy, cz, rad, hits, msd_unused);
+      if (p < b1) {
+        ++count[0];
+        test_aabb<B, false>(env.aabb[2 * p], env.aabb[2 * p + 1], cx, cy, cz, rad, hits, msd_unused);
+      } else if (p < b2) {
+        const int q = p - b1;
+        ++count[1];
+        test_obb<B, false>(env.obb[4 * q], env.obb[4 * q + 1], env.obb[4 * q + 2], env.obb[4 * q + 3],
+                           cx, cy, cz, rad, hits, msd_unused);
+      } else if (p < b3) {
+        ++count[2];
+        test_sphere<B, false>(env.sph[p - b2], cx, cy, cz, rad, hits, msd_unused);
+      } else if (p < b4) {
+        const int q = p - b3;
+        ++count[3];
+        test_capsule<B, false>(env.cap[2 * q], env.cap[2 * q + 1], cx, cy, cz, rad, hits, msd_unused);
+      } else {
+        const int q = p - b4;
+        ++count[4];
+        test_cylinder<B, false>(env.cyl[2 * q], env.cyl[2 * q + 1], cx, cy, cz, rad, hits,
+                                msd_unused);
+      }
     }
   }
-  return count;
 }
 
 // ------------------------------------------------------------------ one configuration per lane
@@ -287,14 +300,11 @@ __device__ void collide_config(const RobotDev* __restrict__ rob, const float4* _
         work.centres += (unsigned long long)nb * n_on;
         if (CULL) {
           const WaveBox box = wave_box<B>(cx, cy, cz, rr, lane_on);
-          const int k0 = test_culled_type<B, 0>(env, box, cx, cy, cz, rr, hits);
-          const int k1 = test_culled_type<B, 1>(env, box, cx, cy, cz, rr, hits);
-          const int k2 = test_culled_type<B, 2>(env, box, cx, cy, cz, rr, hits);
-          const int k3 = test_culled_type<B, 3>(env, box, cx, cy, cz, rr, hits);
-          const int k4 = test_culled_type<B, 4>(env, box, cx, cy, cz, rr, hits);
+          int k[5] = {0, 0, 0, 0, 0};
+          test_culled_all<B>(env, box, cx, cy, cz, rr, hits, k);
           const unsigned long long f = (unsigned long long)nb * n_on;
-          work.pairs[0] += k0 * f; work.pairs[1] += k1 * f; work.pairs[2] += k2 * f;
-          work.pairs[3] += k3 * f; work.pairs[4] += k4 * f;
+#pragma unroll
+          for (int t = 0; t < 5; ++t) work.pairs[t] += k[t] * f;
           work.culls += n_prims;
         } else {
           test_all<B, SD>(env, cx, cy, cz, rr, hits, msd);
