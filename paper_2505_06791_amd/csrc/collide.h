@@ -146,15 +146,32 @@ __device__ __forceinline__ void test_all(const EnvDev& env, const float (&cx)[B]
 
 // ------------------------------------------------------------------ culled primitives
 
+// Wavefront reductions (every lane of the wavefront active; every lane gets
+// the result).  Within each row of 16 lanes the partners come through DPP
+// lane swizzles, which feed the min/max directly instead of going through
+// the LDS crossbar: quad_perm [1,0,3,2] and [2,3,0,1] (partners 1 and 2
+// apart), row_half_mirror (lane i of 8 with 7 - i) and row_mirror (lane i
+// of 16 with 15 - i); then the four rows combine by shuffles 16 and 32 apart.
+template <int CTRL>
+__device__ __forceinline__ float dpp_partner(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fminf(v, dpp_partner<0xB1>(v));
+  v = fminf(v, dpp_partner<0x4E>(v));
+  v = fminf(v, dpp_partner<0x141>(v));
+  v = fminf(v, dpp_partner<0x140>(v));
+  v = fminf(v, __shfl_xor(v, 16, 64));
+  return fminf(v, __shfl_xor(v, 32, 64));
 }
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmaxf(v, dpp_partner<0xB1>(v));
+  v = fmaxf(v, dpp_partner<0x4E>(v));
+  v = fmaxf(v, dpp_partner<0x141>(v));
+  v = fmaxf(v, dpp_partner<0x140>(v));
+  v = fmaxf(v, __shfl_xor(v, 16, 64));
+  return fmaxf(v, __shfl_xor(v, 32, 64));
 }
 
 // Box of the batch's spheres over the counting lanes of the wave.
