@@ -470,8 +470,8 @@ int do_project(const cp_robot* robot, const cp_constraint* constraint, const cp_
   // the kernel compiled for this robot and mask (cp_robot_specialize), when
   // the pooled form is the one to run
   if (!(flags & CP_GENERIC) && p.variant != CP_PROJECT_SEQUENTIAL && use_pool(n_motions, pooled)) {
-    const RtcKernel* rk = rtc_find(const_cast<cp_robot*>(robot), con);
-    if (rk && rk->fn) {
+    RtcFns rk;
+    if (rtc_find(const_cast<cp_robot*>(robot), con, &rk) && rk.pool) {
       hipError_t e = launch_rtc_pool(rk, robot, con, prm, n_motions, d_q_from, d_q_to, d_xi,
                                      d_status, d_iters, (unsigned long long*)d_work,
                                      (hipStream_t)stream);
@@ -495,9 +495,8 @@ int do_validate(const cp_robot* robot, const cp_env* env, const cp_proj_params& 
   if (!d_xi || !d_status) return fail(CP_E_ARG, "NULL buffer");
   // the kernels compiled for this robot (cp_robot_specialize), for the
   // culled form
-  const RtcKernel* rk = nullptr;
-  if (!(flags & (CP_GENERIC | CP_NO_CULL))) rk = rtc_find_validate(const_cast<cp_robot*>(robot));
-  if (rk) {
+  RtcFns rk;
+  if (!(flags & (CP_GENERIC | CP_NO_CULL)) && rtc_find_validate(const_cast<cp_robot*>(robot), &rk)) {
     hipError_t e = launch_rtc_validate(rk, robot, env->view, p.W, n_motions, d_xi, d_status,
                                        (unsigned long long*)d_work, !(flags & CP_NO_EARLY_EXIT),
                                        p.sphere_batch, (hipStream_t)stream);

@@ -11,15 +11,18 @@
 #include "device.h"
 
 namespace cprrtc {
-// A pooled projection kernel compiled at run time for one robot, constraint
-// kind and set of locked axes.
+// Kernels compiled at run time for one robot, constraint kind and set of
+// locked axes (null where not compiled).
+struct RtcFns {
+  hipFunction_t pool = nullptr;                          // pooled projection
+  hipFunction_t plan[2] = {nullptr, nullptr};            // planner round, sphere batch 4 / 8
+  hipFunction_t validate[3] = {nullptr, nullptr, nullptr};  // culled validation, 4 / 8 / 16
+};
 struct RtcKernel {
   int kind = 0;
-  unsigned mask = 0;                // bit i = axis i locked
+  unsigned mask = 0;                 // bit i = axis i locked
   std::vector<hipModule_t> modules;  // every module this entry's kernels live in
-  hipFunction_t fn = nullptr;       // pooled projection
-  hipFunction_t plan_fn[2] = {nullptr, nullptr};   // planner round, sphere batch 4 / 8
-  hipFunction_t validate_fn[3] = {nullptr, nullptr, nullptr};   // validation (culled), batch 4 / 8 / 16
+  RtcFns fns;
   double compile_ms = 0.0;
 };
 struct PlanDev;
@@ -48,18 +51,20 @@ int api_constraint(const cp_constraint* c, const cp_robot* robot, ConDev* out);
 int api_params(const cp_proj_params* params, cp_proj_params* p);
 // The run-time compiled pooled kernel for this robot and constraint, if one
 // was made (nullptr otherwise).
-const RtcKernel* rtc_find(cp_robot* robot, const ConDev& con);
-// Any entry of the robot with validation kernels (they depend on the robot only).
-const RtcKernel* rtc_find_validate(cp_robot* robot);
-hipError_t launch_rtc_validate(const RtcKernel* k, const cp_robot* robot, const EnvDev& env, int W,
+// Copies (under the robot's lock) the kernels compiled for the constraint's
+// kind and mask; false if there are none.
+bool rtc_find(cp_robot* robot, const ConDev& con, RtcFns* out);
+// The validation kernels of any entry of the robot (they depend on the robot only).
+bool rtc_find_validate(cp_robot* robot, RtcFns* out);
+hipError_t launch_rtc_validate(const RtcFns& k, const cp_robot* robot, const EnvDev& env, int W,
                                int n_motions, const float* xi, int* status,
                                unsigned long long* work, bool early, int batch,
                                hipStream_t stream);
-hipError_t launch_rtc_pool(const RtcKernel* k, const cp_robot* robot, const ConDev& con,
+hipError_t launch_rtc_pool(const RtcFns& k, const cp_robot* robot, const ConDev& con,
                            const ProjDev& prm, int n_motions, const float* q_from,
                            const float* q_to, float* xi, int* status, int* iters,
                            unsigned long long* work, hipStream_t stream);
-hipError_t launch_rtc_plan_round(const RtcKernel* k, const cp_robot* robot, const EnvDev& env,
+hipError_t launch_rtc_plan_round(const RtcFns& k, const cp_robot* robot, const EnvDev& env,
                                  const ConDev& con, const ProjDev& prm, const PlanDev& pd,
                                  int sphere_batch, unsigned blocks, size_t lds,
                                  hipStream_t stream);

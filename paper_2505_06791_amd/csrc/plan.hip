@@ -472,11 +472,12 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
     int rounds = 0;
     bool done = false;
     // the round kernel compiled for this robot and mask (cp_robot_specialize), if any
-    const RtcKernel* rk = rtc_find(const_cast<cp_robot*>(robot), con);
-    if (rk && (!rk->plan_fn[0] || lds > 0)) rk = nullptr;   // compiled without the self-check
+    RtcFns rk;
+    const bool use_rtc = rtc_find(const_cast<cp_robot*>(robot), con, &rk) && rk.plan[0] &&
+                         lds == 0;   // (compiled without the self-check)
     while (rounds < o.max_rounds && !done) {
       pd.sample_base = (unsigned)rounds * (unsigned)o.n_groups;
-      if (rk) {
+      if (use_rtc) {
         he = launch_rtc_plan_round(rk, robot, env->view, con, prm, pd, pp.sphere_batch, nb, lds,
                                    st);
         if (he != hipSuccess) return api_hip_fail(he, "cp_plan round (run-time compiled kernel)");

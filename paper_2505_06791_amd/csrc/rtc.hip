@@ -146,15 +146,18 @@ unsigned mask_bits(const ConDev& con) {
 
 }  // namespace
 
-const RtcKernel* rtc_find(cp_robot* robot, const ConDev& con) {
+bool rtc_find(cp_robot* robot, const ConDev& con, RtcFns* out) {
   std::lock_guard<std::mutex> g(robot->rtc_lock);
   const unsigned m = mask_bits(con);
   for (const RtcKernel& k : robot->rtc)
-    if (k.kind == con.kind && k.mask == m) return &k;
-  return nullptr;
+    if (k.kind == con.kind && k.mask == m) {
+      *out = k.fns;
+      return true;
+    }
+  return false;
 }
 
-hipError_t launch_rtc_pool(const RtcKernel* k, const cp_robot* robot, const ConDev& con,
+hipError_t launch_rtc_pool(const RtcFns& k, const cp_robot* robot, const ConDev& con,
                            const ProjDev& prm, int n_motions, const float* q_from,
                            const float* q_to, float* xi, int* status, int* iters,
                            unsigned long long* work, hipStream_t stream) {
@@ -162,18 +165,21 @@ hipError_t launch_rtc_pool(const RtcKernel* k, const cp_robot* robot, const ConD
   ConDev c = con;
   ProjDev p = prm;
   void* args[] = {&rob, &c, &p, &n_motions, &q_from, &q_to, &xi, &status, &iters, &work};
-  return hipModuleLaunchKernel(k->fn, pool_blocks(n_motions), 1, 1, 64, 1, 1, 0, stream, args,
+  return hipModuleLaunchKernel(k.pool, pool_blocks(n_motions), 1, 1, 64, 1, 1, 0, stream, args,
                                nullptr);
 }
 
-const RtcKernel* rtc_find_validate(cp_robot* robot) {
+bool rtc_find_validate(cp_robot* robot, RtcFns* out) {
   std::lock_guard<std::mutex> g(robot->rtc_lock);
   for (const RtcKernel& k : robot->rtc)
-    if (k.validate_fn[0]) return &k;
-  return nullptr;
+    if (k.fns.validate[0]) {
+      *out = k.fns;
+      return true;
+    }
+  return false;
 }
 
-hipError_t launch_rtc_validate(const RtcKernel* k, const cp_robot* robot, const EnvDev& env, int W,
+hipError_t launch_rtc_validate(const RtcFns& k, const cp_robot* robot, const EnvDev& env, int W,
                                int n_motions, const float* xi, int* status,
                                unsigned long long* work, bool early, int batch,
                                hipStream_t stream) {
@@ -183,12 +189,12 @@ hipError_t launch_rtc_validate(const RtcKernel* k, const cp_robot* robot, const 
   int early_i = early ? 1 : 0;
   void* args[] = {&rob, &sph, &e, &W, &n_motions, &xi, &status, &work, &early_i};
   const unsigned nb = (unsigned)(((int64_t)n_motions * W + 255) / 256);
-  return hipModuleLaunchKernel(k->validate_fn[batch == 4 ? 0 : batch == 8 ? 1 : 2], nb, 1, 1, 256,
+  return hipModuleLaunchKernel(k.validate[batch == 4 ? 0 : batch == 8 ? 1 : 2], nb, 1, 1, 256,
                                1, 1, 0, stream,
                                args, nullptr);
 }
 
-hipError_t launch_rtc_plan_round(const RtcKernel* k, const cp_robot* robot, const EnvDev& env,
+hipError_t launch_rtc_plan_round(const RtcFns& k, const cp_robot* robot, const EnvDev& env,
                                  const ConDev& con, const ProjDev& prm, const PlanDev& pd,
                                  int sphere_batch, unsigned blocks, size_t lds,
                                  hipStream_t stream) {
@@ -199,7 +205,7 @@ hipError_t launch_rtc_plan_round(const RtcKernel* k, const cp_robot* robot, cons
   ProjDev p = prm;
   PlanDev d = pd;
   void* args[] = {&rob, &sph, &e, &c, &p, &d};
-  return hipModuleLaunchKernel(k->plan_fn[sphere_batch == 4 ? 0 : 1], blocks, 1, 1, kPlanBlock, 1, 1,
+  return hipModuleLaunchKernel(k.plan[sphere_batch == 4 ? 0 : 1], blocks, 1, 1, kPlanBlock, 1, 1,
                                (unsigned)lds, stream, args, nullptr);
 }
 
@@ -230,9 +236,10 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
     if (what == 0) what = CP_SPECIALIZE_PROJECT;
     if (what & ~(CP_SPECIALIZE_PROJECT | CP_SPECIALIZE_PLAN))
       return api_fail(CP_E_ARG, "cp_robot_specialize: what = %d", what);
-    const RtcKernel* have = rtc_find(robot, con);
-    const bool need_pool = (what & CP_SPECIALIZE_PROJECT) && !(have && have->fn);
-    const bool need_plan = (what & CP_SPECIALIZE_PLAN) && !(have && have->plan_fn[0]);
+    RtcFns have;
+    rtc_find(robot, con, &have);
+    const bool need_pool = (what & CP_SPECIALIZE_PROJECT) && !have.pool;
+    const bool need_plan = (what & CP_SPECIALIZE_PLAN) && !have.plan[0];
     if (!need_pool && !need_plan) {
       if (compile_ms) *compile_ms = 0.0;
       return CP_OK;
@@ -309,14 +316,14 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
       }
       e->modules.push_back(module);
       if (pool) {
-        e->fn = pool;
-        e->validate_fn[0] = val4;
-        e->validate_fn[1] = val8;
-        e->validate_fn[2] = val16;
+        e->fns.pool = pool;
+        e->fns.validate[0] = val4;
+        e->fns.validate[1] = val8;
+        e->fns.validate[2] = val16;
       }
       if (plan4) {
-        e->plan_fn[0] = plan4;
-        e->plan_fn[1] = plan8;
+        e->fns.plan[0] = plan4;
+        e->fns.plan[1] = plan8;
       }
       e->compile_ms += ms;
     }
