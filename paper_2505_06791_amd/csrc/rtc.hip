@@ -69,7 +69,7 @@ std::string kernel_source(const RobotDev& h, int kind, unsigned mask, const floa
   for (int j = 0; j < n; ++j) s += std::string(j ? ", " : "") + (h.prismatic[j] ? "true" : "false");
   s += "};\n    return v[j];\n  }\n";
   // a revolute joint whose limits (plus offset) stay within +-3.2 rad takes
-  // the half-angle sine and cosine
+  // the hardware sine and cosine
   s += "  static __device__ __forceinline__ bool short_angle(const RobotDev*, int j) {\n"
        "    constexpr bool v[" + std::to_string(n) + "] = {";
   for (int j = 0; j < n; ++j) {
