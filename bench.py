@@ -86,18 +86,18 @@ TRAFFIC = [
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h",
                     "paper_2505_06791_amd/csrc/kernels.hip", "paper_2505_06791_amd/csrc/kernels.h"),
-        "sources_sha256": "2ea1648bcc101e46854f13ebc9cefe203006125446cdd8a9f09472d07fc74c74",
-        "fetch_kib": 5289.9, "fetch_scale": 262144.0 / 131083.5,
-        "write_kib": 115976.1, "write_scale": 1.0,
+        "sources_sha256": "a97de158e63ca77983691b4fc8eb1ce4b7678d513b18547b122ae50f239449d4",
+        "fetch_kib": 5290.2, "fetch_scale": 262144.0 / 131083.5,
+        "write_kib": 115977.0, "write_scale": 1.0,
     },
     {
         "kernel": "cp_rtc_pool<7, 1> (hipRTC)",
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h", "paper_2505_06791_amd/csrc/rtc.hip",
                     "paper_2505_06791_amd/csrc/kernels.h", "include/cprrtc.h"),
-        "sources_sha256": "f89b30d1fe6e359038918b522f68d4c7687c8254de3678d37d52d0747f91d7a3",
-        "fetch_kib": 5224.4, "fetch_scale": 262144.0 / 131083.5,
-        "write_kib": 116249.8, "write_scale": 1.0,
+        "sources_sha256": "76b9f33805e9ab7dedc5efbefc98a34630272c7d66a84002ba75f290403bf21f",
+        "fetch_kib": 5215.7, "fetch_scale": 262144.0 / 131083.5,
+        "write_kib": 116180.4, "write_scale": 1.0,
     },
 ]
 
