@@ -86,7 +86,7 @@ TRAFFIC = [
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h",
                     "paper_2505_06791_amd/csrc/kernels.hip", "paper_2505_06791_amd/csrc/kernels.h"),
-        "sources_sha256": "a97de158e63ca77983691b4fc8eb1ce4b7678d513b18547b122ae50f239449d4",
+        "sources_sha256": "41a64d35b209a7dd9e7dbbd9f59255d5d9a844008577175baa02af257ffd2a00",
         "fetch_kib": 5290.2, "fetch_scale": 262144.0 / 131083.5,
         "write_kib": 115977.0, "write_scale": 1.0,
     },
@@ -95,9 +95,9 @@ TRAFFIC = [
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h", "paper_2505_06791_amd/csrc/rtc.hip",
                     "paper_2505_06791_amd/csrc/kernels.h", "include/cprrtc.h"),
-        "sources_sha256": "76b9f33805e9ab7dedc5efbefc98a34630272c7d66a84002ba75f290403bf21f",
-        "fetch_kib": 5215.7, "fetch_scale": 262144.0 / 131083.5,
-        "write_kib": 116180.4, "write_scale": 1.0,
+        "sources_sha256": "d39cf5b8f263bec4f8a6a842c21c4921206f791946cd4ffb07fb1f5d3519f314",
+        "fetch_kib": 5215.2, "fetch_scale": 262144.0 / 131083.5,
+        "write_kib": 116175.3, "write_scale": 1.0,
     },
 ]
 

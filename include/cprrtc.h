@@ -309,10 +309,11 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
  * first, and every later culled validation of this robot's motions
  * (validate_motions, project_validate_motions; the validation kernels
  * depend on the robot only) the second, unless flags hold CP_GENERIC;
- * revolute joints whose limits stay within +-3.2 rad take a short sine and
- * cosine valid there (waypoints are expected within the joint limits);
- * CP_SPECIALIZE_PLAN -- the planner's round kernels: later
- * cp_plan calls of planners of this robot with such a constraint use them.
+ * CP_SPECIALIZE_PLAN -- the planner's round kernels: later cp_plan calls of
+ * planners of this robot with such a constraint use them.  In these kernels
+ * revolute joints whose limits (plus theta) stay within +-3.2 rad take the
+ * hardware sine and cosine, accurate there (waypoints are expected within
+ * the joint limits).
  * The constraint's other values (frame, targets) stay arguments.  Rotation
  * entries within 1e-6 of 0 or +-1 are taken as those values.  Kernels
  * already compiled for the key are not compiled again.  compile_ms:

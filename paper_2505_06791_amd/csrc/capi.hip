@@ -217,6 +217,8 @@ int cp_robot_create(const cp_robot_desc* d, cp_robot** out) {
       h.lo[j] = (float)d->q_lo[j];
       h.hi[j] = (float)d->q_hi[j];
       h.prismatic[j] = d->joint_type[j] == CP_PRISMATIC;
+      h.short_angle[j] = !h.prismatic[j] && std::fabs(h.lo[j] + h.th0[j]) <= 3.2f &&
+                         std::fabs(h.hi[j] + h.th0[j]) <= 3.2f;
     }
     h.chain_begin[0] = 0;
     for (int c = 0; c < d->n_chains; ++c) {

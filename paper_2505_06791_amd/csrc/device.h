@@ -36,6 +36,8 @@ struct RobotDev {
   float lo[kMaxDof];
   float hi[kMaxDof];
   int prismatic[kMaxDof];
+  int short_angle[kMaxDof];          // revolute, angle (limits plus offset) within +-3.2 rad
+                                     // (read by the kernels compiled for the robot)
   int sph_begin[kMaxDof + 1];        // spheres riding in joint frame j: [sph_begin[j], sph_begin[j+1])
 };
 
@@ -161,7 +163,8 @@ struct RobotMem {
   static __device__ __forceinline__ float hi(const RobotDev* r, int j) { return r->hi[j]; }
   static __device__ __forceinline__ bool prismatic(const RobotDev* r, int j) { return r->prismatic[j] != 0; }
   // joint angle bounded by +-3.2 (sincos_hw applies); the library kernels
-  // take the general routine for every joint
+  // take the general routine for every joint, so that all of them (pooled
+  // and one motion per wavefront alike) compute the same bits
   static __device__ __forceinline__ bool short_angle(const RobotDev*, int) { return false; }
   // first joint of chain 1 (ndof for a single chain)
   static __device__ __forceinline__ int chain1(const RobotDev* r, int ndof) {

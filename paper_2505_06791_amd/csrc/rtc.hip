@@ -72,11 +72,7 @@ std::string kernel_source(const RobotDev& h, int kind, unsigned mask, const floa
   // the hardware sine and cosine
   s += "  static __device__ __forceinline__ bool short_angle(const RobotDev*, int j) {\n"
        "    constexpr bool v[" + std::to_string(n) + "] = {";
-  for (int j = 0; j < n; ++j) {
-    const bool sh = !h.prismatic[j] && std::fabs(h.lo[j] + h.th0[j]) <= 3.2f &&
-                    std::fabs(h.hi[j] + h.th0[j]) <= 3.2f;
-    s += std::string(j ? ", " : "") + (sh ? "true" : "false");
-  }
+  for (int j = 0; j < n; ++j) s += std::string(j ? ", " : "") + (h.short_angle[j] ? "true" : "false");
   s += "};\n    return v[j];\n  }\n";
   const int b1 = h.n_chains > 1 ? h.chain_begin[1] : n;
   s += "  static __device__ __forceinline__ int chain1(const RobotDev*, int) { return " +
