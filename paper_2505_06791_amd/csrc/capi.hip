@@ -349,10 +349,15 @@ int cp_env_create(const cp_env_desc* d, cp_env** out) {
     }
     for (int i = 0; i < d->n_obb; ++i) {
       const double* p = d->obb + 15 * i;
-      buf[off[1] + 4 * i] = make_float4((float)p[0], (float)p[1], (float)p[2], 0.f);
-      for (int c = 0; c < 3; ++c)  // box axis c = column c of R
+      // box axis c = column c of R; slot 0 holds the centre's coordinate
+      // along each axis, so the device projects a point with one dot product
+      double oc[3];
+      for (int c = 0; c < 3; ++c) {
+        oc[c] = p[3 + c] * p[0] + p[6 + c] * p[1] + p[9 + c] * p[2];
         buf[off[1] + 4 * i + 1 + c] = make_float4((float)p[3 + c], (float)p[6 + c], (float)p[9 + c],
                                                   (float)p[12 + c]);
+      }
+      buf[off[1] + 4 * i] = make_float4((float)oc[0], (float)oc[1], (float)oc[2], 0.f);
       bound(p[0], p[1], p[2], std::sqrt(p[12] * p[12] + p[13] * p[13] + p[14] * p[14]));
     }
     for (int i = 0; i < d->n_sphere; ++i) {

@@ -22,6 +22,18 @@
 //
 // A pair collides iff dist(centre, solid) <= r; the verdict form compares
 // squared distances, the exact form computes dist - r and keeps its minimum.
+//
+// Instruction count is what bounds these loops (one scalar fetch feeds B
+// spheres, so every saved vector instruction per pair shows), hence:
+//  * an OBB is stored as its three axes with the centre's coordinate along
+//    each (u.c) and its half extents, so the coordinate of a sphere centre
+//    along an axis is one three-term dot product with u.c folded in;
+//  * the square root is the hardware one (about 1 ulp, against the 1e-5 m
+//    band the verdicts are held to);
+//  * in the verdict form, when every sphere of the batch has r < 1 m, the
+//    positive part max(x, 0) of a distance component becomes a clamp to
+//    [0, 1] (an output modifier of the subtraction that forms it): a
+//    component above 1 m gives d2 >= 1 > r^2 clamped or not.
 #pragma once
 #ifndef __HIPCC_RTC__
 #include <float.h>
@@ -38,36 +50,55 @@ constexpr float kCullMargin = 1e-4f;   // metres; far above float32 rounding of 
 
 // ------------------------------------------------------------------ single-primitive tests
 // B sphere centres (per lane) against one primitive (uniform).  Verdict form
-// ORs ballots into hits; exact form lowers msd.
+// ORs ballots into hits; exact form lowers msd.  CLAMP (verdict form only):
+// every radius of the batch is below 1 m.
 
-template <int B, bool SD>
+__device__ __forceinline__ float hw_sqrt(float x) {
+#if __has_builtin(__builtin_amdgcn_sqrtf)
+  return __builtin_amdgcn_sqrtf(x);
+#else
+  return sqrtf(x);
+#endif
+}
+
+// Positive part of a distance component: max(x, 0), or clamp to [0, 1].
+template <bool CLAMP>
+__device__ __forceinline__ float pos_part(float x) {
+  return CLAMP ? __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f) : fmaxf(x, 0.0f);
+}
+
+template <int B, bool SD, bool CLAMP = false>
 __device__ __forceinline__ void test_aabb(const float4 c, const float4 h, const float (&cx)[B],
                                           const float (&cy)[B], const float (&cz)[B],
                                           const float (&rad)[B], uint64_t& hits, float& msd) {
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    const float ex = fmaxf(fabsf(cx[b] - c.x) - h.x, 0.0f);
-    const float ey = fmaxf(fabsf(cy[b] - c.y) - h.y, 0.0f);
-    const float ez = fmaxf(fabsf(cz[b] - c.z) - h.z, 0.0f);
+    const float ex = pos_part<CLAMP>(fabsf(cx[b] - c.x) - h.x);
+    const float ey = pos_part<CLAMP>(fabsf(cy[b] - c.y) - h.y);
+    const float ez = pos_part<CLAMP>(fabsf(cz[b] - c.z) - h.z);
     const float d2 = ex * ex + ey * ey + ez * ez;
-    if (SD) msd = fminf(msd, sqrtf(d2) - rad[b]);
+    if (SD) msd = fminf(msd, hw_sqrt(d2) - rad[b]);
     else hits |= __ballot(d2 <= rad[b] * rad[b]);
   }
 }
 
-template <int B, bool SD>
-__device__ __forceinline__ void test_obb(const float4 c, const float4 u, const float4 v,
+// o = (u.c, v.c, w.c): the box centre's coordinates along its axes; u, v, w
+// the unit axes with the half extents in .w.
+template <int B, bool SD, bool CLAMP = false>
+__device__ __forceinline__ void test_obb(const float4 o, const float4 u, const float4 v,
                                          const float4 w, const float (&cx)[B],
                                          const float (&cy)[B], const float (&cz)[B],
                                          const float (&rad)[B], uint64_t& hits, float& msd) {
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    const float tx = cx[b] - c.x, ty = cy[b] - c.y, tz = cz[b] - c.z;
-    const float eu = fmaxf(fabsf(u.x * tx + u.y * ty + u.z * tz) - u.w, 0.0f);
-    const float ev = fmaxf(fabsf(v.x * tx + v.y * ty + v.z * tz) - v.w, 0.0f);
-    const float ew = fmaxf(fabsf(w.x * tx + w.y * ty + w.z * tz) - w.w, 0.0f);
+    const float pu = fmaf(u.x, cx[b], fmaf(u.y, cy[b], fmaf(u.z, cz[b], -o.x)));
+    const float pv = fmaf(v.x, cx[b], fmaf(v.y, cy[b], fmaf(v.z, cz[b], -o.y)));
+    const float pw = fmaf(w.x, cx[b], fmaf(w.y, cy[b], fmaf(w.z, cz[b], -o.z)));
+    const float eu = pos_part<CLAMP>(fabsf(pu) - u.w);
+    const float ev = pos_part<CLAMP>(fabsf(pv) - v.w);
+    const float ew = pos_part<CLAMP>(fabsf(pw) - w.w);
     const float d2 = eu * eu + ev * ev + ew * ew;
-    if (SD) msd = fminf(msd, sqrtf(d2) - rad[b]);
+    if (SD) msd = fminf(msd, hw_sqrt(d2) - rad[b]);
     else hits |= __ballot(d2 <= rad[b] * rad[b]);
   }
 }
@@ -81,7 +112,7 @@ __device__ __forceinline__ void test_sphere(const float4 s, const float (&cx)[B]
     const float tx = cx[b] - s.x, ty = cy[b] - s.y, tz = cz[b] - s.z;
     const float d2 = tx * tx + ty * ty + tz * tz;
     if (SD) {
-      msd = fminf(msd, fmaxf(sqrtf(d2) - s.w, 0.0f) - rad[b]);
+      msd = fminf(msd, fmaxf(hw_sqrt(d2) - s.w, 0.0f) - rad[b]);
     } else {
       const float reach = s.w + rad[b];
       hits |= __ballot(d2 <= reach * reach);
@@ -101,7 +132,7 @@ __device__ __forceinline__ void test_capsule(const float4 p0, const float4 dv, c
     const float wx = tx - s * dv.x, wy = ty - s * dv.y, wz = tz - s * dv.z;
     const float d2 = wx * wx + wy * wy + wz * wz;
     if (SD) {
-      msd = fminf(msd, fmaxf(sqrtf(d2) - p0.w, 0.0f) - rad[b]);
+      msd = fminf(msd, fmaxf(hw_sqrt(d2) - p0.w, 0.0f) - rad[b]);
     } else {
       const float reach = p0.w + rad[b];
       hits |= __ballot(d2 <= reach * reach);
@@ -109,7 +140,7 @@ __device__ __forceinline__ void test_capsule(const float4 p0, const float4 dv, c
   }
 }
 
-template <int B, bool SD>
+template <int B, bool SD, bool CLAMP = false>
 __device__ __forceinline__ void test_cylinder(const float4 c, const float4 u, const float (&cx)[B],
                                               const float (&cy)[B], const float (&cz)[B],
                                               const float (&rad)[B], uint64_t& hits, float& msd) {
@@ -118,30 +149,47 @@ __device__ __forceinline__ void test_cylinder(const float4 c, const float4 u, co
     const float tx = cx[b] - c.x, ty = cy[b] - c.y, tz = cz[b] - c.z;
     const float al = tx * u.x + ty * u.y + tz * u.z;
     const float wx = tx - al * u.x, wy = ty - al * u.y, wz = tz - al * u.z;
-    const float da = fmaxf(fabsf(al) - c.w, 0.0f);
-    const float dr = fmaxf(sqrtf(wx * wx + wy * wy + wz * wz) - u.w, 0.0f);
+    const float da = pos_part<CLAMP>(fabsf(al) - c.w);
+    const float dr = pos_part<CLAMP>(hw_sqrt(wx * wx + wy * wy + wz * wz) - u.w);
     const float d2 = da * da + dr * dr;
-    if (SD) msd = fminf(msd, sqrtf(d2) - rad[b]);
+    if (SD) msd = fminf(msd, hw_sqrt(d2) - rad[b]);
     else hits |= __ballot(d2 <= rad[b] * rad[b]);
   }
 }
 
+// Is every radius of the batch below 1 m (wavefront-uniform)?
+template <int B>
+__device__ __forceinline__ bool small_radii(const float (&rad)[B]) {
+  bool small = true;
+#pragma unroll
+  for (int b = 0; b < B; ++b) small = small && rad[b] < 1.0f;
+  return small;
+}
+
 // ------------------------------------------------------------------ all primitives
+
+template <int B, bool SD, bool CLAMP>
+__device__ __forceinline__ void test_all_of(const EnvDev& env, const float (&cx)[B],
+                                            const float (&cy)[B], const float (&cz)[B],
+                                            const float (&rad)[B], uint64_t& hits, float& msd) {
+  for (int i = 0; i < env.n_aabb; ++i)
+    test_aabb<B, SD, CLAMP>(env.aabb[2 * i], env.aabb[2 * i + 1], cx, cy, cz, rad, hits, msd);
+  for (int i = 0; i < env.n_obb; ++i)
+    test_obb<B, SD, CLAMP>(env.obb[4 * i], env.obb[4 * i + 1], env.obb[4 * i + 2],
+                           env.obb[4 * i + 3], cx, cy, cz, rad, hits, msd);
+  for (int i = 0; i < env.n_sph; ++i) test_sphere<B, SD>(env.sph[i], cx, cy, cz, rad, hits, msd);
+  for (int i = 0; i < env.n_cap; ++i)
+    test_capsule<B, SD>(env.cap[2 * i], env.cap[2 * i + 1], cx, cy, cz, rad, hits, msd);
+  for (int i = 0; i < env.n_cyl; ++i)
+    test_cylinder<B, SD, CLAMP>(env.cyl[2 * i], env.cyl[2 * i + 1], cx, cy, cz, rad, hits, msd);
+}
 
 template <int B, bool SD>
 __device__ __forceinline__ void test_all(const EnvDev& env, const float (&cx)[B],
                                          const float (&cy)[B], const float (&cz)[B],
                                          const float (&rad)[B], uint64_t& hits, float& msd) {
-  for (int i = 0; i < env.n_aabb; ++i)
-    test_aabb<B, SD>(env.aabb[2 * i], env.aabb[2 * i + 1], cx, cy, cz, rad, hits, msd);
-  for (int i = 0; i < env.n_obb; ++i)
-    test_obb<B, SD>(env.obb[4 * i], env.obb[4 * i + 1], env.obb[4 * i + 2], env.obb[4 * i + 3],
-                    cx, cy, cz, rad, hits, msd);
-  for (int i = 0; i < env.n_sph; ++i) test_sphere<B, SD>(env.sph[i], cx, cy, cz, rad, hits, msd);
-  for (int i = 0; i < env.n_cap; ++i)
-    test_capsule<B, SD>(env.cap[2 * i], env.cap[2 * i + 1], cx, cy, cz, rad, hits, msd);
-  for (int i = 0; i < env.n_cyl; ++i)
-    test_cylinder<B, SD>(env.cyl[2 * i], env.cyl[2 * i + 1], cx, cy, cz, rad, hits, msd);
+  if (!SD && small_radii<B>(rad)) test_all_of<B, SD, true>(env, cx, cy, cz, rad, hits, msd);
+  else test_all_of<B, SD, false>(env, cx, cy, cz, rad, hits, msd);
 }
 
 // ------------------------------------------------------------------ culled primitives
@@ -216,11 +264,11 @@ __device__ __forceinline__ bool near_box(const float4 bs, const WaveBox& box) {
 // scalar registers, and each candidate goes to its type's pair test by its
 // index (a wavefront-uniform branch).  Adds the candidates per type to
 // count[].
-template <int B>
-__device__ __forceinline__ void test_culled_all(const EnvDev& env, const WaveBox& box,
-                                                const float (&cx)[B], const float (&cy)[B],
-                                                const float (&cz)[B], const float (&rad)[B],
-                                                uint64_t& hits, int (&count)[5]) {
+template <int B, bool CLAMP>
+__device__ __forceinline__ void test_culled_of(const EnvDev& env, const WaveBox& box,
+                                               const float (&cx)[B], const float (&cy)[B],
+                                               const float (&cz)[B], const float (&rad)[B],
+                                               uint64_t& hits, int (&count)[5]) {
   const int lane = threadIdx.x & 63;
   const uint64_t act = __ballot(1);
   const int n_act = __popcll(act);
@@ -238,12 +286,13 @@ __device__ __forceinline__ void test_culled_all(const EnvDev& env, const WaveBox
       const int p = base + __popcll(act & ((1ull << l) - 1ull));
       if (p < b1) {
         ++count[0];
-        test_aabb<B, false>(env.aabb[2 * p], env.aabb[2 * p + 1], cx, cy, cz, rad, hits, msd_unused);
+        test_aabb<B, false, CLAMP>(env.aabb[2 * p], env.aabb[2 * p + 1], cx, cy, cz, rad, hits,
+                                   msd_unused);
       } else if (p < b2) {
         const int q = p - b1;
         ++count[1];
-        test_obb<B, false>(env.obb[4 * q], env.obb[4 * q + 1], env.obb[4 * q + 2], env.obb[4 * q + 3],
-                           cx, cy, cz, rad, hits, msd_unused);
+        test_obb<B, false, CLAMP>(env.obb[4 * q], env.obb[4 * q + 1], env.obb[4 * q + 2],
+                                  env.obb[4 * q + 3], cx, cy, cz, rad, hits, msd_unused);
       } else if (p < b3) {
         ++count[2];
         test_sphere<B, false>(env.sph[p - b2], cx, cy, cz, rad, hits, msd_unused);
@@ -254,11 +303,20 @@ __device__ __forceinline__ void test_culled_all(const EnvDev& env, const WaveBox
       } else {
         const int q = p - b4;
         ++count[4];
-        test_cylinder<B, false>(env.cyl[2 * q], env.cyl[2 * q + 1], cx, cy, cz, rad, hits,
-                                msd_unused);
+        test_cylinder<B, false, CLAMP>(env.cyl[2 * q], env.cyl[2 * q + 1], cx, cy, cz, rad, hits,
+                                       msd_unused);
       }
     }
   }
+}
+
+template <int B>
+__device__ __forceinline__ void test_culled_all(const EnvDev& env, const WaveBox& box,
+                                                const float (&cx)[B], const float (&cy)[B],
+                                                const float (&cz)[B], const float (&rad)[B],
+                                                uint64_t& hits, int (&count)[5]) {
+  if (small_radii<B>(rad)) test_culled_of<B, true>(env, box, cx, cy, cz, rad, hits, count);
+  else test_culled_of<B, false>(env, box, cx, cy, cz, rad, hits, count);
 }
 
 // ------------------------------------------------------------------ one configuration per lane

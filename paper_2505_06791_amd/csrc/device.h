@@ -44,7 +44,7 @@ struct RobotDev {
 struct EnvDev {
   int n_aabb, n_obb, n_sph, n_cap, n_cyl;
   const float4* aabb;  // 2 x float4: (centre, 0), (half extents, 0)
-  const float4* obb;   // 4 x float4: (centre, 0), (axis u, half_u), (axis v, half_v), (axis w, half_w)
+  const float4* obb;   // 4 x float4: (u.c, v.c, w.c, 0), (axis u, half_u), (axis v, half_v), (axis w, half_w)
   const float4* sph;   // 1 x float4: (centre, radius)
   const float4* cap;   // 2 x float4: (p0, radius), (p1 - p0, 1/|p1 - p0|^2 or 0)
   const float4* cyl;   // 2 x float4: (centre, half length), (unit axis, radius)
