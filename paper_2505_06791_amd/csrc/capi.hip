@@ -265,17 +265,34 @@ int cp_robot_create(const cp_robot_desc* d, cp_robot** out) {
     std::vector<int> rank(d->n_spheres);
     for (int s = 0; s < d->n_spheres; ++s) rank[order[s]] = s;
     const int n_pairs = (int)r->self_pairs.size() / 2;
-    std::vector<int2> dev_pairs(n_pairs);
-    for (int i = 0; i < n_pairs; ++i)
-      dev_pairs[i] = make_int2(rank[r->self_pairs[2 * i]], rank[r->self_pairs[2 * i + 1]]);
+    const int n_padded = (n_pairs + kSelfPad - 1) / kSelfPad * kSelfPad;
+    std::vector<int2> dev_pairs(n_pairs), cc_pairs(n_padded);
+    {
+      const float never = -1.0f;   // d^2 <= -1 never holds
+      int bits;
+      std::memcpy(&bits, &never, sizeof bits);
+      for (int i = n_pairs; i < n_padded; ++i) cc_pairs[i] = make_int2(0, bits);
+    }
+    for (int i = 0; i < n_pairs; ++i) {
+      const int s0 = rank[r->self_pairs[2 * i]], t0 = rank[r->self_pairs[2 * i + 1]];
+      dev_pairs[i] = make_int2(s0, t0);
+      const double reach = (double)sph[s0].w + (double)sph[t0].w;
+      const float reach2 = (float)(reach * reach);
+      int bits;
+      std::memcpy(&bits, &reach2, sizeof bits);
+      cc_pairs[i] = make_int2(s0 | (t0 << 16), bits);   // positions < kMaxSpheres <= 2^16
+    }
     hipError_t e = hipMalloc((void**)&r->dev, sizeof(RobotDev));
     if (e == hipSuccess) e = hipMalloc((void**)&r->spheres, sizeof(float4) * sph.size());
     if (e == hipSuccess && n_pairs > 0) e = hipMalloc((void**)&r->pairs, sizeof(int2) * n_pairs);
+    if (e == hipSuccess && n_pairs > 0) e = hipMalloc((void**)&r->pairs_cc, sizeof(int2) * n_padded);
     if (e == hipSuccess) e = hipMemcpy(r->dev, &h, sizeof h, hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(r->spheres, sph.data(), sizeof(float4) * sph.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && n_pairs > 0)
       e = hipMemcpy(r->pairs, dev_pairs.data(), sizeof(int2) * n_pairs, hipMemcpyHostToDevice);
+    if (e == hipSuccess && n_pairs > 0)
+      e = hipMemcpy(r->pairs_cc, cc_pairs.data(), sizeof(int2) * n_padded, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       cp_robot_destroy(r);
       return hip_fail(e, "cp_robot_create");
@@ -293,6 +310,7 @@ void cp_robot_destroy(cp_robot* r) {
   if (r->dev) (void)hipFree(r->dev);
   if (r->spheres) (void)hipFree(r->spheres);
   if (r->pairs) (void)hipFree(r->pairs);
+  if (r->pairs_cc) (void)hipFree(r->pairs_cc);
   delete r;
 }
 
@@ -424,7 +442,7 @@ int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const f
                                 d_min_sd, early, 8, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fk_cc_batch launch");
     if (flags & CP_SELF_COLLISION) {
-      e = launch_self_cc(robot->dev, robot->host, robot->spheres, robot->pairs,
+      e = launch_self_cc(robot->dev, robot->host, robot->spheres, robot->pairs_cc,
                          (int)robot->self_pairs.size() / 2, n_cfg, d_q, d_collide, d_min_sd, early,
                          (hipStream_t)stream);
       if (e != hipSuccess) return hip_fail(e, "fk_cc_batch self-collision launch");
@@ -516,7 +534,7 @@ int do_validate(const cp_robot* robot, const cp_env* env, const cp_proj_params& 
     if (e != hipSuccess) return hip_fail(e, "validation launch");
   }
   if (flags & CP_SELF_COLLISION) {
-    hipError_t e = launch_self_cc_motions(robot->dev, robot->host, robot->spheres, robot->pairs,
+    hipError_t e = launch_self_cc_motions(robot->dev, robot->host, robot->spheres, robot->pairs_cc,
                                           (int)robot->self_pairs.size() / 2, p.W, n_motions,
                                           d_xi, d_status, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "self-collision launch");

@@ -205,11 +205,15 @@ __device__ __forceinline__ float dpp_partner(float v) {
   return __builtin_bit_cast(
       float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
-__device__ __forceinline__ float wave_min(float v) {
+// Minimum over the lane's row of 16 lanes.
+__device__ __forceinline__ float row_min(float v) {
   v = fminf(v, dpp_partner<0xB1>(v));
   v = fminf(v, dpp_partner<0x4E>(v));
   v = fminf(v, dpp_partner<0x141>(v));
-  v = fminf(v, dpp_partner<0x140>(v));
+  return fminf(v, dpp_partner<0x140>(v));
+}
+__device__ __forceinline__ float wave_min(float v) {
+  v = row_min(v);
   v = fminf(v, __shfl_xor(v, 16, 64));
   return fminf(v, __shfl_xor(v, 32, 64));
 }

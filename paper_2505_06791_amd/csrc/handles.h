@@ -33,6 +33,7 @@ struct cp_robot {
   cprrtc::RobotDev* dev = nullptr;  // device copy
   float4* spheres = nullptr;        // device spheres, grouped by link
   int2* pairs = nullptr;            // device self-collision pairs (positions in `spheres`)
+  int2* pairs_cc = nullptr;         // the same pairs as (s | t << 16, bits of (r_s + r_t)^2), padded
   std::vector<int32_t> self_pairs;  // host, description order: s0 t0 s1 t1 ...
   std::mutex rtc_lock;              // guards rtc (specialisation may run beside projections)
   std::deque<cprrtc::RtcKernel> rtc; // a deque: entries stay put as more are added

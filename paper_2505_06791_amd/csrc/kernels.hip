@@ -141,18 +141,29 @@ __global__ __launch_bounds__(kBlock) void validate_kernel(
 
 // ------------------------------------------------------------------ self-collision
 
-// One wavefront per configuration: every lane runs the (uniform) forward
-// kinematics, lanes place the sphere centres into LDS (sphere s by lane
-// s mod 64), then lanes test the checked pairs 64 at a time:
+// Four configurations per wavefront, one per row of 16 lanes: the row runs
+// its configuration's forward kinematics (the same value in its 16 lanes),
+// places the sphere centres into LDS (sphere s by lane s mod 16 of the row),
+// then tests the checked pairs 16 at a time:
 // sd = |c_s - c_t| - r_s - r_t, colliding iff sd <= 0 (for the verdict
-// alone, |c_s - c_t|^2 <= (r_s + r_t)^2).
+// alone, |c_s - c_t|^2 <= (r_s + r_t)^2 with the right-hand side stored
+// with the pair, so only the centres' x, y, z are read).
+//   pairs[p] = (s | t << 16, bits of (r_s + r_t)^2), s and t positions in
+//   the link-grouped sphere array; n_pairs real pairs, the list padded to a
+//   multiple of kSelfPad with (0, 0, -1), which never collides.
 //   MOTION = false: item i is configuration i of q; collide[i] |= hit and,
 //                   with min_sd, min_sd[i] = min(min_sd[i], min pair sd)
 //                   (every pair evaluated).
 //   MOTION = true:  item i is waypoint 1 + i mod (W - 1) of motion
 //                   i / (W - 1) in xi; motions whose status is not 0 are
 //                   skipped; a hit sets the status to 2.
-// Four wavefronts per workgroup; LDS holds 4 x n_spheres float4.
+// A row without an item (the grid's tail, a motion already decided) runs
+// its kinematics on a valid row of the input and reports nothing.  Up to
+// four wavefronts per workgroup (fewer for robots with many spheres); LDS
+// holds 4 x n_spheres float4 per wavefront.
+constexpr int kSelfRow = 16;
+constexpr int kSelfPerWave = 64 / kSelfRow;
+static_assert(kSelfPad % kSelfRow == 0, "pairs are read a row at a time");
 constexpr int kSelfWaves = 4;
 
 template <bool MOTION>
@@ -163,29 +174,34 @@ __global__ __launch_bounds__(64 * kSelfWaves) void self_cc_kernel(
     int* __restrict__ status, int early) {
   extern __shared__ float4 centres[];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t item = (int64_t)blockIdx.x * kSelfWaves + w;
-  if (item >= n_items) return;                    // wave-uniform
+  const int g = lane / kSelfRow, l = lane % kSelfRow;
+  const int64_t first = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * kSelfPerWave;
+  if (first >= n_items) return;                   // wave-uniform
+  const int64_t item = first + g;
   const int dof = rob->dof;
+  bool on = item < n_items;
   int64_t motion = 0;
   const float* q;
   if (MOTION) {
-    motion = item / (W - 1);
-    if (status[motion] != 0) return;              // failed or already colliding
-    q = q_all + (motion * W + 1 + item % (W - 1)) * dof;
+    motion = on ? item / (W - 1) : 0;
+    on = on && status[motion] == 0;               // failed or already colliding
+    q = q_all + (on ? motion * W + 1 + item % (W - 1) : 1) * dof;
   } else {
-    q = q_all + item * dof;
+    q = q_all + (on ? item : 0) * dof;
   }
-  float4* c = centres + (size_t)w * rob->n_spheres;
+  if (__ballot(on) == 0) return;
+  const int n_sph = rob->n_spheres;
+  float4* c = centres + (size_t)(w * kSelfPerWave + g) * n_sph;
   for (int ch = 0; ch < rob->n_chains; ++ch) {
     Frame T;
     frame_from(T, rob->base[ch]);
     for (int j = rob->chain_begin[ch]; j < rob->chain_begin[ch + 1]; ++j) {
       joint_advance(T, rob, j, q[j]);
-      for (int s = rob->sph_begin[j] + lane; s < rob->sph_begin[j + 1]; s += 64) {
-        const float4 l = sph[s];
-        c[s] = make_float4(T.r[0] * l.x + T.r[1] * l.y + T.r[2] * l.z + T.p[0],
-                           T.r[3] * l.x + T.r[4] * l.y + T.r[5] * l.z + T.p[1],
-                           T.r[6] * l.x + T.r[7] * l.y + T.r[8] * l.z + T.p[2], l.w);
+      for (int s = rob->sph_begin[j] + l; s < rob->sph_begin[j + 1]; s += kSelfRow) {
+        const float4 ls = sph[s];
+        c[s] = make_float4(T.r[0] * ls.x + T.r[1] * ls.y + T.r[2] * ls.z + T.p[0],
+                           T.r[3] * ls.x + T.r[4] * ls.y + T.r[5] * ls.z + T.p[1],
+                           T.r[6] * ls.x + T.r[7] * ls.y + T.r[8] * ls.z + T.p[2], ls.w);
       }
     }
   }
@@ -194,31 +210,49 @@ __global__ __launch_bounds__(64 * kSelfWaves) void self_cc_kernel(
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
   const bool all_pairs = !MOTION && min_sd;
+  const uint64_t row_bits = 0xFFFFull << (kSelfRow * g);
+  const uint64_t off_rows = __ballot(!on);
+  uint64_t acc = 0;                               // OR of every round's ballot (uniform)
   float msd = FLT_MAX;
-  bool hit_any = false;
-  for (int base = 0; base < n_pairs; base += 64) {
-    const int p = base + lane;
-    bool hit = false;
-    if (p < n_pairs) {
-      const int2 st = pairs[p];
-      const float4 a = c[st.x], b = c[st.y];
-      const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
-      const float d2 = dx * dx + dy * dy + dz * dz, reach = a.w + b.w;
-      if (all_pairs) {
-        const float sd = sqrtf(d2) - reach;
+  if (all_pairs) {
+    for (int base = 0; base < n_pairs; base += kSelfRow) {
+      const int p = base + l;
+      bool hit = false;
+      if (on && p < n_pairs) {
+        const int st = pairs[p].x;
+        const float4 a = c[st & 0xFFFF], b = c[st >> 16];
+        const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+        const float sd = sqrtf(dx * dx + dy * dy + dz * dz) - (a.w + b.w);
         msd = fminf(msd, sd);
         hit = sd <= 0.0f;
-      } else {
-        hit = d2 <= reach * reach;       // the verdict alone: no square root
+      }
+      acc |= __ballot(hit);
+    }
+  } else {
+    // the list is padded to a multiple of kSelfPad with pairs that never
+    // hit, and a row without an item tests its own (finite) centres with its
+    // bits ignored: no lane branches
+    const int2* pb = pairs;                       // wavefront-uniform
+    for (int base = 0; base < n_pairs; base += kSelfPad, pb += kSelfPad) {
+#pragma unroll
+      for (int u = 0; u < kSelfPad / kSelfRow; ++u) {
+        const int2 pr = pb[u * kSelfRow + l];
+        const float4* ca = c + (pr.x & 0xFFFF);
+        const float4* cb = c + (pr.x >> 16);
+        const float dx = ca->x - cb->x, dy = ca->y - cb->y, dz = ca->z - cb->z;
+        acc |= __ballot(dx * dx + dy * dy + dz * dz <= __int_as_float(pr.y));
+      }
+      if (early) {
+        // every row decided (a hit) or without an item
+        const uint64_t x = acc | off_rows;
+        const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+        if ((lo & 0xFFFFu) && (lo >> 16) && (hi & 0xFFFFu) && (hi >> 16)) break;
       }
     }
-    if (__ballot(hit)) {
-      hit_any = true;
-      if (early && !all_pairs) break;
-    }
   }
-  if (all_pairs) msd = wave_min(msd);
-  if (lane == 0) {
+  const bool hit_any = (acc & row_bits) != 0;
+  if (all_pairs) msd = row_min(msd);
+  if (on && l == 0) {
     if (MOTION) {
       if (hit_any) status[motion] = 2;
     } else {
@@ -228,13 +262,21 @@ __global__ __launch_bounds__(64 * kSelfWaves) void self_cc_kernel(
   }
 }
 
+// Wavefronts per workgroup for a robot: LDS of at most 64 KiB per workgroup.
+static int self_waves(int n_spheres) {
+  const int per_wave = (int)sizeof(float4) * kSelfPerWave * n_spheres;
+  return std::max(1, std::min(kSelfWaves, 65536 / per_wave));
+}
+
 hipError_t launch_self_cc(const RobotDev* rob, const RobotDev& host, const float4* sph,
                           const int2* pairs, int n_pairs, int n_cfg, const float* q,
                           uint8_t* collide, float* min_sd, bool early, hipStream_t stream) {
   if (n_pairs == 0 || n_cfg == 0) return hipSuccess;
-  const size_t lds = sizeof(float4) * kSelfWaves * host.n_spheres;
-  const unsigned nb = (unsigned)((n_cfg + kSelfWaves - 1) / kSelfWaves);
-  self_cc_kernel<false><<<nb, 64 * kSelfWaves, lds, stream>>>(
+  const int waves = self_waves(host.n_spheres);
+  const size_t lds = sizeof(float4) * kSelfPerWave * waves * host.n_spheres;
+  const int64_t per_block = (int64_t)kSelfPerWave * waves;
+  const unsigned nb = (unsigned)((n_cfg + per_block - 1) / per_block);
+  self_cc_kernel<false><<<nb, 64 * waves, lds, stream>>>(
       rob, sph, pairs, n_pairs, n_cfg, 0, q, collide, min_sd, nullptr, early ? 1 : 0);
   return hipGetLastError();
 }
@@ -243,10 +285,12 @@ hipError_t launch_self_cc_motions(const RobotDev* rob, const RobotDev& host, con
                                   const int2* pairs, int n_pairs, int W, int n_motions,
                                   const float* xi, int* status, hipStream_t stream) {
   if (n_pairs == 0 || n_motions == 0) return hipSuccess;
-  const size_t lds = sizeof(float4) * kSelfWaves * host.n_spheres;
+  const int waves = self_waves(host.n_spheres);
+  const size_t lds = sizeof(float4) * kSelfPerWave * waves * host.n_spheres;
   const int64_t items = (int64_t)n_motions * (W - 1);
-  const unsigned nb = (unsigned)((items + kSelfWaves - 1) / kSelfWaves);
-  self_cc_kernel<true><<<nb, 64 * kSelfWaves, lds, stream>>>(
+  const int64_t per_block = (int64_t)kSelfPerWave * waves;
+  const unsigned nb = (unsigned)((items + per_block - 1) / per_block);
+  self_cc_kernel<true><<<nb, 64 * waves, lds, stream>>>(
       rob, sph, pairs, n_pairs, items, W, xi, nullptr, nullptr, status, 1);
   return hipGetLastError();
 }
