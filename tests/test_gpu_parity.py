@@ -414,3 +414,63 @@ def test_full_size_sampled(G, name, M, sample):
     ref = _oracle_pv(w, q_from[idx], q_to[idx], 64, w["tau_task"])
     _compare_pv(name + "-full", ref, xi[idx], st[idx], it[idx], w, 64, w["tau_task"])
     assert set(np.unique(st)).issubset({0, 1, 2})
+
+
+def _scaled(w, k):
+    """The workload with every length multiplied by k (revolute joints only):
+    the same verdicts up to rounding, robot spheres k times larger."""
+    assert not np.any(w["robot"]["joint_type"])
+    r = {key: (np.array(v, copy=True) if isinstance(v, np.ndarray) else v)
+         for key, v in w["robot"].items()}
+    r["a"] *= k
+    r["d"] *= k
+    r["base"][:, :3, 3] *= k
+    r["tool"][:, :3, 3] *= k
+    r["sphere"] *= k
+    e = {key: np.array(v, dtype=np.float64, copy=True) for key, v in w["env"].items()}
+    e["aabb"] *= k
+    e["obb"][:, :3] *= k
+    e["obb"][:, 12:15] *= k
+    e["sphere"] *= k
+    e["capsule"] *= k
+    e["cylinder"][:, :3] *= k
+    e["cylinder"][:, 6:8] *= k
+    return dict(robot=r, env=e, constraint=w["constraint"], tau_task=w["tau_task"])
+
+
+@pytest.mark.parametrize("k", [16.0, 25.0])
+def test_metre_spheres_take_the_unclamped_pair_tests(G, k):
+    """The cluttered scene scaled by k: robot spheres of 0.5 to 2 m, so some
+    sphere batches hold a radius of 1 m or more and take the pair tests
+    without the [0, 1] clamp of the distance components, and the others
+    take the clamped ones.  Verdicts per configuration (every primitive)
+    and per motion (culled validation) agree with the oracle outside the
+    band; minimum signed distances within 1e-5 m per unit of scale."""
+    w = _scaled(I.workload("cluttered", 2003), k)
+    radii = w["robot"]["sphere"][:, 3]
+    assert (radii >= 1.0).any() and (radii < 1.0).any()
+    n = 700
+    q32 = I.random_configs(w["robot"], n, 31).astype(np.float32)
+    ro, eo, _ = oracle_views(w)
+    col_o, sd_o = O.fk_cc_batch(ro, eo, q32.astype(np.float64), n_threads=8)
+    band = np.abs(sd_o) <= BAND * k
+    col_g, _ = _gpu_fkcc(G, w, q32)
+    col_x, sd_g = _gpu_fkcc(G, w, q32, want_sd=True)
+    col_n, _ = _gpu_fkcc(G, w, q32, flags=G.NO_EARLY_EXIT)
+    _report("metre spheres", k=k, configs=n, colliding=int(col_o.sum()), band=int(band.sum()))
+    assert 0 < col_o[~band].sum() < (~band).sum()     # both verdicts occur
+    assert np.array_equal(col_g[~band], col_o[~band])
+    assert np.array_equal(col_x[~band], col_o[~band])
+    assert np.array_equal(col_g, col_n)
+    assert np.abs(sd_g.astype(np.float64) - sd_o).max() < 1e-5 * k
+    # motions that hold one configuration at every waypoint collide iff it does
+    W, M = 64, 256
+    robot, env = G.Robot(w["robot"]), G.Env(w["env"])
+    xi = torch.from_numpy(np.repeat(q32[:M, None, :], W, axis=1).copy()).to(DEV)
+    for flags in (0, G.NO_CULL):
+        st = torch.zeros(M, dtype=torch.int32, device=DEV)
+        G.validate_motions(robot, env, G.proj_params(W=W), xi, st, flags=flags)
+        torch.cuda.synchronize()
+        got = st.cpu().numpy()
+        ok = ~band[:M]
+        assert np.array_equal(got[ok], 2 * col_o[:M][ok].astype(np.int32)), flags

@@ -160,3 +160,46 @@ def test_planner_self_collision_flag_checked(G):
     with pytest.raises(G.CprrtcError) as e:
         G.Planner(robot, G.plan_opts(flags=1 << 12))
     assert e.value.code == G.CP_E_ARG
+
+
+def test_self_collision_many_spheres(G):
+    """A robot of 600 spheres (the cluttered arm's 100, six times over with
+    small offsets and half the radius): its workgroups hold fewer
+    wavefronts so the centres fit LDS.  Pair list, per-configuration verdicts
+    and minimum signed distances, and per-motion verdicts agree with the
+    oracle (empty scene: the self-check alone)."""
+    base = I.workload("cluttered", 2404)["robot"]
+    rng = np.random.default_rng(7)
+    rd = {key: (np.array(v, copy=True) if isinstance(v, np.ndarray) else v)
+          for key, v in base.items()}
+    sph = np.concatenate([base["sphere"] for _ in range(6)])
+    sph[:, :3] += rng.uniform(-0.02, 0.02, (len(sph), 3))
+    sph[:, 3] *= 0.5
+    rd["sphere"] = sph
+    rd["sphere_link"] = np.concatenate([base["sphere_link"] for _ in range(6)]).astype(np.int32)
+    w = dict(robot=rd, env=I.empty_env())
+    robot = G.Robot(rd)
+    ro = O.Robot(rd)
+    pairs = O.self_pairs(ro)
+    got = robot.self_pairs()
+    print("spheres", len(sph), "pairs", len(pairs), flush=True)
+    assert len(pairs) > 10000 and np.array_equal(got, pairs)
+    n = 70                                        # 17.5 wavefronts of four rows
+    q32 = I.random_configs(rd, n, 41).astype(np.float32)
+    q64 = q32.astype(np.float64)
+    col_s, sd_s = O.self_cc_batch(ro, q64, n_threads=8)
+    band = np.abs(sd_s) <= BAND
+    col_g, _ = _gpu_fkcc(G, w, q32, flags=G.SELF_COLLISION)
+    col_x, sd_g = _gpu_fkcc(G, w, q32, flags=G.SELF_COLLISION, want_sd=True)
+    print("self-colliding", int(col_s.sum()), "band", int(band.sum()), flush=True)
+    assert 0 < col_s[~band].sum() < (~band).sum()
+    assert np.array_equal(col_g[~band], col_s[~band])
+    assert np.array_equal(col_x[~band], col_s[~band])
+    assert np.abs(sd_g.astype(np.float64) - sd_s).max() < 1e-5
+    W = 32
+    env = G.Env(w["env"])
+    xi = torch.from_numpy(np.repeat(q32[:, None, :], W, axis=1).copy()).to("cuda:0")
+    st = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    G.validate_motions(robot, env, G.proj_params(W=W), xi, st, flags=G.SELF_COLLISION)
+    torch.cuda.synchronize()
+    assert np.array_equal(st.cpu().numpy()[~band], 2 * col_s[~band].astype(np.int32))
