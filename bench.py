@@ -78,7 +78,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3    # MI355X, 256 CU x 2.4 GHz, packed FMA counte
 # HBM traffic of the projection kernel on this workload, from two rocprofv3
 # --pmc runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by
 # what the same counter reads for a plain 256 MiB device copy (FETCH_SIZE
-# reads 131086.8 KiB of 262144, WRITE_SIZE 262144 of 262144).  Valid only
+# reads 131086.7 KiB of 262144, WRITE_SIZE 262144 of 262144).  Valid only
 # for the kernel sources they were taken on.
 TRAFFIC = [
     {
@@ -86,18 +86,18 @@ TRAFFIC = [
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h",
                     "paper_2505_06791_amd/csrc/kernels.hip", "paper_2505_06791_amd/csrc/kernels.h"),
-        "sources_sha256": "ca89ae1ab780aeae72cfdb6b4cd09154b9c0786b7d7d17ab7bb5d60046ba0a9c",
-        "fetch_kib": 5291.8, "fetch_scale": 262144.0 / 131086.8,
-        "write_kib": 115975.3, "write_scale": 1.0,
+        "sources_sha256": "38213fbb144e53f948fc4b2360e155b097aae88304a76daf9f7e1c7b46e150f5",
+        "fetch_kib": 5291.5, "fetch_scale": 262144.0 / 131086.7,
+        "write_kib": 115975.0, "write_scale": 1.0,
     },
     {
         "kernel": "cp_rtc_pool<7, 1> (hipRTC)",
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h", "paper_2505_06791_amd/csrc/rtc.hip",
                     "paper_2505_06791_amd/csrc/kernels.h", "include/cprrtc.h"),
-        "sources_sha256": "e4f23f3ead0752d27c9c1504aaf940e2bb69609867b0e7eb859cf1ebc484398b",
-        "fetch_kib": 5215.4, "fetch_scale": 262144.0 / 131086.8,
-        "write_kib": 116180.9, "write_scale": 1.0,
+        "sources_sha256": "3dcaf246df17452e3d880c3e99b86fb2a17998b1459f67069f0ce295def87fde",
+        "fetch_kib": 5214.9, "fetch_scale": 262144.0 / 131086.7,
+        "write_kib": 116179.1, "write_scale": 1.0,
     },
 ]
 

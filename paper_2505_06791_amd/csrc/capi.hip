@@ -265,7 +265,8 @@ int cp_robot_create(const cp_robot_desc* d, cp_robot** out) {
     std::vector<int> rank(d->n_spheres);
     for (int s = 0; s < d->n_spheres; ++s) rank[order[s]] = s;
     const int n_pairs = (int)r->self_pairs.size() / 2;
-    const int n_padded = (n_pairs + kSelfPad - 1) / kSelfPad * kSelfPad;
+    // a multiple of kSelfPad, and one more group read ahead by the kernel
+    const int n_padded = (n_pairs + kSelfPad - 1) / kSelfPad * kSelfPad + kSelfPad;
     std::vector<int2> dev_pairs(n_pairs), cc_pairs(n_padded);
     {
       const float never = -1.0f;   // d^2 <= -1 never holds
@@ -356,8 +357,10 @@ int cp_env_create(const cp_env_desc* d, cp_env** out) {
     const size_t boff = at;
     size_t bi = boff;
     auto bound = [&](double x, double y, double z, double r) {
-      // float rounding of the centre is covered by the culling margin
-      buf[bi++] = make_float4((float)x, (float)y, (float)z, (float)(r * (1.0 + 1e-6)));
+      // centre and (radius + culling margin)^2; float rounding of the
+      // centre is covered by the margin
+      const double reach = r * (1.0 + 1e-6) + (double)kCullMargin;
+      buf[bi++] = make_float4((float)x, (float)y, (float)z, (float)(reach * reach));
     };
     for (int i = 0; i < d->n_aabb; ++i) {
       const double* p = d->aabb + 6 * i;

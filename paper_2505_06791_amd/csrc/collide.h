@@ -46,7 +46,6 @@
 
 namespace cprrtc {
 
-constexpr float kCullMargin = 1e-4f;   // metres; far above float32 rounding of the box test
 
 // ------------------------------------------------------------------ single-primitive tests
 // B sphere centres (per lane) against one primitive (uniform).  Verdict form
@@ -250,13 +249,14 @@ __device__ __forceinline__ WaveBox wave_box(const float (&cx)[B], const float (&
   return box;
 }
 
-// Does the bounding sphere (centre, radius) come within kCullMargin of the box?
+// Does the bounding sphere come within kCullMargin of the box?  bs holds
+// the centre and (radius + kCullMargin)^2.  med3(x, lo, hi) - x is the
+// signed gap from x to the box along one axis (0 inside).
 __device__ __forceinline__ bool near_box(const float4 bs, const WaveBox& box) {
-  const float ex = fmaxf(fmaxf(box.lo[0] - bs.x, bs.x - box.hi[0]), 0.0f);
-  const float ey = fmaxf(fmaxf(box.lo[1] - bs.y, bs.y - box.hi[1]), 0.0f);
-  const float ez = fmaxf(fmaxf(box.lo[2] - bs.z, bs.z - box.hi[2]), 0.0f);
-  const float reach = bs.w + kCullMargin;
-  return ex * ex + ey * ey + ez * ez <= reach * reach;
+  const float ex = __builtin_amdgcn_fmed3f(bs.x, box.lo[0], box.hi[0]) - bs.x;
+  const float ey = __builtin_amdgcn_fmed3f(bs.y, box.lo[1], box.hi[1]) - bs.y;
+  const float ez = __builtin_amdgcn_fmed3f(bs.z, box.lo[2], box.hi[2]) - bs.z;
+  return ex * ex + ey * ey + ez * ez <= bs.w;
 }
 
 // Test the batch against the primitives whose bounding spheres come near

@@ -41,6 +41,9 @@ struct RobotDev {
   int sph_begin[kMaxDof + 1];        // spheres riding in joint frame j: [sph_begin[j], sph_begin[j+1])
 };
 
+// Culling margin (metres; far above float32 rounding of the box test).
+constexpr float kCullMargin = 1e-4f;
+
 struct EnvDev {
   int n_aabb, n_obb, n_sph, n_cap, n_cyl;
   const float4* aabb;  // 2 x float4: (centre, 0), (half extents, 0)
@@ -49,7 +52,7 @@ struct EnvDev {
   const float4* cap;   // 2 x float4: (p0, radius), (p1 - p0, 1/|p1 - p0|^2 or 0)
   const float4* cyl;   // 2 x float4: (centre, half length), (unit axis, radius)
   const float4* bound; // 1 x float4 per primitive, types in the order above:
-                       // bounding sphere (centre, radius) used for culling
+                       // bounding sphere for culling: (centre, (radius + margin)^2)
 };
 
 enum { KIND_NONE = 0, KIND_POSE = 1, KIND_REL = 2 };

@@ -35,7 +35,7 @@ hipError_t launch_project_mode(int dof, int mode, const RobotDev* rob, const Con
 // Self-collision of configurations (OR into collide, min into min_sd) and of
 // motions' waypoints 1..W-1 (status 0 -> 2 on a hit).  pairs: (s | t << 16,
 // bits of (r_s + r_t)^2) per checked pair, padded to a multiple of kSelfPad
-// entries with (0, 0, -1.0f).
+// entries, plus kSelfPad more, with (0, 0, -1.0f).
 constexpr int kSelfPad = 32;
 hipError_t launch_self_cc(const RobotDev* rob, const RobotDev& host, const float4* sph,
                           const int2* pairs, int n_pairs, int n_cfg, const float* q,

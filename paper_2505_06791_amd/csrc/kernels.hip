@@ -150,7 +150,8 @@ __global__ __launch_bounds__(kBlock) void validate_kernel(
 // with the pair, so only the centres' x, y, z are read).
 //   pairs[p] = (s | t << 16, bits of (r_s + r_t)^2), s and t positions in
 //   the link-grouped sphere array; n_pairs real pairs, the list padded to a
-//   multiple of kSelfPad with (0, 0, -1), which never collides.
+//   multiple of kSelfPad, plus kSelfPad more entries, with (0, 0, -1), which
+//   never collides.
 //   MOTION = false: item i is configuration i of q; collide[i] |= hit and,
 //                   with min_sd, min_sd[i] = min(min_sd[i], min pair sd)
 //                   (every pair evaluated).
@@ -232,11 +233,23 @@ __global__ __launch_bounds__(64 * kSelfWaves) void self_cc_kernel(
     // the list is padded to a multiple of kSelfPad with pairs that never
     // hit, and a row without an item tests its own (finite) centres with its
     // bits ignored: no lane branches
+    // the records of the next trip are loaded before this trip's centres
+    // are read (the list has kSelfPad entries past its padded end for that)
+    constexpr int kU = kSelfPad / kSelfRow;
     const int2* pb = pairs;                       // wavefront-uniform
-    for (int base = 0; base < n_pairs; base += kSelfPad, pb += kSelfPad) {
+    int2 next[kU];
 #pragma unroll
-      for (int u = 0; u < kSelfPad / kSelfRow; ++u) {
-        const int2 pr = pb[u * kSelfRow + l];
+    for (int u = 0; u < kU; ++u) next[u] = pb[u * kSelfRow + l];
+    for (int base = 0; base < n_pairs; base += kSelfPad) {
+      int2 cur[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) cur[u] = next[u];
+      pb += kSelfPad;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) next[u] = pb[u * kSelfRow + l];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int2 pr = cur[u];
         const float4* ca = c + (pr.x & 0xFFFF);
         const float4* cb = c + (pr.x >> 16);
         const float dx = ca->x - cb->x, dy = ca->y - cb->y, dz = ca->z - cb->z;
