@@ -87,17 +87,17 @@ TRAFFIC = [
                     "paper_2505_06791_amd/csrc/project_pool.h",
                     "paper_2505_06791_amd/csrc/kernels.hip", "paper_2505_06791_amd/csrc/kernels.h"),
         "sources_sha256": "38213fbb144e53f948fc4b2360e155b097aae88304a76daf9f7e1c7b46e150f5",
-        "fetch_kib": 5291.5, "fetch_scale": 262144.0 / 131086.7,
-        "write_kib": 115975.0, "write_scale": 1.0,
+        "fetch_kib": 5291.0, "fetch_scale": 262144.0 / 131086.7,
+        "write_kib": 115974.0, "write_scale": 1.0,
     },
     {
         "kernel": "cp_rtc_pool<7, 1> (hipRTC)",
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h", "paper_2505_06791_amd/csrc/rtc.hip",
                     "paper_2505_06791_amd/csrc/kernels.h", "include/cprrtc.h"),
-        "sources_sha256": "3dcaf246df17452e3d880c3e99b86fb2a17998b1459f67069f0ce295def87fde",
-        "fetch_kib": 5214.9, "fetch_scale": 262144.0 / 131086.7,
-        "write_kib": 116179.1, "write_scale": 1.0,
+        "sources_sha256": "7d01b5ad89161e59ecee33f0e2b3a530551e5079db6767edfd51cf9ff18cca94",
+        "fetch_kib": 5214.2, "fetch_scale": 262144.0 / 131086.7,
+        "write_kib": 116180.9, "write_scale": 1.0,
     },
 ]
 

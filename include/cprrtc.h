@@ -186,7 +186,8 @@ int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const f
  * |c_s - c_t| - r_s - r_t <= 0.  With CP_SELF_COLLISION, fk_cc_batch ORs
  * this into d_collide (and takes the minimum into d_min_sd), and motion
  * validation marks a motion colliding (status 2) if any of waypoints
- * 1..W-1 self-collides (one wavefront per waypoint, lanes over the pairs).
+ * 1..W-1 self-collides (16 lanes per configuration or waypoint, over the
+ * pairs).
  *   pairs     out, host, nullable: [capacity][2] sphere indices in
  *             description order, s < t, sorted; at most capacity written
  *   count     out: the number of checked pairs
