@@ -305,6 +305,52 @@ def test_project_single_iteration_budget_fails_off_manifold(oracle_lib):
     assert not ok
 
 
+def _update_case_views(O, case):
+    if case["robot"] == "arm7":
+        rd = I.make_arm(3)
+    else:  # one revolute joint about world z, no offsets: yaw of the tool = q
+        rd = _chain_robot([0.0], [0.0], [0.0], [0.0], [0])
+    if case["constraint"] == "none":
+        cd = I.no_constraint()
+    else:  # yaw locked at 0
+        cd = dict(kind=I.CON_POSE, mask=np.array([0, 0, 0, 0, 0, 1], np.int32),
+                  frame=np.eye(4), target=np.zeros(6), rel_target=np.eye(4))
+    return O.Robot(rd), O.Constraint(cd)
+
+
+def _update_cases():
+    with open(os.path.join(GOLDEN, "update_step.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _update_cases(), ids=lambda c: c["name"])
+def test_update_step_hand_worked(oracle_lib, case):
+    """Algorithm 1's update (task step plus the signed smoothing term
+    (|D| - tau) D, alpha on both, Jacobi snapshot, clamp), the validity test,
+    the contiguous prefix and the frozen values, on hand-worked segments
+    (tests/golden/update_step.json)."""
+    O = oracle_lib
+    rob, c = _update_case_views(O, case)
+    prm = O.params(W=case["W"], max_iters=case["max_iters"], alpha=case["alpha"],
+                   lam=case["lambda"])
+    ok, xi, it, _, trace = O.parallel_project(rob, c, prm, np.asarray(case["xi_init"], float))
+    assert ok == case["ok"]
+    assert it == case.get("iters", case["max_iters"])
+    assert trace.tolist() == case["prog_trace"]
+    np.testing.assert_allclose(xi, np.asarray(case["xi_out"], float), rtol=0, atol=1e-15)
+
+
+def test_update_step_independent_variant_drops_only_the_smoothing_term(oracle_lib):
+    """The independent operator is Algorithm 1 without the smoothing term: on
+    the hand-worked yaw case the new values are xi - 0.5 * 0.8 xi = 0.6 xi."""
+    O = oracle_lib
+    case = [c for c in _update_cases() if c["robot"] == "yaw1" and c["max_iters"] == 1][0]
+    rob, c = _update_case_views(O, case)
+    prm = O.params(W=4, max_iters=1, alpha=0.5, lam=0.5, variant=O.PROJECT_INDEPENDENT)
+    _, xi, _, _ = O.project_motion(rob, c, prm, np.asarray(case["xi_init"], float))
+    np.testing.assert_allclose(xi.ravel(), [0.0, 0.06, 0.078, 0.036], rtol=0, atol=1e-15)
+
+
 # ------------------------------------------------------------------ distances
 
 def test_distances_hand_worked(oracle_lib):
