@@ -169,12 +169,17 @@ const char* cp_last_error(void);    /* thread-local; valid until the next call o
  *   d_collide  [n_cfg] 1 = collides, 0 = free
  *   d_min_sd   [n_cfg] nullable; if given, every pair is evaluated and the
  *              minimum signed distance is written
+ *   d_sphere_xyz [n_cfg][n_spheres][3] nullable; if given, the world centre
+ *              of every robot sphere (the forward kinematics the check runs),
+ *              spheres in description order, float32, written by a separate
+ *              kernel on the same stream
  *   flags      CP_NO_EARLY_EXIT: evaluate every pair even after a collision;
  *              CP_SELF_COLLISION: also the robot against itself
  * Errors: CP_E_ARG (NULL handle/pointer, n_cfg < 0), CP_E_UNSUPPORTED (dof),
  * CP_E_HIP (launch failure). n_cfg = 0 is a no-op. */
 int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const float* d_q,
-                uint8_t* d_collide, float* d_min_sd, int32_t flags, void* stream);
+                uint8_t* d_collide, float* d_min_sd, float* d_sphere_xyz, int32_t flags,
+                void* stream);
 
 /* Self-collision pairs of a robot (specified here; the paper checks the
  * robot against the environment only).  A pair of spheres (s, t) is checked

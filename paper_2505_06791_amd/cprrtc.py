@@ -117,7 +117,7 @@ def lib():
         L.cp_robot_self_pairs.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.cp_env_destroy.argtypes = [vp]
         L.cp_proj_params_default.argtypes = [C.POINTER(ProjParams)]
-        L.fk_cc_batch.argtypes = [vp, vp, C.c_int32, vp, vp, vp, C.c_int32, vp]
+        L.fk_cc_batch.argtypes = [vp, vp, C.c_int32, vp, vp, vp, vp, C.c_int32, vp]
         L.project_validate_motions.argtypes = [vp, vp, C.POINTER(Constraint), C.POINTER(ProjParams),
                                                C.c_int32, vp, vp, vp, vp, vp, vp, C.c_int32, vp]
         L.project_motions.argtypes = [vp, C.POINTER(Constraint), C.POINTER(ProjParams), C.c_int32,
@@ -275,13 +275,18 @@ def _dev(t, dtype):
 
 # ------------------------------------------------------------------ hot path
 
-def fk_cc_batch(robot: Robot, env: Env, q, collide, min_sd=None, flags: int = 0, stream=None):
-    """q: [N, dof] float32 (device); collide: [N] uint8 (device); min_sd: [N] float32 or None."""
+def fk_cc_batch(robot: Robot, env: Env, q, collide, min_sd=None, flags: int = 0, stream=None,
+                sphere_xyz=None):
+    """q: [N, dof] float32 (device); collide: [N] uint8 (device); min_sd: [N] float32 or None;
+    sphere_xyz: [N, n_spheres, 3] float32 or None (sphere centres, description order)."""
     import torch
     n = q.shape[0]
+    if sphere_xyz is not None and tuple(sphere_xyz.shape) != (n, robot.n_spheres, 3):
+        raise CprrtcError(CP_E_ARG, f"sphere_xyz must be [{n}, {robot.n_spheres}, 3]")
     _check(lib().fk_cc_batch(robot.handle, env.handle, n, _dev(q, torch.float32),
                              _dev(collide, torch.uint8),
                              _dev(min_sd, torch.float32) if min_sd is not None else None,
+                             _dev(sphere_xyz, torch.float32) if sphere_xyz is not None else None,
                              flags, _stream(stream)))
 
 

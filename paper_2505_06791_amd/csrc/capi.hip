@@ -283,8 +283,13 @@ int cp_robot_create(const cp_robot_desc* d, cp_robot** out) {
       std::memcpy(&bits, &reach2, sizeof bits);
       cc_pairs[i] = make_int2(s0 | (t0 << 16), bits);   // positions < kMaxSpheres <= 2^16
     }
+    std::vector<int2> sph_map(d->n_spheres);
+    for (int s = 0; s < d->n_spheres; ++s) sph_map[s] = make_int2(rank[s], d->sphere_link[s]);
     hipError_t e = hipMalloc((void**)&r->dev, sizeof(RobotDev));
     if (e == hipSuccess) e = hipMalloc((void**)&r->spheres, sizeof(float4) * sph.size());
+    if (e == hipSuccess) e = hipMalloc((void**)&r->sph_map, sizeof(int2) * sph_map.size());
+    if (e == hipSuccess)
+      e = hipMemcpy(r->sph_map, sph_map.data(), sizeof(int2) * sph_map.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && n_pairs > 0) e = hipMalloc((void**)&r->pairs, sizeof(int2) * n_pairs);
     if (e == hipSuccess && n_pairs > 0) e = hipMalloc((void**)&r->pairs_cc, sizeof(int2) * n_padded);
     if (e == hipSuccess) e = hipMemcpy(r->dev, &h, sizeof h, hipMemcpyHostToDevice);
@@ -312,6 +317,7 @@ void cp_robot_destroy(cp_robot* r) {
   if (r->spheres) (void)hipFree(r->spheres);
   if (r->pairs) (void)hipFree(r->pairs);
   if (r->pairs_cc) (void)hipFree(r->pairs_cc);
+  if (r->sph_map) (void)hipFree(r->sph_map);
   delete r;
 }
 
@@ -434,7 +440,8 @@ void cp_env_destroy(cp_env* env) {
 }
 
 int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const float* d_q,
-                uint8_t* d_collide, float* d_min_sd, int32_t flags, void* stream) {
+                uint8_t* d_collide, float* d_min_sd, float* d_sphere_xyz, int32_t flags,
+                void* stream) {
   try {
     if (!robot || !env) return fail(CP_E_ARG, "fk_cc_batch: NULL handle");
     if (n_cfg < 0) return fail(CP_E_ARG, "fk_cc_batch: n_cfg < 0");
@@ -444,6 +451,11 @@ int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const f
     hipError_t e = launch_fk_cc(robot->dev, robot->spheres, env->view, n_cfg, d_q, d_collide,
                                 d_min_sd, early, 8, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fk_cc_batch launch");
+    if (d_sphere_xyz) {
+      e = launch_sphere_xyz(robot->dev, robot->spheres, robot->sph_map, robot->host.n_spheres,
+                            n_cfg, d_q, d_sphere_xyz, (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "fk_cc_batch sphere centre launch");
+    }
     if (flags & CP_SELF_COLLISION) {
       e = launch_self_cc(robot->dev, robot->host, robot->spheres, robot->pairs_cc,
                          (int)robot->self_pairs.size() / 2, n_cfg, d_q, d_collide, d_min_sd, early,

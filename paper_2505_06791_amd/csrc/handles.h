@@ -34,6 +34,8 @@ struct cp_robot {
   float4* spheres = nullptr;        // device spheres, grouped by link
   int2* pairs = nullptr;            // device self-collision pairs (positions in `spheres`)
   int2* pairs_cc = nullptr;         // the same pairs as (s | t << 16, bits of (r_s + r_t)^2), padded
+  int2* sph_map = nullptr;          // device, per sphere in description order: (position in
+                                    // `spheres`, joint frame that carries it)
   std::vector<int32_t> self_pairs;  // host, description order: s0 t0 s1 t1 ...
   std::mutex rtc_lock;              // guards rtc (specialisation may run beside projections)
   std::deque<cprrtc::RtcKernel> rtc; // a deque: entries stay put as more are added

@@ -13,6 +13,11 @@ hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& en
                         const float* q, uint8_t* collide, float* min_sd, bool early, int batch,
                         hipStream_t stream);
 
+// World centres of every robot sphere of every configuration, [n_cfg][S][3]
+// in description order; map[s] = (position in sph, joint frame of sphere s).
+hipError_t launch_sphere_xyz(const RobotDev* rob, const float4* sph, const int2* map, int n_spheres,
+                             int n_cfg, const float* q, float* xyz, hipStream_t stream);
+
 // Pooled projection: slots per wavefront, whether a launch of n motions uses
 // it (pooled: 1 = always, 0 = never, -1 = by batch size), its grid size.
 constexpr int kPoolSlots = 4;

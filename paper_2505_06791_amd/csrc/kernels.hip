@@ -52,6 +52,36 @@ __global__ __launch_bounds__(kBlock) void fk_cc_kernel(const RobotDev* __restric
   }
 }
 
+// ------------------------------------------------------------------ sphere centres
+
+// One thread per (configuration, sphere): the chain's frames up to the
+// sphere's joint, then R c_local + p.  Consecutive threads write consecutive
+// 12-byte centres, so the output (the bulk of the traffic) is coalesced.
+__global__ __launch_bounds__(kBlock) void sphere_xyz_kernel(const RobotDev* __restrict__ rob,
+                                                            const float4* __restrict__ sph,
+                                                            const int2* __restrict__ map,
+                                                            int n_spheres, int64_t n_items,
+                                                            const float* __restrict__ q,
+                                                            float* __restrict__ xyz) {
+  const int dof = rob->dof;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n_items; t += stride) {
+    const int64_t i = t / n_spheres;
+    const int s = (int)(t - i * n_spheres);
+    const int2 m = map[s];
+    const int c = (rob->n_chains > 1 && m.y >= rob->chain_begin[1]) ? 1 : 0;
+    const float* qi = q + i * dof;
+    Frame T;
+    frame_from(T, rob->base[c]);
+    for (int j = rob->chain_begin[c]; j <= m.y; ++j) joint_advance(T, rob, j, qi[j]);
+    const float4 l = sph[m.x];
+    float* o = xyz + t * 3;
+    o[0] = T.r[0] * l.x + T.r[1] * l.y + T.r[2] * l.z + T.p[0];
+    o[1] = T.r[3] * l.x + T.r[4] * l.y + T.r[5] * l.z + T.p[1];
+    o[2] = T.r[6] * l.x + T.r[7] * l.y + T.r[8] * l.z + T.p[2];
+  }
+}
+
 // ------------------------------------------------------------------ projection (Algorithm 1)
 
 // One motion per W lanes (project_segment).  Writes the segment, status
@@ -353,6 +383,14 @@ hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& en
   } else {
     fk_cc_kernel<8, false><<<nb, kBlock, 0, stream>>>(rob, sph, env, n_cfg, q, collide, nullptr, early);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_sphere_xyz(const RobotDev* rob, const float4* sph, const int2* map, int n_spheres,
+                             int n_cfg, const float* q, float* xyz, hipStream_t stream) {
+  const int64_t items = (int64_t)n_cfg * n_spheres;
+  const unsigned nb = (unsigned)std::min<int64_t>(blocks_for(items), 1 << 20);   // grid-stride beyond
+  sphere_xyz_kernel<<<nb, kBlock, 0, stream>>>(rob, sph, map, n_spheres, items, q, xyz);
   return hipGetLastError();
 }
 

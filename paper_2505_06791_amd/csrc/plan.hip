@@ -413,6 +413,11 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
     he = launch_project_configs(n, robot->dev, con, 2, pl->cfg, pl->cfg_out, pl->cfg_status,
                                 (float)pp.tau_task, 0, 1.0f, 0.0f, st, &sup);
     if (he == hipSuccess) he = launch_fk_cc(robot->dev, robot->spheres, env->view, 2, pl->cfg, pl->cfg_col, pl->cfg_sd, false, 4, st);
+    // with the self-check on, an endpoint must also be clear of the robot itself
+    const int n_self = (int)robot->self_pairs.size() / 2;
+    if (he == hipSuccess && (o.flags & CP_SELF_COLLISION) && n_self > 0)
+      he = launch_self_cc(robot->dev, robot->host, robot->spheres, robot->pairs_cc, n_self, 2,
+                          pl->cfg, pl->cfg_col, pl->cfg_sd, false, st);
     int ok_h[2];
     float sd_h[2];
     if (he == hipSuccess) he = hipMemcpyAsync(ok_h, pl->cfg_status, sizeof ok_h, hipMemcpyDeviceToHost, st);
@@ -422,8 +427,8 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
     if (!sup) return api_fail(CP_E_UNSUPPORTED, "no kernel for dof %d with constraint kind %d", n, con.kind);
     if (!ok_h[0]) return api_fail(CP_E_START, "start is off the constraint manifold");
     if (!ok_h[1]) return api_fail(CP_E_GOAL, "goal is off the constraint manifold");
-    if (!(sd_h[0] > 0.0f)) return api_fail(CP_E_START, "start is in collision");
-    if (!(sd_h[1] > 0.0f)) return api_fail(CP_E_GOAL, "goal is in collision");
+    if (!(sd_h[0] > 0.0f)) return api_fail(CP_E_START, "start is in collision (scene or, with CP_SELF_COLLISION, the robot itself)");
+    if (!(sd_h[1] > 0.0f)) return api_fail(CP_E_GOAL, "goal is in collision (scene or, with CP_SELF_COLLISION, the robot itself)");
 
     const double tol = pp.tau + pp.tau_sm;
     double dsg = 0.0;

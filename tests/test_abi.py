@@ -47,7 +47,7 @@ def test_null_arguments_are_rejected_without_device_work(lib):
     assert lib.cp_robot_create(None, C.byref(out)) == -1
     assert b"NULL" in lib.cp_last_error()
     assert lib.cp_env_create(None, C.byref(out)) == -1
-    assert lib.fk_cc_batch(None, None, 10, None, None, None, 0, None) == -1
+    assert lib.fk_cc_batch(None, None, 10, None, None, None, None, 0, None) == -1
     assert lib.project_validate_motions(None, None, None, None, 1, None, None, None, None, None,
                                         None, 0, None) == -1
     assert lib.project_configs(None, None, 1, None, None, None, C.c_double(1e-5), 10,

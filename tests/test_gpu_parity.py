@@ -66,6 +66,30 @@ def test_fk_cc_batch_matches_oracle(G, name, n):
     assert np.abs(sd_g.astype(np.float64) - sd_o).max() < 1e-5
 
 
+@pytest.mark.parametrize("name,n", [("plain", 257), ("cluttered", 130), ("mobile", 64),
+                                    ("dual", 65)])
+def test_fk_cc_batch_sphere_centres_match_oracle(G, name, n):
+    """d_sphere_xyz: every sphere's world centre, in description order, equals
+    the FP64 forward kinematics of the same float32 configuration within
+    1e-5 m; the verdicts are those of the call without it."""
+    w = I.workload(name, 2000 + n)
+    rd = w["robot"]
+    q32 = I.random_configs(rd, n, 6).astype(np.float32)
+    ro, _, _ = oracle_views(w)
+    robot, env = G.Robot(rd), G.Env(w["env"])
+    q = torch.from_numpy(q32).to(DEV)
+    col = torch.empty(n, dtype=torch.uint8, device=DEV)
+    xyz = torch.full((n, robot.n_spheres, 3), float("nan"), dtype=torch.float32, device=DEV)
+    G.fk_cc_batch(robot, env, q, col, sphere_xyz=xyz)
+    torch.cuda.synchronize()
+    ref = np.stack([O.sphere_centres(ro, x.astype(np.float64)) for x in q32])
+    err = np.abs(xyz.cpu().numpy().astype(np.float64) - ref).max()
+    _report("sphere_xyz", workload=name, n=n, max_err=f"{err:.2e}")
+    assert err < 1e-5
+    col_plain, _ = _gpu_fkcc(G, w, q32)
+    assert np.array_equal(col.cpu().numpy(), col_plain)
+
+
 def test_fk_cc_tiny_scene_by_hand(G):
     """One joint about world z carrying one sphere 0.5 m out at height 0.2;
     a cube of half extent 0.1 centred at (0, 0.8, 0.2): at q = pi/2 the gap is

@@ -154,6 +154,32 @@ def test_planner_with_self_collision(G, name, seeds):
     assert solved >= 1 or name != "plain"
 
 
+def test_planner_rejects_self_colliding_endpoints(G):
+    """With CP_SELF_COLLISION an endpoint that collides with the robot itself
+    (by the oracle, beyond the band) is refused as CP_E_START / CP_E_GOAL;
+    without the flag the same query is accepted (empty scene, no task
+    constraint, so the scene and the manifold accept every endpoint)."""
+    w = I.workload("plain", 1003)
+    ro = O.Robot(w["robot"])
+    pairs = O.self_pairs(ro)
+    sd = [(O.self_min_sd(ro, q, pairs), q) for q in I.random_configs(w["robot"], 400, 17)]
+    hit = [q for s, q in sd if s < -1e-2]
+    free = [q for s, q in sd if s > 1e-2]
+    assert hit and len(free) >= 2, "no self-colliding / free configurations drawn"
+    robot, env = G.Robot(w["robot"]), G.Env(I.empty_env())
+    con = G.constraint(I.no_constraint())
+    pl_self = G.Planner(robot, G.plan_opts(n_groups=64, max_rounds=2, flags=G.SELF_COLLISION))
+    pl_plain = G.Planner(robot, G.plan_opts(n_groups=64, max_rounds=2))
+    for start, goal, code in ((hit[0], free[0], G.CP_E_START), (free[0], hit[0], G.CP_E_GOAL)):
+        with pytest.raises(G.CprrtcError) as e:
+            pl_self.plan(env, con, start, goal, 1)
+        assert e.value.code == code
+        rc, _, _ = pl_plain.plan(env, con, start, goal, 1)
+        assert rc in (G.CP_OK, G.CP_NO_SOLUTION)
+    rc, _, _ = pl_self.plan(env, con, free[0], free[1], 1)
+    assert rc in (G.CP_OK, G.CP_NO_SOLUTION)
+
+
 def test_planner_self_collision_flag_checked(G):
     w = I.workload("plain", 1000)
     robot = G.Robot(w["robot"])
