@@ -5,9 +5,13 @@ Bars: the forward pass equals a float32 reference that rounds at the same
 points (BF16 input, weights and hidden activations; FP32 bias, accumulation
 and output) to 1e-2 of the output range (an activation may round to the
 neighbouring BF16 value: 2^-8 relative; a wrong operand layout errs by
-O(1)); gradients agree with the FP64 oracle evaluated
-at the same BF16-rounded weights and inputs to 2e-2 relative (norm per
-tensor; the GPU also rounds activations and back-propagated errors to BF16).
+O(1)); gradients agree element by element with the FP64 oracle evaluated at
+the same BF16-rounded weights and inputs: |g - g_oracle| <= 1e-2 max|g_oracle|
++ 2e-2 |g_oracle| per tensor.  The GPU also rounds hidden activations and
+back-propagated errors to BF16; emulating those roundings in float32 against
+the FP64 oracle gives at most 4.1e-3 of the tensor's maximum (five random
+13 -> 3 x 256 -> 7 networks), so the bar has a 2.4x margin, and a swapped,
+transposed or sign-flipped term errs by O(1) of the maximum.
 """
 import numpy as np
 import pytest
@@ -70,12 +74,15 @@ def test_forward_matches_reference(G, dims_hidden):
         assert err < 1e-2, (M, err)
 
 
-def test_gradients_match_fp64_oracle(G):
-    net = G.MLP(13, 256, 3, 7, seed=4)
+@pytest.mark.parametrize("dims_hidden,M", [((13, 256, 3, 7), 96), ((26, 512, 3, 14), 300),
+                                           ((5, 64, 2, 3), 1000)])
+def test_gradients_match_fp64_oracle(G, dims_hidden, M):
+    n_in, hid, nh, n_out = dims_hidden
+    net = G.MLP(n_in, hid, nh, n_out, seed=4)
     g = torch.Generator(device=DEV)
     g.manual_seed(1)
-    x = torch.randn((96, 13), generator=g, device=DEV)
-    t = torch.randn((96, 7), generator=g, device=DEV) * 0.3
+    x = torch.randn((M, n_in), generator=g, device=DEV)
+    t = torch.randn((M, n_out), generator=g, device=DEV) * 0.3
     grad, loss = net.gradients(x, t)
     # oracle at the BF16-rounded weights the matrix cores used, FP32 biases
     p = net.get_params()
@@ -90,13 +97,19 @@ def test_gradients_match_fp64_oracle(G):
     gg = grad.cpu().double().numpy()
     assert abs(loss.item() - loss_o) <= 2e-2 * loss_o
     off = 0
+    worst = 0.0
     for l in range(len(net.dims) - 1):
         k, n = net.dims[l], net.dims[l + 1]
-        for sl in (slice(off, off + n * k), slice(off + n * k, off + n * k + n)):
+        for what, sl in (("W", slice(off, off + n * k)), ("b", slice(off + n * k, off + n * k + n))):
             a, b = gg[sl], grad_o[sl]
-            rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
-            assert rel < 2e-2, (l, rel)
+            scale = np.abs(b).max()
+            assert scale > 0, (l, what)
+            excess = np.abs(a - b) - (1e-2 * scale + 2e-2 * np.abs(b))
+            worst = max(worst, float((np.abs(a - b) / scale).max()))
+            assert np.all(excess <= 0), (l, what, int(np.argmax(excess)), float(excess.max()))
         off += n * k + n
+    print("gradients", dims_hidden, "M", M, "max |g - g_oracle| / max|g_oracle|", f"{worst:.2e}",
+          flush=True)
 
 
 def test_training_reduces_the_loss(G):

@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 
 import oracle as O
 from paper_2505_06791_amd import inputs as I
-from tests.helpers import manifold_starts, motion_set, oracle_views
+from tests.helpers import ORACLE_THREADS, manifold_starts, motion_set, oracle_views
 from tests.test_gpu_parity import _compare_pv
 from tests.test_gpu_plan import _check_path
 
@@ -38,6 +38,8 @@ def _workload(name):
         w = dict(I.workload("plain", 2401))
         w["constraint"] = I.no_constraint()
         return w
+    if name == "dual-free":   # the relative-pose workload in an empty scene
+        return dict(I.workload("dual", 2400), env=I.empty_env())
     return I.workload(name, 2400)
 
 
@@ -55,14 +57,15 @@ def _run(G, robot, env, con, w, q_from, q_to, kw, flags):
 def _oracle(w, q_from, q_to, kw):
     ro, eo, co = oracle_views(w)
     return O.project_validate_motions(ro, eo, co, O.params(**kw), q_from.astype(np.float64),
-                                      q_to.astype(np.float64), n_threads=8)
+                                      q_to.astype(np.float64), n_threads=ORACLE_THREADS)
 
 
-@pytest.mark.parametrize("name,W", [("plain", 64), ("cluttered", 64), ("mobile", 32),
-                                    ("dual", 64), ("line", 64), ("none", 64)])
-def test_specialised_kernel_equals_library_kernel(G, name, W):
+@pytest.mark.parametrize("name,W,M,least", [("plain", 64, 48, 10), ("cluttered", 64, 48, 10),
+                                            ("mobile", 32, 48, 10), ("dual-free", 64, 2400, 100),
+                                            ("line", 64, 48, 10), ("none", 64, 48, 10)])
+def test_specialised_kernel_equals_library_kernel(G, name, W, M, least):
     w = _workload(name)
-    q_from, q_to = motion_set(w, 48, 29, W=W)
+    q_from, q_to = motion_set(w, M, 29, W=W)
     robot, env, con = G.Robot(w["robot"]), G.Env(w["env"]), G.constraint(w["constraint"])
     ms = robot.specialize(con)
     assert ms > 0
@@ -73,7 +76,8 @@ def test_specialised_kernel_equals_library_kernel(G, name, W):
     print(name, "compile ms", round(ms, 1), "statuses", np.bincount(st_s, minlength=3), flush=True)
     ref = _oracle(w, q_from, q_to, kw)
     _agree(ref, (xi_s, st_s, it_s), (xi_g, st_g, it_g))
-    _compare_pv(f"{name} specialised", ref, xi_s, st_s, it_s, w, W, w["tau_task"])
+    _compare_pv(f"{name} specialised", ref, xi_s, st_s, it_s, w, W, w["tau_task"],
+                min_compared=least)
 
 
 def _agree(ref, a, b):
@@ -179,9 +183,18 @@ def test_full_size_sampled_specialised(G):
     ref = _oracle_pv(w, q_from[idx], q_to[idx], 64, w["tau_task"])
     _compare_pv("cluttered-full specialised", ref, xi[idx], st[idx], it[idx], w, 64,
                 w["tau_task"])
-    # the library kernels on the same launch: the same verdicts outside the band
+    # the library kernels on the same launch: every motion whose status or
+    # iteration count differs between the two is recomputed by the oracle and
+    # must be in the band (a decision within 1e-5 of its threshold, or a
+    # minimum signed distance within 1e-5 m of 0)
     xi_g, st_g, it_g = _run(G, robot, env, con, w, q_from, q_to, kw, G.GENERIC)
     assert set(np.unique(st)).issubset({0, 1, 2})
+    diff = np.nonzero((st != st_g) | (it != it_g))[0]
     print("statuses specialised", np.bincount(st, minlength=3), "library",
-          np.bincount(st_g, minlength=3), flush=True)
-    assert np.abs(np.bincount(st, minlength=3) - np.bincount(st_g, minlength=3)).max() <= 0.01 * M
+          np.bincount(st_g, minlength=3), "differing motions", len(diff), flush=True)
+    if len(diff):
+        ref_d = _oracle_pv(w, q_from[diff], q_to[diff], 64, w["tau_task"])
+        in_band = (ref_d["proj_margin"] < 1e-5) | (np.abs(ref_d["min_sd"]) < 1e-5)
+        proj_band = ref_d["proj_margin"] < 1e-5
+        assert np.all(in_band), diff[~in_band]
+        assert np.all(proj_band | (it[diff] == it_g[diff])), diff[~proj_band]

@@ -132,6 +132,36 @@ def test_task_jacobian_matches_central_differences(oracle_lib, name, con):
         assert np.abs(J - Jfd).max() < 1e-6 * scale
 
 
+def test_relative_pose_error_by_hand(oracle_lib):
+    """Two one-joint arms (joints about their base z axes, no offsets, tools
+    at the joint origin): chain 0 at the world origin, chain 1's base at
+    (0, g, 0) turned by pi about x, the target pose of tool 2 in tool 1 is
+    (R* = diag(1, -1, -1), p* = (0, g, 0)).  Worked by hand:
+      q = (0, 0):   p' = (0, g, 0), R' = R*              -> e = 0;
+      q = (t, 0):   p' = Rz(t)^T (0, g, 0) = (g sin t, g cos t, 0),
+                    R*^T R' = Rx(pi) Rz(-t) Rx(pi) = Rz(t) -> e = (g sin t, g (cos t - 1), 0, 0, 0, t);
+      q = (0, f):   p' unchanged, R*^T R' = Rz(f)         -> e = (0, 0, 0, 0, 0, f)."""
+    O = oracle_lib
+    g = 0.3
+    base1 = np.eye(4)
+    base1[:3, :3] = np.diag([1.0, -1.0, -1.0])
+    base1[:3, 3] = (0.0, g, 0.0)
+    rd = dict(dof=2, n_chains=2, joint_type=np.zeros(2, np.int32),
+              joint_chain=np.array([0, 1], np.int32), alpha=np.zeros(2), a=np.zeros(2),
+              d=np.zeros(2), theta=np.zeros(2), lo=np.full(2, -2.8), hi=np.full(2, 2.8),
+              base=np.stack([np.eye(4), base1]), tool=np.stack([np.eye(4), np.eye(4)]),
+              sphere_link=np.zeros(1, np.int32), sphere=np.array([[0, 0, 0, 0.05]]))
+    rob, c = O.Robot(rd), O.Constraint(I.relative_pose(g))
+    np.testing.assert_allclose(O.task_error(rob, c, np.array([0.0, 0.0])), np.zeros(6), atol=1e-15)
+    for t in (0.1, -0.7, 2.0):
+        np.testing.assert_allclose(O.task_error(rob, c, np.array([t, 0.0])),
+                                   [g * math.sin(t), g * (math.cos(t) - 1.0), 0, 0, 0, t],
+                                   atol=1e-14)
+    for f in (0.25, -1.3):
+        np.testing.assert_allclose(O.task_error(rob, c, np.array([0.0, f])), [0, 0, 0, 0, 0, f],
+                                   atol=1e-14)
+
+
 def test_position_columns_orthogonal_to_revolute_axes(oracle_lib):
     """With the position rows only, column i is z_i x (p_ee - p_i): orthogonal to z_i."""
     O = oracle_lib
