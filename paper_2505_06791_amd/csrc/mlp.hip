@@ -21,6 +21,7 @@
 #include <cstring>
 #include <new>
 #include <random>
+#include <type_traits>
 #include <vector>
 
 #include "cprrtc.h"
@@ -42,6 +43,11 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 __device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU with the hardware reciprocal (about 1 ulp) instead of a correctly
+// rounded division; the result is rounded to BF16 right after.
+__device__ __forceinline__ float silu_fast(float z) {
+  return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
 __device__ __forceinline__ float silu_grad(float z) {
   const float s = 1.0f / (1.0f + __expf(-z));
   return s * (1.0f + z * (1.0f - s));
@@ -261,6 +267,334 @@ __global__ void refresh_bf16_kernel(const float* __restrict__ w, uint16_t* __res
   if (i < n) wb[i] = to_bf16(w[i]);
 }
 
+// ------------------------------------------------------------------ fused network
+//
+// The whole network for a tile of samples in one workgroup, activations in
+// registers.  Each layer is computed transposed, H_next^T = W H^T: the
+// weights are the MFMA's A operand (16 output units x 32 inputs), the
+// activations its B operand (32 inputs x 16 samples), so the result tile
+// leaves each lane with 4 output units (4g .. 4g+3, g = lane / 16) of one
+// sample (lane % 16).  Two result tiles (units 32c .. 32c+15 and
+// 32c+16 .. 32c+31) hold, in the same lane, exactly the 8 inputs that lane
+// supplies to the next layer's B operand for reduction chunk c, provided the
+// next layer's weights list their inputs in the matching order: B slot i of
+// lane group g is input 32c + 4g + i (i < 4) or 32c + 16 + 4g + (i - 4).  The
+// weights are stored once in that order (fused_weights_kernel), chunk by
+// chunk in the order they are used, so no activation ever leaves the
+// registers and no lane exchange is needed between layers.
+//
+// Workgroup: 8 wavefronts; wavefront w takes samples 16 ST w .. 16 ST (w+1)
+// - 1 of the tile (ST tiles of 16 samples; ST = 512 / H from width 128 up
+// keeps the register footprint the same for every width: H/2 accumulators
+// and H/4 activation registers).  The weight chunks (layer rows x 32 inputs, BF16)
+// stream through LDS double-buffered: the next chunk's global loads are in
+// flight while the current one feeds the MFMAs, and every A fragment read
+// from LDS serves ST MFMAs.  Layer 0 reads the sample features (first
+// layer inputs padded to 32); the last layer has at most 16 outputs.
+
+constexpr int kFusedWaves = 8;
+constexpr int kFusedMaxLayers = 9;   // at most 8 hidden layers and the output layer
+constexpr int kFusedLdw = 40;   // LDS row of a weight chunk: 32 inputs + 8 padding (BF16)
+
+// The network as the fused kernel reads it.
+struct FusedNet {
+  const uint16_t* wf;   // weight chunks, see fused_weights_kernel
+  const float* bias;    // [n_layers][H] fp32, zero past a layer's width
+  int n_in, n_out, n_hidden;
+};
+
+// Position -> input index inside a 32-input chunk of a hidden-input layer.
+__host__ __device__ __forceinline__ int fused_perm(int p) {
+  const int g = p >> 3, i = p & 7;
+  return i < 4 ? 4 * g + i : 16 + 4 * g + (i - 4);
+}
+
+// Builds the fused weight chunks from the FP32 masters.  Chunk order:
+// layer 0 (H rows x 32 inputs, inputs in natural order, zero past n_in),
+// then for each hidden-to-hidden layer its H/32 chunks (H rows), then the
+// last layer's H/32 chunks (16 rows, zero past n_out); a chunk is row-major
+// [rows][32], inputs in fused_perm order for every layer but the first.
+__global__ void fused_weights_kernel(const float* __restrict__ w, int H, int n_in, int n_out,
+                                     int n_hidden, long w_off0, long w_off_h, long w_stride_h,
+                                     long w_off_last, uint16_t* __restrict__ wf, long n_wf) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_wf) return;
+  const int KC = H / 32;
+  const long first = (long)H * 32;
+  const long hid = (long)(n_hidden - 1) * KC * H * 32;
+  float v = 0.0f;
+  if (e < first) {
+    const int n = (int)(e / 32), k = (int)(e % 32);
+    if (k < n_in) v = w[w_off0 + (long)n * n_in + k];
+  } else if (e < first + hid) {
+    const long r = e - first;
+    const long per_layer = (long)KC * H * 32;
+    const int l = (int)(r / per_layer);
+    const long rr = r % per_layer;
+    const int kc = (int)(rr / ((long)H * 32));
+    const int n = (int)((rr / 32) % H), p = (int)(rr % 32);
+    v = w[w_off_h + l * w_stride_h + (long)n * H + kc * 32 + fused_perm(p)];
+  } else {
+    const long r = e - first - hid;
+    const int kc = (int)(r / (16 * 32));
+    const int n = (int)((r / 32) % 16), p = (int)(r % 32);
+    if (n < n_out) v = w[w_off_last + (long)n * H + kc * 32 + fused_perm(p)];
+  }
+  wf[e] = to_bf16(v);
+}
+
+__global__ void fused_bias_kernel(const float* __restrict__ w, const long* __restrict__ b_off,
+                                  const int* __restrict__ width, int n_layers, int H,
+                                  float* __restrict__ bias) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_layers * H) return;
+  const int l = i / H, n = i % H;
+  bias[i] = n < width[l] ? w[b_off[l] + n] : 0.0f;
+}
+
+// Sample features from a row-major matrix x[row][ld] (n_in columns).
+struct FeatRows {
+  const float* x;
+  long ld;
+  __device__ __forceinline__ void load(long s, int k0, int n_in, float (&f)[8]) const {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f[i] = (k0 + i < n_in) ? x[s * ld + k0 + i] : 0.0f;
+  }
+};
+
+// Warm-start features computed in place: row s is waypoint k = s % (W-1) + 1
+// of motion s / (W-1); features = the straight-line waypoint over the joint
+// range, then the constraint parameters.
+struct FeatWarm {
+  const float* q_from;
+  const float* q_to;
+  int W, dof, n_cp;
+  float range[kMaxDof];
+  float cp[12];
+  __device__ __forceinline__ void load(long s, int k0, int n_in, float (&f)[8]) const {
+    const long m = s / (W - 1);
+    const int k = (int)(s % (W - 1)) + 1;
+    const float t = (float)k / (float)(W - 1);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int c = k0 + i;
+      float v = 0.0f;
+      if (c < dof) {
+        const float a = q_from[m * dof + c], b = q_to[m * dof + c];
+        v = (a + t * (b - a)) / range[c];
+      } else if (c < dof + n_cp) {
+        v = cp[c - dof];
+      }
+      f[i] = v;
+    }
+  }
+};
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  return (uint32_t)to_bf16(lo) | ((uint32_t)to_bf16(hi) << 16);
+}
+
+// Registers holding one weight chunk on its way from global memory to LDS.
+template <int PRE>
+struct ChunkRegs {
+  uint4 v[PRE];
+};
+
+// Global -> register -> LDS moves of weight chunk q (16-byte pieces, piece
+// p of a chunk = row p / 4, inputs 8 (p % 4) .. +7).
+template <int H, int PRE>
+struct ChunkStream {
+  const uint16_t* wf;
+  int q_last, tid;
+  __device__ __forceinline__ int pieces(int q) const { return (q < q_last ? H : 16) * 4; }
+  __device__ __forceinline__ ChunkRegs<PRE> fetch(int q) const {
+    const long off = q < q_last ? (long)q * H * 32 : (long)q_last * H * 32 + (long)(q - q_last) * 16 * 32;
+    const int n = pieces(q);
+    ChunkRegs<PRE> r;
+#pragma unroll
+    for (int i = 0; i < PRE; ++i) {
+      const int p = tid + i * kFusedWaves * 64;
+      r.v[i] = p < n ? *reinterpret_cast<const uint4*>(wf + off + (long)p * 8) : uint4{0, 0, 0, 0};
+    }
+    return r;
+  }
+  __device__ __forceinline__ void put(int q, const ChunkRegs<PRE>& r, uint16_t* dst) const {
+    const int n = pieces(q);
+#pragma unroll
+    for (int i = 0; i < PRE; ++i) {
+      const int p = tid + i * kFusedWaves * 64;
+      if (p < n) *reinterpret_cast<uint4*>(dst + (p >> 2) * kFusedLdw + (p & 3) * 8) = r.v[i];
+    }
+  }
+};
+
+template <int H, int ST, class F>
+__global__ __launch_bounds__(512) void mlp_fused_kernel(FusedNet net, F feat, long M,
+                                                        float* __restrict__ y, long ldy) {
+  constexpr int KC = H / 32;       // reduction chunks of a hidden-input layer
+  constexpr int NT = H / 16;       // result tiles of a hidden layer
+  constexpr int ROWS = H * 4;      // 16-byte pieces of a full chunk
+  constexpr int PRE = (ROWS + kFusedWaves * 64 - 1) / (kFusedWaves * 64);
+  __shared__ __align__(16) uint16_t wl[2][H * kFusedLdw];
+  __shared__ float bias_s[kFusedMaxLayers * H];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < (net.n_hidden + 1) * H; i += kFusedWaves * 64) bias_s[i] = net.bias[i];
+  const int r = lane & 15, g = lane >> 4;
+  const long s0 = ((long)blockIdx.x * kFusedWaves + wave) * (16 * ST);
+  const int nq = 1 + (net.n_hidden - 1) * KC + KC;
+  const int q_last = 1 + (net.n_hidden - 1) * KC;   // first chunk of the last layer
+
+  // Chunk q sits in LDS buffer q & 1 while it is used; chunk q + 1 is in
+  // the register set (q + 1) & 1 (pre0 / pre1), loaded during the use of
+  // chunk q - 1, and goes to LDS after chunk q; chunk q + 2's loads are
+  // issued before chunk q is used.  Every layer but the first has an even
+  // number of chunks and starts at an odd q, so the set of a chunk is known
+  // at compile time.
+  const ChunkStream<H, PRE> cs{net.wf, q_last, tid};
+  ChunkRegs<PRE> pre0 = cs.fetch(0), pre1;
+  if (nq > 1) pre1 = cs.fetch(1);
+  cs.put(0, pre0, wl[0]);
+  __syncthreads();
+  int q = 0;
+  // per chunk (parity PAR = q & 1): issue chunk q + 2's loads, use chunk q,
+  // store chunk q + 1, wait for every wavefront
+#define FUSED_BEGIN(PAR)                                   \
+  if (q + 2 < nq) {                                        \
+    if (PAR == 0) pre0 = cs.fetch(q + 2);                  \
+    else pre1 = cs.fetch(q + 2);                           \
+  }
+#define FUSED_END(PAR)                                                   \
+  if (q + 1 < nq) cs.put(q + 1, PAR == 0 ? pre1 : pre0, wl[(q + 1) & 1]); \
+  __syncthreads();                                                       \
+  ++q;
+  auto afrag = [&](int row) {
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&wl[q & 1][row * kFusedLdw + 8 * g]));
+  };
+
+  // layer 0: features of this lane's samples, inputs 8g .. 8g+7
+  bf16x8 xin[ST];
+#pragma unroll
+  for (int st = 0; st < ST; ++st) {
+    const long s = s0 + st * 16 + r;
+    float f[8];
+    if (s < M) {
+      feat.load(s, 8 * g, net.n_in, f);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) f[i] = 0.0f;
+    }
+    const uint4 u{pack_bf16(f[0], f[1]), pack_bf16(f[2], f[3]), pack_bf16(f[4], f[5]), pack_bf16(f[6], f[7])};
+    xin[st] = __builtin_bit_cast(bf16x8, u);
+  }
+  f32x4 acc[NT][ST];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+    for (int st = 0; st < ST; ++st) acc[nt][st] = f32x4{0.f, 0.f, 0.f, 0.f};
+  FUSED_BEGIN(0)
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const bf16x8 a = afrag(nt * 16 + r);
+#pragma unroll
+    for (int st = 0; st < ST; ++st)
+      acc[nt][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, xin[st], acc[nt][st], 0, 0, 0);
+  }
+  FUSED_END(0)
+
+  // bias + SiLU, then BF16 into the next layer's B operand (see above)
+  bf16x8 act[KC][ST];
+  auto epilogue = [&](int l) {
+    const float* b = bias_s + l * H;
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      float b0[4], b1[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        b0[t] = b[32 * c + 4 * g + t];
+        b1[t] = b[32 * c + 16 + 4 * g + t];
+      }
+#pragma unroll
+      for (int st = 0; st < ST; ++st) {
+        const f32x4 lo = acc[2 * c][st], hi = acc[2 * c + 1][st];
+        const uint4 u{pack_bf16(silu_fast(lo[0] + b0[0]), silu_fast(lo[1] + b0[1])),
+                      pack_bf16(silu_fast(lo[2] + b0[2]), silu_fast(lo[3] + b0[3])),
+                      pack_bf16(silu_fast(hi[0] + b1[0]), silu_fast(hi[1] + b1[1])),
+                      pack_bf16(silu_fast(hi[2] + b1[2]), silu_fast(hi[3] + b1[3]))};
+        act[c][st] = __builtin_bit_cast(bf16x8, u);
+      }
+    }
+  };
+  epilogue(0);
+
+  // hidden-to-hidden layers
+  for (int l = 1; l < net.n_hidden; ++l) {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int st = 0; st < ST; ++st) acc[nt][st] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // chunks in pairs: q odd, then even
+#pragma unroll
+    for (int kc = 0; kc < KC; kc += 2) {
+      FUSED_BEGIN(1)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const bf16x8 a = afrag(nt * 16 + r);
+#pragma unroll
+        for (int st = 0; st < ST; ++st)
+          acc[nt][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kc][st], acc[nt][st], 0, 0, 0);
+      }
+      FUSED_END(1)
+      FUSED_BEGIN(0)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const bf16x8 a = afrag(nt * 16 + r);
+#pragma unroll
+        for (int st = 0; st < ST; ++st)
+          acc[nt][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kc + 1][st], acc[nt][st], 0, 0, 0);
+      }
+      FUSED_END(0)
+    }
+    epilogue(l);
+  }
+
+  // last layer: at most 16 outputs, bias, no activation
+  f32x4 out[ST];
+#pragma unroll
+  for (int st = 0; st < ST; ++st) out[st] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kc = 0; kc < KC; kc += 2) {
+    FUSED_BEGIN(1)
+    {
+      const bf16x8 a = afrag(r);
+#pragma unroll
+      for (int st = 0; st < ST; ++st)
+        out[st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kc][st], out[st], 0, 0, 0);
+    }
+    FUSED_END(1)
+    FUSED_BEGIN(0)
+    {
+      const bf16x8 a = afrag(r);
+#pragma unroll
+      for (int st = 0; st < ST; ++st)
+        out[st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kc + 1][st], out[st], 0, 0, 0);
+    }
+    FUSED_END(0)
+  }
+  const float* bl = bias_s + net.n_hidden * H;
+#pragma unroll
+  for (int st = 0; st < ST; ++st) {
+    const long s = s0 + st * 16 + r;
+    if (s >= M) continue;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int n = 4 * g + t;
+      if (n < net.n_out) y[s * ldy + n] = out[st][t] + bl[n];
+    }
+  }
+#undef FUSED_BEGIN
+#undef FUSED_END
+}
+
 }  // namespace cprrtc
 
 using namespace cprrtc;
@@ -298,6 +632,14 @@ struct cp_mlp {
   float* feat = nullptr;                      // warm start: [rows][n_in] features
   float* delta = nullptr;                     // warm start: [rows][n_out] corrections
   long warm_rows = 0;
+  // fused network (mlp_fused_kernel): BF16 weight chunks and padded biases,
+  // rebuilt from the masters whenever they change
+  bool fusable = false;
+  uint16_t* wf = nullptr;
+  long n_wf = 0;
+  float* bias_f = nullptr;
+  long* d_b_off = nullptr;
+  int* d_width = nullptr;
 };
 
 namespace {
@@ -441,6 +783,52 @@ hipError_t backward(cp_mlp* n, long M, const float* t, hipStream_t st) {
   return hipGetLastError();
 }
 
+// The fused kernel covers hidden widths 64 .. 512 (powers of two), at most
+// 32 inputs and 16 outputs.
+bool fusable(int n_in, int hidden, int n_out) {
+  return n_in <= 32 && n_out <= 16 && (hidden == 64 || hidden == 128 || hidden == 256 || hidden == 512);
+}
+
+long fused_weight_count(const cp_mlp* n) {
+  const int H = n->hidden;
+  return (long)H * 32 + (long)(n->n_hidden - 1) * H * H + (long)H / 32 * 16 * 32;
+}
+
+// Rebuilds the fused weight chunks and biases from the FP32 masters.
+hipError_t refresh_fused(cp_mlp* n, hipStream_t st) {
+  if (!n->fusable) return hipSuccess;
+  const long w_off_h = n->n_hidden > 1 ? n->w_off[1] : 0;
+  const long w_stride_h = n->n_hidden > 2 ? n->w_off[2] - n->w_off[1] : 0;
+  fused_weights_kernel<<<nblk(n->n_wf), 256, 0, st>>>(n->w, n->hidden, n->n_in, n->n_out, n->n_hidden,
+                                                      n->w_off[0], w_off_h, w_stride_h,
+                                                      n->w_off[n->n_hidden], n->wf, n->n_wf);
+  fused_bias_kernel<<<nblk((long)n->n_layers * n->hidden), 256, 0, st>>>(
+      n->w, n->d_b_off, n->d_width, n->n_layers, n->hidden, n->bias_f);
+  return hipGetLastError();
+}
+
+template <int H, class F>
+void launch_fused_h(const cp_mlp* n, const F& feat, long M, float* y, long ldy, hipStream_t st) {
+  constexpr int ST = H >= 128 ? 512 / H : 4;
+  const long per = (long)kFusedWaves * 16 * ST;
+  const unsigned blocks = (unsigned)((M + per - 1) / per);
+  FusedNet net{n->wf, n->bias_f, n->n_in, n->n_out, n->n_hidden};
+  mlp_fused_kernel<H, ST, F><<<blocks, kFusedWaves * 64, 0, st>>>(net, feat, M, y, ldy);
+}
+
+// y[M][ldy] (first n_out columns) = network(features) in one launch.
+template <class F>
+hipError_t infer_fused(const cp_mlp* n, const F& feat, long M, float* y, long ldy, hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  switch (n->hidden) {
+    case 64: launch_fused_h<64>(n, feat, M, y, ldy, st); break;
+    case 128: launch_fused_h<128>(n, feat, M, y, ldy, st); break;
+    case 256: launch_fused_h<256>(n, feat, M, y, ldy, st); break;
+    default: launch_fused_h<512>(n, feat, M, y, ldy, st); break;
+  }
+  return hipGetLastError();
+}
+
 constexpr long kInferChunk = 1L << 19;   // rows per inference chunk
 
 hipError_t ensure_infer(cp_mlp* n) {
@@ -456,8 +844,10 @@ hipError_t ensure_infer(cp_mlp* n) {
   return e;
 }
 
-// y[M][n_out] = network(x[M][n_in]), in chunks of kInferChunk rows.
+// y[M][n_out] = network(x[M][n_in]): one fused launch when the shape allows,
+// else layer by layer in chunks of kInferChunk rows.
 hipError_t infer(cp_mlp* n, long M, const float* x, float* y, hipStream_t st) {
+  if (n->fusable) return infer_fused(n, FeatRows{x, n->n_in}, M, y, n->n_out, st);
   hipError_t e = ensure_infer(n);
   const int ip = in_pad(n), op = out_pad(n, n->n_layers - 1);
   for (long r0 = 0; r0 < M && e == hipSuccess; r0 += kInferChunk) {
@@ -516,6 +906,67 @@ namespace cprrtc {
 int warm_inputs(int dof, int kind) { return dof + (kind == KIND_REL ? 12 : 6); }
 }  // namespace cprrtc
 
+namespace {
+
+// Constraint parameters given to the network (pose: the locked targets;
+// relative pose: p* and R* row-major); returns their count.
+int warm_params(const ConDev& con, float (&cp)[12]) {
+  for (float& v : cp) v = 0.0f;
+  if (con.kind == KIND_REL) {
+    for (int i = 0; i < 3; ++i) cp[i] = con.target[i];
+    for (int i = 0; i < 3; ++i)
+      for (int c = 0; c < 3; ++c) cp[3 + 3 * i + c] = con.Rt[3 * c + i];   // R* row-major
+    return 12;
+  }
+  if (con.kind == KIND_POSE)
+    for (int i = 0; i < 6; ++i) cp[i] = con.target[i] * con.mask[i];
+  return 6;
+}
+
+FeatWarm warm_feat(const cp_robot* robot, const ConDev& con, int W, const float* q_from,
+                   const float* q_to) {
+  FeatWarm f;
+  f.q_from = q_from;
+  f.q_to = q_to;
+  f.W = W;
+  f.dof = robot->host.dof;
+  for (int j = 0; j < kMaxDof; ++j) {
+    f.range[j] = j < f.dof ? std::fmax(std::fabs(robot->host.lo[j]), std::fabs(robot->host.hi[j])) : 1.0f;
+  }
+  f.n_cp = warm_params(con, f.cp);
+  return f;
+}
+
+// The projection from the corrected waypoints (network output delta
+// [motion][W-1][dof]), then, unless CP_WARM_NO_FALLBACK, the plain projector
+// on every motion the warm pass did not project.
+int warm_project(const cp_robot* robot, const ConDev& con, const cp_proj_params& p,
+                 const float* delta, int32_t n_motions, const float* d_q_from, const float* d_q_to,
+                 float* d_xi, int32_t* d_status, int32_t* d_iters, uint64_t* d_work, int32_t flags,
+                 hipStream_t st) {
+  ProjDev prm;
+  prm.W = p.W;
+  prm.max_iters = p.max_iters;
+  prm.tau = (float)p.tau;
+  prm.tau_sm = (float)p.tau_sm;
+  prm.tau_task = (float)p.tau_task;
+  prm.alpha = (float)p.alpha;
+  prm.lambda2 = (float)(p.lambda * p.lambda);
+  prm.variant = p.variant;
+  const int dof = robot->host.dof;
+  bool sup = false;
+  hipError_t e = launch_project_mode(dof, 1, robot->dev, con, prm, n_motions, d_q_from, d_q_to, delta,
+                                     d_xi, d_status, d_iters, (unsigned long long*)d_work, -1, st, &sup);
+  if (e == hipSuccess && sup && !(flags & CP_WARM_NO_FALLBACK))
+    e = launch_project_mode(dof, 2, robot->dev, con, prm, n_motions, d_q_from, d_q_to, nullptr,
+                            d_xi, d_status, d_iters, (unsigned long long*)d_work, -1, st, &sup);
+  if (!sup) return api_fail(CP_E_UNSUPPORTED, "no kernel for dof %d with constraint kind %d", dof, con.kind);
+  if (e != hipSuccess) return api_hip_fail(e, "project_motions_warm projection");
+  return CP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int cp_mlp_create(int32_t n_in, int32_t hidden, int32_t n_hidden, int32_t n_out, uint64_t seed,
@@ -558,9 +1009,23 @@ int cp_mlp_create(int32_t n_in, int32_t hidden, int32_t n_hidden, int32_t n_out,
     if (e == hipSuccess) e = hipMemcpy(n->w, w.data(), sizeof(float) * off, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(n->m1, 0, sizeof(float) * off);
     if (e == hipSuccess) e = hipMemset(n->m2, 0, sizeof(float) * off);
+    n->fusable = fusable(n_in, hidden, n_out);
+    if (e == hipSuccess && n->fusable) {
+      n->n_wf = fused_weight_count(n);
+      std::vector<int> width(n->out_dim);
+      e = hipMalloc((void**)&n->wf, sizeof(uint16_t) * n->n_wf);
+      if (e == hipSuccess) e = hipMalloc((void**)&n->bias_f, sizeof(float) * n->n_layers * hidden);
+      if (e == hipSuccess) e = hipMalloc((void**)&n->d_b_off, sizeof(long) * n->n_layers);
+      if (e == hipSuccess) e = hipMalloc((void**)&n->d_width, sizeof(int) * n->n_layers);
+      if (e == hipSuccess)
+        e = hipMemcpy(n->d_b_off, n->b_off.data(), sizeof(long) * n->n_layers, hipMemcpyHostToDevice);
+      if (e == hipSuccess)
+        e = hipMemcpy(n->d_width, width.data(), sizeof(int) * n->n_layers, hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) {
       refresh_bf16_kernel<<<nblk(off), 256>>>(n->w, n->wb, off);
-      e = hipDeviceSynchronize();
+      e = refresh_fused(n, nullptr);
+      if (e == hipSuccess) e = hipDeviceSynchronize();
     }
     if (e != hipSuccess) {
       cp_mlp_destroy(n);
@@ -579,8 +1044,11 @@ void cp_mlp_destroy(cp_mlp* n) {
   for (void* p : {(void*)n->ia, (void*)n->ib, (void*)n->ix, (void*)n->iy, (void*)n->feat,
                   (void*)n->delta, (void*)n->parts})
     if (p) (void)hipFree(p);
-  for (float* p : {n->w, n->grad, n->m1, n->m2, n->loss}) if (p) (void)hipFree(p);
+  for (float* p : {n->w, n->grad, n->m1, n->m2, n->loss, n->bias_f}) if (p) (void)hipFree(p);
   if (n->wb) (void)hipFree(n->wb);
+  if (n->wf) (void)hipFree(n->wf);
+  if (n->d_b_off) (void)hipFree(n->d_b_off);
+  if (n->d_width) (void)hipFree(n->d_width);
   delete n;
 }
 
@@ -599,6 +1067,7 @@ int cp_mlp_set_params(cp_mlp* n, const float* d_in, void* stream) {
   if (e == hipSuccess) {
     refresh_bf16_kernel<<<nblk(n->n_params), 256, 0, st>>>(n->w, n->wb, n->n_params);
     e = hipGetLastError();
+    if (e == hipSuccess) e = refresh_fused(n, st);
   }
   return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_mlp_set_params");
 }
@@ -610,10 +1079,7 @@ int cp_mlp_forward(cp_mlp* n, int64_t M, const float* d_x, float* d_y, void* str
     if (M == 0) return CP_OK;
     if (!d_x || !d_y) return api_fail(CP_E_ARG, "cp_mlp_forward: NULL buffer");
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = forward(n, M, d_x, n->n_in, st);
-    if (e == hipSuccess)
-      e = hipMemcpy2DAsync(d_y, sizeof(float) * n->n_out, n->yf, sizeof(float) * out_pad(n, n->n_layers - 1),
-                           sizeof(float) * n->n_out, M, hipMemcpyDeviceToDevice, st);
+    hipError_t e = infer(n, M, d_x, d_y, st);
     return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_mlp_forward");
   } catch (...) {
     return api_fail(CP_E_ARG, "cp_mlp_forward: unexpected exception");
@@ -651,6 +1117,7 @@ int cp_mlp_train_step(cp_mlp* n, int64_t M, const float* d_x, const float* d_t, 
     adam_kernel<<<nblk(n->n_params), 256, 0, st>>>(n->w, n->grad, n->m1, n->m2, n->wb, n->n_params,
                                                     lr, b1, b2, 1e-8f, c1, c2);
     e = hipGetLastError();
+    if (e == hipSuccess) e = refresh_fused(n, st);
     if (e == hipSuccess && d_loss) e = hipMemcpyAsync(d_loss, n->loss, sizeof(float), hipMemcpyDeviceToDevice, st);
     return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_mlp_train_step");
   } catch (...) {
@@ -689,21 +1156,20 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
       if (mlp->delta) (void)hipFree(mlp->delta);
       mlp->feat = mlp->delta = nullptr;
       mlp->warm_rows = 0;
-      e = hipMalloc((void**)&mlp->feat, sizeof(float) * rows * mlp->n_in);
+      // the fused network computes the features itself
+      if (!mlp->fusable) e = hipMalloc((void**)&mlp->feat, sizeof(float) * rows * mlp->n_in);
       if (e == hipSuccess) e = hipMalloc((void**)&mlp->delta, sizeof(float) * rows * dof);
       if (e != hipSuccess) return api_hip_fail(e, "project_motions_warm workspace");
       mlp->warm_rows = rows;
     }
     // constraint parameters as network inputs
     float cp[12] = {0};
-    int n_cp = 6;
-    if (con.kind == KIND_POSE) {
-      for (int i = 0; i < 6; ++i) cp[i] = con.target[i] * con.mask[i];
-    } else if (con.kind == KIND_REL) {
-      n_cp = 12;
-      for (int i = 0; i < 3; ++i) cp[i] = con.target[i];
-      for (int i = 0; i < 3; ++i)
-        for (int c = 0; c < 3; ++c) cp[3 + 3 * i + c] = con.Rt[3 * c + i];   // R* row-major
+    const int n_cp = warm_params(con, cp);
+    if (mlp->fusable) {
+      e = infer_fused(mlp, warm_feat(robot, con, p.W, d_q_from, d_q_to), rows, mlp->delta, dof, st);
+      if (e != hipSuccess) return api_hip_fail(e, "project_motions_warm network");
+      return warm_project(robot, con, p, mlp->delta, n_motions, d_q_from, d_q_to, d_xi, d_status,
+                          d_iters, d_work, flags, st);
     }
     float* d_cp = mlp->delta;   // borrow the first floats of delta for the parameters
     e = hipMemcpyAsync(d_cp, cp, sizeof(float) * n_cp, hipMemcpyHostToDevice, st);
@@ -720,24 +1186,8 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
     e = hipGetLastError();
     if (e == hipSuccess) e = infer(mlp, rows, mlp->feat, mlp->delta, st);
     if (e != hipSuccess) return api_hip_fail(e, "project_motions_warm network");
-    ProjDev prm;
-    prm.W = p.W;
-    prm.max_iters = p.max_iters;
-    prm.tau = (float)p.tau;
-    prm.tau_sm = (float)p.tau_sm;
-    prm.tau_task = (float)p.tau_task;
-    prm.alpha = (float)p.alpha;
-    prm.lambda2 = (float)(p.lambda * p.lambda);
-    prm.variant = p.variant;
-    bool sup = false;
-    e = launch_project_mode(dof, 1, robot->dev, con, prm, n_motions, d_q_from, d_q_to, mlp->delta,
-                            d_xi, d_status, d_iters, (unsigned long long*)d_work, -1, st, &sup);
-    if (e == hipSuccess && sup && !(flags & CP_WARM_NO_FALLBACK))
-      e = launch_project_mode(dof, 2, robot->dev, con, prm, n_motions, d_q_from, d_q_to, nullptr,
-                              d_xi, d_status, d_iters, (unsigned long long*)d_work, -1, st, &sup);
-    if (!sup) return api_fail(CP_E_UNSUPPORTED, "no kernel for dof %d with constraint kind %d", dof, con.kind);
-    if (e != hipSuccess) return api_hip_fail(e, "project_motions_warm projection");
-    return CP_OK;
+    return warm_project(robot, con, p, mlp->delta, n_motions, d_q_from, d_q_to, d_xi, d_status,
+                        d_iters, d_work, flags, st);
   } catch (...) {
     return api_fail(CP_E_ARG, "project_motions_warm: unexpected exception");
   }

@@ -184,9 +184,16 @@ def test_full_size_sampled_specialised(G):
     _compare_pv("cluttered-full specialised", ref, xi[idx], st[idx], it[idx], w, 64,
                 w["tau_task"])
     # the library kernels on the same launch: every motion whose status or
-    # iteration count differs between the two is recomputed by the oracle and
-    # must be in the band (a decision within 1e-5 of its threshold, or a
-    # minimum signed distance within 1e-5 m of 0)
+    # iteration count differs between the two is recomputed by the oracle.
+    # A differing projection outcome (one kernel projects, the other fails)
+    # must come from a decision within 1e-5 of its threshold.  Where both
+    # project, the two results are different valid projections (float32
+    # rounding moves the iterates by about 1e-6 rad, which can move a
+    # decision that lies near the band edge by one iteration): each is
+    # re-validated by the oracle (start bitwise, limits, task error and
+    # spacing within their thresholds up to the band), and each kernel's
+    # collision verdict must be the oracle's FK and distances on that
+    # kernel's own waypoints, outside the 1e-5 m band.
     xi_g, st_g, it_g = _run(G, robot, env, con, w, q_from, q_to, kw, G.GENERIC)
     assert set(np.unique(st)).issubset({0, 1, 2})
     diff = np.nonzero((st != st_g) | (it != it_g))[0]
@@ -194,7 +201,26 @@ def test_full_size_sampled_specialised(G):
           np.bincount(st_g, minlength=3), "differing motions", len(diff), flush=True)
     if len(diff):
         ref_d = _oracle_pv(w, q_from[diff], q_to[diff], 64, w["tau_task"])
-        in_band = (ref_d["proj_margin"] < 1e-5) | (np.abs(ref_d["min_sd"]) < 1e-5)
         proj_band = ref_d["proj_margin"] < 1e-5
-        assert np.all(in_band), diff[~in_band]
-        assert np.all(proj_band | (it[diff] == it_g[diff])), diff[~proj_band]
+        ro, eo, co = oracle_views(w)
+        max_spacing = 0.05 + 0.025
+        judged = iters_only = 0
+        for j, m in enumerate(diff):
+            if (st[m] == 1) != (st_g[m] == 1):
+                assert proj_band[j], (m, st[m], st_g[m], it[m], it_g[m])
+                continue
+            iters_only += int(st[m] == st_g[m])
+            for s_k, xi_k in ((st[m], xi[m]), (st_g[m], xi_g[m])):
+                if s_k == 1:
+                    continue
+                assert np.array_equal(xi_k[0], q_from[m]), m
+                rep = O.path_report(ro, eo, co, xi_k.astype(np.float64))
+                assert rep["inside"], m
+                assert rep["task_error"] < w["tau_task"] + 1e-5, (m, rep)
+                assert rep["spacing"] < max_spacing + 1e-5, (m, rep)
+                sd = O.path_report(ro, eo, co, xi_k[1:].astype(np.float64))["min_sd"]
+                if abs(sd) >= 1e-5:
+                    assert s_k == (2 if sd <= 0 else 0), (m, s_k, sd)
+                    judged += 1
+        print("differing motions: same status, iterations only", iters_only,
+              "; verdicts judged on each kernel's own waypoints", judged, flush=True)
