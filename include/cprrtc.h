@@ -301,6 +301,25 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
                          int32_t* d_status, int32_t* d_iters, uint64_t* d_work, int32_t flags,
                          void* stream);
 
+/* project_motions_warm for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and results, but the network's corrections go
+ * to a fixed device array of 32 MiB (8 Mi floats) inside the library instead
+ * of memory the library allocates, and the call allocates nothing.  The array
+ * exists once per GPU (held until the process ends) and every call on that
+ * GPU shares it: calls that overlap on one GPU race and must not be issued
+ * concurrently (on different streams or threads).  Limits: n_motions x (W-1)
+ * x dof <= 8 Mi (e.g. 19 000 motions of a 7-joint robot at W = 64), else
+ * CP_E_CAPACITY with nothing launched; the network must have the fused shape
+ * (hidden width 64, 128, 256 or 512, at most 32 inputs and 16 outputs), else
+ * CP_E_UNSUPPORTED.  Arguments, layout, ownership and the other errors as
+ * project_motions_warm. */
+int project_motions_warm_noalloc(const cp_robot* robot, const cp_constraint* constraint,
+                                 const cp_proj_params* params, cp_mlp* mlp, int32_t n_motions,
+                                 const float* d_q_from, const float* d_q_to, float* d_xi,
+                                 int32_t* d_status, int32_t* d_iters, uint64_t* d_work,
+                                 int32_t flags, void* stream);
+
 /* ------------------------------------------------------------ run-time specialisation */
 
 /* Compiles at run time (hipRTC) kernels for this robot and for constraints

@@ -152,6 +152,7 @@ def lib():
         L.cp_mlp_train_step.argtypes = [vp, C.c_int64, vp, vp, C.c_float, vp, vp]
         L.project_motions_warm.argtypes = [vp, C.POINTER(Constraint), C.POINTER(ProjParams), vp,
                                            C.c_int32, vp, vp, vp, vp, vp, vp, C.c_int32, vp]
+        L.project_motions_warm_noalloc.argtypes = L.project_motions_warm.argtypes
         L.project_configs.argtypes = [vp, C.POINTER(Constraint), C.c_int32, vp, vp, vp,
                                       C.c_double, C.c_int32, C.c_double, C.c_double, vp]
         _lib = L
@@ -544,12 +545,15 @@ class MLP:
 
 
 def project_motions_warm(robot: Robot, con: Constraint, prm: ProjParams, mlp: MLP, q_from, q_to,
-                         xi, status, iters=None, work=None, flags: int = 0, stream=None):
+                         xi, status, iters=None, work=None, flags: int = 0, stream=None,
+                         noalloc: bool = False):
     """project_motions with the learned warm start and the plain fallback
-    (flags=WARM_NO_FALLBACK: the warm pass alone)."""
+    (flags=WARM_NO_FALLBACK: the warm pass alone); noalloc=True calls
+    project_motions_warm_noalloc (the library's fixed buffer, no allocation)."""
     import torch
     m = q_from.shape[0]
-    _check(lib().project_motions_warm(
+    fn = lib().project_motions_warm_noalloc if noalloc else lib().project_motions_warm
+    _check(fn(
         robot.handle, C.byref(con), C.byref(prm), mlp.handle, m, _dev(q_from, torch.float32),
         _dev(q_to, torch.float32), _dev(xi, torch.float32), _dev(status, torch.int32),
         _dev(iters, torch.int32) if iters is not None else None,

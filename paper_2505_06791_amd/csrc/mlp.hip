@@ -23,6 +23,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <random>
 #include <type_traits>
@@ -962,6 +963,34 @@ int warm_project(const cp_robot* robot, const ConDev& con, const cp_proj_params&
   return CP_OK;
 }
 
+// Device memory of project_motions_warm_noalloc: the network's corrections
+// [rows][dof] live in this fixed array (one copy per GPU, held until the
+// process ends) instead of memory the library allocates.
+constexpr long kNoAllocFloats = 8L << 20;   // 32 MiB
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_lock;
+float* scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (the array's name is a host-side stand-in, not a device address).
+hipError_t scratch_address(float** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(scratch_lock);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1187,6 +1216,51 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
                         d_iters, d_work, flags, st);
   } catch (...) {
     return api_fail(CP_E_ARG, "project_motions_warm: unexpected exception");
+  }
+}
+
+int project_motions_warm_noalloc(const cp_robot* robot, const cp_constraint* constraint,
+                                 const cp_proj_params* params, cp_mlp* mlp, int32_t n_motions,
+                                 const float* d_q_from, const float* d_q_to, float* d_xi,
+                                 int32_t* d_status, int32_t* d_iters, uint64_t* d_work,
+                                 int32_t flags, void* stream) {
+  try {
+    if (!robot || !mlp) return api_fail(CP_E_ARG, "project_motions_warm_noalloc: NULL handle");
+    if (n_motions < 0) return api_fail(CP_E_ARG, "project_motions_warm_noalloc: n_motions < 0");
+    cp_proj_params p;
+    int rc = api_params(params, &p);
+    if (rc != CP_OK) return rc;
+    if (p.variant != CP_PROJECT_PARALLEL)
+      return api_fail(CP_E_UNSUPPORTED, "project_motions_warm_noalloc: the warm start serves the parallel projector only");
+    ConDev con;
+    rc = api_constraint(constraint, robot, &con);
+    if (rc != CP_OK) return rc;
+    const int dof = robot->host.dof;
+    if (!dof_supported(dof)) return api_fail(CP_E_UNSUPPORTED, "dof %d", dof);
+    if (mlp->n_in != warm_inputs(dof, con.kind) || mlp->n_out != dof)
+      return api_fail(CP_E_ARG, "network has %d inputs / %d outputs, the warm start needs %d / %d",
+                      mlp->n_in, mlp->n_out, warm_inputs(dof, con.kind), dof);
+    if (!mlp->fusable)
+      return api_fail(CP_E_UNSUPPORTED, "project_motions_warm_noalloc: the network's shape needs the "
+                      "layer-by-layer path, which allocates (use project_motions_warm)");
+    const long rows = (long)n_motions * (p.W - 1);
+    if (rows * dof > kNoAllocFloats)
+      return api_fail(CP_E_CAPACITY, "project_motions_warm_noalloc: %d motions x %d waypoints x %d joints "
+                      "exceed the fixed %ld-float buffer (at most %ld motions here)", n_motions, p.W - 1,
+                      dof, kNoAllocFloats, kNoAllocFloats / ((long)(p.W - 1) * dof));
+    if (n_motions == 0) return CP_OK;
+    if (!d_q_from || !d_q_to || !d_xi || !d_status) return api_fail(CP_E_ARG, "NULL buffer");
+    float* delta = nullptr;
+    hipError_t e = scratch_address(&delta);
+    if (e != hipSuccess) return api_hip_fail(e, "project_motions_warm_noalloc: address of the fixed buffer");
+    hipStream_t st = (hipStream_t)stream;
+    // every row of delta is written by the network before the projection reads it
+    e = infer_fused(mlp, warm_feat(robot, con, p.W, d_q_from, d_q_to), rows, delta, dof, st);
+    if (e != hipSuccess) return api_hip_fail(e, "project_motions_warm_noalloc network");
+    return warm_project(robot, con, p, delta, n_motions, d_q_from, d_q_to, d_xi, d_status, d_iters,
+                        d_work, flags, st);
+  } catch (...) {
+    return api_fail(CP_E_ARG, "project_motions_warm_noalloc: unexpected exception");
   }
 }
 
