@@ -146,6 +146,8 @@ def parse():
                     help="obstacle-density sweep of the validation kernel (0 = skip)")
     ap.add_argument("--learned", type=int, default=1,
                     help="measure the warm-start network and the warm-started projector (0 = skip)")
+    ap.add_argument("--learned-queries", type=int, default=128,
+                    help="planning queries of one robot for the learned + batched comparison")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB three times "
                          "(calibration of the HBM traffic counters) and exit")
@@ -292,16 +294,18 @@ def batch_bench(G, I, torch, n, base=3000, make=None, max_dof=9, rounds=800, tau
     256 x rounds/8 sequential) and tree capacity; query preparation and tree
     allocation are excluded."""
     make = make or I.uneven_query
-    queries = []
+    queries, works = [], []
     for s in range(base, base + n):
         w = make(s)
         robot, env, con, start, goal = gpu_query(G, I, torch, w, s)
         if start is not None:
             queries.append((robot, env, con, start, goal, s))
+            works.append(w)
     print(f"batch: {len(queries)} queries prepared", file=sys.stderr, flush=True)
+    shape, tuned = tune_batch_shape(G, I, torch, queries, works, tau_task)
     cap = 16384
     bp = G.BatchPlanner(len(queries), max_dof, G.batch_opts(groups_per_query=32, max_rounds=rounds,
-                                                            capacity=cap, tau_task=tau_task))
+                                                            capacity=cap, tau_task=tau_task, **shape))
     bp.plan(queries[:8])                          # module load and first-touch, untimed
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -310,10 +314,20 @@ def batch_bench(G, I, torch, n, base=3000, make=None, max_dof=9, rounds=800, tau
     print(f"batch: batched {batch_ms:.0f} ms, {(st_b == G.CP_OK).sum()} solved",
           file=sys.stderr, flush=True)
     del bp
+    # the same batch with one launch per (DOF, kind) class and a publish launch per round
+    bp = G.BatchPlanner(len(queries), max_dof, G.batch_opts(groups_per_query=32, max_rounds=rounds,
+                                                            capacity=cap, tau_task=tau_task,
+                                                            flags=G.BATCH_PER_CLASS, **shape))
+    bp.plan(queries[:8])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_c, _, info_c = bp.plan(queries)
+    per_class_ms = (time.perf_counter() - t0) * 1e3
+    del bp
     seq_ms, ok_s = 0.0, 0
     for robot, env, con, start, goal, s in queries:
         pl = G.Planner(robot, G.plan_opts(n_groups=256, max_rounds=rounds // 8, capacity=cap,
-                                          tau_task=tau_task))
+                                          tau_task=tau_task, **shape))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
@@ -327,11 +341,48 @@ def batch_bench(G, I, torch, n, base=3000, make=None, max_dof=9, rounds=800, tau
         del pl
         if (s - base) % 16 == 15:
             print(f"batch: sequential through seed {s}, {seq_ms:.0f} ms", file=sys.stderr, flush=True)
-    return dict(queries=len(queries), batched_ms=batch_ms,
-                batched_solved=int((st_b == G.CP_OK).sum()),
-                batched_rounds=int(max(i["rounds"] for i in info)),
+    b_rounds = int(max(i["rounds"] for i in info))
+    c_rounds = int(max(i["rounds"] for i in info_c))
+    return dict(queries=len(queries), autotuned=dict(chosen=shape, per_class=tuned),
+                batched_ms=batch_ms,
+                batched_solved=int((st_b == G.CP_OK).sum()), batched_rounds=b_rounds,
+                launches_per_round=int(info[0]["launches_per_round"]),
+                ms_per_round=batch_ms / max(b_rounds, 1),
+                per_class_launches=dict(ms=per_class_ms, solved=int((st_c == G.CP_OK).sum()),
+                                        rounds=c_rounds,
+                                        launches_per_round=int(info_c[0]["launches_per_round"]),
+                                        ms_per_round=per_class_ms / max(c_rounds, 1)),
                 sequential_ms=seq_ms, sequential_solved=ok_s,
                 speedup=seq_ms / batch_ms)
+
+
+def tune_batch_shape(G, I, torch, queries, works, tau_task, n=1024):
+    """cp_autotune (waypoints per motion W in {32, 64}, sphere batch of the
+    planners' round kernels in {4, 8}) on sample motions of the first query
+    of each (DOF, constraint kind) class: n motions from its start and goal
+    towards uniform configurations, steered (W-1) tau.  The batch takes the
+    choice of the classes holding most queries."""
+    dev = torch.device("cuda:0")
+    classes = {}
+    for (robot, env, con, a, b, s), w in zip(queries, works):
+        classes.setdefault((w["robot"]["dof"], int(con.kind)), []).append(((robot, env, con, a, b), w))
+    votes, per_class = {}, {}
+    for key, members in sorted(classes.items()):
+        (robot, env, con, a, b), w = members[0]
+        q0 = np.repeat(np.stack([a, b]), n // 2, axis=0)
+        q1 = I.random_displacements(w["robot"], q0, (W - 1) * TAU, 7000 + key[0] * 4 + key[1])
+        qf = torch.from_numpy(q0.astype(np.float32)).to(dev)
+        qt = torch.from_numpy(q1.astype(np.float32)).to(dev)
+        p, cands = G.autotune(robot, env, con, G.proj_params(W=W, tau=TAU, tau_task=tau_task),
+                              qf, qt, tune_W=True, planner=True)
+        pick = (int(p.W), int(p.sphere_batch))
+        votes[pick] = votes.get(pick, 0) + len(members)
+        per_class[f"dof{key[0]}_kind{key[1]}"] = dict(queries=len(members), W=pick[0],
+                                                      sphere_batch=pick[1], candidates=cands)
+    Wc, Bc = max(votes.items(), key=lambda kv: (kv[1], kv[0]))[0]
+    print(f"batch: autotuned W {Wc}, sphere batch {Bc} ({per_class and list(per_class)})",
+          file=sys.stderr, flush=True)
+    return dict(W=Wc, sphere_batch=Bc), per_class
 
 
 def _time_ms(torch, fn, reps):
@@ -379,28 +430,76 @@ def mlp_bench(G, torch, M=65536):
     return out
 
 
-def warm_bench(G, I, torch, n_train=8192, n_eval=4096, tau_task=1e-4):
-    """Learned warm start against the plain projector at tolerance 1e-4
-    (plain scene, seed 1000): the network is trained on pairs from
-    n_train projector motions, then both project n_eval held-out motions."""
+def learned_bench(G, I, torch, name, seed, hidden, n_queries, n_pairs=2_000_000, n_eval=10000,
+                  epochs=8, seq_rounds=100, groups=32, tau_task=1e-4, max_dof=7):
+    """Learned + batched against plain at equal residual 1e-4 on one robot,
+    scene and constraint (the workload `name` at `seed`; a network serves one
+    robot and one constraint).
+
+    Network: n_in -> 3 x hidden (SiLU) -> dof, trained with the library's
+    kernels on n_pairs (waypoint, projected - waypoint) pairs that the
+    library's own projector (Algorithm 1) produced on motions from
+    on-manifold starts (95/5 split), Adam with cosine learning rate.
+    held_out: n_eval fresh motions projected plainly, warm-started alone, and
+    warm-started with the plain fallback (success, iterations, time).
+    planning: n_queries start/goal pairs planned four ways with the same
+    extension budget per query (one cp_plan each with 256 wavefronts x
+    seq_rounds rounds, or one cp_plan_batch with `groups` wavefronts x
+    seq_rounds x 256 / groups rounds), plain or warm-started; the factors
+    divide the plain one-by-one wall time by each mode's."""
     from paper_2505_06791_amd import warmstart
-    w = I.workload("plain", 1000)
+    w = I.workload(name, seed)
     rd, cd = w["robot"], w["constraint"]
-    robot, con = G.Robot(rd), G.constraint(cd)
+    robot, env, con = G.Robot(rd), G.Env(w["env"]), G.constraint(cd)
+    dev = torch.device("cuda:0")
+    # planning queries of this robot, scene and constraint
+    queries = []
+    qs = 0
+    while len(queries) < n_queries and qs < 4 * n_queries:
+        _, _, _, a, b = gpu_query(G, I, torch, w, seed + 100 + qs, robot)
+        qs += 1
+        if a is not None:
+            queries.append((robot, env, con, a, b, seed + 100 + qs))
+    # launch shape by the autotuner (W, sphere batch), used by every mode below
+    shape, tuned = tune_batch_shape(G, I, torch, queries, [w] * len(queries), tau_task)
+    Wr = shape["W"]
     t0 = time.perf_counter()
-    X, T = warmstart.make_pairs(rd, cd, n_train, seed=4000, tau_task=tau_task, robot=robot, con=con)
-    net = G.MLP(warmstart.n_inputs(rd, cd), 256, 3, rd["dof"], seed=4000)
-    hist = warmstart.train(net, X, T, epochs=6, batch=4096)
+    Xs, Ts, n, s, calls = [], [], 0, 4000, 0
+    while n < n_pairs and calls < 24:
+        X, T = warmstart.make_pairs(rd, cd, 16384, seed=s, W=Wr, tau_task=tau_task, robot=robot,
+                                    con=con)
+        Xs.append(X)
+        Ts.append(T)
+        n += X.shape[0]
+        s += 1
+        calls += 1
+    X, T = torch.cat(Xs)[:n_pairs], torch.cat(Ts)[:n_pairs]
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    perm = torch.randperm(X.shape[0], generator=torch.Generator(device=dev).manual_seed(4000),
+                          device=dev)
+    n_val = X.shape[0] // 20
+    Xv, Tv = X[perm[:n_val]].contiguous(), T[perm[:n_val]].contiguous()
+    Xt, Tt = X[perm[n_val:]].contiguous(), T[perm[n_val:]].contiguous()
+    net = G.MLP(warmstart.n_inputs(rd, cd), hidden, 3, rd["dof"], seed=4000)
+    t0 = time.perf_counter()
+    hist = warmstart.train(net, Xt, Tt, epochs=epochs, batch=4096)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    q_from, q_to = warmstart.motion_ends(rd, robot, con, n_eval, seed=4100)
+    val_mse = float(((net.forward(Xv) - Tv) ** 2).mean().item())
+    target_ms = float((Tv ** 2).mean().item())
+    print(f"learned {name}: {X.shape[0]} pairs in {gen_s:.1f} s, trained in {train_s:.1f} s, "
+          f"validation mse {val_mse:.2e} (targets {target_ms:.2e})", file=sys.stderr, flush=True)
+
+    # held-out motions
+    q_from, q_to = warmstart.motion_ends(rd, robot, con, n_eval, seed=4100, W=Wr)
     M, dof = q_from.shape[0], rd["dof"]
-    prm = G.proj_params(W=W, tau=TAU, tau_task=tau_task)
-    xi = torch.empty((M, W, dof), device=q_from.device)
-    st = torch.empty(M, dtype=torch.int32, device=q_from.device)
-    it = torch.empty(M, dtype=torch.int32, device=q_from.device)
-    res = {}
-    for name, fn in (("plain", lambda: G.project_motions(robot, con, prm, q_from, q_to, xi, st, it)),
+    prm = G.proj_params(W=Wr, tau=TAU, tau_task=tau_task)
+    xi = torch.empty((M, Wr, dof), device=dev)
+    st = torch.empty(M, dtype=torch.int32, device=dev)
+    it = torch.empty(M, dtype=torch.int32, device=dev)
+    held = {}
+    for mode, fn in (("plain", lambda: G.project_motions(robot, con, prm, q_from, q_to, xi, st, it)),
                      ("warm_only", lambda: G.project_motions_warm(robot, con, prm, net, q_from, q_to,
                                                                   xi, st, it,
                                                                   flags=G.WARM_NO_FALLBACK)),
@@ -408,10 +507,64 @@ def warm_bench(G, I, torch, n_train=8192, n_eval=4096, tau_task=1e-4):
                                                                       q_to, xi, st, it))):
         ms = _time_ms(torch, fn, 5)
         s_h, i_h = st.cpu().numpy(), it.cpu().numpy()
-        res[name] = dict(ms=ms, success=float((s_h == 0).mean()), mean_iters=float(i_h.mean()))
-    res.update(motions=M, tau_task=tau_task, train_pairs=int(X.shape[0]), train_seconds=train_s,
-               train_loss=[float(h) for h in hist])
-    return res
+        ok = s_h == 0
+        held[mode] = dict(ms=ms, success=float(ok.mean()),
+                          mean_iters_projected=float(i_h[ok].mean()) if ok.any() else None)
+
+    cap = 16384
+
+    def one_by_one(warm):
+        pl = G.Planner(robot, G.plan_opts(n_groups=256, max_rounds=seq_rounds, capacity=cap,
+                                          tau_task=tau_task, **shape))
+        pl.set_warm(net if warm else None)
+        pl.plan(env, con, queries[0][3], queries[0][4], 0)      # module load, untimed
+        total, solved = 0.0, 0
+        for _, _, _, a, b, sd in queries:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            try:
+                rc, _, _ = pl.plan(env, con, a, b, sd)
+            except G.CprrtcError as e:      # a tree filled up: unsolved
+                if e.code != G.CP_E_CAPACITY:
+                    raise
+                rc = e.code
+            total += time.perf_counter() - t1
+            solved += rc == G.CP_OK
+        return dict(ms=total * 1e3, solved=int(solved))
+
+    def batched(warm):
+        bp = G.BatchPlanner(len(queries), max_dof,
+                            G.batch_opts(groups_per_query=groups, max_rounds=seq_rounds * 256 // groups,
+                                         capacity=cap, tau_task=tau_task, **shape))
+        bp.set_warm(net if warm else None)
+        bp.plan(queries[:4])                                      # module load, untimed
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st_b, _, info = bp.plan(queries)
+        ms = (time.perf_counter() - t1) * 1e3
+        return dict(ms=ms, solved=int((st_b == G.CP_OK).sum()),
+                    rounds=int(max(i["rounds"] for i in info)),
+                    launches_per_round=int(info[0]["launches_per_round"]))
+
+    plan = {}
+    for mode, fn in (("plain_one_by_one", lambda: one_by_one(False)),
+                     ("learned_one_by_one", lambda: one_by_one(True)),
+                     ("plain_batched", lambda: batched(False)),
+                     ("learned_batched", lambda: batched(True))):
+        plan[mode] = fn()
+        print(f"learned {name}: {mode} {plan[mode]['ms']:.0f} ms, {plan[mode]['solved']} of "
+              f"{len(queries)} solved", file=sys.stderr, flush=True)
+    base_ms = plan["plain_one_by_one"]["ms"]
+    return dict(workload=f"{name} seed {seed}: one robot, scene and constraint",
+                tau_task=tau_task, autotuned=dict(chosen=shape, per_class=tuned),
+                network=f"{warmstart.n_inputs(rd, cd)}-3x{hidden}-{dof}",
+                train_pairs=int(X.shape[0]), pair_seconds=gen_s, train_seconds=train_s,
+                epochs=epochs, train_loss=[float(h) for h in hist], validation_mse=val_mse,
+                target_mean_square=target_ms, held_out=dict(motions=M, **held),
+                queries=len(queries), planning=plan,
+                factors={"learned_only": base_ms / plan["learned_one_by_one"]["ms"],
+                         "batched_only": base_ms / plan["plain_batched"]["ms"],
+                         "learned_batched": base_ms / plan["learned_batched"]["ms"]})
 
 
 def fkcc_bench(G, I, torch, n=1 << 20, reps=5):
@@ -817,7 +970,11 @@ def main():
         result["density"] = density_bench(G, I, torch)
     if args.learned:
         result["mlp"] = mlp_bench(G, torch)
-        result["warm_start"] = warm_bench(G, I, torch)
+        result["learned_vs_plain"] = {
+            "arm7": learned_bench(G, I, torch, "plain", 1000, 256, args.learned_queries),
+            "dual14": learned_bench(G, I, torch, "dual", 5000, 512, args.learned_queries,
+                                    n_pairs=1_000_000, epochs=6, seq_rounds=50, max_dof=14),
+        }
     if args.cpu_seconds > 0:
         result["cpu_baseline"] = cpu_baseline(I, w, args.cpu_seconds)
     print(json.dumps(result), flush=True)

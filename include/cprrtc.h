@@ -301,6 +301,19 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
                          int32_t* d_status, int32_t* d_iters, uint64_t* d_work, int32_t flags,
                          void* stream);
 
+/* Training pairs of the warm start from motions the projector projected:
+ * for waypoint k = 1..W-1 of motion m, row m (W-1) + k - 1 of d_x
+ * [n_motions (W-1)][dof + 6 (or + 12)] receives the network's features (as
+ * project_motions_warm computes them for the straight waypoint of
+ * d_q_from[m] -> d_q_to[m]) and the row of d_t [n_motions (W-1)][dof] the
+ * target, d_xi[m][k] minus that straight waypoint.  Rows of motions whose
+ * projection failed are written too; the caller keeps the rows it wants.
+ * Device pointers, asynchronous on stream.  Errors: CP_E_ARG,
+ * CP_E_UNSUPPORTED (dof), CP_E_HIP. */
+int cp_warm_pairs(const cp_robot* robot, const cp_constraint* constraint, int32_t W,
+                  int32_t n_motions, const float* d_q_from, const float* d_q_to,
+                  const float* d_xi, float* d_x, float* d_t, void* stream);
+
 /* project_motions_warm for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the same kernels and results, but the network's corrections go
@@ -354,7 +367,8 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
 
 /* Picks the launch shape for a workload by measurement: for every candidate
  * (W in {32, 64} if flags has CP_TUNE_W, else the W of *params; sphere batch
- * in {4, 8, 16}) runs project_validate_motions once untimed and reps times timed
+ * in {4, 8, 16}, or {4, 8} -- the planners' round kernels -- if flags has
+ * CP_TUNE_PLANNER) runs project_validate_motions once untimed and reps times timed
  * on the caller's sample motions (d_q_from, d_q_to: [n_motions][dof] device
  * floats, steered for the W of *params; for another W the end points are
  * moved along the same direction by (W' - 1) / (W - 1) so the initial
@@ -365,7 +379,7 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
  * on stream; allocates its own scratch (n_motions x 64 x dof floats).
  * Errors as project_validate_motions, CP_E_ARG for n_motions < 1 or reps
  * outside 1..1000. */
-enum { CP_TUNE_W = 1 };
+enum { CP_TUNE_W = 1, CP_TUNE_PLANNER = 2 };
 typedef struct cp_tune_report {
   int32_t n;                   /* candidates timed */
   int32_t W[8];
@@ -415,6 +429,7 @@ typedef struct cp_plan_stats {
   int32_t rounds;        /* rounds launched */
   int32_t nodes[2];      /* tree sizes (start tree, goal tree) */
   int32_t overflow;      /* 1 if a tree reached its capacity */
+  int32_t launches_per_round;  /* kernel launches per round */
 } cp_plan_stats;
 
 /* Path shortcutting (specified here; the paper returns the planner's path
@@ -470,6 +485,20 @@ int cp_plan(cp_planner* planner, const cp_env* env, const cp_constraint* constra
  * CP_E_CAPACITY with *count set when capacity < *count.  Synchronous. */
 int cp_planner_tree(const cp_planner* planner, int32_t tree, int32_t capacity, double* q,
                     int32_t* parent, int32_t* count);
+/* Learned warm start for the planner's extensions (paper Section III-A: the
+ * projection of a straight segment; the network is this library's extension,
+ * see project_motions_warm): with a network set, every extension's first
+ * motion q_near -> q_steer is projected from the straight waypoints plus the
+ * network's corrections, and again from the straight line if that fails;
+ * the connect steps project plainly.  A round is then three launches
+ * (samples, the fused network, extensions) and uses the library's round
+ * kernels, not ones compiled for the robot.  mlp = NULL switches it off.
+ * The network is borrowed (it must outlive the plans) and must have the
+ * fused shape (see project_motions_warm_noalloc) with n_in = dof + 6 (+ 12
+ * for a relative pose), n_out = dof; that is checked by cp_plan.  Errors:
+ * CP_E_ARG, CP_E_UNSUPPORTED (with CP_SELF_COLLISION or a projector variant
+ * other than CP_PROJECT_PARALLEL), CP_E_HIP (round buffers). */
+int cp_planner_set_warm(cp_planner* planner, const cp_mlp* mlp);
 /* One-shot form: creates a planner with opts (NULL = defaults), plans on the
  * default stream, destroys it. */
 int plan(const cp_robot* robot, const cp_env* env, const cp_constraint* constraint,
@@ -479,15 +508,21 @@ int plan(const cp_robot* robot, const cp_env* env, const cp_constraint* constrai
 /* ------------------------------------------------------------ batched planning */
 
 /* Many independent queries (robots, DOF, scenes, constraint kinds may all
- * differ) planned together.  Queries are grouped by (DOF, constraint kind);
- * a round is one launch per group, in which each query owns
- * groups_per_query wavefronts and runs the extension step of cp_plan;
+ * differ) planned together (paper Section III: extensions are independent).
+ * Every query owns groups_per_query extensions per round, each the
+ * extension step of cp_plan.  A round is one launch: wavefronts take
+ * (query, extension) tasks from a device counter until none is left, each
+ * running the code specialised for its query's (DOF, constraint kind), and
+ * the last wavefront to finish publishes the round's nodes.  With
+ * CP_BATCH_PER_CLASS (or a warm start, or classes from both sets below) a
+ * round is instead one launch per (DOF, kind) class plus a publish launch.
  * rounds_per_graph rounds are captured in a HIP graph that is replayed until
  * every query is solved, out of budget (max_rounds, rounded up to a whole
  * replay) or out of tree capacity.  Each query's samples depend on its seed
  * only, not on the other queries of the batch.
  * Supported: dof 6, 7, 9 with no / pose constraint; dof 14 with pose /
  * relative-pose constraint. */
+enum { CP_BATCH_PER_CLASS = 1 };
 typedef struct cp_batch_opts {
   cp_proj_params proj;        /* W and sphere_batch shared by the batch */
   int32_t groups_per_query;   /* wavefronts per query per round (16) */
@@ -495,6 +530,7 @@ typedef struct cp_batch_opts {
   int32_t capacity;           /* nodes per tree per query (2048) */
   int32_t max_connect;        /* (64) */
   int32_t rounds_per_graph;   /* rounds per graph replay (4) */
+  int32_t flags;              /* CP_BATCH_PER_CLASS (0) */
 } cp_batch_opts;
 
 typedef struct cp_query {
@@ -518,6 +554,13 @@ void cp_batch_destroy(cp_batch* batch);
  * stats nullable ([n]).  Returns CP_OK unless the call itself fails. */
 int cp_plan_batch(cp_batch* batch, int32_t n, const cp_query* queries, cp_path* paths,
                   int32_t* status, cp_plan_stats* stats, void* stream);
+/* Learned warm start for the batch (as cp_planner_set_warm): every query of
+ * the next cp_plan_batch calls must then use the same robot handle and an
+ * identical constraint (a network serves one robot and one constraint;
+ * otherwise cp_plan_batch returns CP_E_UNSUPPORTED), and a round becomes
+ * three launches (samples, network, extensions).  mlp = NULL switches it
+ * off; the network is borrowed. */
+int cp_batch_set_warm(cp_batch* batch, const cp_mlp* mlp);
 
 #ifdef __cplusplus
 }

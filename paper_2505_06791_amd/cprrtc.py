@@ -23,9 +23,11 @@ NO_EARLY_EXIT = 1
 NO_CULL = 2
 WARM_NO_FALLBACK = 4
 CP_TUNE_W = 1
+CP_TUNE_PLANNER = 2
 POOLED, PER_MOTION, GENERIC = 8, 16, 32
 SPECIALIZE_PROJECT, SPECIALIZE_PLAN = 1, 2
 SELF_COLLISION = 64
+BATCH_PER_CLASS = 1
 PROJECT_PARALLEL, PROJECT_INDEPENDENT, PROJECT_SEQUENTIAL = 0, 1, 2
 WORK_SLOTS = 8
 
@@ -74,7 +76,8 @@ class Path(C.Structure):
 
 
 class PlanStats(C.Structure):
-    _fields_ = [("rounds", C.c_int32), ("nodes", C.c_int32 * 2), ("overflow", C.c_int32)]
+    _fields_ = [("rounds", C.c_int32), ("nodes", C.c_int32 * 2), ("overflow", C.c_int32),
+                ("launches_per_round", C.c_int32)]
 
 
 class ShortcutStats(C.Structure):
@@ -90,7 +93,7 @@ class TuneReport(C.Structure):
 class BatchOpts(C.Structure):
     _fields_ = [("proj", ProjParams), ("groups_per_query", C.c_int32), ("max_rounds", C.c_int32),
                 ("capacity", C.c_int32), ("max_connect", C.c_int32),
-                ("rounds_per_graph", C.c_int32)]
+                ("rounds_per_graph", C.c_int32), ("flags", C.c_int32)]
 
 
 class Query(C.Structure):
@@ -135,6 +138,8 @@ def lib():
                            C.POINTER(PlanOpts), C.POINTER(Path)]
         L.cp_autotune.argtypes = [vp, vp, C.POINTER(Constraint), C.POINTER(ProjParams), C.c_int32,
                                   vp, vp, C.c_int32, C.c_int32, C.POINTER(TuneReport), vp]
+        L.cp_planner_set_warm.argtypes = [vp, vp]
+        L.cp_batch_set_warm.argtypes = [vp, vp]
         L.cp_batch_opts_default.argtypes = [C.POINTER(BatchOpts)]
         L.cp_batch_create.argtypes = [C.POINTER(BatchOpts), C.c_int32, C.c_int32, C.POINTER(vp)]
         L.cp_batch_destroy.argtypes = [vp]
@@ -153,6 +158,8 @@ def lib():
         L.project_motions_warm.argtypes = [vp, C.POINTER(Constraint), C.POINTER(ProjParams), vp,
                                            C.c_int32, vp, vp, vp, vp, vp, vp, C.c_int32, vp]
         L.project_motions_warm_noalloc.argtypes = L.project_motions_warm.argtypes
+        L.cp_warm_pairs.argtypes = [vp, C.POINTER(Constraint), C.c_int32, C.c_int32, vp, vp, vp,
+                                    vp, vp, vp]
         L.project_configs.argtypes = [vp, C.POINTER(Constraint), C.c_int32, vp, vp, vp,
                                       C.c_double, C.c_int32, C.c_double, C.c_double, vp]
         _lib = L
@@ -358,15 +365,17 @@ def project_configs(robot: Robot, con: Constraint, q_in, q_out, status, tol=1e-5
 
 
 def autotune(robot: Robot, env: Env, con: Constraint, params: ProjParams, q_from, q_to,
-             tune_W: bool = False, reps: int = 3, stream=None):
+             tune_W: bool = False, reps: int = 3, stream=None, planner: bool = False):
     """Times project_validate_motions for each candidate launch shape on the
-    sample motions; returns (chosen ProjParams, list of candidate dicts)."""
+    sample motions; returns (chosen ProjParams, list of candidate dicts).
+    planner=True: only the sphere batches the planners' round kernels have."""
     import torch
     p = ProjParams.from_buffer_copy(params)
     rep = TuneReport()
+    flags = (CP_TUNE_W if tune_W else 0) | (CP_TUNE_PLANNER if planner else 0)
     _check(lib().cp_autotune(robot.handle, env.handle, C.byref(con), C.byref(p), q_from.shape[0],
                              _dev(q_from, torch.float32), _dev(q_to, torch.float32),
-                             CP_TUNE_W if tune_W else 0, reps, C.byref(rep), _stream(stream)))
+                             flags, reps, C.byref(rep), _stream(stream)))
     cands = [dict(W=rep.W[i], sphere_batch=rep.sphere_batch[i], ms=rep.ms[i],
                   waypoints_per_s=rep.waypoints_per_s[i]) for i in range(rep.n)]
     return p, cands
@@ -409,10 +418,15 @@ class Planner:
                            C.byref(stats), strm)
         _check(rc)
         st = dict(rounds=stats.rounds, nodes=(stats.nodes[0], stats.nodes[1]),
-                  overflow=stats.overflow)
+                  overflow=stats.overflow, launches_per_round=stats.launches_per_round)
         if rc == CP_OK:
             return rc, buf[: path.len].copy(), st
         return rc, None, st
+
+    def set_warm(self, mlp: "MLP | None"):
+        """Warm-start every extension's first motion with the network (None: off)."""
+        _check(lib().cp_planner_set_warm(self.handle, mlp.handle if mlp is not None else None))
+        self._warm = mlp
 
     def tree(self, t: int):
         """Tree t (0 start, 1 goal) of the last plan: (q [count, dof] float64,
@@ -434,12 +448,12 @@ class Planner:
 
 
 def batch_opts(groups_per_query=16, max_rounds=500, capacity=2048, max_connect=64,
-               rounds_per_graph=4, **proj) -> BatchOpts:
+               rounds_per_graph=4, flags=0, **proj) -> BatchOpts:
     o = BatchOpts()
     lib().cp_batch_opts_default(C.byref(o))
     o.proj = proj_params(**proj)
     o.groups_per_query, o.max_rounds, o.capacity = groups_per_query, max_rounds, capacity
-    o.max_connect, o.rounds_per_graph = max_connect, rounds_per_graph
+    o.max_connect, o.rounds_per_graph, o.flags = max_connect, rounds_per_graph, flags
     return o
 
 
@@ -454,6 +468,12 @@ class BatchPlanner:
         h = C.c_void_p()
         _check(lib().cp_batch_create(C.byref(self.opts), max_queries, max_dof, C.byref(h)))
         self.handle = h
+
+    def set_warm(self, mlp: "MLP | None"):
+        """Warm-start the extensions with the network (None: off); the
+        queries of a warm batch share one robot and one constraint."""
+        _check(lib().cp_batch_set_warm(self.handle, mlp.handle if mlp is not None else None))
+        self._warm = mlp
 
     def plan(self, queries, max_len: int = 65536, stream=None):
         """queries: list of (Robot, Env, Constraint, start, goal, seed).
@@ -479,7 +499,8 @@ class BatchPlanner:
         st = np.array([status[i] for i in range(n)], np.int32)
         out = [bufs[i][: paths[i].len].copy() if st[i] == CP_OK else None for i in range(n)]
         info = [dict(rounds=stats[i].rounds, nodes=(stats[i].nodes[0], stats[i].nodes[1]),
-                     overflow=stats[i].overflow) for i in range(n)]
+                     overflow=stats[i].overflow, launches_per_round=stats[i].launches_per_round)
+                for i in range(n)]
         return st, out, info
 
     def __del__(self):
@@ -542,6 +563,19 @@ class MLP:
         if getattr(self, "handle", None) and _lib is not None:
             _lib.cp_mlp_destroy(self.handle)
             self.handle = None
+
+
+def warm_pairs(robot: Robot, con: Constraint, W: int, q_from, q_to, xi, n_in: int, stream=None):
+    """cp_warm_pairs: (features [M (W-1), n_in], targets [M (W-1), dof]) of
+    every waypoint k >= 1 of the projected motions xi [M, W, dof]."""
+    import torch
+    M, dof = q_from.shape
+    x = torch.empty((M * (W - 1), n_in), dtype=torch.float32, device=q_from.device)
+    t = torch.empty((M * (W - 1), dof), dtype=torch.float32, device=q_from.device)
+    _check(lib().cp_warm_pairs(robot.handle, C.byref(con), W, M, _dev(q_from, torch.float32),
+                               _dev(q_to, torch.float32), _dev(xi, torch.float32),
+                               _dev(x, torch.float32), _dev(t, torch.float32), _stream(stream)))
+    return x, t
 
 
 def project_motions_warm(robot: Robot, con: Constraint, prm: ProjParams, mlp: MLP, q_from, q_to,

@@ -72,4 +72,12 @@ hipError_t launch_rtc_plan_round(const RtcFns& k, const cp_robot* robot, const E
                                  int sphere_batch, unsigned blocks, size_t lds,
                                  hipStream_t stream);
 void rtc_release(cp_robot* robot);
+// Learned warm start for the planners: CP_OK if the network fits the robot's
+// DOF and constraint kind and has the fused shape (else the error, with its
+// message set); corrections delta [n_segments][W-1][dof] of the straight
+// segments q_from[i] -> q_to[i] ([n_segments][dof]) by the fused network.
+int mlp_warm_check(const cp_mlp* mlp, int dof, int kind);
+hipError_t mlp_warm_corrections(const cp_mlp* mlp, const cp_robot* robot, const ConDev& con, int W,
+                                long n_segments, const float* q_from, const float* q_to,
+                                float* delta, hipStream_t st);
 }  // namespace cprrtc

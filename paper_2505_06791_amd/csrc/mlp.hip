@@ -899,6 +899,31 @@ __global__ void warm_features_kernel(const RobotDev* __restrict__ rob, int W, in
   for (int c = 0; c < n_cp; ++c) o[NDOF + c] = cp[c];
 }
 
+// Training pairs of the warm start from projected motions: row
+// m (W-1) + k - 1 holds the features of waypoint k of motion m (as the
+// warm start computes them) and its target, the projected waypoint minus the
+// straight-line one.
+template <int NDOF>
+__global__ void warm_pairs_kernel(FeatWarm f, long rows, const float* __restrict__ xi,
+                                  float* __restrict__ x, float* __restrict__ t) {
+  const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= rows) return;
+  const int n_in = NDOF + f.n_cp;
+  for (int k0 = 0; k0 < n_in; k0 += 8) {
+    float v[8];
+    f.load(row, k0, n_in, v);
+    for (int i = 0; i < 8 && k0 + i < n_in; ++i) x[row * n_in + k0 + i] = v[i];
+  }
+  const long m = row / (f.W - 1);
+  const int k = (int)(row % (f.W - 1)) + 1;
+  const float s = (float)k / (float)(f.W - 1);
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) {
+    const float a = f.q_from[m * NDOF + j], b = f.q_to[m * NDOF + j];
+    t[row * NDOF + j] = xi[(m * f.W + k) * NDOF + j] - (a + s * (b - a));
+  }
+}
+
 namespace cprrtc {
 // feature count of the warm start for a robot and constraint
 int warm_inputs(int dof, int kind) { return dof + (kind == KIND_REL ? 12 : 6); }
@@ -992,6 +1017,27 @@ hipError_t scratch_address(float** out) {
 }
 
 }  // namespace
+
+namespace cprrtc {
+
+int mlp_warm_check(const cp_mlp* mlp, int dof, int kind) {
+  if (mlp->n_in != warm_inputs(dof, kind) || mlp->n_out != dof)
+    return api_fail(CP_E_ARG, "network has %d inputs / %d outputs, the warm start needs %d / %d",
+                    mlp->n_in, mlp->n_out, warm_inputs(dof, kind), dof);
+  if (!mlp->fusable)
+    return api_fail(CP_E_UNSUPPORTED, "the planners' warm start needs a fused network shape "
+                    "(hidden 64/128/256/512, at most 32 inputs and 16 outputs)");
+  return CP_OK;
+}
+
+hipError_t mlp_warm_corrections(const cp_mlp* mlp, const cp_robot* robot, const ConDev& con, int W,
+                                long n_segments, const float* q_from, const float* q_to,
+                                float* delta, hipStream_t st) {
+  return infer_fused(mlp, warm_feat(robot, con, W, q_from, q_to), n_segments * (W - 1), delta,
+                     robot->host.dof, st);
+}
+
+}  // namespace cprrtc
 
 extern "C" {
 
@@ -1216,6 +1262,37 @@ int project_motions_warm(const cp_robot* robot, const cp_constraint* constraint,
                         d_iters, d_work, flags, st);
   } catch (...) {
     return api_fail(CP_E_ARG, "project_motions_warm: unexpected exception");
+  }
+}
+
+int cp_warm_pairs(const cp_robot* robot, const cp_constraint* constraint, int32_t W,
+                  int32_t n_motions, const float* d_q_from, const float* d_q_to,
+                  const float* d_xi, float* d_x, float* d_t, void* stream) {
+  try {
+    if (!robot) return api_fail(CP_E_ARG, "cp_warm_pairs: NULL robot");
+    if (W < 2 || W > 64 || n_motions < 0) return api_fail(CP_E_ARG, "cp_warm_pairs: W or n_motions out of range");
+    ConDev con;
+    int rc = api_constraint(constraint, robot, &con);
+    if (rc != CP_OK) return rc;
+    if (n_motions == 0) return CP_OK;
+    if (!d_q_from || !d_q_to || !d_xi || !d_x || !d_t) return api_fail(CP_E_ARG, "cp_warm_pairs: NULL buffer");
+    const long rows = (long)n_motions * (W - 1);
+    const FeatWarm f = warm_feat(robot, con, W, d_q_from, d_q_to);
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned nb = nblk(rows);
+    switch (robot->host.dof) {
+      case 2: warm_pairs_kernel<2><<<nb, 256, 0, st>>>(f, rows, d_xi, d_x, d_t); break;
+      case 3: warm_pairs_kernel<3><<<nb, 256, 0, st>>>(f, rows, d_xi, d_x, d_t); break;
+      case 6: warm_pairs_kernel<6><<<nb, 256, 0, st>>>(f, rows, d_xi, d_x, d_t); break;
+      case 7: warm_pairs_kernel<7><<<nb, 256, 0, st>>>(f, rows, d_xi, d_x, d_t); break;
+      case 9: warm_pairs_kernel<9><<<nb, 256, 0, st>>>(f, rows, d_xi, d_x, d_t); break;
+      case 14: warm_pairs_kernel<14><<<nb, 256, 0, st>>>(f, rows, d_xi, d_x, d_t); break;
+      default: return api_fail(CP_E_UNSUPPORTED, "dof %d", robot->host.dof);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_warm_pairs");
+  } catch (...) {
+    return api_fail(CP_E_ARG, "cp_warm_pairs: unexpected exception");
   }
 }
 

@@ -49,6 +49,34 @@ __global__ __launch_bounds__(kPlanBlock) void plan_round_kernel(const RobotDev* 
   plan_extend<NDOF, KIND, B, RobotMem, SELF>(rob, sph, env, con, prm, pd, pd.sample_base, g);
 }
 
+// Warm-started rounds: the first motion of every extension starts from
+// waypoints corrected by the learned network.  A round is three launches:
+// the samples (nearest node, steered end) into seg_from / seg_to / seg_near,
+// the network on those segments (delta [G][W-1][NDOF]), then the extensions
+// from there.  A group whose plan is already done records near = -1.
+template <int NDOF>
+__global__ __launch_bounds__(kPlanBlock) void plan_sample_kernel(const RobotDev* __restrict__ rob,
+                                                                 PlanDev pd, float* __restrict__ seg_from,
+                                                                 float* __restrict__ seg_to,
+                                                                 int* __restrict__ seg_near) {
+  const int g = (int)((blockIdx.x * kPlanBlock + threadIdx.x) >> 6);
+  if (g >= pd.n_groups) return;                  // wavefront-uniform
+  write_sample<NDOF>(rob, pd, pd.sample_base, g, seg_from + (size_t)g * NDOF,
+                     seg_to + (size_t)g * NDOF, seg_near + g);
+}
+
+template <int NDOF, int KIND, int B>
+__global__ __launch_bounds__(kPlanBlock) void plan_round_warm_kernel(
+    const RobotDev* __restrict__ rob, const float4* __restrict__ sph, EnvDev env, ConDev con,
+    ProjDev prm, PlanDev pd, const float* __restrict__ seg_from, const float* __restrict__ seg_to,
+    const int* __restrict__ seg_near, const float* __restrict__ delta) {
+  const int g = (int)((blockIdx.x * kPlanBlock + threadIdx.x) >> 6);
+  if (g >= pd.n_groups) return;                  // wavefront-uniform
+  extend_from_sample<NDOF, KIND, B>(rob, sph, env, con, prm, pd, g, seg_from + (size_t)g * NDOF,
+                                    seg_to + (size_t)g * NDOF, seg_near[g],
+                                    delta + (size_t)g * (prm.W - 1) * NDOF);
+}
+
 // Roots (start in tree 0, goal in tree 1) and counters of a fresh plan.
 __global__ void plan_init_kernel(PlanDev pd, const float* __restrict__ ends, int dof) {
   const int t = threadIdx.x;
@@ -118,6 +146,34 @@ __global__ __launch_bounds__(kPlanBlock) void plan_batch_round_kernel(
   plan_extend<NDOF, KIND, B>(P.rob, P.sph, P.env, P.con, prm, P.pd, *round * (unsigned)groups, g);
 }
 
+// Warm-started batch rounds (every query of one class): samples of
+// wavefront w = query w / groups, group w % groups into segment w.
+template <int NDOF>
+__global__ __launch_bounds__(kPlanBlock) void plan_batch_sample_kernel(
+    const ProblemDev* __restrict__ probs, int n_probs, int groups, const unsigned* __restrict__ round,
+    float* __restrict__ seg_from, float* __restrict__ seg_to, int* __restrict__ seg_near) {
+  const int w = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * kPlanBlock + threadIdx.x) >> 6));
+  const int qi = w / groups, g = w % groups;
+  if (qi >= n_probs) return;                     // wavefront-uniform
+  const ProblemDev& P = probs[qi];
+  write_sample<NDOF>(P.rob, P.pd, *round * (unsigned)groups, g, seg_from + (size_t)w * NDOF,
+                     seg_to + (size_t)w * NDOF, seg_near + w);
+}
+
+template <int NDOF, int KIND, int B>
+__global__ __launch_bounds__(kPlanBlock) void plan_batch_warm_kernel(
+    const ProblemDev* __restrict__ probs, int n_probs, int groups, ProjDev prm,
+    const float* __restrict__ seg_from, const float* __restrict__ seg_to,
+    const int* __restrict__ seg_near, const float* __restrict__ delta) {
+  const int w = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * kPlanBlock + threadIdx.x) >> 6));
+  const int qi = w / groups, g = w % groups;
+  if (qi >= n_probs) return;                     // wavefront-uniform
+  const ProblemDev& P = probs[qi];
+  extend_from_sample<NDOF, KIND, B>(P.rob, P.sph, P.env, P.con, prm, P.pd, g,
+                                    seg_from + (size_t)w * NDOF, seg_to + (size_t)w * NDOF,
+                                    seg_near[w], delta + (size_t)w * (prm.W - 1) * NDOF);
+}
+
 template <int NDOF, int KIND>
 static void launch_batch_class(int batch, unsigned nb, hipStream_t st, const ProblemDev* probs,
                                int n, int groups, const ProjDev& prm, const unsigned* round) {
@@ -141,6 +197,111 @@ static bool launch_batch_round(int dof, int kind, int batch, unsigned nb, hipStr
     case 14 * 4 + KIND_REL: launch_batch_class<14, KIND_REL>(batch, nb, st, probs, n, groups, prm, round); return true;
     default: return false;
   }
+}
+
+// One round of a batch in one launch: every wavefront takes (query, group)
+// tasks from a device counter until none is left and runs the extension
+// with the code of the query's (DOF, constraint kind) class (branch uniform
+// per wavefront); the last wavefront to finish publishes every query's new
+// nodes, advances the round and resets the counters for the next round.
+// Class sets: 0 = DOF 6, 7, 9 without or with a pose constraint; 1 = DOF 14
+// with a pose or relative-pose constraint.  queue[0]: next task,
+// queue[1]: wavefronts finished (both zero when a round starts).
+template <int SET, int B>
+__global__ __launch_bounds__(kPlanBlock) void plan_batch_queue_kernel(
+    ProblemDev* __restrict__ probs, int n_probs, int groups, ProjDev prm,
+    unsigned* __restrict__ round, unsigned* __restrict__ queue, unsigned n_waves) {
+  const int lane = threadIdx.x & 63;
+  const unsigned r = __builtin_amdgcn_readfirstlane(*round);
+  const unsigned total = (unsigned)n_probs * (unsigned)groups;
+  while (true) {
+    unsigned t = 0;
+    if (lane == 0) t = atomicAdd(&queue[0], 1u);
+    t = __builtin_amdgcn_readfirstlane(t);
+    if (t >= total) break;
+    const int qi = (int)(t / (unsigned)groups), g = (int)(t % (unsigned)groups);
+    const ProblemDev& P = probs[qi];
+    const unsigned base = r * (unsigned)groups;
+#define CP_QUEUE_CASE(ND, K)                                                   \
+  case ND * 4 + K:                                                             \
+    plan_extend<ND, K, B>(P.rob, P.sph, P.env, P.con, prm, P.pd, base, g);   \
+    break;
+    if constexpr (SET == 0) {
+      switch (P.dof * 4 + P.con.kind) {
+        CP_QUEUE_CASE(6, KIND_NONE)
+        CP_QUEUE_CASE(6, KIND_POSE)
+        CP_QUEUE_CASE(7, KIND_NONE)
+        CP_QUEUE_CASE(7, KIND_POSE)
+        CP_QUEUE_CASE(9, KIND_NONE)
+        CP_QUEUE_CASE(9, KIND_POSE)
+        default: break;
+      }
+    } else {
+      switch (P.dof * 4 + P.con.kind) {
+        CP_QUEUE_CASE(14, KIND_POSE)
+        CP_QUEUE_CASE(14, KIND_REL)
+        default: break;
+      }
+    }
+#undef CP_QUEUE_CASE
+  }
+  // the last wavefront out publishes (all appends of the round are done)
+  __threadfence();
+  unsigned fin = 0;
+  if (lane == 0) fin = atomicAdd(&queue[1], 1u);
+  fin = __builtin_amdgcn_readfirstlane(fin);
+  if (fin == n_waves - 1) {
+    __threadfence();
+    for (int i = lane; i < n_probs; i += 64) {
+      int* ctl = probs[i].pd.ctl;
+      const int cap = probs[i].pd.cap;
+      ctl[kCtlPublished + 0] = min(atomicAdd(&ctl[kCtlCount + 0], 0), cap);
+      ctl[kCtlPublished + 1] = min(atomicAdd(&ctl[kCtlCount + 1], 0), cap);
+    }
+    if (lane == 0) {
+      *round = r + 1u;
+      queue[0] = 0u;
+      queue[1] = 0u;
+    }
+  }
+}
+
+template <int NDOF, int KIND>
+static void launch_batch_warm_class(int batch, unsigned nb, hipStream_t st, const ProblemDev* probs,
+                                    int n, int groups, const ProjDev& prm, const float* f,
+                                    const float* t, const int* nr, const float* delta) {
+  if (batch == 4)
+    plan_batch_warm_kernel<NDOF, KIND, 4><<<nb, kPlanBlock, 0, st>>>(probs, n, groups, prm, f, t, nr, delta);
+  else
+    plan_batch_warm_kernel<NDOF, KIND, 8><<<nb, kPlanBlock, 0, st>>>(probs, n, groups, prm, f, t, nr, delta);
+}
+
+// One warm-started batch round for the queries of one class: samples, the
+// network, extensions.
+static bool launch_batch_warm_round(int dof, int kind, int batch, unsigned nb, hipStream_t st,
+                                    const ProblemDev* probs, int n, int groups, const ProjDev& prm,
+                                    const unsigned* round, float* f, float* t, int* nr,
+                                    float* delta, const cp_mlp* mlp, const cp_robot* robot,
+                                    const ConDev& con, hipError_t* he) {
+#define CP_BATCH_WARM(ND, K)                                                                          \
+  {                                                                                                   \
+    plan_batch_sample_kernel<ND><<<nb, kPlanBlock, 0, st>>>(probs, n, groups, round, f, t, nr);       \
+    *he = mlp_warm_corrections(mlp, robot, con, prm.W, (long)n * groups, f, t, delta, st);            \
+    launch_batch_warm_class<ND, K>(batch, nb, st, probs, n, groups, prm, f, t, nr, delta);            \
+    return true;                                                                                      \
+  }
+  switch (dof * 4 + kind) {
+    case 6 * 4 + KIND_NONE: CP_BATCH_WARM(6, KIND_NONE)
+    case 6 * 4 + KIND_POSE: CP_BATCH_WARM(6, KIND_POSE)
+    case 7 * 4 + KIND_NONE: CP_BATCH_WARM(7, KIND_NONE)
+    case 7 * 4 + KIND_POSE: CP_BATCH_WARM(7, KIND_POSE)
+    case 9 * 4 + KIND_NONE: CP_BATCH_WARM(9, KIND_NONE)
+    case 9 * 4 + KIND_POSE: CP_BATCH_WARM(9, KIND_POSE)
+    case 14 * 4 + KIND_POSE: CP_BATCH_WARM(14, KIND_POSE)
+    case 14 * 4 + KIND_REL: CP_BATCH_WARM(14, KIND_REL)
+    default: return false;
+  }
+#undef CP_BATCH_WARM
 }
 
 __global__ void publish_batch_kernel(ProblemDev* probs, int n_probs, unsigned* round) {
@@ -226,6 +387,51 @@ static bool launch_round_ndof(int kind, int batch, unsigned nb, hipStream_t st, 
   return false;
 }
 
+template <int NDOF>
+static bool launch_warm_ndof(int kind, int batch, unsigned nb, hipStream_t st, const RobotDev* rob,
+                             const float4* sph, const EnvDev& env, const ConDev& con,
+                             const ProjDev& prm, const PlanDev& pd, float* f, float* t, int* nr,
+                             float* delta, const cp_mlp* mlp, const cp_robot* robot,
+                             hipError_t* he) {
+  if (kind == KIND_REL && NDOF % 2 != 0) return false;
+  plan_sample_kernel<NDOF><<<nb, kPlanBlock, 0, st>>>(rob, pd, f, t, nr);
+  *he = mlp_warm_corrections(mlp, robot, con, prm.W, pd.n_groups, f, t, delta, st);
+#define CP_WARM_KIND(K)                                                                              \
+  if (batch == 4)                                                                                    \
+    plan_round_warm_kernel<NDOF, K, 4><<<nb, kPlanBlock, 0, st>>>(rob, sph, env, con, prm, pd, f, t, nr, delta); \
+  else                                                                                               \
+    plan_round_warm_kernel<NDOF, K, 8><<<nb, kPlanBlock, 0, st>>>(rob, sph, env, con, prm, pd, f, t, nr, delta);
+  switch (kind) {
+    case KIND_NONE: CP_WARM_KIND(KIND_NONE) return true;
+    case KIND_POSE: CP_WARM_KIND(KIND_POSE) return true;
+    case KIND_REL:
+      if constexpr (NDOF % 2 == 0) {
+        CP_WARM_KIND(KIND_REL)
+        return true;
+      }
+      return false;
+  }
+#undef CP_WARM_KIND
+  return false;
+}
+
+// One warm-started round of a single query: samples, network, extensions.
+static bool launch_warm_round(int dof, int kind, int batch, unsigned nb, hipStream_t st,
+                              const RobotDev* rob, const float4* sph, const EnvDev& env,
+                              const ConDev& con, const ProjDev& prm, const PlanDev& pd, float* f,
+                              float* t, int* nr, float* delta, const cp_mlp* mlp,
+                              const cp_robot* robot, hipError_t* he) {
+  switch (dof) {
+    case 2: return launch_warm_ndof<2>(kind, batch, nb, st, rob, sph, env, con, prm, pd, f, t, nr, delta, mlp, robot, he);
+    case 3: return launch_warm_ndof<3>(kind, batch, nb, st, rob, sph, env, con, prm, pd, f, t, nr, delta, mlp, robot, he);
+    case 6: return launch_warm_ndof<6>(kind, batch, nb, st, rob, sph, env, con, prm, pd, f, t, nr, delta, mlp, robot, he);
+    case 7: return launch_warm_ndof<7>(kind, batch, nb, st, rob, sph, env, con, prm, pd, f, t, nr, delta, mlp, robot, he);
+    case 9: return launch_warm_ndof<9>(kind, batch, nb, st, rob, sph, env, con, prm, pd, f, t, nr, delta, mlp, robot, he);
+    case 14: return launch_warm_ndof<14>(kind, batch, nb, st, rob, sph, env, con, prm, pd, f, t, nr, delta, mlp, robot, he);
+    default: return false;
+  }
+}
+
 static bool launch_round(int dof, int kind, int batch, unsigned nb, hipStream_t st,
                          const RobotDev* rob, const float4* sph, const EnvDev& env,
                          const ConDev& con, const ProjDev& prm, const PlanDev& pd, size_t lds) {
@@ -264,6 +470,12 @@ struct cp_planner {
   int* cfg_status = nullptr;
   uint8_t* cfg_col = nullptr;
   float* cfg_sd = nullptr;
+  // learned warm start (cp_planner_set_warm): the network and its round buffers
+  const cp_mlp* warm = nullptr;
+  float* seg_from = nullptr;  // [n_groups][dof]
+  float* seg_to = nullptr;    // [n_groups][dof]
+  int* seg_near = nullptr;    // [n_groups]
+  float* delta = nullptr;     // [n_groups][W-1][dof]
 };
 
 namespace {
@@ -292,6 +504,8 @@ void free_planner(cp_planner* p) {
   if (p->cfg_status) (void)hipFree(p->cfg_status);
   if (p->cfg_col) (void)hipFree(p->cfg_col);
   if (p->cfg_sd) (void)hipFree(p->cfg_sd);
+  for (void* b : {(void*)p->seg_from, (void*)p->seg_to, (void*)p->seg_near, (void*)p->delta})
+    if (b) (void)hipFree(b);
   delete p;
 }
 
@@ -367,6 +581,28 @@ int cp_planner_create(const cp_robot* robot, const cp_plan_opts* opts, cp_planne
 }
 
 void cp_planner_destroy(cp_planner* p) { free_planner(p); }
+
+int cp_planner_set_warm(cp_planner* pl, const cp_mlp* mlp) {
+  try {
+    if (!pl) return api_fail(CP_E_ARG, "cp_planner_set_warm: NULL planner");
+    if (mlp && (pl->opts.flags & CP_SELF_COLLISION))
+      return api_fail(CP_E_UNSUPPORTED, "cp_planner_set_warm: warm-started rounds do not check self-collision");
+    if (mlp && pl->opts.proj.variant != CP_PROJECT_PARALLEL)
+      return api_fail(CP_E_UNSUPPORTED, "cp_planner_set_warm: the warm start serves the parallel projector only");
+    if (mlp && !pl->seg_from) {
+      const size_t G = pl->opts.n_groups, n = pl->dof, W = pl->opts.proj.W;
+      hipError_t e = hipMalloc((void**)&pl->seg_from, sizeof(float) * G * n);
+      if (e == hipSuccess) e = hipMalloc((void**)&pl->seg_to, sizeof(float) * G * n);
+      if (e == hipSuccess) e = hipMalloc((void**)&pl->seg_near, sizeof(int) * G);
+      if (e == hipSuccess) e = hipMalloc((void**)&pl->delta, sizeof(float) * G * (W - 1) * n);
+      if (e != hipSuccess) return api_hip_fail(e, "cp_planner_set_warm");
+    }
+    pl->warm = mlp;
+    return CP_OK;
+  } catch (...) {
+    return api_fail(CP_E_ARG, "cp_planner_set_warm: unexpected exception");
+  }
+}
 
 int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
             const double* start, const double* goal, uint64_t seed, cp_path* out,
@@ -476,13 +712,25 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
 
     int rounds = 0;
     bool done = false;
+    if (pl->warm) {
+      rc = mlp_warm_check(pl->warm, n, con.kind);
+      if (rc != CP_OK) return rc;
+    }
     // the round kernel compiled for this robot and mask (cp_robot_specialize), if any
+    // (warm-started rounds use the library's kernels)
     RtcFns rk;
-    const bool use_rtc = rtc_find(const_cast<cp_robot*>(robot), con, &rk) && rk.plan[0] &&
-                         lds == 0;   // (compiled without the self-check)
+    const bool use_rtc = !pl->warm && rtc_find(const_cast<cp_robot*>(robot), con, &rk) &&
+                         rk.plan[0] && lds == 0;   // (compiled without the self-check)
     while (rounds < o.max_rounds && !done) {
       pd.sample_base = (unsigned)rounds * (unsigned)o.n_groups;
-      if (use_rtc) {
+      if (pl->warm) {
+        hipError_t we = hipSuccess;
+        if (!launch_warm_round(n, con.kind, pp.sphere_batch, nb, st, robot->dev, robot->spheres,
+                               env->view, con, prm, pd, pl->seg_from, pl->seg_to, pl->seg_near,
+                               pl->delta, pl->warm, robot, &we))
+          return api_fail(CP_E_UNSUPPORTED, "no planning kernel for dof %d, constraint kind %d", n, con.kind);
+        if (we != hipSuccess) return api_hip_fail(we, "cp_plan warm-start network");
+      } else if (use_rtc) {
         he = launch_rtc_plan_round(rk, robot, env->view, con, prm, pd, pp.sphere_batch, nb, lds,
                                    st);
         if (he != hipSuccess) return api_hip_fail(he, "cp_plan round (run-time compiled kernel)");
@@ -505,6 +753,7 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
     const int* hc = pl->host_ctl;
     if (stats) {
       stats->rounds = rounds;
+      stats->launches_per_round = pl->warm ? 4 : 2;
       stats->nodes[0] = std::min(hc[kCtlCount + 0], o.capacity);
       stats->nodes[1] = std::min(hc[kCtlCount + 1], o.capacity);
       stats->overflow = hc[kCtlOverflow];
@@ -613,6 +862,7 @@ void cp_batch_opts_default(cp_batch_opts* o) {
   o->capacity = 2048;
   o->max_connect = 64;
   o->rounds_per_graph = 4;
+  o->flags = 0;
 }
 
 }  // extern "C"
@@ -626,6 +876,7 @@ struct cp_batch {
   float* scratch = nullptr;    // [Q][G][W][max_dof]
   int* ctl = nullptr;          // [Q][kCtlInts]
   unsigned* round = nullptr;   // device round counter
+  unsigned* queue = nullptr;   // device task counter and finished-wavefront count
   ProblemDev* probs = nullptr; // [Q]
   int* host_ctl = nullptr;     // pinned [Q][kCtlInts]
   float* ends = nullptr;       // [Q][2][max_dof] endpoint scratch
@@ -635,6 +886,12 @@ struct cp_batch {
   uint8_t* cfg_col = nullptr;  // [2Q]
   float* cfg_sd = nullptr;     // [2Q]
   hipStream_t stream = nullptr;
+  // learned warm start (cp_batch_set_warm): the network and its round buffers
+  const cp_mlp* warm = nullptr;
+  float* seg_from = nullptr;   // [Q * G][max_dof]
+  float* seg_to = nullptr;
+  int* seg_near = nullptr;     // [Q * G]
+  float* delta = nullptr;      // [Q * G][W-1][max_dof]
 };
 
 namespace {
@@ -642,8 +899,9 @@ namespace {
 void free_batch(cp_batch* b) {
   if (!b) return;
   for (void* p : {(void*)b->q, (void*)b->parent, (void*)b->edge, (void*)b->scratch, (void*)b->ctl,
-                  (void*)b->round, (void*)b->probs, (void*)b->ends, (void*)b->ends_off,
-                  (void*)b->cfg_out, (void*)b->cfg_status, (void*)b->cfg_col, (void*)b->cfg_sd})
+                  (void*)b->round, (void*)b->queue, (void*)b->probs, (void*)b->ends, (void*)b->ends_off,
+                  (void*)b->cfg_out, (void*)b->cfg_status, (void*)b->cfg_col, (void*)b->cfg_sd,
+                  (void*)b->seg_from, (void*)b->seg_to, (void*)b->seg_near, (void*)b->delta})
     if (p) (void)hipFree(p);
   if (b->host_ctl) (void)hipHostFree(b->host_ctl);
   if (b->stream) (void)hipStreamDestroy(b->stream);
@@ -675,7 +933,7 @@ int cp_batch_create(const cp_batch_opts* opts, int32_t max_queries, int32_t max_
     if (max_queries < 1 || max_queries > 65536 || max_dof < 1 || max_dof > kMaxDof)
       return api_fail(CP_E_ARG, "cp_batch_create: max_queries or max_dof out of range");
     if (o.groups_per_query < 2 || o.capacity < 2 || o.max_rounds < 1 || o.max_connect < 0 ||
-        o.rounds_per_graph < 1 || o.rounds_per_graph > 64)
+        o.rounds_per_graph < 1 || o.rounds_per_graph > 64 || (o.flags & ~CP_BATCH_PER_CLASS))
       return api_fail(CP_E_ARG, "cp_batch_create: options out of range");
     cp_batch* b = new (std::nothrow) cp_batch;
     if (!b) return api_fail(CP_E_ARG, "out of host memory");
@@ -689,6 +947,7 @@ int cp_batch_create(const cp_batch_opts* opts, int32_t max_queries, int32_t max_
     if (e == hipSuccess) e = hipMalloc((void**)&b->scratch, sizeof(float) * Q * Gq * W * D);
     if (e == hipSuccess) e = hipMalloc((void**)&b->ctl, sizeof(int) * Q * kCtlInts);
     if (e == hipSuccess) e = hipMalloc((void**)&b->round, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->queue, sizeof(unsigned) * 2);
     if (e == hipSuccess) e = hipMalloc((void**)&b->probs, sizeof(ProblemDev) * Q);
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->host_ctl, sizeof(int) * Q * kCtlInts, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void**)&b->ends, sizeof(float) * Q * 2 * D);
@@ -710,6 +969,27 @@ int cp_batch_create(const cp_batch_opts* opts, int32_t max_queries, int32_t max_
 }
 
 void cp_batch_destroy(cp_batch* b) { free_batch(b); }
+
+int cp_batch_set_warm(cp_batch* b, const cp_mlp* mlp) {
+  try {
+    if (!b) return api_fail(CP_E_ARG, "cp_batch_set_warm: NULL batch");
+    if (mlp && b->opts.proj.variant != CP_PROJECT_PARALLEL)
+      return api_fail(CP_E_UNSUPPORTED, "cp_batch_set_warm: the warm start serves the parallel projector only");
+    if (mlp && !b->seg_from) {
+      const size_t QG = (size_t)b->max_queries * b->opts.groups_per_query, D = b->max_dof,
+                   W = b->opts.proj.W;
+      hipError_t e = hipMalloc((void**)&b->seg_from, sizeof(float) * QG * D);
+      if (e == hipSuccess) e = hipMalloc((void**)&b->seg_to, sizeof(float) * QG * D);
+      if (e == hipSuccess) e = hipMalloc((void**)&b->seg_near, sizeof(int) * QG);
+      if (e == hipSuccess) e = hipMalloc((void**)&b->delta, sizeof(float) * QG * (W - 1) * D);
+      if (e != hipSuccess) return api_hip_fail(e, "cp_batch_set_warm");
+    }
+    b->warm = mlp;
+    return CP_OK;
+  } catch (...) {
+    return api_fail(CP_E_ARG, "cp_batch_set_warm: unexpected exception");
+  }
+}
 
 int cp_plan_batch(cp_batch* b, int32_t n, const cp_query* queries, cp_path* paths,
                   int32_t* status, cp_plan_stats* stats, void* caller_stream) {
@@ -802,6 +1082,14 @@ int cp_plan_batch(cp_batch* b, int32_t n, const cp_query* queries, cp_path* path
         if (!(qq.goal[j] >= qq.robot->host.lo[j] && qq.goal[j] <= qq.robot->host.hi[j]) && status[i] == CP_OK) status[i] = CP_E_GOAL;
       }
     }
+    // a warm-started batch: one network serves one robot and one constraint
+    if (b->warm) {
+      for (int i = 1; i < n; ++i)
+        if (queries[i].robot != queries[0].robot || std::memcmp(&probs[i].con, &probs[0].con, sizeof(ConDev)) != 0)
+          return api_fail(CP_E_UNSUPPORTED, "cp_plan_batch: a warm-started batch needs one robot and one constraint (query %d differs)", perm[i]);
+      int rc = mlp_warm_check(b->warm, probs[0].dof, probs[0].con.kind);
+      if (rc != CP_OK) return rc;
+    }
     he = hipMemcpyAsync(b->ends, ends.data(), sizeof(float) * ends.size(), hipMemcpyHostToDevice, st);
     if (he == hipSuccess) he = hipMemcpyAsync(b->ends_off, ends_off.data(), sizeof(int) * n, hipMemcpyHostToDevice, st);
     // endpoints on the manifold and collision-free (device checks per query)
@@ -843,8 +1131,9 @@ int cp_plan_batch(cp_batch* b, int32_t n, const cp_query* queries, cp_path* path
         if (he == hipSuccess) he = hipStreamSynchronize(st);
       }
     }
-    const unsigned zero = 0;
+    const unsigned zero = 0, zeros[2] = {0, 0};
     if (he == hipSuccess) he = hipMemcpyAsync(b->round, &zero, sizeof zero, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(b->queue, zeros, sizeof zeros, hipMemcpyHostToDevice, st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
     if (he != hipSuccess) return api_hip_fail(he, "cp_plan_batch init");
 
@@ -858,21 +1147,68 @@ int cp_plan_batch(cp_batch* b, int32_t n, const cp_query* queries, cp_path* path
       k = e2;
     }
     const int R = o.rounds_per_graph;
+    // one launch per round over the task queue when every class is in one set
+    int set = -1;
+    for (const auto& rg : ranges) {
+      const int d = probs[rg.first].dof, k = probs[rg.first].con.kind;
+      const int cs = (d == 14) ? 1 : (d == 6 || d == 7 || d == 9) ? 0 : 2;
+      set = set < 0 ? cs : (set == cs ? set : 2);
+    }
+    const bool queued = !b->warm && !(o.flags & CP_BATCH_PER_CLASS) && (set == 0 || set == 1);
+    unsigned q_blocks = 0;
+    if (queued) {
+      int per_cu = 0, cus = 0;
+      hipError_t oe = set == 0
+          ? (pp.sphere_batch == 4
+                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, plan_batch_queue_kernel<0, 4>, kPlanBlock, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, plan_batch_queue_kernel<0, 8>, kPlanBlock, 0))
+          : (pp.sphere_batch == 4
+                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, plan_batch_queue_kernel<1, 4>, kPlanBlock, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, plan_batch_queue_kernel<1, 8>, kPlanBlock, 0));
+      int dev = 0;
+      if (oe == hipSuccess) oe = hipGetDevice(&dev);
+      if (oe == hipSuccess) oe = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (oe != hipSuccess) return api_hip_fail(oe, "cp_plan_batch occupancy");
+      const long tasks = (long)n * Gq;
+      const long resident = (long)std::max(per_cu, 1) * std::max(cus, 1);
+      q_blocks = (unsigned)std::max(1L, std::min(resident, (tasks * 64 + kPlanBlock - 1) / kPlanBlock));
+    }
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     he = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-    if (he == hipSuccess) {
+    if (he == hipSuccess && queued) {
+      const unsigned waves = q_blocks * (kPlanBlock / 64);
+      for (int r = 0; r < R; ++r) {
+        if (set == 0 && pp.sphere_batch == 4)
+          plan_batch_queue_kernel<0, 4><<<q_blocks, kPlanBlock, 0, st>>>(b->probs, n, Gq, prm, b->round, b->queue, waves);
+        else if (set == 0)
+          plan_batch_queue_kernel<0, 8><<<q_blocks, kPlanBlock, 0, st>>>(b->probs, n, Gq, prm, b->round, b->queue, waves);
+        else if (pp.sphere_batch == 4)
+          plan_batch_queue_kernel<1, 4><<<q_blocks, kPlanBlock, 0, st>>>(b->probs, n, Gq, prm, b->round, b->queue, waves);
+        else
+          plan_batch_queue_kernel<1, 8><<<q_blocks, kPlanBlock, 0, st>>>(b->probs, n, Gq, prm, b->round, b->queue, waves);
+      }
+      he = hipStreamEndCapture(st, &graph);
+    } else if (he == hipSuccess) {
+      hipError_t we = hipSuccess;
       for (int r = 0; r < R; ++r) {
         for (const auto& rg : ranges) {
           const int cnt = rg.second - rg.first;
           const long waves = (long)cnt * Gq;
           const unsigned nb = (unsigned)((waves * 64 + kPlanBlock - 1) / kPlanBlock);
-          launch_batch_round(probs[rg.first].dof, probs[rg.first].con.kind, pp.sphere_batch, nb, st,
-                             b->probs + rg.first, cnt, Gq, prm, b->round);
+          if (b->warm)
+            launch_batch_warm_round(probs[rg.first].dof, probs[rg.first].con.kind, pp.sphere_batch, nb,
+                                    st, b->probs + rg.first, cnt, Gq, prm, b->round, b->seg_from,
+                                    b->seg_to, b->seg_near, b->delta, b->warm, queries[0].robot,
+                                    probs[0].con, &we);
+          else
+            launch_batch_round(probs[rg.first].dof, probs[rg.first].con.kind, pp.sphere_batch, nb, st,
+                               b->probs + rg.first, cnt, Gq, prm, b->round);
         }
         publish_batch_kernel<<<(n + 255) / 256, 256, 0, st>>>(b->probs, n, b->round);
       }
       he = hipStreamEndCapture(st, &graph);
+      if (he == hipSuccess && we != hipSuccess) he = we;
     }
     if (he == hipSuccess) he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (he != hipSuccess) {
@@ -911,6 +1247,7 @@ int cp_plan_batch(cp_batch* b, int32_t n, const cp_query* queries, cp_path* path
     for (int i = 0; i < n; ++i) {
       const int* hc = b->host_ctl + (size_t)i * kCtlInts;
       stats_k[i].rounds = done_round[i] >= 0 ? done_round[i] : rounds;
+      stats_k[i].launches_per_round = queued ? 1 : b->warm ? 4 : (int)ranges.size() + 1;
       stats_k[i].nodes[0] = std::min(hc[kCtlCount + 0], o.capacity);
       stats_k[i].nodes[1] = std::min(hc[kCtlCount + 1], o.capacity);
       stats_k[i].overflow = hc[kCtlOverflow];

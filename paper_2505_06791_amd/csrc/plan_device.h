@@ -154,12 +154,16 @@ __device__ __forceinline__ bool self_collides(const RobotDev* __restrict__ rob,
 // One motion a -> b on this wavefront (lanes 0..W-1), projected and
 // validated (with n_self > 0 also against the robot itself).  q: this
 // lane's projected waypoint; end: xi[W-1] broadcast.
+// delta (nullable): the learned warm start's corrections of waypoints
+// 1..W-1 ([W-1][NDOF]); the segment is first projected from the corrected
+// waypoints and, if that fails, again from the straight line.
 template <int NDOF, int KIND, int B, class P = RobotMem, bool SELF = false>
 __device__ __forceinline__ bool try_motion(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
                            const EnvDev& env, const ConDev& con, const ProjDev& prm,
                            float* __restrict__ scratch, const int2* __restrict__ self_pairs,
                            int n_self, const float (&a)[NDOF],
-                           const float (&b)[NDOF], float (&q)[NDOF], float (&end)[NDOF]) {
+                           const float (&b)[NDOF], float (&q)[NDOF], float (&end)[NDOF],
+                           const float* __restrict__ delta = nullptr) {
   const int W = prm.W;
   const int lane = threadIdx.x & 63;
   const int k = lane % W;
@@ -168,15 +172,28 @@ __device__ __forceinline__ bool try_motion(const RobotDev* __restrict__ rob, con
   const uint64_t wmask = (W == 64) ? ~0ull : ((1ull << W) - 1ull);
   const uint64_t segmask = wmask << seg;
   const float s = (float)k / (float)(W - 1);
-#pragma unroll
-  for (int j = 0; j < NDOF; ++j) q[j] = a[j] + s * (b[j] - a[j]);
   int iters = 0;
   unsigned long long updates = 0;
-  const bool ok =
-      prm.variant == CP_PROJECT_SEQUENTIAL
-          ? project_sequential<NDOF, KIND>(rob, con, prm, k, seg, !in_motion, q, iters, updates)
-          : project_segment<NDOF, KIND, P>(rob, con, prm, k, seg, wmask, segmask, !in_motion, q,
-                                           iters, updates);
+  bool ok = false;
+  if (delta != nullptr) {
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) {
+      q[j] = a[j] + s * (b[j] - a[j]);
+      if (in_motion && k >= 1)
+        q[j] = fminf(fmaxf(q[j] + delta[(k - 1) * NDOF + j], P::lo(rob, j)), P::hi(rob, j));
+    }
+    ok = project_segment<NDOF, KIND, P>(rob, con, prm, k, seg, wmask, segmask, !in_motion, q,
+                                        iters, updates);
+    ok = __shfl(ok ? 1 : 0, 0, 64) != 0;
+  }
+  if (!ok) {
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) q[j] = a[j] + s * (b[j] - a[j]);
+    ok = prm.variant == CP_PROJECT_SEQUENTIAL
+             ? project_sequential<NDOF, KIND>(rob, con, prm, k, seg, !in_motion, q, iters, updates)
+             : project_segment<NDOF, KIND, P>(rob, con, prm, k, seg, wmask, segmask, !in_motion, q,
+                                              iters, updates);
+  }
   if (!__shfl(ok ? 1 : 0, 0, 64)) return false;
   float* xk = scratch + (size_t)(in_motion ? lane : 0) * NDOF;
   if (in_motion) {
@@ -247,19 +264,15 @@ __device__ __forceinline__ bool plan_done(const PlanDev& pd) {
   return __atomic_load_n(&pd.ctl[kCtlDone], __ATOMIC_RELAXED) != 0;
 }
 
-// One tree extension of one wavefront (group g of the round): sample, grow
-// the group's tree by one motion, then towards the other tree.
-template <int NDOF, int KIND, int B, class P = RobotMem, bool SELF = false>
-__device__ __forceinline__ void plan_extend(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
-                            const EnvDev& env, const ConDev& con, const ProjDev& prm,
-                            const PlanDev& pd, unsigned sample_base, int g) {
+// The extension's sample (Halton point of group g, tree g & 1), its
+// nearest published node and the steered end: q_near = node `near`, q_steer.
+template <int NDOF, class P = RobotMem>
+__device__ __forceinline__ int plan_sample(const RobotDev* __restrict__ rob, const PlanDev& pd,
+                                           unsigned sample_base, int g, float (&qn)[NDOF],
+                                           float (&qs)[NDOF]) {
   const int lane = threadIdx.x & 63;
-  if (__shfl(plan_done(pd) ? 1 : 0, 0, 64)) return;
-  const int W = prm.W;
-  const int X = g & 1, Y = X ^ 1;               // half the wavefronts grow each tree
-  const int pubX = pd.ctl[kCtlPublished + X], pubY = pd.ctl[kCtlPublished + Y];
-  float* scratch = pd.scratch + (size_t)g * W * NDOF;
-
+  const int X = g & 1;                          // half the wavefronts grow each tree
+  const int pubX = pd.ctl[kCtlPublished + X];
   // Halton sample: lane j computes coordinate j, then every lane takes all.
   float u = 0.0f;
   if (lane < NDOF) {
@@ -269,14 +282,29 @@ __device__ __forceinline__ void plan_extend(const RobotDev* __restrict__ rob, co
   float qr[NDOF];
 #pragma unroll
   for (int j = 0; j < NDOF; ++j) qr[j] = P::lo(rob, j) + __shfl(u, j, 64) * (P::hi(rob, j) - P::lo(rob, j));
-
   float d2;
   const int near = nearest_node<NDOF>(pd.q[X], pubX, pd.cap, qr, d2);
-  float qn[NDOF], qs[NDOF], q[NDOF], qe[NDOF];
   load_node<NDOF>(pd, X, near, qn);
   steer<NDOF>(qn, qr, pd.step, qs);
+  return near;
+}
+
+// The rest of an extension after its sample: the motion q_near -> q_steer
+// (warm-started when delta, [W-1][NDOF], is given), its append, then the
+// connect loop towards the nearest node of the other tree (plain projection).
+template <int NDOF, int KIND, int B, class P = RobotMem, bool SELF = false>
+__device__ __forceinline__ void plan_extend_from(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
+                            const EnvDev& env, const ConDev& con, const ProjDev& prm,
+                            const PlanDev& pd, int g, int near, const float (&qn)[NDOF],
+                            const float (&qs0)[NDOF], const float* __restrict__ delta) {
+  const int lane = threadIdx.x & 63;
+  const int W = prm.W;
+  const int X = g & 1, Y = X ^ 1;
+  const int pubY = pd.ctl[kCtlPublished + Y];
+  float* scratch = pd.scratch + (size_t)g * W * NDOF;
+  float qs[NDOF], q[NDOF], qe[NDOF], d2;
   if (!try_motion<NDOF, KIND, B, P, SELF>(rob, sph, env, con, prm, scratch, pd.self_pairs, pd.n_self, qn,
-                                    qs, q, qe)) return;
+                                    qs0, q, qe, delta)) return;
   int cur = append_node<NDOF>(pd, W, X, near, q);
   if (cur < 0) return;
 
@@ -308,6 +336,64 @@ __device__ __forceinline__ void plan_extend(const RobotDev* __restrict__ rob, co
     for (int j = 0; j < NDOF; ++j) qe[j] = qe2[j];
     dcur = dnew;
   }
+}
+
+
+// One tree extension of one wavefront (group g of the round): sample, grow
+// the group's tree by one motion, then towards the other tree.
+template <int NDOF, int KIND, int B, class P = RobotMem, bool SELF = false>
+__device__ __forceinline__ void plan_extend(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
+                            const EnvDev& env, const ConDev& con, const ProjDev& prm,
+                            const PlanDev& pd, unsigned sample_base, int g) {
+  if (__shfl(plan_done(pd) ? 1 : 0, 0, 64)) return;
+  float qn[NDOF], qs[NDOF];
+  const int near = plan_sample<NDOF, P>(rob, pd, sample_base, g, qn, qs);
+  plan_extend_from<NDOF, KIND, B, P, SELF>(rob, sph, env, con, prm, pd, g, near, qn, qs, nullptr);
+}
+
+// Warm-started rounds, first half: the sample of group g (its nearest node
+// and steered end) written for the network; near = -1 when the plan is done.
+template <int NDOF>
+__device__ __forceinline__ void write_sample(const RobotDev* __restrict__ rob, const PlanDev& pd,
+                                             unsigned sample_base, int g, float* __restrict__ from,
+                                             float* __restrict__ to, int* __restrict__ near_out) {
+  const int lane = threadIdx.x & 63;
+  float qn[NDOF], qs[NDOF];
+  int near = -1;
+  if (!__shfl(plan_done(pd) ? 1 : 0, 0, 64)) {
+    near = plan_sample<NDOF>(rob, pd, sample_base, g, qn, qs);
+  } else {
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) qn[j] = qs[j] = 0.0f;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NDOF; ++j) {
+      from[j] = qn[j];
+      to[j] = qs[j];
+    }
+    *near_out = near;
+  }
+}
+
+// Warm-started rounds, second half: the extension from the recorded sample,
+// its first motion corrected by delta ([W-1][NDOF]).
+template <int NDOF, int KIND, int B>
+__device__ __forceinline__ void extend_from_sample(const RobotDev* __restrict__ rob,
+                                                   const float4* __restrict__ sph, const EnvDev& env,
+                                                   const ConDev& con, const ProjDev& prm,
+                                                   const PlanDev& pd, int g,
+                                                   const float* __restrict__ from,
+                                                   const float* __restrict__ to, int near,
+                                                   const float* __restrict__ delta) {
+  if (near < 0 || __shfl(plan_done(pd) ? 1 : 0, 0, 64)) return;
+  float qn[NDOF], qs[NDOF];
+#pragma unroll
+  for (int j = 0; j < NDOF; ++j) {
+    qn[j] = from[j];
+    qs[j] = to[j];
+  }
+  plan_extend_from<NDOF, KIND, B>(rob, sph, env, con, prm, pd, g, near, qn, qs, delta);
 }
 
 }  // namespace cprrtc

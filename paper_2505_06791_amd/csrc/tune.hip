@@ -1,5 +1,6 @@
 // Launch-shape autotuner: times project_validate_motions on the caller's
-// sample motions for every candidate (W, sphere batch 4 / 8 / 16) and keeps
+// sample motions for every candidate (W, sphere batch 4 / 8 / 16, or 4 / 8
+// for the planners' round kernels) and keeps
 // the fastest by validated-waypoint throughput.
 #include <hip/hip_runtime.h>
 
@@ -78,7 +79,7 @@ int cp_autotune(const cp_robot* robot, const cp_env* env, const cp_constraint* c
         rc = api_hip_fail(e, "cp_autotune rescale");
         break;
       }
-      for (int bi = 0; bi < 3 && rc == CP_OK; ++bi) {
+      for (int bi = 0; bi < ((flags & CP_TUNE_PLANNER) ? 2 : 3) && rc == CP_OK; ++bi) {
         cp_proj_params p = base;
         p.W = W;
         p.sphere_batch = Bs[bi];

@@ -2,7 +2,8 @@
 
 Pairs (waypoint of a straight-line segment, constraint parameters) ->
 (its projected value - the waypoint), taken from motions the library's own
-motion projector (project_motions, Algorithm 1) projected successfully:
+motion projector (project_motions, Algorithm 1) projected successfully and
+formed by the library (cp_warm_pairs, the features the warm start uses):
 segments start at an on-manifold q_near (random configurations put on the
 manifold by project_configs) and head for a random sample, at most (W-1) tau
 long, as the planner draws them.  The network is trained with the library's
@@ -30,14 +31,6 @@ def constraint_features(cd: dict) -> np.ndarray:
 
 def n_inputs(rd: dict, cd: dict) -> int:
     return int(rd["dof"]) + len(constraint_features(cd))
-
-
-def features(rd: dict, cd: dict, q):
-    """Network inputs for configurations q (torch [N, dof], device)."""
-    import torch
-    rng = np.maximum(np.abs(rd["lo"]), np.abs(rd["hi"])).astype(np.float32)
-    c = torch.from_numpy(constraint_features(cd)).to(q.device)
-    return torch.cat([q / torch.from_numpy(rng).to(q.device), c.expand(q.shape[0], -1)], 1).contiguous()
 
 
 def motion_ends(rd: dict, robot, con, n: int, seed: int, W: int = 64, tau: float = 0.05,
@@ -77,11 +70,9 @@ def make_pairs(rd: dict, cd: dict, n_motions: int, seed: int, W: int = 64, tau: 
     G.project_motions(robot, con, G.proj_params(W=W, tau=tau, tau_task=tau_task), q_from, q_to,
                       xi, st)
     good = st == 0
-    s = (torch.arange(W, device=q_from.device, dtype=torch.float32) / (W - 1))[None, :, None]
-    straight = q_from[good, None, :] + s * (q_to[good] - q_from[good])[:, None, :]
-    X = features(rd, cd, straight[:, 1:, :].reshape(-1, dof))
-    T = (xi[good][:, 1:, :] - straight[:, 1:, :]).reshape(-1, dof).contiguous()
-    return X, T
+    X, T = G.warm_pairs(robot, con, W, q_from, q_to, xi, n_inputs(rd, cd))
+    keep = good.repeat_interleave(W - 1)
+    return X[keep].contiguous(), T[keep].contiguous()
 
 
 def train(mlp: G.MLP, X, T, epochs: int = 10, batch: int = 4096, lr_max: float = 1e-3,

@@ -47,16 +47,22 @@ def _queries(G, specs):
     return qs, ws, ends
 
 
-def test_uneven_batch_paths_pass_oracle_revalidation(G):
+@pytest.mark.parametrize("flags", [0, 1])
+def test_uneven_batch_paths_pass_oracle_revalidation(G, flags):
+    """flags 0: one launch per round over the task queue (every class of
+    this batch is in the DOF 6/7/9 set); 1 (CP_BATCH_PER_CLASS): one launch
+    per class and a publish launch per round."""
     specs = ([(I.workload("plain", s), s) for s in range(1000, 1004)]
              + [(six_dof(s), s) for s in (1500, 1501)]
              + [(I.workload("mobile", 3000), 3000)]
              + [(I.workload("plain", 1004), 1004)])          # classes interleaved on purpose
     qs, ws, ends = _queries(G, specs)
     bp = G.BatchPlanner(len(qs), 9, G.batch_opts(groups_per_query=32, max_rounds=400,
-                                                 capacity=4096, tau_task=1e-3))
+                                                 capacity=4096, tau_task=1e-3, flags=flags))
     status, paths, stats = bp.plan(qs)
     print("status", status.tolist(), "rounds", [s["rounds"] for s in stats], flush=True)
+    # three classes: (6, none), (7, pose), (9, pose)
+    assert all(s["launches_per_round"] == (4 if flags else 1) for s in stats), stats
     for i, (w, e) in enumerate(zip(ws, ends)):
         assert status[i] in (G.CP_OK, G.CP_NO_SOLUTION, G.CP_E_CAPACITY)
         if status[i] == G.CP_OK:

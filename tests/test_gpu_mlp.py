@@ -197,3 +197,27 @@ def test_trained_warm_start_gain(G):
     assert hist[-1] < hist[0]
     assert np.all(st_w[st_p == 0] == 0)
     _revalidate_segments(w, xi_w, st_w, 64, 1e-4)
+
+
+@pytest.mark.parametrize("name,seed", [("plain", 1000), ("dual", 5000)])
+def test_warm_pairs_match_reference(G, name, seed):
+    """cp_warm_pairs: features (straight waypoint over the joint range, then
+    the constraint parameters) and targets (projected - straight waypoint) of
+    every waypoint k >= 1, against float32 references computed here."""
+    from paper_2505_06791_amd import warmstart
+    w = I.workload(name, seed)
+    rd, cd = w["robot"], w["constraint"]
+    robot, con = G.Robot(rd), G.constraint(cd)
+    W = 64 if name == "plain" else 32
+    q_from, q_to = warmstart.motion_ends(rd, robot, con, 64, seed=77, W=W)
+    M, dof = q_from.shape
+    xi = torch.randn((M, W, dof), device=DEV)          # any segment: the kernel only subtracts
+    x, t = G.warm_pairs(robot, con, W, q_from, q_to, xi, warmstart.n_inputs(rd, cd))
+    s = (torch.arange(W, device=DEV, dtype=torch.float32) / (W - 1))[None, :, None]
+    straight = (q_from[:, None, :] + s * (q_to - q_from)[:, None, :])[:, 1:, :].reshape(-1, dof)
+    rng = torch.from_numpy(np.maximum(np.abs(rd["lo"]), np.abs(rd["hi"])).astype(np.float32)).to(DEV)
+    cp = torch.from_numpy(warmstart.constraint_features(cd)).to(DEV)
+    x_ref = torch.cat([straight / rng, cp.expand(straight.shape[0], -1)], 1)
+    t_ref = xi[:, 1:, :].reshape(-1, dof) - straight
+    assert torch.allclose(x, x_ref, rtol=0, atol=2e-6), (x - x_ref).abs().max().item()
+    assert torch.allclose(t, t_ref, rtol=0, atol=2e-6), (t - t_ref).abs().max().item()
