@@ -147,7 +147,8 @@ def parse():
     ap.add_argument("--learned", type=int, default=1,
                     help="measure the warm-start network and the warm-started projector (0 = skip)")
     ap.add_argument("--learned-queries", type=int, default=128,
-                    help="planning queries of one robot for the learned + batched comparison")
+                    help="planning queries of one robot for the learned + batched comparison "
+                         "(0 = skip; the network's throughput is still measured)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB three times "
                          "(calibration of the HBM traffic counters) and exit")
@@ -970,11 +971,12 @@ def main():
         result["density"] = density_bench(G, I, torch)
     if args.learned:
         result["mlp"] = mlp_bench(G, torch)
-        result["learned_vs_plain"] = {
-            "arm7": learned_bench(G, I, torch, "plain", 1000, 256, args.learned_queries),
-            "dual14": learned_bench(G, I, torch, "dual", 5000, 512, args.learned_queries,
-                                    n_pairs=1_000_000, epochs=6, seq_rounds=50, max_dof=14),
-        }
+        if args.learned_queries > 0:
+            result["learned_vs_plain"] = {
+                "arm7": learned_bench(G, I, torch, "plain", 1000, 256, args.learned_queries),
+                "dual14": learned_bench(G, I, torch, "dual", 5000, 512, args.learned_queries,
+                                        n_pairs=1_000_000, epochs=6, seq_rounds=50, max_dof=14),
+            }
     if args.cpu_seconds > 0:
         result["cpu_baseline"] = cpu_baseline(I, w, args.cpu_seconds)
     print(json.dumps(result), flush=True)

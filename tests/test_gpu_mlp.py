@@ -175,8 +175,10 @@ def test_warm_start_network_shape_is_checked(G):
 
 def test_trained_warm_start_gain(G):
     """Train on pairs the projector produces (plain scene, upright), then
-    compare on held-out motions at tolerance 1e-4: the gain is reported, and
-    the warm start must not lose a motion the plain projector projects."""
+    compare on held-out motions at tolerance 1e-4: the warm start must not
+    lose a motion the plain projector projects, and with the fallback it
+    must project at least 3 points more of the motions (measured: 75% plain,
+    86% warm + fallback on these 300)."""
     from paper_2505_06791_amd import warmstart
     w = I.workload("plain", 1000)
     rd, cd = w["robot"], w["constraint"]
@@ -196,6 +198,7 @@ def test_trained_warm_start_gain(G):
           "warm+fallback", it_w.mean(), flush=True)
     assert hist[-1] < hist[0]
     assert np.all(st_w[st_p == 0] == 0)
+    assert (st_w == 0).mean() >= (st_p == 0).mean() + 0.03
     _revalidate_segments(w, xi_w, st_w, 64, 1e-4)
 
 
