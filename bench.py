@@ -599,10 +599,22 @@ def fkcc_bench(G, I, torch, n=1 << 20, reps=5):
     self_per_cfg = rd["dof"] * FK_JOINT_FLOPS + len(rd["sphere"]) * SPHERE_CENTRE_FLOPS + \
         pairs * SELF_PAIR_FLOPS
     self_tflops = n * self_per_cfg / (self_ms * 1e-3) / 1e12
+    # the FK/CC kernel compiled at run time for the robot (cp_robot_specialize)
+    rob_s = G.Robot(rd)
+    compile_ms = rob_s.specialize(G.constraint(w["constraint"]))
+    col_s = torch.empty(n, dtype=torch.uint8, device=dev)
+    spec_ms = _time_ms(torch, lambda: G.fk_cc_batch(rob_s, env, q, col_s, flags=G.NO_EARLY_EXIT),
+                       reps)
+    spec_early_ms = _time_ms(torch, lambda: G.fk_cc_batch(rob_s, env, q, col_s), reps)
+    spec_tflops = n * per_cfg / (spec_ms * 1e-3) / 1e12
     return dict(configs=n, every_pair_ms=full_ms, early_exit_ms=early_ms,
                 colliding=colliding, gflop_per_launch=n * per_cfg / 1e9,
                 achieved_tflops=tflops, peak_tflops=FP32_VECTOR_PEAK_TFLOPS,
                 frac=tflops / FP32_VECTOR_PEAK_TFLOPS,
+                specialised=dict(compile_ms=compile_ms, every_pair_ms=spec_ms,
+                                 early_exit_ms=spec_early_ms, achieved_tflops=spec_tflops,
+                                 frac=spec_tflops / FP32_VECTOR_PEAK_TFLOPS,
+                                 colliding=int(col_s.sum().item())),
                 self_collision=dict(pairs=pairs, with_self_ms=both_ms, self_ms=self_ms,
                                     colliding_with_self=colliding_self,
                                     gflop=n * self_per_cfg / 1e9, achieved_tflops=self_tflops,

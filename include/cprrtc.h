@@ -54,9 +54,9 @@ enum {
                             wavefront whatever the batch size (results are the same) */
   CP_PER_MOTION = 16,    /* project_validate_motions: project with one motion per wavefront
                             whatever the batch size (results are the same) */
-  CP_GENERIC = 32,       /* project_validate_motions, validate_motions: use the library's
-                            projection and validation kernels even where
-                            cp_robot_specialize compiled some for the robot */
+  CP_GENERIC = 32,       /* project_validate_motions, validate_motions, fk_cc_batch: use
+                            the library's projection, validation and FK/CC kernels even
+                            where cp_robot_specialize compiled some for the robot */
   CP_SELF_COLLISION = 64 /* fk_cc_batch, validate_motions, project_validate_motions: also
                             check the robot against itself (cp_robot_self_pairs) */
 };
@@ -340,13 +340,15 @@ int project_motions_warm_noalloc(const cp_robot* robot, const cp_constraint* con
  * base and tool frames, collision spheres and the mask written in as
  * constants (the kernel source is the library's own device code; only the
  * constants differ), and keeps them in the robot handle.  what:
- * CP_SPECIALIZE_PROJECT (0 means this) -- the pooled projection kernel and
- * the culled validation kernels: later calls that project this robot's
- * motions in the pooled form (project_motions, project_validate_motions;
- * see CP_POOLED) with a constraint of the same kind and mask use the
- * first, and every later culled validation of this robot's motions
- * (validate_motions, project_validate_motions; the validation kernels
- * depend on the robot only) the second, unless flags hold CP_GENERIC;
+ * CP_SPECIALIZE_PROJECT (0 means this) -- the pooled projection kernel, the
+ * culled validation kernels and the FK/CC kernel of configurations: later
+ * calls that project this robot's motions in the pooled form
+ * (project_motions, project_validate_motions; see CP_POOLED) with a
+ * constraint of the same kind and mask use the first, every later culled
+ * validation of this robot's motions (validate_motions,
+ * project_validate_motions; the validation kernels depend on the robot
+ * only) the second, and fk_cc_batch calls of this robot without distances
+ * (d_min_sd NULL) the third, unless flags hold CP_GENERIC;
  * CP_SPECIALIZE_PLAN -- the planner's round kernels: later cp_plan calls of
  * planners of this robot with such a constraint use them.  In these kernels
  * revolute joints whose limits (plus theta) stay within +-3.2 rad take the

@@ -448,9 +448,19 @@ int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const f
     if (n_cfg == 0) return CP_OK;
     if (!d_q || !d_collide) return fail(CP_E_ARG, "fk_cc_batch: NULL buffer");
     const bool early = !(flags & CP_NO_EARLY_EXIT);
-    hipError_t e = launch_fk_cc(robot->dev, robot->spheres, env->view, n_cfg, d_q, d_collide,
-                                d_min_sd, early, 8, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "fk_cc_batch launch");
+    // the kernel compiled for this robot (cp_robot_specialize) for the
+    // verdicts alone; the signed distances take the library kernel
+    RtcFns rk;
+    hipError_t e;
+    if (!d_min_sd && !(flags & CP_GENERIC) &&
+        rtc_find_validate(const_cast<cp_robot*>(robot), &rk) && rk.fkcc[1]) {
+      e = launch_rtc_fk_cc(rk, robot, env->view, n_cfg, d_q, d_collide, early, 8, (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "fk_cc_batch launch (run-time compiled kernel)");
+    } else {
+      e = launch_fk_cc(robot->dev, robot->spheres, env->view, n_cfg, d_q, d_collide, d_min_sd, early,
+                       8, (hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "fk_cc_batch launch");
+    }
     if (d_sphere_xyz) {
       e = launch_sphere_xyz(robot->dev, robot->spheres, robot->sph_map, robot->host.n_spheres,
                             n_cfg, d_q, d_sphere_xyz, (hipStream_t)stream);

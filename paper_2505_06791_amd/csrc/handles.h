@@ -17,6 +17,7 @@ struct RtcFns {
   hipFunction_t pool = nullptr;                          // pooled projection
   hipFunction_t plan[2] = {nullptr, nullptr};            // planner round, sphere batch 4 / 8
   hipFunction_t validate[3] = {nullptr, nullptr, nullptr};  // culled validation, 4 / 8 / 16
+  hipFunction_t fkcc[2] = {nullptr, nullptr};              // FK + CC of configurations, 4 / 8
 };
 struct RtcKernel {
   int kind = 0;
@@ -72,6 +73,11 @@ hipError_t launch_rtc_plan_round(const RtcFns& k, const cp_robot* robot, const E
                                  int sphere_batch, unsigned blocks, size_t lds,
                                  hipStream_t stream);
 void rtc_release(cp_robot* robot);
+// fk_cc_batch's check (collision flags only) with the kernel compiled for
+// the robot (RtcFns::fkcc, sphere batch 4 or 8).
+hipError_t launch_rtc_fk_cc(const RtcFns& k, const cp_robot* robot, const EnvDev& env, int n_cfg,
+                            const float* q, uint8_t* collide, bool early, int batch,
+                            hipStream_t stream);
 // Learned warm start for the planners: CP_OK if the network fits the robot's
 // DOF and constraint kind and has the fused shape (else the error, with its
 // message set); corrections delta [n_segments][W-1][dof] of the straight

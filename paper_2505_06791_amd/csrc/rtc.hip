@@ -112,6 +112,18 @@ std::string kernel_source(const RobotDev& h, int kind, unsigned mask, const floa
   s += "  project_pool_body<" + std::to_string(n) + ", " + std::to_string(kind) + ", 0, " +
        std::to_string(kPoolSlots) +
        ", RtcPolicy>(rob, con, prm, n_motions, q_from, q_to, nullptr, xi, status, iters, work);\n}\n";
+    // FK + CC of independent configurations (fk_cc_batch without distances)
+    for (int b : {4, 8})
+      s += "extern \"C\" __global__ __launch_bounds__(256) void cp_rtc_fkcc" + std::to_string(b) +
+           "(const RobotDev* __restrict__ rob, const float4* __restrict__ sph, EnvDev env,\n"
+           "    int n_cfg, const float* __restrict__ q, unsigned char* __restrict__ collide, int early) {\n"
+           "  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;\n"
+           "  const bool on = i < n_cfg;\n"
+           "  const float* qi = q + (on ? i : 0) * " + std::to_string(n) + ";\n"
+           "  uint64_t hits;\n  float msd;\n  CcWork cw;\n  cc_work_clear(cw);\n"
+           "  collide_config<" + std::to_string(b) + ", false, false, false, RtcPolicy>(rob, sph, env, qi, on,\n"
+           "      0ull, early != 0, hits, msd, cw);\n"
+           "  if (on) collide[i] = (unsigned char)((hits >> (threadIdx.x & 63)) & 1u);\n}\n";
     for (int b : {4, 8, 16})
       s += "extern \"C\" __global__ __launch_bounds__(256) void cp_rtc_validate" + std::to_string(b) +
            "(const RobotDev* __restrict__ rob, const float4* __restrict__ sph, EnvDev env, int W,\n"
@@ -162,6 +174,19 @@ hipError_t launch_rtc_pool(const RtcFns& k, const cp_robot* robot, const ConDev&
   ProjDev p = prm;
   void* args[] = {&rob, &c, &p, &n_motions, &q_from, &q_to, &xi, &status, &iters, &work};
   return hipModuleLaunchKernel(k.pool, pool_blocks(n_motions), 1, 1, 64, 1, 1, 0, stream, args,
+                               nullptr);
+}
+
+hipError_t launch_rtc_fk_cc(const RtcFns& k, const cp_robot* robot, const EnvDev& env, int n_cfg,
+                            const float* q, uint8_t* collide, bool early, int batch,
+                            hipStream_t stream) {
+  const RobotDev* rob = robot->dev;
+  const float4* sph = robot->spheres;
+  EnvDev e = env;
+  int n = n_cfg, ea = early ? 1 : 0;
+  void* args[] = {&rob, &sph, &e, &n, &q, &collide, &ea};
+  const unsigned nb = (unsigned)(((int64_t)n_cfg + 255) / 256);
+  return hipModuleLaunchKernel(k.fkcc[batch == 4 ? 0 : 1], nb, 1, 1, 256, 1, 1, 0, stream, args,
                                nullptr);
 }
 
@@ -289,6 +314,9 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
     if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&val4, module, "cp_rtc_validate4");
     if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&val8, module, "cp_rtc_validate8");
     if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&val16, module, "cp_rtc_validate16");
+    hipFunction_t fk4 = nullptr, fk8 = nullptr;
+    if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&fk4, module, "cp_rtc_fkcc4");
+    if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&fk8, module, "cp_rtc_fkcc8");
     if (he == hipSuccess && need_plan) he = hipModuleGetFunction(&plan4, module, "cp_rtc_plan4");
     if (he == hipSuccess && need_plan) he = hipModuleGetFunction(&plan8, module, "cp_rtc_plan8");
     if (he != hipSuccess) {
@@ -316,6 +344,8 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
         e->fns.validate[0] = val4;
         e->fns.validate[1] = val8;
         e->fns.validate[2] = val16;
+        e->fns.fkcc[0] = fk4;
+        e->fns.fkcc[1] = fk8;
       }
       if (plan4) {
         e->fns.plan[0] = plan4;

@@ -224,3 +224,29 @@ def test_full_size_sampled_specialised(G):
                     judged += 1
         print("differing motions: same status, iterations only", iters_only,
               "; verdicts judged on each kernel's own waypoints", judged, flush=True)
+
+
+@pytest.mark.parametrize("name,n", [("plain", 4099), ("cluttered", 2050), ("mobile", 1025),
+                                    ("dual", 1030)])
+def test_specialised_fk_cc_matches_oracle(G, name, n):
+    """fk_cc_batch with the FK/CC kernel compiled for the robot: verdicts equal
+    the FP64 oracle's outside the 1e-5 m band, with and without early exit,
+    and equal the library kernel's (CP_GENERIC) outside the band."""
+    w = I.workload(name, 1300 + n)
+    q32 = I.random_configs(w["robot"], n, 9).astype(np.float32)
+    ro, eo, _ = oracle_views(w)
+    col_o, sd_o = O.fk_cc_batch(ro, eo, q32.astype(np.float64), n_threads=ORACLE_THREADS)
+    robot, env = G.Robot(w["robot"]), G.Env(w["env"])
+    assert robot.specialize(G.constraint(w["constraint"])) > 0
+    q = torch.from_numpy(q32).to("cuda:0")
+    out = {}
+    for flags in (0, G.NO_EARLY_EXIT, G.GENERIC):
+        col = torch.full((n,), 7, dtype=torch.uint8, device="cuda:0")
+        G.fk_cc_batch(robot, env, q, col, flags=flags)
+        torch.cuda.synchronize()
+        out[flags] = col.cpu().numpy().astype(bool)
+    band = np.abs(sd_o) <= 1e-5
+    print(name, n, "band", int(band.sum()), "colliding", int(col_o.sum()), flush=True)
+    for flags, col in out.items():
+        assert np.array_equal(col[~band], col_o[~band].astype(bool)), flags
+    assert np.array_equal(out[0], out[G.NO_EARLY_EXIT])
