@@ -53,6 +53,11 @@ __device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z));
 __device__ __forceinline__ float silu_fast(float z) {
   return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
 }
+// SiLU'(z) = s (1 + z (1 - s)), s = sigmoid(z), with the hardware reciprocal.
+__device__ __forceinline__ float silu_grad_fast(float z) {
+  const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+  return sg * (1.0f + z * (1.0f - sg));
+}
 __device__ __forceinline__ float silu_grad(float z) {
   const float s = 1.0f / (1.0f + __expf(-z));
   return s * (1.0f + z * (1.0f - s));
@@ -448,9 +453,24 @@ struct ChunkStream {
   }
 };
 
-template <int H, int ST, int NW, class F>
+// What a training forward pass keeps for the backward pass (all [sample]
+// rows): the layer-0 inputs as BF16 (32 columns), every hidden layer's
+// pre-activation (FP32) and activation (BF16), the output gradient of the
+// mean squared error as BF16 (16 columns) and the loss (accumulated).
+struct TrainIO {
+  const float* target;   // [M][n_out]
+  uint16_t* xb;          // [M][32]
+  float* z;              // [n_hidden][M][H]
+  uint16_t* a;           // [n_hidden][M][H]
+  uint16_t* dy;          // [M][16]
+  float* loss;
+  float inv_mn;          // 1 / (M n_out)
+};
+
+template <int H, int ST, int NW, class F, bool TRAIN = false>
 __global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(FusedNet net, F feat, long M,
-                                                        float* __restrict__ y, long ldy) {
+                                                        float* __restrict__ y, long ldy,
+                                                        TrainIO tr = TrainIO{}) {
   constexpr int KC = H / 32;       // reduction chunks of a hidden-input layer
   constexpr int NT = H / 16;       // result tiles of a hidden layer
   constexpr int ROWS = H * 4;      // 16-byte pieces of a full chunk
@@ -526,6 +546,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(FusedNet net, F feat
     }
     const uint4 u{pack_bf16(f[0], f[1]), pack_bf16(f[2], f[3]), pack_bf16(f[4], f[5]), pack_bf16(f[6], f[7])};
     xin[st] = __builtin_bit_cast(bf16x8, u);
+    if (TRAIN && s < M) *reinterpret_cast<uint4*>(tr.xb + s * 32 + 8 * g) = u;
   }
   FUSED_BEGIN(0)
   chunk_mfma(xin, 0);
@@ -533,7 +554,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(FusedNet net, F feat
 
   // SiLU, then BF16 into the next layer's B operand (see above)
   bf16x8 act[KC][ST];
-  auto epilogue = [&]() {
+  auto epilogue = [&](int l) {
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
 #pragma unroll
@@ -544,10 +565,20 @@ __global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(FusedNet net, F feat
                       pack_bf16(silu_fast(hi[0]), silu_fast(hi[1])),
                       pack_bf16(silu_fast(hi[2]), silu_fast(hi[3]))};
         act[c][st] = __builtin_bit_cast(bf16x8, u);
+        if (TRAIN) {
+          const long s = s0 + st * 16 + r;
+          if (s < M) {
+            const long row = ((long)l * M + s) * H + 32 * c + 4 * g;
+            *reinterpret_cast<f32x4*>(tr.z + row) = lo;
+            *reinterpret_cast<f32x4*>(tr.z + row + 16) = hi;
+            *reinterpret_cast<uint2*>(tr.a + row) = uint2{u.x, u.y};
+            *reinterpret_cast<uint2*>(tr.a + row + 16) = uint2{u.z, u.w};
+          }
+        }
       }
     }
   };
-  epilogue();
+  epilogue(0);
 
   // hidden-to-hidden layers
   for (int l = 1; l < net.n_hidden; ++l) {
@@ -561,7 +592,7 @@ __global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(FusedNet net, F feat
       chunk_mfma(act[kc + 1], -1);
       FUSED_END(0)
     }
-    epilogue();
+    epilogue(l);
   }
 
   // last layer: at most 16 outputs, bias, no activation
@@ -578,18 +609,310 @@ __global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(FusedNet net, F feat
     for (int st = 0; st < ST; ++st)
       out[st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kc][st], out[st], 0, 0, 0);
   }
+  float lsum = 0.0f;
 #pragma unroll
   for (int st = 0; st < ST; ++st) {
     const long s = s0 + st * 16 + r;
     if (s >= M) continue;
+    if (TRAIN) {
+      // dY = 2 (y - t) / (M n_out) on the real outputs, zero on the padding
+      float d[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int n = 4 * g + t;
-      if (n < net.n_out) y[s * ldy + n] = out[st][t];
+      for (int t = 0; t < 4; ++t) {
+        const int n = 4 * g + t;
+        d[t] = n < net.n_out ? out[st][t] - tr.target[s * net.n_out + n] : 0.0f;
+        lsum += d[t] * d[t];
+      }
+      const float k = 2.0f * tr.inv_mn;
+      *reinterpret_cast<uint2*>(tr.dy + s * 16 + 4 * g) =
+          uint2{pack_bf16(k * d[0], k * d[1]), pack_bf16(k * d[2], k * d[3])};
     }
+    if (y) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int n = 4 * g + t;
+        if (n < net.n_out) y[s * ldy + n] = out[st][t];
+      }
+    }
+  }
+  if (TRAIN) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+    if (lane == 0) atomicAdd(tr.loss, lsum * tr.inv_mn);
   }
 #undef FUSED_BEGIN
 #undef FUSED_END
+}
+
+// Backward pass of the fused network for the samples of mlp_fused_kernel's
+// training forward (same sample mapping): from dY, every hidden layer's
+// pre-activation gradient dZ_l = (W_{l+1}^T dZ_{l+1}) * SiLU'(z_l) into dz
+// ([n_hidden][M][H], BF16), computed transposed with the transposed weights
+// as the A operand, so dZ_l stays in registers as the next product's B
+// operand exactly as activations do in the forward pass.  Weight chunks
+// (fused_weights_t_kernel): the output layer's W^T as one chunk of H rows x
+// 32 (output units, natural order, zero past n_out), then, from the last
+// hidden-to-hidden layer down, each one's H/32 chunks of W^T (H rows x 32
+// output units in fused_perm order), all in the chunk_at layout.
+template <int H, int ST, int NW>
+__global__ __launch_bounds__(NW * 64) void mlp_bwd_fused_kernel(const uint16_t* __restrict__ wbt,
+                                                            int n_hidden, long M, TrainIO tr,
+                                                            uint16_t* __restrict__ dz) {
+  constexpr int KC = H / 32;
+  constexpr int NT = H / 16;
+  constexpr int PRE = (H * 4 + NW * 64 - 1) / (NW * 64);
+  __shared__ __align__(16) uint16_t wl[2][H * kFusedLdw];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const long s0 = ((long)blockIdx.x * NW + wave) * (16 * ST);
+  const int nq = 1 + (n_hidden - 1) * KC;
+  const ChunkStream<H, PRE, NW> cs{wbt, nq, tid};    // every chunk is H x 32
+  ChunkRegs<PRE> pre0 = cs.fetch(0), pre1;
+  if (nq > 1) pre1 = cs.fetch(1);
+  cs.put(0, pre0, wl[0]);
+  __syncthreads();
+  int q = 0;
+#define BWD_BEGIN(PAR)                                     \
+  if (q + 2 < nq) {                                        \
+    if (PAR == 0) pre0 = cs.fetch(q + 2);                  \
+    else pre1 = cs.fetch(q + 2);                           \
+  }
+#define BWD_END(PAR)                                                     \
+  if (q + 1 < nq) cs.put(q + 1, PAR == 0 ? pre1 : pre0, wl[(q + 1) & 1]); \
+  __syncthreads();                                                       \
+  ++q;
+  f32x4 acc[NT][ST];
+  auto chunk_mfma = [&](const bf16x8 (&b)[ST], bool first) {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
+                                                      &wl[q & 1][chunk_at(nt * 16 + r, g)]));
+#pragma unroll
+      for (int st = 0; st < ST; ++st)
+        acc[nt][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            a, b[st], first ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[nt][st], 0, 0, 0);
+    }
+  };
+  // output layer: B operand = dY (outputs 8g .. 8g+7 of this lane's sample)
+  bf16x8 dyb[ST];
+#pragma unroll
+  for (int st = 0; st < ST; ++st) {
+    const long s = s0 + st * 16 + r;
+    uint4 u{0u, 0u, 0u, 0u};
+    if (s < M && g < 2) u = *reinterpret_cast<const uint4*>(tr.dy + s * 16 + 8 * g);
+    dyb[st] = __builtin_bit_cast(bf16x8, u);
+  }
+  BWD_BEGIN(0)
+  chunk_mfma(dyb, true);
+  BWD_END(0)
+  // dZ_l = acc * SiLU'(z_l), stored, and kept as the next B operand
+  bf16x8 act[KC][ST];
+  auto epilogue = [&](int l) {
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+#pragma unroll
+      for (int st = 0; st < ST; ++st) {
+        const long s = s0 + st * 16 + r;
+        const bool in = s < M;
+        const long row = ((long)l * M + (in ? s : 0)) * H + 32 * c + 4 * g;
+        f32x4 zl{0.f, 0.f, 0.f, 0.f}, zh{0.f, 0.f, 0.f, 0.f};
+        if (in) {
+          zl = *reinterpret_cast<const f32x4*>(tr.z + row);
+          zh = *reinterpret_cast<const f32x4*>(tr.z + row + 16);
+        }
+        const f32x4 lo = acc[2 * c][st], hi = acc[2 * c + 1][st];
+        const uint4 u{pack_bf16(lo[0] * silu_grad_fast(zl[0]), lo[1] * silu_grad_fast(zl[1])),
+                      pack_bf16(lo[2] * silu_grad_fast(zl[2]), lo[3] * silu_grad_fast(zl[3])),
+                      pack_bf16(hi[0] * silu_grad_fast(zh[0]), hi[1] * silu_grad_fast(zh[1])),
+                      pack_bf16(hi[2] * silu_grad_fast(zh[2]), hi[3] * silu_grad_fast(zh[3]))};
+        act[c][st] = __builtin_bit_cast(bf16x8, u);
+        if (in) {
+          *reinterpret_cast<uint2*>(dz + row) = uint2{u.x, u.y};
+          *reinterpret_cast<uint2*>(dz + row + 16) = uint2{u.z, u.w};
+        }
+      }
+    }
+  };
+  epilogue(n_hidden - 1);
+  for (int l = n_hidden - 1; l >= 1; --l) {
+#pragma unroll
+    for (int kc = 0; kc < KC; kc += 2) {
+      BWD_BEGIN(1)
+      chunk_mfma(act[kc], kc == 0);
+      BWD_END(1)
+      BWD_BEGIN(0)
+      chunk_mfma(act[kc + 1], false);
+      BWD_END(0)
+    }
+    epilogue(l - 1);
+  }
+#undef BWD_BEGIN
+#undef BWD_END
+}
+
+// Builds the backward weight chunks (see mlp_bwd_fused_kernel) from the
+// FP32 masters.
+__global__ void fused_weights_t_kernel(const float* __restrict__ w, int H, int n_out, int n_hidden,
+                                       long w_off_h, long w_stride_h, long w_off_last,
+                                       uint16_t* __restrict__ wbt, long n_wbt) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_wbt) return;
+  const long first = (long)H * 32;
+  float v = 0.0f;
+  if (e < first) {
+    const int k = (int)(e / 32), n = (int)(e % 32);
+    if (n < n_out) v = w[w_off_last + (long)n * H + k];
+  } else {
+    const long r = e - first;
+    const long per_layer = (long)H * H;
+    const int j = (int)(r / per_layer);          // 0: the last hidden-to-hidden layer
+    const long rr = r % per_layer;
+    const int c = (int)(rr / ((long)H * 32));
+    const int k = (int)((rr / 32) % H), p = (int)(rr % 32);
+    const int l = n_hidden - 1 - j;              // hidden-to-hidden layer index 1 .. n_hidden-1
+    v = w[w_off_h + (long)(l - 1) * w_stride_h + (long)(32 * c + fused_perm(p)) * H + k];
+  }
+  wbt[e] = to_bf16(v);
+}
+
+// Weight gradients of one training step, all layers in one launch:
+// blockIdx.y = layer, blockIdx.z = range of the batch, blockIdx.x = a
+// 64 x 64 tile of dW = dZ^T X (or, for the last x, the layer's bias
+// gradient, column sums of dZ); each writes its range's partial sums into
+// parts[z][parameter index] (summed in a fixed order by the update kernel).
+struct DwLayer {
+  Mat A;          // dZ^T: (unit, sample)
+  Mat B;          // X: (sample, input)
+  int N, K;       // units, inputs
+  long w_off, b_off;
+};
+struct DwArgs {
+  DwLayer L[kFusedMaxLayers];
+  long M;         // samples
+  int ks;         // samples per range (a multiple of 32)
+  long n_params;
+  float* parts;
+};
+
+__global__ __launch_bounds__(256) void dw_kernel(DwArgs args) {
+  __shared__ __align__(16) uint16_t As[kBM][kBK + kPad];
+  __shared__ __align__(16) uint16_t Bs[kBN][kBK + kPad];
+  const DwLayer& L = args.L[blockIdx.y];
+  const int tn = (L.K + kBN - 1) / kBN, tm = (L.N + kBM - 1) / kBM;
+  const int tile = blockIdx.x;
+  if (tile > tm * tn) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kb = blockIdx.z * args.ks;
+  const int ke = (int)min((long)kb + args.ks, args.M);
+  float* out = args.parts + (long)blockIdx.z * args.n_params;
+  if (tile == tm * tn) {            // bias gradient: sums of dZ over this range
+    for (int n = tid; n < L.N; n += 256) {
+      float sum = 0.0f;
+      for (int s = kb; s < ke; ++s) sum += from_bf16(L.A.p[(long)n * L.A.rs + (long)s * L.A.cs]);
+      out[L.b_off + n] = sum;
+    }
+    return;
+  }
+  const int m0 = (tile / tn) * kBM, n0 = (tile % tn) * kBN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const Mat Bt{L.B.p, L.B.cs, L.B.rs};
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kb; k0 < ke; k0 += kBK) {
+    stage<kBM>(As, L.A, m0, k0, L.N, ke, tid);
+    stage<kBN>(Bs, Bt, n0, k0, L.K, ke, tid);
+    __syncthreads();
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    bf16x8 a[2], b[2];
+    for (int i = 0; i < 2; ++i)
+      a[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&As[wm + i * 16 + fr][fk]));
+    for (int j = 0; j < 2; ++j)
+      b[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bs[wn + j * 16 + fr][fk]));
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  const int col = lane & 15, rb = (lane >> 4) * 4;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int t = 0; t < 4; ++t) {
+        const int gm = m0 + wm + i * 16 + rb + t, gn = n0 + wn + j * 16 + col;
+        if (gm < L.N && gn < L.K) out[L.w_off + (long)gm * L.K + gn] = acc[i][j][t];
+      }
+}
+
+// The parameter index -> positions in the fused forward and backward weight
+// chunks and the padded biases (-1 where a parameter has none).
+struct FusedMap {
+  int n_layers, H, n_in, n_out, n_hidden;
+  long w_off[kFusedMaxLayers], b_off[kFusedMaxLayers];
+  __device__ __forceinline__ static int inv_perm(int kk) {
+    return kk < 16 ? 8 * (kk >> 2) + (kk & 3) : 8 * ((kk - 16) >> 2) + 4 + ((kk - 16) & 3);
+  }
+  __device__ void locate(long i, long& fwd, long& bwd, long& bias) const {
+    fwd = bwd = bias = -1;
+    int l = n_layers - 1;
+    while (l > 0 && i < w_off[l]) --l;
+    const int K = l == 0 ? n_in : H, N = l + 1 < n_layers ? H : n_out;
+    if (i >= b_off[l]) {
+      bias = (long)l * H + (i - b_off[l]);
+      return;
+    }
+    const long e = i - w_off[l];
+    const int n = (int)(e / K), k = (int)(e % K);
+    const int KC = H / 32;
+    if (l == 0) {
+      fwd = (long)n * 32 + k;
+    } else if (l < n_layers - 1) {
+      fwd = (long)H * 32 + (long)(l - 1) * KC * H * 32 + (long)(k / 32) * H * 32 + (long)n * 32 + inv_perm(k & 31);
+      bwd = (long)H * 32 + (long)(n_hidden - 1 - l) * H * H + (long)(n / 32) * H * 32 + (long)k * 32 + inv_perm(n & 31);
+    } else {
+      fwd = (long)H * 32 + (long)(n_hidden - 1) * H * H + (long)n * H + (k & ~31) + inv_perm(k & 31);
+      bwd = (long)k * 32 + n;
+    }
+    (void)N;
+  }
+};
+
+// One update of every parameter from the partial gradients: g = sum over
+// the ranges (fixed order); mode 0 stores g; mode 1 takes an Adam step on
+// the FP32 master and refreshes its BF16 copy, its fused forward and
+// backward chunk entries and the padded bias.  Thread 0 also hands out the
+// step's loss and clears the accumulator for the next step.
+__global__ void train_update_kernel(int mode, const float* __restrict__ parts, int n_parts,
+                                    long n_params, float* __restrict__ grad, float* __restrict__ w,
+                                    float* __restrict__ m1, float* __restrict__ m2,
+                                    uint16_t* __restrict__ wb, uint16_t* __restrict__ wf,
+                                    uint16_t* __restrict__ wbt, float* __restrict__ bias_f,
+                                    FusedMap map, float lr, float b1, float b2, float eps, float c1,
+                                    float c2, float* __restrict__ loss, float* __restrict__ loss_out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    if (loss_out) *loss_out = *loss;
+    *loss = 0.0f;
+  }
+  if (i >= n_params) return;
+  float gi = 0.0f;
+  for (int z = 0; z < n_parts; ++z) gi += parts[(long)z * n_params + i];
+  if (mode == 0) {
+    grad[i] = gi;
+    return;
+  }
+  const float a = b1 * m1[i] + (1.0f - b1) * gi;
+  const float v = b2 * m2[i] + (1.0f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = v;
+  const float nw = w[i] - lr * (a / c1) / (sqrtf(v / c2) + eps);
+  w[i] = nw;
+  const uint16_t hb = to_bf16(nw);
+  wb[i] = hb;
+  long fwd, bwd, bias;
+  map.locate(i, fwd, bwd, bias);
+  if (fwd >= 0) wf[fwd] = hb;
+  if (bwd >= 0) wbt[bwd] = hb;
+  if (bias >= 0) bias_f[bias] = nw;
 }
 
 }  // namespace cprrtc
@@ -637,6 +960,16 @@ struct cp_mlp {
   float* bias_f = nullptr;
   long* d_b_off = nullptr;
   int* d_width = nullptr;
+  // fused training: backward weight chunks and the step's buffers
+  uint16_t* wbt = nullptr;
+  long n_wbt = 0;
+  long tr_rows = 0;
+  uint16_t* t_xb = nullptr;   // [rows][32]
+  float* t_z = nullptr;       // [n_hidden][rows][H]
+  uint16_t* t_a = nullptr;    // [n_hidden][rows][H]
+  uint16_t* t_dy = nullptr;   // [rows][16]
+  uint16_t* t_dz = nullptr;   // [n_hidden][rows][H]
+  float* t_parts = nullptr;   // [kTrainParts][n_params]
 };
 
 namespace {
@@ -801,6 +1134,105 @@ hipError_t refresh_fused(cp_mlp* n, hipStream_t st) {
                                                       n->w_off[n->n_hidden], n->wf, n->n_wf);
   fused_bias_kernel<<<nblk((long)n->n_layers * n->hidden), 256, 0, st>>>(
       n->w, n->d_b_off, n->d_width, n->n_layers, n->hidden, n->bias_f);
+  fused_weights_t_kernel<<<nblk(n->n_wbt), 256, 0, st>>>(n->w, n->hidden, n->n_out, n->n_hidden,
+                                                        w_off_h, w_stride_h, n->w_off[n->n_hidden],
+                                                        n->wbt, n->n_wbt);
+  return hipGetLastError();
+}
+
+constexpr int kTrainParts = 32;   // batch ranges of the weight-gradient launch
+
+// samples per wavefront in the training kernels: one tile of 16 from width
+// 256 up (twice the workgroups of the inference shape at small batches)
+template <int H>
+constexpr int train_st() { return H >= 256 ? 1 : 256 / H; }
+
+void free_train(cp_mlp* n) {
+  for (void* p : {(void*)n->t_xb, (void*)n->t_z, (void*)n->t_a, (void*)n->t_dy, (void*)n->t_dz})
+    if (p) (void)hipFree(p);
+  n->t_xb = n->t_a = n->t_dy = n->t_dz = nullptr;
+  n->t_z = nullptr;
+  n->tr_rows = 0;
+}
+
+hipError_t ensure_train(cp_mlp* n, long M) {
+  hipError_t e = hipSuccess;
+  if (!n->t_parts) e = hipMalloc((void**)&n->t_parts, sizeof(float) * kTrainParts * n->n_params);
+  if (e != hipSuccess || M <= n->tr_rows) return e;
+  free_train(n);
+  const long r = std::max(M, 256L), H = n->hidden, L = n->n_hidden;
+  e = hipMalloc((void**)&n->t_xb, sizeof(uint16_t) * r * 32);
+  if (e == hipSuccess) e = hipMalloc((void**)&n->t_z, sizeof(float) * L * r * H);
+  if (e == hipSuccess) e = hipMalloc((void**)&n->t_a, sizeof(uint16_t) * L * r * H);
+  if (e == hipSuccess) e = hipMalloc((void**)&n->t_dy, sizeof(uint16_t) * r * 16);
+  if (e == hipSuccess) e = hipMalloc((void**)&n->t_dz, sizeof(uint16_t) * L * r * H);
+  if (e == hipSuccess) n->tr_rows = r;
+  return e;
+}
+
+template <int H>
+void launch_train_h(const cp_mlp* n, long M, const float* x, const TrainIO& tr, hipStream_t st) {
+  constexpr int ST = train_st<H>();
+  const long per = (long)kFusedWaves * 16 * ST;
+  const unsigned blocks = (unsigned)((M + per - 1) / per);
+  FusedNet net{n->wf, n->bias_f, n->n_in, n->n_out, n->n_hidden};
+  mlp_fused_kernel<H, ST, kFusedWaves, FeatRows, true><<<blocks, kFusedWaves * 64, 0, st>>>(
+      net, FeatRows{x, n->n_in}, M, nullptr, 0, tr);
+  mlp_bwd_fused_kernel<H, ST, kFusedWaves><<<blocks, kFusedWaves * 64, 0, st>>>(
+      n->wbt, n->n_hidden, M, tr, n->t_dz);
+}
+
+// One training step (mode 1: Adam with learning rate lr and bias corrections
+// c1, c2) or the gradients alone (mode 0, into d_grad) of the mean squared
+// error over M samples, in four launches: forward (keeping what the backward
+// pass needs), backward, the weight gradients of every layer, the update.
+hipError_t fused_train(cp_mlp* n, long M, const float* x, const float* t, int mode, float* d_grad,
+                       float* d_loss, float lr, float c1, float c2, hipStream_t st) {
+  hipError_t e = ensure_train(n, M);
+  if (e != hipSuccess) return e;
+  const int H = n->hidden, L = n->n_hidden;
+  TrainIO tr{t, n->t_xb, n->t_z, n->t_a, n->t_dy, n->loss, 1.0f / ((float)M * (float)n->n_out)};
+  switch (H) {
+    case 64: launch_train_h<64>(n, M, x, tr, st); break;
+    case 128: launch_train_h<128>(n, M, x, tr, st); break;
+    case 256: launch_train_h<256>(n, M, x, tr, st); break;
+    default: launch_train_h<512>(n, M, x, tr, st); break;
+  }
+  // weight and bias gradients of every layer, in kTrainParts batch ranges
+  DwArgs da;
+  std::memset(&da, 0, sizeof da);
+  const int ks = (int)(((M + kTrainParts - 1) / kTrainParts + kBK - 1) / kBK * kBK);
+  const int parts = (int)((M + ks - 1) / ks);
+  da.M = M;
+  da.ks = ks;
+  da.n_params = n->n_params;
+  da.parts = n->t_parts;
+  int max_tiles = 0;
+  for (int l = 0; l < n->n_layers; ++l) {
+    DwLayer& D = da.L[l];
+    D.N = n->out_dim[l];
+    D.K = n->in_dim[l];
+    D.w_off = n->w_off[l];
+    D.b_off = n->b_off[l];
+    D.A = l + 1 < n->n_layers ? Mat{n->t_dz + (long)l * M * H, 1, (long)H} : Mat{n->t_dy, 1, 16};
+    D.B = l == 0 ? Mat{n->t_xb, 32, 1} : Mat{n->t_a + (long)(l - 1) * M * H, (long)H, 1};
+    max_tiles = std::max(max_tiles, ((D.N + kBM - 1) / kBM) * ((D.K + kBN - 1) / kBN) + 1);
+  }
+  dw_kernel<<<dim3(max_tiles, n->n_layers, parts), 256, 0, st>>>(da);
+  FusedMap map;
+  std::memset(&map, 0, sizeof map);
+  map.n_layers = n->n_layers;
+  map.H = H;
+  map.n_in = n->n_in;
+  map.n_out = n->n_out;
+  map.n_hidden = L;
+  for (int l = 0; l < n->n_layers; ++l) {
+    map.w_off[l] = n->w_off[l];
+    map.b_off[l] = n->b_off[l];
+  }
+  train_update_kernel<<<nblk(n->n_params), 256, 0, st>>>(
+      mode, n->t_parts, parts, n->n_params, d_grad, n->w, n->m1, n->m2, n->wb, n->wf, n->wbt,
+      n->bias_f, map, lr, 0.9f, 0.999f, 1e-8f, c1, c2, n->loss, d_loss);
   return hipGetLastError();
 }
 
@@ -1079,13 +1511,16 @@ int cp_mlp_create(int32_t n_in, int32_t hidden, int32_t n_hidden, int32_t n_out,
     if (e == hipSuccess) e = hipMalloc((void**)&n->m2, sizeof(float) * off);
     if (e == hipSuccess) e = hipMalloc((void**)&n->loss, sizeof(float));
     if (e == hipSuccess) e = hipMemcpy(n->w, w.data(), sizeof(float) * off, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(n->loss, 0, sizeof(float));
     if (e == hipSuccess) e = hipMemset(n->m1, 0, sizeof(float) * off);
     if (e == hipSuccess) e = hipMemset(n->m2, 0, sizeof(float) * off);
     n->fusable = fusable(n_in, hidden, n_out);
     if (e == hipSuccess && n->fusable) {
       n->n_wf = fused_weight_count(n);
+      n->n_wbt = (long)hidden * 32 + (long)(n_hidden - 1) * hidden * hidden;
       std::vector<int> width(n->out_dim);
       e = hipMalloc((void**)&n->wf, sizeof(uint16_t) * n->n_wf);
+      if (e == hipSuccess) e = hipMalloc((void**)&n->wbt, sizeof(uint16_t) * n->n_wbt);
       if (e == hipSuccess) e = hipMalloc((void**)&n->bias_f, sizeof(float) * n->n_layers * hidden);
       if (e == hipSuccess) e = hipMalloc((void**)&n->d_b_off, sizeof(long) * n->n_layers);
       if (e == hipSuccess) e = hipMalloc((void**)&n->d_width, sizeof(int) * n->n_layers);
@@ -1119,6 +1554,9 @@ void cp_mlp_destroy(cp_mlp* n) {
   for (float* p : {n->w, n->grad, n->m1, n->m2, n->loss, n->bias_f}) if (p) (void)hipFree(p);
   if (n->wb) (void)hipFree(n->wb);
   if (n->wf) (void)hipFree(n->wf);
+  if (n->wbt) (void)hipFree(n->wbt);
+  free_train(n);
+  if (n->t_parts) (void)hipFree(n->t_parts);
   if (n->d_b_off) (void)hipFree(n->d_b_off);
   if (n->d_width) (void)hipFree(n->d_width);
   delete n;
@@ -1164,6 +1602,11 @@ int cp_mlp_gradients(cp_mlp* n, int64_t M, const float* d_x, const float* d_t, f
     if (!n || !d_x || !d_t) return api_fail(CP_E_ARG, "cp_mlp_gradients: NULL argument");
     if (M < 1) return api_fail(CP_E_ARG, "cp_mlp_gradients: M < 1");
     hipStream_t st = (hipStream_t)stream;
+    if (n->fusable) {
+      hipError_t e = fused_train(n, M, d_x, d_t, 0, n->grad, d_loss, 0.0f, 1.0f, 1.0f, st);
+      if (e == hipSuccess && d_grad) e = hipMemcpyAsync(d_grad, n->grad, sizeof(float) * n->n_params, hipMemcpyDeviceToDevice, st);
+      return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_mlp_gradients");
+    }
     hipError_t e = forward(n, M, d_x, n->n_in, st);
     if (e == hipSuccess) e = backward(n, M, d_t, st);
     if (e == hipSuccess && d_grad) e = hipMemcpyAsync(d_grad, n->grad, sizeof(float) * n->n_params, hipMemcpyDeviceToDevice, st);
@@ -1180,6 +1623,12 @@ int cp_mlp_train_step(cp_mlp* n, int64_t M, const float* d_x, const float* d_t, 
     if (!n || !d_x || !d_t) return api_fail(CP_E_ARG, "cp_mlp_train_step: NULL argument");
     if (M < 1 || !(lr > 0)) return api_fail(CP_E_ARG, "cp_mlp_train_step: M < 1 or lr <= 0");
     hipStream_t st = (hipStream_t)stream;
+    if (n->fusable) {
+      n->step += 1;
+      const float c1 = 1.0f - std::pow(0.9f, (float)n->step), c2 = 1.0f - std::pow(0.999f, (float)n->step);
+      hipError_t e = fused_train(n, M, d_x, d_t, 1, nullptr, d_loss, lr, c1, c2, st);
+      return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_mlp_train_step");
+    }
     hipError_t e = forward(n, M, d_x, n->n_in, st);
     if (e == hipSuccess) e = backward(n, M, d_t, st);
     if (e != hipSuccess) return api_hip_fail(e, "cp_mlp_train_step");
