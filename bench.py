@@ -89,18 +89,18 @@ TRAFFIC = [
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h",
                     "paper_2505_06791_amd/csrc/kernels.hip", "paper_2505_06791_amd/csrc/kernels.h"),
-        "sources_sha256": "38213fbb144e53f948fc4b2360e155b097aae88304a76daf9f7e1c7b46e150f5",
-        "fetch_kib": 5291.0, "fetch_scale": 262144.0 / 131086.7,
-        "write_kib": 115974.0, "write_scale": 1.0,
+        "sources_sha256": "416c3f3f4a40f0dd090a1766ff5a15f9385800993eb5b8190530edec45396a43",
+        "fetch_kib": 5290.3, "fetch_scale": 262144.0 / 131086.6,
+        "write_kib": 115974.8, "write_scale": 1.0,
     },
     {
         "kernel": "cp_rtc_pool<7, 1> (hipRTC)",
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h", "paper_2505_06791_amd/csrc/rtc.hip",
                     "paper_2505_06791_amd/csrc/kernels.h", "include/cprrtc.h"),
-        "sources_sha256": "7d01b5ad89161e59ecee33f0e2b3a530551e5079db6767edfd51cf9ff18cca94",
-        "fetch_kib": 5214.2, "fetch_scale": 262144.0 / 131086.7,
-        "write_kib": 116180.9, "write_scale": 1.0,
+        "sources_sha256": "bf43a567e582c68872150ca5c27482e12164232810d04736624231ca0c2a2371",
+        "fetch_kib": 5206.1, "fetch_scale": 262144.0 / 131086.6,
+        "write_kib": 116176.8, "write_scale": 1.0,
     },
 ]
 
