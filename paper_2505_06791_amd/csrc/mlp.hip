@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -453,24 +454,28 @@ struct ChunkStream {
   }
 };
 
-// What a training forward pass keeps for the backward pass (all [sample]
-// rows): the layer-0 inputs as BF16 (32 columns), every hidden layer's
-// pre-activation (FP32) and activation (BF16), the output gradient of the
-// mean squared error as BF16 (16 columns) and the loss (accumulated).
+// What a training forward pass keeps for the backward pass and the weight
+// gradients: the layer-0 inputs, every hidden layer's activation and the
+// output gradient of the mean squared error, all BF16 and transposed
+// (unit-major rows of ldt >= M samples, so that a 16-byte load holds 8
+// consecutive samples of one unit, the matrix cores' operand layout for a
+// reduction over samples); SiLU' of every hidden pre-activation (BF16, in
+// the result layout of the kernels, read back by the backward pass); the
+// loss (accumulated).
 struct TrainIO {
   const float* target;   // [M][n_out]
-  uint16_t* xb;          // [M][32]
-  float* z;              // [n_hidden][M][H]
-  uint16_t* a;           // [n_hidden][M][H]
-  uint16_t* dy;          // [M][16]
+  uint16_t* xt;          // [32][ldt]
+  uint16_t* d;           // SiLU'(z): [block][n_hidden][wavefront][tile][lane][4]
+  uint16_t* at;          // [n_hidden][H][ldt]
+  uint16_t* dyt;         // [16][ldt]
   float* loss;
   float inv_mn;          // 1 / (M n_out)
+  long ldt;
 };
 
-template <int H, int ST, int NW, class F, bool TRAIN = false>
+template <int H, int ST, int NW, class F>
 __global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(FusedNet net, F feat, long M,
-                                                        float* __restrict__ y, long ldy,
-                                                        TrainIO tr = TrainIO{}) {
+                                                        float* __restrict__ y, long ldy) {
   constexpr int KC = H / 32;       // reduction chunks of a hidden-input layer
   constexpr int NT = H / 16;       // result tiles of a hidden layer
   constexpr int ROWS = H * 4;      // 16-byte pieces of a full chunk
@@ -546,7 +551,6 @@ __global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(FusedNet net, F feat
     }
     const uint4 u{pack_bf16(f[0], f[1]), pack_bf16(f[2], f[3]), pack_bf16(f[4], f[5]), pack_bf16(f[6], f[7])};
     xin[st] = __builtin_bit_cast(bf16x8, u);
-    if (TRAIN && s < M) *reinterpret_cast<uint4*>(tr.xb + s * 32 + 8 * g) = u;
   }
   FUSED_BEGIN(0)
   chunk_mfma(xin, 0);
@@ -565,16 +569,6 @@ __global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(FusedNet net, F feat
                       pack_bf16(silu_fast(hi[0]), silu_fast(hi[1])),
                       pack_bf16(silu_fast(hi[2]), silu_fast(hi[3]))};
         act[c][st] = __builtin_bit_cast(bf16x8, u);
-        if (TRAIN) {
-          const long s = s0 + st * 16 + r;
-          if (s < M) {
-            const long row = ((long)l * M + s) * H + 32 * c + 4 * g;
-            *reinterpret_cast<f32x4*>(tr.z + row) = lo;
-            *reinterpret_cast<f32x4*>(tr.z + row + 16) = hi;
-            *reinterpret_cast<uint2*>(tr.a + row) = uint2{u.x, u.y};
-            *reinterpret_cast<uint2*>(tr.a + row + 16) = uint2{u.z, u.w};
-          }
-        }
       }
     }
   };
@@ -609,148 +603,350 @@ __global__ __launch_bounds__(NW * 64) void mlp_fused_kernel(FusedNet net, F feat
     for (int st = 0; st < ST; ++st)
       out[st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[kc][st], out[st], 0, 0, 0);
   }
-  float lsum = 0.0f;
 #pragma unroll
   for (int st = 0; st < ST; ++st) {
     const long s = s0 + st * 16 + r;
     if (s >= M) continue;
-    if (TRAIN) {
-      // dY = 2 (y - t) / (M n_out) on the real outputs, zero on the padding
-      float d[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int n = 4 * g + t;
-        d[t] = n < net.n_out ? out[st][t] - tr.target[s * net.n_out + n] : 0.0f;
-        lsum += d[t] * d[t];
-      }
-      const float k = 2.0f * tr.inv_mn;
-      *reinterpret_cast<uint2*>(tr.dy + s * 16 + 4 * g) =
-          uint2{pack_bf16(k * d[0], k * d[1]), pack_bf16(k * d[2], k * d[3])};
+    for (int t = 0; t < 4; ++t) {
+      const int n = 4 * g + t;
+      if (n < net.n_out) y[s * ldy + n] = out[st][t];
     }
-    if (y) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int n = 4 * g + t;
-        if (n < net.n_out) y[s * ldy + n] = out[st][t];
-      }
-    }
-  }
-  if (TRAIN) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-    if (lane == 0) atomicAdd(tr.loss, lsum * tr.inv_mn);
   }
 #undef FUSED_BEGIN
 #undef FUSED_END
 }
 
-// Backward pass of the fused network for the samples of mlp_fused_kernel's
-// training forward (same sample mapping): from dY, every hidden layer's
-// pre-activation gradient dZ_l = (W_{l+1}^T dZ_{l+1}) * SiLU'(z_l) into dz
-// ([n_hidden][M][H], BF16), computed transposed with the transposed weights
-// as the A operand, so dZ_l stays in registers as the next product's B
-// operand exactly as activations do in the forward pass.  Weight chunks
-// (fused_weights_t_kernel): the output layer's W^T as one chunk of H rows x
-// 32 (output units, natural order, zero past n_out), then, from the last
-// hidden-to-hidden layer down, each one's H/32 chunks of W^T (H rows x 32
-// output units in fused_perm order), all in the chunk_at layout.
-template <int H, int ST, int NW>
-__global__ __launch_bounds__(NW * 64) void mlp_bwd_fused_kernel(const uint16_t* __restrict__ wbt,
-                                                            int n_hidden, long M, TrainIO tr,
-                                                            uint16_t* __restrict__ dz) {
-  constexpr int KC = H / 32;
-  constexpr int NT = H / 16;
-  constexpr int PRE = (H * 4 + NW * 64 - 1) / (NW * 64);
-  __shared__ __align__(16) uint16_t wl[2][H * kFusedLdw];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r = lane & 15, g = lane >> 4;
-  const long s0 = ((long)blockIdx.x * NW + wave) * (16 * ST);
-  const int nq = 1 + (n_hidden - 1) * KC;
-  const ChunkStream<H, PRE, NW> cs{wbt, nq, tid};    // every chunk is H x 32
-  ChunkRegs<PRE> pre0 = cs.fetch(0), pre1;
-  if (nq > 1) pre1 = cs.fetch(1);
-  cs.put(0, pre0, wl[0]);
-  __syncthreads();
-  int q = 0;
-#define BWD_BEGIN(PAR)                                     \
-  if (q + 2 < nq) {                                        \
-    if (PAR == 0) pre0 = cs.fetch(q + 2);                  \
-    else pre1 = cs.fetch(q + 2);                           \
-  }
-#define BWD_END(PAR)                                                     \
-  if (q + 1 < nq) cs.put(q + 1, PAR == 0 ? pre1 : pre0, wl[(q + 1) & 1]); \
-  __syncthreads();                                                       \
-  ++q;
-  f32x4 acc[NT][ST];
-  auto chunk_mfma = [&](const bf16x8 (&b)[ST], bool first) {
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(
-                                                      &wl[q & 1][chunk_at(nt * 16 + r, g)]));
-#pragma unroll
-      for (int st = 0; st < ST; ++st)
-        acc[nt][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-            a, b[st], first ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[nt][st], 0, 0, 0);
-    }
-  };
-  // output layer: B operand = dY (outputs 8g .. 8g+7 of this lane's sample)
-  bf16x8 dyb[ST];
-#pragma unroll
-  for (int st = 0; st < ST; ++st) {
-    const long s = s0 + st * 16 + r;
-    uint4 u{0u, 0u, 0u, 0u};
-    if (s < M && g < 2) u = *reinterpret_cast<const uint4*>(tr.dy + s * 16 + 8 * g);
-    dyb[st] = __builtin_bit_cast(bf16x8, u);
-  }
-  BWD_BEGIN(0)
-  chunk_mfma(dyb, true);
-  BWD_END(0)
-  // dZ_l = acc * SiLU'(z_l), stored, and kept as the next B operand
-  bf16x8 act[KC][ST];
-  auto epilogue = [&](int l) {
-#pragma unroll
-    for (int c = 0; c < KC; ++c) {
-#pragma unroll
-      for (int st = 0; st < ST; ++st) {
-        const long s = s0 + st * 16 + r;
-        const bool in = s < M;
-        const long row = ((long)l * M + (in ? s : 0)) * H + 32 * c + 4 * g;
-        f32x4 zl{0.f, 0.f, 0.f, 0.f}, zh{0.f, 0.f, 0.f, 0.f};
-        if (in) {
-          zl = *reinterpret_cast<const f32x4*>(tr.z + row);
-          zh = *reinterpret_cast<const f32x4*>(tr.z + row + 16);
-        }
-        const f32x4 lo = acc[2 * c][st], hi = acc[2 * c + 1][st];
-        const uint4 u{pack_bf16(lo[0] * silu_grad_fast(zl[0]), lo[1] * silu_grad_fast(zl[1])),
-                      pack_bf16(lo[2] * silu_grad_fast(zl[2]), lo[3] * silu_grad_fast(zl[3])),
-                      pack_bf16(hi[0] * silu_grad_fast(zh[0]), hi[1] * silu_grad_fast(zh[1])),
-                      pack_bf16(hi[2] * silu_grad_fast(zh[2]), hi[3] * silu_grad_fast(zh[3]))};
-        act[c][st] = __builtin_bit_cast(bf16x8, u);
-        if (in) {
-          *reinterpret_cast<uint2*>(dz + row) = uint2{u.x, u.y};
-          *reinterpret_cast<uint2*>(dz + row + 16) = uint2{u.z, u.w};
-        }
-      }
-    }
-  };
-  epilogue(n_hidden - 1);
-  for (int l = n_hidden - 1; l >= 1; --l) {
-#pragma unroll
-    for (int kc = 0; kc < KC; kc += 2) {
-      BWD_BEGIN(1)
-      chunk_mfma(act[kc], kc == 0);
-      BWD_END(1)
-      BWD_BEGIN(0)
-      chunk_mfma(act[kc + 1], false);
-      BWD_END(0)
-    }
-    epilogue(l - 1);
-  }
-#undef BWD_BEGIN
-#undef BWD_END
+// Training forward and backward passes for small batches.  A workgroup
+// takes SB = 16 ST samples and its NW wavefronts split each layer's units
+// (16 T per wavefront), so a batch of a few thousand samples still spreads
+// over every CU.  A layer's input block (SB samples x its inputs, BF16) sits
+// in LDS; a wavefront reads it as the A operand and its weight fragments
+// straight from global memory as the B operand (the rows of its units in
+// the fused chunk layout, whose input order the A reads follow), with the
+// next groups of k-chunks in flight while it works on this one.  Results
+// (C: unit = lane % 16, samples 4 (lane / 16) + i) go through the epilogue
+// into the other LDS block, which is then written out transposed for the
+// weight gradients.  SiLU' of the pre-activations is stored in the C layout
+// itself (per workgroup, layer, wavefront, tile), which the backward pass
+// reads with the same mapping.
+// Workgroups are dispatched to the eight XCDs in turn (workgroup i to XCD
+// i % 8).  The training kernels give XCD x the x-th contiguous eighth of the
+// batch, so the forward pass, the backward pass and the weight-gradient
+// range of the same samples run on one XCD and meet their data in its L2.
+__device__ __forceinline__ long xcd_block(long i, long n) {
+  return n % 8 == 0 ? (i % 8) * (n / 8) + i / 8 : i;
 }
 
-// Builds the backward weight chunks (see mlp_bwd_fused_kernel) from the
+template <int H>
+struct TrainShape {
+  static constexpr int NW = H >= 256 ? 8 : H / 32;          // wavefronts per workgroup
+  static constexpr int T = H / (16 * NW);                    // unit tiles per wavefront
+  static constexpr int KC = H / 32;                          // k-chunks of a hidden layer
+  static constexpr int G = H >= 512 ? 4 : 2;                 // k-chunk groups per layer (even)
+  static constexpr int GK = KC / G;                          // k-chunks per group
+  static constexpr int ST = 1;                               // 16-sample tiles per workgroup
+  static constexpr int SB = 16 * ST;
+  static constexpr int LDA = H + 8;                          // LDS row stride (elements)
+  static constexpr int KCW = KC / NW;                        // output-layer k-chunks per wavefront
+  static_assert(T >= 1 && GK >= 1 && KCW >= 1, "unsupported width");
+};
+
+// A operand: the 8 inputs of k-chunk c at fused_perm slots 8g .. 8g+7 of
+// row s of an activation block (inputs 32c + 4g + 0..3 and 32c + 16 + 4g + 0..3).
+template <int LDA>
+__device__ __forceinline__ bf16x8 act_frag_perm(const uint16_t* blk, int s, int c, int g) {
+  const uint16_t* row = blk + s * LDA + 32 * c + 4 * g;
+  const uint2 lo = *reinterpret_cast<const uint2*>(row);
+  const uint2 hi = *reinterpret_cast<const uint2*>(row + 16);
+  return __builtin_bit_cast(bf16x8, uint4{lo.x, lo.y, hi.x, hi.y});
+}
+template <int LDA>
+__device__ __forceinline__ bf16x8 act_frag_nat(const uint16_t* blk, int s, int g) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(blk + s * LDA + 8 * g));
+}
+
+__device__ __forceinline__ uint16_t bf16_bits(float v) { return (uint16_t)(pack_bf16(v, 0.0f) & 0xffffu); }
+
+// Writes an LDS block (SB sample rows x W columns, row stride LDA) out
+// transposed: column u to out[u * ldt + sample], 8 samples per 16-byte store.
+template <int W, int SB, int LDA, int NTH>
+__device__ __forceinline__ void block_out_t(const uint16_t* blk, int rows, uint16_t* out, long ldt,
+                                            int tid) {
+  for (int p = tid; p < W * (SB / 8); p += NTH) {
+    const int u = p / (SB / 8), s8 = (p % (SB / 8)) * 8;
+    uint16_t v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = blk[(s8 + i) * LDA + u];
+    uint16_t* dst = out + (long)u * ldt + s8;
+    if (s8 + 8 <= rows) {
+      *reinterpret_cast<uint4*>(dst) =
+          uint4{v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16),
+                v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16)};
+    } else {
+      for (int i = 0; i < 8 && s8 + i < rows; ++i) dst[i] = v[i];
+    }
+  }
+}
+
+template <int H>
+__global__ __launch_bounds__(TrainShape<H>::NW * 64) void mlp_train_fwd_kernel(FusedNet net,
+                                                                             FeatRows feat, long M,
+                                                                             TrainIO tr) {
+  using S = TrainShape<H>;
+  constexpr int NW = S::NW, T = S::T, G = S::G, GK = S::GK, ST = S::ST, SB = S::SB, LDA = S::LDA;
+  constexpr int KCW = S::KCW, NTH = NW * 64;
+  __shared__ __align__(16) uint16_t act[2][SB * LDA];
+  __shared__ __align__(16) f32x4 red[NW][ST][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const long blk = xcd_block(blockIdx.x, gridDim.x);
+  const long sb = blk * SB;
+  const int rows = (int)min((long)SB, M - sb);
+  const int nh = net.n_hidden;
+  const int u0 = wave * 16 * T;
+  const uint16_t* wh = net.wf + (long)H * 32;                          // hidden layers
+  const uint16_t* wl = net.wf + (long)H * 32 + (long)(nh - 1) * H * H;  // output layer [16][H]
+
+  // weight fragments: layer 0 and the output layer now, the first two
+  // groups of the hidden layers into the two register sets
+  uint4 w0[T], wo[KCW], ws0[T][GK], ws1[T][GK];
+#pragma unroll
+  for (int t = 0; t < T; ++t) w0[t] = *reinterpret_cast<const uint4*>(net.wf + (long)(u0 + 16 * t + r) * 32 + 8 * g);
+#pragma unroll
+  for (int i = 0; i < KCW; ++i)
+    wo[i] = *reinterpret_cast<const uint4*>(wl + (long)r * H + 32 * (wave * KCW + i) + 8 * g);
+  const int NG = (nh - 1) * G;
+  auto load_group = [&](int q, uint4 (&w)[T][GK]) {
+    const int l = 1 + q / G, j = q % G;
+    const uint16_t* base = wh + (long)(l - 1) * H * H + (long)(j * GK) * H * 32;
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int cc = 0; cc < GK; ++cc)
+        w[t][cc] = *reinterpret_cast<const uint4*>(base + (long)cc * H * 32 + (long)(u0 + 16 * t + r) * 32 + 8 * g);
+  };
+  if (NG > 0) load_group(0, ws0);
+  if (NG > 1) load_group(1, ws1);
+
+  // layer-0 inputs: BF16 into LDS block 0 (32 columns, zero padded)
+  for (int e = tid; e < SB * 32; e += NTH) {
+    const int s = e / 32, k = e % 32;
+    const float v = (s < rows && k < net.n_in) ? feat.x[(sb + s) * feat.ld + k] : 0.0f;
+    act[0][s * LDA + k] = bf16_bits(v);
+  }
+  __syncthreads();
+  block_out_t<32, SB, LDA, NTH>(act[0], rows, tr.xt + sb, tr.ldt, tid);
+
+  f32x4 acc[T][ST];
+  auto start = [&](int l) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const float b = net.bias[l * H + u0 + 16 * t + r];
+#pragma unroll
+      for (int st = 0; st < ST; ++st) acc[t][st] = f32x4{b, b, b, b};
+    }
+  };
+  // SiLU' to its store, SiLU into LDS block `out`, then the block to a_l
+  auto epilogue = [&](int l, int out) {
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int st = 0; st < ST; ++st) {
+        const f32x4 z = acc[t][st];
+        const long di = ((((blk * nh + l) * NW + wave) * T + t) * ST + st) * 64 + lane;
+        reinterpret_cast<uint2*>(tr.d)[di] =
+            uint2{pack_bf16(silu_grad_fast(z[0]), silu_grad_fast(z[1])),
+                  pack_bf16(silu_grad_fast(z[2]), silu_grad_fast(z[3]))};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          act[out][(16 * st + 4 * g + i) * LDA + u0 + 16 * t + r] = bf16_bits(silu_fast(z[i]));
+      }
+    __syncthreads();
+    block_out_t<H, SB, LDA, NTH>(act[out], rows, tr.at + (long)l * H * tr.ldt + sb, tr.ldt, tid);
+  };
+
+  // layer 0 (one k-chunk, natural input order)
+  start(0);
+#pragma unroll
+  for (int st = 0; st < ST; ++st) {
+    const bf16x8 a = act_frag_nat<LDA>(act[0], 16 * st + r, g);
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      acc[t][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, w0[t]), acc[t][st], 0, 0, 0);
+  }
+  epilogue(0, 1);
+  int in = 1;
+  // hidden-to-hidden layers: groups alternate between the register sets
+  for (int l = 1; l < nh; ++l) {
+    start(l);
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int q = (l - 1) * G + j;
+      auto& w = (j & 1) ? ws1 : ws0;
+#pragma unroll
+      for (int cc = 0; cc < GK; ++cc) {
+        const int c = j * GK + cc;
+#pragma unroll
+        for (int st = 0; st < ST; ++st) {
+          const bf16x8 a = act_frag_perm<LDA>(act[in], 16 * st + r, c, g);
+#pragma unroll
+          for (int t = 0; t < T; ++t)
+            acc[t][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, w[t][cc]), acc[t][st], 0, 0, 0);
+        }
+      }
+      if (q + 2 < NG) load_group(q + 2, w);
+    }
+    epilogue(l, in ^ 1);
+    in ^= 1;
+  }
+
+  // output layer: each wavefront reduces its KCW k-chunks for all 16
+  // outputs, wavefront 0 sums the partials in a fixed order
+  f32x4 o[ST];
+#pragma unroll
+  for (int st = 0; st < ST; ++st) {
+    o[st] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < KCW; ++i) {
+      const bf16x8 a = act_frag_perm<LDA>(act[in], 16 * st + r, wave * KCW + i, g);
+      o[st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, wo[i]), o[st], 0, 0, 0);
+    }
+    red[wave][st][lane] = o[st];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  // dY = 2 (y - t) / (M n_out) on the real outputs, zero on the padding:
+  // output r, samples 4g .. 4g+3 of each tile (consecutive in dyt's row r)
+  const float bo = r < net.n_out ? net.bias[nh * H + r] : 0.0f;
+  float lsum = 0.0f;
+#pragma unroll
+  for (int st = 0; st < ST; ++st) {
+    f32x4 y = f32x4{bo, bo, bo, bo};
+    for (int w = 0; w < NW; ++w) y += red[w][st][lane];
+    float d[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int s = 16 * st + 4 * g + i;
+      d[i] = 0.0f;
+      if (s < rows && r < net.n_out) d[i] = y[i] - tr.target[(sb + s) * net.n_out + r];
+      lsum += d[i] * d[i];
+    }
+    const float k = 2.0f * tr.inv_mn;
+    uint16_t* dst = tr.dyt + (long)r * tr.ldt + sb + 16 * st + 4 * g;
+    if (16 * st + 4 * g + 4 <= rows) {
+      *reinterpret_cast<uint2*>(dst) = uint2{pack_bf16(k * d[0], k * d[1]), pack_bf16(k * d[2], k * d[3])};
+    } else {
+      for (int i = 0; i < 4 && 16 * st + 4 * g + i < rows; ++i) dst[i] = bf16_bits(k * d[i]);
+    }
+  }
+#pragma unroll
+  for (int o2 = 32; o2 >= 1; o2 >>= 1) lsum += __shfl_xor(lsum, o2, 64);
+  if (lane == 0) atomicAdd(tr.loss, lsum * tr.inv_mn);
+}
+
+// Backward pass for mlp_train_fwd_kernel's samples: dZ_{n_h-1} = (W_out^T
+// dY) * SiLU'(z), then dZ_{l-1} = (W_l^T dZ_l) * SiLU'(z_{l-1}) down to
+// layer 0, each to dzt ([n_hidden][H][ldt], BF16, transposed).  The
+// transposed weights come from the backward chunks (fused_weights_t_kernel):
+// the output layer's W^T ([H][32], natural order), then per hidden layer
+// from the last down, H/32 chunks of [H][32] in fused_perm order.
+template <int H>
+__global__ __launch_bounds__(TrainShape<H>::NW * 64) void mlp_train_bwd_kernel(
+    const uint16_t* __restrict__ wbt, int nh, long M, TrainIO tr, uint16_t* __restrict__ dzt) {
+  using S = TrainShape<H>;
+  constexpr int NW = S::NW, T = S::T, G = S::G, GK = S::GK, ST = S::ST, SB = S::SB, LDA = S::LDA;
+  constexpr int NTH = NW * 64;
+  __shared__ __align__(16) uint16_t act[2][SB * LDA];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const long blk = xcd_block(blockIdx.x, gridDim.x);
+  const long sb = blk * SB;
+  const int rows = (int)min((long)SB, M - sb);
+  const int u0 = wave * 16 * T;
+  const uint16_t* wh = wbt + (long)H * 32;
+  uint4 wo[T], ws0[T][GK], ws1[T][GK];
+#pragma unroll
+  for (int t = 0; t < T; ++t) wo[t] = *reinterpret_cast<const uint4*>(wbt + (long)(u0 + 16 * t + r) * 32 + 8 * g);
+  const int NG = (nh - 1) * G;
+  // group q: product j = q / G (layer l = nh - 1 - j), k-chunks (q % G) GK ..
+  auto load_group = [&](int q, uint4 (&w)[T][GK]) {
+    const int j = q / G, c0 = (q % G) * GK;
+    const uint16_t* base = wh + (long)j * H * H + (long)c0 * H * 32;
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int cc = 0; cc < GK; ++cc)
+        w[t][cc] = *reinterpret_cast<const uint4*>(base + (long)cc * H * 32 + (long)(u0 + 16 * t + r) * 32 + 8 * g);
+  };
+  if (NG > 0) load_group(0, ws0);
+  if (NG > 1) load_group(1, ws1);
+
+  // dY into LDS block 0 (32 columns, zero past 16)
+  for (int e = tid; e < SB * 32; e += NTH) {
+    const int s = e % SB, k = e / SB;
+    act[0][s * LDA + k] = (s < rows && k < 16) ? tr.dyt[(long)k * tr.ldt + sb + s] : (uint16_t)0;
+  }
+  __syncthreads();
+
+  f32x4 acc[T][ST];
+  // dZ_l = acc * SiLU'(z_l) into LDS block `out`, then the block to dzt_l
+  auto epilogue = [&](int l, int out) {
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int st = 0; st < ST; ++st) {
+        const long di = ((((blk * nh + l) * NW + wave) * T + t) * ST + st) * 64 + lane;
+        const uint2 dv = reinterpret_cast<const uint2*>(tr.d)[di];
+        const float dd[4] = {__uint_as_float(dv.x << 16), __uint_as_float(dv.x & 0xffff0000u),
+                             __uint_as_float(dv.y << 16), __uint_as_float(dv.y & 0xffff0000u)};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          act[out][(16 * st + 4 * g + i) * LDA + u0 + 16 * t + r] = bf16_bits(acc[t][st][i] * dd[i]);
+      }
+    __syncthreads();
+    block_out_t<H, SB, LDA, NTH>(act[out], rows, dzt + (long)l * H * tr.ldt + sb, tr.ldt, tid);
+  };
+
+  // output layer: one k-chunk of dY (natural order)
+#pragma unroll
+  for (int st = 0; st < ST; ++st) {
+    const bf16x8 a = act_frag_nat<LDA>(act[0], 16 * st + r, g);
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      acc[t][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, wo[t]),
+                                                           f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+  }
+  epilogue(nh - 1, 1);
+  int in = 1;
+  for (int l = nh - 1; l >= 1; --l) {
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int st = 0; st < ST; ++st) acc[t][st] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int q = (nh - 1 - l) * G + j;
+      auto& w = (j & 1) ? ws1 : ws0;
+#pragma unroll
+      for (int cc = 0; cc < GK; ++cc) {
+        const int c = j * GK + cc;
+#pragma unroll
+        for (int st = 0; st < ST; ++st) {
+          const bf16x8 a = act_frag_perm<LDA>(act[in], 16 * st + r, c, g);
+#pragma unroll
+          for (int t = 0; t < T; ++t)
+            acc[t][st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, w[t][cc]), acc[t][st], 0, 0, 0);
+        }
+      }
+      if (q + 2 < NG) load_group(q + 2, w);
+    }
+    epilogue(l - 1, in ^ 1);
+    in ^= 1;
+  }
+}
+
+// Builds the backward weight chunks (see mlp_train_bwd_kernel) from the
 // FP32 masters.
 __global__ void fused_weights_t_kernel(const float* __restrict__ w, int H, int n_out, int n_hidden,
                                        long w_off_h, long w_stride_h, long w_off_last,
@@ -773,74 +969,6 @@ __global__ void fused_weights_t_kernel(const float* __restrict__ w, int H, int n
     v = w[w_off_h + (long)(l - 1) * w_stride_h + (long)(32 * c + fused_perm(p)) * H + k];
   }
   wbt[e] = to_bf16(v);
-}
-
-// Weight gradients of one training step, all layers in one launch:
-// blockIdx.y = layer, blockIdx.z = range of the batch, blockIdx.x = a
-// 64 x 64 tile of dW = dZ^T X (or, for the last x, the layer's bias
-// gradient, column sums of dZ); each writes its range's partial sums into
-// parts[z][parameter index] (summed in a fixed order by the update kernel).
-struct DwLayer {
-  Mat A;          // dZ^T: (unit, sample)
-  Mat B;          // X: (sample, input)
-  int N, K;       // units, inputs
-  long w_off, b_off;
-};
-struct DwArgs {
-  DwLayer L[kFusedMaxLayers];
-  long M;         // samples
-  int ks;         // samples per range (a multiple of 32)
-  long n_params;
-  float* parts;
-};
-
-__global__ __launch_bounds__(256) void dw_kernel(DwArgs args) {
-  __shared__ __align__(16) uint16_t As[kBM][kBK + kPad];
-  __shared__ __align__(16) uint16_t Bs[kBN][kBK + kPad];
-  const DwLayer& L = args.L[blockIdx.y];
-  const int tn = (L.K + kBN - 1) / kBN, tm = (L.N + kBM - 1) / kBM;
-  const int tile = blockIdx.x;
-  if (tile > tm * tn) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int kb = blockIdx.z * args.ks;
-  const int ke = (int)min((long)kb + args.ks, args.M);
-  float* out = args.parts + (long)blockIdx.z * args.n_params;
-  if (tile == tm * tn) {            // bias gradient: sums of dZ over this range
-    for (int n = tid; n < L.N; n += 256) {
-      float sum = 0.0f;
-      for (int s = kb; s < ke; ++s) sum += from_bf16(L.A.p[(long)n * L.A.rs + (long)s * L.A.cs]);
-      out[L.b_off + n] = sum;
-    }
-    return;
-  }
-  const int m0 = (tile / tn) * kBM, n0 = (tile % tn) * kBN;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const Mat Bt{L.B.p, L.B.cs, L.B.rs};
-  f32x4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kb; k0 < ke; k0 += kBK) {
-    stage<kBM>(As, L.A, m0, k0, L.N, ke, tid);
-    stage<kBN>(Bs, Bt, n0, k0, L.K, ke, tid);
-    __syncthreads();
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
-    bf16x8 a[2], b[2];
-    for (int i = 0; i < 2; ++i)
-      a[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&As[wm + i * 16 + fr][fk]));
-    for (int j = 0; j < 2; ++j)
-      b[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Bs[wn + j * 16 + fr][fk]));
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
-  }
-  const int col = lane & 15, rb = (lane >> 4) * 4;
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
-      for (int t = 0; t < 4; ++t) {
-        const int gm = m0 + wm + i * 16 + rb + t, gn = n0 + wn + j * 16 + col;
-        if (gm < L.N && gn < L.K) out[L.w_off + (long)gm * L.K + gn] = acc[i][j][t];
-      }
 }
 
 // The parameter index -> positions in the fused forward and backward weight
@@ -876,43 +1004,209 @@ struct FusedMap {
   }
 };
 
-// One update of every parameter from the partial gradients: g = sum over
-// the ranges (fixed order); mode 0 stores g; mode 1 takes an Adam step on
-// the FP32 master and refreshes its BF16 copy, its fused forward and
-// backward chunk entries and the padded bias.  Thread 0 also hands out the
-// step's loss and clears the accumulator for the next step.
-__global__ void train_update_kernel(int mode, const float* __restrict__ parts, int n_parts,
-                                    long n_params, float* __restrict__ grad, float* __restrict__ w,
-                                    float* __restrict__ m1, float* __restrict__ m2,
-                                    uint16_t* __restrict__ wb, uint16_t* __restrict__ wf,
-                                    uint16_t* __restrict__ wbt, float* __restrict__ bias_f,
-                                    FusedMap map, float lr, float b1, float b2, float eps, float c1,
-                                    float c2, float* __restrict__ loss, float* __restrict__ loss_out) {
+// What a training step updates, and how: mode 0 stores the gradient; mode
+// 1 takes an Adam step on the FP32 master (learning rate lr, moments b1,
+// b2, bias corrections c1, c2) and refreshes its BF16 copy, its fused
+// forward and backward chunk entries and the padded bias.
+struct UpdateArgs {
+  int mode;
+  float* grad;
+  float* w;
+  float* m1;
+  float* m2;
+  uint16_t* wb;
+  uint16_t* wf;
+  uint16_t* wbt;
+  float* bias_f;
+  FusedMap map;
+  float lr, b1, b2, eps, c1, c2;
+  float* loss;       // the step's loss accumulator (cleared after the hand-out)
+  float* loss_out;   // nullable
+};
+
+__device__ __forceinline__ void update_param(const UpdateArgs& u, long i, float gi) {
+  if (u.mode == 0) {
+    u.grad[i] = gi;
+    return;
+  }
+  const float a = u.b1 * u.m1[i] + (1.0f - u.b1) * gi;
+  const float v = u.b2 * u.m2[i] + (1.0f - u.b2) * gi * gi;
+  u.m1[i] = a;
+  u.m2[i] = v;
+  const float nw = u.w[i] - u.lr * (a / u.c1) / (sqrtf(v / u.c2) + u.eps);
+  u.w[i] = nw;
+  const uint16_t hb = to_bf16(nw);
+  u.wb[i] = hb;
+  long fwd, bwd, bias;
+  u.map.locate(i, fwd, bwd, bias);
+  if (fwd >= 0) u.wf[fwd] = hb;
+  if (bwd >= 0) u.wbt[bwd] = hb;
+  if (bias >= 0) u.bias_f[bias] = nw;
+}
+
+// Weight gradients of one training step, all layers in one launch:
+// blockIdx.x = range of the batch (eight ranges: range x on XCD x, where
+// the training kernels left its samples), blockIdx.y = a TM x TN tile of
+// dW = dZ^T X, blockIdx.z = layer.  Each workgroup writes its range's
+// partial sums into parts[range][parameter index], summed in a fixed order
+// by train_update_kernel.  (Finishing a tile in the workgroup of its last
+// range instead, behind a counter, needs a device-scope release per
+// workgroup, which writes back the XCD's L2 each time: measured ten times
+// slower than the separate launch.)
+// Both operands are stored transposed (unit-major rows of ld samples), so
+// every operand fragment of the matrix cores (one unit, 8 consecutive
+// samples) is one 16-byte load from global memory: no LDS staging.  The
+// four wavefronts of a workgroup take every fourth 32-sample step of the
+// range, keep D steps of fragments in flight, and sum their partial tiles
+// through LDS at the end.  The workgroups of a layer's first column of
+// tiles also form its bias gradient (sums of dZ over the samples) on the
+// matrix cores, as the product with a fragment of ones.
+struct DwLayer {
+  const uint16_t* A;   // dZ^T: (unit n, sample s) at A[n * ld + s]
+  const uint16_t* B;   // X^T: (input k, sample s) at B[k * ld + s]
+  int N, K;            // units, inputs
+  int NA, KB;          // unit and input rows present (multiples of 16; zero past N, K)
+  long w_off, b_off;
+};
+struct DwArgs {
+  DwLayer L[kFusedMaxLayers];
+  long M;         // samples
+  long ld;        // row stride of the operands (>= M, a multiple of 8)
+  int ks;         // samples per range (a multiple of 32)
+  long n_params;
+  float* parts;   // [ranges][n_params]
+};
+
+// The first lim (< 8) of the 8 BF16 values in v, zeros after.
+__device__ __forceinline__ uint4 keep_first(uint4 v, int lim) {
+  uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) w[j] &= 2 * j + 1 < lim ? 0xffffffffu : (2 * j < lim ? 0x0000ffffu : 0u);
+  return uint4{w[0], w[1], w[2], w[3]};
+}
+
+template <int MI, int NI, int D>
+__global__ __launch_bounds__(256) void dw_kernel(DwArgs args) {
+  constexpr int TM = 16 * MI, TN = 16 * NI, NACC = MI * NI + MI;
+  __shared__ f32x4 red[NACC][64];
+  const DwLayer& L = args.L[blockIdx.z];
+  const int tn = (L.K + TN - 1) / TN, tm = (L.N + TM - 1) / TM;
+  const int tile = blockIdx.y;
+  if (tile >= tm * tn) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r = lane & 15, g = lane >> 4;
+  const long kb = (long)blockIdx.x * args.ks;
+  const long ke = min(kb + (long)args.ks, args.M);
+  const int m0 = (tile / tn) * TM, n0 = (tile % tn) * TN;
+  const bool with_bias = n0 == 0;
+  const int all_steps = (int)((ke - kb + 31) / 32);
+  const int ns = all_steps > wave ? (all_steps - wave + 3) / 4 : 0;   // steps wave, wave + 4, ...
+  const long ld = args.ld;
+  // fragment: row `row` (unit or input), samples k0 + 8g .. +7 (zero past ke)
+  auto frag = [&](const uint16_t* base, int row, int avail, long k0) {
+    uint4 v{0u, 0u, 0u, 0u};
+    const long kk = k0 + 8 * g;
+    if (row < avail && kk < ke) {
+      v = *reinterpret_cast<const uint4*>(base + (long)row * ld + kk);
+      if (ke - kk < 8) v = keep_first(v, (int)(ke - kk));
+    }
+    return v;
+  };
+  uint4 fa[D][MI], fb[D][NI];
+  auto load = [&](int i, uint4 (&a)[MI], uint4 (&b)[NI]) {
+    const long k0 = kb + 32L * (wave + 4 * i);
+#pragma unroll
+    for (int mi = 0; mi < MI; ++mi) a[mi] = frag(L.A, m0 + 16 * mi + r, L.NA, k0);
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni) b[ni] = frag(L.B, n0 + 16 * ni + r, L.KB, k0);
+  };
+  f32x4 acc[MI][NI], accb[MI];
+#pragma unroll
+  for (int i = 0; i < MI; ++i) {
+    accb[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  const uint4 one_bits{0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u};   // BF16 1.0 x 8
+  const bf16x8 ones = __builtin_bit_cast(bf16x8, one_bits);
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (d < ns) load(d, fa[d], fb[d]);
+  for (int i0 = 0; i0 < ns; i0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int i = i0 + d;
+      if (i < ns) {
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi) {
+          const bf16x8 av = __builtin_bit_cast(bf16x8, fa[d][mi]);
+#pragma unroll
+          for (int ni = 0; ni < NI; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, fb[d][ni]),
+                                                                  acc[mi][ni], 0, 0, 0);
+          if (with_bias) accb[mi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones, accb[mi], 0, 0, 0);
+        }
+        if (i + D < ns) load(i + D, fa[d], fb[d]);
+      }
+    }
+  }
+  // wavefronts 3, 2, 1 hand their partial tiles to wavefront 0 in turn
+  for (int w = 3; w >= 1; --w) {
+    if (wave == w) {
+#pragma unroll
+      for (int mi = 0; mi < MI; ++mi) {
+#pragma unroll
+        for (int ni = 0; ni < NI; ++ni) red[mi * NI + ni][lane] = acc[mi][ni];
+        red[MI * NI + mi][lane] = accb[mi];
+      }
+    }
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+      for (int mi = 0; mi < MI; ++mi) {
+#pragma unroll
+        for (int ni = 0; ni < NI; ++ni) acc[mi][ni] += red[mi * NI + ni][lane];
+        accb[mi] += red[MI * NI + mi][lane];
+      }
+    }
+    __syncthreads();
+  }
+  if (wave != 0) return;
+  float* out = args.parts + (long)blockIdx.x * args.n_params;
+  const int col = lane & 15, rb = (lane >> 4) * 4;
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi) {
+#pragma unroll
+    for (int ni = 0; ni < NI; ++ni)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int gm = m0 + mi * 16 + rb + t, gn = n0 + ni * 16 + col;
+        if (gm < L.N && gn < L.K) out[L.w_off + (long)gm * L.K + gn] = acc[mi][ni][t];
+      }
+    if (with_bias && col == 0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int gm = m0 + mi * 16 + rb + t;
+        if (gm < L.N) out[L.b_off + gm] = accb[mi][t];
+      }
+    }
+  }
+}
+
+// Sums the ranges' partial gradients of every parameter in a fixed order
+// and updates it (update_param); thread 0 also hands out the step's loss
+// and clears the accumulator for the next step.
+__global__ void train_update_kernel(const float* __restrict__ parts, int n_parts, long n_params,
+                                    UpdateArgs u) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
-    if (loss_out) *loss_out = *loss;
-    *loss = 0.0f;
+    if (u.loss_out) *u.loss_out = *u.loss;
+    *u.loss = 0.0f;
   }
   if (i >= n_params) return;
   float gi = 0.0f;
   for (int z = 0; z < n_parts; ++z) gi += parts[(long)z * n_params + i];
-  if (mode == 0) {
-    grad[i] = gi;
-    return;
-  }
-  const float a = b1 * m1[i] + (1.0f - b1) * gi;
-  const float v = b2 * m2[i] + (1.0f - b2) * gi * gi;
-  m1[i] = a;
-  m2[i] = v;
-  const float nw = w[i] - lr * (a / c1) / (sqrtf(v / c2) + eps);
-  w[i] = nw;
-  const uint16_t hb = to_bf16(nw);
-  wb[i] = hb;
-  long fwd, bwd, bias;
-  map.locate(i, fwd, bwd, bias);
-  if (fwd >= 0) wf[fwd] = hb;
-  if (bwd >= 0) wbt[bwd] = hb;
-  if (bias >= 0) bias_f[bias] = nw;
+  update_param(u, i, gi);
 }
 
 }  // namespace cprrtc
@@ -964,11 +1258,11 @@ struct cp_mlp {
   uint16_t* wbt = nullptr;
   long n_wbt = 0;
   long tr_rows = 0;
-  uint16_t* t_xb = nullptr;   // [rows][32]
-  float* t_z = nullptr;       // [n_hidden][rows][H]
-  uint16_t* t_a = nullptr;    // [n_hidden][rows][H]
-  uint16_t* t_dy = nullptr;   // [rows][16]
-  uint16_t* t_dz = nullptr;   // [n_hidden][rows][H]
+  uint16_t* t_xt = nullptr;   // [32][rows]
+  uint16_t* t_d = nullptr;    // SiLU' of the pre-activations, [n_hidden][rows][H]
+  uint16_t* t_at = nullptr;   // [n_hidden][H][rows]
+  uint16_t* t_dyt = nullptr;  // [16][rows]
+  uint16_t* t_dzt = nullptr;  // [n_hidden][H][rows]
   float* t_parts = nullptr;   // [kTrainParts][n_params]
 };
 
@@ -1140,46 +1434,45 @@ hipError_t refresh_fused(cp_mlp* n, hipStream_t st) {
   return hipGetLastError();
 }
 
-constexpr int kTrainParts = 32;   // batch ranges of the weight-gradient launch
+constexpr int kTrainParts = 8;    // batch ranges of the weight-gradient launch (one per XCD)
 
-// samples per wavefront in the training kernels: one tile of 16 from width
-// 256 up (twice the workgroups of the inference shape at small batches)
-template <int H>
-constexpr int train_st() { return H >= 256 ? 1 : 256 / H; }
+
+// Row stride of the transposed training buffers: M rounded up to 32 (the
+// weight-gradient steps, which also covers the workgroups' 16-sample
+// blocks), plus 64 samples so that consecutive rows start 128 bytes apart
+// modulo a power of two and spread over the memory channels.
+long train_ld(long M) { return (M + 31) / 32 * 32 + 64; }
 
 void free_train(cp_mlp* n) {
-  for (void* p : {(void*)n->t_xb, (void*)n->t_z, (void*)n->t_a, (void*)n->t_dy, (void*)n->t_dz})
+  for (void* p : {(void*)n->t_xt, (void*)n->t_d, (void*)n->t_at, (void*)n->t_dyt, (void*)n->t_dzt})
     if (p) (void)hipFree(p);
-  n->t_xb = n->t_a = n->t_dy = n->t_dz = nullptr;
-  n->t_z = nullptr;
+  n->t_xt = n->t_d = n->t_at = n->t_dyt = n->t_dzt = nullptr;
   n->tr_rows = 0;
 }
 
 hipError_t ensure_train(cp_mlp* n, long M) {
   hipError_t e = hipSuccess;
   if (!n->t_parts) e = hipMalloc((void**)&n->t_parts, sizeof(float) * kTrainParts * n->n_params);
-  if (e != hipSuccess || M <= n->tr_rows) return e;
+
+  if (e != hipSuccess || train_ld(M) <= n->tr_rows) return e;
   free_train(n);
-  const long r = std::max(M, 256L), H = n->hidden, L = n->n_hidden;
-  e = hipMalloc((void**)&n->t_xb, sizeof(uint16_t) * r * 32);
-  if (e == hipSuccess) e = hipMalloc((void**)&n->t_z, sizeof(float) * L * r * H);
-  if (e == hipSuccess) e = hipMalloc((void**)&n->t_a, sizeof(uint16_t) * L * r * H);
-  if (e == hipSuccess) e = hipMalloc((void**)&n->t_dy, sizeof(uint16_t) * r * 16);
-  if (e == hipSuccess) e = hipMalloc((void**)&n->t_dz, sizeof(uint16_t) * L * r * H);
+  const long r = train_ld(std::max(M, 256L)), H = n->hidden, L = n->n_hidden;
+  e = hipMalloc((void**)&n->t_xt, sizeof(uint16_t) * r * 32);
+  if (e == hipSuccess) e = hipMalloc((void**)&n->t_d, sizeof(uint16_t) * L * r * H);
+  if (e == hipSuccess) e = hipMalloc((void**)&n->t_at, sizeof(uint16_t) * L * r * H);
+  if (e == hipSuccess) e = hipMalloc((void**)&n->t_dyt, sizeof(uint16_t) * r * 16);
+  if (e == hipSuccess) e = hipMalloc((void**)&n->t_dzt, sizeof(uint16_t) * L * r * H);
   if (e == hipSuccess) n->tr_rows = r;
   return e;
 }
 
 template <int H>
 void launch_train_h(const cp_mlp* n, long M, const float* x, const TrainIO& tr, hipStream_t st) {
-  constexpr int ST = train_st<H>();
-  const long per = (long)kFusedWaves * 16 * ST;
-  const unsigned blocks = (unsigned)((M + per - 1) / per);
+  using S = TrainShape<H>;
+  const unsigned blocks = (unsigned)((M + S::SB - 1) / S::SB);
   FusedNet net{n->wf, n->bias_f, n->n_in, n->n_out, n->n_hidden};
-  mlp_fused_kernel<H, ST, kFusedWaves, FeatRows, true><<<blocks, kFusedWaves * 64, 0, st>>>(
-      net, FeatRows{x, n->n_in}, M, nullptr, 0, tr);
-  mlp_bwd_fused_kernel<H, ST, kFusedWaves><<<blocks, kFusedWaves * 64, 0, st>>>(
-      n->wbt, n->n_hidden, M, tr, n->t_dz);
+  mlp_train_fwd_kernel<H><<<blocks, S::NW * 64, 0, st>>>(net, FeatRows{x, n->n_in}, M, tr);
+  mlp_train_bwd_kernel<H><<<blocks, S::NW * 64, 0, st>>>(n->wbt, n->n_hidden, M, tr, n->t_dzt);
 }
 
 // One training step (mode 1: Adam with learning rate lr and bias corrections
@@ -1191,48 +1484,75 @@ hipError_t fused_train(cp_mlp* n, long M, const float* x, const float* t, int mo
   hipError_t e = ensure_train(n, M);
   if (e != hipSuccess) return e;
   const int H = n->hidden, L = n->n_hidden;
-  TrainIO tr{t, n->t_xb, n->t_z, n->t_a, n->t_dy, n->loss, 1.0f / ((float)M * (float)n->n_out)};
+  const long ldt = train_ld(M);
+  TrainIO tr{t, n->t_xt, n->t_d, n->t_at, n->t_dyt, n->loss, 1.0f / ((float)M * (float)n->n_out), ldt};
   switch (H) {
     case 64: launch_train_h<64>(n, M, x, tr, st); break;
     case 128: launch_train_h<128>(n, M, x, tr, st); break;
     case 256: launch_train_h<256>(n, M, x, tr, st); break;
     default: launch_train_h<512>(n, M, x, tr, st); break;
   }
-  // weight and bias gradients of every layer, in kTrainParts batch ranges
+  // weight and bias gradients of every layer, in batch ranges
   DwArgs da;
   std::memset(&da, 0, sizeof da);
-  const int ks = (int)(((M + kTrainParts - 1) / kTrainParts + kBK - 1) / kBK * kBK);
+  // eight batch ranges, one per XCD
+  const int ks = (int)(((M + 7) / 8 + kBK - 1) / kBK * kBK);
   const int parts = (int)((M + ks - 1) / ks);
   da.M = M;
+  da.ld = ldt;
   da.ks = ks;
   da.n_params = n->n_params;
   da.parts = n->t_parts;
+  // 32 x 32 tiles (more workgroups, four steps in flight) for batches of a
+  // few thousand samples, 64 x 64 above
+  const bool small = M <= 8192;
+  const int MI = small ? 2 : 4, NI = MI, TM = 16 * MI, TN = 16 * NI;
   int max_tiles = 0;
   for (int l = 0; l < n->n_layers; ++l) {
     DwLayer& D = da.L[l];
+    const bool last = l + 1 == n->n_layers;
     D.N = n->out_dim[l];
     D.K = n->in_dim[l];
+    D.NA = last ? 16 : H;
+    D.KB = l == 0 ? 32 : H;
     D.w_off = n->w_off[l];
     D.b_off = n->b_off[l];
-    D.A = l + 1 < n->n_layers ? Mat{n->t_dz + (long)l * M * H, 1, (long)H} : Mat{n->t_dy, 1, 16};
-    D.B = l == 0 ? Mat{n->t_xb, 32, 1} : Mat{n->t_a + (long)(l - 1) * M * H, (long)H, 1};
-    max_tiles = std::max(max_tiles, ((D.N + kBM - 1) / kBM) * ((D.K + kBN - 1) / kBN) + 1);
+    D.A = last ? n->t_dyt : n->t_dzt + (long)l * H * ldt;
+    D.B = l == 0 ? n->t_xt : n->t_at + (long)(l - 1) * H * ldt;
+    max_tiles = std::max(max_tiles, ((D.N + TM - 1) / TM) * ((D.K + TN - 1) / TN));
   }
-  dw_kernel<<<dim3(max_tiles, n->n_layers, parts), 256, 0, st>>>(da);
-  FusedMap map;
-  std::memset(&map, 0, sizeof map);
-  map.n_layers = n->n_layers;
-  map.H = H;
-  map.n_in = n->n_in;
-  map.n_out = n->n_out;
-  map.n_hidden = L;
+  UpdateArgs u;
+  std::memset(&u, 0, sizeof u);
+  u.mode = mode;
+  u.grad = d_grad;
+  u.w = n->w;
+  u.m1 = n->m1;
+  u.m2 = n->m2;
+  u.wb = n->wb;
+  u.wf = n->wf;
+  u.wbt = n->wbt;
+  u.bias_f = n->bias_f;
+  u.map.n_layers = n->n_layers;
+  u.map.H = H;
+  u.map.n_in = n->n_in;
+  u.map.n_out = n->n_out;
+  u.map.n_hidden = L;
   for (int l = 0; l < n->n_layers; ++l) {
-    map.w_off[l] = n->w_off[l];
-    map.b_off[l] = n->b_off[l];
+    u.map.w_off[l] = n->w_off[l];
+    u.map.b_off[l] = n->b_off[l];
   }
-  train_update_kernel<<<nblk(n->n_params), 256, 0, st>>>(
-      mode, n->t_parts, parts, n->n_params, d_grad, n->w, n->m1, n->m2, n->wb, n->wf, n->wbt,
-      n->bias_f, map, lr, 0.9f, 0.999f, 1e-8f, c1, c2, n->loss, d_loss);
+  u.lr = lr;
+  u.b1 = 0.9f;
+  u.b2 = 0.999f;
+  u.eps = 1e-8f;
+  u.c1 = c1;
+  u.c2 = c2;
+  u.loss = n->loss;
+  u.loss_out = d_loss;
+  const dim3 grid(parts, max_tiles, n->n_layers);
+  if (small) dw_kernel<2, 2, 4><<<grid, 256, 0, st>>>(da);
+  else dw_kernel<4, 4, 2><<<grid, 256, 0, st>>>(da);
+  train_update_kernel<<<nblk(n->n_params), 256, 0, st>>>(n->t_parts, parts, n->n_params, u);
   return hipGetLastError();
 }
 
