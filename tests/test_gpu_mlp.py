@@ -75,7 +75,7 @@ def test_forward_matches_reference(G, dims_hidden):
 
 
 @pytest.mark.parametrize("dims_hidden,M", [((13, 256, 3, 7), 96), ((26, 512, 3, 14), 300),
-                                           ((5, 64, 2, 3), 1000)])
+                                           ((5, 64, 2, 3), 1000), ((13, 256, 3, 7), 9000)])
 def test_gradients_match_fp64_oracle(G, dims_hidden, M):
     n_in, hid, nh, n_out = dims_hidden
     net = G.MLP(n_in, hid, nh, n_out, seed=4)
