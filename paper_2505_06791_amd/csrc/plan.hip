@@ -315,8 +315,12 @@ __global__ void publish_batch_kernel(ProblemDev* probs, int n_probs, unsigned* r
   if (i == 0) *round += 1u;
 }
 
+// Roots of both trees and a fresh control block per query; done_init[i] = 1
+// marks a query with nothing to search (endpoint check failed, or start and
+// goal already connected at the roots).
 __global__ void plan_batch_init_kernel(ProblemDev* probs, int n_probs, const float* __restrict__ ends,
-                                       const int* __restrict__ ends_off) {
+                                       const int* __restrict__ ends_off,
+                                       const int* __restrict__ done_init) {
   const int i = blockIdx.x;
   if (i >= n_probs) return;
   const PlanDev& pd = probs[i].pd;
@@ -326,8 +330,56 @@ __global__ void plan_batch_init_kernel(ProblemDev* probs, int n_probs, const flo
     for (int j = 0; j < dof; ++j) pd.q[t][(size_t)j * pd.cap] = ends[ends_off[i] + t * dof + j];
     pd.parent[t][0] = -1;
   }
-  if (t < kCtlInts) pd.ctl[t] = (t == kCtlCount || t == kCtlCount + 1 || t == kCtlPublished ||
-                                  t == kCtlPublished + 1) ? 1 : 0;
+  if (t < kCtlInts)
+    pd.ctl[t] = (t == kCtlCount || t == kCtlCount + 1 || t == kCtlPublished || t == kCtlPublished + 1)
+                    ? 1
+                    : (t == kCtlDone ? done_init[i] : 0);
+}
+
+// Endpoint checks of every query of a batch in one launch, one wavefront
+// per query: lane 0 takes the start, lane 1 the goal; ok[2i + lane] = task
+// error below tol (no projection step), sd[2i + lane] = minimum signed
+// distance of the robot's spheres to the query's scene.  The queries run
+// side by side; each lane's collision check walks the whole scene.
+__global__ __launch_bounds__(64) void batch_ends_kernel(const ProblemDev* __restrict__ probs,
+                                                        int n_probs, const float* __restrict__ ends,
+                                                        const int* __restrict__ ends_off, float tol,
+                                                        int* __restrict__ ok, float* __restrict__ sd) {
+  const int i = blockIdx.x;
+  if (i >= n_probs) return;
+  const ProblemDev& P = probs[i];
+  const int lane = threadIdx.x;
+  const bool on = lane < 2;
+  const float* q = ends + ends_off[i] + (on ? lane : 0) * P.dof;
+  float einf = 0.0f;
+#define CP_ENDS_CASE(ND, K)                                       \
+  case ND * 4 + K: {                                              \
+    float qa[ND], g[ND];                                          \
+    for (int j = 0; j < ND; ++j) qa[j] = q[j];                    \
+    task_step<ND, K>(P.rob, P.con, qa, 0.0f, g, einf);            \
+    break;                                                        \
+  }
+  switch (P.dof * 4 + P.con.kind) {
+    CP_ENDS_CASE(6, KIND_NONE)
+    CP_ENDS_CASE(6, KIND_POSE)
+    CP_ENDS_CASE(7, KIND_NONE)
+    CP_ENDS_CASE(7, KIND_POSE)
+    CP_ENDS_CASE(9, KIND_NONE)
+    CP_ENDS_CASE(9, KIND_POSE)
+    CP_ENDS_CASE(14, KIND_POSE)
+    CP_ENDS_CASE(14, KIND_REL)
+    default: einf = FLT_MAX; break;
+  }
+#undef CP_ENDS_CASE
+  uint64_t hits;
+  float msd;
+  CcWork cw;
+  cc_work_clear(cw);
+  collide_config<4, true, false, false>(P.rob, P.sph, P.env, q, on, 0ull, false, hits, msd, cw);
+  if (on) {
+    ok[2 * i + lane] = einf < tol ? 1 : 0;
+    sd[2 * i + lane] = msd;
+  }
 }
 
 // Path assembly for many queries: item = (query, tree, node, mode, offset).
@@ -881,10 +933,9 @@ struct cp_batch {
   int* host_ctl = nullptr;     // pinned [Q][kCtlInts]
   float* ends = nullptr;       // [Q][2][max_dof] endpoint scratch
   int* ends_off = nullptr;     // [Q]
-  float* cfg_out = nullptr;
-  int* cfg_status = nullptr;   // [2Q]
-  uint8_t* cfg_col = nullptr;  // [2Q]
-  float* cfg_sd = nullptr;     // [2Q]
+  int* cfg_status = nullptr;   // [2Q] endpoint on the manifold
+  float* cfg_sd = nullptr;     // [2Q] endpoint's minimum signed distance
+  int* done_init = nullptr;    // [Q] nothing to search
   hipStream_t stream = nullptr;
   // learned warm start (cp_batch_set_warm): the network and its round buffers
   const cp_mlp* warm = nullptr;
@@ -900,7 +951,7 @@ void free_batch(cp_batch* b) {
   if (!b) return;
   for (void* p : {(void*)b->q, (void*)b->parent, (void*)b->edge, (void*)b->scratch, (void*)b->ctl,
                   (void*)b->round, (void*)b->queue, (void*)b->probs, (void*)b->ends, (void*)b->ends_off,
-                  (void*)b->cfg_out, (void*)b->cfg_status, (void*)b->cfg_col, (void*)b->cfg_sd,
+                  (void*)b->cfg_status, (void*)b->cfg_sd, (void*)b->done_init,
                   (void*)b->seg_from, (void*)b->seg_to, (void*)b->seg_near, (void*)b->delta})
     if (p) (void)hipFree(p);
   if (b->host_ctl) (void)hipHostFree(b->host_ctl);
@@ -952,10 +1003,9 @@ int cp_batch_create(const cp_batch_opts* opts, int32_t max_queries, int32_t max_
     if (e == hipSuccess) e = hipHostMalloc((void**)&b->host_ctl, sizeof(int) * Q * kCtlInts, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void**)&b->ends, sizeof(float) * Q * 2 * D);
     if (e == hipSuccess) e = hipMalloc((void**)&b->ends_off, sizeof(int) * Q);
-    if (e == hipSuccess) e = hipMalloc((void**)&b->cfg_out, sizeof(float) * Q * 2 * D);
     if (e == hipSuccess) e = hipMalloc((void**)&b->cfg_status, sizeof(int) * Q * 2);
-    if (e == hipSuccess) e = hipMalloc((void**)&b->cfg_col, Q * 2);
     if (e == hipSuccess) e = hipMalloc((void**)&b->cfg_sd, sizeof(float) * Q * 2);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->done_init, sizeof(int) * Q);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
       free_batch(b);
@@ -1092,16 +1142,13 @@ int cp_plan_batch(cp_batch* b, int32_t n, const cp_query* queries, cp_path* path
     }
     he = hipMemcpyAsync(b->ends, ends.data(), sizeof(float) * ends.size(), hipMemcpyHostToDevice, st);
     if (he == hipSuccess) he = hipMemcpyAsync(b->ends_off, ends_off.data(), sizeof(int) * n, hipMemcpyHostToDevice, st);
-    // endpoints on the manifold and collision-free (device checks per query)
-    for (int i = 0; i < n && he == hipSuccess; ++i) {
-      const cp_query& qq = queries[i];
-      bool sup = false;
-      he = launch_project_configs(probs[i].dof, qq.robot->dev, probs[i].con, 2, b->ends + (size_t)i * 2 * D,
-                                  b->cfg_out + (size_t)i * 2 * D, b->cfg_status + 2 * i,
-                                  (float)pp.tau_task, 0, 1.0f, 0.0f, st, &sup);
-      if (he == hipSuccess)
-        he = launch_fk_cc(qq.robot->dev, qq.robot->spheres, qq.env->view, 2, b->ends + (size_t)i * 2 * D,
-                          b->cfg_col + 2 * i, b->cfg_sd + 2 * i, false, 4, st);
+    // endpoints on the manifold and collision-free: every query's two
+    // checks in one launch (the problem records go up first)
+    if (he == hipSuccess) he = hipMemcpyAsync(b->probs, probs.data(), sizeof(ProblemDev) * n, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) {
+      batch_ends_kernel<<<n, 64, 0, st>>>(b->probs, n, b->ends, b->ends_off, (float)pp.tau_task,
+                                          b->cfg_status, b->cfg_sd);
+      he = hipGetLastError();
     }
     std::vector<int> ok_h(2 * n);
     std::vector<float> sd_h(2 * n);
@@ -1115,21 +1162,20 @@ int cp_plan_batch(cp_batch* b, int32_t n, const cp_query* queries, cp_path* path
       if (status[i] == CP_OK && !(ok_h[2 * i + 1] && sd_h[2 * i + 1] > 0.0f)) status[i] = CP_E_GOAL;
       active[i] = status[i] == CP_OK;
     }
-    // problems whose endpoints fail are given a zero group budget by marking them done
-    he = hipMemcpyAsync(b->probs, probs.data(), sizeof(ProblemDev) * n, hipMemcpyHostToDevice, st);
-    if (he == hipSuccess) {
-      plan_batch_init_kernel<<<n, 64, 0, st>>>(b->probs, n, b->ends, b->ends_off);
-      he = hipGetLastError();
-    }
-    for (int i = 0; i < n && he == hipSuccess; ++i) {
+    // problems whose endpoints fail, or whose start and goal already
+    // connect, are marked done at once (zero group budget, connection at
+    // the roots)
+    std::vector<int> done_init(n, 0);
+    for (int i = 0; i < n; ++i) {
       double dsg = 0.0;
       for (int j = 0; j < probs[i].dof; ++j) dsg += (queries[i].start[j] - queries[i].goal[j]) * (queries[i].start[j] - queries[i].goal[j]);
       const bool trivial = active[i] && std::sqrt(dsg) < tol;
-      if (!active[i] || trivial) {   // nothing to search: done flag set, connection at the roots
-        const int done_block[4] = {1, 0, 0, 0};
-        he = hipMemcpyAsync(b->ctl + (size_t)i * kCtlInts + kCtlDone, done_block, sizeof done_block, hipMemcpyHostToDevice, st);
-        if (he == hipSuccess) he = hipStreamSynchronize(st);
-      }
+      done_init[i] = (!active[i] || trivial) ? 1 : 0;
+    }
+    he = hipMemcpyAsync(b->done_init, done_init.data(), sizeof(int) * n, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) {
+      plan_batch_init_kernel<<<n, 64, 0, st>>>(b->probs, n, b->ends, b->ends_off, b->done_init);
+      he = hipGetLastError();
     }
     const unsigned zero = 0, zeros[2] = {0, 0};
     if (he == hipSuccess) he = hipMemcpyAsync(b->round, &zero, sizeof zero, hipMemcpyHostToDevice, st);
