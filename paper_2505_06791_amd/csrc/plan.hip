@@ -208,7 +208,7 @@ static bool launch_batch_round(int dof, int kind, int batch, unsigned nb, hipStr
 // with a pose or relative-pose constraint.  queue[0]: next task,
 // queue[1]: wavefronts finished (both zero when a round starts).
 template <int SET, int B>
-__global__ __launch_bounds__(kPlanBlock) void plan_batch_queue_kernel(
+__global__ __launch_bounds__(kPlanBlock, SET == 0 ? 2 : 1) void plan_batch_queue_kernel(
     ProblemDev* __restrict__ probs, int n_probs, int groups, ProjDev prm,
     unsigned* __restrict__ round, unsigned* __restrict__ queue, unsigned n_waves) {
   const int lane = threadIdx.x & 63;
