@@ -409,6 +409,61 @@ done:
   msd_out = msd;
 }
 
+// Minimum signed distance of one configuration (the same q in every lane
+// of the wavefront) to the scene, the lanes splitting the primitives: lane l
+// takes primitives l, l + 64, ... in type order against every sphere.  The
+// minimum runs over the same pairs and pair values as collide_config's exact
+// form, so it is the same number; a query's endpoints are checked this way
+// instead of one lane walking the whole scene.  Every lane gets the result.
+template <int B, class P = RobotMem>
+__device__ float config_min_sd(const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
+                               const EnvDev& env, const float* q) {
+  const int lane = threadIdx.x & 63;
+  const int b1 = env.n_aabb, b2 = b1 + env.n_obb, b3 = b2 + env.n_sph, b4 = b3 + env.n_cap;
+  const int n = b4 + env.n_cyl;
+  float msd = FLT_MAX;
+  uint64_t unused = 0;
+  const int nch = P::n_chains(rob);
+  for (int c = 0; c < nch; ++c) {
+    Frame T;
+    frame_from_p<P>(T, rob, c, false);
+    const int j1 = P::chain_begin(rob, c + 1);
+    for (int j = P::chain_begin(rob, c); j < j1; ++j) {
+      joint_advance<P>(T, rob, j, q[j]);
+      const int s1 = P::sph_begin(rob, j + 1);
+      for (int s = P::sph_begin(rob, j); s < s1; s += B) {
+        float cx[B], cy[B], cz[B], rr[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+          const float4 l = P::sphere(sph, min(s + b, s1 - 1));
+          cx[b] = T.r[0] * l.x + T.r[1] * l.y + T.r[2] * l.z + T.p[0];
+          cy[b] = T.r[3] * l.x + T.r[4] * l.y + T.r[5] * l.z + T.p[1];
+          cz[b] = T.r[6] * l.x + T.r[7] * l.y + T.r[8] * l.z + T.p[2];
+          rr[b] = l.w;
+        }
+        for (int p = lane; p < n; p += 64) {
+          if (p < b1) {
+            test_aabb<B, true>(env.aabb[2 * p], env.aabb[2 * p + 1], cx, cy, cz, rr, unused, msd);
+          } else if (p < b2) {
+            const int k = p - b1;
+            test_obb<B, true>(env.obb[4 * k], env.obb[4 * k + 1], env.obb[4 * k + 2], env.obb[4 * k + 3],
+                              cx, cy, cz, rr, unused, msd);
+          } else if (p < b3) {
+            test_sphere<B, true>(env.sph[p - b2], cx, cy, cz, rr, unused, msd);
+          } else if (p < b4) {
+            const int k = p - b3;
+            test_capsule<B, true>(env.cap[2 * k], env.cap[2 * k + 1], cx, cy, cz, rr, unused, msd);
+          } else {
+            const int k = p - b4;
+            test_cylinder<B, true>(env.cyl[2 * k], env.cyl[2 * k + 1], cx, cy, cz, rr, unused, msd);
+          }
+        }
+      }
+    }
+  }
+  return wave_min(msd);
+}
+
 // Validation of projected segments, thread gid of the launch: waypoints
 // 1..W-1 of every motion whose projection succeeded (status 0) run FK + CC,
 // one waypoint per lane; the motion leaves at the first batch in which any

@@ -9,6 +9,11 @@ namespace cprrtc {
 
 bool dof_supported(int dof);
 
+// Scene check of n_cfg configurations, one wavefront each with its lanes
+// splitting the primitives: collide[i] = min_sd[i] <= 0, min_sd[i] as
+// fk_cc's exact form (for a query's few endpoints).
+hipError_t launch_config_sd(const RobotDev* rob, const float4* sph, const EnvDev& env, int n_cfg,
+                            const float* q, uint8_t* collide, float* min_sd, hipStream_t stream);
 hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& env, int n_cfg,
                         const float* q, uint8_t* collide, float* min_sd, bool early, int batch,
                         hipStream_t stream);

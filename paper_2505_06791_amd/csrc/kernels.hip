@@ -52,6 +52,24 @@ __global__ __launch_bounds__(kBlock) void fk_cc_kernel(const RobotDev* __restric
   }
 }
 
+// Scene check of a few configurations (a query's endpoints), one wavefront
+// each, its lanes splitting the primitives (config_min_sd); same outputs as
+// fk_cc_kernel<B, true> with every batch evaluated.
+template <int B>
+__global__ __launch_bounds__(64) void config_sd_kernel(const RobotDev* __restrict__ rob,
+                                                       const float4* __restrict__ sph, EnvDev env,
+                                                       int n_cfg, const float* __restrict__ q,
+                                                       uint8_t* __restrict__ collide,
+                                                       float* __restrict__ min_sd) {
+  const int i = blockIdx.x;
+  if (i >= n_cfg) return;
+  const float sd = config_min_sd<B>(rob, sph, env, q + (int64_t)i * rob->dof);
+  if (threadIdx.x == 0) {
+    collide[i] = sd <= 0.0f ? 1 : 0;
+    min_sd[i] = sd;
+  }
+}
+
 // ------------------------------------------------------------------ sphere centres
 
 // One thread per (configuration, sphere): the chain's frames up to the
@@ -371,6 +389,13 @@ __global__ __launch_bounds__(kBlock) void project_configs_kernel(
 // ------------------------------------------------------------------ launchers
 
 static unsigned blocks_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+hipError_t launch_config_sd(const RobotDev* rob, const float4* sph, const EnvDev& env, int n_cfg,
+                            const float* q, uint8_t* collide, float* min_sd, hipStream_t stream) {
+  if (n_cfg <= 0) return hipSuccess;
+  config_sd_kernel<4><<<n_cfg, 64, 0, stream>>>(rob, sph, env, n_cfg, q, collide, min_sd);
+  return hipGetLastError();
+}
 
 hipError_t launch_fk_cc(const RobotDev* rob, const float4* sph, const EnvDev& env, int n_cfg,
                         const float* q, uint8_t* collide, float* min_sd, bool early, int batch,

@@ -337,10 +337,10 @@ __global__ void plan_batch_init_kernel(ProblemDev* probs, int n_probs, const flo
 }
 
 // Endpoint checks of every query of a batch in one launch, one wavefront
-// per query: lane 0 takes the start, lane 1 the goal; ok[2i + lane] = task
-// error below tol (no projection step), sd[2i + lane] = minimum signed
-// distance of the robot's spheres to the query's scene.  The queries run
-// side by side; each lane's collision check walks the whole scene.
+// per query: lane 0 takes the start, lane 1 the goal for the task error
+// (ok[2i + e] = error below tol, no projection step); the minimum signed
+// distance of the robot's spheres to the query's scene (sd[2i + e]) comes
+// from all lanes splitting the primitives (config_min_sd), start then goal.
 __global__ __launch_bounds__(64) void batch_ends_kernel(const ProblemDev* __restrict__ probs,
                                                         int n_probs, const float* __restrict__ ends,
                                                         const int* __restrict__ ends_off, float tol,
@@ -371,14 +371,10 @@ __global__ __launch_bounds__(64) void batch_ends_kernel(const ProblemDev* __rest
     default: einf = FLT_MAX; break;
   }
 #undef CP_ENDS_CASE
-  uint64_t hits;
-  float msd;
-  CcWork cw;
-  cc_work_clear(cw);
-  collide_config<4, true, false, false>(P.rob, P.sph, P.env, q, on, 0ull, false, hits, msd, cw);
-  if (on) {
-    ok[2 * i + lane] = einf < tol ? 1 : 0;
-    sd[2 * i + lane] = msd;
+  if (on) ok[2 * i + lane] = einf < tol ? 1 : 0;
+  for (int e = 0; e < 2; ++e) {
+    const float d = config_min_sd<4>(P.rob, P.sph, P.env, ends + ends_off[i] + e * P.dof);
+    if (lane == 0) sd[2 * i + e] = d;
   }
 }
 
@@ -700,7 +696,7 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
     bool sup = false;
     he = launch_project_configs(n, robot->dev, con, 2, pl->cfg, pl->cfg_out, pl->cfg_status,
                                 (float)pp.tau_task, 0, 1.0f, 0.0f, st, &sup);
-    if (he == hipSuccess) he = launch_fk_cc(robot->dev, robot->spheres, env->view, 2, pl->cfg, pl->cfg_col, pl->cfg_sd, false, 4, st);
+    if (he == hipSuccess) he = launch_config_sd(robot->dev, robot->spheres, env->view, 2, pl->cfg, pl->cfg_col, pl->cfg_sd, st);
     // with the self-check on, an endpoint must also be clear of the robot itself
     const int n_self = (int)robot->self_pairs.size() / 2;
     if (he == hipSuccess && (o.flags & CP_SELF_COLLISION) && n_self > 0)

@@ -136,3 +136,36 @@ def test_batch_rejects_bad_arguments(G):
     assert ex.value.code == G.CP_E_ARG
     status, paths, stats = bp.plan([])
     assert len(status) == 0
+
+
+def test_batch_endpoint_scene_checks_match_fk_cc(G):
+    """A batch's endpoint scene check (one wavefront per query, its lanes
+    splitting the primitives) evaluates the same pairs as fk_cc_batch's
+    exact form: on a scene of all five primitive types (180; about half of
+    the random configurations collide), with no task constraint, a start is
+    refused (CP_E_START) exactly when fk_cc_batch
+    gives it a minimum signed distance <= 0, outside a 1e-5 m band; the goal
+    is free in every query."""
+    rd = I.make_arm(2300, 7, 60)
+    env_d = I.make_mixed(2301, 150, cube_side=3.0)
+    env_d["aabb"] = I.make_boxes(2303, 30, cube_side=3.0)["aabb"]   # all five types
+    robot, env, con = G.Robot(rd), G.Env(env_d), G.constraint(I.no_constraint())
+    q = torch.from_numpy(I.random_configs(rd, 512, 2302).astype(np.float32)).to("cuda:0")
+    col = torch.empty(512, dtype=torch.uint8, device="cuda:0")
+    sd = torch.empty(512, dtype=torch.float32, device="cuda:0")
+    G.fk_cc_batch(robot, env, q, col, sd)
+    sd_h = sd.cpu().numpy()
+    qs_h = q.cpu().numpy().astype(np.float64)
+    free = np.nonzero(sd_h > 1e-3)[0]
+    hit = np.nonzero(sd_h <= 0.0)[0]
+    assert len(free) > 40 and len(hit) > 20, (len(free), len(hit))
+    goal = qs_h[free[0]]
+    starts = np.concatenate([free[1:33], hit[:32]])
+    qs = [(robot, env, con, qs_h[i], goal, 7000 + k) for k, i in enumerate(starts)]
+    bp = G.BatchPlanner(len(qs), 7, G.batch_opts(groups_per_query=4, max_rounds=4, capacity=1024))
+    status, _, _ = bp.plan(qs)
+    refused = status == G.CP_E_START
+    expect = sd_h[starts] <= 0.0
+    in_band = np.abs(sd_h[starts]) < 1e-5
+    assert np.array_equal(refused[~in_band], expect[~in_band]), (refused.astype(int), expect.astype(int))
+    assert not np.any(status == G.CP_E_GOAL)
