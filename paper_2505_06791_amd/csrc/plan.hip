@@ -95,29 +95,51 @@ __global__ void publish_kernel(int* ctl, int cap) {
   }
 }
 
-// Path assembly.  Item i = (tree, node, mode, offset): mode 0 copies points
-// 1..W-1 of the node's edge, mode 1 copies points W-2..0 (the edge walked
-// backwards), mode 2 copies the node's own configuration (one point).
-__global__ void gather_path_kernel(PlanDev pd, const int* __restrict__ items, int n_items, int W,
-                                   int dof, float* __restrict__ out) {
-  const int i = blockIdx.x;
-  if (i >= n_items) return;
-  const int tree = items[4 * i + 0], node = items[4 * i + 1], mode = items[4 * i + 2],
-            off = items[4 * i + 3];
-  if (mode == 2) {
-    for (int j = threadIdx.x; j < dof; j += blockDim.x)
-      out[(size_t)off * dof + j] = pd.q[tree][(size_t)j * pd.cap + node];
-    return;
+// The path of a connected planner, assembled on the device: thread 0 walks
+// both trees' parent links from the connection (tree-0 chain n0 -> root into
+// items[0..], tree-1 chain n1 -> root into items[cap..]) and writes
+// hdr = {path rows, chain lengths}; then the block copies, into out (rows
+// of dof floats), the tree-0 edges from the root to n0 (points 1..W-1 of
+// each), n1's configuration, and the tree-1 edges from n1 back to its root
+// (each reversed, points W-2..0).  Rows 0 and len-1 are the caller's own
+// end points and are left to the host.  Nothing is copied when the path
+// would not fit max_rows.
+__global__ void path_walk_kernel(PlanDev pd, int n0, int n1, int W, int dof, int* __restrict__ items,
+                                 int* __restrict__ hdr, float* __restrict__ out, long max_rows) {
+  __shared__ int c0s, c1s;
+  if (threadIdx.x == 0) {
+    int c0 = 0, c1 = 0;
+    for (int v = n0; v > 0 && c0 < pd.cap; v = pd.parent[0][v]) items[c0++] = v;
+    for (int v = n1; v > 0 && c1 < pd.cap; v = pd.parent[1][v]) items[pd.cap + c1++] = v;
+    c0s = c0;
+    c1s = c1;
+    hdr[0] = 1 + c0 * (W - 1) + 1 + c1 * (W - 1);
+    hdr[1] = c0;
+    hdr[2] = c1;
   }
-  const float* e = pd.edge[tree] + (size_t)node * W * dof;
-  for (int t = threadIdx.x; t < (W - 1) * dof; t += blockDim.x) {
-    const int p = t / dof, j = t % dof;
-    const int src = mode == 1 ? (W - 2 - p) : (p + 1);
-    out[(size_t)(off + p) * dof + j] = e[(size_t)src * dof + j];
+  __syncthreads();
+  const int c0 = c0s, c1 = c1s, seg = (W - 1) * dof;
+  if ((long)1 + (long)(c0 + c1) * (W - 1) + 1 > max_rows) return;
+  // tree-0 edges, root first
+  for (long t = threadIdx.x; t < (long)c0 * seg; t += blockDim.x) {
+    const int k = (int)(t / seg), r = (int)(t % seg), p = r / dof, j = r % dof;
+    const int node = items[c0 - 1 - k];
+    out[(size_t)(1 + k * (W - 1) + p) * dof + j] = pd.edge[0][((size_t)node * W + p + 1) * dof + j];
+  }
+  const int mid = 1 + c0 * (W - 1);
+  for (int j = threadIdx.x; j < dof; j += blockDim.x) out[(size_t)mid * dof + j] = pd.q[1][(size_t)j * pd.cap + n1];
+  // tree-1 edges from n1 back to the root, each reversed
+  for (long t = threadIdx.x; t < (long)c1 * seg; t += blockDim.x) {
+    const int k = (int)(t / seg), r = (int)(t % seg), p = r / dof, j = r % dof;
+    const int node = items[pd.cap + k];
+    out[(size_t)(mid + 1 + k * (W - 1) + p) * dof + j] = pd.edge[1][((size_t)node * W + W - 2 - p) * dof + j];
   }
 }
 
 // ------------------------------------------------------------------ batched planning
+
+constexpr int kHostIoFloats = 64;       // pinned staging of a planner (endpoints, checks, header)
+constexpr int kPathPrefixRows = 4096;   // path rows fetched with the header
 
 // One planning query of a batch: its robot, scene, constraint and trees.
 struct ProblemDev {
@@ -509,10 +531,15 @@ struct cp_planner {
   float* edge[2] = {nullptr, nullptr};
   float* scratch = nullptr;
   int* ctl = nullptr;
-  int* items = nullptr;       // device list for gather_path_kernel
+  int* items = nullptr;       // device chain lists of path_walk_kernel
   float* path_buf = nullptr;  // device path buffer
   int* host_ctl = nullptr;    // pinned mirror of the control block
   size_t path_cap = 0;        // points that fit in path_buf / items
+  int* path_hdr = nullptr;    // device {path rows, chain lengths} (path_walk_kernel)
+  // pinned staging: endpoints out, check results and path header back, the
+  // first kPathPrefixRows rows of the path back in the same synchronisation
+  float* host_io = nullptr;
+  float* host_path = nullptr;
   float* cfg = nullptr;       // [2][dof] start/goal scratch for checks
   float* cfg_out = nullptr;
   int* cfg_status = nullptr;
@@ -547,6 +574,9 @@ void free_planner(cp_planner* p) {
   if (p->items) (void)hipFree(p->items);
   if (p->path_buf) (void)hipFree(p->path_buf);
   if (p->host_ctl) (void)hipHostFree(p->host_ctl);
+  if (p->host_io) (void)hipHostFree(p->host_io);
+  if (p->host_path) (void)hipHostFree(p->host_path);
+  if (p->path_hdr) (void)hipFree(p->path_hdr);
   if (p->cfg) (void)hipFree(p->cfg);
   if (p->cfg_out) (void)hipFree(p->cfg_out);
   if (p->cfg_status) (void)hipFree(p->cfg_status);
@@ -612,6 +642,10 @@ int cp_planner_create(const cp_robot* robot, const cp_plan_opts* opts, cp_planne
     if (e == hipSuccess) e = hipMalloc((void**)&pl->items, sizeof(int) * 4 * 2 * cap);
     if (e == hipSuccess) e = hipMalloc((void**)&pl->path_buf, sizeof(float) * pl->path_cap * n);
     if (e == hipSuccess) e = hipHostMalloc((void**)&pl->host_ctl, sizeof(int) * kCtlInts, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&pl->host_io, sizeof(float) * kHostIoFloats, hipHostMallocDefault);
+    if (e == hipSuccess)
+      e = hipHostMalloc((void**)&pl->host_path, sizeof(float) * kPathPrefixRows * n, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&pl->path_hdr, sizeof(int) * 4);
     if (e == hipSuccess) e = hipMalloc((void**)&pl->cfg, sizeof(float) * 2 * n);
     if (e == hipSuccess) e = hipMalloc((void**)&pl->cfg_out, sizeof(float) * 2 * n);
     if (e == hipSuccess) e = hipMalloc((void**)&pl->cfg_status, sizeof(int) * 2);
@@ -686,12 +720,14 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
         if (!(c[j] >= robot->host.lo[j] && c[j] <= robot->host.hi[j]))
           return api_fail(e == 0 ? CP_E_START : CP_E_GOAL, "%s outside the joint limits", e == 0 ? "start" : "goal");
     }
-    std::vector<float> ends(2 * n);
+    // pinned staging: [0, 2n) the endpoints, [2n, 2n + 2) the checks'
+    // statuses (int bits), [2n + 2, 2n + 4) their distances
+    float* io = pl->host_io;
     for (int j = 0; j < n; ++j) {
-      ends[j] = (float)start[j];
-      ends[n + j] = (float)goal[j];
+      io[j] = (float)start[j];
+      io[n + j] = (float)goal[j];
     }
-    hipError_t he = hipMemcpyAsync(pl->cfg, ends.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice, st);
+    hipError_t he = hipMemcpyAsync(pl->cfg, io, sizeof(float) * 2 * n, hipMemcpyHostToDevice, st);
     if (he != hipSuccess) return api_hip_fail(he, "cp_plan");
     bool sup = false;
     he = launch_project_configs(n, robot->dev, con, 2, pl->cfg, pl->cfg_out, pl->cfg_status,
@@ -702,10 +738,10 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
     if (he == hipSuccess && (o.flags & CP_SELF_COLLISION) && n_self > 0)
       he = launch_self_cc(robot->dev, robot->host, robot->spheres, robot->pairs_cc, n_self, 2,
                           pl->cfg, pl->cfg_col, pl->cfg_sd, false, st);
-    int ok_h[2];
-    float sd_h[2];
-    if (he == hipSuccess) he = hipMemcpyAsync(ok_h, pl->cfg_status, sizeof ok_h, hipMemcpyDeviceToHost, st);
-    if (he == hipSuccess) he = hipMemcpyAsync(sd_h, pl->cfg_sd, sizeof sd_h, hipMemcpyDeviceToHost, st);
+    int* ok_h = reinterpret_cast<int*>(io + 2 * n);
+    float* sd_h = io + 2 * n + 2;
+    if (he == hipSuccess) he = hipMemcpyAsync(ok_h, pl->cfg_status, sizeof(int) * 2, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(sd_h, pl->cfg_sd, sizeof(float) * 2, hipMemcpyDeviceToHost, st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
     if (he != hipSuccess) return api_hip_fail(he, "cp_plan endpoint checks");
     if (!sup) return api_fail(CP_E_UNSUPPORTED, "no kernel for dof %d with constraint kind %d", n, con.kind);
@@ -738,11 +774,9 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
     pd.n_groups = o.n_groups;
     pd.max_connect = o.max_connect;
     pd.step = (float)((W - 1) * pp.tau);
-    he = hipMemcpyAsync(pl->cfg, ends.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice, st);
-    if (he == hipSuccess) {
-      plan_init_kernel<<<1, 64, 0, st>>>(pd, pl->cfg, n);
-      he = hipGetLastError();
-    }
+    // (pl->cfg still holds the endpoints)
+    plan_init_kernel<<<1, 64, 0, st>>>(pd, pl->cfg, n);
+    he = hipGetLastError();
     if (he != hipSuccess) return api_hip_fail(he, "cp_plan init");
     pd.connect2 = (float)(tol * tol);
     uint64_t state = seed;
@@ -811,48 +845,34 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
       return CP_NO_SOLUTION;
     }
 
-    // path: tree-0 chain root -> n0, bridge to n1, tree-1 chain n1 -> root
+    // path: tree-0 chain root -> n0, bridge to n1, tree-1 chain n1 -> root,
+    // assembled on the device; its header and first rows come back in one
+    // synchronisation
     const int X = hc[kCtlConn + 0], a = hc[kCtlConn + 1], b = hc[kCtlConn + 2];
     const int n0 = X == 0 ? a : b, n1 = X == 0 ? b : a;
-    std::vector<int> par[2];
-    for (int t = 0; t < 2; ++t) {
-      const int cnt = std::min(hc[kCtlCount + t], o.capacity);
-      par[t].resize(cnt);
-      he = hipMemcpy(par[t].data(), pl->parent[t], sizeof(int) * cnt, hipMemcpyDeviceToHost);
-      if (he != hipSuccess) return api_hip_fail(he, "cp_plan path");
-    }
-    std::vector<int> chain0, chain1;
-    for (int v = n0; v > 0; v = par[0][v]) chain0.push_back(v);
-    std::reverse(chain0.begin(), chain0.end());
-    for (int v = n1; v > 0; v = par[1][v]) chain1.push_back(v);
-    const size_t len = 1 + chain0.size() * (W - 1) + 1 + chain1.size() * (W - 1);
-    out->len = (int32_t)len;
-    if ((size_t)out->capacity < len) return api_fail(CP_E_CAPACITY, "path needs %zu rows", len);
-    std::vector<int> items;
-    int off = 1;
-    for (int v : chain0) {
-      items.insert(items.end(), {0, v, 0, off});
-      off += W - 1;
-    }
-    items.insert(items.end(), {1, n1, 2, off});
-    off += 1;
-    for (int v : chain1) {
-      items.insert(items.end(), {1, v, 1, off});
-      off += W - 1;
-    }
-    const int n_items = (int)items.size() / 4;
-    std::vector<float> pts(len * n);
-    he = hipMemcpyAsync(pl->items, items.data(), sizeof(int) * items.size(), hipMemcpyHostToDevice, st);
-    if (he == hipSuccess) {
-      gather_path_kernel<<<n_items, 64, 0, st>>>(pd, pl->items, n_items, W, n, pl->path_buf);
-      he = hipGetLastError();
-    }
+    path_walk_kernel<<<1, 256, 0, st>>>(pd, n0, n1, W, n, pl->items, pl->path_hdr, pl->path_buf,
+                                        (long)pl->path_cap);
+    he = hipGetLastError();
+    int* hdr = reinterpret_cast<int*>(io + kHostIoFloats - 4);
+    const size_t pre = std::min((size_t)kPathPrefixRows, pl->path_cap);
+    if (he == hipSuccess) he = hipMemcpyAsync(hdr, pl->path_hdr, sizeof(int) * 4, hipMemcpyDeviceToHost, st);
     if (he == hipSuccess)
-      he = hipMemcpyAsync(pts.data(), pl->path_buf, sizeof(float) * len * n, hipMemcpyDeviceToHost, st);
+      he = hipMemcpyAsync(pl->host_path, pl->path_buf, sizeof(float) * pre * n, hipMemcpyDeviceToHost, st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
     if (he != hipSuccess) return api_hip_fail(he, "cp_plan path");
-    for (size_t i = 1; i + 1 < len; ++i)
-      for (int j = 0; j < n; ++j) out->q[i * n + j] = (double)pts[i * n + j];
+    const size_t len = (size_t)hdr[0];
+    out->len = (int32_t)len;
+    if ((size_t)out->capacity < len) return api_fail(CP_E_CAPACITY, "path needs %zu rows", len);
+    for (size_t i = 1; i + 1 < std::min(len, pre); ++i)
+      for (int j = 0; j < n; ++j) out->q[i * n + j] = (double)pl->host_path[i * n + j];
+    if (len > pre) {   // the rest of a long path
+      std::vector<float> rest((len - pre) * n);
+      he = hipMemcpyAsync(rest.data(), pl->path_buf + pre * n, sizeof(float) * rest.size(), hipMemcpyDeviceToHost, st);
+      if (he == hipSuccess) he = hipStreamSynchronize(st);
+      if (he != hipSuccess) return api_hip_fail(he, "cp_plan path");
+      for (size_t i = pre; i + 1 < len; ++i)
+        for (int j = 0; j < n; ++j) out->q[i * n + j] = (double)rest[(i - pre) * n + j];
+    }
     // the end points are the caller's own values
     std::memcpy(out->q, start, sizeof(double) * n);
     std::memcpy(out->q + (len - 1) * n, goal, sizeof(double) * n);
