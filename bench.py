@@ -89,18 +89,18 @@ TRAFFIC = [
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h",
                     "paper_2505_06791_amd/csrc/kernels.hip", "paper_2505_06791_amd/csrc/kernels.h"),
-        "sources_sha256": "416c3f3f4a40f0dd090a1766ff5a15f9385800993eb5b8190530edec45396a43",
-        "fetch_kib": 5290.3, "fetch_scale": 262144.0 / 131086.6,
-        "write_kib": 115974.8, "write_scale": 1.0,
+        "sources_sha256": "34619569645ab8a6e49d12a9a11f62a4dd4c40c758f068a56a56ae9ba50eabb2",
+        "fetch_kib": 5291.8, "fetch_scale": 262144.0 / 131086.6,
+        "write_kib": 115975.7, "write_scale": 1.0,
     },
     {
         "kernel": "cp_rtc_pool<7, 1> (hipRTC)",
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h", "paper_2505_06791_amd/csrc/rtc.hip",
                     "paper_2505_06791_amd/csrc/kernels.h", "include/cprrtc.h"),
-        "sources_sha256": "bf43a567e582c68872150ca5c27482e12164232810d04736624231ca0c2a2371",
-        "fetch_kib": 5206.1, "fetch_scale": 262144.0 / 131086.6,
-        "write_kib": 116176.8, "write_scale": 1.0,
+        "sources_sha256": "c6b1c8b3fce564f3ba296058b7970eab6baca98c357841c93d8702d049bdcd95",
+        "fetch_kib": 5206.5, "fetch_scale": 262144.0 / 131086.6,
+        "write_kib": 116178.1, "write_scale": 1.0,
     },
 ]
 
