@@ -1510,8 +1510,9 @@ hipError_t fused_train(cp_mlp* n, long M, const float* x, const float* t, int mo
   da.ks = ks;
   da.n_params = n->n_params;
   da.parts = n->t_parts;
-  // 32 x 32 tiles (more workgroups, four steps in flight) for batches of a
-  // few thousand samples, 64 x 64 above
+  // 32 x 32 tiles (more workgroups, two steps in flight; measured against
+  // four steps, 64 x 64 and 32 x 64 tiles and 4 or 16 ranges) for batches of
+  // a few thousand samples, 64 x 64 above
   const bool small = M <= 8192;
   const int MI = small ? 2 : 4, NI = MI, TM = 16 * MI, TN = 16 * NI;
   int max_tiles = 0;
@@ -1557,7 +1558,7 @@ hipError_t fused_train(cp_mlp* n, long M, const float* x, const float* t, int mo
   u.loss = n->loss;
   u.loss_out = d_loss;
   const dim3 grid(parts, max_tiles, n->n_layers);
-  if (small) dw_kernel<2, 2, 4><<<grid, 256, 0, st>>>(da);
+  if (small) dw_kernel<2, 2, 2><<<grid, 256, 0, st>>>(da);
   else dw_kernel<4, 4, 2><<<grid, 256, 0, st>>>(da);
   train_update_kernel<<<nblk(n->n_params), 256, 0, st>>>(n->t_parts, parts, n->n_params, u);
   return hipGetLastError();
