@@ -13,7 +13,13 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZE=1: a separate build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (the process must preload the sanitizer
+# runtimes; tests/test_oracle_sanitized.py runs the oracle's pins that way)
+SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
+LIB_PATH = os.path.join(_HERE, "liboracle_san.so" if SANITIZE else "liboracle.so")
+SANITIZE_FLAGS = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                  "-fno-sanitize-recover=undefined"]
 
 MOTION_VALID, MOTION_PROJ_FAIL, MOTION_COLLISION = 0, 1, 2
 
@@ -55,7 +61,8 @@ def build(force: bool = False) -> str:
     """Compile oracle.c with gcc (OpenMP over independent items only)."""
     src = os.path.join(_HERE, "oracle.c")
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-o", LIB_PATH,
+        opt = SANITIZE_FLAGS if SANITIZE else ["-O2"]
+        subprocess.check_call(["gcc", *opt, "-fPIC", "-shared", "-fopenmp", "-o", LIB_PATH,
                                src, "-lm"], cwd=_HERE)
     return LIB_PATH
 
