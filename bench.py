@@ -98,9 +98,9 @@ TRAFFIC = [
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h", "paper_2505_06791_amd/csrc/rtc.hip",
                     "paper_2505_06791_amd/csrc/kernels.h", "include/cprrtc.h"),
-        "sources_sha256": "c6b1c8b3fce564f3ba296058b7970eab6baca98c357841c93d8702d049bdcd95",
-        "fetch_kib": 5206.5, "fetch_scale": 262144.0 / 131086.6,
-        "write_kib": 116178.1, "write_scale": 1.0,
+        "sources_sha256": "749de2629c3cae98773e704ac6a9eb0969d5061d44a40aafee8dcaed4aad91d4",
+        "fetch_kib": 5206.4, "fetch_scale": 262144.0 / 131086.6,
+        "write_kib": 116186.9, "write_scale": 1.0,
     },
 ]
 
@@ -157,7 +157,19 @@ def parse():
                          "round budget (0 = skip)")
     ap.add_argument("--batch-queries", type=int, default=512,
                     help="uneven queries planned in one batch and one by one (0 = skip)")
+    ap.add_argument("--query-log", default="",
+                    help="write one JSON line per planning query of the plan legs to this file")
     return ap.parse_args()
+
+
+# per-query records of the planning legs (--query-log): one JSON object a line
+QUERY_LOG = None
+
+
+def log_query(**rec):
+    if QUERY_LOG is not None:
+        QUERY_LOG.write(json.dumps(rec) + "\n")
+        QUERY_LOG.flush()
 
 
 def gpu_query(G, I, torch, w, seed, robot=None):
@@ -216,6 +228,11 @@ def plan_bench(G, I, torch, name, seeds, tau_task, variant=0, fixed=None, max_ro
         n += 1
         ok += rc == G.CP_OK
         solved.append(rc == G.CP_OK)
+        log_query(leg="plan", scene=name, seed=seed, variant=variant,
+                  robot="fixed" if fixed is not None else "per seed", tau_task=tau_task,
+                  ms=times[-1], status=int(rc), solved=bool(rc == G.CP_OK), rounds=int(st["rounds"]),
+                  nodes=[int(v) for v in st.get("nodes", (0, 0))],
+                  path_rows=int(len(path)) if rc == G.CP_OK else 0)
         if rc != G.CP_OK and unsolved is not None:
             unsolved.append(seed)
         rounds.append(st["rounds"])
@@ -312,6 +329,10 @@ def batch_bench(G, I, torch, n, base=3000, make=None, max_dof=9, rounds=800, tau
     t0 = time.perf_counter()
     st_b, _, info = bp.plan(queries)
     batch_ms = (time.perf_counter() - t0) * 1e3
+    for (_, _, _, _, _, s), st, inf in zip(queries, st_b, info):
+        log_query(leg="batch", seed=s, tau_task=tau_task, status=int(st), solved=bool(st == G.CP_OK),
+                  rounds=int(inf["rounds"]), nodes=[int(v) for v in inf["nodes"]],
+                  batch_ms=batch_ms)
     print(f"batch: batched {batch_ms:.0f} ms, {(st_b == G.CP_OK).sum()} solved",
           file=sys.stderr, flush=True)
     del bp
@@ -781,7 +802,7 @@ def host_threads():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build",
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -791,6 +812,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    global QUERY_LOG
+    if args.query_log:
+        QUERY_LOG = open(args.query_log, "w")
     dev = torch.device("cuda:0")
     if args.copy_mb > 0:
         n = args.copy_mb * (1 << 20) // 4

@@ -282,6 +282,16 @@ int cp_mlp_gradients(cp_mlp* mlp, int64_t M, const float* d_x, const float* d_t,
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the mean squared error. */
 int cp_mlp_train_step(cp_mlp* mlp, int64_t M, const float* d_x, const float* d_t, float lr,
                       float* d_loss, void* stream);
+/* Adam state, for checkpoints: the first and second moment estimates
+ * (d_m1, d_m2: [num_params] float32 device, the parameter order above) and
+ * the number of steps taken (which sets the bias corrections of the next
+ * step).  get copies them out (step: host pointer, nullable), set copies
+ * them in; with cp_mlp_get_params / cp_mlp_set_params they restore a run
+ * exactly (the training kernels sum in a fixed order).  Asynchronous on
+ * `stream`.  Errors: CP_E_ARG (NULL handle or moment buffer, step < 0),
+ * CP_E_HIP. */
+int cp_mlp_get_state(const cp_mlp* mlp, float* d_m1, float* d_m2, int64_t* step, void* stream);
+int cp_mlp_set_state(cp_mlp* mlp, const float* d_m1, const float* d_m2, int64_t step, void* stream);
 
 /* project_motions with a learned warm start: every waypoint k >= 1 starts at
  * clamp(straight line + net(features)), features = (waypoint / joint range,

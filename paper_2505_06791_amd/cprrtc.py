@@ -155,6 +155,8 @@ def lib():
         L.cp_mlp_forward.argtypes = [vp, C.c_int64, vp, vp, vp]
         L.cp_mlp_gradients.argtypes = [vp, C.c_int64, vp, vp, vp, vp, vp]
         L.cp_mlp_train_step.argtypes = [vp, C.c_int64, vp, vp, C.c_float, vp, vp]
+        L.cp_mlp_get_state.argtypes = [vp, vp, vp, C.POINTER(C.c_int64), vp]
+        L.cp_mlp_set_state.argtypes = [vp, vp, vp, C.c_int64, vp]
         L.project_motions_warm.argtypes = [vp, C.POINTER(Constraint), C.POINTER(ProjParams), vp,
                                            C.c_int32, vp, vp, vp, vp, vp, vp, C.c_int32, vp]
         L.project_motions_warm_noalloc.argtypes = L.project_motions_warm.argtypes
@@ -558,6 +560,61 @@ class MLP:
                                        _dev(t, torch.float32), C.c_float(lr),
                                        _dev(loss, torch.float32) if loss is not None else None,
                                        _stream()))
+
+    def get_state(self):
+        """Adam state: (m1, m2 device tensors, step count)."""
+        import torch
+        m1 = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        m2 = torch.empty_like(m1)
+        step = C.c_int64()
+        _check(lib().cp_mlp_get_state(self.handle, _dev(m1, torch.float32), _dev(m2, torch.float32),
+                                      C.byref(step), _stream()))
+        return m1, m2, int(step.value)
+
+    def set_state(self, m1, m2, step: int):
+        import torch
+        _check(lib().cp_mlp_set_state(self.handle, _dev(m1, torch.float32), _dev(m2, torch.float32),
+                                      int(step), _stream()))
+
+    # Checkpoint: <path>.json (shape, step, layout) and <path>.bin (parameters,
+    # then the two Adam moment vectors, float32 little-endian), read back with
+    # json and numpy.fromfile only.
+    CHECKPOINT_FORMAT = "cprrtc-mlp-1"
+
+    def save(self, path: str):
+        import json
+        import torch
+        p = self.get_params()
+        m1, m2, step = self.get_state()
+        torch.cuda.synchronize()
+        blob = torch.cat([p, m1, m2]).cpu().numpy().astype("<f4")
+        blob.tofile(path + ".bin")
+        with open(path + ".json", "w") as f:
+            json.dump(dict(format=self.CHECKPOINT_FORMAT, n_in=self.n_in, hidden=self.hidden,
+                           n_hidden=self.n_hidden, n_out=self.n_out, n_params=self.n_params,
+                           step=step, dtype="float32-le", arrays=["params", "adam_m1", "adam_m2"]),
+                      f, indent=1)
+
+    @classmethod
+    def load(cls, path: str) -> "MLP":
+        import json
+        import torch
+        with open(path + ".json") as f:
+            h = json.load(f)
+        if h.get("format") != cls.CHECKPOINT_FORMAT:
+            raise ValueError(f"{path}.json: not a {cls.CHECKPOINT_FORMAT} checkpoint")
+        net = cls(h["n_in"], h["hidden"], h["n_hidden"], h["n_out"])
+        n = net.n_params
+        if n != h["n_params"]:
+            raise ValueError(f"{path}.json: {h['n_params']} parameters, the shape has {n}")
+        blob = np.fromfile(path + ".bin", dtype="<f4")
+        if blob.size != 3 * n:
+            raise ValueError(f"{path}.bin: {blob.size} values, expected {3 * n}")
+        t = torch.from_numpy(blob.astype(np.float32)).to("cuda")
+        net.set_params(t[:n].contiguous())
+        net.set_state(t[n:2 * n].contiguous(), t[2 * n:].contiguous(), int(h["step"]))
+        torch.cuda.synchronize()
+        return net
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

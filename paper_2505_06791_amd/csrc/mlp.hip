@@ -1910,6 +1910,24 @@ int cp_mlp_set_params(cp_mlp* n, const float* d_in, void* stream) {
   return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_mlp_set_params");
 }
 
+int cp_mlp_get_state(const cp_mlp* n, float* d_m1, float* d_m2, int64_t* step, void* stream) {
+  if (!n || !d_m1 || !d_m2) return api_fail(CP_E_ARG, "cp_mlp_get_state: NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(d_m1, n->m1, sizeof(float) * n->n_params, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_m2, n->m2, sizeof(float) * n->n_params, hipMemcpyDeviceToDevice, st);
+  if (step) *step = n->step;
+  return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_mlp_get_state");
+}
+
+int cp_mlp_set_state(cp_mlp* n, const float* d_m1, const float* d_m2, int64_t step, void* stream) {
+  if (!n || !d_m1 || !d_m2 || step < 0) return api_fail(CP_E_ARG, "cp_mlp_set_state: bad argument");
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(n->m1, d_m1, sizeof(float) * n->n_params, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(n->m2, d_m2, sizeof(float) * n->n_params, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) n->step = step;
+  return e == hipSuccess ? CP_OK : api_hip_fail(e, "cp_mlp_set_state");
+}
+
 int cp_mlp_forward(cp_mlp* n, int64_t M, const float* d_x, float* d_y, void* stream) {
   try {
     if (!n) return api_fail(CP_E_ARG, "cp_mlp_forward: NULL handle");

@@ -224,3 +224,29 @@ def test_warm_pairs_match_reference(G, name, seed):
     t_ref = xi[:, 1:, :].reshape(-1, dof) - straight
     assert torch.allclose(x, x_ref, rtol=0, atol=2e-6), (x - x_ref).abs().max().item()
     assert torch.allclose(t, t_ref, rtol=0, atol=2e-6), (t - t_ref).abs().max().item()
+
+
+def test_checkpoint_resumes_exactly(G, tmp_path):
+    """MLP.save / MLP.load (parameters and Adam state through the C ABI,
+    a JSON header and a float32 file): a run resumed from the checkpoint
+    takes bit-identical steps (the training kernels sum in a fixed order)."""
+    net = G.MLP(13, 256, 3, 7, seed=11)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(3)
+    xs = [torch.randn((4096, 13), generator=g, device=DEV) for _ in range(6)]
+    ts = [torch.randn((4096, 7), generator=g, device=DEV) * 0.3 for _ in range(6)]
+    for i in range(3):
+        net.train_step(xs[i], ts[i], 1e-3)
+    path = str(tmp_path / "net")
+    net.save(path)
+    net2 = G.MLP.load(path)
+    for i in range(3, 6):
+        net.train_step(xs[i], ts[i], 1e-3)
+        net2.train_step(xs[i], ts[i], 1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(net.get_params(), net2.get_params())
+    m1a, m2a, sa = net.get_state()
+    m1b, m2b, sb = net2.get_state()
+    assert sa == sb == 6
+    assert torch.equal(m1a, m1b) and torch.equal(m2a, m2b)
+    assert torch.equal(net.forward(xs[0]), net2.forward(xs[0]))
