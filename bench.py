@@ -98,9 +98,9 @@ TRAFFIC = [
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h", "paper_2505_06791_amd/csrc/rtc.hip",
                     "paper_2505_06791_amd/csrc/kernels.h", "include/cprrtc.h"),
-        "sources_sha256": "749de2629c3cae98773e704ac6a9eb0969d5061d44a40aafee8dcaed4aad91d4",
-        "fetch_kib": 5206.4, "fetch_scale": 262144.0 / 131086.6,
-        "write_kib": 116186.9, "write_scale": 1.0,
+        "sources_sha256": "382717b393ef5d64656bedf00f98f0849561b36dd3523d1ce47adf974d91f37d",
+        "fetch_kib": 5218.2, "fetch_scale": 262144.0 / 131086.6,
+        "write_kib": 116229.7, "write_scale": 1.0,
     },
 ]
 

@@ -12,12 +12,19 @@
 #include <hip/hiprtc.h>
 
 #include <algorithm>
+#include <cerrno>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <iterator>
 #include <string>
 #include <vector>
+
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include "cprrtc.h"
 #include "device.h"
@@ -237,6 +244,79 @@ void rtc_release(cp_robot* robot) {
   robot->rtc.clear();
 }
 
+// Compiled code objects are kept on disk, keyed by a hash of everything the
+// compilation sees (the generated source, the library's device headers, the
+// options and the target), so a later process skips the compiler.  The
+// directory is $CPRRTC_RTC_CACHE (the value 0 turns the cache off), else
+// $XDG_CACHE_HOME/cprrtc, else $HOME/.cache/cprrtc; a missing or unusable
+// directory, or an unreadable entry, just means compiling.
+uint64_t fnv1a(uint64_t h, const char* p, size_t n) {
+  for (size_t i = 0; i < n; ++i) {
+    h ^= (unsigned char)p[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+std::string cache_dir() {
+  const char* e = std::getenv("CPRRTC_RTC_CACHE");
+  if (e) return std::string(e) == "0" ? std::string() : std::string(e);
+  const char* x = std::getenv("XDG_CACHE_HOME");
+  if (x && *x) return std::string(x) + "/cprrtc";
+  const char* h = std::getenv("HOME");
+  return h && *h ? std::string(h) + "/.cache/cprrtc" : std::string();
+}
+
+// mkdir -p of an absolute or relative directory; false if it is not usable
+bool make_dirs(const std::string& d) {
+  if (d.empty()) return false;
+  for (size_t i = 1; i <= d.size(); ++i) {
+    if (i == d.size() || d[i] == '/') {
+      const std::string part = d.substr(0, i);
+      if (mkdir(part.c_str(), 0755) != 0 && errno != EEXIST) return false;
+    }
+  }
+  return access(d.c_str(), W_OK) == 0;
+}
+
+std::string cache_key(const std::string& src, const char* const* opts, int n_opts) {
+  uint64_t a = 0xcbf29ce484222325ull, b = 0x84222325cbf29ce4ull;
+  auto add = [&](const char* p, size_t n) {
+    a = fnv1a(a, p, n);
+    b = fnv1a(b ^ n, p, n);
+  };
+  add(src.data(), src.size());
+  for (int i = 0; i < kRtcHeaderCount; ++i) {
+    add(kRtcHeaderNames[i], std::strlen(kRtcHeaderNames[i]));
+    add(kRtcHeaders[i], std::strlen(kRtcHeaders[i]));
+  }
+  for (int i = 0; i < n_opts; ++i) add(opts[i], std::strlen(opts[i]));
+  char k[40];
+  std::snprintf(k, sizeof k, "%016llx%016llx", (unsigned long long)a, (unsigned long long)b);
+  return k;
+}
+
+std::vector<char> cache_read(const std::string& path) {
+  std::ifstream f(path, std::ios::binary);
+  if (!f) return {};
+  return std::vector<char>(std::istreambuf_iterator<char>(f), std::istreambuf_iterator<char>());
+}
+
+void cache_write(const std::string& dir, const std::string& path, const std::vector<char>& code) {
+  if (!make_dirs(dir)) return;
+  const std::string tmp = path + ".tmp." + std::to_string((long)getpid());
+  {
+    std::ofstream f(tmp, std::ios::binary);
+    if (!f) return;
+    f.write(code.data(), (std::streamsize)code.size());
+    if (!f) {
+      std::remove(tmp.c_str());
+      return;
+    }
+  }
+  if (std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
+}
+
 }  // namespace cprrtc
 
 using namespace cprrtc;
@@ -278,11 +358,6 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
     const std::string src = kernel_source(robot->host, con.kind, mask_bits(con),
                                           reinterpret_cast<const float*>(sph.data()),
                                           robot->host.n_spheres, need_pool, need_plan);
-    hiprtcProgram prog = nullptr;
-    hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "cprrtc_rtc_pool.hip", kRtcHeaderCount,
-                                         kRtcHeaders, kRtcHeaderNames);
-    if (r != HIPRTC_SUCCESS)
-      return api_fail(CP_E_RTC, "hiprtcCreateProgram: %s", hiprtcGetErrorString(r));
     const std::string arch = std::string("--offload-arch=") + props.gcnArchName;
     // packed FP32 instructions stay out of every kernel, as in the library;
     // finite values without signed-zero distinctions let products with the
@@ -291,25 +366,38 @@ int cp_robot_specialize(cp_robot* robot, const cp_constraint* constraint, int32_
     const char* opts[] = {arch.c_str(), "-O3", "-std=c++17", "-Xclang", "-target-feature",
                           "-Xclang", "-packed-fp32-ops", "-fno-signed-zeros",
                           "-ffinite-math-only"};
-    r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
-    if (r != HIPRTC_SUCCESS) {
-      size_t n = 0;
-      hiprtcGetProgramLogSize(prog, &n);
-      std::string log(n, '\0');
-      if (n) hiprtcGetProgramLog(prog, &log[0]);
-      hiprtcDestroyProgram(&prog);
-      if (log.size() > 400) log.resize(400);
-      return api_fail(CP_E_RTC, "hiprtcCompileProgram: %s", log.c_str());
-    }
-    size_t size = 0;
-    hiprtcGetCodeSize(prog, &size);
-    std::vector<char> code(size);
-    hiprtcGetCode(prog, code.data());
-    hiprtcDestroyProgram(&prog);
+    const int n_opts = (int)(sizeof opts / sizeof opts[0]);
+    const std::string dir = cache_dir();
+    const std::string entry = dir.empty() ? std::string() : dir + "/" + cache_key(src, opts, n_opts) + ".co";
     hipModule_t module = nullptr;
+    std::vector<char> code = entry.empty() ? std::vector<char>() : cache_read(entry);
+    if (!code.empty() && hipModuleLoadData(&module, code.data()) != hipSuccess) module = nullptr;
+    if (!module) {
+      hiprtcProgram prog = nullptr;
+      hiprtcResult r = hiprtcCreateProgram(&prog, src.c_str(), "cprrtc_rtc_pool.hip", kRtcHeaderCount,
+                                           kRtcHeaders, kRtcHeaderNames);
+      if (r != HIPRTC_SUCCESS)
+        return api_fail(CP_E_RTC, "hiprtcCreateProgram: %s", hiprtcGetErrorString(r));
+      r = hiprtcCompileProgram(prog, n_opts, opts);
+      if (r != HIPRTC_SUCCESS) {
+        size_t n = 0;
+        hiprtcGetProgramLogSize(prog, &n);
+        std::string log(n, '\0');
+        if (n) hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        if (log.size() > 400) log.resize(400);
+        return api_fail(CP_E_RTC, "hiprtcCompileProgram: %s", log.c_str());
+      }
+      size_t size = 0;
+      hiprtcGetCodeSize(prog, &size);
+      code.assign(size, '\0');
+      hiprtcGetCode(prog, code.data());
+      hiprtcDestroyProgram(&prog);
+      he = hipModuleLoadData(&module, code.data());
+      if (he == hipSuccess && !entry.empty()) cache_write(dir, entry, code);
+    }
     hipFunction_t pool = nullptr, plan4 = nullptr, plan8 = nullptr, val4 = nullptr, val8 = nullptr,
                   val16 = nullptr;
-    he = hipModuleLoadData(&module, code.data());
     if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&pool, module, "cp_rtc_pool");
     if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&val4, module, "cp_rtc_validate4");
     if (he == hipSuccess && need_pool) he = hipModuleGetFunction(&val8, module, "cp_rtc_validate8");

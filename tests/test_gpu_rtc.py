@@ -250,3 +250,27 @@ def test_specialised_fk_cc_matches_oracle(G, name, n):
     for flags, col in out.items():
         assert np.array_equal(col[~band], col_o[~band].astype(bool)), flags
     assert np.array_equal(out[0], out[G.NO_EARLY_EXIT])
+
+
+def test_compiled_kernels_come_back_from_the_disk_cache(G, tmp_path, monkeypatch):
+    """A second robot handle with the same description and constraint mask
+    reads the code object the first one compiled from the disk cache
+    (CPRRTC_RTC_CACHE) instead of compiling, and its kernels give the same
+    bits."""
+    monkeypatch.setenv("CPRRTC_RTC_CACHE", str(tmp_path / "rtc"))
+    w = _workload("plain")
+    con, env = G.constraint(w["constraint"]), G.Env(w["env"])
+    r1 = G.Robot(w["robot"])
+    ms1 = r1.specialize(con)
+    assert len(list((tmp_path / "rtc").glob("*.co"))) == 1
+    r2 = G.Robot(w["robot"])
+    ms2 = r2.specialize(con)
+    assert len(list((tmp_path / "rtc").glob("*.co"))) == 1
+    print("compile ms", round(ms1, 1), "from the cache", round(ms2, 1), flush=True)
+    assert ms2 < 0.5 * ms1
+    q_from, q_to = motion_set(w, 48, 31)
+    kw = dict(W=64, tau_task=w["tau_task"])
+    a = _run(G, r1, env, con, w, q_from, q_to, kw, G.POOLED)
+    b = _run(G, r2, env, con, w, q_from, q_to, kw, G.POOLED)
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    assert np.array_equal(a[0], b[0], equal_nan=True)
