@@ -639,7 +639,7 @@ __device__ __forceinline__ long xcd_block(long i, long n) {
 
 template <int H, int ST_>
 struct TrainShape {
-  static constexpr int NW = H >= 256 ? 8 : H / 32;          // wavefronts per workgroup
+  static constexpr int NW = H >= 512 ? 16 : H >= 256 ? 8 : H / 32;   // wavefronts per workgroup
   static constexpr int T = H / (16 * NW);                    // unit tiles per wavefront
   static constexpr int KC = H / 32;                          // k-chunks of a hidden layer
   static constexpr int G = H >= 512 ? 4 : 2;                 // k-chunk groups per layer (even)
