@@ -417,6 +417,14 @@ def test_project_validate_edge_cases(G):
 
 
 def test_project_configs_matches_oracle(G):
+    """Single-configuration projection against the oracle config by config.
+    Where the FP64 iteration converges within 12 Newton steps the FP32 kernel
+    must converge too, and typically to the same point (median distance
+    1e-5 rad; the manifold is not a point, so a path that passes near a
+    singular Jacobian, where the damped step amplifies rounding, may end
+    elsewhere on it: at most 5% of these beyond 1e-3 rad).  Over all
+    configurations the statuses may differ on at most 5% (runs the oracle
+    needs more than 12 steps for)."""
     for name in ("plain", "cluttered", "dual"):
         w = I.workload(name, 77)
         robot, con = G.Robot(w["robot"]), G.constraint(w["constraint"])
@@ -428,17 +436,27 @@ def test_project_configs_matches_oracle(G):
         torch.cuda.synchronize()
         qo_h, st_h = qo.cpu().numpy(), st.cpu().numpy()
         ro, _, co = oracle_views(w)
-        n_ok = 0
         for q, s in zip(qo_h, st_h):
             if s:
-                n_ok += 1
                 e = O.task_error(ro, co, q.astype(np.float64))
                 assert np.abs(e).max() < 2e-5
                 assert np.all(q >= w["robot"]["lo"] - 1e-6) and np.all(q <= w["robot"]["hi"] + 1e-6)
-        ok_o = sum(O.project_config(ro, co, q.astype(np.float64), tol=1e-5, max_iters=100)[0]
-                   for q in q32)
-        _report("project_configs", workload=name, gpu_ok=n_ok, oracle_ok=ok_o)
-        assert n_ok >= 0.8 * ok_o
+        ref = [O.project_config(ro, co, q.astype(np.float64), tol=1e-5, max_iters=100) for q in q32]
+        ok_o = np.array([r[0] for r in ref])
+        it_o = np.array([r[2] for r in ref])
+        q_o = np.stack([r[1] for r in ref])
+        quick = ok_o & (it_o <= 12)
+        differ = (st_h != 0) != ok_o
+        dq = np.abs(qo_h - q_o).max(axis=1)
+        _report("project_configs", workload=name, gpu_ok=int((st_h != 0).sum()), oracle_ok=int(ok_o.sum()),
+                quick=int(quick.sum()), differ=int(differ.sum()),
+                differ_quick=int((differ & quick).sum()), dq_median=float(np.median(dq[quick])),
+                dq_p95=float(np.percentile(dq[quick], 95)), dq_max=float(dq[quick].max()))
+        assert quick.sum() >= 100
+        assert np.all(st_h[quick] != 0), np.nonzero(quick & (st_h == 0))[0]
+        assert np.median(dq[quick]) <= 1e-5
+        assert np.mean(dq[quick] > 1e-3) <= 0.05
+        assert differ.sum() <= 0.05 * len(q32)
 
 
 @pytest.mark.parametrize("name,M,sample", [("cluttered", 65536, 48)])
