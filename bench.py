@@ -420,6 +420,22 @@ def _time_ms(torch, fn, reps):
     return float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
 
+def _time_ms_stream(torch, fn, reps, warm=5):
+    """Mean time of `reps` back-to-back calls between one event pair (after
+    `warm` untimed calls): for launches of tens of microseconds, where an
+    event pair per call would add its own overhead to every launch."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
 BF16_MFMA_PEAK_TFLOPS = 2500.0     # MI355X dense BF16 matrix cores
 
 
@@ -437,11 +453,11 @@ def mlp_bench(G, torch, M=65536):
         dims = [n_in] + [hid] * nh + [n_out]
         kn = [dims[i] * dims[i + 1] for i in range(len(dims) - 1)]
         x = torch.randn((M, n_in), device=dev)
-        fwd_ms = _time_ms(torch, lambda: net.forward(x), 5)
+        fwd_ms = _time_ms_stream(torch, lambda: net.forward(x), 50)
         B = 4096
         xb, tb = x[:B].contiguous(), torch.randn((B, n_out), device=dev)
         loss = torch.zeros(1, device=dev)
-        train_ms = _time_ms(torch, lambda: net.train_step(xb, tb, 1e-4, loss), 10)
+        train_ms = _time_ms_stream(torch, lambda: net.train_step(xb, tb, 1e-4, loss), 50)
         fwd_flops = 2 * M * sum(kn)
         train_flops = 2 * B * (2 * sum(kn) + sum(kn[1:]))
         out[name] = dict(inference_samples=M, inference_ms=fwd_ms,
