@@ -89,18 +89,18 @@ TRAFFIC = [
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h",
                     "paper_2505_06791_amd/csrc/kernels.hip", "paper_2505_06791_amd/csrc/kernels.h"),
-        "sources_sha256": "34619569645ab8a6e49d12a9a11f62a4dd4c40c758f068a56a56ae9ba50eabb2",
-        "fetch_kib": 5291.8, "fetch_scale": 262144.0 / 131086.6,
-        "write_kib": 115975.7, "write_scale": 1.0,
+        "sources_sha256": "2822e5a878533e8ad3dcd7eb5a9d6c6aef1d343234511f30a62e0881c00fcf63",
+        "fetch_kib": 5290.2, "fetch_scale": 262144.0 / 131086.6,
+        "write_kib": 115974.4, "write_scale": 1.0,
     },
     {
         "kernel": "cp_rtc_pool<7, 1> (hipRTC)",
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h", "paper_2505_06791_amd/csrc/rtc.hip",
                     "paper_2505_06791_amd/csrc/kernels.h", "include/cprrtc.h"),
-        "sources_sha256": "382717b393ef5d64656bedf00f98f0849561b36dd3523d1ce47adf974d91f37d",
-        "fetch_kib": 5218.2, "fetch_scale": 262144.0 / 131086.6,
-        "write_kib": 116229.7, "write_scale": 1.0,
+        "sources_sha256": "aa4d33447e0144c46959c984c3e8412b222ee9b79ba39993fccf3626fc6492d1",
+        "fetch_kib": 5206.5, "fetch_scale": 262144.0 / 131086.6,
+        "write_kib": 116187.2, "write_scale": 1.0,
     },
 ]
 

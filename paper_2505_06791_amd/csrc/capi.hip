@@ -265,15 +265,19 @@ int cp_robot_create(const cp_robot_desc* d, cp_robot** out) {
     std::vector<int> rank(d->n_spheres);
     for (int s = 0; s < d->n_spheres; ++s) rank[order[s]] = s;
     const int n_pairs = (int)r->self_pairs.size() / 2;
-    // a multiple of kSelfPad, and one more group read ahead by the kernel
-    const int n_padded = (n_pairs + kSelfPad - 1) / kSelfPad * kSelfPad + kSelfPad;
-    std::vector<int2> dev_pairs(n_pairs), cc_pairs(n_padded);
-    {
-      const float never = -1.0f;   // d^2 <= -1 never holds
-      int bits;
-      std::memcpy(&bits, &never, sizeof bits);
-      for (int i = n_pairs; i < n_padded; ++i) cc_pairs[i] = make_int2(0, bits);
-    }
+    // The kernel's list: each checked pair filed under its first sphere s,
+    // a sphere's pairs in groups of kGroup records (the last group filled up
+    // with never-hitting records of the same s), group g at entries
+    // (g / 16) kSelfPad + g % 16 + 16 u, so the 16 lanes of a row take 16
+    // groups per loop trip and each reads its c_s once per group; then
+    // never-hitting records up to a multiple of kSelfPad, and kSelfPad more
+    // that the kernel reads ahead.
+    constexpr int kGroup = kSelfPad / 16;
+    const float never = -1.0f;   // d^2 <= -1 never holds
+    int never_bits;
+    std::memcpy(&never_bits, &never, sizeof never_bits);
+    std::vector<int2> dev_pairs(n_pairs);
+    std::vector<std::vector<int2>> by_s(d->n_spheres);
     for (int i = 0; i < n_pairs; ++i) {
       const int s0 = rank[r->self_pairs[2 * i]], t0 = rank[r->self_pairs[2 * i + 1]];
       dev_pairs[i] = make_int2(s0, t0);
@@ -281,8 +285,23 @@ int cp_robot_create(const cp_robot_desc* d, cp_robot** out) {
       const float reach2 = (float)(reach * reach);
       int bits;
       std::memcpy(&bits, &reach2, sizeof bits);
-      cc_pairs[i] = make_int2(s0 | (t0 << 16), bits);   // positions < kMaxSpheres <= 2^16
+      by_s[s0].push_back(make_int2(s0 | (t0 << 16), bits));   // positions < kMaxSpheres <= 2^16
     }
+    std::vector<int2> groups;   // kGroup records per group
+    for (int s = 0; s < d->n_spheres; ++s) {
+      const std::vector<int2>& v = by_s[s];
+      for (size_t k = 0; k < v.size(); k += kGroup)
+        for (int u = 0; u < kGroup; ++u)
+          groups.push_back(k + u < v.size() ? v[k + u] : make_int2(s | (s << 16), never_bits));
+    }
+    const int n_groups = (int)groups.size() / kGroup;
+    const int n_cc = (n_groups + 15) / 16 * kSelfPad;
+    const int n_padded = n_cc + kSelfPad;
+    std::vector<int2> cc_pairs(n_padded, make_int2(0, never_bits));
+    for (int g = 0; g < n_groups; ++g)
+      for (int u = 0; u < kGroup; ++u)
+        cc_pairs[(g / 16) * kSelfPad + g % 16 + 16 * u] = groups[(size_t)g * kGroup + u];
+    r->n_cc = n_cc;
     std::vector<int2> sph_map(d->n_spheres);
     for (int s = 0; s < d->n_spheres; ++s) sph_map[s] = make_int2(rank[s], d->sphere_link[s]);
     hipError_t e = hipMalloc((void**)&r->dev, sizeof(RobotDev));
@@ -467,9 +486,8 @@ int fk_cc_batch(const cp_robot* robot, const cp_env* env, int32_t n_cfg, const f
       if (e != hipSuccess) return hip_fail(e, "fk_cc_batch sphere centre launch");
     }
     if (flags & CP_SELF_COLLISION) {
-      e = launch_self_cc(robot->dev, robot->host, robot->spheres, robot->pairs_cc,
-                         (int)robot->self_pairs.size() / 2, n_cfg, d_q, d_collide, d_min_sd, early,
-                         (hipStream_t)stream);
+      e = launch_self_cc(robot->dev, robot->host, robot->spheres, robot->pairs_cc, robot->n_cc,
+                         n_cfg, d_q, d_collide, d_min_sd, early, (hipStream_t)stream);
       if (e != hipSuccess) return hip_fail(e, "fk_cc_batch self-collision launch");
     }
     return CP_OK;
@@ -560,8 +578,8 @@ int do_validate(const cp_robot* robot, const cp_env* env, const cp_proj_params& 
   }
   if (flags & CP_SELF_COLLISION) {
     hipError_t e = launch_self_cc_motions(robot->dev, robot->host, robot->spheres, robot->pairs_cc,
-                                          (int)robot->self_pairs.size() / 2, p.W, n_motions,
-                                          d_xi, d_status, (hipStream_t)stream);
+                                          robot->n_cc, p.W, n_motions, d_xi, d_status,
+                                          (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "self-collision launch");
   }
   return CP_OK;

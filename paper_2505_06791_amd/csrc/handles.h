@@ -34,7 +34,9 @@ struct cp_robot {
   cprrtc::RobotDev* dev = nullptr;  // device copy
   float4* spheres = nullptr;        // device spheres, grouped by link
   int2* pairs = nullptr;            // device self-collision pairs (positions in `spheres`)
-  int2* pairs_cc = nullptr;         // the same pairs as (s | t << 16, bits of (r_s + r_t)^2), padded
+  int2* pairs_cc = nullptr;         // the same pairs as (s | t << 16, bits of (r_s + r_t)^2),
+                                    // grouped by s for the self-collision kernel
+  int n_cc = 0;                     // entries of pairs_cc the kernel walks
   int2* sph_map = nullptr;          // device, per sphere in description order: (position in
                                     // `spheres`, joint frame that carries it)
   std::vector<int32_t> self_pairs;  // host, description order: s0 t0 s1 t1 ...

@@ -43,15 +43,19 @@ hipError_t launch_project_mode(int dof, int mode, const RobotDev* rob, const Con
                                hipStream_t stream, bool* supported);
 
 // Self-collision of configurations (OR into collide, min into min_sd) and of
-// motions' waypoints 1..W-1 (status 0 -> 2 on a hit).  pairs: (s | t << 16,
-// bits of (r_s + r_t)^2) per checked pair, padded to a multiple of kSelfPad
-// entries, plus kSelfPad more, with (0, 0, -1.0f).
+// motions' waypoints 1..W-1 (status 0 -> 2 on a hit).  pairs: n_entries
+// records (s | t << 16, bits of (r_s + r_t)^2), n_entries a multiple of
+// kSelfPad, and kSelfPad more past the end.  The checked pairs come in
+// groups of kSelfPad / 16 records sharing their first sphere s, group g at
+// entries (g / 16) kSelfPad + g % 16 + 16 u (u < kSelfPad / 16); records
+// with (r_s + r_t)^2 = -1 fill groups and the list up, never hit and are
+// left out of the minimum.
 constexpr int kSelfPad = 32;
 hipError_t launch_self_cc(const RobotDev* rob, const RobotDev& host, const float4* sph,
-                          const int2* pairs, int n_pairs, int n_cfg, const float* q,
+                          const int2* pairs, int n_entries, int n_cfg, const float* q,
                           uint8_t* collide, float* min_sd, bool early, hipStream_t stream);
 hipError_t launch_self_cc_motions(const RobotDev* rob, const RobotDev& host, const float4* sph,
-                                  const int2* pairs, int n_pairs, int W, int n_motions,
+                                  const int2* pairs, int n_entries, int W, int n_motions,
                                   const float* xi, int* status, hipStream_t stream);
 
 hipError_t launch_validate(const RobotDev* rob, const float4* sph, const EnvDev& env, int W,

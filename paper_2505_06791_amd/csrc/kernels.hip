@@ -197,9 +197,12 @@ __global__ __launch_bounds__(kBlock) void validate_kernel(
 // alone, |c_s - c_t|^2 <= (r_s + r_t)^2 with the right-hand side stored
 // with the pair, so only the centres' x, y, z are read).
 //   pairs[p] = (s | t << 16, bits of (r_s + r_t)^2), s and t positions in
-//   the link-grouped sphere array; n_pairs real pairs, the list padded to a
-//   multiple of kSelfPad, plus kSelfPad more entries, with (0, 0, -1), which
-//   never collides.
+//   the link-grouped sphere array; n_entries records (a multiple of
+//   kSelfPad) plus kSelfPad more, in groups of kU = kSelfPad / 16 records
+//   sharing s (group g at (g / 16) kSelfPad + g % 16 + 16 u), so lane l of
+//   a row reads c_s once per loop trip; records with (r_s + r_t)^2 = -1
+//   fill groups and the list up: they never collide and the minimum skips
+//   them.
 //   MOTION = false: item i is configuration i of q; collide[i] |= hit and,
 //                   with min_sd, min_sd[i] = min(min_sd[i], min pair sd)
 //                   (every pair evaluated).
@@ -218,7 +221,7 @@ constexpr int kSelfWaves = 4;
 template <bool MOTION>
 __global__ __launch_bounds__(64 * kSelfWaves) void self_cc_kernel(
     const RobotDev* __restrict__ rob, const float4* __restrict__ sph,
-    const int2* __restrict__ pairs, int n_pairs, int64_t n_items, int W,
+    const int2* __restrict__ pairs, int n_entries, int64_t n_items, int W,
     const float* __restrict__ q_all, uint8_t* __restrict__ collide, float* __restrict__ min_sd,
     int* __restrict__ status, int early) {
   extern __shared__ float4 centres[];
@@ -264,16 +267,18 @@ __global__ __launch_bounds__(64 * kSelfWaves) void self_cc_kernel(
   uint64_t acc = 0;                               // OR of every round's ballot (uniform)
   float msd = FLT_MAX;
   if (all_pairs) {
-    for (int base = 0; base < n_pairs; base += kSelfRow) {
+    for (int base = 0; base < n_entries; base += kSelfRow) {
       const int p = base + l;
       bool hit = false;
-      if (on && p < n_pairs) {
-        const int st = pairs[p].x;
-        const float4 a = c[st & 0xFFFF], b = c[st >> 16];
-        const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
-        const float sd = sqrtf(dx * dx + dy * dy + dz * dz) - (a.w + b.w);
-        msd = fminf(msd, sd);
-        hit = sd <= 0.0f;
+      if (on && p < n_entries) {
+        const int2 pr = pairs[p];
+        if (__int_as_float(pr.y) >= 0.0f) {          // not a filler
+          const float4 a = c[pr.x & 0xFFFF], b = c[pr.x >> 16];
+          const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+          const float sd = sqrtf(dx * dx + dy * dy + dz * dz) - (a.w + b.w);
+          msd = fminf(msd, sd);
+          hit = sd <= 0.0f;
+        }
       }
       acc |= __ballot(hit);
     }
@@ -288,19 +293,21 @@ __global__ __launch_bounds__(64 * kSelfWaves) void self_cc_kernel(
     int2 next[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) next[u] = pb[u * kSelfRow + l];
-    for (int base = 0; base < n_pairs; base += kSelfPad) {
+    for (int base = 0; base < n_entries; base += kSelfPad) {
       int2 cur[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) cur[u] = next[u];
       pb += kSelfPad;
 #pragma unroll
       for (int u = 0; u < kU; ++u) next[u] = pb[u * kSelfRow + l];
+      // the lane's kU records of this trip share their first sphere
+      const float4* ca = c + (cur[0].x & 0xFFFF);
+      const float ax = ca->x, ay = ca->y, az = ca->z;
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int2 pr = cur[u];
-        const float4* ca = c + (pr.x & 0xFFFF);
         const float4* cb = c + (pr.x >> 16);
-        const float dx = ca->x - cb->x, dy = ca->y - cb->y, dz = ca->z - cb->z;
+        const float dx = ax - cb->x, dy = ay - cb->y, dz = az - cb->z;
         acc |= __ballot(dx * dx + dy * dy + dz * dz <= __int_as_float(pr.y));
       }
       if (early) {
@@ -330,29 +337,29 @@ static int self_waves(int n_spheres) {
 }
 
 hipError_t launch_self_cc(const RobotDev* rob, const RobotDev& host, const float4* sph,
-                          const int2* pairs, int n_pairs, int n_cfg, const float* q,
+                          const int2* pairs, int n_entries, int n_cfg, const float* q,
                           uint8_t* collide, float* min_sd, bool early, hipStream_t stream) {
-  if (n_pairs == 0 || n_cfg == 0) return hipSuccess;
+  if (n_entries == 0 || n_cfg == 0) return hipSuccess;
   const int waves = self_waves(host.n_spheres);
   const size_t lds = sizeof(float4) * kSelfPerWave * waves * host.n_spheres;
   const int64_t per_block = (int64_t)kSelfPerWave * waves;
   const unsigned nb = (unsigned)((n_cfg + per_block - 1) / per_block);
   self_cc_kernel<false><<<nb, 64 * waves, lds, stream>>>(
-      rob, sph, pairs, n_pairs, n_cfg, 0, q, collide, min_sd, nullptr, early ? 1 : 0);
+      rob, sph, pairs, n_entries, n_cfg, 0, q, collide, min_sd, nullptr, early ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_self_cc_motions(const RobotDev* rob, const RobotDev& host, const float4* sph,
-                                  const int2* pairs, int n_pairs, int W, int n_motions,
+                                  const int2* pairs, int n_entries, int W, int n_motions,
                                   const float* xi, int* status, hipStream_t stream) {
-  if (n_pairs == 0 || n_motions == 0) return hipSuccess;
+  if (n_entries == 0 || n_motions == 0) return hipSuccess;
   const int waves = self_waves(host.n_spheres);
   const size_t lds = sizeof(float4) * kSelfPerWave * waves * host.n_spheres;
   const int64_t items = (int64_t)n_motions * (W - 1);
   const int64_t per_block = (int64_t)kSelfPerWave * waves;
   const unsigned nb = (unsigned)((items + per_block - 1) / per_block);
   self_cc_kernel<true><<<nb, 64 * waves, lds, stream>>>(
-      rob, sph, pairs, n_pairs, items, W, xi, nullptr, nullptr, status, 1);
+      rob, sph, pairs, n_entries, items, W, xi, nullptr, nullptr, status, 1);
   return hipGetLastError();
 }
 

@@ -736,7 +736,7 @@ int cp_plan(cp_planner* pl, const cp_env* env, const cp_constraint* constraint,
     // with the self-check on, an endpoint must also be clear of the robot itself
     const int n_self = (int)robot->self_pairs.size() / 2;
     if (he == hipSuccess && (o.flags & CP_SELF_COLLISION) && n_self > 0)
-      he = launch_self_cc(robot->dev, robot->host, robot->spheres, robot->pairs_cc, n_self, 2,
+      he = launch_self_cc(robot->dev, robot->host, robot->spheres, robot->pairs_cc, robot->n_cc, 2,
                           pl->cfg, pl->cfg_col, pl->cfg_sd, false, st);
     int* ok_h = reinterpret_cast<int*>(io + 2 * n);
     float* sd_h = io + 2 * n + 2;
