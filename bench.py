@@ -98,9 +98,9 @@ TRAFFIC = [
         "sources": ("paper_2505_06791_amd/csrc/project.h", "paper_2505_06791_amd/csrc/device.h",
                     "paper_2505_06791_amd/csrc/project_pool.h", "paper_2505_06791_amd/csrc/rtc.hip",
                     "paper_2505_06791_amd/csrc/kernels.h", "include/cprrtc.h"),
-        "sources_sha256": "aa4d33447e0144c46959c984c3e8412b222ee9b79ba39993fccf3626fc6492d1",
-        "fetch_kib": 5206.5, "fetch_scale": 262144.0 / 131086.6,
-        "write_kib": 116187.2, "write_scale": 1.0,
+        "sources_sha256": "798f22cdd1ea6d679d6c40f938a1e394af2e9133138366008cc0c0ec12500eb6",
+        "fetch_kib": 5217.5, "fetch_scale": 262144.0 / 131086.6,
+        "write_kib": 116231.2, "write_scale": 1.0,
     },
 ]
 

@@ -246,10 +246,11 @@ void rtc_release(cp_robot* robot) {
 
 // Compiled code objects are kept on disk, keyed by a hash of everything the
 // compilation sees (the generated source, the library's device headers, the
-// options and the target), so a later process skips the compiler.  The
-// directory is $CPRRTC_RTC_CACHE (the value 0 turns the cache off), else
-// $XDG_CACHE_HOME/cprrtc, else $HOME/.cache/cprrtc; a missing or unusable
-// directory, or an unreadable entry, just means compiling.
+// options, the target and the run-time compiler's version), so a later
+// process skips the compiler.  The directory is $CPRRTC_RTC_CACHE (the
+// value 0 turns the cache off), else $XDG_CACHE_HOME/cprrtc, else
+// $HOME/.cache/cprrtc; a missing or unusable directory, or an unreadable
+// entry, just means compiling.
 uint64_t fnv1a(uint64_t h, const char* p, size_t n) {
   for (size_t i = 0; i < n; ++i) {
     h ^= (unsigned char)p[i];
@@ -291,6 +292,10 @@ std::string cache_key(const std::string& src, const char* const* opts, int n_opt
     add(kRtcHeaders[i], std::strlen(kRtcHeaders[i]));
   }
   for (int i = 0; i < n_opts; ++i) add(opts[i], std::strlen(opts[i]));
+  // a code object from another run-time compiler is not reused
+  int ver[2] = {0, 0};
+  if (hiprtcVersion(&ver[0], &ver[1]) == HIPRTC_SUCCESS)
+    add(reinterpret_cast<const char*>(ver), sizeof ver);
   char k[40];
   std::snprintf(k, sizeof k, "%016llx%016llx", (unsigned long long)a, (unsigned long long)b);
   return k;
